@@ -1,0 +1,124 @@
+"""Seeded synthetic charges on the unit cube and their closed-form potentials.
+
+Shared by the tests, the benchmark and the smoke check; it holds none of the
+solver's arithmetic (no stencils, Green's functions, transforms or moments),
+only charge densities sampled on nodes and the exact continuous potentials
+they induce under Delta phi = f with phi -> -q/(4 pi |x|).
+
+Charges
+  bump      f = w (1 - rho^2)^4 for rho = |x - c| / R < 1, else 0.
+            phi = w R^2 psi(rho),
+            psi = rho^2/6 - rho^4/5 + rho^6/7 - rho^8/18 + rho^10/110 - 1/10
+                  (rho < 1),   -128 / (3465 rho)  (rho >= 1).
+  smooth    the paper's smooth test charge (sec. 6.1): f = (r - r^2)^4 for
+            r = |x - x0| / Ro < 1, Ro = 1/4, x0 = (1/2, 1/2, 1/2), with the
+            potential printed there.
+
+Workloads (seeded with numpy's PCG64; per bump: centre (3 uniforms),
+radius, weight, in that order):
+  one_bump      config 'plain FP64, 32^3': w = 1, R = 0.35, centre (1/2)^3
+  bumps(k, ...) k bumps, centres U[lo, hi]^3, radii U(r0, r1), weights U(-1, 1)
+"""
+from dataclasses import dataclass
+
+import numpy as np
+
+
+@dataclass(frozen=True)
+class Bump:
+    centre: tuple
+    radius: float
+    weight: float
+
+
+def _rho(N, c, R):
+    ax = np.arange(N + 1) / N
+    d0 = (ax - c[0])[:, None, None]
+    d1 = (ax - c[1])[None, :, None]
+    d2 = (ax - c[2])[None, None, :]
+    return np.sqrt(d0 * d0 + d1 * d1 + d2 * d2) / R
+
+
+def bump_charge(N, bumps):
+    """Sum of bump charges sampled on the (N+1)^3 nodes g/N of [0, 1]^3."""
+    f = np.zeros((N + 1,) * 3)
+    for bp in bumps:
+        r = _rho(N, bp.centre, bp.radius)
+        f += bp.weight * np.where(r < 1.0, (1.0 - r * r) ** 4, 0.0)
+    return f
+
+
+def _psi_bump(r):
+    r2 = r * r
+    inside = r2 / 6 - r2 ** 2 / 5 + r2 ** 3 / 7 - r2 ** 4 / 18 + r2 ** 5 / 110 - 0.1
+    rs = np.where(r > 0, r, 1.0)
+    outside = -128.0 / (3465.0 * rs)
+    return np.where(r < 1.0, inside, outside)
+
+
+def bump_potential(N, bumps):
+    """Closed-form potential of bump_charge on the same nodes."""
+    phi = np.zeros((N + 1,) * 3)
+    for bp in bumps:
+        r = _rho(N, bp.centre, bp.radius)
+        phi += bp.weight * bp.radius ** 2 * _psi_bump(r)
+    return phi
+
+
+def bump_potential_at(x, bumps):
+    """Closed-form potential at arbitrary points x (shape (m, 3))."""
+    x = np.asarray(x, dtype=np.float64)
+    phi = np.zeros(len(x))
+    for bp in bumps:
+        r = np.linalg.norm(x - np.asarray(bp.centre), axis=1) / bp.radius
+        phi += bp.weight * bp.radius ** 2 * _psi_bump(r)
+    return phi
+
+
+SMOOTH_RO = 0.25
+
+
+def smooth_charge(N):
+    """The paper's smooth charge (sec. 6.1) on the nodes of [0, 1]^3."""
+    r = _rho(N, (0.5, 0.5, 0.5), SMOOTH_RO)
+    return np.where(r < 1.0, (r - r * r) ** 4, 0.0)
+
+
+def smooth_potential(N):
+    """The closed-form potential printed with the smooth charge (sec. 6.1)."""
+    r = _rho(N, (0.5, 0.5, 0.5), SMOOTH_RO)
+    inside = (r ** 6 / 42 - r ** 7 / 14 + r ** 8 / 12 - 2 * r ** 9 / 45 + r ** 10 / 110 - 1.0 / 1260)
+    rs = np.where(r > 0, r, 1.0)
+    outside = -1.0 / (2310.0 * rs)
+    return SMOOTH_RO ** 2 * np.where(r < 1.0, inside, outside)
+
+
+def one_bump():
+    return [Bump((0.5, 0.5, 0.5), 0.35, 1.0)]
+
+
+def bumps(k, seed, radius=(0.1, 0.2), centre=(0.3, 0.7)):
+    """k seeded bumps; centres U[centre]^3, radii U(radius), weights U(-1, 1)."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    out = []
+    for _ in range(k):
+        c = tuple(float(v) for v in rng.uniform(centre[0], centre[1], size=3))
+        R = float(rng.uniform(radius[0], radius[1]))
+        w = float(rng.uniform(-1.0, 1.0))
+        out.append(Bump(c, R, w))
+    return out
+
+
+# the named workloads: (N, n, Q, bumps)
+WORKLOADS = {
+    "fp64_32": dict(N=32, n=8, Q=4, bumps=lambda: one_bump()),
+    "fp32_128": dict(N=128, n=16, Q=4, bumps=lambda: bumps(3, 102)),
+    "fp32_256_q6": dict(N=256, n=32, Q=6, bumps=lambda: bumps(8, 103, radius=(0.05, 0.15))),
+    "fp32_256_q4": dict(N=256, n=32, Q=4, bumps=lambda: bumps(8, 103, radius=(0.05, 0.15))),
+}
+
+
+def workload(name):
+    """(N, n, Q, bumps) of a named workload."""
+    w = WORKLOADS[name]
+    return w["N"], w["n"], w["Q"], w["bumps"]()

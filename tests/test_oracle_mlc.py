@@ -1,0 +1,149 @@
+"""Pins of the two-level MLC oracle as a whole (paper sec. 4.1, sec. 6.1)."""
+import numpy as np
+import pytest
+
+import mlc_inputs as mi
+from oracle import convolution as conv
+from oracle import mlc
+from oracle.dgf import dgf_cached
+
+
+def _global_discrete(G1, Z, f, N):
+    """G^h * f on all nodes, by Hockney over the whole grid, plus the
+    Mehrstellen correction h^2 f / 12 (sec. 2 eq. msCorr4)."""
+    h = 1.0 / N
+    g = conv.conv_hockney(G1, Z, f, np.zeros(3, int), np.full(3, N), M=2 * N + 1)
+    return h * h * g
+
+
+@pytest.mark.parametrize("Q,beta", [(4, 3), (4, 6), (6, 3), (6, 6)])
+def test_boundary_values_literal_vs_regrouped(Q, beta):
+    """The node-by-node evaluation phi^B = loc_g(g) + I(phi^H - loc_g)(g)
+    (sec. 4.1 eqs. philocmlcII, mlcfulldiscr) equals the per-patch
+    regrouping used for larger problems (linearity of I)."""
+    N, n = 16, 8
+    G1 = dgf_cached(Q, 64)
+    f = mi.bump_charge(N, [mi.Bump((0.45, 0.5, 0.55), 0.3, 1.0)])
+    prm = mlc.Params(N=N, n=n, alpha=3, beta=beta, P=4, Q=Q, Z=64)
+    phi1, a = mlc.mlc_solve(f, prm, G1, keep=True)
+    phi2, b = mlc.mlc_solve(f, prm, G1, bc_mode="literal", keep=True)
+    sk = mlc.skeleton_mask(N, n)
+    assert np.abs(a["phiB"] - b["phiB"])[sk].max() < 1e-14 * np.abs(b["phiB"]).max()
+    assert np.abs(phi1 - phi2).max() < 1e-14 * np.abs(phi2).max()
+
+
+@pytest.mark.parametrize("Q", [4, 6])
+def test_local_convolution_direct_vs_fft(Q):
+    """Both convolution modes of step 1 agree (Hockney is exact)."""
+    N, n = 16, 8
+    G1 = dgf_cached(Q, 64)
+    f = mi.bump_charge(N, [mi.Bump((0.4, 0.55, 0.5), 0.3, 1.0)])
+    prm = mlc.Params(N=N, n=n, alpha=3, beta=6, P=4, Q=Q, Z=64)
+    q = mlc.patch_charge(f, n, (1, 0, 1))
+    a = mlc.local_field(G1, prm, q, "direct")
+    b = mlc.local_field(G1, prm, q, "fft")
+    assert np.abs(a - b).max() < 1e-13 * np.abs(a).max()
+
+
+@pytest.mark.parametrize("Q", [4, 6])
+def test_dirichlet_reproduces_discrete_solution(Q):
+    """Fed the exact boundary values of the global discrete potential, the
+    patch Dirichlet solves (sec. 4.1 eq. last_step_fulldiscr) return it in
+    every patch interior (uniqueness of the discrete Dirichlet problem)."""
+    N, n = 16, 8
+    G1 = dgf_cached(Q, 64)
+    f = mi.bump_charge(N, [mi.Bump((0.45, 0.5, 0.52), 0.3, 1.0)])
+    u = _global_discrete(G1, 64, f, N)
+    for i in mlc.patch_indices(N, n):
+        sl = tuple(slice(n * i[d], n * i[d] + n + 1) for d in range(3))
+        inner = mlc.dirichlet_solve(u[sl], f[sl], Q, 1.0 / N)
+        assert np.abs(inner - u[sl][1:-1, 1:-1, 1:-1]).max() < 1e-14 * np.abs(u).max() * 10
+
+
+def test_discretisation_is_fourth_order():
+    """G^h * f + C2 h^2 f converges to the continuous potential at O(h^4)
+    (sec. 2 eq. msCorr4)."""
+    G1 = dgf_cached(4, 64)
+    bumps = mi.one_bump()
+    errs = []
+    for N in (16, 32, 64):
+        f = mi.bump_charge(N, bumps)
+        u = _global_discrete(G1, 64, f, N) + f / (12.0 * N * N)
+        ex = mi.bump_potential(N, bumps)
+        errs.append(np.abs(u - ex).max() / np.abs(ex).max())
+    assert errs[0] / errs[1] > 12 and errs[1] / errs[2] > 12, errs
+
+
+def test_mlc0_barrier_error_falls_with_beta():
+    """Barrier error of MLC-0 (beta = alpha) scales like beta^-q: L19,
+    doubling beta cuts it by at least ~16 (sec. 6.1, Table 1 discussion)."""
+    G1 = dgf_cached(4, 128)
+    N, n = 64, 16
+    f = mi.smooth_charge(N)
+    u = _global_discrete(G1, 128, f, N) + f / (12.0 * N * N)
+    errs = []
+    for beta in (3, 6):
+        prm = mlc.Params(N=N, n=n, alpha=beta, beta=beta, P=4, Q=4, Z=128)
+        phi = mlc.mlc_solve(f, prm, G1)
+        errs.append(np.abs(phi - u).max() / np.abs(u).max())
+    assert errs[0] / errs[1] > 16, errs
+
+
+def test_legendre_far_field_reduces_error():
+    """At fixed alpha, adding the Legendre far field out to beta lowers the
+    error, and P = 4 beats P = 1 (Tables 2, 3)."""
+    G1 = dgf_cached(4, 128)
+    N, n = 64, 16
+    f = mi.smooth_charge(N)
+    ex = mi.smooth_potential(N)
+
+    def err(alpha, beta, P):
+        prm = mlc.Params(N=N, n=n, alpha=alpha, beta=beta, P=P, Q=4, Z=128)
+        return np.abs(mlc.mlc_solve(f, prm, G1) - ex).max() / np.abs(ex).max()
+
+    e0 = err(1.5, 1.5, 4)
+    e1 = err(1.5, 3, 1)
+    e4 = err(1.5, 3, 4)
+    assert e4 < e1 < e0, (e0, e1, e4)
+
+
+def test_linearity():
+    N, n = 16, 8
+    G1 = dgf_cached(4, 64)
+    prm = mlc.Params(N=N, n=n, alpha=3, beta=6, P=4, Q=4, Z=64)
+    f1 = mi.bump_charge(N, [mi.Bump((0.4, 0.5, 0.5), 0.3, 1.0)])
+    f2 = mi.bump_charge(N, [mi.Bump((0.6, 0.45, 0.55), 0.25, -0.7)])
+    a, b = 0.3, -1.7
+    lhs = mlc.mlc_solve(a * f1 + b * f2, prm, G1)
+    rhs = a * mlc.mlc_solve(f1, prm, G1) + b * mlc.mlc_solve(f2, prm, G1)
+    assert np.abs(lhs - rhs).max() < 1e-13 * np.abs(rhs).max()
+
+
+def test_cube_symmetry():
+    """A charge invariant under the cube's symmetries gives a potential with
+    the same symmetries (the plane choice and the interpolation are
+    symmetric)."""
+    N, n = 32, 8
+    G1 = dgf_cached(6, 64)
+    prm = mlc.Params(N=N, n=n, alpha=3, beta=6, P=4, Q=6, Z=64)
+    f = mi.bump_charge(N, mi.one_bump())
+    phi = mlc.mlc_solve(f, prm, G1)
+    s = np.abs(phi).max()
+    for perm in [(1, 0, 2), (0, 2, 1), (2, 0, 1)]:
+        assert np.abs(phi - np.transpose(phi, perm)).max() < 1e-13 * s
+    for ax in range(3):
+        assert np.abs(phi - np.flip(phi, ax)).max() < 1e-13 * s
+
+
+def test_plain_config_error_vs_closed_form():
+    """The 32^3 single-bump problem (8^3 patches, alpha=3, beta=6, P=4, L19)
+    lands within the O(h^4) discretisation error of the closed form."""
+    N, n, Q, bumps = mi.workload("fp64_32")
+    G1 = dgf_cached(Q, 64)
+    f = mi.bump_charge(N, bumps)
+    ex = mi.bump_potential(N, bumps)
+    prm = mlc.Params(N=N, n=n, alpha=3, beta=6, P=4, Q=Q, Z=64)
+    err = np.abs(mlc.mlc_solve(f, prm, G1) - ex).max() / np.abs(ex).max()
+    glob = _global_discrete(G1, 64, f, N) + f / (12.0 * N * N)
+    eg = np.abs(glob - ex).max() / np.abs(ex).max()
+    assert err < 2 * eg, (err, eg)
