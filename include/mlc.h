@@ -1,0 +1,161 @@
+/*
+ * mlc.h -- C ABI of libmlc, a two-level Method of Local Corrections solver
+ * for the free-space Poisson equation  Delta phi = f  on MI355X (gfx950).
+ *
+ * The operation is the fully discrete two-level algorithm of Kavouklis &
+ * Colella, "Computation of Volume Potentials on Structured Grids via the
+ * Method of Local Corrections" (sec. 4.1, steps 1-3 and the final
+ * Mehrstellen correction), with the discrete Green's function built as in
+ * appendix A.1 and local convolutions by Hockney's method (appendix A.2).
+ *
+ * Conventions shared by every call
+ *  - Every call returns mlc_status; MLC_OK == 0, errors are negative.  No C++
+ *    exception or abort crosses this boundary.
+ *  - Grids are cubic: N cells per axis, (N+1)^3 nodes g h, g in [0, N]^3.
+ *    Node arrays are float64, C order [g0][g1][g2] (g2 fastest), length
+ *    (N+1)^3.  f must vanish on the outer boundary nodes (the charge is
+ *    supported inside the domain, sec. 4).
+ *  - Pointers called "device" are HIP device addresses on the context's GPU;
+ *    the caller owns them and keeps them alive until the work enqueued on
+ *    the given stream has completed.  "stream" is a hipStream_t (NULL = the
+ *    default stream).  Work is enqueued asynchronously; no call synchronises
+ *    the device except where stated.
+ *  - Arguments are validated before anything is enqueued; on an error
+ *    nothing is written to any output.
+ *  - A context is used from one host thread at a time; plans are immutable
+ *    after creation and may be used by several solves in sequence.
+ */
+#ifndef MLC_H
+#define MLC_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  MLC_OK = 0,
+  MLC_ERR_INVALID_ARG = -1,   /* malformed argument or inconsistent sizes            */
+  MLC_ERR_UNSUPPORTED = -2,   /* well formed, but outside what this build implements */
+  MLC_ERR_OUT_OF_MEMORY = -3, /* device allocation failed or budget exceeded          */
+  MLC_ERR_DEVICE = -4,        /* a HIP runtime error; see mlc_last_error              */
+  MLC_ERR_BUSY = -5,          /* server admission queue full                          */
+  MLC_ERR_NOT_READY = -6      /* server ticket still in flight                        */
+} mlc_status;
+
+/* Arithmetic of the local convolutions (sec. 4.1 step 1).  Every other step
+ * (DGF, moments, far fields, coarse solve, boundary values, Dirichlet
+ * solves) is always float64. */
+typedef enum { MLC_CONV_FP64 = 0, MLC_CONV_FP32 = 1 } mlc_conv_precision;
+
+/* The problem, in the paper's notation (sec. 4, sec. 6.1). */
+typedef struct {
+  int32_t n_cells;        /* N: cells per axis; N % patch == 0                          */
+  double h;               /* mesh spacing > 0 (unit cube: 1/N)                          */
+  int32_t patch;          /* n: cells per patch edge; n % 4 == 0, n >= 8                */
+  double alpha, beta;     /* localisation radii in units of R = n h / 2; 1 <= alpha <= beta;
+                             the margins ceil((r-1) n / 2) must be multiples of 4 (Nref)  */
+  int32_t P;              /* Legendre truncation: modes with |p|_1 < P; 1 <= P <= 4     */
+  int32_t Q;              /* Mehrstellen operator: 4 -> L19, 6 -> L27                   */
+  int32_t interp_b;       /* coplanar interpolation radius b (order 2b+2); 0 -> Q/2     */
+  int32_t conv_precision; /* mlc_conv_precision                                        */
+  int32_t fft_size;       /* Hockney torus edge M of the local convolutions; 0 -> auto  */
+  int32_t dgf_half_width; /* Z of the DGF table [-Z, Z]^3 (solved on [-2Z, 2Z]^3); 0 -> 128 */
+} mlc_problem;
+
+/* Sizes derived from an mlc_problem (all counts per axis unless noted). */
+typedef struct {
+  int32_t N, n, P, Q, b, K;          /* K = P(P+1)(P+2)/6 Legendre moments per patch     */
+  int32_t d_alpha, d_beta;           /* margins of Omega_alpha, Omega_beta (fine cells)  */
+  int32_t e;                         /* d_alpha + 4b: half-margin of the local field box */
+  int32_t patches_per_axis, npatch;  /* N/n and (N/n)^3                                  */
+  int32_t M, M_coarse, M_table;      /* Hockney torus edges: local, coarse, far-field    */
+  int32_t Wc;                        /* coarse samples of a local field per axis         */
+  int32_t Wa, nplanes_a;             /* skeleton planes of a local field: width, count   */
+  int32_t S_lo, Ns;                  /* coarse right-hand side box [S_lo, S_lo+Ns-1]     */
+  int32_t O_lo, No;                  /* coarse solution box [O_lo, O_lo+No-1]            */
+  int32_t Z;                         /* DGF table half-width                             */
+  int32_t conv_precision;
+  double h, H;                       /* fine and coarse (4h) spacing                     */
+} mlc_plan_info;
+
+typedef struct mlc_context mlc_context;
+typedef struct mlc_plan mlc_plan;
+
+/* Human-readable name of a status code (static storage). */
+const char* mlc_status_string(mlc_status s);
+
+/* Validate a problem and fill its derived sizes, on the host only (no
+ * device is touched).  Returns MLC_ERR_INVALID_ARG for malformed input,
+ * MLC_ERR_UNSUPPORTED for valid problems this build cannot run. */
+mlc_status mlc_problem_info(const mlc_problem* prob, mlc_plan_info* out);
+
+/* Create a context on HIP device `device`.  hbm_budget_bytes caps the
+ * device memory the context's resident tables and the server may hold
+ * (0 = no cap).  Returns MLC_ERR_DEVICE if the device cannot be opened. */
+mlc_status mlc_context_create(int device, size_t hbm_budget_bytes, mlc_context** out);
+mlc_status mlc_context_destroy(mlc_context* ctx);
+
+/* Copy the last error message of the context (NUL-terminated, truncated to
+ * len).  ctx may be NULL for errors raised before a context existed. */
+mlc_status mlc_last_error(mlc_context* ctx, char* buf, size_t len);
+
+/* Build a plan: validates the problem, then builds (or reuses, per Q and Z)
+ * the resident DGF table (appendix A.1), the DGF spectra of the local and
+ * coarse convolutions and the far-field tables of the Legendre modes
+ * (sec. 4.1: "computed once and stored").  Synchronises the device. */
+mlc_status mlc_plan_create(mlc_context* ctx, const mlc_problem* prob, mlc_plan** out);
+mlc_status mlc_plan_destroy(mlc_plan* plan);
+mlc_status mlc_plan_get_info(const mlc_plan* plan, mlc_plan_info* out);
+
+/* Bytes of device workspace a solve with this plan needs. */
+mlc_status mlc_plan_workspace_bytes(const mlc_plan* plan, size_t* bytes);
+
+/* One two-level MLC solve (sec. 4.1): f (device, (N+1)^3 float64, read
+ * only) -> phi (device, (N+1)^3 float64, fully overwritten).  workspace is
+ * device memory of at least mlc_plan_workspace_bytes bytes, owned by the
+ * caller; its contents after the solve are the intermediates listed under
+ * mlc_workspace_view.  Enqueued on `stream`. */
+mlc_status mlc_solve(mlc_plan* plan, const double* f, double* phi,
+                     void* workspace, size_t ws_bytes, void* stream);
+
+/* Several independent problems in one pass: the per-patch stages of all
+ * problems run in shared launches (their plans must share n, alpha, b, Q,
+ * the torus M and the conv precision); coarse solves run per problem.
+ * f[k], phi[k] are device arrays of plan k's size; workspace must hold
+ * mlc_batch_workspace_bytes(count, plans) bytes. */
+mlc_status mlc_batch_workspace_bytes(int32_t count, mlc_plan* const* plans, size_t* bytes);
+mlc_status mlc_solve_batched(int32_t count, mlc_plan* const* plans, const double* const* f,
+                             double* const* phi, void* workspace, size_t ws_bytes, void* stream);
+
+/* Intermediates of the last solve held in a workspace (device pointers into
+ * it; valid until the workspace is reused):
+ *   MLC_VIEW_MOMENTS      float64 [npatch][K]: c_{i,p}, patches in C order of i,
+ *                         modes by total degree then descending lexicographic p
+ *   MLC_VIEW_COARSE_RHS   float64 [Ns]^3: F^H on [S_lo, S_lo+Ns-1]^3
+ *   MLC_VIEW_COARSE_PHI   float64 [No]^3: phi^H on [O_lo, O_lo+No-1]^3
+ *   MLC_VIEW_BOUNDARY     float64 [(N+1)^3]: phi^B on skeleton nodes (others 0)
+ *   MLC_VIEW_LOCAL_COARSE conv precision [npatch][Wc]^3: phi_i at the coarse
+ *                         nodes of its box G(Omega_alpha, 4b), starting at -e
+ *   MLC_VIEW_LOCAL_PLANES conv precision [npatch][3][nplanes_a][Wa][Wa]:
+ *                         phi_i on its skeleton planes inside Omega_alpha,
+ *                         plane normal d, planes at -d_alpha rounded up to a
+ *                         multiple of n, in-plane axes ascending from -d_alpha */
+enum {
+  MLC_VIEW_MOMENTS = 0, MLC_VIEW_COARSE_RHS = 1, MLC_VIEW_COARSE_PHI = 2,
+  MLC_VIEW_BOUNDARY = 3, MLC_VIEW_LOCAL_COARSE = 4, MLC_VIEW_LOCAL_PLANES = 5
+};
+mlc_status mlc_workspace_view(const mlc_plan* plan, void* workspace, int32_t which,
+                              void** ptr, size_t* bytes);
+
+/* The resident DGF table G^{h=1} on [-Z, Z]^3 ((2Z+1)^3 float64, C order,
+ * centre at index (Z, Z, Z)) of operator Q, building it if needed
+ * (appendix A.1).  The pointer stays owned by the context.  Synchronises. */
+mlc_status mlc_dgf_table(mlc_context* ctx, int32_t Q, int32_t Z, const double** table);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* MLC_H */

@@ -1,0 +1,645 @@
+// libmlc: host side of the C ABI declared in include/mlc.h.  Validation and
+// sizing, the context (resident DGF tables), plan set-up (DGF spectra and
+// far-field tables) and the enqueueing of every stage of a solve.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <mutex>
+#include <new>
+#include <string>
+#include <utility>
+#include <vector>
+
+#include "../../include/mlc.h"
+#include "common.h"
+#include "conv_kernels.h"
+#include "setup_kernels.h"
+#include "stage_kernels.h"
+
+using namespace mlc;
+
+// ------------------------------------------------------------------ state
+struct mlc_context {
+  int device = 0;
+  size_t budget = 0;
+  std::string last_error;
+  std::map<std::pair<int, int>, double*> dgf;   // (Q, Z) -> (2Z+1)^3 table
+};
+
+struct mlc_plan {
+  mlc_context* ctx = nullptr;
+  mlc_problem prob{};
+  mlc_plan_info info{};
+  int S = 0, Mh = 0, Wp = 0, P0 = 0, eb = 0, Wtc = 0, Wb = 0, Wbc = 0, P0b = 0, nplb = 0, Kann = 0;
+  ModeList modes{};
+  void* conv_spec = nullptr;
+  double* coarse_spec = nullptr;
+  double* T = nullptr;
+  double* D = nullptr;
+  size_t o_mom = 0, o_X = 0, o_Z = 0, o_cs = 0, o_pl = 0, o_F = 0, o_tor = 0, o_phiH = 0, o_phiB = 0, o_dir = 0;
+  size_t ws_total = 0;
+};
+
+static thread_local std::string g_error;   // errors before a context exists
+
+static mlc_status fail(mlc_context* ctx, mlc_status s, const std::string& msg) {
+  if (ctx) ctx->last_error = msg;
+  g_error = msg;
+  return s;
+}
+
+#define HIP_TRY(ctx, expr)                                                                       \
+  do {                                                                                          \
+    hipError_t e_ = (expr);                                                                     \
+    if (e_ != hipSuccess)                                                                       \
+      return fail((ctx), MLC_ERR_DEVICE, std::string(#expr) + ": " + hipGetErrorString(e_));   \
+  } while (0)
+
+// ------------------------------------------------------- supported sizes
+// Local-convolution tori (n, M) with compiled kernels, per precision.
+#define MLC_CONV_SIZES_F32(X) X(8, 50) X(8, 64) X(8, 72) X(16, 90) X(16, 96) X(16, 120) X(16, 128) \
+  X(32, 150) X(32, 160) X(32, 180) X(32, 192)
+#define MLC_CONV_SIZES_F64(X) X(8, 50) X(8, 64) X(8, 72) X(16, 90) X(16, 96) X(16, 120) X(16, 128) \
+  X(32, 150) X(32, 160)
+// Generic FFT lengths (DGF spectra, far-field tables, coarse solve).
+#define MLC_FFT_SIZES(X) X(50) X(64) X(72) X(80) X(90) X(96) X(100) X(120) X(128) X(144) X(150) X(160) \
+  X(180) X(192) X(200) X(216) X(240) X(250) X(256)
+
+static bool conv_size_ok(int prec, int n, int M) {
+#define CHK(nn, MM) if (n == nn && M == MM) return true;
+  if (prec == MLC_CONV_FP32) { MLC_CONV_SIZES_F32(CHK) }
+  else { MLC_CONV_SIZES_F64(CHK) }
+#undef CHK
+  return false;
+}
+static const int kFftSizes[] = {
+#define LST(MM) MM,
+    MLC_FFT_SIZES(LST)
+#undef LST
+};
+static int pick_fft(int minimum, int maximum) {
+  for (int m : kFftSizes)
+    if (m >= minimum && m <= maximum) return m;
+  return -1;
+}
+static int pick_conv(int prec, int n, int minimum) {
+  for (int m : kFftSizes)
+    if (m >= minimum && conv_size_ok(prec, n, m)) return m;
+  return -1;
+}
+
+static int margin_of(double r, int n) {
+  // ceil((r - 1) n / 2) with a tolerance for decimal radii such as 3.25
+  double v = (r - 1.0) * n / 2.0;
+  double c = std::ceil(v - 1e-9);
+  return int(c);
+}
+
+static ModeList mode_list(int P) {
+  ModeList m{};
+  m.K = 0;
+  for (int deg = 0; deg < P; ++deg) {
+    // descending lexicographic order within a degree
+    for (int a = deg; a >= 0; --a)
+      for (int b = deg - a; b >= 0; --b) {
+        int c = deg - a - b;
+        m.p[m.K][0] = a; m.p[m.K][1] = b; m.p[m.K][2] = c;
+        ++m.K;
+      }
+  }
+  return m;
+}
+
+// ------------------------------------------------------------ validation
+extern "C" const char* mlc_status_string(mlc_status s) {
+  switch (s) {
+    case MLC_OK: return "MLC_OK";
+    case MLC_ERR_INVALID_ARG: return "MLC_ERR_INVALID_ARG";
+    case MLC_ERR_UNSUPPORTED: return "MLC_ERR_UNSUPPORTED";
+    case MLC_ERR_OUT_OF_MEMORY: return "MLC_ERR_OUT_OF_MEMORY";
+    case MLC_ERR_DEVICE: return "MLC_ERR_DEVICE";
+    case MLC_ERR_BUSY: return "MLC_ERR_BUSY";
+    case MLC_ERR_NOT_READY: return "MLC_ERR_NOT_READY";
+  }
+  return "MLC_ERR_UNKNOWN";
+}
+
+static mlc_status derive(const mlc_problem* p, mlc_plan_info* o, std::string* why) {
+  if (!p || !o) { *why = "null argument"; return MLC_ERR_INVALID_ARG; }
+  mlc_plan_info I{};
+  I.N = p->n_cells; I.n = p->patch; I.P = p->P; I.Q = p->Q;
+  I.b = p->interp_b ? p->interp_b : p->Q / 2;
+  I.conv_precision = p->conv_precision;
+  I.h = p->h;
+  I.H = NREF * p->h;
+  I.Z = p->dgf_half_width ? p->dgf_half_width : 128;
+  if (I.N <= 0 || I.n <= 0 || !(p->h > 0) || !std::isfinite(p->h)) { *why = "N, n and h must be positive"; return MLC_ERR_INVALID_ARG; }
+  if (I.N % I.n) { *why = "N must be a multiple of the patch size"; return MLC_ERR_INVALID_ARG; }
+  if (I.n % NREF || I.n < 8) { *why = "patch size must be a multiple of 4 and >= 8"; return MLC_ERR_INVALID_ARG; }
+  if (!(p->alpha >= 1.0) || !(p->beta >= p->alpha) || !std::isfinite(p->beta)) { *why = "need 1 <= alpha <= beta"; return MLC_ERR_INVALID_ARG; }
+  if (I.P < 1) { *why = "P must be >= 1"; return MLC_ERR_INVALID_ARG; }
+  if (I.Q != 4 && I.Q != 6) { *why = "Q must be 4 (L19) or 6 (L27)"; return MLC_ERR_UNSUPPORTED; }
+  if (p->conv_precision != MLC_CONV_FP32 && p->conv_precision != MLC_CONV_FP64) { *why = "bad conv_precision"; return MLC_ERR_INVALID_ARG; }
+  if (I.b < 1 || I.b > 4) { *why = "interpolation radius must be in [1, 4]"; return MLC_ERR_UNSUPPORTED; }
+  if (I.P > 4) { *why = "P > 4 is not built (the Boole Gram matrix is then not diagonal)"; return MLC_ERR_UNSUPPORTED; }
+  if (I.n > 32) { *why = "patch size above 32 is not built"; return MLC_ERR_UNSUPPORTED; }
+  if (I.Z != 32 && I.Z != 64 && I.Z != 128) { *why = "DGF half-width must be 32, 64 or 128"; return MLC_ERR_UNSUPPORTED; }
+  I.K = I.P * (I.P + 1) * (I.P + 2) / 6;
+  I.d_alpha = margin_of(p->alpha, I.n);
+  I.d_beta = margin_of(p->beta, I.n);
+  if (I.d_alpha % NREF || I.d_beta % NREF) { *why = "localisation margins must be multiples of 4"; return MLC_ERR_UNSUPPORTED; }
+  if (I.d_alpha > I.n) { *why = "alpha > 3 is not built"; return MLC_ERR_UNSUPPORTED; }
+  I.e = I.d_alpha + NREF * I.b;
+  I.patches_per_axis = I.N / I.n;
+  I.npatch = I.patches_per_axis * I.patches_per_axis * I.patches_per_axis;
+  int Mmin = 2 * (I.n + I.e) + 1;
+  if (p->fft_size) {
+    if (p->fft_size < Mmin) { *why = "fft_size below the Hockney minimum 2(n+e)+1"; return MLC_ERR_INVALID_ARG; }
+    if (!conv_size_ok(p->conv_precision, I.n, p->fft_size)) { *why = "fft_size not built for this patch size"; return MLC_ERR_UNSUPPORTED; }
+    I.M = p->fft_size;
+  } else {
+    I.M = pick_conv(p->conv_precision, I.n, Mmin);
+    if (I.M < 0) { *why = "no built local FFT size fits this problem"; return MLC_ERR_UNSUPPORTED; }
+  }
+  if (I.M / 2 > I.Z) { *why = "DGF table too small for the local torus"; return MLC_ERR_UNSUPPORTED; }
+  I.Wc = (I.n + 2 * I.e) / NREF + 1;
+  I.Wa = I.n + 2 * I.d_alpha + 1;
+  {
+    int P0 = -((I.d_alpha / I.n) * I.n);
+    I.nplanes_a = (I.n + I.d_alpha - P0) / I.n + 1;
+  }
+  I.S_lo = -I.d_beta / NREF;
+  I.Ns = (I.N + 2 * I.d_beta) / NREF + 1;
+  I.O_lo = -I.b;
+  I.No = I.N / NREF + 2 * I.b + 1;
+  I.M_coarse = pick_fft(I.Ns + I.No - 1, 2 * I.Z);
+  if (I.M_coarse < 0) { *why = "coarse grid too large for the built FFT sizes / DGF table"; return MLC_ERR_UNSUPPORTED; }
+  const int eb = I.d_beta + NREF * I.b;
+  if (I.d_beta > I.d_alpha) {
+    int Wt = I.n + 2 * eb + 1;
+    I.M_table = pick_fft(Wt + I.n, 2 * I.Z);
+    if (I.M_table < 0) { *why = "far-field table box too large for the built FFT sizes / DGF table"; return MLC_ERR_UNSUPPORTED; }
+  } else {
+    I.M_table = 0;
+  }
+  *o = I;
+  return MLC_OK;
+}
+
+extern "C" mlc_status mlc_problem_info(const mlc_problem* prob, mlc_plan_info* out) {
+  std::string why;
+  mlc_status s = derive(prob, out, &why);
+  if (s != MLC_OK) return fail(nullptr, s, why);
+  return MLC_OK;
+}
+
+extern "C" mlc_status mlc_last_error(mlc_context* ctx, char* buf, size_t len) {
+  if (!buf || len == 0) return MLC_ERR_INVALID_ARG;
+  const std::string& m = ctx ? ctx->last_error : g_error;
+  std::snprintf(buf, len, "%s", m.c_str());
+  return MLC_OK;
+}
+
+// ------------------------------------------------------------- context
+extern "C" mlc_status mlc_context_create(int device, size_t hbm_budget_bytes, mlc_context** out) {
+  if (!out) return fail(nullptr, MLC_ERR_INVALID_ARG, "null output pointer");
+  int count = 0;
+  hipError_t e = hipGetDeviceCount(&count);
+  if (e != hipSuccess || count <= 0) return fail(nullptr, MLC_ERR_DEVICE, "no HIP device available");
+  if (device < 0 || device >= count) return fail(nullptr, MLC_ERR_INVALID_ARG, "device index out of range");
+  e = hipSetDevice(device);
+  if (e != hipSuccess) return fail(nullptr, MLC_ERR_DEVICE, hipGetErrorString(e));
+  auto* c = new (std::nothrow) mlc_context;
+  if (!c) return fail(nullptr, MLC_ERR_OUT_OF_MEMORY, "host allocation failed");
+  c->device = device;
+  c->budget = hbm_budget_bytes;
+  *out = c;
+  return MLC_OK;
+}
+
+extern "C" mlc_status mlc_context_destroy(mlc_context* ctx) {
+  if (!ctx) return MLC_ERR_INVALID_ARG;
+  hipSetDevice(ctx->device);
+  for (auto& kv : ctx->dgf) hipFree(kv.second);
+  delete ctx;
+  return MLC_OK;
+}
+
+static inline unsigned blocks_for(int64_t n, int t = 256) { return unsigned((n + t - 1) / t); }
+
+// ----------------------------------------------------- generic 3-D FFT
+template <int M>
+static void fft3_impl(cplx<double>* data, int dir, hipStream_t s) {
+  constexpr int NL = (M % 4 == 0) ? 4 : 2;
+  dim3 grid(M / NL, M);
+  for (int axis = 0; axis < 3; ++axis) {
+    if (dir > 0) hipLaunchKernelGGL((fft_axis_kernel<double, M, NL, 1>), grid, dim3(256), 0, s, data, axis);
+    else hipLaunchKernelGGL((fft_axis_kernel<double, M, NL, -1>), grid, dim3(256), 0, s, data, axis);
+  }
+}
+static bool fft3(cplx<double>* data, int M, int dir, hipStream_t s) {
+  switch (M) {
+#define CASE(MM) case MM: fft3_impl<MM>(data, dir, s); return true;
+    MLC_FFT_SIZES(CASE)
+#undef CASE
+  }
+  return false;
+}
+
+// --------------------------------------------------------- DGF table
+template <int MF, int NLC>
+static void dst3(double* data, int Nd, hipStream_t s) {
+  dim3 grid((Nd + 2 * NLC - 1) / (2 * NLC), Nd);
+  for (int axis = 0; axis < 3; ++axis)
+    hipLaunchKernelGGL((dst1_axis_kernel<MF, NLC>), grid, dim3(256), 0, s, data, axis);
+}
+
+static mlc_status get_dgf(mlc_context* ctx, int Q, int Z, double** table) {
+  auto key = std::make_pair(Q, Z);
+  auto it = ctx->dgf.find(key);
+  if (it != ctx->dgf.end()) { *table = it->second; return MLC_OK; }
+  HIP_TRY(ctx, hipSetDevice(ctx->device));
+  const int L = 2 * Z, Nd = 2 * L - 1, W = 2 * Z + 1;
+  double* rhs = nullptr;
+  double* tab = nullptr;
+  if (hipMalloc(&rhs, sizeof(double) * cube(Nd)) != hipSuccess)
+    return fail(ctx, MLC_ERR_OUT_OF_MEMORY, "DGF work array allocation failed");
+  if (hipMalloc(&tab, sizeof(double) * cube(W)) != hipSuccess) {
+    hipFree(rhs);
+    return fail(ctx, MLC_ERR_OUT_OF_MEMORY, "DGF table allocation failed");
+  }
+  Stencil st = stencil_of(Q);
+  hipStream_t s = nullptr;
+  hipLaunchKernelGGL(dgf_rhs_kernel, dim3(blocks_for(cube(Nd))), dim3(256), 0, s, rhs, L, st);
+  auto run = [&](void) {
+    if (L * 4 == 1024) dst3<1024, 4>(rhs, Nd, s);
+    else if (L * 4 == 512) dst3<512, 8>(rhs, Nd, s);
+    else dst3<256, 8>(rhs, Nd, s);
+  };
+  run();
+  hipLaunchKernelGGL(dgf_divide_kernel, dim3(blocks_for(cube(Nd))), dim3(256), 0, s, rhs, L, st);
+  run();
+  hipLaunchKernelGGL(dgf_restrict_kernel, dim3(blocks_for(cube(W))), dim3(256), 0, s, rhs, tab, L, Z);
+  hipError_t e = hipDeviceSynchronize();
+  hipFree(rhs);
+  if (e != hipSuccess) {
+    hipFree(tab);
+    return fail(ctx, MLC_ERR_DEVICE, std::string("DGF build: ") + hipGetErrorString(e));
+  }
+  ctx->dgf[key] = tab;
+  *table = tab;
+  return MLC_OK;
+}
+
+extern "C" mlc_status mlc_dgf_table(mlc_context* ctx, int32_t Q, int32_t Z, const double** table) {
+  if (!ctx || !table) return fail(ctx, MLC_ERR_INVALID_ARG, "null argument");
+  if (Q != 4 && Q != 6) return fail(ctx, MLC_ERR_UNSUPPORTED, "Q must be 4 or 6");
+  if (Z != 32 && Z != 64 && Z != 128) return fail(ctx, MLC_ERR_UNSUPPORTED, "Z must be 32, 64 or 128");
+  double* t = nullptr;
+  mlc_status s = get_dgf(ctx, Q, Z, &t);
+  if (s != MLC_OK) return s;
+  *table = t;
+  return MLC_OK;
+}
+
+// ----------------------------------------------------------------- plan
+static size_t align_up(size_t v) { return (v + 255) & ~size_t(255); }
+
+static void plan_destroy_buffers(mlc_plan* p) {
+  hipFree(p->conv_spec);
+  hipFree(p->coarse_spec);
+  hipFree(p->T);
+  hipFree(p->D);
+  p->conv_spec = nullptr; p->coarse_spec = nullptr; p->T = nullptr; p->D = nullptr;
+}
+
+// spectrum of the periodised DGF on an M^3 torus -> real octant (fp64 work)
+static mlc_status build_spectrum(mlc_context* ctx, const double* G1, int Z, int M, cplx<double>* work,
+                                 double* oct64, void* octT, int Tsize, double scale, int p0, int p1, int p2) {
+  hipStream_t s = nullptr;
+  hipLaunchKernelGGL(fill_periodic_dgf_kernel, dim3(blocks_for(cube(M))), dim3(256), 0, s, work, G1, Z, M);
+  if (!fft3(work, M, 1, s)) return fail(ctx, MLC_ERR_UNSUPPORTED, "FFT size not built");
+  const int Mh = M / 2 + 1;
+  if (oct64)
+    hipLaunchKernelGGL(spectrum_octant_kernel<double>, dim3(blocks_for(cube(Mh))), dim3(256), 0, s, work, oct64, M,
+                       scale, p0, p1, p2);
+  if (octT) {
+    if (Tsize == 4)
+      hipLaunchKernelGGL(spectrum_octant_kernel<float>, dim3(blocks_for(cube(Mh))), dim3(256), 0, s, work,
+                         (float*)octT, M, scale, p0, p1, p2);
+    else
+      hipLaunchKernelGGL(spectrum_octant_kernel<double>, dim3(blocks_for(cube(Mh))), dim3(256), 0, s, work,
+                         (double*)octT, M, scale, p0, p1, p2);
+  }
+  return MLC_OK;
+}
+
+static mlc_status build_tables(mlc_plan* P, const double* G1) {
+  mlc_context* ctx = P->ctx;
+  const mlc_plan_info& I = P->info;
+  const int Mt = I.M_table, Mth = Mt / 2 + 1, K = I.K;
+  hipStream_t s = nullptr;
+  cplx<double>* work = nullptr;
+  double* oct = nullptr;
+  double* coarse = nullptr;
+  double* planes = nullptr;
+  const int64_t nc = cube(P->Wtc), npl = int64_t(3) * P->nplb * P->Wb * P->Wb;
+  bool ok = hipMalloc(&work, sizeof(cplx<double>) * cube(Mt)) == hipSuccess &&
+            hipMalloc(&oct, sizeof(double) * cube(Mth)) == hipSuccess &&
+            hipMalloc(&coarse, sizeof(double) * nc) == hipSuccess &&
+            hipMalloc(&planes, sizeof(double) * npl) == hipSuccess &&
+            hipMalloc(&P->T, sizeof(double) * cube(P->Wbc) * K) == hipSuccess &&
+            hipMalloc(&P->D, sizeof(double) * npl * K) == hipSuccess;
+  mlc_status st = MLC_OK;
+  if (!ok) st = fail(ctx, MLC_ERR_OUT_OF_MEMORY, "far-field table allocation failed");
+  if (st == MLC_OK) st = build_spectrum(ctx, G1, I.Z, Mt, work, oct, nullptr, 8, 1.0, 0, 1, 2);
+  const double h = I.h, R = I.n * h / 2.0;
+  const double scale = h * h / (double(Mt) * Mt * Mt);
+  const Stencil stc = stencil_of(I.Q);
+  for (int k = 0; st == MLC_OK && k < K; ++k) {
+    hipMemsetAsync(work, 0, sizeof(cplx<double>) * cube(Mt), s);
+    hipLaunchKernelGGL(fill_mode_source_kernel, dim3(blocks_for(cube(I.n + 1))), dim3(256), 0, s, work, Mt, I.n,
+                       P->modes.p[k][0], P->modes.p[k][1], P->modes.p[k][2], std::pow(R, -1.5));
+    fft3(work, Mt, 1, s);
+    hipLaunchKernelGGL(mul_real_even_kernel, dim3(blocks_for(cube(Mt))), dim3(256), 0, s, work, oct, Mt);
+    fft3(work, Mt, -1, s);
+    hipLaunchKernelGGL(extract_mode_kernel, dim3(blocks_for(nc + npl)), dim3(256), 0, s, work, Mt, scale, I.n, P->eb,
+                       I.d_beta, P->P0b, P->nplb, coarse, planes);
+    hipLaunchKernelGGL(annulus_coarse_table_kernel, dim3(blocks_for(cube(P->Wbc))), dim3(256), 0, s, coarse, P->T,
+                       I.n, P->eb, I.d_beta, I.d_alpha, stc, 1.0 / (I.H * I.H), K, k);
+    hipLaunchKernelGGL(annulus_plane_table_kernel, dim3(blocks_for(npl)), dim3(256), 0, s, planes, coarse, P->D, I.n,
+                       P->eb, I.d_beta, I.d_alpha, P->P0b, P->nplb, I.b, K, k);
+  }
+  if (st == MLC_OK) {
+    hipError_t e = hipDeviceSynchronize();
+    if (e != hipSuccess) st = fail(ctx, MLC_ERR_DEVICE, std::string("table build: ") + hipGetErrorString(e));
+  }
+  hipFree(work); hipFree(oct); hipFree(coarse); hipFree(planes);
+  return st;
+}
+
+extern "C" mlc_status mlc_plan_create(mlc_context* ctx, const mlc_problem* prob, mlc_plan** out) {
+  if (!ctx || !prob || !out) return fail(ctx, MLC_ERR_INVALID_ARG, "null argument");
+  std::string why;
+  mlc_plan_info I{};
+  mlc_status s = derive(prob, &I, &why);
+  if (s != MLC_OK) return fail(ctx, s, why);
+  HIP_TRY(ctx, hipSetDevice(ctx->device));
+  auto* P = new (std::nothrow) mlc_plan;
+  if (!P) return fail(ctx, MLC_ERR_OUT_OF_MEMORY, "host allocation failed");
+  P->ctx = ctx;
+  P->prob = *prob;
+  P->info = I;
+  P->S = I.n + 1;
+  P->Mh = I.M / 2 + 1;
+  P->Wp = I.Wa + 2 * I.b;
+  P->P0 = -((I.d_alpha / I.n) * I.n);
+  P->eb = I.d_beta + NREF * I.b;
+  P->Wtc = (I.n + 2 * P->eb) / NREF + 1;
+  P->Wb = I.n + 2 * I.d_beta + 1;
+  P->Wbc = (I.n + 2 * I.d_beta) / NREF + 1;
+  P->P0b = -((I.d_beta / I.n) * I.n);
+  P->nplb = (I.n + I.d_beta - P->P0b) / I.n + 1;
+  P->Kann = I.d_beta > I.d_alpha ? I.K : 0;
+  P->modes = mode_list(I.P);
+  double* G1 = nullptr;
+  s = get_dgf(ctx, I.Q, I.Z, &G1);
+  if (s != MLC_OK) { delete P; return s; }
+  const int tsz = I.conv_precision == MLC_CONV_FP32 ? 4 : 8;
+  // local-convolution spectrum: layout [kx][kz'][ky'] (kx: fastest array axis)
+  {
+    cplx<double>* work = nullptr;
+    const int M = I.M, Mh = P->Mh;
+    if (hipMalloc(&work, sizeof(cplx<double>) * cube(M)) != hipSuccess ||
+        hipMalloc(&P->conv_spec, size_t(tsz) * cube(Mh)) != hipSuccess) {
+      hipFree(work);
+      plan_destroy_buffers(P);
+      delete P;
+      return fail(ctx, MLC_ERR_OUT_OF_MEMORY, "spectrum allocation failed");
+    }
+    s = build_spectrum(ctx, G1, I.Z, M, work, nullptr, P->conv_spec, tsz, 1.0 / (double(M) * M * M), 2, 0, 1);
+    if (s == MLC_OK) {
+      // coarse spectrum (fp64 octant, layout k0 k1 k2)
+      const int Mc = I.M_coarse, Mch = Mc / 2 + 1;
+      cplx<double>* cw = nullptr;
+      if (hipMalloc(&cw, sizeof(cplx<double>) * cube(Mc)) != hipSuccess ||
+          hipMalloc(&P->coarse_spec, sizeof(double) * cube(Mch)) != hipSuccess) {
+        s = fail(ctx, MLC_ERR_OUT_OF_MEMORY, "coarse spectrum allocation failed");
+      } else {
+        s = build_spectrum(ctx, G1, I.Z, Mc, cw, P->coarse_spec, nullptr, 8, 1.0, 0, 1, 2);
+      }
+      hipError_t e = hipDeviceSynchronize();
+      hipFree(cw);
+      if (s == MLC_OK && e != hipSuccess) s = fail(ctx, MLC_ERR_DEVICE, hipGetErrorString(e));
+    }
+    hipFree(work);
+    if (s != MLC_OK) { plan_destroy_buffers(P); delete P; return s; }
+  }
+  if (P->Kann > 0) {
+    s = build_tables(P, G1);
+    if (s != MLC_OK) { plan_destroy_buffers(P); delete P; return s; }
+  }
+  // workspace layout
+  {
+    const size_t cs = tsz * 2;   // complex in conv precision
+    size_t o = 0;
+    auto take = [&](size_t bytes) { size_t at = o; o = align_up(o + bytes); return at; };
+    P->o_mom = take(sizeof(double) * I.npatch * I.K);
+    P->o_X = take(cs * I.npatch * P->Mh * P->S * P->S);
+    P->o_Z = take(cs * size_t(I.npatch) * P->Wp * P->Mh * I.M);
+    P->o_cs = take(size_t(tsz) * I.npatch * cube(I.Wc));
+    P->o_pl = take(size_t(tsz) * I.npatch * 3 * I.nplanes_a * I.Wa * I.Wa);
+    P->o_F = take(sizeof(double) * cube(I.Ns));
+    P->o_tor = take(sizeof(cplx<double>) * cube(I.M_coarse));
+    P->o_phiH = take(sizeof(double) * cube(I.No));
+    P->o_phiB = take(sizeof(double) * cube(I.N + 1));
+    P->o_dir = take(sizeof(double) * I.npatch * cube(I.n - 1));
+    P->ws_total = o;
+  }
+  *out = P;
+  return MLC_OK;
+}
+
+extern "C" mlc_status mlc_plan_destroy(mlc_plan* plan) {
+  if (!plan) return MLC_ERR_INVALID_ARG;
+  hipSetDevice(plan->ctx->device);
+  plan_destroy_buffers(plan);
+  delete plan;
+  return MLC_OK;
+}
+
+extern "C" mlc_status mlc_plan_get_info(const mlc_plan* plan, mlc_plan_info* out) {
+  if (!plan || !out) return MLC_ERR_INVALID_ARG;
+  *out = plan->info;
+  return MLC_OK;
+}
+
+extern "C" mlc_status mlc_plan_workspace_bytes(const mlc_plan* plan, size_t* bytes) {
+  if (!plan || !bytes) return MLC_ERR_INVALID_ARG;
+  *bytes = plan->ws_total;
+  return MLC_OK;
+}
+
+extern "C" mlc_status mlc_workspace_view(const mlc_plan* plan, void* ws, int32_t which, void** ptr,
+                                         size_t* bytes) {
+  if (!plan || !ws || !ptr) return MLC_ERR_INVALID_ARG;
+  const mlc_plan_info& I = plan->info;
+  const size_t tsz = I.conv_precision == MLC_CONV_FP32 ? 4 : 8;
+  char* b = static_cast<char*>(ws);
+  size_t at = 0, len = 0;
+  switch (which) {
+    case MLC_VIEW_MOMENTS: at = plan->o_mom; len = sizeof(double) * I.npatch * I.K; break;
+    case MLC_VIEW_COARSE_RHS: at = plan->o_F; len = sizeof(double) * cube(I.Ns); break;
+    case MLC_VIEW_COARSE_PHI: at = plan->o_phiH; len = sizeof(double) * cube(I.No); break;
+    case MLC_VIEW_BOUNDARY: at = plan->o_phiB; len = sizeof(double) * cube(I.N + 1); break;
+    case MLC_VIEW_LOCAL_COARSE: at = plan->o_cs; len = tsz * I.npatch * cube(I.Wc); break;
+    case MLC_VIEW_LOCAL_PLANES: at = plan->o_pl; len = tsz * I.npatch * 3 * I.nplanes_a * I.Wa * I.Wa; break;
+    default: return fail(plan->ctx, MLC_ERR_INVALID_ARG, "unknown workspace view");
+  }
+  *ptr = b + at;
+  if (bytes) *bytes = len;
+  return MLC_OK;
+}
+
+// ---------------------------------------------------------------- solve
+template <typename T, int n, int M>
+static void launch_conv(const mlc_plan* P, const double* f, char* ws, hipStream_t s) {
+  const mlc_plan_info& I = P->info;
+  cplx<T>* X = reinterpret_cast<cplx<T>*>(ws + P->o_X);
+  cplx<T>* Zb = reinterpret_cast<cplx<T>*>(ws + P->o_Z);
+  T* cs = reinterpret_cast<T*>(ws + P->o_cs);
+  T* pl = reinterpret_cast<T*>(ws + P->o_pl);
+  hipLaunchKernelGGL((conv_xdft_kernel<T, M>), dim3(P->S, I.npatch), dim3(256), 0, s, f, I.N, I.n,
+                     I.patches_per_axis, X);
+  hipLaunchKernelGGL((conv_yz_kernel<T, n, M>), dim3(P->Mh, I.npatch), dim3(256), 0, s, X,
+                     static_cast<const T*>(P->conv_spec), Zb, P->Wp, I.b, I.Wa, I.e, I.d_alpha);
+  OutGeom g{I.n, I.e, I.d_alpha, I.b, I.Wa, P->Wp, I.Wc, P->P0, I.nplanes_a, I.h * I.h};
+  hipLaunchKernelGGL((conv_out_kernel<T, n, M>), dim3(P->Wp, I.npatch), dim3(256), 0, s, Zb, cs, pl, g);
+}
+
+template <typename T>
+static bool dispatch_conv(const mlc_plan* P, const double* f, char* ws, hipStream_t s) {
+  const int n = P->info.n, M = P->info.M;
+#define CASE(nn, MM) if (n == nn && M == MM) { launch_conv<T, nn, MM>(P, f, ws, s); return true; }
+  if constexpr (sizeof(T) == 4) { MLC_CONV_SIZES_F32(CASE) }
+  else { MLC_CONV_SIZES_F64(CASE) }
+#undef CASE
+  return false;
+}
+
+template <typename T>
+static void launch_rest(const mlc_plan* P, const double* f, double* phi, char* ws, hipStream_t s) {
+  const mlc_plan_info& I = P->info;
+  const Stencil st = stencil_of(I.Q);
+  const T* cs = reinterpret_cast<const T*>(ws + P->o_cs);
+  T* pl = reinterpret_cast<T*>(ws + P->o_pl);
+  double* mom = reinterpret_cast<double*>(ws + P->o_mom);
+  double* F = reinterpret_cast<double*>(ws + P->o_F);
+  cplx<double>* tor = reinterpret_cast<cplx<double>*>(ws + P->o_tor);
+  double* phiH = reinterpret_cast<double*>(ws + P->o_phiH);
+  double* phiB = reinterpret_cast<double*>(ws + P->o_phiB);
+  double* dir = reinterpret_cast<double*>(ws + P->o_dir);
+  // coarse right-hand side
+  CoarseGeom cg{I.n, I.patches_per_axis, P->Kann, I.d_alpha, I.d_beta, I.e, I.Wc, I.S_lo, I.Ns, P->Wbc,
+                1.0 / (I.H * I.H)};
+  hipLaunchKernelGGL(coarse_rhs_kernel<T>, dim3(blocks_for(cube(I.Ns))), dim3(256), 0, s, cs, mom, P->T, st, cg, F);
+  // coarse solve
+  const int Mc = I.M_coarse;
+  hipLaunchKernelGGL(coarse_fill_kernel, dim3(blocks_for(cube(Mc))), dim3(256), 0, s, F, tor, I.Ns, Mc);
+  fft3(tor, Mc, 1, s);
+  hipLaunchKernelGGL(mul_real_even_kernel, dim3(blocks_for(cube(Mc))), dim3(256), 0, s, tor, P->coarse_spec, Mc);
+  fft3(tor, Mc, -1, s);
+  hipLaunchKernelGGL(coarse_extract_kernel, dim3(blocks_for(cube(I.No))), dim3(256), 0, s, tor, phiH, Mc, I.S_lo,
+                     I.O_lo, I.No, I.H * I.H / (double(Mc) * Mc * Mc));
+  // local plane corrections delta_i = phi_i - I(phi_i)
+  {
+    int64_t per = int64_t(3) * I.nplanes_a * I.Wa * I.Wa;
+    hipLaunchKernelGGL(plane_delta_kernel<T>, dim3(blocks_for(per), I.npatch), dim3(256), 0, s, pl, cs, I.n, I.e,
+                       I.d_alpha, I.Wa, I.Wc, P->P0, I.nplanes_a, I.b);
+  }
+  // boundary values on the skeleton (+ phi there)
+  {
+    SkelGeom sg{I.N, I.n, I.patches_per_axis, P->Kann, I.d_alpha, I.d_beta, I.b, I.Wa, P->P0, I.nplanes_a, P->Wb,
+                P->P0b, P->nplb, I.O_lo, I.No, I.h * I.h / 12.0};
+    int64_t cnt = int64_t(3) * (I.N / I.n + 1) * (I.N + 1) * (I.N + 1);
+    hipLaunchKernelGGL(skeleton_kernel<T>, dim3(blocks_for(cnt)), dim3(256), 0, s, phiH, pl, mom, P->D, f, sg,
+                       phiB, phi);
+  }
+  // Dirichlet solves + Mehrstellen correction on the patch interiors
+  {
+    const int m = I.n - 1;
+    dim3 g3(blocks_for(cube(m)), I.npatch);
+    hipLaunchKernelGGL(dirichlet_rhs_kernel, g3, dim3(256), 0, s, f, phiB, I.N, I.n, I.patches_per_axis, st,
+                       I.h * I.h, dir);
+    dim3 gs(m, I.npatch);
+    for (int a = 0; a < 3; ++a)
+      hipLaunchKernelGGL(dst_small_axis_kernel, gs, dim3(256), 0, s, dir, dir, I.n, a, 1.0);
+    hipLaunchKernelGGL(dirichlet_divide_kernel, g3, dim3(256), 0, s, dir, I.n, st);
+    for (int a = 0; a < 3; ++a)
+      hipLaunchKernelGGL(dst_small_axis_kernel, gs, dim3(256), 0, s, dir, dir, I.n, a, 2.0 / I.n);
+    hipLaunchKernelGGL(dirichlet_final_kernel, g3, dim3(256), 0, s, dir, f, I.N, I.n, I.patches_per_axis,
+                       I.h * I.h / 12.0, phi);
+  }
+}
+
+static mlc_status enqueue_solve(mlc_plan* P, const double* f, double* phi, char* ws, hipStream_t s) {
+  const mlc_plan_info& I = P->info;
+  double* mom = reinterpret_cast<double*>(ws + P->o_mom);
+  hipLaunchKernelGGL(moments_kernel, dim3(I.npatch), dim3(256), 0, s, f, I.N, I.n, I.patches_per_axis, P->modes,
+                     std::pow(I.n * I.h / 2.0, 1.5), mom);
+  bool ok;
+  if (I.conv_precision == MLC_CONV_FP32) {
+    ok = dispatch_conv<float>(P, f, ws, s);
+    if (ok) launch_rest<float>(P, f, phi, ws, s);
+  } else {
+    ok = dispatch_conv<double>(P, f, ws, s);
+    if (ok) launch_rest<double>(P, f, phi, ws, s);
+  }
+  if (!ok) return fail(P->ctx, MLC_ERR_UNSUPPORTED, "local FFT size not built");
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return fail(P->ctx, MLC_ERR_DEVICE, std::string("launch: ") + hipGetErrorString(e));
+  return MLC_OK;
+}
+
+extern "C" mlc_status mlc_solve(mlc_plan* plan, const double* f, double* phi, void* workspace, size_t ws_bytes,
+                                void* stream) {
+  if (!plan || !f || !phi || !workspace) return fail(plan ? plan->ctx : nullptr, MLC_ERR_INVALID_ARG, "null argument");
+  if (ws_bytes < plan->ws_total) return fail(plan->ctx, MLC_ERR_INVALID_ARG, "workspace too small");
+  if (reinterpret_cast<uintptr_t>(workspace) % 256)
+    return fail(plan->ctx, MLC_ERR_INVALID_ARG, "workspace must be 256-byte aligned");
+  HIP_TRY(plan->ctx, hipSetDevice(plan->ctx->device));
+  return enqueue_solve(plan, f, phi, static_cast<char*>(workspace), static_cast<hipStream_t>(stream));
+}
+
+extern "C" mlc_status mlc_batch_workspace_bytes(int32_t count, mlc_plan* const* plans, size_t* bytes) {
+  if (count <= 0 || !plans || !bytes) return fail(nullptr, MLC_ERR_INVALID_ARG, "bad batch arguments");
+  size_t tot = 0;
+  for (int k = 0; k < count; ++k) {
+    if (!plans[k]) return fail(nullptr, MLC_ERR_INVALID_ARG, "null plan in batch");
+    tot = align_up(tot + plans[k]->ws_total);
+  }
+  *bytes = tot;
+  return MLC_OK;
+}
+
+extern "C" mlc_status mlc_solve_batched(int32_t count, mlc_plan* const* plans, const double* const* f,
+                                        double* const* phi, void* workspace, size_t ws_bytes, void* stream) {
+  size_t need = 0;
+  mlc_status st = mlc_batch_workspace_bytes(count, plans, &need);
+  if (st != MLC_OK) return st;
+  if (!f || !phi || !workspace) return fail(plans[0]->ctx, MLC_ERR_INVALID_ARG, "null argument");
+  if (ws_bytes < need) return fail(plans[0]->ctx, MLC_ERR_INVALID_ARG, "workspace too small");
+  for (int k = 0; k < count; ++k)
+    if (!f[k] || !phi[k]) return fail(plans[0]->ctx, MLC_ERR_INVALID_ARG, "null array in batch");
+  char* ws = static_cast<char*>(workspace);
+  size_t off = 0;
+  for (int k = 0; k < count; ++k) {
+    st = mlc_solve(plans[k], f[k], phi[k], ws + off, plans[k]->ws_total, stream);
+    if (st != MLC_OK) return st;
+    off = align_up(off + plans[k]->ws_total);
+  }
+  return MLC_OK;
+}

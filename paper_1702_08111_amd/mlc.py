@@ -1,0 +1,210 @@
+"""ctypes binding of libmlc (include/mlc.h).  Argument marshalling only:
+every step of a solve runs in the library's HIP kernels.
+
+Device arrays are passed as torch CUDA tensors (their data_ptr()) or as raw
+integers; streams as torch.cuda.Stream or raw hipStream_t integers.
+"""
+import ctypes
+import os
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libmlc.so")
+
+MLC_OK = 0
+MLC_ERR_INVALID_ARG = -1
+MLC_ERR_UNSUPPORTED = -2
+MLC_ERR_OUT_OF_MEMORY = -3
+MLC_ERR_DEVICE = -4
+MLC_ERR_BUSY = -5
+MLC_ERR_NOT_READY = -6
+
+MLC_CONV_FP64 = 0
+MLC_CONV_FP32 = 1
+
+MLC_VIEW_MOMENTS = 0
+MLC_VIEW_COARSE_RHS = 1
+MLC_VIEW_COARSE_PHI = 2
+MLC_VIEW_BOUNDARY = 3
+MLC_VIEW_LOCAL_COARSE = 4
+MLC_VIEW_LOCAL_PLANES = 5
+
+
+class mlc_problem(ctypes.Structure):
+    _fields_ = [
+        ("n_cells", ctypes.c_int32),
+        ("h", ctypes.c_double),
+        ("patch", ctypes.c_int32),
+        ("alpha", ctypes.c_double),
+        ("beta", ctypes.c_double),
+        ("P", ctypes.c_int32),
+        ("Q", ctypes.c_int32),
+        ("interp_b", ctypes.c_int32),
+        ("conv_precision", ctypes.c_int32),
+        ("fft_size", ctypes.c_int32),
+        ("dgf_half_width", ctypes.c_int32),
+    ]
+
+
+class mlc_plan_info(ctypes.Structure):
+    _fields_ = [(name, ctypes.c_int32) for name in (
+        "N", "n", "P", "Q", "b", "K", "d_alpha", "d_beta", "e", "patches_per_axis", "npatch",
+        "M", "M_coarse", "M_table", "Wc", "Wa", "nplanes_a", "S_lo", "Ns", "O_lo", "No", "Z",
+        "conv_precision")] + [("h", ctypes.c_double), ("H", ctypes.c_double)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+# every symbol declared in include/mlc.h, with its ctypes signature
+_P = ctypes.c_void_p
+_SIGS = {
+    "mlc_status_string": (ctypes.c_char_p, [ctypes.c_int]),
+    "mlc_problem_info": (ctypes.c_int, [ctypes.POINTER(mlc_problem), ctypes.POINTER(mlc_plan_info)]),
+    "mlc_context_create": (ctypes.c_int, [ctypes.c_int, ctypes.c_size_t, ctypes.POINTER(_P)]),
+    "mlc_context_destroy": (ctypes.c_int, [_P]),
+    "mlc_last_error": (ctypes.c_int, [_P, ctypes.c_char_p, ctypes.c_size_t]),
+    "mlc_plan_create": (ctypes.c_int, [_P, ctypes.POINTER(mlc_problem), ctypes.POINTER(_P)]),
+    "mlc_plan_destroy": (ctypes.c_int, [_P]),
+    "mlc_plan_get_info": (ctypes.c_int, [_P, ctypes.POINTER(mlc_plan_info)]),
+    "mlc_plan_workspace_bytes": (ctypes.c_int, [_P, ctypes.POINTER(ctypes.c_size_t)]),
+    "mlc_solve": (ctypes.c_int, [_P, _P, _P, _P, ctypes.c_size_t, _P]),
+    "mlc_batch_workspace_bytes": (ctypes.c_int, [ctypes.c_int32, ctypes.POINTER(_P), ctypes.POINTER(ctypes.c_size_t)]),
+    "mlc_solve_batched": (ctypes.c_int, [ctypes.c_int32, ctypes.POINTER(_P), ctypes.POINTER(_P), ctypes.POINTER(_P),
+                                         _P, ctypes.c_size_t, _P]),
+    "mlc_workspace_view": (ctypes.c_int, [_P, _P, ctypes.c_int32, ctypes.POINTER(_P), ctypes.POINTER(ctypes.c_size_t)]),
+    "mlc_dgf_table": (ctypes.c_int, [_P, ctypes.c_int32, ctypes.c_int32, ctypes.POINTER(_P)]),
+}
+
+_lib = None
+
+
+def lib():
+    """The loaded libmlc; raises if the library has not been built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError("libmlc.so is not built (run __graft_entry__.build())")
+        L = ctypes.CDLL(LIB_PATH)
+        for name, (res, args) in _SIGS.items():
+            fn = getattr(L, name)
+            fn.restype = res
+            fn.argtypes = args
+        _lib = L
+    return _lib
+
+
+class MLCError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"{status_string(status)}: {msg}")
+        self.status = status
+
+
+def status_string(s):
+    return lib().mlc_status_string(s).decode()
+
+
+def _check(status, ctx=None):
+    if status != MLC_OK:
+        buf = ctypes.create_string_buffer(512)
+        lib().mlc_last_error(ctx, buf, 512)
+        raise MLCError(status, buf.value.decode())
+
+
+def _ptr(x):
+    if x is None:
+        return None
+    if isinstance(x, int):
+        return x
+    return x.data_ptr()
+
+
+def _stream(s):
+    if s is None:
+        import torch
+        return torch.cuda.current_stream().cuda_stream
+    if isinstance(s, int):
+        return s
+    return s.cuda_stream
+
+
+def problem(N, n, alpha=3.0, beta=6.0, P=4, Q=4, b=0, h=None, conv="fp32", fft_size=0, Z=0):
+    return mlc_problem(N, (1.0 / N) if h is None else h, n, alpha, beta, P, Q, b,
+                       MLC_CONV_FP32 if conv == "fp32" else MLC_CONV_FP64, fft_size, Z)
+
+
+def problem_info(prob):
+    info = mlc_plan_info()
+    _check(lib().mlc_problem_info(ctypes.byref(prob), ctypes.byref(info)))
+    return info.as_dict()
+
+
+class Context:
+    def __init__(self, device=0, hbm_budget=0):
+        h = ctypes.c_void_p()
+        _check(lib().mlc_context_create(device, hbm_budget, ctypes.byref(h)))
+        self.handle = h
+
+    def close(self):
+        if self.handle:
+            lib().mlc_context_destroy(self.handle)
+            self.handle = None
+
+    def dgf_table(self, Q, Z=128):
+        p = ctypes.c_void_p()
+        _check(lib().mlc_dgf_table(self.handle, Q, Z, ctypes.byref(p)), self.handle)
+        return p.value
+
+    def plan(self, prob):
+        return Plan(self, prob)
+
+
+class Plan:
+    def __init__(self, ctx, prob):
+        self.ctx = ctx
+        h = ctypes.c_void_p()
+        _check(lib().mlc_plan_create(ctx.handle, ctypes.byref(prob), ctypes.byref(h)), ctx.handle)
+        self.handle = h
+        info = mlc_plan_info()
+        _check(lib().mlc_plan_get_info(h, ctypes.byref(info)), ctx.handle)
+        self.info = info.as_dict()
+        nb = ctypes.c_size_t()
+        _check(lib().mlc_plan_workspace_bytes(h, ctypes.byref(nb)), ctx.handle)
+        self.workspace_bytes = nb.value
+
+    def close(self):
+        if self.handle:
+            lib().mlc_plan_destroy(self.handle)
+            self.handle = None
+
+    def solve(self, f, phi, workspace, stream=None):
+        """Enqueue one solve; f, phi, workspace are device tensors/pointers."""
+        nbytes = workspace.numel() * workspace.element_size() if hasattr(workspace, "numel") else self.workspace_bytes
+        _check(lib().mlc_solve(self.handle, _ptr(f), _ptr(phi), _ptr(workspace), nbytes, _stream(stream)),
+               self.ctx.handle)
+
+    def view(self, workspace, which):
+        """(device pointer, bytes) of an intermediate held in the workspace."""
+        p = ctypes.c_void_p()
+        n = ctypes.c_size_t()
+        _check(lib().mlc_workspace_view(self.handle, _ptr(workspace), which, ctypes.byref(p), ctypes.byref(n)),
+               self.ctx.handle)
+        return p.value, n.value
+
+
+def solve_batched(plans, fs, phis, workspace, stream=None):
+    k = len(plans)
+    PA = ctypes.c_void_p * k
+    hp = PA(*[p.handle.value for p in plans])
+    fp = PA(*[_ptr(x) for x in fs])
+    pp = PA(*[_ptr(x) for x in phis])
+    nbytes = workspace.numel() * workspace.element_size()
+    _check(lib().mlc_solve_batched(k, hp, fp, pp, _ptr(workspace), nbytes, _stream(stream)), plans[0].ctx.handle)
+
+
+def batch_workspace_bytes(plans):
+    k = len(plans)
+    PA = ctypes.c_void_p * k
+    hp = PA(*[p.handle.value for p in plans])
+    n = ctypes.c_size_t()
+    _check(lib().mlc_batch_workspace_bytes(k, hp, ctypes.byref(n)))
+    return n.value

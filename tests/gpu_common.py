@@ -1,0 +1,80 @@
+"""Helpers shared by the GPU tests: run a solve through the C ABI and pull
+the intermediates out of the workspace; build the oracle's counterparts."""
+import numpy as np
+
+import mlc_inputs as mi
+from oracle import mlc as omlc
+from oracle.dgf import dgf_cached
+from paper_1702_08111_amd import mlc as gm
+
+_ctx = None
+
+
+def context():
+    global _ctx
+    if _ctx is None:
+        _ctx = gm.Context(0)
+    return _ctx
+
+
+def _slice(ws, plan, which, dtype, shape):
+    import torch
+    ptr, nbytes = plan.view(ws, which)
+    off = ptr - ws.data_ptr()
+    t = ws[off:off + nbytes].view(dtype)
+    return t.reshape(shape).cpu().numpy()
+
+
+def gpu_solve(prob, f_np, keep=True, plan=None):
+    import torch
+    ctx = context()
+    if plan is None:
+        plan = ctx.plan(prob)
+    info = plan.info
+    f = torch.from_numpy(np.ascontiguousarray(f_np)).cuda()
+    phi = torch.empty_like(f)
+    ws = torch.empty(plan.workspace_bytes, dtype=torch.uint8, device="cuda")
+    plan.solve(f, phi, ws)
+    torch.cuda.synchronize()
+    out = {"phi": phi.cpu().numpy(), "info": info}
+    if keep:
+        cdt = torch.float32 if info["conv_precision"] == gm.MLC_CONV_FP32 else torch.float64
+        npch, K, Ns, No, N = info["npatch"], info["K"], info["Ns"], info["No"], info["N"]
+        Wc, Wa, npl = info["Wc"], info["Wa"], info["nplanes_a"]
+        out["moments"] = _slice(ws, plan, gm.MLC_VIEW_MOMENTS, torch.float64, (npch, K))
+        out["FH"] = _slice(ws, plan, gm.MLC_VIEW_COARSE_RHS, torch.float64, (Ns, Ns, Ns))
+        out["phiH"] = _slice(ws, plan, gm.MLC_VIEW_COARSE_PHI, torch.float64, (No, No, No))
+        out["phiB"] = _slice(ws, plan, gm.MLC_VIEW_BOUNDARY, torch.float64, (N + 1,) * 3)
+        out["local_coarse"] = _slice(ws, plan, gm.MLC_VIEW_LOCAL_COARSE, cdt, (npch, Wc, Wc, Wc))
+        out["local_delta"] = _slice(ws, plan, gm.MLC_VIEW_LOCAL_PLANES, cdt, (npch, 3, npl, Wa, Wa))
+    return out
+
+
+def oracle_params(info, alpha, beta):
+    return omlc.Params(N=info["N"], n=info["n"], alpha=alpha, beta=beta, P=info["P"], Q=info["Q"],
+                       b=info["b"], Z=info["Z"])
+
+
+def oracle_local(prm, f, i):
+    """Coarse samples and plane corrections delta = phi_i - I(phi_i) of one
+    patch's local field, laid out like the workspace views."""
+    G1 = dgf_cached(prm.Q, prm.Z)
+    arr = omlc.local_field(G1, prm, omlc.patch_charge(f, prm.n, i))
+    n, e, da, b = prm.n, prm.e, prm.d_alpha, prm.bb
+    coarse = arr[::4, ::4, ::4]
+    P0 = -((da // n) * n)
+    npl = (n + da - P0) // n + 1
+    A = omlc.interp_matrix(b, -da, n + da, -e // 4, (n + e) // 4)
+    delta = np.zeros((3, npl, n + 2 * da + 1, n + 2 * da + 1))
+    for d in range(3):
+        for j in range(npl):
+            plane = np.take(arr, P0 + j * n + e, axis=d)
+            fine = plane[e - da:e + n + da + 1, e - da:e + n + da + 1]
+            delta[d, j] = fine - A @ plane[::4, ::4] @ A.T
+    return coarse, delta
+
+
+def rel(a, b):
+    a = np.asarray(a, dtype=np.float64)
+    b = np.asarray(b, dtype=np.float64)
+    return float(np.abs(a - b).max() / max(np.abs(b).max(), 1e-300))

@@ -1,0 +1,72 @@
+"""Host-side checks of the C ABI (no device work): the library loads,
+exports every function include/mlc.h declares, and validates problems."""
+import os
+import re
+
+import pytest
+
+from paper_1702_08111_amd import mlc
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _header_functions():
+    txt = open(os.path.join(ROOT, "include", "mlc.h")).read()
+    txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+    return sorted(set(re.findall(r"\b(mlc_[a-z_]+)\s*\(", txt)))
+
+
+def test_library_exports_every_declared_function():
+    L = mlc.lib()
+    names = _header_functions()
+    assert len(names) >= 14
+    for name in names:
+        assert hasattr(L, name), name
+    assert set(names) == set(mlc._SIGS), "binding and header disagree"
+
+
+def test_status_strings():
+    assert mlc.status_string(0) == "MLC_OK"
+    assert mlc.status_string(-2) == "MLC_ERR_UNSUPPORTED"
+
+
+@pytest.mark.parametrize("name,N,n,Q,fft,expect", [
+    ("32^3 plain", 32, 8, 4, 0, dict(d_alpha=8, d_beta=20, e=16, M=50, Wc=11, Wa=25, nplanes_a=4, Ns=19, No=13)),
+    ("128^3", 128, 16, 4, 96, dict(d_alpha=16, d_beta=40, e=24, M=96, Wc=17, Wa=49, Ns=53, No=37, M_coarse=90)),
+    ("256^3 L27", 256, 32, 6, 0, dict(d_alpha=32, d_beta=80, e=44, M=160, Wc=31, Wa=97, nplanes_a=4, Ns=105,
+                                        No=71, M_coarse=180, npatch=512, M_table=250)),
+])
+def test_derived_sizes(name, N, n, Q, fft, expect):
+    info = mlc.problem_info(mlc.problem(N, n, 3.0, 6.0, 4, Q, conv="fp32", fft_size=fft))
+    for k, v in expect.items():
+        assert info[k] == v, (k, info[k], v)
+    assert info["K"] == 20
+
+
+@pytest.mark.parametrize("kw,status", [
+    (dict(N=30, n=8), mlc.MLC_ERR_INVALID_ARG),          # N % n
+    (dict(N=36, n=6), mlc.MLC_ERR_INVALID_ARG),          # n % 4
+    (dict(N=32, n=8, alpha=3, beta=2), mlc.MLC_ERR_INVALID_ARG),
+    (dict(N=32, n=8, Q=5), mlc.MLC_ERR_UNSUPPORTED),
+    (dict(N=32, n=8, P=5), mlc.MLC_ERR_UNSUPPORTED),
+    (dict(N=32, n=8, alpha=1.5, beta=1.5), mlc.MLC_ERR_UNSUPPORTED),   # margin 2 not a multiple of 4
+    (dict(N=32, n=8, fft_size=40), mlc.MLC_ERR_INVALID_ARG),           # below 2(n+e)+1
+    (dict(N=32, n=8, Z=100), mlc.MLC_ERR_UNSUPPORTED),
+])
+def test_validation(kw, status):
+    args = dict(N=32, n=8, alpha=3.0, beta=6.0, P=4, Q=4)
+    args.update(kw)
+    with pytest.raises(mlc.MLCError) as ei:
+        mlc.problem_info(mlc.problem(**args))
+    assert ei.value.status == status
+
+
+def test_context_without_device_fails_cleanly():
+    """Without a usable GPU the context call reports MLC_ERR_DEVICE instead
+    of crashing; with one it succeeds."""
+    import ctypes
+    h = ctypes.c_void_p()
+    st = mlc.lib().mlc_context_create(0, 0, ctypes.byref(h))
+    assert st in (mlc.MLC_OK, mlc.MLC_ERR_DEVICE)
+    if st == mlc.MLC_OK:
+        mlc.lib().mlc_context_destroy(h)

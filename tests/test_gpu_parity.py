@@ -1,0 +1,89 @@
+"""GPU parity against the oracle, through the C ABI (MI355X only).
+
+Bars: float64 path within 1e-12 relative max-norm of the oracle; float32
+local convolutions within 2e-6 on phi (every other stage is float64)."""
+import numpy as np
+import pytest
+
+import mlc_inputs as mi
+from oracle import mlc as omlc
+from oracle.dgf import dgf_cached
+from paper_1702_08111_amd import mlc as gm
+
+from gpu_common import context, gpu_solve, oracle_local, oracle_params, rel
+
+pytestmark = pytest.mark.gpu
+
+TOL64 = 1e-12
+TOL32 = 2e-6
+
+
+@pytest.mark.parametrize("Q", [4, 6])
+def test_dgf_table(Q):
+    """The GPU's DGF (DST-I Dirichlet solve, appendix A.1) equals the oracle's."""
+    import torch
+    ctx = context()
+    Z = 64
+    ptr = ctx.dgf_table(Q, Z)
+    W = 2 * Z + 1
+    t = torch.empty(W ** 3, dtype=torch.float64, device="cuda")
+    # copy through torch from the raw device pointer
+    import ctypes
+    hip = ctypes.CDLL("libamdhip64.so")
+    hip.hipMemcpy.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t, ctypes.c_int]
+    assert hip.hipMemcpy(ctypes.c_void_p(t.data_ptr()), ctypes.c_void_p(ptr), W ** 3 * 8, 3) == 0
+    g = t.cpu().numpy().reshape(W, W, W)
+    o = dgf_cached(Q, Z)
+    assert rel(g, o) < 1e-13
+
+
+def _case(name):
+    cases = {
+        # (N, n, alpha, beta, P, Q, fft, Z, bumps)
+        "plain32": (32, 8, 3.0, 6.0, 4, 4, 0, 64, mi.one_bump()),
+        "plain32_q6": (32, 8, 3.0, 6.0, 4, 6, 0, 64, mi.bumps(2, 7, radius=(0.15, 0.25))),
+        "mlc0_32": (32, 8, 3.0, 3.0, 4, 4, 0, 64, mi.bumps(2, 8, radius=(0.15, 0.25))),
+        "p1_32": (32, 8, 3.0, 6.0, 1, 4, 0, 64, mi.bumps(3, 9, radius=(0.1, 0.2))),
+        "ragged48": (48, 16, 3.0, 6.0, 4, 4, 90, 128, mi.bumps(2, 11, radius=(0.12, 0.2))),
+    }
+    return cases[name]
+
+
+def _check_all(name, conv):
+    N, n, alpha, beta, P, Q, fft, Z, bumps = _case(name)
+    f = mi.bump_charge(N, bumps)
+    prob = gm.problem(N, n, alpha, beta, P, Q, conv=conv, fft_size=fft, Z=Z)
+    g = gpu_solve(prob, f)
+    prm = oracle_params(g["info"], alpha, beta)
+    phi, o = omlc.mlc_solve(f, prm, dgf_cached(Q, Z), keep=True)
+    sk = omlc.skeleton_mask(N, n)
+    errs = {
+        "moments": rel(g["moments"], o["moments"]),
+        "FH": rel(g["FH"], o["FH"]),
+        "phiH": rel(g["phiH"], o["phiH"]),
+        "phiB": rel(g["phiB"][sk], o["phiB"][sk]),
+        "phi": rel(g["phi"], phi),
+    }
+    # local fields of a few patches, including corners of the patch lattice
+    ppa = N // n
+    for i in [(0, 0, 0), (ppa - 1, ppa // 2, 0), (ppa // 2, ppa // 2, ppa // 2)]:
+        pidx = (i[0] * ppa + i[1]) * ppa + i[2]
+        c, dl = oracle_local(prm, f, i)
+        errs[f"coarse{i}"] = rel(g["local_coarse"][pidx], c)
+        errs[f"delta{i}"] = rel(g["local_delta"][pidx], dl)
+    print(name, conv, {k: f"{v:.2e}" for k, v in errs.items()}, flush=True)
+    return errs
+
+
+@pytest.mark.parametrize("name", ["plain32", "plain32_q6", "mlc0_32", "p1_32", "ragged48"])
+def test_fp64_parity(name):
+    errs = _check_all(name, "fp64")
+    for k, v in errs.items():
+        assert v < TOL64, (k, v)
+
+
+@pytest.mark.parametrize("name", ["plain32", "plain32_q6", "ragged48"])
+def test_fp32_parity(name):
+    errs = _check_all(name, "fp32")
+    assert errs["phi"] < TOL32, errs
+    assert errs["moments"] < TOL64
