@@ -1,0 +1,244 @@
+"""Benchmark of the two-level MLC solve on one MI355X.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload fp32_256_q6]
+
+One step = one full two-level MLC solve (local convolutions, moments, coarse
+right-hand side, coarse solve, skeleton boundary values, Dirichlet solves,
+correction) of a 256^3 problem whose charge already sits in HBM.  Prints one
+JSON line: grid points/s (N^3 per solve) of the float32-convolution path,
+with the float64 path, the errors, p50/p99 latency, the roofline of the
+dominant kernel and the CPU oracle timed on a bounded sample.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+import mlc_inputs as mi
+
+HBM_PEAK_GBS = 8000.0          # MI355X HBM3E
+FP32_PEAK_TFLOPS = 157.3       # MI355X fp32 vector
+FP64_PEAK_TFLOPS = 78.6
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", default="fp32_256_q6")
+    ap.add_argument("--fp64-steps", type=int, default=5)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-budget", type=float, default=15.0, help="seconds of sampled per-patch oracle work")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="also run a plain device copy of known size (for HBM counter scaling)")
+    return ap.parse_args()
+
+
+def kernel_model(info):
+    """Algorithmic bytes and flops per launch of each local-convolution kernel
+    (whole batch of patches).  Bytes: the kernel's compulsory reads and writes
+    in HBM (inputs once, outputs once).  Flops: nominal FFT counts
+    5 L log2 L per complex line of length L, 4 per real x complex MAC,
+    2 per real x complex product."""
+    conv = 4 if info["conv_precision"] == 1 else 8       # bytes per real in conv precision
+    cb = 2 * conv                                        # complex
+    n, M, P = info["n"], info["M"], info["npatch"]
+    S, Mh = n + 1, M // 2 + 1
+    Wp = info["Wa"] + 2 * info["b"]
+    Wc, Wa, npl = info["Wc"], info["Wa"], info["nplanes_a"]
+    lg = np.log2(M)
+    fft = 5.0 * M * lg
+    X = P * Mh * S * S * cb
+    Zb = P * Wp * Mh * M * cb
+    outs = P * (Wc ** 3 + 3 * npl * Wa * Wa) * conv
+    return {
+        "conv_xdft": dict(bytes=P * S ** 3 * 8 + X, flops=P * S * Mh * S * S * 4.0),
+        "conv_yz": dict(bytes=X + Zb + Mh ** 3 * conv,
+                        flops=P * Mh * (S * fft + M * 2 * fft + 2.0 * M * M)),
+        "conv_out": dict(bytes=Zb + outs, flops=P * Wp * (Mh * fft + ((Wp + 1) // 2) * fft)),
+    }
+
+
+def cpu_baseline(name, budget):
+    import scipy.fft
+    cores = len(os.sched_getaffinity(0))
+    with scipy.fft.set_workers(cores):
+        return _cpu_baseline(name, budget, cores)
+
+
+def _cpu_baseline(name, budget, cores):
+    """The oracle (oracle/, float64 NumPy/SciPy, untuned) on the host cores:
+    its per-patch step-1 work (local field, moments, coarse charges, skeleton
+    contributions) on a sample of patches within `budget` seconds, plus the
+    global work (coarse solve, coarse interpolation, all Dirichlet solves)
+    once; the full-solve time is estimated as per-patch x patches + global.
+    Plan-time tables (DGF, Legendre far fields) are excluded, as on the GPU.
+    SciPy's FFTs run with one worker per available core."""
+    from oracle import legendre as leg
+    from oracle import mlc as om
+    from oracle import convolution as oconv
+    from oracle.dgf import dgf
+
+    N, n, Q, bumps = mi.workload(name)
+    f = mi.bump_charge(N, bumps)
+    prm = om.Params(N=N, n=n, alpha=3.0, beta=6.0, P=4, Q=Q, Z=128)
+    G1 = dgf(Q, 128)
+    Phi, T, Phi_lo, _ = om.far_field_tables(G1, prm)
+    tabs = om._annulus_plane_tables(Phi, Phi_lo, prm)
+    patches = om.patch_indices(N, n)
+    order = np.random.default_rng(0).permutation(len(patches))
+    S_lo, S_hi, O_lo, O_hi = om.coarse_boxes(prm)
+    FH = np.zeros((S_hi - S_lo + 1,) * 3)
+    accum = np.zeros((N + 1,) * 3)
+    cache = {}
+    e, da = prm.e, prm.d_alpha
+    done = 0
+    t0 = time.perf_counter()
+    while done < len(patches) and (time.perf_counter() - t0 < budget or done < 2):
+        i = patches[order[done]]
+        lo = n * i
+        phi_i = om.local_field(G1, prm, om.patch_charge(f, n, i), "fft", cache)
+        c = leg.moments(f[lo[0]:lo[0] + n + 1, lo[1]:lo[1] + n + 1, lo[2]:lo[2] + n + 1], n, prm.P, prm.R)
+        lap = om.coarse_laplacian_of_samples(phi_i, Q, prm.H)
+        lap_lo = (lo - e) // 4 + 1
+        ca_lo, ca_hi = (lo - da) // 4, (lo + n + da) // 4
+        FH[tuple(slice(ca_lo[d] - S_lo, ca_hi[d] - S_lo + 1) for d in range(3))] += \
+            lap[tuple(slice(ca_lo[d] - lap_lo[d], ca_hi[d] - lap_lo[d] + 1) for d in range(3))]
+        om._accumulate_local(accum, phi_i, lo, prm)
+        om._accumulate_annulus(accum, c, tabs, lo, prm)
+        done += 1
+    t_patch = (time.perf_counter() - t0) / done
+    t1 = time.perf_counter()
+    phiH = prm.H ** 2 * oconv.conv_hockney(G1, prm.Z, FH, np.full(3, O_lo - S_lo), np.full(3, O_hi - S_lo))
+    phiB = accum + om._interp_coarse_everywhere(phiH, O_lo, prm)
+    for i in patches:
+        lo = n * i
+        sl = tuple(slice(lo[d], lo[d] + n + 1) for d in range(3))
+        om.dirichlet_solve(phiB[sl], f[sl], Q, prm.hh)
+    t_global = time.perf_counter() - t1
+    est = t_patch * len(patches) + t_global
+    return {
+        "value": float(N ** 3 / est), "unit": "grid points/s", "cores": cores, "kind": "oracle",
+        "sample": (f"oracle float64 step-1 work on {done} of {len(patches)} patches "
+                   f"({t_patch:.3f} s/patch) + global coarse solve/interpolation/Dirichlet "
+                   f"({t_global:.1f} s); full solve estimated {est:.1f} s"),
+    }
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the path is single-GPU "
+              "and multi-GPU sharding is described in DESIGN.md, not built.", file=sys.stderr)
+        sys.exit(2)
+    import torch
+    from paper_1702_08111_amd import mlc as gm
+
+    N, n, Q, bumps = mi.workload(args.workload)
+    f_np = mi.bump_charge(N, bumps)
+    exact = mi.bump_potential(N, bumps)
+    dev = torch.device("cuda:0")
+    f = torch.from_numpy(f_np).to(dev)
+    ctx = gm.Context(0)
+    p32 = ctx.plan(gm.problem(N, n, 3.0, 6.0, 4, Q, conv="fp32"))
+    p64 = ctx.plan(gm.problem(N, n, 3.0, 6.0, 4, Q, conv="fp64"))
+    ws = torch.empty(max(p32.workspace_bytes, p64.workspace_bytes), dtype=torch.uint8, device=dev)
+    phi32 = torch.empty_like(f)
+    phi64 = torch.empty_like(f)
+    stream = torch.cuda.current_stream()
+
+    def timed(plan, phi, steps, warmup, timing):
+        for _ in range(warmup):
+            plan.solve(f, phi, ws, stream)
+        torch.cuda.synchronize()
+        if timing:
+            plan.set_timing(True)
+        ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(steps)]
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for k in range(steps):
+            ev[k][0].record(stream)
+            plan.solve(f, phi, ws, stream)
+            ev[k][1].record(stream)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        lat = np.array([a.elapsed_time(b) for a, b in ev])
+        kt = plan.timing() if timing else {}
+        if timing:
+            plan.set_timing(False)
+        return (t1 - t0) * 1e3 / steps, lat, kt
+
+    ms32, lat32, kt32 = timed(p32, phi32, args.steps, args.warmup, True)
+    ms64, lat64, _ = timed(p64, phi64, args.fp64_steps, 1, False)
+    a32, a64 = phi32.cpu().numpy(), phi64.cpu().numpy()
+    scale = np.abs(a64).max()
+    err_32_64 = float(np.abs(a32 - a64).max() / scale)
+    err64_exact = float(np.abs(a64 - exact).max() / np.abs(exact).max())
+    err32_exact = float(np.abs(a32 - exact).max() / np.abs(exact).max())
+
+    # roofline of the dominant kernel (largest measured time per solve)
+    model = kernel_model(p32.info)
+    per_kernel = {k: v[1] / v[0] for k, v in kt32.items()}   # ms per launch
+    dom = max(per_kernel, key=per_kernel.get)
+    roof = None
+    if dom in model:
+        t = per_kernel[dom] * 1e-3
+        gbs = model[dom]["bytes"] / t / 1e9
+        tfs = model[dom]["flops"] / t / 1e12
+        if gbs / HBM_PEAK_GBS >= tfs / FP32_PEAK_TFLOPS:
+            roof = {"bound": "hbm", "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                    "frac": round(gbs / HBM_PEAK_GBS, 4), "traffic": None}
+        else:
+            roof = {"bound": "alu", "achieved": round(tfs, 2), "peak": FP32_PEAK_TFLOPS, "unit": "TFLOP/s",
+                    "frac": round(tfs / FP32_PEAK_TFLOPS, 4), "traffic": None}
+        roof["kernel"] = dom
+        roof["ms_per_launch"] = round(per_kernel[dom], 4)
+
+    if args.copy_calibration:
+        src = torch.empty(256 * 1024 * 1024, dtype=torch.uint8, device=dev)
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        cpu = cpu_baseline(args.workload, args.cpu_budget)
+
+    value = N ** 3 / (ms32 * 1e-3)
+    line = {
+        "metric": "grid points/s per MLC solve at 256^3, FP32 vs FP64 at stated err; p50/p99 latency",
+        "value": value,
+        "unit": "grid points/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms32,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32 local convolutions, f64 elsewhere",
+        "data": "synthetic",
+        "config": {"workload": f"two-level MLC, {N}^3 cells, {n}^3-cell patches ({N // n}^3 = "
+                               f"{(N // n) ** 3}), L{19 if Q == 4 else 27} (Q={Q}), alpha=3, beta=6, P=4, "
+                               f"{len(bumps)} seeded compact bumps",
+                   "N": N, "patch": n, "Q": Q, "alpha": 3.0, "beta": 6.0, "P": 4,
+                   "fft_size": p32.info["M"], "coarse_fft": p32.info["M_coarse"]},
+        "p50_ms": float(np.percentile(lat32, 50)),
+        "p99_ms": float(np.percentile(lat32, 99)),
+        "fp64": {"value": N ** 3 / (ms64 * 1e-3), "ms_per_step": ms64,
+                 "p50_ms": float(np.percentile(lat64, 50)), "p99_ms": float(np.percentile(lat64, 99))},
+        "error": {"fp32_vs_fp64_relmax": err_32_64, "fp64_vs_closed_form": err64_exact,
+                  "fp32_vs_closed_form": err32_exact},
+        "kernels_ms": {k: round(v, 4) for k, v in sorted(per_kernel.items(), key=lambda kv: -kv[1])},
+        "roofline": roof,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -155,6 +155,21 @@ mlc_status mlc_workspace_view(const mlc_plan* plan, void* workspace, int32_t whi
  * (appendix A.1).  The pointer stays owned by the context.  Synchronises. */
 mlc_status mlc_dgf_table(mlc_context* ctx, int32_t Q, int32_t Z, const double** table);
 
+/* Per-kernel timing of solves (instrumentation, not part of the method).
+ * While enabled, every kernel a solve with this plan enqueues is bracketed
+ * by HIP events on the solve's stream.  mlc_plan_timing waits for the
+ * recorded events, then reports, per kernel name, the number of launches
+ * and their summed duration in milliseconds since timing was enabled; it
+ * fills at most `max` entries and sets *count to the number of distinct
+ * kernels.  Enabling resets the sums. */
+typedef struct {
+  char name[48];
+  int32_t launches;
+  double total_ms;
+} mlc_kernel_time;
+mlc_status mlc_plan_set_timing(mlc_plan* plan, int32_t enable);
+mlc_status mlc_plan_timing(mlc_plan* plan, mlc_kernel_time* out, int32_t max, int32_t* count);
+
 #ifdef __cplusplus
 }
 #endif

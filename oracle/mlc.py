@@ -366,7 +366,7 @@ def _annulus_plane_tables(Phi, Phi_lo, prm):
             planes = np.take(Phi, P - Phi_lo, axis=d + 1)            # (K, a0, a1) over the table box
             fine = planes[:, eb - db:eb + n + db + 1, eb - db:eb + n + db + 1]
             coarse = planes[:, ::NREF, ::NREF]
-            out[(d, P)] = fine - np.einsum("xa,kab,yb->kxy", A, coarse, A)
+            out[(d, P)] = fine - A @ coarse @ A.T
     return out
 
 

@@ -41,6 +41,42 @@ struct mlc_plan {
   double* D = nullptr;
   size_t o_mom = 0, o_X = 0, o_Z = 0, o_cs = 0, o_pl = 0, o_F = 0, o_tor = 0, o_phiH = 0, o_phiB = 0, o_dir = 0;
   size_t ws_total = 0;
+  // per-kernel timing (instrumentation)
+  struct Pending { const char* name; hipEvent_t a, b; };
+  mutable bool timing_on = false;
+  mutable std::vector<Pending> pending;
+  mutable std::vector<hipEvent_t> event_pool;
+  mutable std::vector<std::pair<std::string, std::pair<int, double>>> acc;
+};
+
+static hipEvent_t pool_event(const mlc_plan* P) {
+  if (!P->event_pool.empty()) {
+    hipEvent_t e = P->event_pool.back();
+    P->event_pool.pop_back();
+    return e;
+  }
+  hipEvent_t e = nullptr;
+  hipEventCreate(&e);
+  return e;
+}
+
+// Brackets one launch (or a fixed group of launches) with timing events when
+// timing is enabled on the plan.
+struct TimedScope {
+  const mlc_plan* P;
+  hipStream_t s;
+  const char* name;
+  hipEvent_t a = nullptr;
+  TimedScope(const mlc_plan* p, hipStream_t st, const char* nm) : P(p), s(st), name(nm) {
+    if (P->timing_on) { a = pool_event(P); hipEventRecord(a, s); }
+  }
+  ~TimedScope() {
+    if (P->timing_on && a) {
+      hipEvent_t b = pool_event(P);
+      hipEventRecord(b, s);
+      P->pending.push_back({name, a, b});
+    }
+  }
 };
 
 static thread_local std::string g_error;   // errors before a context exists
@@ -463,9 +499,50 @@ extern "C" mlc_status mlc_plan_create(mlc_context* ctx, const mlc_problem* prob,
   return MLC_OK;
 }
 
+static void drain_timing(const mlc_plan* P) {
+  for (auto& pe : P->pending) {
+    hipEventSynchronize(pe.b);
+    float ms = 0.f;
+    hipEventElapsedTime(&ms, pe.a, pe.b);
+    bool found = false;
+    for (auto& kv : P->acc)
+      if (kv.first == pe.name) { kv.second.first += 1; kv.second.second += ms; found = true; break; }
+    if (!found) P->acc.push_back({pe.name, {1, double(ms)}});
+    P->event_pool.push_back(pe.a);
+    P->event_pool.push_back(pe.b);
+  }
+  P->pending.clear();
+}
+
+extern "C" mlc_status mlc_plan_set_timing(mlc_plan* plan, int32_t enable) {
+  if (!plan) return fail(nullptr, MLC_ERR_INVALID_ARG, "null plan");
+  drain_timing(plan);
+  plan->acc.clear();
+  plan->timing_on = enable != 0;
+  return MLC_OK;
+}
+
+extern "C" mlc_status mlc_plan_timing(mlc_plan* plan, mlc_kernel_time* out, int32_t max, int32_t* count) {
+  if (!plan || !count || (max > 0 && !out)) return fail(plan ? plan->ctx : nullptr, MLC_ERR_INVALID_ARG, "bad argument");
+  drain_timing(plan);
+  int k = 0;
+  for (auto& kv : plan->acc) {
+    if (k < max) {
+      std::snprintf(out[k].name, sizeof(out[k].name), "%s", kv.first.c_str());
+      out[k].launches = kv.second.first;
+      out[k].total_ms = kv.second.second;
+    }
+    ++k;
+  }
+  *count = k;
+  return MLC_OK;
+}
+
 extern "C" mlc_status mlc_plan_destroy(mlc_plan* plan) {
   if (!plan) return MLC_ERR_INVALID_ARG;
   hipSetDevice(plan->ctx->device);
+  drain_timing(plan);
+  for (hipEvent_t e : plan->event_pool) hipEventDestroy(e);
   plan_destroy_buffers(plan);
   delete plan;
   return MLC_OK;
@@ -512,12 +589,21 @@ static void launch_conv(const mlc_plan* P, const double* f, char* ws, hipStream_
   cplx<T>* Zb = reinterpret_cast<cplx<T>*>(ws + P->o_Z);
   T* cs = reinterpret_cast<T*>(ws + P->o_cs);
   T* pl = reinterpret_cast<T*>(ws + P->o_pl);
-  hipLaunchKernelGGL((conv_xdft_kernel<T, M>), dim3(P->S, I.npatch), dim3(256), 0, s, f, I.N, I.n,
-                     I.patches_per_axis, X);
-  hipLaunchKernelGGL((conv_yz_kernel<T, n, M>), dim3(P->Mh, I.npatch), dim3(256), 0, s, X,
-                     static_cast<const T*>(P->conv_spec), Zb, P->Wp, I.b, I.Wa, I.e, I.d_alpha);
+  {
+    TimedScope ts(P, s, "conv_xdft");
+    hipLaunchKernelGGL((conv_xdft_kernel<T, M>), dim3(P->S, I.npatch), dim3(256), 0, s, f, I.N, I.n,
+                       I.patches_per_axis, X);
+  }
+  {
+    TimedScope ts(P, s, "conv_yz");
+    hipLaunchKernelGGL((conv_yz_kernel<T, n, M>), dim3(P->Mh, I.npatch), dim3(256), 0, s, X,
+                       static_cast<const T*>(P->conv_spec), Zb, P->Wp, I.b, I.Wa, I.e, I.d_alpha);
+  }
   OutGeom g{I.n, I.e, I.d_alpha, I.b, I.Wa, P->Wp, I.Wc, P->P0, I.nplanes_a, I.h * I.h};
-  hipLaunchKernelGGL((conv_out_kernel<T, n, M>), dim3(P->Wp, I.npatch), dim3(256), 0, s, Zb, cs, pl, g);
+  {
+    TimedScope ts(P, s, "conv_out");
+    hipLaunchKernelGGL((conv_out_kernel<T, n, M>), dim3(P->Wp, I.npatch), dim3(256), 0, s, Zb, cs, pl, g);
+  }
 }
 
 template <typename T>
@@ -545,17 +631,24 @@ static void launch_rest(const mlc_plan* P, const double* f, double* phi, char* w
   // coarse right-hand side
   CoarseGeom cg{I.n, I.patches_per_axis, P->Kann, I.d_alpha, I.d_beta, I.e, I.Wc, I.S_lo, I.Ns, P->Wbc,
                 1.0 / (I.H * I.H)};
-  hipLaunchKernelGGL(coarse_rhs_kernel<T>, dim3(blocks_for(cube(I.Ns))), dim3(256), 0, s, cs, mom, P->T, st, cg, F);
+  {
+    TimedScope ts(P, s, "coarse_rhs");
+    hipLaunchKernelGGL(coarse_rhs_kernel<T>, dim3(blocks_for(cube(I.Ns))), dim3(256), 0, s, cs, mom, P->T, st, cg, F);
+  }
   // coarse solve
   const int Mc = I.M_coarse;
-  hipLaunchKernelGGL(coarse_fill_kernel, dim3(blocks_for(cube(Mc))), dim3(256), 0, s, F, tor, I.Ns, Mc);
-  fft3(tor, Mc, 1, s);
-  hipLaunchKernelGGL(mul_real_even_kernel, dim3(blocks_for(cube(Mc))), dim3(256), 0, s, tor, P->coarse_spec, Mc);
-  fft3(tor, Mc, -1, s);
-  hipLaunchKernelGGL(coarse_extract_kernel, dim3(blocks_for(cube(I.No))), dim3(256), 0, s, tor, phiH, Mc, I.S_lo,
-                     I.O_lo, I.No, I.H * I.H / (double(Mc) * Mc * Mc));
+  {
+    TimedScope ts(P, s, "coarse_solve");
+    hipLaunchKernelGGL(coarse_fill_kernel, dim3(blocks_for(cube(Mc))), dim3(256), 0, s, F, tor, I.Ns, Mc);
+    fft3(tor, Mc, 1, s);
+    hipLaunchKernelGGL(mul_real_even_kernel, dim3(blocks_for(cube(Mc))), dim3(256), 0, s, tor, P->coarse_spec, Mc);
+    fft3(tor, Mc, -1, s);
+    hipLaunchKernelGGL(coarse_extract_kernel, dim3(blocks_for(cube(I.No))), dim3(256), 0, s, tor, phiH, Mc, I.S_lo,
+                       I.O_lo, I.No, I.H * I.H / (double(Mc) * Mc * Mc));
+  }
   // local plane corrections delta_i = phi_i - I(phi_i)
   {
+    TimedScope ts(P, s, "plane_delta");
     int64_t per = int64_t(3) * I.nplanes_a * I.Wa * I.Wa;
     hipLaunchKernelGGL(plane_delta_kernel<T>, dim3(blocks_for(per), I.npatch), dim3(256), 0, s, pl, cs, I.n, I.e,
                        I.d_alpha, I.Wa, I.Wc, P->P0, I.nplanes_a, I.b);
@@ -565,12 +658,14 @@ static void launch_rest(const mlc_plan* P, const double* f, double* phi, char* w
     SkelGeom sg{I.N, I.n, I.patches_per_axis, P->Kann, I.d_alpha, I.d_beta, I.b, I.Wa, P->P0, I.nplanes_a, P->Wb,
                 P->P0b, P->nplb, I.O_lo, I.No, I.h * I.h / 12.0};
     int64_t cnt = int64_t(3) * (I.N / I.n + 1) * (I.N + 1) * (I.N + 1);
+    TimedScope ts(P, s, "skeleton");
     hipLaunchKernelGGL(skeleton_kernel<T>, dim3(blocks_for(cnt)), dim3(256), 0, s, phiH, pl, mom, P->D, f, sg,
                        phiB, phi);
   }
   // Dirichlet solves + Mehrstellen correction on the patch interiors
   {
     const int m = I.n - 1;
+    TimedScope ts(P, s, "dirichlet");
     dim3 g3(blocks_for(cube(m)), I.npatch);
     hipLaunchKernelGGL(dirichlet_rhs_kernel, g3, dim3(256), 0, s, f, phiB, I.N, I.n, I.patches_per_axis, st,
                        I.h * I.h, dir);
@@ -588,8 +683,11 @@ static void launch_rest(const mlc_plan* P, const double* f, double* phi, char* w
 static mlc_status enqueue_solve(mlc_plan* P, const double* f, double* phi, char* ws, hipStream_t s) {
   const mlc_plan_info& I = P->info;
   double* mom = reinterpret_cast<double*>(ws + P->o_mom);
-  hipLaunchKernelGGL(moments_kernel, dim3(I.npatch), dim3(256), 0, s, f, I.N, I.n, I.patches_per_axis, P->modes,
-                     std::pow(I.n * I.h / 2.0, 1.5), mom);
+  {
+    TimedScope ts(P, s, "moments");
+    hipLaunchKernelGGL(moments_kernel, dim3(I.npatch), dim3(256), 0, s, f, I.N, I.n, I.patches_per_axis, P->modes,
+                       std::pow(I.n * I.h / 2.0, 1.5), mom);
+  }
   bool ok;
   if (I.conv_precision == MLC_CONV_FP32) {
     ok = dispatch_conv<float>(P, f, ws, s);

@@ -55,6 +55,10 @@ class mlc_plan_info(ctypes.Structure):
         return {k: getattr(self, k) for k, _ in self._fields_}
 
 
+class mlc_kernel_time(ctypes.Structure):
+    _fields_ = [("name", ctypes.c_char * 48), ("launches", ctypes.c_int32), ("total_ms", ctypes.c_double)]
+
+
 # every symbol declared in include/mlc.h, with its ctypes signature
 _P = ctypes.c_void_p
 _SIGS = {
@@ -73,6 +77,9 @@ _SIGS = {
                                          _P, ctypes.c_size_t, _P]),
     "mlc_workspace_view": (ctypes.c_int, [_P, _P, ctypes.c_int32, ctypes.POINTER(_P), ctypes.POINTER(ctypes.c_size_t)]),
     "mlc_dgf_table": (ctypes.c_int, [_P, ctypes.c_int32, ctypes.c_int32, ctypes.POINTER(_P)]),
+    "mlc_plan_set_timing": (ctypes.c_int, [_P, ctypes.c_int32]),
+    "mlc_plan_timing": (ctypes.c_int, [_P, ctypes.POINTER(mlc_kernel_time), ctypes.c_int32,
+                                       ctypes.POINTER(ctypes.c_int32)]),
 }
 
 _lib = None
@@ -181,6 +188,16 @@ class Plan:
         nbytes = workspace.numel() * workspace.element_size() if hasattr(workspace, "numel") else self.workspace_bytes
         _check(lib().mlc_solve(self.handle, _ptr(f), _ptr(phi), _ptr(workspace), nbytes, _stream(stream)),
                self.ctx.handle)
+
+    def set_timing(self, enable):
+        _check(lib().mlc_plan_set_timing(self.handle, 1 if enable else 0), self.ctx.handle)
+
+    def timing(self):
+        """{kernel name: (launches, total ms)} since timing was enabled."""
+        arr = (mlc_kernel_time * 64)()
+        cnt = ctypes.c_int32()
+        _check(lib().mlc_plan_timing(self.handle, arr, 64, ctypes.byref(cnt)), self.ctx.handle)
+        return {arr[k].name.decode(): (arr[k].launches, arr[k].total_ms) for k in range(min(cnt.value, 64))}
 
     def view(self, workspace, which):
         """(device pointer, bytes) of an intermediate held in the workspace."""
