@@ -19,6 +19,7 @@
 //         complex FFT) -> coarse samples and skeleton planes, times h^2.
 #pragma once
 #include "common.h"
+#include "fft_reg.h"
 
 namespace mlc {
 
@@ -58,59 +59,133 @@ __global__ void __launch_bounds__(256) conv_xdft_kernel(const double* __restrict
   }
 }
 
-template <typename T> struct ConvCfg;
-template <> struct ConvCfg<float> { static constexpr int CB = 16, NLB = 4, CK = 8; };
-template <> struct ConvCfg<double> { static constexpr int CB = 8, NLB = 4, CK = 4; };
+// Lines transformed together per batch (one thread per (line, pass index)).
+template <typename T, int M> struct Batch {
+  static constexpr int R1 = Split<M>::R1, R2 = Split<M>::R2;
+  static constexpr int RMAX = R1 > R2 ? R1 : R2;
+  static constexpr int CB = 256 / RMAX;
+  // odd padded line stride of the exchange buffer
+  static constexpr int XL = (XLayout<M>::LINE % 2) ? XLayout<M>::LINE : XLayout<M>::LINE + 1;
+};
+// conv_out holds the whole (kx, y) plane in LDS; fp64 uses fewer lines per batch.
+template <typename T, int M> struct OutBatch {
+  static constexpr int CB = sizeof(T) == 4 ? Batch<T, M>::CB : 4;
+};
 
-template <int n, int NLB> struct SRows { static constexpr int v = ((n + 1 + NLB - 1) / NLB) * NLB; };
+template <typename T>
+__device__ __forceinline__ cplx<T> conjw(cplx<T> w) { return {w.x, -w.y}; }
 
 template <typename T, int n, int M>
 __global__ void __launch_bounds__(256) conv_yz_kernel(const cplx<T>* __restrict__ X, const T* __restrict__ spec,
                                                       cplx<T>* __restrict__ Zb, int Wp, int b, int Wa, int e, int da) {
   constexpr int Mh = M / 2 + 1;
   constexpr int S = n + 1;
-  constexpr int CB = ConvCfg<T>::CB, NLB = ConvCfg<T>::NLB;
-  constexpr int SR = SRows<n, NLB>::v;
-  __shared__ cplx<T> Y[SR * M];
-  __shared__ cplx<T> Cb[CB * M];
+  constexpr int R1 = Split<M>::R1, R2 = Split<M>::R2;
+  constexpr int CB = Batch<T, M>::CB, XL = Batch<T, M>::XL;
+  __shared__ cplx<T> Y[S * M];
+  __shared__ cplx<T> Ex[CB * XL];
   __shared__ cplx<T> tw[M];
+  __shared__ short zmap[M];
   const int kx = blockIdx.x, p = blockIdx.y;
-  const cplx<T>* xin = X + (int64_t(p) * Mh + kx) * S * S;
-  for (int t = threadIdx.x; t < SR * M; t += blockDim.x) {
-    int r = t / M, c = t % M;
-    Y[t] = (r < S && c < S) ? xin[r * S + c] : cplx<T>{T(0), T(0)};
-  }
+  const int tid = threadIdx.x;
   fill_twiddles(tw, M);
+  for (int m = tid; m < M; m += blockDim.x) zmap[m] = -1;
   __syncthreads();
-  // FFT along y of every source row sz
+  for (int zi = tid; zi < Wp; zi += blockDim.x) {
+    int z = out_coord(zi, b, Wa, e, da, n);
+    zmap[z < 0 ? z + M : z] = short(zi);
+  }
+  const cplx<T>* xin = X + (int64_t(p) * Mh + kx) * S * S;
+  const cplx<T> zero = {T(0), T(0)};
+  // ---- FFT along y of the S source rows (CB rows per batch) ----
 #pragma unroll 1
-  for (int rb = 0; rb < SR; rb += NLB) fft_lines<T, M, NLB, 256, 1, false>(Y + rb * M, M, 1, tw);
+  for (int rb = 0; rb < S; rb += CB) {
+    if (tid < CB * R2) {
+      const int t = tid % R2, r = tid / R2, sz = rb + r;
+      cplx<T> v[R1];
+#pragma unroll
+      for (int j1 = 0; j1 < R1; ++j1) {
+        int sy = t + R2 * j1;
+        v[j1] = (sz < S && sy < S) ? xin[sz * S + sy] : zero;
+      }
+      dft_reg<T, R1, 1>(v, tw, M / R1);
+      cplx<T>* ex = Ex + r * XL + t * (R1 + 1);
+#pragma unroll
+      for (int k1 = 0; k1 < R1; ++k1) ex[k1] = (k1 == 0 || t == 0) ? v[k1] : cmul(v[k1], tw[t * k1]);
+    }
+    __syncthreads();
+    if (tid < CB * R1) {
+      const int s = tid % R1, r = tid / R1, sz = rb + r;
+      cplx<T> u[R2];
+#pragma unroll
+      for (int t = 0; t < R2; ++t) u[t] = Ex[r * XL + t * (R1 + 1) + s];
+      dft_reg<T, R2, 1>(u, tw, M / R2);
+      if (sz < S) {
+#pragma unroll
+        for (int k2 = 0; k2 < R2; ++k2) Y[sz * M + s + R1 * k2] = u[k2];
+      }
+    }
+    __syncthreads();
+  }
+  // ---- per column ky: FFT along z, times the spectrum, inverse along z ----
   const T* sp = spec + int64_t(kx) * Mh * Mh;
   cplx<T>* zout = Zb + (int64_t(p) * Wp * Mh + kx) * M;
 #pragma unroll 1
   for (int cb = 0; cb < M; cb += CB) {
-    for (int t = threadIdx.x; t < CB * M; t += blockDim.x) {
-      int c = t % CB, z = t / CB;
-      Cb[c * M + z] = (z < S && cb + c < M) ? Y[z * M + cb + c] : cplx<T>{T(0), T(0)};
+    if (tid < CB * R2) {
+      const int c = tid % CB, t = tid / CB, ky = cb + c;
+      cplx<T> v[R1];
+#pragma unroll
+      for (int j1 = 0; j1 < R1; ++j1) {
+        int sz = t + R2 * j1;
+        v[j1] = (sz < S && ky < M) ? Y[sz * M + ky] : zero;
+      }
+      dft_reg<T, R1, 1>(v, tw, M / R1);
+      cplx<T>* ex = Ex + c * XL + t * (R1 + 1);
+#pragma unroll
+      for (int k1 = 0; k1 < R1; ++k1) ex[k1] = (k1 == 0 || t == 0) ? v[k1] : cmul(v[k1], tw[t * k1]);
     }
     __syncthreads();
-    fft_lines<T, M, CB, 256, 1, false>(Cb, M, 1, tw);
-    for (int t = threadIdx.x; t < CB * M; t += blockDim.x) {
-      int c = t / M, kz = t % M;
-      int ky = cb + c;
-      if (ky >= M) continue;
-      int az = kz <= M / 2 ? kz : M - kz, ay = ky <= M / 2 ? ky : M - ky;
-      T g = sp[az * Mh + ay];
-      Cb[t] = {Cb[t].x * g, Cb[t].y * g};
+    const bool act = tid < CB * R1;
+    const int s = tid % R1, c2 = tid / R1;
+    cplx<T> u[R2];
+    if (act) {
+      const int ky = cb + c2;
+#pragma unroll
+      for (int t = 0; t < R2; ++t) u[t] = Ex[c2 * XL + t * (R1 + 1) + s];
+      dft_reg<T, R2, 1>(u, tw, M / R2);
+      const int ay = ky < M ? (ky <= M / 2 ? ky : M - ky) : 0;
+      const T* srow = sp + ay * Mh;
+#pragma unroll
+      for (int k2 = 0; k2 < R2; ++k2) {
+        int kz = s + R1 * k2;
+        T g = srow[kz <= M / 2 ? kz : M - kz];
+        u[k2] = {u[k2].x * g, u[k2].y * g};
+      }
+      dft_reg<T, R2, -1>(u, tw, M / R2);
+#pragma unroll
+      for (int t = 1; t < R2; ++t)
+        if (s) u[t] = cmul(u[t], conjw(tw[t * s]));
     }
     __syncthreads();
-    fft_lines<T, M, CB, 256, -1, false>(Cb, M, 1, tw);
-    for (int t = threadIdx.x; t < CB * Wp; t += blockDim.x) {
-      int c = t % CB, zi = t / CB;
-      if (cb + c >= M) continue;
-      int z = out_coord(zi, b, Wa, e, da, n);
-      int slot = z < 0 ? z + M : z;
-      zout[int64_t(zi) * Mh * M + cb + c] = Cb[c * M + slot];
+    if (act) {
+#pragma unroll
+      for (int t = 0; t < R2; ++t) Ex[c2 * XL + s * (R2 + 1) + t] = u[t];
+    }
+    __syncthreads();
+    if (tid < CB * R2) {
+      const int c = tid % CB, t = tid / CB, ky = cb + c;
+      cplx<T> v[R1];
+#pragma unroll
+      for (int s1 = 0; s1 < R1; ++s1) v[s1] = Ex[c * XL + s1 * (R2 + 1) + t];
+      dft_reg<T, R1, -1>(v, tw, M / R1);
+      if (ky < M) {
+#pragma unroll
+        for (int j1 = 0; j1 < R1; ++j1) {
+          int zi = zmap[t + R2 * j1];
+          if (zi >= 0) zout[int64_t(zi) * Mh * M + ky] = v[j1];
+        }
+      }
     }
     __syncthreads();
   }
@@ -127,32 +202,56 @@ template <typename T, int n, int M>
 __global__ void __launch_bounds__(256) conv_out_kernel(const cplx<T>* __restrict__ Zb, T* __restrict__ coarse,
                                                        T* __restrict__ planes, OutGeom g) {
   constexpr int Mh = M / 2 + 1;
-  constexpr int CK = ConvCfg<T>::CK;
+  constexpr int R1 = Split<M>::R1, R2 = Split<M>::R2;
+  constexpr int CB = OutBatch<T, M>::CB, XL = Batch<T, M>::XL;
   constexpr int WPMAX = n + 2 * n + 1 + 2 * 4;  // Wa + 2b with d_alpha <= n, b <= 4
   __shared__ cplx<T> A[Mh * WPMAX];
-  __shared__ cplx<T> Cb[CK * M];
+  __shared__ cplx<T> Ex[CB * XL];
   __shared__ cplx<T> tw[M];
+  __shared__ short omap[M];
   const int zi = blockIdx.x, p = blockIdx.y;
   const int Wp = g.Wp;
+  const int tid = threadIdx.x;
   fill_twiddles(tw, M);
+  for (int m = tid; m < M; m += blockDim.x) omap[m] = -1;
+  __syncthreads();
+  for (int k = tid; k < Wp; k += blockDim.x) {
+    int y = out_coord(k, g.b, g.Wa, g.e, g.da, n);
+    omap[y < 0 ? y + M : y] = short(k);
+  }
+  __syncthreads();
   const cplx<T>* zin = Zb + (int64_t(p) * Wp + zi) * Mh * M;
-  // inverse FFT along y for every kx; keep the Wp output y's
+  // ---- inverse FFT along y for every kx (CB rows per batch) ----
 #pragma unroll 1
-  for (int kb = 0; kb < Mh; kb += CK) {
-    __syncthreads();
-    for (int t = threadIdx.x; t < CK * M; t += blockDim.x) {
-      int r = t / M, ky = t % M;
-      Cb[t] = (kb + r < Mh) ? zin[int64_t(kb + r) * M + ky] : cplx<T>{T(0), T(0)};
-    }
-    __syncthreads();
-    fft_lines<T, M, CK, 256, -1, false>(Cb, M, 1, tw);
-    for (int t = threadIdx.x; t < CK * Wp; t += blockDim.x) {
-      int r = t / Wp, yi = t % Wp;
-      if (kb + r < Mh) {
-        int y = out_coord(yi, g.b, g.Wa, g.e, g.da, n);
-        A[(kb + r) * Wp + yi] = Cb[r * M + (y < 0 ? y + M : y)];
+  for (int kb = 0; kb < Mh; kb += CB) {
+    if (tid < CB * R1) {
+      const int s = tid % R1, r = tid / R1, kx = kb + r;
+      cplx<T> u[R2];
+#pragma unroll
+      for (int k2 = 0; k2 < R2; ++k2) u[k2] = kx < Mh ? zin[int64_t(kx) * M + s + R1 * k2] : cplx<T>{T(0), T(0)};
+      dft_reg<T, R2, -1>(u, tw, M / R2);
+#pragma unroll
+      for (int t = 0; t < R2; ++t) {
+        cplx<T> w = (s && t) ? cmul(u[t], conjw(tw[t * s])) : u[t];
+        Ex[r * XL + s * (R2 + 1) + t] = w;
       }
     }
+    __syncthreads();
+    if (tid < CB * R2) {
+      const int t = tid % R2, r = tid / R2, kx = kb + r;
+      cplx<T> v[R1];
+#pragma unroll
+      for (int s1 = 0; s1 < R1; ++s1) v[s1] = Ex[r * XL + s1 * (R2 + 1) + t];
+      dft_reg<T, R1, -1>(v, tw, M / R1);
+      if (kx < Mh) {
+#pragma unroll
+        for (int j1 = 0; j1 < R1; ++j1) {
+          int yi = omap[t + R2 * j1];
+          if (yi >= 0) A[kx * Wp + yi] = v[j1];
+        }
+      }
+    }
+    __syncthreads();
   }
   const int z = out_coord(zi, g.b, g.Wa, g.e, g.da, n);
   const bool zin_a = z >= -g.da && z <= n + g.da;
@@ -161,47 +260,70 @@ __global__ void __launch_bounds__(256) conv_out_kernel(const cplx<T>* __restrict
   const int npl = g.npl, Wa = g.Wa, Wc = g.Wc;
   T* cbase = coarse + int64_t(p) * Wc * Wc * Wc;
   T* pbase = planes + int64_t(p) * 3 * npl * Wa * Wa;
-  // Hermitian inverse along x: two real lines (y_j, y_j+1) per complex line
+  // ---- Hermitian inverse along x: two real lines (y1, y1+1) per complex line ----
 #pragma unroll 1
-  for (int yb = 0; yb < Wp; yb += 2 * CK) {
-    __syncthreads();
-    for (int t = threadIdx.x; t < CK * M; t += blockDim.x) {
-      int c = t / M, k = t % M;
-      int y1 = yb + 2 * c, y2 = y1 + 1;
-      cplx<T> h1 = {T(0), T(0)}, h2 = {T(0), T(0)};
-      if (k < Mh) {
-        if (y1 < Wp) h1 = A[k * Wp + y1];
-        if (y2 < Wp) h2 = A[k * Wp + y2];
-      } else {
-        if (y1 < Wp) { h1 = A[(M - k) * Wp + y1]; h1.y = -h1.y; }
-        if (y2 < Wp) { h2 = A[(M - k) * Wp + y2]; h2.y = -h2.y; }
+  for (int yb = 0; yb < Wp; yb += 2 * CB) {
+    if (tid < CB * R1) {
+      const int s = tid % R1, c = tid / R1;
+      const int y1 = yb + 2 * c, y2 = y1 + 1;
+      cplx<T> u[R2];
+#pragma unroll
+      for (int k2 = 0; k2 < R2; ++k2) {
+        int k = s + R1 * k2;
+        cplx<T> h1 = {T(0), T(0)}, h2 = {T(0), T(0)};
+        if (k < Mh) {
+          if (y1 < Wp) h1 = A[k * Wp + y1];
+          if (y2 < Wp) h2 = A[k * Wp + y2];
+        } else {
+          if (y1 < Wp) h1 = conjw(A[(M - k) * Wp + y1]);
+          if (y2 < Wp) h2 = conjw(A[(M - k) * Wp + y2]);
+        }
+        if (k == 0 || k == M / 2) { h1.y = T(0); h2.y = T(0); }   // real DC / Nyquist
+        u[k2] = {h1.x - h2.y, h1.y + h2.x};                        // h1 + i h2
       }
-      if (k == 0 || k == M / 2) { h1.y = T(0); h2.y = T(0); }   // real DC / Nyquist
-      Cb[t] = {h1.x - h2.y, h1.y + h2.x};   // h1 + i h2
-    }
-    __syncthreads();
-    fft_lines<T, M, CK, 256, -1, false>(Cb, M, 1, tw);
-    for (int t = threadIdx.x; t < 2 * CK * Wp; t += blockDim.x) {
-      int yl = t / Wp, xi = t % Wp;
-      int yi = yb + yl;
-      if (yi >= Wp) continue;
-      int y = out_coord(yi, g.b, g.Wa, g.e, g.da, n);
-      int x = out_coord(xi, g.b, g.Wa, g.e, g.da, n);
-      cplx<T> zv = Cb[(yl >> 1) * M + (x < 0 ? x + M : x)];
-      T val = T(((yl & 1) ? zv.y : zv.x) * g.h2);
-      const bool yin_a = y >= -g.da && y <= n + g.da;
-      const bool xin_a = x >= -g.da && x <= n + g.da;
-      if (zc && mod_pos(y, NREF) == 0 && mod_pos(x, NREF) == 0)
-        cbase[(int64_t((z + g.e) / NREF) * Wc + (y + g.e) / NREF) * Wc + (x + g.e) / NREF] = val;
-      if (zpl && yin_a && xin_a)
-        pbase[((int64_t(0) * npl + (z - g.P0) / n) * Wa + (y + g.da)) * Wa + (x + g.da)] = val;
-      if (zin_a && yin_a && xin_a) {
-        if (mod_pos(y, n) == 0)
-          pbase[((int64_t(1) * npl + (y - g.P0) / n) * Wa + (z + g.da)) * Wa + (x + g.da)] = val;
-        if (mod_pos(x, n) == 0)
-          pbase[((int64_t(2) * npl + (x - g.P0) / n) * Wa + (z + g.da)) * Wa + (y + g.da)] = val;
+      dft_reg<T, R2, -1>(u, tw, M / R2);
+#pragma unroll
+      for (int t = 0; t < R2; ++t) {
+        cplx<T> w = (s && t) ? cmul(u[t], conjw(tw[t * s])) : u[t];
+        Ex[c * XL + s * (R2 + 1) + t] = w;
       }
     }
+    __syncthreads();
+    if (tid < CB * R2) {
+      const int t = tid % R2, c = tid / R2;
+      cplx<T> v[R1];
+#pragma unroll
+      for (int s1 = 0; s1 < R1; ++s1) v[s1] = Ex[c * XL + s1 * (R2 + 1) + t];
+      dft_reg<T, R1, -1>(v, tw, M / R1);
+#pragma unroll
+      for (int j1 = 0; j1 < R1; ++j1) {
+        int xi = omap[t + R2 * j1];
+        if (xi < 0) continue;
+        int x = out_coord(xi, g.b, g.Wa, g.e, g.da, n);
+        const bool xin_a = x >= -g.da && x <= n + g.da;
+        const bool xc = mod_pos(x, NREF) == 0;
+        const bool xpl = xin_a && mod_pos(x, n) == 0;
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+          int yi = yb + 2 * c + h;
+          if (yi >= Wp) continue;
+          int y = out_coord(yi, g.b, g.Wa, g.e, g.da, n);
+          T val = T(double(h ? v[j1].y : v[j1].x) * g.h2);
+          const bool yin_a = y >= -g.da && y <= n + g.da;
+          if (zc && xc && mod_pos(y, NREF) == 0)
+            cbase[(int64_t((z + g.e) / NREF) * Wc + (y + g.e) / NREF) * Wc + (x + g.e) / NREF] = val;
+          if (zpl && yin_a && xin_a)
+            pbase[((int64_t(0) * npl + (z - g.P0) / n) * Wa + (y + g.da)) * Wa + (x + g.da)] = val;
+          if (zin_a && yin_a && xin_a) {
+            if (mod_pos(y, n) == 0)
+              pbase[((int64_t(1) * npl + (y - g.P0) / n) * Wa + (z + g.da)) * Wa + (x + g.da)] = val;
+            if (xpl)
+              pbase[((int64_t(2) * npl + (x - g.P0) / n) * Wa + (z + g.da)) * Wa + (y + g.da)] = val;
+          }
+        }
+      }
+    }
+    __syncthreads();
   }
 }
 

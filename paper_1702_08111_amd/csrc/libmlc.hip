@@ -35,6 +35,7 @@ struct mlc_plan {
   mlc_plan_info info{};
   int S = 0, Mh = 0, Wp = 0, P0 = 0, eb = 0, Wtc = 0, Wb = 0, Wbc = 0, P0b = 0, nplb = 0, Kann = 0;
   ModeList modes{};
+  LagW lagw{};
   void* conv_spec = nullptr;
   double* coarse_spec = nullptr;
   double* T = nullptr;
@@ -441,11 +442,12 @@ extern "C" mlc_status mlc_plan_create(mlc_context* ctx, const mlc_problem* prob,
   P->nplb = (I.n + I.d_beta - P->P0b) / I.n + 1;
   P->Kann = I.d_beta > I.d_alpha ? I.K : 0;
   P->modes = mode_list(I.P);
+  P->lagw = make_lagw(I.b);
   double* G1 = nullptr;
   s = get_dgf(ctx, I.Q, I.Z, &G1);
   if (s != MLC_OK) { delete P; return s; }
   const int tsz = I.conv_precision == MLC_CONV_FP32 ? 4 : 8;
-  // local-convolution spectrum: layout [kx][kz'][ky'] (kx: fastest array axis)
+  // local-convolution spectrum: layout [kx][ky'][kz'] (kx: fastest array axis)
   {
     cplx<double>* work = nullptr;
     const int M = I.M, Mh = P->Mh;
@@ -456,7 +458,7 @@ extern "C" mlc_status mlc_plan_create(mlc_context* ctx, const mlc_problem* prob,
       delete P;
       return fail(ctx, MLC_ERR_OUT_OF_MEMORY, "spectrum allocation failed");
     }
-    s = build_spectrum(ctx, G1, I.Z, M, work, nullptr, P->conv_spec, tsz, 1.0 / (double(M) * M * M), 2, 0, 1);
+    s = build_spectrum(ctx, G1, I.Z, M, work, nullptr, P->conv_spec, tsz, 1.0 / (double(M) * M * M), 2, 1, 0);
     if (s == MLC_OK) {
       // coarse spectrum (fp64 octant, layout k0 k1 k2)
       const int Mc = I.M_coarse, Mch = Mc / 2 + 1;
@@ -633,7 +635,12 @@ static void launch_rest(const mlc_plan* P, const double* f, double* phi, char* w
                 1.0 / (I.H * I.H)};
   {
     TimedScope ts(P, s, "coarse_rhs");
-    hipLaunchKernelGGL(coarse_rhs_kernel<T>, dim3(blocks_for(cube(I.Ns))), dim3(256), 0, s, cs, mom, P->T, st, cg, F);
+    hipLaunchKernelGGL(coarse_rhs_kernel<T>, dim3(blocks_for(cube(I.Ns))), dim3(256), 0, s, cs, st, cg, F);
+  }
+  if (P->Kann > 0) {
+    TimedScope ts(P, s, "coarse_annulus");
+    const int q = I.n / NREF;
+    hipLaunchKernelGGL(coarse_annulus_kernel, dim3(q * q * q), dim3(256), 0, s, mom, P->T, cg, F);
   }
   // coarse solve
   const int Mc = I.M_coarse;
@@ -649,18 +656,22 @@ static void launch_rest(const mlc_plan* P, const double* f, double* phi, char* w
   // local plane corrections delta_i = phi_i - I(phi_i)
   {
     TimedScope ts(P, s, "plane_delta");
-    int64_t per = int64_t(3) * I.nplanes_a * I.Wa * I.Wa;
-    hipLaunchKernelGGL(plane_delta_kernel<T>, dim3(blocks_for(per), I.npatch), dim3(256), 0, s, pl, cs, I.n, I.e,
-                       I.d_alpha, I.Wa, I.Wc, P->P0, I.nplanes_a, I.b);
+    PlaneGeom pg{I.n, I.e, I.d_alpha, I.Wa, I.Wc, P->P0, I.nplanes_a, I.b};
+    hipLaunchKernelGGL(plane_delta_kernel<T>, dim3(3 * I.nplanes_a, I.npatch), dim3(256), 0, s, pl, cs, pg,
+                       P->lagw);
   }
   // boundary values on the skeleton (+ phi there)
   {
     SkelGeom sg{I.N, I.n, I.patches_per_axis, P->Kann, I.d_alpha, I.d_beta, I.b, I.Wa, P->P0, I.nplanes_a, P->Wb,
                 P->P0b, P->nplb, I.O_lo, I.No, I.h * I.h / 12.0};
     int64_t cnt = int64_t(3) * (I.N / I.n + 1) * (I.N + 1) * (I.N + 1);
+    if (P->Kann > 0) {
+      TimedScope ts(P, s, "skeleton_annulus");
+      hipLaunchKernelGGL(skeleton_annulus_kernel, dim3(I.n * I.n, 3), dim3(256), 0, s, mom, P->D, sg, phiB);
+    }
     TimedScope ts(P, s, "skeleton");
-    hipLaunchKernelGGL(skeleton_kernel<T>, dim3(blocks_for(cnt)), dim3(256), 0, s, phiH, pl, mom, P->D, f, sg,
-                       phiB, phi);
+    hipLaunchKernelGGL(skeleton_kernel<T>, dim3(blocks_for(cnt)), dim3(256), 0, s, phiH, pl, f, sg, P->lagw,
+                       P->Kann > 0 ? 1 : 0, phiB, phi);
   }
   // Dirichlet solves + Mehrstellen correction on the patch interiors
   {

@@ -78,13 +78,11 @@ struct CoarseGeom {
   double invH2;
 };
 
-// F^H[c] = sum_i F_i[c]: Delta^H of phi_i's coarse samples on C(Omega_alpha(i)),
-// the Legendre far field sum_p c_{i,p} T_p[c - n i / 4] on
-// C(Omega_beta(i)) \ C(Omega_alpha(i)) (T is zero on the inner box), patches
+// Inner part of F^H: F[c] = sum over patches i with c in C(Omega_alpha(i)) of
+// Delta^H of phi_i's coarse samples (sec. 4.1 eq. FDLD, first case), patches
 // visited in a fixed order.
 template <typename T>
-__global__ void __launch_bounds__(256) coarse_rhs_kernel(const T* __restrict__ cs, const double* __restrict__ mom,
-                                                         const double* __restrict__ Tt, Stencil st, CoarseGeom g,
+__global__ void __launch_bounds__(256) coarse_rhs_kernel(const T* __restrict__ cs, Stencil st, CoarseGeom g,
                                                          double* __restrict__ F) {
   int64_t idx = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
   if (idx >= cube(g.Ns)) return;
@@ -93,45 +91,113 @@ __global__ void __launch_bounds__(256) coarse_rhs_kernel(const T* __restrict__ c
   c[1] = g.S_lo + int((idx / g.Ns) % g.Ns);
   c[0] = g.S_lo + int(idx / (int64_t(g.Ns) * g.Ns));
   const int n = g.n, q = n / NREF;
-  // patches whose C(Omega_beta) contains c: n i - db <= 4c <= n i + n + db
+  // patches whose C(Omega_alpha) contains c: n i - da <= 4c <= n i + n + da
   int lo[3], hi[3];
   for (int d = 0; d < 3; ++d) {
-    int a = NREF * c[d] - n - g.db;   // n i >= a
-    lo[d] = a >= 0 ? (a + n - 1) / n : -((-a) / n);
-    int bnd = NREF * c[d] + g.db;     // n i <= bnd
-    hi[d] = bnd >= 0 ? bnd / n : -((-bnd + n - 1) / n);
-    lo[d] = max(lo[d], 0);
-    hi[d] = min(hi[d], g.ppa - 1);
+    int a = NREF * c[d] - n - g.da;
+    lo[d] = max(a >= 0 ? (a + n - 1) / n : -((-a) / n), 0);
+    int bnd = NREF * c[d] + g.da;
+    hi[d] = min(bnd >= 0 ? bnd / n : -((-bnd + n - 1) / n), g.ppa - 1);
   }
-  const int Wc = g.Wc, Wbc = g.Wbc, K = g.K;
+  const int Wc = g.Wc, o = g.e / NREF;
   double s = 0.0;
   for (int a0 = lo[0]; a0 <= hi[0]; ++a0)
     for (int a1 = lo[1]; a1 <= hi[1]; ++a1)
       for (int a2 = lo[2]; a2 <= hi[2]; ++a2) {
-        int r0 = c[0] - q * a0, r1 = c[1] - q * a1, r2 = c[2] - q * a2;   // coarse coords rel. patch
-        int alo = -g.da / NREF, ahi = (n + g.da) / NREF;
+        int r0 = c[0] - q * a0 + o, r1 = c[1] - q * a1 + o, r2 = c[2] - q * a2 + o;
         int pidx = (a0 * g.ppa + a1) * g.ppa + a2;
-        if (r0 >= alo && r0 <= ahi && r1 >= alo && r1 <= ahi && r2 >= alo && r2 <= ahi) {
-          const T* base = cs + int64_t(pidx) * Wc * Wc * Wc;
-          int o = g.e / NREF;
-          double l = 0.0;
-          for (int s0 = -1; s0 <= 1; ++s0)
-            for (int s1 = -1; s1 <= 1; ++s1)
-              for (int s2 = -1; s2 <= 1; ++s2) {
-                int nz = (s0 != 0) + (s1 != 0) + (s2 != 0);
-                l += st.b[nz] * double(base[(int64_t(r0 + s0 + o) * Wc + (r1 + s1 + o)) * Wc + (r2 + s2 + o)]);
-              }
-          s += l * g.invH2;
-        } else if (K > 0) {
-          int ob = g.db / NREF;
-          const double* tv = Tt + ((int64_t(r0 + ob) * Wbc + (r1 + ob)) * Wbc + (r2 + ob)) * K;
-          const double* mv = mom + int64_t(pidx) * K;
-          double l = 0.0;
-          for (int k = 0; k < K; ++k) l += mv[k] * tv[k];
-          s += l;
-        }
+        const T* base = cs + int64_t(pidx) * Wc * Wc * Wc;
+        double l = 0.0;
+        for (int s0 = -1; s0 <= 1; ++s0)
+          for (int s1 = -1; s1 <= 1; ++s1)
+            for (int s2 = -1; s2 <= 1; ++s2) {
+              int nz = (s0 != 0) + (s1 != 0) + (s2 != 0);
+              l += st.b[nz] * double(base[(int64_t(r0 + s0) * Wc + (r1 + s1)) * Wc + (r2 + s2)]);
+            }
+        s += l * g.invH2;
       }
   F[idx] = s;
+}
+
+constexpr int MAXPATCH = 512;   // patches whose moments fit the LDS of one block
+
+// Annulus part of F^H (sec. 4.1 eq. FDLD, second case), added to F:
+//   F[c] += sum_i sum_p c_{i,p} T_p[c - n i / 4],  T zero on C(Omega_alpha(0)).
+// Write c = q k + rho (q = n/4, rho in [0, q)^3); then c - n i/4 =
+// q (k - i) + rho, so for one rho the sum is a convolution over the patch
+// lattice.  Block = one rho; the block's threads take the lattice points k;
+// all moments sit in LDS; the table values of one lattice offset are read
+// once and reused by every k.
+__global__ void __launch_bounds__(256) coarse_annulus_kernel(const double* __restrict__ mom,
+                                                             const double* __restrict__ Tt, CoarseGeom g,
+                                                             double* __restrict__ F) {
+  __shared__ double cm[MAXPATCH * KMAX];
+  const int n = g.n, q = n / NREF, K = g.K, ppa = g.ppa;
+  const int npatch = ppa * ppa * ppa;
+  const bool in_lds = npatch <= MAXPATCH;
+  if (in_lds)
+    for (int t = threadIdx.x; t < npatch * K; t += blockDim.x) cm[t] = mom[t];
+  const double* cmp = in_lds ? cm : mom;
+  const int rb = blockIdx.x;
+  const int rho[3] = {rb / (q * q), (rb / q) % q, rb % q};
+  // lattice points k with c = q k + rho inside the support box
+  int klo[3], kn[3], dlo[3], dhi[3];
+  const int S_hi = g.S_lo + g.Ns - 1;
+  const int blo = -g.db / NREF, bhi = (n + g.db) / NREF;   // C(Omega_beta(0))
+  for (int d = 0; d < 3; ++d) {
+    int a = g.S_lo - rho[d];
+    klo[d] = a >= 0 ? (a + q - 1) / q : -((-a) / q);
+    int bnd = S_hi - rho[d];
+    int khi = bnd >= 0 ? bnd / q : -((-bnd + q - 1) / q);
+    kn[d] = khi - klo[d] + 1;
+    // lattice offsets D = k - i with q D + rho inside C(Omega_beta(0))
+    int x = blo - rho[d];
+    dlo[d] = x >= 0 ? (x + q - 1) / q : -((-x) / q);
+    int y = bhi - rho[d];
+    dhi[d] = y >= 0 ? y / q : -((-y + q - 1) / q);
+  }
+  __syncthreads();
+  constexpr int PER = 16;
+  const int nk = kn[0] * kn[1] * kn[2];
+  const int ob = g.db / NREF, Wbc = g.Wbc;
+  for (int kbase = 0; kbase < nk; kbase += PER * 256) {
+  double acc[PER];
+#pragma unroll
+  for (int t = 0; t < PER; ++t) acc[t] = 0.0;
+  for (int D0 = dlo[0]; D0 <= dhi[0]; ++D0)
+    for (int D1 = dlo[1]; D1 <= dhi[1]; ++D1)
+      for (int D2 = dlo[2]; D2 <= dhi[2]; ++D2) {
+        const double* tv = Tt + ((int64_t(q * D0 + rho[0] + ob) * Wbc + (q * D1 + rho[1] + ob)) * Wbc +
+                                 (q * D2 + rho[2] + ob)) * K;
+        double tr[KMAX];
+#pragma unroll
+        for (int p = 0; p < KMAX; ++p) tr[p] = p < K ? tv[p] : 0.0;
+#pragma unroll
+        for (int t = 0; t < PER; ++t) {
+          int kk = kbase + threadIdx.x + t * 256;
+          if (kk >= nk) break;
+          int i0 = klo[0] + kk / (kn[1] * kn[2]) - D0;
+          int i1 = klo[1] + (kk / kn[2]) % kn[1] - D1;
+          int i2 = klo[2] + kk % kn[2] - D2;
+          if (i0 < 0 || i0 >= ppa || i1 < 0 || i1 >= ppa || i2 < 0 || i2 >= ppa) continue;
+          const double* mv = cmp + ((i0 * ppa + i1) * ppa + i2) * K;
+          double l = 0.0;
+#pragma unroll
+          for (int p = 0; p < KMAX; ++p)
+            if (p < K) l += tr[p] * mv[p];
+          acc[t] += l;
+        }
+      }
+#pragma unroll
+  for (int t = 0; t < PER; ++t) {
+    int kk = kbase + threadIdx.x + t * 256;
+    if (kk >= nk) break;
+    int c0 = q * (klo[0] + kk / (kn[1] * kn[2])) + rho[0];
+    int c1 = q * (klo[1] + (kk / kn[2]) % kn[1]) + rho[1];
+    int c2 = q * (klo[2] + kk % kn[2]) + rho[2];
+    F[(int64_t(c0 - g.S_lo) * g.Ns + (c1 - g.S_lo)) * g.Ns + (c2 - g.S_lo)] += acc[t];
+  }
+  }
 }
 
 // Coarse Hockney solve: F^H on slots [0, Ns)^3 of a zeroed Mc^3 torus.
@@ -154,42 +220,77 @@ __global__ void coarse_extract_kernel(const cplx<double>* __restrict__ tor, doub
 }
 
 // ---------------------------------------------- local plane corrections ----
-// delta_i = phi_i - I(phi_i) on phi_i's skeleton planes inside Omega_alpha,
-// in place; I interpolates phi_i's coarse samples in the plane.
-template <typename T>
-__global__ void plane_delta_kernel(T* __restrict__ planes, const T* __restrict__ cs, int n, int e, int da, int Wa,
-                                   int Wc, int P0, int npl, int b) {
-  const int p = blockIdx.y;
-  const int64_t per = int64_t(3) * npl * Wa * Wa;
-  int64_t r = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-  if (r >= per) return;
-  int v = int(r % Wa), u = int((r / Wa) % Wa), j = int((r / (int64_t(Wa) * Wa)) % npl);
-  int d = int(r / (int64_t(Wa) * Wa * npl));
-  int P = P0 + j * n;
-  int xu = -da + u, xv = -da + v;
-  int U0 = xu >= 0 ? xu / NREF : -((-xu + NREF - 1) / NREF);
-  int V0 = xv >= 0 ? xv / NREF : -((-xv + NREF - 1) / NREF);
-  int tu = xu - NREF * U0, tv = xv - NREF * V0;
-  double wu[10], wv[10];
-  int ku0 = 0, ku1 = 0, kv0 = 0, kv1 = 0;
-  if (tu) { lagrange_weights(b, tu / double(NREF), wu); ku0 = -b; ku1 = b + 1; } else { wu[b] = 1.0; }
-  if (tv) { lagrange_weights(b, tv / double(NREF), wv); kv0 = -b; kv1 = b + 1; } else { wv[b] = 1.0; }
-  const T* cb = cs + int64_t(p) * Wc * Wc * Wc;
-  int o = e / NREF, cd = (P + e) / NREF;
-  double s = 0.0;
-  for (int ku = ku0; ku <= ku1; ++ku) {
-    double rs = 0.0;
-    for (int kv = kv0; kv <= kv1; ++kv) {
-      int c[3];
-      c[d] = cd;
-      c[d == 0 ? 1 : 0] = U0 + ku + o;
-      c[d == 2 ? 1 : 2] = V0 + kv + o;
-      rs += wv[kv + b] * double(cb[(int64_t(c[0]) * Wc + c[1]) * Wc + c[2]]);
-    }
-    s += wu[ku + b] * rs;
+// Lagrange weights of the coplanar interpolation for the four fine offsets
+// t = x - 4 floor(x/4) within a coarse cell: w[t][k+b], k = -b..b+1
+// (t = 0: the single weight 1 at k = 0).
+struct LagW { double w[4][10]; };
+
+inline LagW make_lagw(int b) {
+  LagW L{};
+  for (int t = 0; t < 4; ++t) {
+    if (t == 0) { L.w[0][b] = 1.0; continue; }
+    lagrange_weights(b, t / double(NREF), L.w[t]);
   }
-  T* pl = planes + int64_t(p) * per + r;
-  *pl = T(double(*pl) - s);
+  return L;
+}
+
+__device__ __forceinline__ int floor4(int x) { return x >= 0 ? x / NREF : -((-x + NREF - 1) / NREF); }
+
+constexpr int WCMAX = 40, WAMAX = 97;
+
+struct PlaneGeom { int n, e, da, Wa, Wc, P0, npl, b; };
+
+// delta_i = phi_i - I(phi_i) on phi_i's skeleton planes inside Omega_alpha,
+// in place.  Block (plane, patch): the plane's coarse samples go to LDS, are
+// interpolated along the faster in-plane axis row by row, then along the
+// slower one.
+template <typename T>
+__global__ void __launch_bounds__(256) plane_delta_kernel(T* __restrict__ planes, const T* __restrict__ cs,
+                                                          PlaneGeom g, LagW lw) {
+  __shared__ double C[WCMAX * WCMAX];
+  __shared__ double R[WCMAX * WAMAX];
+  const int pl = blockIdx.x, p = blockIdx.y;
+  const int d = pl / g.npl, j = pl % g.npl;
+  const int n = g.n, Wc = g.Wc, Wa = g.Wa, b = g.b, o = g.e / NREF;
+  const int cd = (g.P0 + j * n + g.e) / NREF;
+  const T* cb = cs + int64_t(p) * Wc * Wc * Wc;
+  for (int t = threadIdx.x; t < Wc * Wc; t += blockDim.x) {
+    int cu = t / Wc, cv = t % Wc;
+    int c[3];
+    c[d] = cd;
+    c[d == 0 ? 1 : 0] = cu;
+    c[d == 2 ? 1 : 2] = cv;
+    C[t] = double(cb[(int64_t(c[0]) * Wc + c[1]) * Wc + c[2]]);
+  }
+  __syncthreads();
+  for (int t = threadIdx.x; t < Wc * Wa; t += blockDim.x) {
+    int cu = t / Wa, v = t % Wa;
+    int xv = -g.da + v, V0 = floor4(xv), tv = xv - NREF * V0;
+    const double* row = C + cu * Wc + V0 + o;
+    double s;
+    if (tv == 0) {
+      s = row[0];
+    } else {
+      s = 0.0;
+      for (int k = -b; k <= b + 1; ++k) s += lw.w[tv][k + b] * row[k];
+    }
+    R[cu * Wa + v] = s;
+  }
+  __syncthreads();
+  T* out = planes + ((int64_t(p) * 3 + d) * g.npl + j) * Wa * Wa;
+  for (int t = threadIdx.x; t < Wa * Wa; t += blockDim.x) {
+    int u = t / Wa, v = t % Wa;
+    int xu = -g.da + u, U0 = floor4(xu), tu = xu - NREF * U0;
+    const double* col = R + (U0 + o) * Wa + v;
+    double s;
+    if (tu == 0) {
+      s = col[0];
+    } else {
+      s = 0.0;
+      for (int k = -b; k <= b + 1; ++k) s += lw.w[tu][k + b] * col[k * Wa];
+    }
+    out[t] = T(double(out[t]) - s);
+  }
 }
 
 // ------------------------------------------------------------ skeleton ----
@@ -198,16 +299,100 @@ struct SkelGeom {
   double c2h2;   // C2 h^2
 };
 
-// phi^B[g] = I(phi^H)(g) + sum_{i in S_alpha(g)} delta_i[g]
-//          + sum_{i in S_beta(g)} sum_p c_{i,p} D_p[g - n i]
-// for every skeleton node g (taken once, on its lowest face-normal axis);
-// also writes phi[g] = phi^B[g] + C2 h^2 f[g] (sec. 4.1 eqs. mlcfulldiscr,
+// Legendre far field of the annulus patches at every skeleton node
+// (sec. 4.1 eq. philocmlcII, second sum, after the regrouping by linearity):
+//   A[g] = sum_{i in S_beta(g)} sum_p c_{i,p} D_p[g - n i],
+// D_p = Phi_p - I(Phi_p) on the skeleton planes of Omega_beta(0), zero on
+// Omega_alpha(0).  With g = n k + r (r in [0, n)^2 in the face plane of
+// normal d, r_d = 0), g - n i = n (k - i) + r: for one (d, r) the sum is a
+// convolution over the patch lattice.  Block = one (r, d); threads take the
+// lattice points k; moments in LDS; the table values of one lattice offset
+// are read once per block.  Writes A into phiB (every canonical node).
+__global__ void __launch_bounds__(256) skeleton_annulus_kernel(const double* __restrict__ mom,
+                                                               const double* __restrict__ D, SkelGeom g,
+                                                               double* __restrict__ phiB) {
+  __shared__ double cm[MAXPATCH * KMAX];
+  const int n = g.n, K = g.K, ppa = g.ppa, N = g.N, Np = N + 1;
+  const int npatch = ppa * ppa * ppa;
+  const int ra = blockIdx.x / n, rb = blockIdx.x % n, d = blockIdx.y;
+  const int a0 = d == 0 ? 1 : 0, a1 = d == 2 ? 1 : 2;
+  // canonical plane: no in-plane axis below d on a patch face
+  if ((a0 < d && ra == 0) || (a1 < d && rb == 0)) return;
+  const bool in_lds = npatch <= MAXPATCH;
+  if (in_lds)
+    for (int t = threadIdx.x; t < npatch * K; t += blockDim.x) cm[t] = mom[t];
+  const double* cmp = in_lds ? cm : mom;
+  __syncthreads();
+  // offsets k - i = Dl with n Dl + r inside Omega_beta(0) on each axis
+  auto drange = [&](int r, int& lo, int& hi) {
+    int x = -g.db - r;
+    lo = x >= 0 ? (x + n - 1) / n : -((-x) / n);
+    int y = n + g.db - r;
+    hi = y >= 0 ? y / n : -((-y + n - 1) / n);
+  };
+  int dlo[3], dhi[3];
+  drange(0, dlo[0], dhi[0]);
+  drange(ra, dlo[1], dhi[1]);
+  drange(rb, dlo[2], dhi[2]);
+  // lattice points: kd in [0, ppa], ka, kb in [0, ppa] with n k + r <= N
+  const int nka = (ra == 0) ? ppa + 1 : ppa, nkb = (rb == 0) ? ppa + 1 : ppa;
+  const int nk = (ppa + 1) * nka * nkb;
+  constexpr int PER = 8;
+  for (int kbase = 0; kbase < nk; kbase += PER * 256) {
+    double acc[PER];
+#pragma unroll
+    for (int t = 0; t < PER; ++t) acc[t] = 0.0;
+    for (int E0 = dlo[0]; E0 <= dhi[0]; ++E0)
+      for (int E1 = dlo[1]; E1 <= dhi[1]; ++E1)
+        for (int E2 = dlo[2]; E2 <= dhi[2]; ++E2) {
+          int jb = (n * E0 - g.P0b) / n;
+          const double* dv = D + ((((int64_t(d) * g.nplb + jb) * g.Wb + (ra + n * E1 + g.db)) * g.Wb) +
+                                  (rb + n * E2 + g.db)) * K;
+          double tr[KMAX];
+#pragma unroll
+          for (int p = 0; p < KMAX; ++p) tr[p] = p < K ? dv[p] : 0.0;
+#pragma unroll
+          for (int t = 0; t < PER; ++t) {
+            int kk = kbase + threadIdx.x + t * 256;
+            if (kk >= nk) break;
+            int kd = kk / (nka * nkb), ka = (kk / nkb) % nka, kb = kk % nkb;
+            int i[3];
+            i[d] = kd - E0;
+            i[a0] = ka - E1;
+            i[a1] = kb - E2;
+            if (i[0] < 0 || i[0] >= ppa || i[1] < 0 || i[1] >= ppa || i[2] < 0 || i[2] >= ppa) continue;
+            const double* mv = cmp + ((i[0] * ppa + i[1]) * ppa + i[2]) * K;
+            double l = 0.0;
+#pragma unroll
+            for (int p = 0; p < KMAX; ++p)
+              if (p < K) l += tr[p] * mv[p];
+            acc[t] += l;
+          }
+        }
+#pragma unroll
+    for (int t = 0; t < PER; ++t) {
+      int kk = kbase + threadIdx.x + t * 256;
+      if (kk >= nk) break;
+      int kd = kk / (nka * nkb), ka = (kk / nkb) % nka, kb = kk % nkb;
+      int gg[3];
+      gg[d] = n * kd;
+      gg[a0] = n * ka + ra;
+      gg[a1] = n * kb + rb;
+      phiB[(int64_t(gg[0]) * Np + gg[1]) * Np + gg[2]] = acc[t];
+    }
+  }
+}
+
+// phi^B[g] = I(phi^H)(g) + sum_{i in S_alpha(g)} delta_i[g] (+ the annulus
+// far field already in phiB when `annulus`) for every skeleton node g (taken
+// once, on its lowest face-normal axis); also writes
+// phi[g] = phi^B[g] + C2 h^2 f[g] (sec. 4.1 eqs. mlcfulldiscr,
 // mcapplicationfulldiscr).
 template <typename T>
 __global__ void __launch_bounds__(256) skeleton_kernel(const double* __restrict__ phiH, const T* __restrict__ delta,
-                                                       const double* __restrict__ mom, const double* __restrict__ D,
-                                                       const double* __restrict__ f, SkelGeom g,
-                                                       double* __restrict__ phiB, double* __restrict__ phi) {
+                                                       const double* __restrict__ f, SkelGeom g, LagW lw,
+                                                       int annulus, double* __restrict__ phiB,
+                                                       double* __restrict__ phi) {
   const int N = g.N, n = g.n, Np = N + 1;
   const int planes = N / n + 1;
   int64_t idx = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
@@ -226,10 +411,9 @@ __global__ void __launch_bounds__(256) skeleton_kernel(const double* __restrict_
   double val;
   {
     int U0 = u / NREF, V0 = v / NREF, tu = u - NREF * U0, tv = v - NREF * V0;
-    double wu[10], wv[10];
-    int ku0 = 0, ku1 = 0, kv0 = 0, kv1 = 0;
-    if (tu) { lagrange_weights(g.b, tu / double(NREF), wu); ku0 = -g.b; ku1 = g.b + 1; } else { wu[g.b] = 1.0; }
-    if (tv) { lagrange_weights(g.b, tv / double(NREF), wv); kv0 = -g.b; kv1 = g.b + 1; } else { wv[g.b] = 1.0; }
+    const double* wu = lw.w[tu];
+    const double* wv = lw.w[tv];
+    int ku0 = tu ? -g.b : 0, ku1 = tu ? g.b + 1 : 0, kv0 = tv ? -g.b : 0, kv1 = tv ? g.b + 1 : 0;
     int cd = gg[d] / NREF - g.O_lo;
     double s = 0.0;
     for (int ku = ku0; ku <= ku1; ++ku) {
@@ -245,35 +429,24 @@ __global__ void __launch_bounds__(256) skeleton_kernel(const double* __restrict_
     }
     val = s;
   }
-  // patches with g in Omega_beta(i): n i - db <= g <= n i + n + db
+  // patches with g in Omega_alpha(i): n i - da <= g <= n i + n + da
   int lo[3], hi[3];
   for (int a = 0; a < 3; ++a) {
-    int x = gg[a] - n - g.db;
+    int x = gg[a] - n - g.da;
     lo[a] = max(x >= 0 ? (x + n - 1) / n : -((-x) / n), 0);
-    int y = gg[a] + g.db;
-    hi[a] = min(y / n, g.ppa - 1);
+    hi[a] = min((gg[a] + g.da) / n, g.ppa - 1);
   }
-  const int Wa = g.Wa, Wb = g.Wb, K = g.K;
+  const int Wa = g.Wa;
   for (int i0 = lo[0]; i0 <= hi[0]; ++i0)
     for (int i1 = lo[1]; i1 <= hi[1]; ++i1)
       for (int i2 = lo[2]; i2 <= hi[2]; ++i2) {
         int r[3] = {gg[0] - n * i0, gg[1] - n * i1, gg[2] - n * i2};
         int pidx = (i0 * g.ppa + i1) * g.ppa + i2;
-        bool inner = r[0] >= -g.da && r[0] <= n + g.da && r[1] >= -g.da && r[1] <= n + g.da && r[2] >= -g.da &&
-                     r[2] <= n + g.da;
-        if (inner) {
-          int jj = (r[d] - g.P0) / n;
-          val += double(delta[((((int64_t(pidx) * 3 + d) * g.npl + jj) * Wa + (r[a0] + g.da)) * Wa) + (r[a1] + g.da)]);
-        } else if (K > 0) {
-          int jb = (r[d] - g.P0b) / n;
-          const double* dv = D + ((((int64_t(d) * g.nplb + jb) * Wb + (r[a0] + g.db)) * Wb) + (r[a1] + g.db)) * K;
-          const double* mv = mom + int64_t(pidx) * K;
-          double l = 0.0;
-          for (int k = 0; k < K; ++k) l += mv[k] * dv[k];
-          val += l;
-        }
+        int jj = (r[d] - g.P0) / n;
+        val += double(delta[((((int64_t(pidx) * 3 + d) * g.npl + jj) * Wa + (r[a0] + g.da)) * Wa) + (r[a1] + g.da)]);
       }
   int64_t node = (int64_t(gg[0]) * Np + gg[1]) * Np + gg[2];
+  if (annulus) val += phiB[node];
   phiB[node] = val;
   phi[node] = val + g.c2h2 * f[node];
 }
