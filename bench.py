@@ -182,7 +182,9 @@ def main():
 
     # roofline of the dominant kernel (largest measured time per solve)
     model = kernel_model(p32.info)
-    per_kernel = {k: v[1] / v[0] for k, v in kt32.items()}   # ms per launch
+    # ms per solve of each kernel (a kernel may be launched once per patch chunk)
+    per_kernel = {k: v[1] / args.steps for k, v in kt32.items()}
+    launches = {k: v[0] / args.steps for k, v in kt32.items()}
     dom = max(per_kernel, key=per_kernel.get)
     roof = None
     if dom in model:
@@ -196,7 +198,8 @@ def main():
             roof = {"bound": "alu", "achieved": round(tfs, 2), "peak": FP32_PEAK_TFLOPS, "unit": "TFLOP/s",
                     "frac": round(tfs / FP32_PEAK_TFLOPS, 4), "traffic": None}
         roof["kernel"] = dom
-        roof["ms_per_launch"] = round(per_kernel[dom], 4)
+        roof["launches_per_solve"] = launches[dom]
+        roof["ms_per_launch"] = round(per_kernel[dom] / launches[dom], 4)
 
     if args.copy_calibration:
         src = torch.empty(256 * 1024 * 1024, dtype=torch.uint8, device=dev)

@@ -67,9 +67,11 @@ template <typename T, int M> struct Batch {
   // odd padded line stride of the exchange buffer
   static constexpr int XL = (XLayout<M>::LINE % 2) ? XLayout<M>::LINE : XLayout<M>::LINE + 1;
 };
-// conv_out holds the whole (kx, y) plane in LDS; fp64 uses fewer lines per batch.
+// conv_out holds the whole (kx, y) plane in LDS, so one block fills a CU:
+// fp32 runs 512 threads (more lines per batch); fp64 fewer lines to fit.
 template <typename T, int M> struct OutBatch {
-  static constexpr int CB = sizeof(T) == 4 ? Batch<T, M>::CB : 4;
+  static constexpr int NT = sizeof(T) == 4 ? 512 : 256;
+  static constexpr int CB = sizeof(T) == 4 ? NT / Batch<T, M>::RMAX : 4;
 };
 
 template <typename T>
@@ -77,7 +79,8 @@ __device__ __forceinline__ cplx<T> conjw(cplx<T> w) { return {w.x, -w.y}; }
 
 template <typename T, int n, int M>
 __global__ void __launch_bounds__(256) conv_yz_kernel(const cplx<T>* __restrict__ X, const T* __restrict__ spec,
-                                                      cplx<T>* __restrict__ Zb, int Wp, int b, int Wa, int e, int da) {
+                                                      cplx<T>* __restrict__ Zb, int Wp, int b, int Wa, int e, int da,
+                                                      int p0) {
   constexpr int Mh = M / 2 + 1;
   constexpr int S = n + 1;
   constexpr int R1 = Split<M>::R1, R2 = Split<M>::R2;
@@ -86,7 +89,8 @@ __global__ void __launch_bounds__(256) conv_yz_kernel(const cplx<T>* __restrict_
   __shared__ cplx<T> Ex[CB * XL];
   __shared__ cplx<T> tw[M];
   __shared__ short zmap[M];
-  const int kx = blockIdx.x, p = blockIdx.y;
+  // p: patch; pc: its slot in the chunk-local Zb (patches p0 .. p0 + gridDim.y - 1)
+  const int kx = blockIdx.x, pc = blockIdx.y, p = p0 + pc;
   const int tid = threadIdx.x;
   fill_twiddles(tw, M);
   for (int m = tid; m < M; m += blockDim.x) zmap[m] = -1;
@@ -129,7 +133,7 @@ __global__ void __launch_bounds__(256) conv_yz_kernel(const cplx<T>* __restrict_
   }
   // ---- per column ky: FFT along z, times the spectrum, inverse along z ----
   const T* sp = spec + int64_t(kx) * Mh * Mh;
-  cplx<T>* zout = Zb + (int64_t(p) * Wp * Mh + kx) * M;
+  cplx<T>* zout = Zb + (int64_t(pc) * Wp * Mh + kx) * M;
 #pragma unroll 1
   for (int cb = 0; cb < M; cb += CB) {
     if (tid < CB * R2) {
@@ -199,8 +203,9 @@ struct OutGeom {
 __device__ __forceinline__ int mod_pos(int a, int m) { int r = a % m; return r < 0 ? r + m : r; }
 
 template <typename T, int n, int M>
-__global__ void __launch_bounds__(256) conv_out_kernel(const cplx<T>* __restrict__ Zb, T* __restrict__ coarse,
-                                                       T* __restrict__ planes, OutGeom g) {
+__global__ void __launch_bounds__((OutBatch<T, M>::NT)) conv_out_kernel(const cplx<T>* __restrict__ Zb,
+                                                                      T* __restrict__ coarse,
+                                                                      T* __restrict__ planes, OutGeom g, int p0) {
   constexpr int Mh = M / 2 + 1;
   constexpr int R1 = Split<M>::R1, R2 = Split<M>::R2;
   constexpr int CB = OutBatch<T, M>::CB, XL = Batch<T, M>::XL;
@@ -209,7 +214,7 @@ __global__ void __launch_bounds__(256) conv_out_kernel(const cplx<T>* __restrict
   __shared__ cplx<T> Ex[CB * XL];
   __shared__ cplx<T> tw[M];
   __shared__ short omap[M];
-  const int zi = blockIdx.x, p = blockIdx.y;
+  const int zi = blockIdx.x, pc = blockIdx.y, p = p0 + pc;
   const int Wp = g.Wp;
   const int tid = threadIdx.x;
   fill_twiddles(tw, M);
@@ -220,15 +225,28 @@ __global__ void __launch_bounds__(256) conv_out_kernel(const cplx<T>* __restrict
     omap[y < 0 ? y + M : y] = short(k);
   }
   __syncthreads();
-  const cplx<T>* zin = Zb + (int64_t(p) * Wp + zi) * Mh * M;
+  const cplx<T>* zin = Zb + (int64_t(pc) * Wp + zi) * Mh * M;
   // ---- inverse FFT along y for every kx (CB rows per batch) ----
+  // each thread's next-batch row values are loaded while the current batch
+  // is transformed
+  cplx<T> nxt[R2];
+  {
+    const int s = tid % R1, kx = tid / R1;
+#pragma unroll
+    for (int k2 = 0; k2 < R2; ++k2)
+      nxt[k2] = (tid < CB * R1 && kx < Mh) ? zin[int64_t(kx) * M + s + R1 * k2] : cplx<T>{T(0), T(0)};
+  }
 #pragma unroll 1
   for (int kb = 0; kb < Mh; kb += CB) {
     if (tid < CB * R1) {
-      const int s = tid % R1, r = tid / R1, kx = kb + r;
+      const int s = tid % R1, r = tid / R1;
       cplx<T> u[R2];
 #pragma unroll
-      for (int k2 = 0; k2 < R2; ++k2) u[k2] = kx < Mh ? zin[int64_t(kx) * M + s + R1 * k2] : cplx<T>{T(0), T(0)};
+      for (int k2 = 0; k2 < R2; ++k2) u[k2] = nxt[k2];
+      const int kn = kb + CB + r;
+#pragma unroll
+      for (int k2 = 0; k2 < R2; ++k2)
+        nxt[k2] = kn < Mh ? zin[int64_t(kn) * M + s + R1 * k2] : cplx<T>{T(0), T(0)};
       dft_reg<T, R2, -1>(u, tw, M / R2);
 #pragma unroll
       for (int t = 0; t < R2; ++t) {

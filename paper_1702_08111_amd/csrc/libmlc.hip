@@ -3,8 +3,10 @@
 // far-field tables) and the enqueueing of every stage of a solve.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <map>
 #include <mutex>
@@ -34,12 +36,16 @@ struct mlc_plan {
   mlc_problem prob{};
   mlc_plan_info info{};
   int S = 0, Mh = 0, Wp = 0, P0 = 0, eb = 0, Wtc = 0, Wb = 0, Wbc = 0, P0b = 0, nplb = 0, Kann = 0;
+  int chunk = 0;   // patches per local-convolution chunk
   ModeList modes{};
   LagW lagw{};
   void* conv_spec = nullptr;
   double* coarse_spec = nullptr;
   double* T = nullptr;
   double* D = nullptr;
+  double* Am = nullptr;   // skeleton far-field table laid out for MFMA
+  double* Tm = nullptr;   // coarse far-field table laid out for MFMA
+  MfmaGeom mg_skel{}, mg_coarse{};
   size_t o_mom = 0, o_X = 0, o_Z = 0, o_cs = 0, o_pl = 0, o_F = 0, o_tor = 0, o_phiH = 0, o_phiB = 0, o_dir = 0;
   size_t ws_total = 0;
   // per-kernel timing (instrumentation)
@@ -350,7 +356,9 @@ static void plan_destroy_buffers(mlc_plan* p) {
   hipFree(p->coarse_spec);
   hipFree(p->T);
   hipFree(p->D);
-  p->conv_spec = nullptr; p->coarse_spec = nullptr; p->T = nullptr; p->D = nullptr;
+  hipFree(p->Am);
+  hipFree(p->Tm);
+  p->conv_spec = nullptr; p->coarse_spec = nullptr; p->T = nullptr; p->D = nullptr; p->Am = nullptr; p->Tm = nullptr;
 }
 
 // spectrum of the periodised DGF on an M^3 torus -> real octant (fp64 work)
@@ -415,7 +423,44 @@ static mlc_status build_tables(mlc_plan* P, const double* G1) {
     if (e != hipSuccess) st = fail(ctx, MLC_ERR_DEVICE, std::string("table build: ") + hipGetErrorString(e));
   }
   hipFree(work); hipFree(oct); hipFree(coarse); hipFree(planes);
-  return st;
+  if (st != MLC_OK) return st;
+  // MFMA layouts of both tables
+  auto cdiv_floor = [](int a, int b) { return a >= 0 ? a / b : -((-a + b - 1) / b); };
+  auto cdiv_ceil = [](int a, int b) { return a >= 0 ? (a + b - 1) / b : -((-a) / b); };
+  const int n = I.n, db = I.d_beta, ppa = I.patches_per_axis, KP = (K + 3) / 4 * 4;
+  {
+    MfmaGeom& g = P->mg_skel;
+    g.ppa = ppa; g.K = K; g.KP = KP; g.nr = n * n;
+    g.e0lo = cdiv_ceil(-db, n);
+    g.ne0 = cdiv_floor(n + db, n) - g.e0lo + 1;
+    g.elo = cdiv_ceil(-db - (n - 1), n);
+    g.ne = cdiv_floor(n + db, n) - g.elo + 1;
+    g.nk0 = g.nk1 = g.nk2 = ppa + 1;
+    g.k0lo = g.k1lo = g.k2lo = 0;
+    int64_t total = int64_t(3) * g.ne0 * g.ne * g.ne * (KP / 4) * g.nr * 4;
+    if (hipMalloc(&P->Am, sizeof(double) * total) != hipSuccess)
+      return fail(ctx, MLC_ERR_OUT_OF_MEMORY, "far-field MFMA table allocation failed");
+    hipLaunchKernelGGL(skel_mfma_table_kernel, dim3(blocks_for(total)), dim3(256), 0, s, P->D, P->Am, n, db, P->P0b,
+                       P->nplb, P->Wb, K, g);
+  }
+  {
+    MfmaGeom& g = P->mg_coarse;
+    const int q = n / NREF, cb = db / NREF;
+    g.ppa = ppa; g.K = K; g.KP = KP; g.nr = q * q * q;
+    g.elo = cdiv_ceil(-cb - (q - 1), q);
+    g.ne = cdiv_floor((n + db) / NREF, q) - g.elo + 1;
+    g.e0lo = g.elo; g.ne0 = g.ne;
+    g.k0lo = g.k1lo = g.k2lo = cdiv_floor(I.S_lo, q);
+    g.nk0 = g.nk1 = g.nk2 = cdiv_floor(I.S_lo + I.Ns - 1, q) - g.k0lo + 1;
+    int64_t total = int64_t(g.ne) * g.ne * g.ne * (KP / 4) * g.nr * 4;
+    if (hipMalloc(&P->Tm, sizeof(double) * total) != hipSuccess)
+      return fail(ctx, MLC_ERR_OUT_OF_MEMORY, "far-field MFMA table allocation failed");
+    hipLaunchKernelGGL(coarse_mfma_table_kernel, dim3(blocks_for(total)), dim3(256), 0, s, P->T, P->Tm, q, db,
+                       P->Wbc, K, g);
+  }
+  hipError_t e = hipDeviceSynchronize();
+  if (e != hipSuccess) return fail(ctx, MLC_ERR_DEVICE, std::string("table layout: ") + hipGetErrorString(e));
+  return MLC_OK;
 }
 
 extern "C" mlc_status mlc_plan_create(mlc_context* ctx, const mlc_problem* prob, mlc_plan** out) {
@@ -487,7 +532,13 @@ extern "C" mlc_status mlc_plan_create(mlc_context* ctx, const mlc_problem* prob,
     auto take = [&](size_t bytes) { size_t at = o; o = align_up(o + bytes); return at; };
     P->o_mom = take(sizeof(double) * I.npatch * I.K);
     P->o_X = take(cs * I.npatch * P->Mh * P->S * P->S);
-    P->o_Z = take(cs * size_t(I.npatch) * P->Wp * P->Mh * I.M);
+    // chunk so that one chunk's Zb is at most ~2 GB (MLC_CONV_CHUNK overrides);
+    // smaller chunks measured no faster at 256^3, only the workspace shrinks
+    const size_t per_patch = cs * size_t(P->Wp) * P->Mh * I.M;
+    int chunk = int(std::max<size_t>(1, (size_t(2048) << 20) / per_patch));
+    if (const char* env = std::getenv("MLC_CONV_CHUNK")) chunk = std::max(1, std::atoi(env));
+    P->chunk = std::min(chunk, I.npatch);
+    P->o_Z = take(per_patch * P->chunk);
     P->o_cs = take(size_t(tsz) * I.npatch * cube(I.Wc));
     P->o_pl = take(size_t(tsz) * I.npatch * 3 * I.nplanes_a * I.Wa * I.Wa);
     P->o_F = take(sizeof(double) * cube(I.Ns));
@@ -596,15 +647,21 @@ static void launch_conv(const mlc_plan* P, const double* f, char* ws, hipStream_
     hipLaunchKernelGGL((conv_xdft_kernel<T, M>), dim3(P->S, I.npatch), dim3(256), 0, s, f, I.N, I.n,
                        I.patches_per_axis, X);
   }
-  {
-    TimedScope ts(P, s, "conv_yz");
-    hipLaunchKernelGGL((conv_yz_kernel<T, n, M>), dim3(P->Mh, I.npatch), dim3(256), 0, s, X,
-                       static_cast<const T*>(P->conv_spec), Zb, P->Wp, I.b, I.Wa, I.e, I.d_alpha);
-  }
   OutGeom g{I.n, I.e, I.d_alpha, I.b, I.Wa, P->Wp, I.Wc, P->P0, I.nplanes_a, I.h * I.h};
-  {
-    TimedScope ts(P, s, "conv_out");
-    hipLaunchKernelGGL((conv_out_kernel<T, n, M>), dim3(P->Wp, I.npatch), dim3(256), 0, s, Zb, cs, pl, g);
+  // patches in chunks: the chunk's z-transformed spectra (Zb) stay small
+  // enough to be re-read from the last-level cache
+  for (int p0 = 0; p0 < I.npatch; p0 += P->chunk) {
+    const int np = std::min(P->chunk, I.npatch - p0);
+    {
+      TimedScope ts(P, s, "conv_yz");
+      hipLaunchKernelGGL((conv_yz_kernel<T, n, M>), dim3(P->Mh, np), dim3(256), 0, s, X,
+                         static_cast<const T*>(P->conv_spec), Zb, P->Wp, I.b, I.Wa, I.e, I.d_alpha, p0);
+    }
+    {
+      TimedScope ts(P, s, "conv_out");
+      hipLaunchKernelGGL((conv_out_kernel<T, n, M>), dim3(P->Wp, np), dim3(OutBatch<T, M>::NT), 0, s, Zb, cs,
+                         pl, g, p0);
+    }
   }
 }
 
@@ -640,7 +697,10 @@ static void launch_rest(const mlc_plan* P, const double* f, double* phi, char* w
   if (P->Kann > 0) {
     TimedScope ts(P, s, "coarse_annulus");
     const int q = I.n / NREF;
-    hipLaunchKernelGGL(coarse_annulus_kernel, dim3(q * q * q), dim3(256), 0, s, mom, P->T, cg, F);
+    const MfmaGeom& g = P->mg_coarse;
+    const int nk = g.nk0 * g.nk1 * g.nk2;
+    hipLaunchKernelGGL(coarse_annulus_mfma_kernel, dim3((g.nr + 63) / 64, (nk + 63) / 64), dim3(256), 0, s, P->Tm,
+                       mom, g, q, I.S_lo, I.Ns, F);
   }
   // coarse solve
   const int Mc = I.M_coarse;
@@ -667,7 +727,10 @@ static void launch_rest(const mlc_plan* P, const double* f, double* phi, char* w
     int64_t cnt = int64_t(3) * (I.N / I.n + 1) * (I.N + 1) * (I.N + 1);
     if (P->Kann > 0) {
       TimedScope ts(P, s, "skeleton_annulus");
-      hipLaunchKernelGGL(skeleton_annulus_kernel, dim3(I.n * I.n, 3), dim3(256), 0, s, mom, P->D, sg, phiB);
+      const MfmaGeom& g = P->mg_skel;
+      const int nk = g.nk0 * g.nk1 * g.nk2;
+      hipLaunchKernelGGL(skeleton_annulus_mfma_kernel, dim3((g.nr + 63) / 64, (nk + 63) / 64, 3), dim3(256), 0, s,
+                         P->Am, mom, g, I.n, I.N, phiB);
     }
     TimedScope ts(P, s, "skeleton");
     hipLaunchKernelGGL(skeleton_kernel<T>, dim3(blocks_for(cnt)), dim3(256), 0, s, phiH, pl, f, sg, P->lagw,

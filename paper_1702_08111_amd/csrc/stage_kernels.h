@@ -119,87 +119,6 @@ __global__ void __launch_bounds__(256) coarse_rhs_kernel(const T* __restrict__ c
   F[idx] = s;
 }
 
-constexpr int MAXPATCH = 512;   // patches whose moments fit the LDS of one block
-
-// Annulus part of F^H (sec. 4.1 eq. FDLD, second case), added to F:
-//   F[c] += sum_i sum_p c_{i,p} T_p[c - n i / 4],  T zero on C(Omega_alpha(0)).
-// Write c = q k + rho (q = n/4, rho in [0, q)^3); then c - n i/4 =
-// q (k - i) + rho, so for one rho the sum is a convolution over the patch
-// lattice.  Block = one rho; the block's threads take the lattice points k;
-// all moments sit in LDS; the table values of one lattice offset are read
-// once and reused by every k.
-__global__ void __launch_bounds__(256) coarse_annulus_kernel(const double* __restrict__ mom,
-                                                             const double* __restrict__ Tt, CoarseGeom g,
-                                                             double* __restrict__ F) {
-  __shared__ double cm[MAXPATCH * KMAX];
-  const int n = g.n, q = n / NREF, K = g.K, ppa = g.ppa;
-  const int npatch = ppa * ppa * ppa;
-  const bool in_lds = npatch <= MAXPATCH;
-  if (in_lds)
-    for (int t = threadIdx.x; t < npatch * K; t += blockDim.x) cm[t] = mom[t];
-  const double* cmp = in_lds ? cm : mom;
-  const int rb = blockIdx.x;
-  const int rho[3] = {rb / (q * q), (rb / q) % q, rb % q};
-  // lattice points k with c = q k + rho inside the support box
-  int klo[3], kn[3], dlo[3], dhi[3];
-  const int S_hi = g.S_lo + g.Ns - 1;
-  const int blo = -g.db / NREF, bhi = (n + g.db) / NREF;   // C(Omega_beta(0))
-  for (int d = 0; d < 3; ++d) {
-    int a = g.S_lo - rho[d];
-    klo[d] = a >= 0 ? (a + q - 1) / q : -((-a) / q);
-    int bnd = S_hi - rho[d];
-    int khi = bnd >= 0 ? bnd / q : -((-bnd + q - 1) / q);
-    kn[d] = khi - klo[d] + 1;
-    // lattice offsets D = k - i with q D + rho inside C(Omega_beta(0))
-    int x = blo - rho[d];
-    dlo[d] = x >= 0 ? (x + q - 1) / q : -((-x) / q);
-    int y = bhi - rho[d];
-    dhi[d] = y >= 0 ? y / q : -((-y + q - 1) / q);
-  }
-  __syncthreads();
-  constexpr int PER = 16;
-  const int nk = kn[0] * kn[1] * kn[2];
-  const int ob = g.db / NREF, Wbc = g.Wbc;
-  for (int kbase = 0; kbase < nk; kbase += PER * 256) {
-  double acc[PER];
-#pragma unroll
-  for (int t = 0; t < PER; ++t) acc[t] = 0.0;
-  for (int D0 = dlo[0]; D0 <= dhi[0]; ++D0)
-    for (int D1 = dlo[1]; D1 <= dhi[1]; ++D1)
-      for (int D2 = dlo[2]; D2 <= dhi[2]; ++D2) {
-        const double* tv = Tt + ((int64_t(q * D0 + rho[0] + ob) * Wbc + (q * D1 + rho[1] + ob)) * Wbc +
-                                 (q * D2 + rho[2] + ob)) * K;
-        double tr[KMAX];
-#pragma unroll
-        for (int p = 0; p < KMAX; ++p) tr[p] = p < K ? tv[p] : 0.0;
-#pragma unroll
-        for (int t = 0; t < PER; ++t) {
-          int kk = kbase + threadIdx.x + t * 256;
-          if (kk >= nk) break;
-          int i0 = klo[0] + kk / (kn[1] * kn[2]) - D0;
-          int i1 = klo[1] + (kk / kn[2]) % kn[1] - D1;
-          int i2 = klo[2] + kk % kn[2] - D2;
-          if (i0 < 0 || i0 >= ppa || i1 < 0 || i1 >= ppa || i2 < 0 || i2 >= ppa) continue;
-          const double* mv = cmp + ((i0 * ppa + i1) * ppa + i2) * K;
-          double l = 0.0;
-#pragma unroll
-          for (int p = 0; p < KMAX; ++p)
-            if (p < K) l += tr[p] * mv[p];
-          acc[t] += l;
-        }
-      }
-#pragma unroll
-  for (int t = 0; t < PER; ++t) {
-    int kk = kbase + threadIdx.x + t * 256;
-    if (kk >= nk) break;
-    int c0 = q * (klo[0] + kk / (kn[1] * kn[2])) + rho[0];
-    int c1 = q * (klo[1] + (kk / kn[2]) % kn[1]) + rho[1];
-    int c2 = q * (klo[2] + kk % kn[2]) + rho[2];
-    F[(int64_t(c0 - g.S_lo) * g.Ns + (c1 - g.S_lo)) * g.Ns + (c2 - g.S_lo)] += acc[t];
-  }
-  }
-}
-
 // Coarse Hockney solve: F^H on slots [0, Ns)^3 of a zeroed Mc^3 torus.
 __global__ void coarse_fill_kernel(const double* __restrict__ F, cplx<double>* __restrict__ tor, int Ns, int Mc) {
   int64_t idx = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
@@ -249,6 +168,8 @@ __global__ void __launch_bounds__(256) plane_delta_kernel(T* __restrict__ planes
                                                           PlaneGeom g, LagW lw) {
   __shared__ double C[WCMAX * WCMAX];
   __shared__ double R[WCMAX * WAMAX];
+  __shared__ double W[4][10];
+  if (threadIdx.x < 40) W[threadIdx.x / 10][threadIdx.x % 10] = lw.w[threadIdx.x / 10][threadIdx.x % 10];
   const int pl = blockIdx.x, p = blockIdx.y;
   const int d = pl / g.npl, j = pl % g.npl;
   const int n = g.n, Wc = g.Wc, Wa = g.Wa, b = g.b, o = g.e / NREF;
@@ -272,7 +193,7 @@ __global__ void __launch_bounds__(256) plane_delta_kernel(T* __restrict__ planes
       s = row[0];
     } else {
       s = 0.0;
-      for (int k = -b; k <= b + 1; ++k) s += lw.w[tv][k + b] * row[k];
+      for (int k = -b; k <= b + 1; ++k) s += W[tv][k + b] * row[k];
     }
     R[cu * Wa + v] = s;
   }
@@ -287,7 +208,7 @@ __global__ void __launch_bounds__(256) plane_delta_kernel(T* __restrict__ planes
       s = col[0];
     } else {
       s = 0.0;
-      for (int k = -b; k <= b + 1; ++k) s += lw.w[tu][k + b] * col[k * Wa];
+      for (int k = -b; k <= b + 1; ++k) s += W[tu][k + b] * col[k * Wa];
     }
     out[t] = T(double(out[t]) - s);
   }
@@ -299,86 +220,197 @@ struct SkelGeom {
   double c2h2;   // C2 h^2
 };
 
-// Legendre far field of the annulus patches at every skeleton node
-// (sec. 4.1 eq. philocmlcII, second sum, after the regrouping by linearity):
-//   A[g] = sum_{i in S_beta(g)} sum_p c_{i,p} D_p[g - n i],
-// D_p = Phi_p - I(Phi_p) on the skeleton planes of Omega_beta(0), zero on
-// Omega_alpha(0).  With g = n k + r (r in [0, n)^2 in the face plane of
-// normal d, r_d = 0), g - n i = n (k - i) + r: for one (d, r) the sum is a
-// convolution over the patch lattice.  Block = one (r, d); threads take the
-// lattice points k; moments in LDS; the table values of one lattice offset
-// are read once per block.  Writes A into phiB (every canonical node).
-__global__ void __launch_bounds__(256) skeleton_annulus_kernel(const double* __restrict__ mom,
-                                                               const double* __restrict__ D, SkelGeom g,
-                                                               double* __restrict__ phiB) {
-  __shared__ double cm[MAXPATCH * KMAX];
-  const int n = g.n, K = g.K, ppa = g.ppa, N = g.N, Np = N + 1;
-  const int npatch = ppa * ppa * ppa;
-  const int ra = blockIdx.x / n, rb = blockIdx.x % n, d = blockIdx.y;
-  const int a0 = d == 0 ? 1 : 0, a1 = d == 2 ? 1 : 2;
-  // canonical plane: no in-plane axis below d on a patch face
-  if ((a0 < d && ra == 0) || (a1 < d && rb == 0)) return;
-  const bool in_lds = npatch <= MAXPATCH;
-  if (in_lds)
-    for (int t = threadIdx.x; t < npatch * K; t += blockDim.x) cm[t] = mom[t];
-  const double* cmp = in_lds ? cm : mom;
-  __syncthreads();
-  // offsets k - i = Dl with n Dl + r inside Omega_beta(0) on each axis
-  auto drange = [&](int r, int& lo, int& hi) {
-    int x = -g.db - r;
-    lo = x >= 0 ? (x + n - 1) / n : -((-x) / n);
-    int y = n + g.db - r;
-    hi = y >= 0 ? y / n : -((-y + n - 1) / n);
-  };
-  int dlo[3], dhi[3];
-  drange(0, dlo[0], dhi[0]);
-  drange(ra, dlo[1], dhi[1]);
-  drange(rb, dlo[2], dhi[2]);
-  // lattice points: kd in [0, ppa], ka, kb in [0, ppa] with n k + r <= N
-  const int nka = (ra == 0) ? ppa + 1 : ppa, nkb = (rb == 0) ? ppa + 1 : ppa;
-  const int nk = (ppa + 1) * nka * nkb;
-  constexpr int PER = 8;
-  for (int kbase = 0; kbase < nk; kbase += PER * 256) {
-    double acc[PER];
+// ---------------------------------------------- annulus sums on MFMA ----
+// Both Legendre far-field sums are dense contractions over (lattice offset E,
+// mode p) once the intra-patch position is fixed:
+//   out[r][k] = sum_{E, p} A[E][p][r] * c[k - E][p]
+// with A a re-laid-out, zero-padded far-field table and c the moments
+// (zero outside the patch lattice).  They run on v_mfma_f64_16x16x4f64:
+// A fragment lane l = row (r) l%16, column p = l/16; B fragment lane l =
+// column (k) l%16, row p = l/16; accumulator lane l, register j holds
+// out[4 j + l/16][l%16].
+typedef double f64x4 __attribute__((ext_vector_type(4)));
+
+struct MfmaGeom {
+  int ppa, K, KP;            // patches per axis, moments, moments padded to 4
+  int nr;                    // rows (intra-patch positions) of one orientation
+  int e0lo, ne0, elo, ne;    // offset box: first axis [e0lo, e0lo+ne0), others [elo, elo+ne)
+  int nk0, nk1, nk2;         // lattice box sizes (k0 slowest)
+  int k0lo, k1lo, k2lo;      // lattice box origins
+};
+
+// A rows for the skeleton: r = ra * n + rb over the face plane of normal d;
+// table Am[d][E][pc][r][4] (E = (E0, E1, E2) over the offset box), value
+// D[d][E0 plane][ra + n E1][rb + n E2][p] when inside the table, else 0.
+__global__ void skel_mfma_table_kernel(const double* __restrict__ D, double* __restrict__ Am, int n, int db,
+                                       int P0b, int nplb, int Wb, int K, MfmaGeom mg) {
+  const int npc = mg.KP / 4;
+  const int64_t per_d = int64_t(mg.ne0) * mg.ne * mg.ne * npc * mg.nr * 4;
+  int64_t idx = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (idx >= 3 * per_d) return;
+  int j = int(idx % 4);
+  int64_t t = idx / 4;
+  int r = int(t % mg.nr); t /= mg.nr;
+  int pc = int(t % npc); t /= npc;
+  int e2 = int(t % mg.ne); t /= mg.ne;
+  int e1 = int(t % mg.ne); t /= mg.ne;
+  int e0 = int(t % mg.ne0);
+  int d = int(t / mg.ne0);
+  int p = 4 * pc + j;
+  int E0 = mg.e0lo + e0, E1 = mg.elo + e1, E2 = mg.elo + e2;
+  int ra = r / n, rb = r % n;
+  int jb = (n * E0 - P0b) / n;
+  int ub = ra + n * E1 + db, vb = rb + n * E2 + db;
+  double v = 0.0;
+  if (p < K && jb >= 0 && jb < nplb && ub >= 0 && ub < Wb && vb >= 0 && vb < Wb)
+    v = D[((((int64_t(d) * nplb + jb) * Wb + ub) * Wb) + vb) * K + p];
+  Am[idx] = v;
+}
+
+// A rows for the coarse grid: rho = (r0, r1, r2) in [0, q)^3; table
+// Tm[E][pc][rho][4] = T[q E + rho][p] inside C(Omega_beta(0)), else 0.
+__global__ void coarse_mfma_table_kernel(const double* __restrict__ Tt, double* __restrict__ Tm, int q, int db,
+                                         int Wbc, int K, MfmaGeom mg) {
+  const int npc = mg.KP / 4;
+  const int64_t total = int64_t(mg.ne) * mg.ne * mg.ne * npc * mg.nr * 4;
+  int64_t idx = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (idx >= total) return;
+  int j = int(idx % 4);
+  int64_t t = idx / 4;
+  int r = int(t % mg.nr); t /= mg.nr;
+  int pc = int(t % npc); t /= npc;
+  int e2 = int(t % mg.ne); t /= mg.ne;
+  int e1 = int(t % mg.ne);
+  int e0 = int(t / mg.ne);
+  int p = 4 * pc + j;
+  int rr[3] = {r / (q * q), (r / q) % q, r % q};
+  int E[3] = {mg.elo + e0, mg.elo + e1, mg.elo + e2};
+  int ob = db / NREF;
+  int c[3];
+  bool ok = p < K;
+  for (int a = 0; a < 3; ++a) {
+    c[a] = q * E[a] + rr[a] + ob;
+    ok = ok && c[a] >= 0 && c[a] < Wbc;
+  }
+  Tm[idx] = ok ? Tt[((int64_t(c[0]) * Wbc + c[1]) * Wbc + c[2]) * K + p] : 0.0;
+}
+
+// One wave: 16 rows x 64 lattice points (four 16-column tiles); a block of
+// four waves covers 64 rows.  `orient` selects the skeleton orientation
+// (grid z), or is -1 for the coarse grid.  Returns accumulators per tile.
+__device__ __forceinline__ void annulus_mfma_tiles(const double* __restrict__ Am, const double* __restrict__ mom,
+                                                   const MfmaGeom& mg, int d, int rowbase, int kbase,
+                                                   f64x4 acc[4]) {
+  const int lane = threadIdx.x & 63;
+  const int rl = lane & 15, pj = lane >> 4;
+  const int npc = mg.KP / 4;
+  const int nk = mg.nk0 * mg.nk1 * mg.nk2;
+  int kk0[4], kk1[4], kk2[4];
+  bool kin[4];
 #pragma unroll
-    for (int t = 0; t < PER; ++t) acc[t] = 0.0;
-    for (int E0 = dlo[0]; E0 <= dhi[0]; ++E0)
-      for (int E1 = dlo[1]; E1 <= dhi[1]; ++E1)
-        for (int E2 = dlo[2]; E2 <= dhi[2]; ++E2) {
-          int jb = (n * E0 - g.P0b) / n;
-          const double* dv = D + ((((int64_t(d) * g.nplb + jb) * g.Wb + (ra + n * E1 + g.db)) * g.Wb) +
-                                  (rb + n * E2 + g.db)) * K;
-          double tr[KMAX];
+  for (int t = 0; t < 4; ++t) {
+    int k = kbase + 16 * t + rl;
+    kin[t] = k < nk;
+    int kc = kin[t] ? k : 0;
+    kk0[t] = mg.k0lo + kc / (mg.nk1 * mg.nk2);
+    kk1[t] = mg.k1lo + (kc / mg.nk2) % mg.nk1;
+    kk2[t] = mg.k2lo + kc % mg.nk2;
+    acc[t] = f64x4{0.0, 0.0, 0.0, 0.0};
+  }
+  const int ppa = mg.ppa, K = mg.K;
+  const int64_t per_d = int64_t(mg.ne0) * mg.ne * mg.ne * npc * mg.nr * 4;
+  const double* Ad = Am + (d > 0 ? d : 0) * per_d;
+  for (int e0 = 0; e0 < mg.ne0; ++e0)
+    for (int e1 = 0; e1 < mg.ne; ++e1)
+      for (int e2 = 0; e2 < mg.ne; ++e2) {
+        const int E0 = mg.e0lo + e0, E1 = mg.elo + e1, E2 = mg.elo + e2;
+        // patch index of every column for this offset (or -1)
+        int ip[4];
+        bool any = false;
 #pragma unroll
-          for (int p = 0; p < KMAX; ++p) tr[p] = p < K ? dv[p] : 0.0;
+        for (int t = 0; t < 4; ++t) {
+          // lattice axes (k0, k1, k2) are (normal, lower in-plane, upper in-plane)
+          // for a skeleton orientation d, array axes for the coarse grid
+          int i0 = kk0[t] - E0, i1 = kk1[t] - E1, i2 = kk2[t] - E2;
+          bool v = kin[t] && i0 >= 0 && i0 < ppa && i1 >= 0 && i1 < ppa && i2 >= 0 && i2 < ppa;
+          int ia[3];
+          if (d <= 0) { ia[0] = i0; ia[1] = i1; ia[2] = i2; }
+          else if (d == 1) { ia[1] = i0; ia[0] = i1; ia[2] = i2; }
+          else { ia[2] = i0; ia[0] = i1; ia[1] = i2; }
+          ip[t] = v ? (ia[0] * ppa + ia[1]) * ppa + ia[2] : -1;
+          any = any || v;
+        }
+        if (!__any(any)) continue;
+        const double* Ae = Ad + ((int64_t(e0) * mg.ne + e1) * mg.ne + e2) * npc * mg.nr * 4;
+        for (int pc = 0; pc < npc; ++pc) {
+          const double a = rowbase + rl < mg.nr ? Ae[(int64_t(pc) * mg.nr + rowbase + rl) * 4 + pj] : 0.0;
+          const int p = 4 * pc + pj;
 #pragma unroll
-          for (int t = 0; t < PER; ++t) {
-            int kk = kbase + threadIdx.x + t * 256;
-            if (kk >= nk) break;
-            int kd = kk / (nka * nkb), ka = (kk / nkb) % nka, kb = kk % nkb;
-            int i[3];
-            i[d] = kd - E0;
-            i[a0] = ka - E1;
-            i[a1] = kb - E2;
-            if (i[0] < 0 || i[0] >= ppa || i[1] < 0 || i[1] >= ppa || i[2] < 0 || i[2] >= ppa) continue;
-            const double* mv = cmp + ((i[0] * ppa + i[1]) * ppa + i[2]) * K;
-            double l = 0.0;
-#pragma unroll
-            for (int p = 0; p < KMAX; ++p)
-              if (p < K) l += tr[p] * mv[p];
-            acc[t] += l;
+          for (int t = 0; t < 4; ++t) {
+            const double b = (ip[t] >= 0 && p < K) ? mom[int64_t(ip[t]) * K + p] : 0.0;
+            acc[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc[t], 0, 0, 0);
           }
         }
+      }
+}
+
+// Skeleton: rows r = ra * n + rb of the face plane of normal d = blockIdx.z,
+// columns k = (kd, ka, kb) in [0, ppa]^3; writes the far field into phiB at
+// every canonical skeleton node.
+__global__ void __launch_bounds__(256) skeleton_annulus_mfma_kernel(const double* __restrict__ Am,
+                                                                    const double* __restrict__ mom, MfmaGeom mg,
+                                                                    int n, int N, double* __restrict__ phiB) {
+  const int d = blockIdx.z;
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int rowbase = blockIdx.x * 64 + wave * 16;
+  const int kbase = blockIdx.y * 64;
+  f64x4 acc[4];
+  annulus_mfma_tiles(Am, mom, mg, d, rowbase, kbase, acc);
+  const int a0 = d == 0 ? 1 : 0, a1 = d == 2 ? 1 : 2, Np = N + 1;
+  const int nk = mg.nk0 * mg.nk1 * mg.nk2;
 #pragma unroll
-    for (int t = 0; t < PER; ++t) {
-      int kk = kbase + threadIdx.x + t * 256;
-      if (kk >= nk) break;
-      int kd = kk / (nka * nkb), ka = (kk / nkb) % nka, kb = kk % nkb;
+  for (int t = 0; t < 4; ++t) {
+    int k = kbase + 16 * t + (lane & 15);
+    if (k >= nk) continue;
+    int kd = k / (mg.nk1 * mg.nk2), ka = (k / mg.nk2) % mg.nk1, kb = k % mg.nk2;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      int r = rowbase + 4 * j + (lane >> 4);
+      int ra = r / n, rb = r % n;
+      if ((a0 < d && ra == 0) || (a1 < d && rb == 0)) continue;     // not canonical
       int gg[3];
       gg[d] = n * kd;
       gg[a0] = n * ka + ra;
       gg[a1] = n * kb + rb;
-      phiB[(int64_t(gg[0]) * Np + gg[1]) * Np + gg[2]] = acc[t];
+      if (gg[a0] > N || gg[a1] > N) continue;
+      phiB[(int64_t(gg[0]) * Np + gg[1]) * Np + gg[2]] = acc[t][j];
+    }
+  }
+}
+
+// Coarse grid: rows rho in [0, q)^3, columns k over the lattice box; adds the
+// far field to F[c = q k + rho] inside the support box.
+__global__ void __launch_bounds__(256) coarse_annulus_mfma_kernel(const double* __restrict__ Tm,
+                                                                  const double* __restrict__ mom, MfmaGeom mg,
+                                                                  int q, int S_lo, int Ns, double* __restrict__ F) {
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int rowbase = blockIdx.x * 64 + wave * 16;
+  const int kbase = blockIdx.y * 64;
+  f64x4 acc[4];
+  annulus_mfma_tiles(Tm, mom, mg, -1, rowbase, kbase, acc);
+  const int nk = mg.nk0 * mg.nk1 * mg.nk2;
+#pragma unroll
+  for (int t = 0; t < 4; ++t) {
+    int k = kbase + 16 * t + (lane & 15);
+    if (k >= nk) continue;
+    int k0 = mg.k0lo + k / (mg.nk1 * mg.nk2), k1 = mg.k1lo + (k / mg.nk2) % mg.nk1, k2 = mg.k2lo + k % mg.nk2;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      int r = rowbase + 4 * j + (lane >> 4);
+      if (r >= mg.nr) continue;
+      int c0 = q * k0 + r / (q * q), c1 = q * k1 + (r / q) % q, c2 = q * k2 + r % q;
+      if (c0 < S_lo || c0 >= S_lo + Ns || c1 < S_lo || c1 >= S_lo + Ns || c2 < S_lo || c2 >= S_lo + Ns) continue;
+      F[(int64_t(c0 - S_lo) * Ns + (c1 - S_lo)) * Ns + (c2 - S_lo)] += acc[t][j];
     }
   }
 }
