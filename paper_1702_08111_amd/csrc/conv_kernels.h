@@ -101,17 +101,34 @@ __global__ void __launch_bounds__(256) conv_yz_kernel(const cplx<T>* __restrict_
   }
   const cplx<T>* xin = X + (int64_t(p) * Mh + kx) * S * S;
   const cplx<T> zero = {T(0), T(0)};
+  // the block's source rows, loaded up front (R1 >= ceil(S / R2) values each)
+  constexpr int NBR = (S + CB - 1) / CB;
+  constexpr int NJ = (S + R2 - 1) / R2;   // nonzero inputs of one pass-1 line
+  cplx<T> xr[NBR][NJ];
+  {
+    const int t = tid % R2, r = tid / R2;
+#pragma unroll
+    for (int j = 0; j < NBR; ++j)
+#pragma unroll
+      for (int j1 = 0; j1 < NJ; ++j1) {
+        int sz = j * CB + r, sy = t + R2 * j1;
+        xr[j][j1] = (tid < CB * R2 && sz < S && sy < S) ? xin[sz * S + sy] : zero;
+      }
+  }
   // ---- FFT along y of the S source rows (CB rows per batch) ----
 #pragma unroll 1
-  for (int rb = 0; rb < S; rb += CB) {
+  for (int rb = 0, jr = 0; rb < S; rb += CB, ++jr) {
     if (tid < CB * R2) {
-      const int t = tid % R2, r = tid / R2, sz = rb + r;
+      const int t = tid % R2, r = tid / R2;
       cplx<T> v[R1];
 #pragma unroll
-      for (int j1 = 0; j1 < R1; ++j1) {
-        int sy = t + R2 * j1;
-        v[j1] = (sz < S && sy < S) ? xin[sz * S + sy] : zero;
-      }
+      for (int j1 = 0; j1 < R1; ++j1) v[j1] = zero;
+#pragma unroll
+      for (int j = 0; j < NBR; ++j)
+        if (j == jr) {
+#pragma unroll
+          for (int j1 = 0; j1 < NJ; ++j1) v[j1] = xr[j][j1];
+        }
       dft_reg<T, R1, 1>(v, tw, M / R1);
       cplx<T>* ex = Ex + r * XL + t * (R1 + 1);
 #pragma unroll
@@ -214,39 +231,61 @@ __global__ void __launch_bounds__((OutBatch<T, M>::NT)) conv_out_kernel(const cp
   __shared__ cplx<T> Ex[CB * XL];
   __shared__ cplx<T> tw[M];
   __shared__ short omap[M];
+  // per output index i (same list on the y and x axes): coordinate and flags
+  // bit 0: inside Omega_alpha, bit 1: coarse node, bit 2: skeleton plane
+  __shared__ short ocrd[WPMAX];
+  __shared__ unsigned char oflg[WPMAX];
   const int zi = blockIdx.x, pc = blockIdx.y, p = p0 + pc;
   const int Wp = g.Wp;
   const int tid = threadIdx.x;
+  const cplx<T>* zin = Zb + (int64_t(pc) * Wp + zi) * Mh * M;
+  // issue the block's row loads first: all of them (fp32) or one batch ahead
+  constexpr int NBY = (Mh + CB - 1) / CB;
+  constexpr int PRE = sizeof(T) == 4 ? NBY : 1;
+  cplx<T> pre[PRE][R2];
+  {
+    const int s = tid % R1, r = tid / R1;
+#pragma unroll
+    for (int j = 0; j < PRE; ++j) {
+      const int kx = j * CB + r;
+#pragma unroll
+      for (int k2 = 0; k2 < R2; ++k2)
+        pre[j][k2] = (tid < CB * R1 && kx < Mh) ? zin[int64_t(kx) * M + s + R1 * k2] : cplx<T>{T(0), T(0)};
+    }
+  }
   fill_twiddles(tw, M);
   for (int m = tid; m < M; m += blockDim.x) omap[m] = -1;
   __syncthreads();
   for (int k = tid; k < Wp; k += blockDim.x) {
     int y = out_coord(k, g.b, g.Wa, g.e, g.da, n);
     omap[y < 0 ? y + M : y] = short(k);
+    ocrd[k] = short(y);
+    bool ina = y >= -g.da && y <= n + g.da;
+    oflg[k] = (ina ? 1 : 0) | (mod_pos(y, NREF) == 0 ? 2 : 0) | ((ina && mod_pos(y, n) == 0) ? 4 : 0);
   }
   __syncthreads();
-  const cplx<T>* zin = Zb + (int64_t(pc) * Wp + zi) * Mh * M;
   // ---- inverse FFT along y for every kx (CB rows per batch) ----
-  // each thread's next-batch row values are loaded while the current batch
-  // is transformed
-  cplx<T> nxt[R2];
-  {
-    const int s = tid % R1, kx = tid / R1;
-#pragma unroll
-    for (int k2 = 0; k2 < R2; ++k2)
-      nxt[k2] = (tid < CB * R1 && kx < Mh) ? zin[int64_t(kx) * M + s + R1 * k2] : cplx<T>{T(0), T(0)};
-  }
 #pragma unroll 1
-  for (int kb = 0; kb < Mh; kb += CB) {
+  for (int kb = 0, jb = 0; kb < Mh; kb += CB, ++jb) {
     if (tid < CB * R1) {
       const int s = tid % R1, r = tid / R1;
       cplx<T> u[R2];
+      if constexpr (PRE == NBY) {
+        // fully prefetched: select batch jb from registers
 #pragma unroll
-      for (int k2 = 0; k2 < R2; ++k2) u[k2] = nxt[k2];
-      const int kn = kb + CB + r;
+        for (int j = 0; j < PRE; ++j)
+          if (j == jb) {
 #pragma unroll
-      for (int k2 = 0; k2 < R2; ++k2)
-        nxt[k2] = kn < Mh ? zin[int64_t(kn) * M + s + R1 * k2] : cplx<T>{T(0), T(0)};
+            for (int k2 = 0; k2 < R2; ++k2) u[k2] = pre[j][k2];
+          }
+      } else {
+#pragma unroll
+        for (int k2 = 0; k2 < R2; ++k2) u[k2] = pre[0][k2];
+        const int kn = kb + CB + r;
+#pragma unroll
+        for (int k2 = 0; k2 < R2; ++k2)
+          pre[0][k2] = kn < Mh ? zin[int64_t(kn) * M + s + R1 * k2] : cplx<T>{T(0), T(0)};
+      }
       dft_reg<T, R2, -1>(u, tw, M / R2);
 #pragma unroll
       for (int t = 0; t < R2; ++t) {
@@ -271,10 +310,8 @@ __global__ void __launch_bounds__((OutBatch<T, M>::NT)) conv_out_kernel(const cp
     }
     __syncthreads();
   }
-  const int z = out_coord(zi, g.b, g.Wa, g.e, g.da, n);
-  const bool zin_a = z >= -g.da && z <= n + g.da;
-  const bool zc = mod_pos(z, NREF) == 0;
-  const bool zpl = zin_a && mod_pos(z, n) == 0;
+  const int z = ocrd[zi];
+  const bool zin_a = oflg[zi] & 1, zc = oflg[zi] & 2, zpl = oflg[zi] & 4;
   const int npl = g.npl, Wa = g.Wa, Wc = g.Wc;
   T* cbase = coarse + int64_t(p) * Wc * Wc * Wc;
   T* pbase = planes + int64_t(p) * 3 * npl * Wa * Wa;
@@ -317,25 +354,21 @@ __global__ void __launch_bounds__((OutBatch<T, M>::NT)) conv_out_kernel(const cp
       for (int j1 = 0; j1 < R1; ++j1) {
         int xi = omap[t + R2 * j1];
         if (xi < 0) continue;
-        int x = out_coord(xi, g.b, g.Wa, g.e, g.da, n);
-        const bool xin_a = x >= -g.da && x <= n + g.da;
-        const bool xc = mod_pos(x, NREF) == 0;
-        const bool xpl = xin_a && mod_pos(x, n) == 0;
+        const int x = ocrd[xi], xf = oflg[xi];
 #pragma unroll
         for (int h = 0; h < 2; ++h) {
           int yi = yb + 2 * c + h;
           if (yi >= Wp) continue;
-          int y = out_coord(yi, g.b, g.Wa, g.e, g.da, n);
+          const int y = ocrd[yi], yf = oflg[yi];
           T val = T(double(h ? v[j1].y : v[j1].x) * g.h2);
-          const bool yin_a = y >= -g.da && y <= n + g.da;
-          if (zc && xc && mod_pos(y, NREF) == 0)
+          if (zc && (xf & 2) && (yf & 2))
             cbase[(int64_t((z + g.e) / NREF) * Wc + (y + g.e) / NREF) * Wc + (x + g.e) / NREF] = val;
-          if (zpl && yin_a && xin_a)
+          if (zpl && (yf & 1) && (xf & 1))
             pbase[((int64_t(0) * npl + (z - g.P0) / n) * Wa + (y + g.da)) * Wa + (x + g.da)] = val;
-          if (zin_a && yin_a && xin_a) {
-            if (mod_pos(y, n) == 0)
+          if (zin_a && (yf & 1) && (xf & 1)) {
+            if (yf & 4)
               pbase[((int64_t(1) * npl + (y - g.P0) / n) * Wa + (z + g.da)) * Wa + (x + g.da)] = val;
-            if (xpl)
+            if (xf & 4)
               pbase[((int64_t(2) * npl + (x - g.P0) / n) * Wa + (z + g.da)) * Wa + (y + g.da)] = val;
           }
         }

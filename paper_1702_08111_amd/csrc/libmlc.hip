@@ -740,17 +740,13 @@ static void launch_rest(const mlc_plan* P, const double* f, double* phi, char* w
   {
     const int m = I.n - 1;
     TimedScope ts(P, s, "dirichlet");
-    dim3 g3(blocks_for(cube(m)), I.npatch);
-    hipLaunchKernelGGL(dirichlet_rhs_kernel, g3, dim3(256), 0, s, f, phiB, I.N, I.n, I.patches_per_axis, st,
-                       I.h * I.h, dir);
-    dim3 gs(m, I.npatch);
-    for (int a = 0; a < 3; ++a)
-      hipLaunchKernelGGL(dst_small_axis_kernel, gs, dim3(256), 0, s, dir, dir, I.n, a, 1.0);
-    hipLaunchKernelGGL(dirichlet_divide_kernel, g3, dim3(256), 0, s, dir, I.n, st);
-    for (int a = 0; a < 3; ++a)
-      hipLaunchKernelGGL(dst_small_axis_kernel, gs, dim3(256), 0, s, dir, dir, I.n, a, 2.0 / I.n);
-    hipLaunchKernelGGL(dirichlet_final_kernel, g3, dim3(256), 0, s, dir, f, I.N, I.n, I.patches_per_axis,
-                       I.h * I.h / 12.0, phi);
+    DirGeom dg{I.N, I.n, I.patches_per_axis, I.h * I.h, I.h * I.h / 12.0, 2.0 / I.n, st};
+    dim3 gd((I.npatch * m + 3) / 4);
+    hipLaunchKernelGGL(dirichlet_mfma_kernel<0>, gd, dim3(256), 0, s, f, phiB, dir, phi, dg);
+    hipLaunchKernelGGL(dirichlet_mfma_kernel<1>, gd, dim3(256), 0, s, f, phiB, dir, phi, dg);
+    hipLaunchKernelGGL(dirichlet_mfma_kernel<2>, gd, dim3(256), 0, s, f, phiB, dir, phi, dg);
+    hipLaunchKernelGGL(dirichlet_mfma_kernel<3>, gd, dim3(256), 0, s, f, phiB, dir, phi, dg);
+    hipLaunchKernelGGL(dirichlet_mfma_kernel<4>, gd, dim3(256), 0, s, f, phiB, dir, phi, dg);
   }
 }
 

@@ -483,95 +483,146 @@ __global__ void __launch_bounds__(256) skeleton_kernel(const double* __restrict_
   phi[node] = val + g.c2h2 * f[node];
 }
 
-// ----------------------------------------------------------- Dirichlet ----
-// rhs[p][m0][m1][m2] over the (n-1)^3 interior nodes of patch p:
-//   h^2 f[g] - sum_{s : g+s on the patch boundary} b_|s| phi^B[g+s].
-__global__ void dirichlet_rhs_kernel(const double* __restrict__ f, const double* __restrict__ phiB, int N, int n,
-                                     int ppa, Stencil st, double h2, double* __restrict__ rhs) {
-  const int m = n - 1;
-  const int p = blockIdx.y;
-  int64_t t = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-  if (t >= cube(m)) return;
-  int m2 = int(t % m), m1 = int((t / m) % m), m0 = int(t / (int64_t(m) * m));
-  const int i0 = p / (ppa * ppa), i1 = (p / ppa) % ppa, i2 = p % ppa;
-  const int64_t Np = N + 1;
-  int l0 = m0 + 1, l1 = m1 + 1, l2 = m2 + 1;   // patch-local node
-  int64_t base = (int64_t(n) * i0) * Np * Np + int64_t(n) * i1 * Np + int64_t(n) * i2;
-  double s = h2 * f[base + (l0 * Np + l1) * Np + l2];
-  if (l0 == 1 || l0 == n - 1 || l1 == 1 || l1 == n - 1 || l2 == 1 || l2 == n - 1) {
-    for (int s0 = -1; s0 <= 1; ++s0)
-      for (int s1 = -1; s1 <= 1; ++s1)
-        for (int s2 = -1; s2 <= 1; ++s2) {
-          int k0 = l0 + s0, k1 = l1 + s1, k2 = l2 + s2;
-          bool bnd = k0 == 0 || k0 == n || k1 == 0 || k1 == n || k2 == 0 || k2 == n;
-          if (!bnd) continue;
-          int nz = (s0 != 0) + (s1 != 0) + (s2 != 0);
-          s -= st.b[nz] * phiB[base + (k0 * Np + k1) * Np + k2];
-        }
-  }
-  rhs[int64_t(p) * cube(m) + t] = s;
-}
+// --------------------------------------------- Dirichlet solves on MFMA ----
+// The patch solve (sec. 4.1 eq. last_step_fulldiscr) diagonalises in the
+// DST-I basis of length m = n - 1: u = S^-1 (S rhs / lambda) with
+// S[k][j] = sin(pi (k+1)(j+1) / n) along each axis and S^-1 = (2/n) S.  Each
+// axis transform is, per slab (one wave, m x m padded to 32 x 32), the
+// product S (32 x 32) x slab (32 x 32) on v_mfma_f64_16x16x4f64.  Five passes:
+//   0: right-hand side h^2 f - (boundary terms), then forward along axis 2
+//   1: forward along axis 1
+//   2: forward along axis 0, divide by the symbol, inverse along axis 0
+//   3: inverse along axis 1
+//   4: inverse along axis 2, then phi = u + C2 h^2 f on the patch interior
+struct DirGeom {
+  int N, n, ppa;
+  double h2, c2h2, scale;   // scale: (2/n) per inverse pass
+  Stencil st;
+};
 
-// Dense DST-I of length m = n-1 along one axis of each patch's m^3 block:
-//   out[k] = scale * sum_j sin(pi (k+1)(j+1) / n) in[j].
-// Block (slab u, patch): the slab is the m x m plane of the two axes other
-// than `axis`... processed as m lines of length m.
-__global__ void __launch_bounds__(256) dst_small_axis_kernel(const double* __restrict__ in, double* __restrict__ out,
-                                                             int n, int axis, double scale) {
-  const int m = n - 1;
-  __shared__ double sn[SMAXN * SMAXN];
-  __shared__ double slab[SMAXN * SMAXN];
-  const int u = blockIdx.x, p = blockIdx.y;
-  for (int t = threadIdx.x; t < m * m; t += blockDim.x) {
-    int k = t / m, j = t % m;
-    // sin(pi (k+1)(j+1)/n) with an exact integer argument reduced mod 2n
-    int a = ((k + 1) * (j + 1)) % (2 * n);
-    sn[t] = sinpi(double(a) / double(n));
+template <int PASS>
+__global__ void __launch_bounds__(256) dirichlet_mfma_kernel(const double* __restrict__ f,
+                                                             const double* __restrict__ phiB,
+                                                             double* __restrict__ work, double* __restrict__ phi,
+                                                             DirGeom g) {
+  __shared__ double Sm[32 * 33];
+  __shared__ double Ls[4][32 * 33];
+  const int m = g.n - 1;
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  __shared__ double sn[2 * 32], cs[32];
+  // sin(pi a / n) for a < 2n and cos(pi (k+1) / n): every entry of the
+  // transform matrix and of the symbol is one of these
+  if (threadIdx.x < 2 * g.n) sn[threadIdx.x] = sinpi(double(threadIdx.x) / double(g.n));
+  if (threadIdx.x < m) cs[threadIdx.x] = cospi(double(threadIdx.x + 1) / double(g.n));
+  __syncthreads();
+  for (int t = threadIdx.x; t < 32 * 32; t += blockDim.x) {
+    int k = t / 32, j = t % 32;
+    Sm[k * 33 + j] = (k < m && j < m) ? sn[((k + 1) * (j + 1)) % (2 * g.n)] : 0.0;
   }
-  // slab: lines along `axis`; the other two axes are (u, w) with u the slower
-  const int64_t M3 = cube(m);
-  const int64_t sa = axis == 0 ? int64_t(m) * m : (axis == 1 ? m : 1);
-  const int64_t su = axis == 0 ? m : int64_t(m) * m;   // slower other axis
-  const int64_t sw = axis == 2 ? m : 1;                 // faster other axis
-  const double* ib = in + int64_t(p) * M3 + u * su;
-  for (int t = threadIdx.x; t < m * m; t += blockDim.x) {
-    int j = t / m, w = t % m;   // element j of line w
-    slab[j * m + w] = ib[j * sa + w * sw];
+  const int slab = blockIdx.x * 4 + wave;     // over patches x m
+  const int p = slab / m, u = slab % m;
+  const bool live = p < g.ppa * g.ppa * g.ppa;
+  const int axis = (PASS == 0 || PASS == 4) ? 2 : (PASS == 1 || PASS == 3) ? 1 : 0;
+  // element (j along the transform axis, w along the faster other axis) of slab u
+  const int64_t M3 = int64_t(m) * m * m;
+  auto off = [&](int j, int w) -> int64_t {
+    if (axis == 2) return int64_t(u) * m * m + int64_t(w) * m + j;
+    if (axis == 1) return int64_t(u) * m * m + int64_t(j) * m + w;
+    return int64_t(j) * m * m + int64_t(u) * m + w;
+  };
+  double* wp = work + int64_t(p) * M3;
+  const int i0 = p / (g.ppa * g.ppa), i1 = (p / g.ppa) % g.ppa, i2 = p % g.ppa;
+  const int64_t Np = g.N + 1;
+  const int64_t pbase = (int64_t(g.n) * i0) * Np * Np + int64_t(g.n) * i1 * Np + int64_t(g.n) * i2;
+  double* L = Ls[wave];
+  // load the slab (rows j, columns w), zero-padded to 32 x 32
+  for (int t = lane; t < 32 * 32; t += 64) {
+    int j = t / 32, w = t % 32;
+    double v = 0.0;
+    if (live && j < m && w < m) {
+      if constexpr (PASS == 0) {
+        // node (l0, l1, l2) = (u, w, j) + 1 inside the patch
+        int l0 = u + 1, l1 = w + 1, l2 = j + 1;
+        v = g.h2 * f[pbase + (l0 * Np + l1) * Np + l2];
+        if (l0 == 1 || l0 == g.n - 1 || l1 == 1 || l1 == g.n - 1 || l2 == 1 || l2 == g.n - 1) {
+          for (int s0 = -1; s0 <= 1; ++s0)
+            for (int s1 = -1; s1 <= 1; ++s1)
+              for (int s2 = -1; s2 <= 1; ++s2) {
+                int k0 = l0 + s0, k1 = l1 + s1, k2 = l2 + s2;
+                if (!(k0 == 0 || k0 == g.n || k1 == 0 || k1 == g.n || k2 == 0 || k2 == g.n)) continue;
+                int nz = (s0 != 0) + (s1 != 0) + (s2 != 0);
+                v -= g.st.b[nz] * phiB[pbase + (k0 * Np + k1) * Np + k2];
+              }
+        }
+      } else {
+        v = wp[off(j, w)];
+      }
+    }
+    L[j * 33 + w] = v;
   }
   __syncthreads();
-  double* ob = out + int64_t(p) * M3 + u * su;
-  for (int t = threadIdx.x; t < m * m; t += blockDim.x) {
-    int k = t / m, w = t % m;
-    double s = 0.0;
-    for (int j = 0; j < m; ++j) s += sn[k * m + j] * slab[j * m + w];
-    ob[k * sa + w * sw] = scale * s;
+  // out[k][w] = sum_j S[k][j] L[j][w]; A lane = row l%16, col l/16; B lane = col l%16, row l/16
+  auto product = [&](double* dst) {
+    f64x4 acc[2][2];
+#pragma unroll
+    for (int kt = 0; kt < 2; ++kt)
+#pragma unroll
+      for (int wt = 0; wt < 2; ++wt) acc[kt][wt] = f64x4{0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+    for (int jj = 0; jj < 8; ++jj) {
+      const int jrow = 4 * jj + (lane >> 4);
+#pragma unroll
+      for (int kt = 0; kt < 2; ++kt) {
+        const double a = Sm[(16 * kt + (lane & 15)) * 33 + jrow];
+#pragma unroll
+        for (int wt = 0; wt < 2; ++wt) {
+          const double b = L[jrow * 33 + 16 * wt + (lane & 15)];
+          acc[kt][wt] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc[kt][wt], 0, 0, 0);
+        }
+      }
+    }
+#pragma unroll
+    for (int kt = 0; kt < 2; ++kt)
+#pragma unroll
+      for (int wt = 0; wt < 2; ++wt)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) dst[(16 * kt + 4 * r + (lane >> 4)) * 33 + 16 * wt + (lane & 15)] = acc[kt][wt][r];
+  };
+  // each wave's slab is its own: the product reads all of L into the MFMA
+  // accumulators before writing the result back over it
+  double* O = L;
+  product(O);
+  __syncthreads();
+  if constexpr (PASS == 2) {
+    // divide the coefficient (k0 = row, k1 = u, k2 = w) by the symbol, then inverse along axis 0
+    for (int t = lane; t < 32 * 32; t += 64) {
+      int k = t / 32, w = t % 32;
+      double v = 0.0;
+      if (k < m && w < m) {
+        double c0 = cs[k], c1 = cs[u], c2 = cs[w];
+        double lam = g.st.b[0] + 2.0 * g.st.b[1] * (c0 + c1 + c2) + 4.0 * g.st.b[2] * (c0 * c1 + c0 * c2 + c1 * c2) +
+                     8.0 * g.st.b[3] * c0 * c1 * c2;
+        v = O[k * 33 + w] / lam;
+      }
+      L[k * 33 + w] = v;
+    }
+    __syncthreads();
+    product(O);
+    __syncthreads();
   }
-}
-
-__global__ void dirichlet_divide_kernel(double* __restrict__ data, int n, Stencil st) {
-  const int m = n - 1;
-  const int p = blockIdx.y;
-  int64_t t = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-  if (t >= cube(m)) return;
-  int k2 = int(t % m) + 1, k1 = int((t / m) % m) + 1, k0 = int(t / (int64_t(m) * m)) + 1;
-  double c0 = cospi(double(k0) / n), c1 = cospi(double(k1) / n), c2 = cospi(double(k2) / n);
-  double lam = st.b[0] + 2.0 * st.b[1] * (c0 + c1 + c2) + 4.0 * st.b[2] * (c0 * c1 + c0 * c2 + c1 * c2) +
-               8.0 * st.b[3] * c0 * c1 * c2;
-  data[int64_t(p) * cube(m) + t] /= lam;
-}
-
-// phi = u + C2 h^2 f on the interior nodes of every patch.
-__global__ void dirichlet_final_kernel(const double* __restrict__ u, const double* __restrict__ f, int N, int n,
-                                       int ppa, double c2h2, double* __restrict__ phi) {
-  const int m = n - 1;
-  const int p = blockIdx.y;
-  int64_t t = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-  if (t >= cube(m)) return;
-  int m2 = int(t % m), m1 = int((t / m) % m), m0 = int(t / (int64_t(m) * m));
-  const int i0 = p / (ppa * ppa), i1 = (p / ppa) % ppa, i2 = p % ppa;
-  const int64_t Np = N + 1;
-  int64_t node = (int64_t(n) * i0 + m0 + 1) * Np * Np + (int64_t(n) * i1 + m1 + 1) * Np + int64_t(n) * i2 + m2 + 1;
-  phi[node] = u[int64_t(p) * cube(m) + t] + c2h2 * f[node];
+  const double sc = (PASS >= 2) ? g.scale : 1.0;
+  if (!live) return;
+  for (int t = lane; t < m * m; t += 64) {
+    int k = t / m, w = t % m;
+    double v = sc * O[k * 33 + w];
+    if constexpr (PASS == 4) {
+      int l0 = u + 1, l1 = w + 1, l2 = k + 1;
+      int64_t node = pbase + (l0 * Np + l1) * Np + l2;
+      phi[node] = v + g.c2h2 * f[node];
+    } else {
+      wp[off(k, w)] = v;
+    }
+  }
 }
 
 }  // namespace mlc
