@@ -27,14 +27,16 @@ FP64_PEAK_TFLOPS = 78.6
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=20)
-    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--steps", type=int, default=200)
+    ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--workload", default="fp32_256_q6")
     ap.add_argument("--fp64-steps", type=int, default=5)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-budget", type=float, default=15.0, help="seconds of sampled per-patch oracle work")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain device copy of known size (for HBM counter scaling)")
+    ap.add_argument("--batch-steps", type=int, default=5,
+                    help="timed steps of the 64-problem uneven batch (0: skip)")
     return ap.parse_args()
 
 
@@ -129,6 +131,48 @@ def _cpu_baseline(name, budget, cores):
     }
 
 
+def batch_bench(ctx, steps, dev):
+    """The 64-problem uneven batch (N in {32, 64, 96, 128, 192}, 16^3-cell
+    patches, L19, float32 convolutions, 1-4 seeded bumps each) solved by
+    one mlc_solve_batched call per step."""
+    import torch
+    from paper_1702_08111_amd import mlc as gm
+    probs = mi.batch_problems()
+    plans_by_n = {}
+    plans = []
+    for N, _ in probs:
+        if N not in plans_by_n:
+            plans_by_n[N] = ctx.plan(gm.problem(N, 16, 3.0, 6.0, 4, 4, conv="fp32"))
+        plans.append(plans_by_n[N])
+    fs = [torch.from_numpy(mi.bump_charge(N, b)).to(dev) for N, b in probs]
+    phis = [torch.empty_like(f) for f in fs]
+    ws = torch.empty(gm.batch_workspace_bytes(plans), dtype=torch.uint8, device=dev)
+    stream = torch.cuda.current_stream()
+    gm.solve_batched(plans, fs, phis, ws, stream)
+    torch.cuda.synchronize()
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(steps)]
+    t0 = time.perf_counter()
+    for k in range(steps):
+        ev[k][0].record(stream)
+        gm.solve_batched(plans, fs, phis, ws, stream)
+        ev[k][1].record(stream)
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) * 1e3 / steps
+    lat = np.array([a.elapsed_time(b) for a, b in ev])
+    points = sum(N ** 3 for N, _ in probs)
+    out = {"value": points / (ms * 1e-3), "unit": "grid points/s", "ms_per_step": ms,
+           "p50_ms": float(np.percentile(lat, 50)), "p99_ms": float(np.percentile(lat, 99)),
+           "problems": len(probs), "patches": int(sum(p.info["npatch"] for p in plans)),
+           "workspace_gb": round(ws.numel() / 1e9, 2),
+           "config": "64 problems, N ~ U{32,64,96,128,192} (seed 104), 16^3-cell patches, L19, P=4, "
+                     "alpha=3, beta=6, fp32 convolutions, one mlc_solve_batched call"}
+    del ws, fs, phis
+    for p in plans_by_n.values():
+        p.close()
+    torch.cuda.empty_cache()
+    return out
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -207,6 +251,8 @@ def main():
         dst.copy_(src)
         torch.cuda.synchronize()
 
+    batch = batch_bench(ctx, args.batch_steps, dev) if args.batch_steps > 0 else None
+
     cpu = None
     if not args.no_cpu_baseline:
         cpu = cpu_baseline(args.workload, args.cpu_budget)
@@ -239,6 +285,7 @@ def main():
         "kernels_ms": {k: round(v, 4) for k, v in sorted(per_kernel.items(), key=lambda kv: -kv[1])},
         "roofline": roof,
         "cpu_baseline": cpu,
+        "batch": batch,
     }
     print(json.dumps(line), flush=True)
 

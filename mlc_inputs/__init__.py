@@ -18,6 +18,10 @@ Workloads (seeded with numpy's PCG64; per bump: centre (3 uniforms),
 radius, weight, in that order):
   one_bump      config 'plain FP64, 32^3': w = 1, R = 0.35, centre (1/2)^3
   bumps(k, ...) k bumps, centres U[lo, hi]^3, radii U(r0, r1), weights U(-1, 1)
+  batch_problems  uneven batch: per problem N ~ U{sizes}, then the bump count
+                U{1..4}, then its bumps, all from one stream
+  serving_requests  request mix: per request N, n, Q, bump count, bumps;
+                arrival gaps Exp(1/rate) from a second stream
 """
 from dataclasses import dataclass
 
@@ -40,11 +44,23 @@ def _rho(N, c, R):
 
 
 def bump_charge(N, bumps):
-    """Sum of bump charges sampled on the (N+1)^3 nodes g/N of [0, 1]^3."""
+    """Sum of bump charges sampled on the (N+1)^3 nodes g/N of [0, 1]^3
+    (each bump evaluated on the nodes of its bounding box only; it is zero
+    elsewhere)."""
     f = np.zeros((N + 1,) * 3)
+    ax = np.arange(N + 1) / N
     for bp in bumps:
-        r = _rho(N, bp.centre, bp.radius)
-        f += bp.weight * np.where(r < 1.0, (1.0 - r * r) ** 4, 0.0)
+        c, R = bp.centre, bp.radius
+        box = []
+        for d in range(3):
+            lo = max(int(np.floor((c[d] - R) * N)) - 1, 0)
+            hi = min(int(np.ceil((c[d] + R) * N)) + 1, N)
+            box.append(slice(lo, hi + 1))
+        d0 = (ax[box[0]] - c[0])[:, None, None]
+        d1 = (ax[box[1]] - c[1])[None, :, None]
+        d2 = (ax[box[2]] - c[2])[None, None, :]
+        r = np.sqrt(d0 * d0 + d1 * d1 + d2 * d2) / R
+        f[tuple(box)] += bp.weight * np.where(r < 1.0, (1.0 - r * r) ** 4, 0.0)
     return f
 
 
@@ -97,15 +113,52 @@ def one_bump():
     return [Bump((0.5, 0.5, 0.5), 0.35, 1.0)]
 
 
-def bumps(k, seed, radius=(0.1, 0.2), centre=(0.3, 0.7)):
-    """k seeded bumps; centres U[centre]^3, radii U(radius), weights U(-1, 1)."""
-    rng = np.random.Generator(np.random.PCG64(seed))
+def _draw_bumps(rng, k, radius, centre):
     out = []
     for _ in range(k):
         c = tuple(float(v) for v in rng.uniform(centre[0], centre[1], size=3))
         R = float(rng.uniform(radius[0], radius[1]))
         w = float(rng.uniform(-1.0, 1.0))
         out.append(Bump(c, R, w))
+    return out
+
+
+def bumps(k, seed, radius=(0.1, 0.2), centre=(0.3, 0.7)):
+    """k seeded bumps; centres U[centre]^3, radii U(radius), weights U(-1, 1)."""
+    return _draw_bumps(np.random.Generator(np.random.PCG64(seed)), k, radius, centre)
+
+
+BATCH_SIZES = (32, 64, 96, 128, 192)
+
+
+def batch_problems(count=64, seed=104, sizes=BATCH_SIZES, radius=(0.1, 0.2), centre=(0.3, 0.7)):
+    """Uneven batch: [(N, bumps)], N ~ U{sizes}, 1-4 bumps each."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    out = []
+    for _ in range(count):
+        N = int(sizes[int(rng.integers(0, len(sizes)))])
+        k = int(rng.integers(1, 5))
+        out.append((N, _draw_bumps(rng, k, radius, centre)))
+    return out
+
+
+SERVING_SIZES = (64, 128, 192, 256)
+
+
+def serving_requests(count, rate, seed=105, sizes=SERVING_SIZES, patches=(16, 32), orders=(4, 6)):
+    """Request stream: [(t_arrival, N, n, Q, bumps)] with Poisson arrivals at
+    `rate` per second (gaps from a second stream seeded seed + 1)."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    gaps = np.random.Generator(np.random.PCG64(seed + 1)).exponential(1.0 / rate, size=count)
+    out = []
+    t = 0.0
+    for i in range(count):
+        N = int(sizes[int(rng.integers(0, len(sizes)))])
+        n = int(patches[int(rng.integers(0, len(patches)))])
+        Q = int(orders[int(rng.integers(0, len(orders)))])
+        k = int(rng.integers(1, 5))
+        t += float(gaps[i])
+        out.append((t, N, n, Q, _draw_bumps(rng, k, (0.1, 0.2), (0.3, 0.7))))
     return out
 
 

@@ -31,4 +31,34 @@ __host__ __device__ inline int out_coord(int i, int b, int Wa, int e, int da, in
   return n + da + NREF * (i - b - Wa + 1);
 }
 
+// One problem of a batch as the patch-level kernels see it.  Patches of all
+// problems are numbered consecutively: problem k owns the global patch slots
+// [patch0, patch0 + ppa^3).
+struct ProbDesc {
+  const double* f;
+  double* phi;
+  double* phiB;
+  int N, ppa, patch0, pad;
+  double h2;    // h^2
+  double R15;   // (n h / 2)^{3/2}, the Legendre basis scale
+};
+
+// Index of the problem owning global patch slot g (descriptors sorted by
+// patch0, patch0 of the first is 0).
+__device__ __forceinline__ int find_problem(const ProbDesc* __restrict__ pd, int nprob, int g) {
+  int lo = 0, hi = nprob - 1;
+  while (lo < hi) {
+    int mid = (lo + hi + 1) >> 1;
+    if (pd[mid].patch0 <= g) lo = mid; else hi = mid - 1;
+  }
+  return lo;
+}
+
+// Descriptors travel to the device as kernel arguments, DESC_PACK at a time.
+constexpr int DESC_PACK = 8;
+struct DescPack { ProbDesc d[DESC_PACK]; int count; };
+__global__ void desc_upload_kernel(ProbDesc* __restrict__ dst, DescPack pk) {
+  if (int(threadIdx.x) < pk.count) dst[threadIdx.x] = pk.d[threadIdx.x];
+}
+
 }  // namespace mlc

@@ -24,15 +24,18 @@
 namespace mlc {
 
 template <typename T, int M>
-__global__ void __launch_bounds__(256) conv_xdft_kernel(const double* __restrict__ f, int N, int n, int ppa,
-                                                        cplx<T>* __restrict__ X) {
+__global__ void __launch_bounds__(256) conv_xdft_kernel(const ProbDesc* __restrict__ pd, int nprob, int n,
+                                                        cplx<T>* __restrict__ X, int p0) {
   constexpr int Mh = M / 2 + 1;
   __shared__ T q[SMAX * SMAX];
   __shared__ cplx<T> tw[M];
   const int S = n + 1;
-  const int p = blockIdx.y, sz = blockIdx.x;
-  const int i0 = p / (ppa * ppa), i1 = (p / ppa) % ppa, i2 = p % ppa;
-  const int64_t Np = N + 1;
+  const int p = p0 + blockIdx.y, sz = blockIdx.x;
+  const ProbDesc& D = pd[find_problem(pd, nprob, p)];
+  const double* f = D.f;
+  const int ppa = D.ppa, pl = p - D.patch0;
+  const int i0 = pl / (ppa * ppa), i1 = (pl / ppa) % ppa, i2 = pl % ppa;
+  const int64_t Np = D.N + 1;
   const double cz = (sz == 0 || sz == n) ? 0.5 : 1.0;
   const double* fp = f + (int64_t(n) * i0 + sz) * Np * Np + int64_t(n) * i1 * Np + int64_t(n) * i2;
   for (int t = threadIdx.x; t < S * S; t += blockDim.x) {
@@ -214,7 +217,6 @@ __global__ void __launch_bounds__(256) conv_yz_kernel(const cplx<T>* __restrict_
 
 struct OutGeom {
   int n, e, da, b, Wa, Wp, Wc, P0, npl;
-  double h2;
 };
 
 __device__ __forceinline__ int mod_pos(int a, int m) { int r = a % m; return r < 0 ? r + m : r; }
@@ -222,7 +224,9 @@ __device__ __forceinline__ int mod_pos(int a, int m) { int r = a % m; return r <
 template <typename T, int n, int M>
 __global__ void __launch_bounds__((OutBatch<T, M>::NT)) conv_out_kernel(const cplx<T>* __restrict__ Zb,
                                                                       T* __restrict__ coarse,
-                                                                      T* __restrict__ planes, OutGeom g, int p0) {
+                                                                      T* __restrict__ planes, OutGeom g,
+                                                                      const ProbDesc* __restrict__ pd, int nprob,
+                                                                      int p0) {
   constexpr int Mh = M / 2 + 1;
   constexpr int R1 = Split<M>::R1, R2 = Split<M>::R2;
   constexpr int CB = OutBatch<T, M>::CB, XL = Batch<T, M>::XL;
@@ -238,6 +242,7 @@ __global__ void __launch_bounds__((OutBatch<T, M>::NT)) conv_out_kernel(const cp
   const int zi = blockIdx.x, pc = blockIdx.y, p = p0 + pc;
   const int Wp = g.Wp;
   const int tid = threadIdx.x;
+  const double h2 = pd[find_problem(pd, nprob, p)].h2;
   const cplx<T>* zin = Zb + (int64_t(pc) * Wp + zi) * Mh * M;
   // issue the block's row loads first: all of them (fp32) or one batch ahead
   constexpr int NBY = (Mh + CB - 1) / CB;
@@ -360,7 +365,7 @@ __global__ void __launch_bounds__((OutBatch<T, M>::NT)) conv_out_kernel(const cp
           int yi = yb + 2 * c + h;
           if (yi >= Wp) continue;
           const int y = ocrd[yi], yf = oflg[yi];
-          T val = T(double(h ? v[j1].y : v[j1].x) * g.h2);
+          T val = T(double(h ? v[j1].y : v[j1].x) * h2);
           if (zc && (xf & 2) && (yf & 2))
             cbase[(int64_t((z + g.e) / NREF) * Wc + (y + g.e) / NREF) * Wc + (x + g.e) / NREF] = val;
           if (zpl && (yf & 1) && (xf & 1))

@@ -36,7 +36,6 @@ struct mlc_plan {
   mlc_problem prob{};
   mlc_plan_info info{};
   int S = 0, Mh = 0, Wp = 0, P0 = 0, eb = 0, Wtc = 0, Wb = 0, Wbc = 0, P0b = 0, nplb = 0, Kann = 0;
-  int chunk = 0;   // patches per local-convolution chunk
   ModeList modes{};
   LagW lagw{};
   void* conv_spec = nullptr;
@@ -46,7 +45,8 @@ struct mlc_plan {
   double* Am = nullptr;   // skeleton far-field table laid out for MFMA
   double* Tm = nullptr;   // coarse far-field table laid out for MFMA
   MfmaGeom mg_skel{}, mg_coarse{};
-  size_t o_mom = 0, o_X = 0, o_Z = 0, o_cs = 0, o_pl = 0, o_F = 0, o_tor = 0, o_phiH = 0, o_phiB = 0, o_dir = 0;
+  // workspace offsets of the plan's own (batch-of-one) layout
+  size_t o_mom = 0, o_cs = 0, o_pl = 0, o_F = 0, o_phiH = 0, o_phiB = 0;
   size_t ws_total = 0;
   // per-kernel timing (instrumentation)
   struct Pending { const char* name; hipEvent_t a, b; };
@@ -463,6 +463,74 @@ static mlc_status build_tables(mlc_plan* P, const double* G1) {
   return MLC_OK;
 }
 
+// --------------------------------------------------------- batch layout
+// Plans whose patch-level work is identical (patch size, margins, P, Q, b,
+// convolution precision, local torus, DGF table) form one class: the patch
+// kernels of all their problems run as single launches over the
+// concatenated patch list, with per-problem data reached through ProbDesc.
+static bool same_class(const mlc_plan* a, const mlc_plan* b) {
+  const mlc_plan_info &A = a->info, &B = b->info;
+  return A.n == B.n && A.d_alpha == B.d_alpha && A.d_beta == B.d_beta && A.P == B.P && A.Q == B.Q &&
+         A.b == B.b && A.conv_precision == B.conv_precision && A.M == B.M && A.Z == B.Z;
+}
+
+// Workspace of one class group, relative to the group's base:
+//   descriptors | per patch (all problems): moments, x-DFTs, one chunk of
+//   z-transformed spectra, coarse samples, skeleton planes, Dirichlet work |
+//   per problem: F^H, coarse torus (consecutive within equal M_coarse),
+//   phi^H, phi^B.
+struct Layout {
+  size_t o_desc = 0, o_mom = 0, o_X = 0, o_Z = 0, o_cs = 0, o_pl = 0, o_dir = 0;
+  std::vector<size_t> o_F, o_tor, o_phiH, o_phiB;
+  std::vector<int> patch0;
+  int total = 0, chunk = 0;
+  size_t bytes = 0;
+};
+
+static const int kMaxGridY = 65535;
+
+static Layout layout_of(const std::vector<mlc_plan*>& g) {
+  Layout L;
+  const mlc_plan* P = g[0];
+  const mlc_plan_info& I = P->info;
+  const int np = int(g.size());
+  const size_t tsz = I.conv_precision == MLC_CONV_FP32 ? 4 : 8, csz = 2 * tsz;
+  for (int k = 0; k < np; ++k) {
+    L.patch0.push_back(L.total);
+    L.total += g[k]->info.npatch;
+  }
+  const size_t T = size_t(L.total);
+  size_t o = 0;
+  auto take = [&](size_t bytes) { size_t at = o; o = align_up(o + bytes); return at; };
+  L.o_desc = take(sizeof(ProbDesc) * np);
+  L.o_mom = take(sizeof(double) * T * I.K);
+  L.o_X = take(csz * T * P->Mh * P->S * P->S);
+  // chunk so that one chunk's z-transformed spectra stay at most ~2 GB
+  // (MLC_CONV_CHUNK overrides); smaller chunks measured no faster at 256^3
+  const size_t per_patch = csz * size_t(P->Wp) * P->Mh * I.M;
+  int chunk = int(std::max<size_t>(1, (size_t(2048) << 20) / per_patch));
+  if (const char* env = std::getenv("MLC_CONV_CHUNK")) chunk = std::max(1, std::atoi(env));
+  L.chunk = std::min(std::min(chunk, L.total), kMaxGridY);
+  L.o_Z = take(per_patch * L.chunk);
+  L.o_cs = take(tsz * T * cube(I.Wc));
+  L.o_pl = take(tsz * T * 3 * I.nplanes_a * I.Wa * I.Wa);
+  L.o_dir = take(sizeof(double) * T * cube(I.n - 1));
+  L.o_F.resize(np); L.o_tor.resize(np); L.o_phiH.resize(np); L.o_phiB.resize(np);
+  for (int k = 0; k < np; ++k) L.o_F[k] = take(sizeof(double) * cube(g[k]->info.Ns));
+  std::vector<int> done(np, 0);
+  for (int k = 0; k < np; ++k) {
+    if (done[k]) continue;
+    const int Mc = g[k]->info.M_coarse;
+    for (int j = k; j < np; ++j)
+      if (!done[j] && g[j]->info.M_coarse == Mc) { L.o_tor[j] = o; o += sizeof(cplx<double>) * cube(Mc); done[j] = 1; }
+    o = align_up(o);
+  }
+  for (int k = 0; k < np; ++k) L.o_phiH[k] = take(sizeof(double) * cube(g[k]->info.No));
+  for (int k = 0; k < np; ++k) L.o_phiB[k] = take(sizeof(double) * cube(g[k]->info.N + 1));
+  L.bytes = o;
+  return L;
+}
+
 extern "C" mlc_status mlc_plan_create(mlc_context* ctx, const mlc_problem* prob, mlc_plan** out) {
   if (!ctx || !prob || !out) return fail(ctx, MLC_ERR_INVALID_ARG, "null argument");
   std::string why;
@@ -525,28 +593,16 @@ extern "C" mlc_status mlc_plan_create(mlc_context* ctx, const mlc_problem* prob,
     s = build_tables(P, G1);
     if (s != MLC_OK) { plan_destroy_buffers(P); delete P; return s; }
   }
-  // workspace layout
+  // workspace layout (a batch of one)
   {
-    const size_t cs = tsz * 2;   // complex in conv precision
-    size_t o = 0;
-    auto take = [&](size_t bytes) { size_t at = o; o = align_up(o + bytes); return at; };
-    P->o_mom = take(sizeof(double) * I.npatch * I.K);
-    P->o_X = take(cs * I.npatch * P->Mh * P->S * P->S);
-    // chunk so that one chunk's Zb is at most ~2 GB (MLC_CONV_CHUNK overrides);
-    // smaller chunks measured no faster at 256^3, only the workspace shrinks
-    const size_t per_patch = cs * size_t(P->Wp) * P->Mh * I.M;
-    int chunk = int(std::max<size_t>(1, (size_t(2048) << 20) / per_patch));
-    if (const char* env = std::getenv("MLC_CONV_CHUNK")) chunk = std::max(1, std::atoi(env));
-    P->chunk = std::min(chunk, I.npatch);
-    P->o_Z = take(per_patch * P->chunk);
-    P->o_cs = take(size_t(tsz) * I.npatch * cube(I.Wc));
-    P->o_pl = take(size_t(tsz) * I.npatch * 3 * I.nplanes_a * I.Wa * I.Wa);
-    P->o_F = take(sizeof(double) * cube(I.Ns));
-    P->o_tor = take(sizeof(cplx<double>) * cube(I.M_coarse));
-    P->o_phiH = take(sizeof(double) * cube(I.No));
-    P->o_phiB = take(sizeof(double) * cube(I.N + 1));
-    P->o_dir = take(sizeof(double) * I.npatch * cube(I.n - 1));
-    P->ws_total = o;
+    Layout L = layout_of({P});
+    P->o_mom = L.o_mom;
+    P->o_cs = L.o_cs;
+    P->o_pl = L.o_pl;
+    P->o_F = L.o_F[0];
+    P->o_phiH = L.o_phiH[0];
+    P->o_phiB = L.o_phiB[0];
+    P->ws_total = L.bytes;
   }
   *out = P;
   return MLC_OK;
@@ -635,40 +691,96 @@ extern "C" mlc_status mlc_workspace_view(const mlc_plan* plan, void* ws, int32_t
 }
 
 // ---------------------------------------------------------------- solve
+// One class group of a batch, enqueued on one stream.
+struct Group {
+  std::vector<mlc_plan*> plans;
+  std::vector<int> pos;   // positions of the problems in the caller's batch
+  std::vector<const double*> f;
+  std::vector<double*> phi;
+  Layout L;
+  size_t off = 0;         // the group's region of the workspace
+  char* ws = nullptr;
+  ProbDesc* desc = nullptr;
+};
+
+template <int M>
+static void fft3_batch_impl(cplx<double>* data, int dir, int nb, hipStream_t s) {
+  constexpr int NL = (M % 4 == 0) ? 4 : 2;
+  dim3 grid(M / NL, M, nb);
+  for (int axis = 0; axis < 3; ++axis) {
+    if (dir > 0) hipLaunchKernelGGL((fft_axis_kernel<double, M, NL, 1>), grid, dim3(256), 0, s, data, axis);
+    else hipLaunchKernelGGL((fft_axis_kernel<double, M, NL, -1>), grid, dim3(256), 0, s, data, axis);
+  }
+}
+static bool fft3_batch(cplx<double>* data, int M, int dir, int nb, hipStream_t s) {
+  switch (M) {
+#define CASE(MM) case MM: fft3_batch_impl<MM>(data, dir, nb, s); return true;
+    MLC_FFT_SIZES(CASE)
+#undef CASE
+  }
+  return false;
+}
+
+static void upload_descs(const Group& G, hipStream_t s) {
+  const int np = int(G.plans.size());
+  for (int k0 = 0; k0 < np; k0 += DESC_PACK) {
+    DescPack pk{};
+    pk.count = std::min(DESC_PACK, np - k0);
+    for (int j = 0; j < pk.count; ++j) {
+      const int k = k0 + j;
+      const mlc_plan_info& I = G.plans[k]->info;
+      ProbDesc& d = pk.d[j];
+      d.f = G.f[k];
+      d.phi = G.phi[k];
+      d.phiB = reinterpret_cast<double*>(G.ws + G.L.o_phiB[k]);
+      d.N = I.N;
+      d.ppa = I.patches_per_axis;
+      d.patch0 = G.L.patch0[k];
+      d.h2 = I.h * I.h;
+      d.R15 = std::pow(I.n * I.h / 2.0, 1.5);
+    }
+    hipLaunchKernelGGL(desc_upload_kernel, dim3(1), dim3(DESC_PACK), 0, s, G.desc + k0, pk);
+  }
+}
+
 template <typename T, int n, int M>
-static void launch_conv(const mlc_plan* P, const double* f, char* ws, hipStream_t s) {
+static void launch_conv(const Group& G, hipStream_t s) {
+  const mlc_plan* P = G.plans[0];
   const mlc_plan_info& I = P->info;
-  cplx<T>* X = reinterpret_cast<cplx<T>*>(ws + P->o_X);
-  cplx<T>* Zb = reinterpret_cast<cplx<T>*>(ws + P->o_Z);
-  T* cs = reinterpret_cast<T*>(ws + P->o_cs);
-  T* pl = reinterpret_cast<T*>(ws + P->o_pl);
+  const Layout& L = G.L;
+  const int np = int(G.plans.size());
+  cplx<T>* X = reinterpret_cast<cplx<T>*>(G.ws + L.o_X);
+  cplx<T>* Zb = reinterpret_cast<cplx<T>*>(G.ws + L.o_Z);
+  T* cs = reinterpret_cast<T*>(G.ws + L.o_cs);
+  T* pl = reinterpret_cast<T*>(G.ws + L.o_pl);
   {
     TimedScope ts(P, s, "conv_xdft");
-    hipLaunchKernelGGL((conv_xdft_kernel<T, M>), dim3(P->S, I.npatch), dim3(256), 0, s, f, I.N, I.n,
-                       I.patches_per_axis, X);
+    for (int p0 = 0; p0 < L.total; p0 += kMaxGridY)
+      hipLaunchKernelGGL((conv_xdft_kernel<T, M>), dim3(P->S, std::min(kMaxGridY, L.total - p0)), dim3(256), 0, s,
+                         G.desc, np, I.n, X, p0);
   }
-  OutGeom g{I.n, I.e, I.d_alpha, I.b, I.Wa, P->Wp, I.Wc, P->P0, I.nplanes_a, I.h * I.h};
+  OutGeom g{I.n, I.e, I.d_alpha, I.b, I.Wa, P->Wp, I.Wc, P->P0, I.nplanes_a};
   // patches in chunks: the chunk's z-transformed spectra (Zb) stay small
   // enough to be re-read from the last-level cache
-  for (int p0 = 0; p0 < I.npatch; p0 += P->chunk) {
-    const int np = std::min(P->chunk, I.npatch - p0);
+  for (int p0 = 0; p0 < L.total; p0 += L.chunk) {
+    const int cnt = std::min(L.chunk, L.total - p0);
     {
       TimedScope ts(P, s, "conv_yz");
-      hipLaunchKernelGGL((conv_yz_kernel<T, n, M>), dim3(P->Mh, np), dim3(256), 0, s, X,
+      hipLaunchKernelGGL((conv_yz_kernel<T, n, M>), dim3(P->Mh, cnt), dim3(256), 0, s, X,
                          static_cast<const T*>(P->conv_spec), Zb, P->Wp, I.b, I.Wa, I.e, I.d_alpha, p0);
     }
     {
       TimedScope ts(P, s, "conv_out");
-      hipLaunchKernelGGL((conv_out_kernel<T, n, M>), dim3(P->Wp, np), dim3(OutBatch<T, M>::NT), 0, s, Zb, cs,
-                         pl, g, p0);
+      hipLaunchKernelGGL((conv_out_kernel<T, n, M>), dim3(P->Wp, cnt), dim3(OutBatch<T, M>::NT), 0, s, Zb, cs,
+                         pl, g, G.desc, np, p0);
     }
   }
 }
 
 template <typename T>
-static bool dispatch_conv(const mlc_plan* P, const double* f, char* ws, hipStream_t s) {
-  const int n = P->info.n, M = P->info.M;
-#define CASE(nn, MM) if (n == nn && M == MM) { launch_conv<T, nn, MM>(P, f, ws, s); return true; }
+static bool dispatch_conv(const Group& G, hipStream_t s) {
+  const int n = G.plans[0]->info.n, M = G.plans[0]->info.M;
+#define CASE(nn, MM) if (n == nn && M == MM) { launch_conv<T, nn, MM>(G, s); return true; }
   if constexpr (sizeof(T) == 4) { MLC_CONV_SIZES_F32(CASE) }
   else { MLC_CONV_SIZES_F64(CASE) }
 #undef CASE
@@ -676,99 +788,141 @@ static bool dispatch_conv(const mlc_plan* P, const double* f, char* ws, hipStrea
 }
 
 template <typename T>
-static void launch_rest(const mlc_plan* P, const double* f, double* phi, char* ws, hipStream_t s) {
-  const mlc_plan_info& I = P->info;
-  const Stencil st = stencil_of(I.Q);
-  const T* cs = reinterpret_cast<const T*>(ws + P->o_cs);
-  T* pl = reinterpret_cast<T*>(ws + P->o_pl);
-  double* mom = reinterpret_cast<double*>(ws + P->o_mom);
-  double* F = reinterpret_cast<double*>(ws + P->o_F);
-  cplx<double>* tor = reinterpret_cast<cplx<double>*>(ws + P->o_tor);
-  double* phiH = reinterpret_cast<double*>(ws + P->o_phiH);
-  double* phiB = reinterpret_cast<double*>(ws + P->o_phiB);
-  double* dir = reinterpret_cast<double*>(ws + P->o_dir);
-  // coarse right-hand side
-  CoarseGeom cg{I.n, I.patches_per_axis, P->Kann, I.d_alpha, I.d_beta, I.e, I.Wc, I.S_lo, I.Ns, P->Wbc,
-                1.0 / (I.H * I.H)};
+static void launch_rest(const Group& G, hipStream_t s) {
+  const mlc_plan* P0 = G.plans[0];
+  const mlc_plan_info& I0 = P0->info;
+  const Layout& L = G.L;
+  const int np = int(G.plans.size());
+  const Stencil st = stencil_of(I0.Q);
+  const T* cs = reinterpret_cast<const T*>(G.ws + L.o_cs);
+  T* pl = reinterpret_cast<T*>(G.ws + L.o_pl);
+  const double* mom = reinterpret_cast<const double*>(G.ws + L.o_mom);
+  double* dir = reinterpret_cast<double*>(G.ws + L.o_dir);
+  auto F_of = [&](int k) { return reinterpret_cast<double*>(G.ws + L.o_F[k]); };
+  auto tor_of = [&](int k) { return reinterpret_cast<cplx<double>*>(G.ws + L.o_tor[k]); };
+  auto phiH_of = [&](int k) { return reinterpret_cast<double*>(G.ws + L.o_phiH[k]); };
+  auto phiB_of = [&](int k) { return reinterpret_cast<double*>(G.ws + L.o_phiB[k]); };
+  const int64_t csz = cube(I0.Wc), plsz = int64_t(3) * I0.nplanes_a * I0.Wa * I0.Wa;
+  // coarse right-hand side, per problem
   {
-    TimedScope ts(P, s, "coarse_rhs");
-    hipLaunchKernelGGL(coarse_rhs_kernel<T>, dim3(blocks_for(cube(I.Ns))), dim3(256), 0, s, cs, st, cg, F);
+    TimedScope ts(P0, s, "coarse_rhs");
+    for (int k = 0; k < np; ++k) {
+      const mlc_plan* P = G.plans[k];
+      const mlc_plan_info& I = P->info;
+      CoarseGeom cg{I.n, I.patches_per_axis, P->Kann, I.d_alpha, I.d_beta, I.e, I.Wc, I.S_lo, I.Ns, P->Wbc,
+                    1.0 / (I.H * I.H)};
+      hipLaunchKernelGGL(coarse_rhs_kernel<T>, dim3(blocks_for(cube(I.Ns))), dim3(256), 0, s,
+                         cs + L.patch0[k] * csz, st, cg, F_of(k));
+    }
   }
-  if (P->Kann > 0) {
-    TimedScope ts(P, s, "coarse_annulus");
-    const int q = I.n / NREF;
-    const MfmaGeom& g = P->mg_coarse;
-    const int nk = g.nk0 * g.nk1 * g.nk2;
-    hipLaunchKernelGGL(coarse_annulus_mfma_kernel, dim3((g.nr + 63) / 64, (nk + 63) / 64), dim3(256), 0, s, P->Tm,
-                       mom, g, q, I.S_lo, I.Ns, F);
+  if (P0->Kann > 0) {
+    TimedScope ts(P0, s, "coarse_annulus");
+    const int q = I0.n / NREF;
+    for (int k = 0; k < np; ++k) {
+      const mlc_plan* P = G.plans[k];
+      const mlc_plan_info& I = P->info;
+      const MfmaGeom& g = P->mg_coarse;
+      const int nk = g.nk0 * g.nk1 * g.nk2;
+      hipLaunchKernelGGL(coarse_annulus_mfma_kernel, dim3((g.nr + 63) / 64, (nk + 63) / 64), dim3(256), 0, s, P->Tm,
+                         mom + int64_t(L.patch0[k]) * I.K, g, q, I.S_lo, I.Ns, F_of(k));
+    }
   }
-  // coarse solve
-  const int Mc = I.M_coarse;
+  // coarse solves, the FFTs batched over problems of equal coarse torus
   {
-    TimedScope ts(P, s, "coarse_solve");
-    hipLaunchKernelGGL(coarse_fill_kernel, dim3(blocks_for(cube(Mc))), dim3(256), 0, s, F, tor, I.Ns, Mc);
-    fft3(tor, Mc, 1, s);
-    hipLaunchKernelGGL(mul_real_even_kernel, dim3(blocks_for(cube(Mc))), dim3(256), 0, s, tor, P->coarse_spec, Mc);
-    fft3(tor, Mc, -1, s);
-    hipLaunchKernelGGL(coarse_extract_kernel, dim3(blocks_for(cube(I.No))), dim3(256), 0, s, tor, phiH, Mc, I.S_lo,
-                       I.O_lo, I.No, I.H * I.H / (double(Mc) * Mc * Mc));
+    TimedScope ts(P0, s, "coarse_solve");
+    for (int k = 0; k < np; ++k) {
+      const mlc_plan_info& I = G.plans[k]->info;
+      hipLaunchKernelGGL(coarse_fill_kernel, dim3(blocks_for(cube(I.M_coarse))), dim3(256), 0, s, F_of(k), tor_of(k),
+                         I.Ns, I.M_coarse);
+    }
+    std::vector<int> done(np, 0);
+    for (int k = 0; k < np; ++k) {
+      if (done[k]) continue;
+      const int Mc = G.plans[k]->info.M_coarse;
+      int nb = 0;
+      for (int j = k; j < np; ++j)
+        if (!done[j] && G.plans[j]->info.M_coarse == Mc) { done[j] = 1; ++nb; }
+      fft3_batch(tor_of(k), Mc, 1, nb, s);
+      hipLaunchKernelGGL(mul_real_even_kernel, dim3(blocks_for(cube(Mc)), nb), dim3(256), 0, s, tor_of(k),
+                         G.plans[k]->coarse_spec, Mc);
+      fft3_batch(tor_of(k), Mc, -1, nb, s);
+    }
+    for (int k = 0; k < np; ++k) {
+      const mlc_plan_info& I = G.plans[k]->info;
+      const int Mc = I.M_coarse;
+      hipLaunchKernelGGL(coarse_extract_kernel, dim3(blocks_for(cube(I.No))), dim3(256), 0, s, tor_of(k), phiH_of(k),
+                         Mc, I.S_lo, I.O_lo, I.No, I.H * I.H / (double(Mc) * Mc * Mc));
+    }
   }
-  // local plane corrections delta_i = phi_i - I(phi_i)
+  // local plane corrections delta_i = phi_i - I(phi_i), all patches
   {
-    TimedScope ts(P, s, "plane_delta");
-    PlaneGeom pg{I.n, I.e, I.d_alpha, I.Wa, I.Wc, P->P0, I.nplanes_a, I.b};
-    hipLaunchKernelGGL(plane_delta_kernel<T>, dim3(3 * I.nplanes_a, I.npatch), dim3(256), 0, s, pl, cs, pg,
-                       P->lagw);
+    TimedScope ts(P0, s, "plane_delta");
+    PlaneGeom pg{I0.n, I0.e, I0.d_alpha, I0.Wa, I0.Wc, P0->P0, I0.nplanes_a, I0.b};
+    for (int p0 = 0; p0 < L.total; p0 += kMaxGridY)
+      hipLaunchKernelGGL(plane_delta_kernel<T>, dim3(3 * I0.nplanes_a, std::min(kMaxGridY, L.total - p0)), dim3(256),
+                         0, s, pl, cs, pg, P0->lagw, p0);
   }
-  // boundary values on the skeleton (+ phi there)
-  {
-    SkelGeom sg{I.N, I.n, I.patches_per_axis, P->Kann, I.d_alpha, I.d_beta, I.b, I.Wa, P->P0, I.nplanes_a, P->Wb,
-                P->P0b, P->nplb, I.O_lo, I.No, I.h * I.h / 12.0};
-    int64_t cnt = int64_t(3) * (I.N / I.n + 1) * (I.N + 1) * (I.N + 1);
-    if (P->Kann > 0) {
-      TimedScope ts(P, s, "skeleton_annulus");
+  // boundary values on the skeleton (+ phi there), per problem
+  if (P0->Kann > 0) {
+    TimedScope ts(P0, s, "skeleton_annulus");
+    for (int k = 0; k < np; ++k) {
+      const mlc_plan* P = G.plans[k];
+      const mlc_plan_info& I = P->info;
       const MfmaGeom& g = P->mg_skel;
       const int nk = g.nk0 * g.nk1 * g.nk2;
       hipLaunchKernelGGL(skeleton_annulus_mfma_kernel, dim3((g.nr + 63) / 64, (nk + 63) / 64, 3), dim3(256), 0, s,
-                         P->Am, mom, g, I.n, I.N, phiB);
+                         P->Am, mom + int64_t(L.patch0[k]) * I.K, g, I.n, I.N, phiB_of(k));
     }
-    TimedScope ts(P, s, "skeleton");
-    hipLaunchKernelGGL(skeleton_kernel<T>, dim3(blocks_for(cnt)), dim3(256), 0, s, phiH, pl, f, sg, P->lagw,
-                       P->Kann > 0 ? 1 : 0, phiB, phi);
   }
-  // Dirichlet solves + Mehrstellen correction on the patch interiors
   {
-    const int m = I.n - 1;
-    TimedScope ts(P, s, "dirichlet");
-    DirGeom dg{I.N, I.n, I.patches_per_axis, I.h * I.h, I.h * I.h / 12.0, 2.0 / I.n, st};
-    dim3 gd((I.npatch * m + 3) / 4);
-    hipLaunchKernelGGL(dirichlet_mfma_kernel<0>, gd, dim3(256), 0, s, f, phiB, dir, phi, dg);
-    hipLaunchKernelGGL(dirichlet_mfma_kernel<1>, gd, dim3(256), 0, s, f, phiB, dir, phi, dg);
-    hipLaunchKernelGGL(dirichlet_mfma_kernel<2>, gd, dim3(256), 0, s, f, phiB, dir, phi, dg);
-    hipLaunchKernelGGL(dirichlet_mfma_kernel<3>, gd, dim3(256), 0, s, f, phiB, dir, phi, dg);
-    hipLaunchKernelGGL(dirichlet_mfma_kernel<4>, gd, dim3(256), 0, s, f, phiB, dir, phi, dg);
+    TimedScope ts(P0, s, "skeleton");
+    for (int k = 0; k < np; ++k) {
+      const mlc_plan* P = G.plans[k];
+      const mlc_plan_info& I = P->info;
+      SkelGeom sg{I.N, I.n, I.patches_per_axis, P->Kann, I.d_alpha, I.d_beta, I.b, I.Wa, P->P0, I.nplanes_a, P->Wb,
+                  P->P0b, P->nplb, I.O_lo, I.No, I.h * I.h / 12.0};
+      int64_t cnt = int64_t(3) * (I.N / I.n + 1) * (I.N + 1) * (I.N + 1);
+      hipLaunchKernelGGL(skeleton_kernel<T>, dim3(blocks_for(cnt)), dim3(256), 0, s, phiH_of(k),
+                         pl + L.patch0[k] * plsz, G.f[k], sg, P->lagw, P->Kann > 0 ? 1 : 0, phiB_of(k), G.phi[k]);
+    }
+  }
+  // Dirichlet solves + Mehrstellen correction on the patch interiors, all patches
+  {
+    const int m = I0.n - 1;
+    TimedScope ts(P0, s, "dirichlet");
+    DirGeom dg{I0.n, L.total, 2.0 / I0.n, st};
+    dim3 gd(unsigned((int64_t(L.total) * m + 3) / 4));
+    hipLaunchKernelGGL(dirichlet_mfma_kernel<0>, gd, dim3(256), 0, s, G.desc, np, dir, dg);
+    hipLaunchKernelGGL(dirichlet_mfma_kernel<1>, gd, dim3(256), 0, s, G.desc, np, dir, dg);
+    hipLaunchKernelGGL(dirichlet_mfma_kernel<2>, gd, dim3(256), 0, s, G.desc, np, dir, dg);
+    hipLaunchKernelGGL(dirichlet_mfma_kernel<3>, gd, dim3(256), 0, s, G.desc, np, dir, dg);
+    hipLaunchKernelGGL(dirichlet_mfma_kernel<4>, gd, dim3(256), 0, s, G.desc, np, dir, dg);
   }
 }
 
-static mlc_status enqueue_solve(mlc_plan* P, const double* f, double* phi, char* ws, hipStream_t s) {
-  const mlc_plan_info& I = P->info;
-  double* mom = reinterpret_cast<double*>(ws + P->o_mom);
+static mlc_status enqueue_group(const Group& G, hipStream_t s) {
+  const mlc_plan* P0 = G.plans[0];
+  const mlc_plan_info& I0 = P0->info;
+  const int np = int(G.plans.size());
+  upload_descs(G, s);
   {
-    TimedScope ts(P, s, "moments");
-    hipLaunchKernelGGL(moments_kernel, dim3(I.npatch), dim3(256), 0, s, f, I.N, I.n, I.patches_per_axis, P->modes,
-                       std::pow(I.n * I.h / 2.0, 1.5), mom);
+    TimedScope ts(P0, s, "moments");
+    double* mom = reinterpret_cast<double*>(G.ws + G.L.o_mom);
+    for (int p0 = 0; p0 < G.L.total; p0 += kMaxGridY)
+      hipLaunchKernelGGL(moments_kernel, dim3(std::min(kMaxGridY, G.L.total - p0)), dim3(256), 0, s, G.desc, np,
+                         I0.n, P0->modes, mom, p0);
   }
   bool ok;
-  if (I.conv_precision == MLC_CONV_FP32) {
-    ok = dispatch_conv<float>(P, f, ws, s);
-    if (ok) launch_rest<float>(P, f, phi, ws, s);
+  if (I0.conv_precision == MLC_CONV_FP32) {
+    ok = dispatch_conv<float>(G, s);
+    if (ok) launch_rest<float>(G, s);
   } else {
-    ok = dispatch_conv<double>(P, f, ws, s);
-    if (ok) launch_rest<double>(P, f, phi, ws, s);
+    ok = dispatch_conv<double>(G, s);
+    if (ok) launch_rest<double>(G, s);
   }
-  if (!ok) return fail(P->ctx, MLC_ERR_UNSUPPORTED, "local FFT size not built");
+  if (!ok) return fail(P0->ctx, MLC_ERR_UNSUPPORTED, "local FFT size not built");
   hipError_t e = hipGetLastError();
-  if (e != hipSuccess) return fail(P->ctx, MLC_ERR_DEVICE, std::string("launch: ") + hipGetErrorString(e));
+  if (e != hipSuccess) return fail(P0->ctx, MLC_ERR_DEVICE, std::string("launch: ") + hipGetErrorString(e));
   return MLC_OK;
 }
 
@@ -779,35 +933,74 @@ extern "C" mlc_status mlc_solve(mlc_plan* plan, const double* f, double* phi, vo
   if (reinterpret_cast<uintptr_t>(workspace) % 256)
     return fail(plan->ctx, MLC_ERR_INVALID_ARG, "workspace must be 256-byte aligned");
   HIP_TRY(plan->ctx, hipSetDevice(plan->ctx->device));
-  return enqueue_solve(plan, f, phi, static_cast<char*>(workspace), static_cast<hipStream_t>(stream));
+  Group G;
+  G.plans = {plan};
+  G.f = {f};
+  G.phi = {phi};
+  G.L = layout_of(G.plans);
+  G.ws = static_cast<char*>(workspace);
+  G.desc = reinterpret_cast<ProbDesc*>(G.ws + G.L.o_desc);
+  return enqueue_group(G, static_cast<hipStream_t>(stream));
+}
+
+// Split a batch into class groups (first-appearance order) and lay them out
+// one after another in the workspace.
+static mlc_status make_groups(int32_t count, mlc_plan* const* plans, std::vector<Group>* out, size_t* bytes) {
+  if (count <= 0 || !plans || !bytes) return fail(nullptr, MLC_ERR_INVALID_ARG, "bad batch arguments");
+  for (int k = 0; k < count; ++k)
+    if (!plans[k]) return fail(nullptr, MLC_ERR_INVALID_ARG, "null plan in batch");
+  mlc_context* ctx = plans[0]->ctx;
+  for (int k = 1; k < count; ++k)
+    if (plans[k]->ctx != ctx) return fail(ctx, MLC_ERR_INVALID_ARG, "plans of one batch must share a context");
+  std::vector<Group> groups;
+  for (int k = 0; k < count; ++k) {
+    size_t gi = 0;
+    while (gi < groups.size() && !same_class(groups[gi].plans[0], plans[k])) ++gi;
+    if (gi == groups.size()) groups.emplace_back();
+    groups[gi].plans.push_back(plans[k]);
+    groups[gi].pos.push_back(k);
+  }
+  size_t off = 0;
+  for (auto& G : groups) {
+    G.L = layout_of(G.plans);
+    G.off = off;
+    off = align_up(off + G.L.bytes);
+  }
+  *bytes = off;
+  if (out) *out = std::move(groups);
+  return MLC_OK;
 }
 
 extern "C" mlc_status mlc_batch_workspace_bytes(int32_t count, mlc_plan* const* plans, size_t* bytes) {
-  if (count <= 0 || !plans || !bytes) return fail(nullptr, MLC_ERR_INVALID_ARG, "bad batch arguments");
-  size_t tot = 0;
-  for (int k = 0; k < count; ++k) {
-    if (!plans[k]) return fail(nullptr, MLC_ERR_INVALID_ARG, "null plan in batch");
-    tot = align_up(tot + plans[k]->ws_total);
-  }
-  *bytes = tot;
-  return MLC_OK;
+  return make_groups(count, plans, nullptr, bytes);
 }
 
 extern "C" mlc_status mlc_solve_batched(int32_t count, mlc_plan* const* plans, const double* const* f,
                                         double* const* phi, void* workspace, size_t ws_bytes, void* stream) {
   size_t need = 0;
-  mlc_status st = mlc_batch_workspace_bytes(count, plans, &need);
+  std::vector<Group> groups;
+  mlc_status st = make_groups(count, plans, &groups, &need);
   if (st != MLC_OK) return st;
-  if (!f || !phi || !workspace) return fail(plans[0]->ctx, MLC_ERR_INVALID_ARG, "null argument");
-  if (ws_bytes < need) return fail(plans[0]->ctx, MLC_ERR_INVALID_ARG, "workspace too small");
+  mlc_context* ctx = plans[0]->ctx;
+  if (!f || !phi || !workspace) return fail(ctx, MLC_ERR_INVALID_ARG, "null argument");
+  if (ws_bytes < need) return fail(ctx, MLC_ERR_INVALID_ARG, "workspace too small");
+  if (reinterpret_cast<uintptr_t>(workspace) % 256)
+    return fail(ctx, MLC_ERR_INVALID_ARG, "workspace must be 256-byte aligned");
   for (int k = 0; k < count; ++k)
-    if (!f[k] || !phi[k]) return fail(plans[0]->ctx, MLC_ERR_INVALID_ARG, "null array in batch");
-  char* ws = static_cast<char*>(workspace);
-  size_t off = 0;
-  for (int k = 0; k < count; ++k) {
-    st = mlc_solve(plans[k], f[k], phi[k], ws + off, plans[k]->ws_total, stream);
+    if (!f[k] || !phi[k]) return fail(ctx, MLC_ERR_INVALID_ARG, "null array in batch");
+  HIP_TRY(ctx, hipSetDevice(ctx->device));
+  char* base = static_cast<char*>(workspace);
+  for (auto& G : groups) {
+    for (int k : G.pos) {
+      G.f.push_back(f[k]);
+      G.phi.push_back(phi[k]);
+    }
+    G.ws = base + G.off;
+    G.desc = reinterpret_cast<ProbDesc*>(G.ws + G.L.o_desc);
+  }
+  for (auto& G : groups) {
+    st = enqueue_group(G, static_cast<hipStream_t>(stream));
     if (st != MLC_OK) return st;
-    off = align_up(off + plans[k]->ws_total);
   }
   return MLC_OK;
 }

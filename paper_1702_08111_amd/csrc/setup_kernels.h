@@ -104,12 +104,14 @@ __global__ void dgf_restrict_kernel(const double* u, double* table, int L, int Z
 
 // ------------------------------------------------- generic axis FFT ----
 // Complex M^3 array, transform along `axis`.  NL lines per block; lines
-// adjacent along the fastest other axis.
+// adjacent along the fastest other axis; blockIdx.z: array of a batch of
+// consecutive M^3 arrays.
 template <typename T, int M, int NL, int DIR>
 __global__ void __launch_bounds__(256) fft_axis_kernel(cplx<T>* data, int axis) {
   __shared__ cplx<T> buf[NL * M];
   __shared__ cplx<T> tw[M];
   fill_twiddles(tw, M);
+  data += int64_t(blockIdx.z) * M * M * M;
   const int64_t es = axis == 2 ? 1 : (axis == 1 ? M : int64_t(M) * M);
   const int64_t vs = axis == 2 ? M : 1;
   const int64_t us = axis == 0 ? M : int64_t(M) * M;
@@ -190,9 +192,11 @@ __global__ void fill_mode_source_kernel(cplx<double>* out, int M, int n, int p0,
 
 // Multiply a complex M^3 array by a real-even spectrum stored as its octant
 // [Mh]^3 (layout k0, k1, k2).
+// blockIdx.y: array of a batch of consecutive M^3 arrays.
 __global__ void mul_real_even_kernel(cplx<double>* data, const double* oct, int M) {
   int64_t idx = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
   if (idx >= cube(M)) return;
+  data += int64_t(blockIdx.y) * cube(M);
   const int Mh = M / 2 + 1;
   int k2 = int(idx % M), k1 = int((idx / M) % M), k0 = int(idx / (int64_t(M) * M));
   k0 = min(k0, M - k0); k1 = min(k1, M - k1); k2 = min(k2, M - k2);

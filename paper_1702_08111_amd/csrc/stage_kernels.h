@@ -20,14 +20,18 @@ __device__ inline double boole_w(int j, int n) {
   return (r == 0 ? 14.0 : (r == 2 ? 12.0 : 32.0)) * base;
 }
 
-__global__ void __launch_bounds__(256) moments_kernel(const double* __restrict__ f, int N, int n, int ppa,
-                                                      ModeList modes, double R15, double* __restrict__ out) {
+__global__ void __launch_bounds__(256) moments_kernel(const ProbDesc* __restrict__ pd, int nprob, int n,
+                                                      ModeList modes, double* __restrict__ out, int p0) {
   __shared__ double B[4][SMAXN];
   __shared__ double mu1[4];
   __shared__ double red[256];
   const int S = n + 1;
-  const int p = blockIdx.x;
-  const int i0 = p / (ppa * ppa), i1 = (p / ppa) % ppa, i2 = p % ppa;
+  const int p = p0 + blockIdx.x;
+  const ProbDesc& D = pd[find_problem(pd, nprob, p)];
+  const double* f = D.f;
+  const int N = D.N, ppa = D.ppa, pl = p - D.patch0;
+  const double R15 = D.R15;
+  const int i0 = pl / (ppa * ppa), i1 = (pl / ppa) % ppa, i2 = pl % ppa;
   for (int t = threadIdx.x; t < 4 * S; t += blockDim.x) {
     int a = t / S, j = t % S;
     double tt = (j - 0.5 * n) / (0.5 * n);
@@ -165,12 +169,12 @@ struct PlaneGeom { int n, e, da, Wa, Wc, P0, npl, b; };
 // slower one.
 template <typename T>
 __global__ void __launch_bounds__(256) plane_delta_kernel(T* __restrict__ planes, const T* __restrict__ cs,
-                                                          PlaneGeom g, LagW lw) {
+                                                          PlaneGeom g, LagW lw, int p0) {
   __shared__ double C[WCMAX * WCMAX];
   __shared__ double R[WCMAX * WAMAX];
   __shared__ double W[4][10];
   if (threadIdx.x < 40) W[threadIdx.x / 10][threadIdx.x % 10] = lw.w[threadIdx.x / 10][threadIdx.x % 10];
-  const int pl = blockIdx.x, p = blockIdx.y;
+  const int pl = blockIdx.x, p = p0 + blockIdx.y;
   const int d = pl / g.npl, j = pl % g.npl;
   const int n = g.n, Wc = g.Wc, Wa = g.Wa, b = g.b, o = g.e / NREF;
   const int cd = (g.P0 + j * n + g.e) / NREF;
@@ -495,16 +499,14 @@ __global__ void __launch_bounds__(256) skeleton_kernel(const double* __restrict_
 //   3: inverse along axis 1
 //   4: inverse along axis 2, then phi = u + C2 h^2 f on the patch interior
 struct DirGeom {
-  int N, n, ppa;
-  double h2, c2h2, scale;   // scale: (2/n) per inverse pass
+  int n, npatch;
+  double scale;   // 2/n per inverse pass
   Stencil st;
 };
 
 template <int PASS>
-__global__ void __launch_bounds__(256) dirichlet_mfma_kernel(const double* __restrict__ f,
-                                                             const double* __restrict__ phiB,
-                                                             double* __restrict__ work, double* __restrict__ phi,
-                                                             DirGeom g) {
+__global__ void __launch_bounds__(256) dirichlet_mfma_kernel(const ProbDesc* __restrict__ pd, int nprob,
+                                                             double* __restrict__ work, DirGeom g) {
   __shared__ double Sm[32 * 33];
   __shared__ double Ls[4][32 * 33];
   const int m = g.n - 1;
@@ -521,7 +523,13 @@ __global__ void __launch_bounds__(256) dirichlet_mfma_kernel(const double* __res
   }
   const int slab = blockIdx.x * 4 + wave;     // over patches x m
   const int p = slab / m, u = slab % m;
-  const bool live = p < g.ppa * g.ppa * g.ppa;
+  const bool live = p < g.npatch;
+  const ProbDesc& D = pd[find_problem(pd, nprob, live ? p : 0)];
+  const double* f = D.f;
+  const double* phiB = D.phiB;
+  double* phi = D.phi;
+  const int ppa = D.ppa, pl = p - D.patch0;
+  const double h2 = D.h2;
   const int axis = (PASS == 0 || PASS == 4) ? 2 : (PASS == 1 || PASS == 3) ? 1 : 0;
   // element (j along the transform axis, w along the faster other axis) of slab u
   const int64_t M3 = int64_t(m) * m * m;
@@ -531,8 +539,8 @@ __global__ void __launch_bounds__(256) dirichlet_mfma_kernel(const double* __res
     return int64_t(j) * m * m + int64_t(u) * m + w;
   };
   double* wp = work + int64_t(p) * M3;
-  const int i0 = p / (g.ppa * g.ppa), i1 = (p / g.ppa) % g.ppa, i2 = p % g.ppa;
-  const int64_t Np = g.N + 1;
+  const int i0 = pl / (ppa * ppa), i1 = (pl / ppa) % ppa, i2 = pl % ppa;
+  const int64_t Np = D.N + 1;
   const int64_t pbase = (int64_t(g.n) * i0) * Np * Np + int64_t(g.n) * i1 * Np + int64_t(g.n) * i2;
   double* L = Ls[wave];
   // load the slab (rows j, columns w), zero-padded to 32 x 32
@@ -543,7 +551,7 @@ __global__ void __launch_bounds__(256) dirichlet_mfma_kernel(const double* __res
       if constexpr (PASS == 0) {
         // node (l0, l1, l2) = (u, w, j) + 1 inside the patch
         int l0 = u + 1, l1 = w + 1, l2 = j + 1;
-        v = g.h2 * f[pbase + (l0 * Np + l1) * Np + l2];
+        v = h2 * f[pbase + (l0 * Np + l1) * Np + l2];
         if (l0 == 1 || l0 == g.n - 1 || l1 == 1 || l1 == g.n - 1 || l2 == 1 || l2 == g.n - 1) {
           for (int s0 = -1; s0 <= 1; ++s0)
             for (int s1 = -1; s1 <= 1; ++s1)
@@ -618,7 +626,7 @@ __global__ void __launch_bounds__(256) dirichlet_mfma_kernel(const double* __res
     if constexpr (PASS == 4) {
       int l0 = u + 1, l1 = w + 1, l2 = k + 1;
       int64_t node = pbase + (l0 * Np + l1) * Np + l2;
-      phi[node] = v + g.c2h2 * f[node];
+      phi[node] = v + (h2 / 12.0) * f[node];
     } else {
       wp[off(k, w)] = v;
     }
