@@ -37,6 +37,9 @@ def parse():
                     help="also run a plain device copy of known size (for HBM counter scaling)")
     ap.add_argument("--batch-steps", type=int, default=5,
                     help="timed steps of the 64-problem uneven batch (0: skip)")
+    ap.add_argument("--serve-requests", type=int, default=1000,
+                    help="measured requests of the serving loop after 50 warm-ups (0: skip)")
+    ap.add_argument("--serve-load", type=float, default=0.7, help="arrival rate / saturation rate")
     return ap.parse_args()
 
 
@@ -173,6 +176,92 @@ def batch_bench(ctx, steps, dev):
     return out
 
 
+def serving_bench(ctx, count, load, dev, warm=50, sat_requests=120, pool=4, ring=32):
+    """The serving loop: requests with N ~ U{64,128,192,256}, n ~ U{16,32},
+    Q ~ U{4,6}, 1-4 seeded bumps, float32 convolutions.  First the
+    saturation rate (a burst of requests, drained); then Poisson arrivals at
+    `load` x that rate, warm-ups then `count` measured requests.  Each (N)
+    keeps `pool` charges (those of its first requests) reused cyclically and
+    a ring of output arrays; plans are built up front (resident tables)."""
+    import torch
+    from paper_1702_08111_amd import mlc as gm
+    reqs = mi.serving_requests(warm + count + sat_requests, 1.0, seed=105)
+    charges, outs = {}, {}
+    for _, N, n, Q, b in reqs:
+        lst = charges.setdefault(N, [])
+        if len(lst) < pool:
+            lst.append(torch.from_numpy(mi.bump_charge(N, b)).to(dev))
+    for N in charges:
+        outs[N] = [torch.empty((N + 1,) * 3, dtype=torch.float64, device=dev) for _ in range(ring)]
+    torch.cuda.synchronize()
+    srv = gm.Server(ctx, budget_bytes=48 << 30, streams=3, max_batch=8)
+    probs = {}
+    for _, N, n, Q, _ in reqs:
+        if (N, n, Q) not in probs:
+            probs[(N, n, Q)] = gm.problem(N, n, 3.0, 6.0, 4, Q, conv="fp32")
+            srv.prepare(probs[(N, n, Q)])
+    use = {N: 0 for N in charges}
+
+    def submit(N, n, Q):
+        k = use[N]
+        use[N] += 1
+        st, t = srv.submit(probs[(N, n, Q)], charges[N][k % pool], outs[N][k % ring])
+        assert st == gm.MLC_OK, st
+        return t
+
+    # saturation: a burst, drained
+    burst = reqs[warm + count:]
+    t0 = time.perf_counter()
+    tickets = [submit(N, n, Q) for _, N, n, Q, _ in burst]
+    srv.drain()
+    sat_wall = time.perf_counter() - t0
+    for t in tickets:
+        srv.poll(t)
+    sat_rate = len(burst) / sat_wall
+    sat_points = sum(N ** 3 for _, N, _, _, _ in burst) / sat_wall
+    # open loop at load x saturation: arrival times rescaled from the unit-rate stream
+    rate = load * sat_rate
+    stream = reqs[:warm + count]
+    pending = {}
+    done = []
+    t0 = time.perf_counter()
+    k = 0
+    while k < len(stream) or pending:
+        now = time.perf_counter() - t0
+        while k < len(stream) and stream[k][0] / rate <= now:
+            _, N, n, Q, _ = stream[k]
+            pending[submit(N, n, Q)] = (k, N)
+            k += 1
+        for t in list(pending):
+            r = srv.poll(t)
+            if r is not None:
+                kk, N = pending.pop(t)
+                done.append((kk, N, r, time.perf_counter() - t0))
+        if k < len(stream):
+            wait = stream[k][0] / rate - (time.perf_counter() - t0)
+            if wait > 2e-4:
+                time.sleep(min(wait, 1e-3))
+    srv.close()
+    meas = [d for d in done if d[0] >= warm]
+    lat = np.array([d[2]["total_ms"] for d in meas])
+    qms = np.array([d[2]["queue_ms"] for d in meas])
+    bad = sum(1 for d in done if d[2]["status"] != 0)
+    first = min(stream[d[0]][0] / rate for d in meas)
+    last = max(d[3] for d in meas)
+    points = sum(d[1] ** 3 for d in meas)
+    del charges, outs
+    torch.cuda.empty_cache()
+    return {"value": points / (last - first), "unit": "grid points/s",
+            "p50_ms": float(np.percentile(lat, 50)), "p99_ms": float(np.percentile(lat, 99)),
+            "queue_p50_ms": float(np.percentile(qms, 50)), "queue_p99_ms": float(np.percentile(qms, 99)),
+            "mean_batch": float(np.mean([d[2]["batch_size"] for d in meas])),
+            "requests": len(meas), "warmup": warm, "failed": bad,
+            "arrival_rate_rps": rate, "load": load, "saturation_rps": sat_rate,
+            "saturation_points_per_s": sat_points,
+            "config": "Poisson arrivals; N ~ U{64,128,192,256}, n ~ U{16,32}, Q ~ U{4,6}, 1-4 bumps (seed 105), "
+                      "P=4, alpha=3, beta=6, fp32 convolutions; 3 streams, batches of <= 8, 48 GB arena"}
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -252,6 +341,7 @@ def main():
         torch.cuda.synchronize()
 
     batch = batch_bench(ctx, args.batch_steps, dev) if args.batch_steps > 0 else None
+    serving = serving_bench(ctx, args.serve_requests, args.serve_load, dev) if args.serve_requests > 0 else None
 
     cpu = None
     if not args.no_cpu_baseline:
@@ -286,6 +376,7 @@ def main():
         "roofline": roof,
         "cpu_baseline": cpu,
         "batch": batch,
+        "serving": serving,
     }
     print(json.dumps(line), flush=True)
 

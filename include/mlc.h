@@ -113,6 +113,10 @@ mlc_status mlc_plan_get_info(const mlc_plan* plan, mlc_plan_info* out);
 /* Bytes of device workspace a solve with this plan needs. */
 mlc_status mlc_plan_workspace_bytes(const mlc_plan* plan, size_t* bytes);
 
+/* The same figure computed from the problem alone, on the host (no device
+ * is touched; equal to mlc_plan_workspace_bytes of the problem's plan). */
+mlc_status mlc_problem_workspace_bytes(const mlc_problem* prob, size_t* bytes);
+
 /* One two-level MLC solve (sec. 4.1): f (device, (N+1)^3 float64, read
  * only) -> phi (device, (N+1)^3 float64, fully overwritten).  workspace is
  * device memory of at least mlc_plan_workspace_bytes bytes, owned by the
@@ -169,6 +173,63 @@ typedef struct {
 } mlc_kernel_time;
 mlc_status mlc_plan_set_timing(mlc_plan* plan, int32_t enable);
 mlc_status mlc_plan_timing(mlc_plan* plan, mlc_kernel_time* out, int32_t max, int32_t* count);
+
+/* ------------------------------------------------------------- serving
+ * A request loop over one context.  mlc_server_submit queues a solve
+ * (problem, f, phi as for mlc_solve) and returns at once; the server's own
+ * host thread builds plans on first use (kept resident: DGF tables, spectra
+ * and far-field tables per distinct problem), admits queued requests in
+ * arrival order as a stream slot and workspace memory free up, and launches
+ * queued requests whose patch work is identical (same n, radii, P, Q, b,
+ * torus, precision; any N) together through the batched solve.  Launches run
+ * on several streams, so requests admitted while others run overlap with
+ * them on the device.  Workspaces come from one device arena of
+ * workspace_budget_bytes allocated at creation; a request whose workspace
+ * alone exceeds it is refused at submit.
+ *
+ * f and phi are device arrays the caller owns and keeps alive (f unchanged)
+ * until the ticket reports done.  A request's result does not depend on
+ * which other requests share its launch (the per-problem arithmetic is the
+ * same).  Server calls may come from one caller thread at a time; while a
+ * server runs, its context may still be used from that thread (plan builds
+ * are serialised inside the context). */
+typedef struct {
+  size_t workspace_budget_bytes; /* device arena for solve workspaces; 0 -> 16 GiB          */
+  int32_t streams;               /* concurrent launches (HIP streams, default priority);
+                                    0 -> 2, at most 8                                        */
+  int32_t max_batch;             /* most requests per launch; 0 -> 16                         */
+  int32_t max_queue;             /* unfinished requests allowed; 0 -> 4096                    */
+} mlc_server_config;
+
+typedef struct {
+  int32_t status;      /* mlc_status of the request's solve                              */
+  int32_t batch_size;  /* requests in the launch that ran it                             */
+  double queue_ms;     /* submit -> launch enqueued (includes a first-use plan build)     */
+  double device_ms;    /* the launch's device time, from HIP events around it            */
+  double total_ms;     /* submit -> completion observed by the server thread             */
+} mlc_timing;
+
+typedef struct mlc_server mlc_server;
+
+/* Start a server on ctx (allocates the arena and streams, starts its thread). */
+mlc_status mlc_server_create(mlc_context* ctx, const mlc_server_config* cfg, mlc_server** out);
+/* Build the problem's plan now (resident tables) instead of at first use.
+ * Synchronises the device. */
+mlc_status mlc_server_prepare(mlc_server* srv, const mlc_problem* prob);
+/* Queue one solve.  MLC_ERR_INVALID_ARG / MLC_ERR_UNSUPPORTED for a bad
+ * problem, MLC_ERR_OUT_OF_MEMORY if its workspace exceeds the arena,
+ * MLC_ERR_BUSY if max_queue requests are unfinished.  *ticket is nonzero. */
+mlc_status mlc_server_submit(mlc_server* srv, const mlc_problem* prob, const double* f, double* phi,
+                             uint64_t* ticket);
+/* Status of a ticket: MLC_ERR_NOT_READY (*done = 0) while queued or
+ * running; once finished, *done = 1, *t (if not NULL) is filled, the ticket
+ * is released (polling it again is MLC_ERR_INVALID_ARG) and the return value
+ * is the solve's own status. */
+mlc_status mlc_server_poll(mlc_server* srv, uint64_t ticket, int32_t* done, mlc_timing* t);
+/* Block until every submitted request has finished. */
+mlc_status mlc_server_drain(mlc_server* srv);
+/* Drain, stop the thread, free plans, arena and streams. */
+mlc_status mlc_server_destroy(mlc_server* srv);
 
 #ifdef __cplusplus
 }

@@ -9,7 +9,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 LIB = os.path.join(HERE, "libmlc.so")
-SOURCES = [os.path.join(HERE, "csrc", "libmlc.hip")]
+SOURCES = [os.path.join(HERE, "csrc", "libmlc.hip"), os.path.join(HERE, "csrc", "server.hip")]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [

@@ -27,7 +27,9 @@ using namespace mlc;
 struct mlc_context {
   int device = 0;
   size_t budget = 0;
+  std::mutex err_mu;    // guards last_error
   std::string last_error;
+  std::mutex build_mu;  // serialises plan and DGF builds (a server thread may build too)
   std::map<std::pair<int, int>, double*> dgf;   // (Q, Z) -> (2Z+1)^3 table
 };
 
@@ -89,10 +91,17 @@ struct TimedScope {
 static thread_local std::string g_error;   // errors before a context exists
 
 static mlc_status fail(mlc_context* ctx, mlc_status s, const std::string& msg) {
-  if (ctx) ctx->last_error = msg;
+  if (ctx) {
+    std::lock_guard<std::mutex> lk(ctx->err_mu);
+    ctx->last_error = msg;
+  }
   g_error = msg;
   return s;
 }
+
+// for the serving loop (server.hip)
+void mlc_set_error(mlc_context* ctx, const std::string& msg) { fail(ctx, MLC_OK, msg); }
+int mlc_context_device(const mlc_context* ctx) { return ctx->device; }
 
 #define HIP_TRY(ctx, expr)                                                                       \
   do {                                                                                          \
@@ -241,8 +250,12 @@ extern "C" mlc_status mlc_problem_info(const mlc_problem* prob, mlc_plan_info* o
 
 extern "C" mlc_status mlc_last_error(mlc_context* ctx, char* buf, size_t len) {
   if (!buf || len == 0) return MLC_ERR_INVALID_ARG;
-  const std::string& m = ctx ? ctx->last_error : g_error;
-  std::snprintf(buf, len, "%s", m.c_str());
+  if (ctx) {
+    std::lock_guard<std::mutex> lk(ctx->err_mu);
+    std::snprintf(buf, len, "%s", ctx->last_error.c_str());
+  } else {
+    std::snprintf(buf, len, "%s", g_error.c_str());
+  }
   return MLC_OK;
 }
 
@@ -342,6 +355,7 @@ extern "C" mlc_status mlc_dgf_table(mlc_context* ctx, int32_t Q, int32_t Z, cons
   if (Q != 4 && Q != 6) return fail(ctx, MLC_ERR_UNSUPPORTED, "Q must be 4 or 6");
   if (Z != 32 && Z != 64 && Z != 128) return fail(ctx, MLC_ERR_UNSUPPORTED, "Z must be 32, 64 or 128");
   double* t = nullptr;
+  std::lock_guard<std::mutex> lk(ctx->build_mu);
   mlc_status s = get_dgf(ctx, Q, Z, &t);
   if (s != MLC_OK) return s;
   *table = t;
@@ -489,25 +503,25 @@ struct Layout {
 
 static const int kMaxGridY = 65535;
 
-static Layout layout_of(const std::vector<mlc_plan*>& g) {
+static Layout layout_of(const std::vector<const mlc_plan_info*>& g) {
   Layout L;
-  const mlc_plan* P = g[0];
-  const mlc_plan_info& I = P->info;
+  const mlc_plan_info& I = *g[0];
   const int np = int(g.size());
   const size_t tsz = I.conv_precision == MLC_CONV_FP32 ? 4 : 8, csz = 2 * tsz;
+  const int S = I.n + 1, Mh = I.M / 2 + 1, Wp = I.Wa + 2 * I.b;
   for (int k = 0; k < np; ++k) {
     L.patch0.push_back(L.total);
-    L.total += g[k]->info.npatch;
+    L.total += g[k]->npatch;
   }
   const size_t T = size_t(L.total);
   size_t o = 0;
   auto take = [&](size_t bytes) { size_t at = o; o = align_up(o + bytes); return at; };
   L.o_desc = take(sizeof(ProbDesc) * np);
   L.o_mom = take(sizeof(double) * T * I.K);
-  L.o_X = take(csz * T * P->Mh * P->S * P->S);
+  L.o_X = take(csz * T * Mh * S * S);
   // chunk so that one chunk's z-transformed spectra stay at most ~2 GB
   // (MLC_CONV_CHUNK overrides); smaller chunks measured no faster at 256^3
-  const size_t per_patch = csz * size_t(P->Wp) * P->Mh * I.M;
+  const size_t per_patch = csz * size_t(Wp) * Mh * I.M;
   int chunk = int(std::max<size_t>(1, (size_t(2048) << 20) / per_patch));
   if (const char* env = std::getenv("MLC_CONV_CHUNK")) chunk = std::max(1, std::atoi(env));
   L.chunk = std::min(std::min(chunk, L.total), kMaxGridY);
@@ -516,19 +530,35 @@ static Layout layout_of(const std::vector<mlc_plan*>& g) {
   L.o_pl = take(tsz * T * 3 * I.nplanes_a * I.Wa * I.Wa);
   L.o_dir = take(sizeof(double) * T * cube(I.n - 1));
   L.o_F.resize(np); L.o_tor.resize(np); L.o_phiH.resize(np); L.o_phiB.resize(np);
-  for (int k = 0; k < np; ++k) L.o_F[k] = take(sizeof(double) * cube(g[k]->info.Ns));
+  for (int k = 0; k < np; ++k) L.o_F[k] = take(sizeof(double) * cube(g[k]->Ns));
   std::vector<int> done(np, 0);
   for (int k = 0; k < np; ++k) {
     if (done[k]) continue;
-    const int Mc = g[k]->info.M_coarse;
+    const int Mc = g[k]->M_coarse;
     for (int j = k; j < np; ++j)
-      if (!done[j] && g[j]->info.M_coarse == Mc) { L.o_tor[j] = o; o += sizeof(cplx<double>) * cube(Mc); done[j] = 1; }
+      if (!done[j] && g[j]->M_coarse == Mc) { L.o_tor[j] = o; o += sizeof(cplx<double>) * cube(Mc); done[j] = 1; }
     o = align_up(o);
   }
-  for (int k = 0; k < np; ++k) L.o_phiH[k] = take(sizeof(double) * cube(g[k]->info.No));
-  for (int k = 0; k < np; ++k) L.o_phiB[k] = take(sizeof(double) * cube(g[k]->info.N + 1));
+  for (int k = 0; k < np; ++k) L.o_phiH[k] = take(sizeof(double) * cube(g[k]->No));
+  for (int k = 0; k < np; ++k) L.o_phiB[k] = take(sizeof(double) * cube(g[k]->N + 1));
   L.bytes = o;
   return L;
+}
+
+static std::vector<const mlc_plan_info*> infos_of(const std::vector<mlc_plan*>& g) {
+  std::vector<const mlc_plan_info*> v;
+  for (const mlc_plan* p : g) v.push_back(&p->info);
+  return v;
+}
+
+extern "C" mlc_status mlc_problem_workspace_bytes(const mlc_problem* prob, size_t* bytes) {
+  if (!prob || !bytes) return fail(nullptr, MLC_ERR_INVALID_ARG, "null argument");
+  mlc_plan_info I{};
+  std::string why;
+  mlc_status s = derive(prob, &I, &why);
+  if (s != MLC_OK) return fail(nullptr, s, why);
+  *bytes = layout_of({&I}).bytes;
+  return MLC_OK;
 }
 
 extern "C" mlc_status mlc_plan_create(mlc_context* ctx, const mlc_problem* prob, mlc_plan** out) {
@@ -538,6 +568,7 @@ extern "C" mlc_status mlc_plan_create(mlc_context* ctx, const mlc_problem* prob,
   mlc_status s = derive(prob, &I, &why);
   if (s != MLC_OK) return fail(ctx, s, why);
   HIP_TRY(ctx, hipSetDevice(ctx->device));
+  std::lock_guard<std::mutex> lk(ctx->build_mu);
   auto* P = new (std::nothrow) mlc_plan;
   if (!P) return fail(ctx, MLC_ERR_OUT_OF_MEMORY, "host allocation failed");
   P->ctx = ctx;
@@ -595,7 +626,7 @@ extern "C" mlc_status mlc_plan_create(mlc_context* ctx, const mlc_problem* prob,
   }
   // workspace layout (a batch of one)
   {
-    Layout L = layout_of({P});
+    Layout L = layout_of({&P->info});
     P->o_mom = L.o_mom;
     P->o_cs = L.o_cs;
     P->o_pl = L.o_pl;
@@ -937,7 +968,7 @@ extern "C" mlc_status mlc_solve(mlc_plan* plan, const double* f, double* phi, vo
   G.plans = {plan};
   G.f = {f};
   G.phi = {phi};
-  G.L = layout_of(G.plans);
+  G.L = layout_of(infos_of(G.plans));
   G.ws = static_cast<char*>(workspace);
   G.desc = reinterpret_cast<ProbDesc*>(G.ws + G.L.o_desc);
   return enqueue_group(G, static_cast<hipStream_t>(stream));
@@ -962,7 +993,7 @@ static mlc_status make_groups(int32_t count, mlc_plan* const* plans, std::vector
   }
   size_t off = 0;
   for (auto& G : groups) {
-    G.L = layout_of(G.plans);
+    G.L = layout_of(infos_of(G.plans));
     G.off = off;
     off = align_up(off + G.L.bytes);
   }

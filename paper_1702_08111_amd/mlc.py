@@ -59,6 +59,19 @@ class mlc_kernel_time(ctypes.Structure):
     _fields_ = [("name", ctypes.c_char * 48), ("launches", ctypes.c_int32), ("total_ms", ctypes.c_double)]
 
 
+class mlc_server_config(ctypes.Structure):
+    _fields_ = [("workspace_budget_bytes", ctypes.c_size_t), ("streams", ctypes.c_int32),
+                ("max_batch", ctypes.c_int32), ("max_queue", ctypes.c_int32)]
+
+
+class mlc_timing(ctypes.Structure):
+    _fields_ = [("status", ctypes.c_int32), ("batch_size", ctypes.c_int32), ("queue_ms", ctypes.c_double),
+                ("device_ms", ctypes.c_double), ("total_ms", ctypes.c_double)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
 # every symbol declared in include/mlc.h, with its ctypes signature
 _P = ctypes.c_void_p
 _SIGS = {
@@ -71,6 +84,7 @@ _SIGS = {
     "mlc_plan_destroy": (ctypes.c_int, [_P]),
     "mlc_plan_get_info": (ctypes.c_int, [_P, ctypes.POINTER(mlc_plan_info)]),
     "mlc_plan_workspace_bytes": (ctypes.c_int, [_P, ctypes.POINTER(ctypes.c_size_t)]),
+    "mlc_problem_workspace_bytes": (ctypes.c_int, [ctypes.POINTER(mlc_problem), ctypes.POINTER(ctypes.c_size_t)]),
     "mlc_solve": (ctypes.c_int, [_P, _P, _P, _P, ctypes.c_size_t, _P]),
     "mlc_batch_workspace_bytes": (ctypes.c_int, [ctypes.c_int32, ctypes.POINTER(_P), ctypes.POINTER(ctypes.c_size_t)]),
     "mlc_solve_batched": (ctypes.c_int, [ctypes.c_int32, ctypes.POINTER(_P), ctypes.POINTER(_P), ctypes.POINTER(_P),
@@ -80,6 +94,12 @@ _SIGS = {
     "mlc_plan_set_timing": (ctypes.c_int, [_P, ctypes.c_int32]),
     "mlc_plan_timing": (ctypes.c_int, [_P, ctypes.POINTER(mlc_kernel_time), ctypes.c_int32,
                                        ctypes.POINTER(ctypes.c_int32)]),
+    "mlc_server_create": (ctypes.c_int, [_P, ctypes.POINTER(mlc_server_config), ctypes.POINTER(_P)]),
+    "mlc_server_prepare": (ctypes.c_int, [_P, ctypes.POINTER(mlc_problem)]),
+    "mlc_server_submit": (ctypes.c_int, [_P, ctypes.POINTER(mlc_problem), _P, _P, ctypes.POINTER(ctypes.c_uint64)]),
+    "mlc_server_poll": (ctypes.c_int, [_P, ctypes.c_uint64, ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(mlc_timing)]),
+    "mlc_server_drain": (ctypes.c_int, [_P]),
+    "mlc_server_destroy": (ctypes.c_int, [_P]),
 }
 
 _lib = None
@@ -137,6 +157,12 @@ def _stream(s):
 def problem(N, n, alpha=3.0, beta=6.0, P=4, Q=4, b=0, h=None, conv="fp32", fft_size=0, Z=0):
     return mlc_problem(N, (1.0 / N) if h is None else h, n, alpha, beta, P, Q, b,
                        MLC_CONV_FP32 if conv == "fp32" else MLC_CONV_FP64, fft_size, Z)
+
+
+def problem_workspace_bytes(prob):
+    n = ctypes.c_size_t()
+    _check(lib().mlc_problem_workspace_bytes(ctypes.byref(prob), ctypes.byref(n)))
+    return n.value
 
 
 def problem_info(prob):
@@ -225,3 +251,46 @@ def batch_workspace_bytes(plans):
     n = ctypes.c_size_t()
     _check(lib().mlc_batch_workspace_bytes(k, hp, ctypes.byref(n)))
     return n.value
+
+
+class Server:
+    """Request loop over a context (mlc_server_*): submit() queues a solve and
+    returns a ticket; poll() reports it; the server's thread batches and
+    launches requests on its own streams."""
+
+    def __init__(self, ctx, budget_bytes=0, streams=0, max_batch=0, max_queue=0):
+        self.ctx = ctx
+        cfg = mlc_server_config(budget_bytes, streams, max_batch, max_queue)
+        h = ctypes.c_void_p()
+        _check(lib().mlc_server_create(ctx.handle, ctypes.byref(cfg), ctypes.byref(h)), ctx.handle)
+        self.handle = h
+
+    def prepare(self, prob):
+        _check(lib().mlc_server_prepare(self.handle, ctypes.byref(prob)), self.ctx.handle)
+
+    def submit(self, prob, f, phi):
+        """Returns (status, ticket); status MLC_ERR_BUSY when the queue is full."""
+        t = ctypes.c_uint64()
+        st = lib().mlc_server_submit(self.handle, ctypes.byref(prob), _ptr(f), _ptr(phi), ctypes.byref(t))
+        if st not in (MLC_OK, MLC_ERR_BUSY):
+            _check(st, self.ctx.handle)
+        return st, t.value
+
+    def poll(self, ticket):
+        """None while pending, else the timing dict (with the solve's status)."""
+        done = ctypes.c_int32()
+        tm = mlc_timing()
+        st = lib().mlc_server_poll(self.handle, ticket, ctypes.byref(done), ctypes.byref(tm))
+        if st == MLC_ERR_NOT_READY:
+            return None
+        if not done.value:
+            _check(st, self.ctx.handle)
+        return tm.as_dict()
+
+    def drain(self):
+        _check(lib().mlc_server_drain(self.handle), self.ctx.handle)
+
+    def close(self):
+        if self.handle:
+            lib().mlc_server_destroy(self.handle)
+            self.handle = None

@@ -70,3 +70,35 @@ def test_context_without_device_fails_cleanly():
     assert st in (mlc.MLC_OK, mlc.MLC_ERR_DEVICE)
     if st == mlc.MLC_OK:
         mlc.lib().mlc_context_destroy(h)
+
+
+def test_problem_workspace_bytes_host_only():
+    """Workspace sizing needs no device; it covers at least phi^B on all
+    nodes and the Dirichlet work arrays of every patch, and grows with N."""
+    sizes = []
+    for N in (64, 128, 256):
+        prob = mlc.problem(N, 32, 3.0, 6.0, 4, 6, conv="fp32")
+        b = mlc.problem_workspace_bytes(prob)
+        npatch = (N // 32) ** 3
+        assert b >= (N + 1) ** 3 * 8 + npatch * 31 ** 3 * 8
+        assert b % 256 == 0
+        sizes.append(b)
+    assert sizes[0] < sizes[1] < sizes[2]
+    with pytest.raises(mlc.MLCError):
+        mlc.problem_workspace_bytes(mlc.problem(100, 32, 3.0, 6.0, 4, 6))
+
+
+def test_server_calls_reject_null_handles():
+    """Every serving call validates its handle before touching a device."""
+    import ctypes
+    L = mlc.lib()
+    h = ctypes.c_void_p()
+    assert L.mlc_server_create(None, None, ctypes.byref(h)) == mlc.MLC_ERR_INVALID_ARG
+    prob = mlc.problem(32, 8)
+    t = ctypes.c_uint64()
+    assert L.mlc_server_submit(None, ctypes.byref(prob), 1, 1, ctypes.byref(t)) == mlc.MLC_ERR_INVALID_ARG
+    done = ctypes.c_int32()
+    assert L.mlc_server_poll(None, 1, ctypes.byref(done), None) == mlc.MLC_ERR_INVALID_ARG
+    assert L.mlc_server_prepare(None, ctypes.byref(prob)) == mlc.MLC_ERR_INVALID_ARG
+    assert L.mlc_server_drain(None) == mlc.MLC_ERR_INVALID_ARG
+    assert L.mlc_server_destroy(None) == mlc.MLC_ERR_INVALID_ARG
