@@ -61,7 +61,11 @@ typedef struct {
   int32_t Q;              /* Mehrstellen operator: 4 -> L19, 6 -> L27                   */
   int32_t interp_b;       /* coplanar interpolation radius b (order 2b+2); 0 -> Q/2     */
   int32_t conv_precision; /* mlc_conv_precision                                        */
-  int32_t fft_size;       /* Hockney torus edge M of the local convolutions; 0 -> auto  */
+  int32_t fft_size;       /* Hockney torus edge M of the local convolutions: > 0 exact;
+                             0 -> the smallest built size >= 2(n+e)+1; -1 -> autotuned:
+                             plan creation times every built size on a probe grid and
+                             keeps the fastest (cached per patch-work class in the
+                             context; mlc_problem_info reports the smallest)          */
   int32_t dgf_half_width; /* Z of the DGF table [-Z, Z]^3 (solved on [-2Z, 2Z]^3); 0 -> 128 */
 } mlc_problem;
 

@@ -31,6 +31,7 @@ struct mlc_context {
   std::string last_error;
   std::mutex build_mu;  // serialises plan and DGF builds (a server thread may build too)
   std::map<std::pair<int, int>, double*> dgf;   // (Q, Z) -> (2Z+1)^3 table
+  std::map<std::vector<int>, int> tuned;          // autotuned local torus per patch-work class
 };
 
 struct mlc_plan {
@@ -208,7 +209,8 @@ static mlc_status derive(const mlc_problem* p, mlc_plan_info* o, std::string* wh
   I.patches_per_axis = I.N / I.n;
   I.npatch = I.patches_per_axis * I.patches_per_axis * I.patches_per_axis;
   int Mmin = 2 * (I.n + I.e) + 1;
-  if (p->fft_size) {
+  if (p->fft_size < -1) { *why = "fft_size must be > 0, 0 (smallest) or -1 (autotune)"; return MLC_ERR_INVALID_ARG; }
+  if (p->fft_size > 0) {
     if (p->fft_size < Mmin) { *why = "fft_size below the Hockney minimum 2(n+e)+1"; return MLC_ERR_INVALID_ARG; }
     if (!conv_size_ok(p->conv_precision, I.n, p->fft_size)) { *why = "fft_size not built for this patch size"; return MLC_ERR_UNSUPPORTED; }
     I.M = p->fft_size;
@@ -561,6 +563,8 @@ extern "C" mlc_status mlc_problem_workspace_bytes(const mlc_problem* prob, size_
   return MLC_OK;
 }
 
+static int autotune_conv(mlc_context* ctx, const mlc_plan_info& I, const double* G1);
+
 extern "C" mlc_status mlc_plan_create(mlc_context* ctx, const mlc_problem* prob, mlc_plan** out) {
   if (!ctx || !prob || !out) return fail(ctx, MLC_ERR_INVALID_ARG, "null argument");
   std::string why;
@@ -590,6 +594,13 @@ extern "C" mlc_status mlc_plan_create(mlc_context* ctx, const mlc_problem* prob,
   double* G1 = nullptr;
   s = get_dgf(ctx, I.Q, I.Z, &G1);
   if (s != MLC_OK) { delete P; return s; }
+  if (prob->fft_size == -1) {
+    const int M = autotune_conv(ctx, I, G1);
+    if (M < 0) { delete P; return fail(ctx, MLC_ERR_DEVICE, "local FFT autotune failed"); }
+    I.M = M;
+    P->info = I;
+    P->Mh = M / 2 + 1;
+  }
   const int tsz = I.conv_precision == MLC_CONV_FP32 ? 4 : 8;
   // local-convolution spectrum: layout [kx][ky'][kz'] (kx: fastest array axis)
   {
@@ -1034,4 +1045,81 @@ extern "C" mlc_status mlc_solve_batched(int32_t count, mlc_plan* const* plans, c
     if (st != MLC_OK) return st;
   }
   return MLC_OK;
+}
+
+// ------------------------------------------------------------- autotune
+// Local torus edge M for fft_size = -1: every built size >= the Hockney
+// minimum (and within the DGF table) is timed on a 4x4x4-patch probe grid
+// (the three local-convolution kernels, zero charge), and the fastest is
+// kept per patch-work class in the context.  Synchronises the device.
+template <typename T>
+static double time_conv(mlc_context* ctx, const mlc_plan_info& I0, const double* G1, int M) {
+  mlc_plan Pt;
+  Pt.ctx = ctx;
+  Pt.info = I0;
+  Pt.info.M = M;
+  Pt.info.N = 4 * I0.n;
+  Pt.info.patches_per_axis = 4;
+  Pt.info.npatch = 64;
+  Pt.S = I0.n + 1;
+  Pt.Mh = M / 2 + 1;
+  Pt.Wp = I0.Wa + 2 * I0.b;
+  Pt.P0 = -((I0.d_alpha / I0.n) * I0.n);
+  const mlc_plan_info& I = Pt.info;
+  cplx<double>* work = nullptr;
+  double* f = nullptr;
+  char* ws = nullptr;
+  hipEvent_t a = nullptr, b = nullptr;
+  double ms = -1.0;
+  const Layout L = layout_of({&I});
+  const size_t fbytes = sizeof(double) * cube(I.N + 1);
+  if (hipMalloc(&work, sizeof(cplx<double>) * cube(M)) == hipSuccess &&
+      hipMalloc(&Pt.conv_spec, sizeof(T) * cube(Pt.Mh)) == hipSuccess &&
+      hipMalloc(&f, fbytes) == hipSuccess && hipMalloc(&ws, L.bytes) == hipSuccess &&
+      hipEventCreate(&a) == hipSuccess && hipEventCreate(&b) == hipSuccess &&
+      build_spectrum(ctx, G1, I.Z, M, work, nullptr, Pt.conv_spec, int(sizeof(T)), 1.0 / (double(M) * M * M), 2, 1,
+                     0) == MLC_OK &&
+      hipMemset(f, 0, fbytes) == hipSuccess) {
+    Group G;
+    G.plans = {&Pt};
+    G.f = {f};
+    G.phi = {nullptr};
+    G.L = L;
+    G.ws = ws;
+    G.desc = reinterpret_cast<ProbDesc*>(ws + L.o_desc);
+    hipStream_t s = nullptr;
+    upload_descs(G, s);
+    bool ok = dispatch_conv<T>(G, s);
+    hipEventRecord(a, s);
+    for (int r = 0; ok && r < 3; ++r) dispatch_conv<T>(G, s);
+    hipEventRecord(b, s);
+    float t = 0.f;
+    if (ok && hipEventSynchronize(b) == hipSuccess && hipEventElapsedTime(&t, a, b) == hipSuccess) ms = t / 3.0;
+  }
+  hipDeviceSynchronize();
+  if (a) hipEventDestroy(a);
+  if (b) hipEventDestroy(b);
+  hipFree(work);
+  hipFree(Pt.conv_spec);
+  Pt.conv_spec = nullptr;
+  hipFree(f);
+  hipFree(ws);
+  return ms;
+}
+
+static int autotune_conv(mlc_context* ctx, const mlc_plan_info& I, const double* G1) {
+  const std::vector<int> key{I.n, I.e, I.conv_precision, I.Q, I.Z};
+  auto it = ctx->tuned.find(key);
+  if (it != ctx->tuned.end()) return it->second;
+  const int Mmin = 2 * (I.n + I.e) + 1;
+  int best = -1;
+  double best_ms = 0.0;
+  for (int M : kFftSizes) {
+    if (M < Mmin || M / 2 > I.Z || !conv_size_ok(I.conv_precision, I.n, M)) continue;
+    const double ms = I.conv_precision == MLC_CONV_FP32 ? time_conv<float>(ctx, I, G1, M)
+                                                          : time_conv<double>(ctx, I, G1, M);
+    if (ms > 0.0 && (best < 0 || ms < best_ms)) { best = M; best_ms = ms; }
+  }
+  if (best > 0) ctx->tuned[key] = best;
+  return best;
 }

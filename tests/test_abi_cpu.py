@@ -102,3 +102,13 @@ def test_server_calls_reject_null_handles():
     assert L.mlc_server_prepare(None, ctypes.byref(prob)) == mlc.MLC_ERR_INVALID_ARG
     assert L.mlc_server_drain(None) == mlc.MLC_ERR_INVALID_ARG
     assert L.mlc_server_destroy(None) == mlc.MLC_ERR_INVALID_ARG
+
+
+def test_fft_size_autotune_flag():
+    """fft_size = -1 (autotune) validates like 0; below -1 is rejected."""
+    a = mlc.problem_info(mlc.problem(64, 16, 3.0, 6.0, 4, 4, fft_size=-1))
+    b = mlc.problem_info(mlc.problem(64, 16, 3.0, 6.0, 4, 4, fft_size=0))
+    assert a["M"] == b["M"] == 90
+    with pytest.raises(mlc.MLCError) as ei:
+        mlc.problem_info(mlc.problem(64, 16, 3.0, 6.0, 4, 4, fft_size=-2))
+    assert ei.value.status == mlc.MLC_ERR_INVALID_ARG

@@ -104,3 +104,24 @@ def test_batch_validation():
     ws = torch.empty(need - 256, dtype=torch.uint8, device="cuda")
     with pytest.raises(gm.MLCError):
         gm.solve_batched(plans, fs, phis, ws)
+
+
+def test_autotuned_torus():
+    """fft_size = -1 picks one of the built tori >= the Hockney minimum (the
+    same one again from the context's cache) and the solve keeps parity."""
+    import torch
+    ctx = context()
+    prob = gm.problem(64, 16, 3.0, 6.0, 4, 4, conv="fp32", fft_size=-1)
+    p1 = ctx.plan(prob)
+    p2 = ctx.plan(prob)
+    M = p1.info["M"]
+    print("autotuned M", M, flush=True)
+    assert M in (90, 96, 120, 128) and p2.info["M"] == M
+    f_np = mi.bump_charge(64, mi.bumps(2, 41))
+    f = torch.from_numpy(f_np).cuda()
+    got = _alone(p1, f)
+    prm = oracle_params(p1.info, 3.0, 6.0)
+    ref = omlc.mlc_solve(f_np, prm, dgf_cached(4, 128))
+    assert rel(got, ref) < 2e-6
+    p1.close()
+    p2.close()

@@ -105,6 +105,13 @@ def test_symbol_matches_stencil(Q):
 
 
 def test_stencil_coefficients_from_paper():
-    """Appendix A.1 values, typed once more from the table."""
-    assert stencil_b(4) == pytest.approx((-4.0, 1 / 3, 1 / 6, 0.0), abs=1e-16)
-    assert stencil_b(6) == pytest.approx((-64 / 15, 7 / 15, 1 / 10, 1 / 30), abs=1e-16)
+    """The oracle's weights equal the appendix's printed values
+    (tests/golden/mehrstellen_coefficients.txt)."""
+    import os
+    from fractions import Fraction
+    path = os.path.join(os.path.dirname(__file__), "golden", "mehrstellen_coefficients.txt")
+    rows = [ln.split() for ln in open(path) if ln.strip() and not ln.startswith("#")]
+    assert len(rows) == 2
+    for Q, *bs in rows:
+        want = [float(Fraction(b)) for b in bs]
+        assert stencil_b(int(Q)) == pytest.approx(want, abs=1e-16), Q
