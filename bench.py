@@ -68,6 +68,38 @@ def kernel_model(info):
     }
 
 
+KERNEL_SOURCES = ["paper_1702_08111_amd/csrc/conv_kernels.h", "paper_1702_08111_amd/csrc/fft_reg.h",
+                  "paper_1702_08111_amd/csrc/fft.h", "paper_1702_08111_amd/csrc/common.h"]
+
+
+def kernel_source_hash():
+    import hashlib
+    root = os.path.dirname(os.path.abspath(__file__))
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(root, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(kernel, workload):
+    """HBM bytes per launch of `kernel` from the committed rocprofv3 counter
+    summary (FETCH_SIZE x its copy-kernel scale + WRITE_SIZE), or None when no
+    summary exists or the kernel sources changed since it was taken."""
+    root = os.path.dirname(os.path.abspath(__file__))
+    path = os.path.join(root, "profiles", f"{kernel}_{workload}_hbm_traffic.md")
+    if not os.path.exists(path):
+        return None
+    vals = {}
+    for ln in open(path):
+        if "=" in ln and ln.strip().startswith("- `"):
+            k, v = ln.strip()[3:].split("`", 1)[0].split("=", 1)
+            vals[k.strip()] = v.strip()
+    if vals.get("source_hash") != kernel_source_hash():
+        return None
+    return float(vals["traffic_bytes_per_launch"])
+
+
 def cpu_baseline(name, budget):
     import scipy.fft
     cores = len(os.sched_getaffinity(0))
@@ -333,6 +365,9 @@ def main():
         roof["kernel"] = dom
         roof["launches_per_solve"] = launches[dom]
         roof["ms_per_launch"] = round(per_kernel[dom] / launches[dom], 4)
+        tr = measured_traffic(dom, args.workload)
+        roof["traffic"] = tr
+        roof["algorithmic_bytes_per_launch"] = model[dom]["bytes"] / launches[dom]
 
     if args.copy_calibration:
         src = torch.empty(256 * 1024 * 1024, dtype=torch.uint8, device=dev)

@@ -132,7 +132,7 @@ __global__ void __launch_bounds__(256) conv_yz_kernel(const cplx<T>* __restrict_
 #pragma unroll
           for (int j1 = 0; j1 < NJ; ++j1) v[j1] = xr[j][j1];
         }
-      dft_reg<T, R1, 1>(v, tw, M / R1);
+      dft_reg_nz<T, R1, 1, NJ>(v, tw, M / R1);
       cplx<T>* ex = Ex + r * XL + t * (R1 + 1);
 #pragma unroll
       for (int k1 = 0; k1 < R1; ++k1) ex[k1] = (k1 == 0 || t == 0) ? v[k1] : cmul(v[k1], tw[t * k1]);
@@ -162,9 +162,9 @@ __global__ void __launch_bounds__(256) conv_yz_kernel(const cplx<T>* __restrict_
 #pragma unroll
       for (int j1 = 0; j1 < R1; ++j1) {
         int sz = t + R2 * j1;
-        v[j1] = (sz < S && ky < M) ? Y[sz * M + ky] : zero;
+        v[j1] = (j1 < NJ && sz < S && ky < M) ? Y[sz * M + ky] : zero;
       }
-      dft_reg<T, R1, 1>(v, tw, M / R1);
+      dft_reg_nz<T, R1, 1, NJ>(v, tw, M / R1);
       cplx<T>* ex = Ex + c * XL + t * (R1 + 1);
 #pragma unroll
       for (int k1 = 0; k1 < R1; ++k1) ex[k1] = (k1 == 0 || t == 0) ? v[k1] : cmul(v[k1], tw[t * k1]);
@@ -239,10 +239,17 @@ __global__ void __launch_bounds__((OutBatch<T, M>::NT)) conv_out_kernel(const cp
   // bit 0: inside Omega_alpha, bit 1: coarse node, bit 2: skeleton plane
   __shared__ short ocrd[WPMAX];
   __shared__ unsigned char oflg[WPMAX];
+  // rows (output y) whose whole x line is needed, and rows that only need
+  // the x coordinates of skeleton planes
+  __shared__ short frow[WPMAX], crow[WPMAX];
+  __shared__ int nfull, ncols;
+  // inverse twiddles of the skeleton-plane x coordinates: Wx[j][k] = w^(k x_j)
+  constexpr int NPLMAX = 4;
+  __shared__ cplx<T> Wx[NPLMAX * (M / 2)];
   const int zi = blockIdx.x, pc = blockIdx.y, p = p0 + pc;
   const int Wp = g.Wp;
   const int tid = threadIdx.x;
-  const double h2 = pd[find_problem(pd, nprob, p)].h2;
+  const double hsq = pd[find_problem(pd, nprob, p)].h2;
   const cplx<T>* zin = Zb + (int64_t(pc) * Wp + zi) * Mh * M;
   // issue the block's row loads first: all of them (fp32) or one batch ahead
   constexpr int NBY = (Mh + CB - 1) / CB;
@@ -269,6 +276,33 @@ __global__ void __launch_bounds__((OutBatch<T, M>::NT)) conv_out_kernel(const cp
     oflg[k] = (ina ? 1 : 0) | (mod_pos(y, NREF) == 0 ? 2 : 0) | ((ina && mod_pos(y, n) == 0) ? 4 : 0);
   }
   __syncthreads();
+  for (int t = tid; t < g.npl * (M / 2); t += blockDim.x) {
+    const int j = t / (M / 2), k = t % (M / 2);
+    const int x = g.P0 + j * n, xs = x < 0 ? x + M : x;
+    Wx[t] = tw[(k * xs) % M];
+  }
+  if (tid < 64) {
+    // compact the two row lists in ascending order with wave ballots
+    const int zf = oflg[zi];
+    int a = 0, c = 0;
+    const uint64_t below = (uint64_t(1) << tid) - 1;
+    for (int base = 0; base < Wp; base += 64) {
+      const int yi = base + tid;
+      const int yf = yi < Wp ? oflg[yi] : 0;
+      // z-plane rows in Omega_alpha, coarse rows of a coarse z, y-plane rows
+      const bool full = ((zf & 4) && (yf & 1)) || ((zf & 2) && (yf & 2)) || ((zf & 1) && (yf & 4));
+      const bool col = !full && (zf & 1) && (yf & 1);   // x-plane columns only
+      const uint64_t mf = __ballot(full), mc = __ballot(col);
+      if (full) frow[a + __popcll(mf & below)] = short(yi);
+      if (col) crow[c + __popcll(mc & below)] = short(yi);
+      a += __popcll(mf);
+      c += __popcll(mc);
+    }
+    if (tid == 0) {
+      nfull = a;
+      ncols = c;
+    }
+  }
   // ---- inverse FFT along y for every kx (CB rows per batch) ----
 #pragma unroll 1
   for (int kb = 0, jb = 0; kb < Mh; kb += CB, ++jb) {
@@ -320,12 +354,43 @@ __global__ void __launch_bounds__((OutBatch<T, M>::NT)) conv_out_kernel(const cp
   const int npl = g.npl, Wa = g.Wa, Wc = g.Wc;
   T* cbase = coarse + int64_t(p) * Wc * Wc * Wc;
   T* pbase = planes + int64_t(p) * 3 * npl * Wa * Wa;
-  // ---- Hermitian inverse along x: two real lines (y1, y1+1) per complex line ----
+  const int nf = nfull, ncl = ncols;
+  // ---- x-plane columns of the other rows: direct Hermitian sums ----
+  //   f(x) = F_0 + (-1)^x F_{M/2} + 2 sum_{0<k<M/2} Re(F_k e^{2 pi i k x / M})
+  for (int q = tid; q < ncl * npl; q += blockDim.x) {
+    const int yi = crow[q / npl], j = q % npl;
+    const int x = g.P0 + j * n, xs = x < 0 ? x + M : x;
+    const cplx<T>* wj = Wx + j * (M / 2);
+    // four interleaved partial sums over k = 1 .. M/2 - 1
+    constexpr int KT = M / 2 - 1;
+    T acc[4] = {T(0), T(0), T(0), T(0)};
+#pragma unroll 2
+    for (int k0 = 1; k0 + 3 <= KT; k0 += 4) {
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const cplx<T> a = A[(k0 + u) * Wp + yi];
+        const cplx<T> w = wj[k0 + u];
+        acc[u] += a.x * w.x + a.y * w.y;
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < KT % 4; ++u) {
+      const int k = KT - KT % 4 + 1 + u;
+      const cplx<T> a = A[k * Wp + yi];
+      const cplx<T> w = wj[k];
+      acc[u] += a.x * w.x + a.y * w.y;
+    }
+    const T dc = A[yi].x, ny = A[(M / 2) * Wp + yi].x;
+    const T val = dc + ((xs & 1) ? -ny : ny) + T(2) * ((acc[0] + acc[1]) + (acc[2] + acc[3]));
+    const int y = ocrd[yi];
+    pbase[((int64_t(2) * npl + j) * Wa + (z + g.da)) * Wa + (y + g.da)] = T(double(val) * hsq);
+  }
+  // ---- Hermitian inverse along x of the full rows: two real lines per complex line ----
 #pragma unroll 1
-  for (int yb = 0; yb < Wp; yb += 2 * CB) {
+  for (int fb = 0; fb < nf; fb += 2 * CB) {
     if (tid < CB * R1) {
       const int s = tid % R1, c = tid / R1;
-      const int y1 = yb + 2 * c, y2 = y1 + 1;
+      const int y1 = fb + 2 * c < nf ? frow[fb + 2 * c] : Wp, y2 = fb + 2 * c + 1 < nf ? frow[fb + 2 * c + 1] : Wp;
       cplx<T> u[R2];
 #pragma unroll
       for (int k2 = 0; k2 < R2; ++k2) {
@@ -362,10 +427,11 @@ __global__ void __launch_bounds__((OutBatch<T, M>::NT)) conv_out_kernel(const cp
         const int x = ocrd[xi], xf = oflg[xi];
 #pragma unroll
         for (int h = 0; h < 2; ++h) {
-          int yi = yb + 2 * c + h;
-          if (yi >= Wp) continue;
+          const int fi = fb + 2 * c + h;
+          if (fi >= nf) continue;
+          const int yi = frow[fi];
           const int y = ocrd[yi], yf = oflg[yi];
-          T val = T(double(h ? v[j1].y : v[j1].x) * h2);
+          T val = T(double(h ? v[j1].y : v[j1].x) * hsq);
           if (zc && (xf & 2) && (yf & 2))
             cbase[(int64_t((z + g.e) / NREF) * Wc + (y + g.e) / NREF) * Wc + (x + g.e) / NREF] = val;
           if (zpl && (yf & 1) && (xf & 1))

@@ -58,6 +58,43 @@ __device__ __forceinline__ void dft_reg(cplx<T>* v, const cplx<T>* tw, int step)
   }
 }
 
+// The same DFT when only the first NZ inputs can be nonzero (zero-padded
+// source lines): with R = A * B and NZ <= B, the first-stage DFTs over
+// v[j2 + B j1] each see one input (j1 = 0), so they reduce to the twiddle
+// products, and the second-stage DFTs again have NZ leading inputs.
+template <typename T, int R, int DIR, int NZ>
+__device__ __forceinline__ void dft_reg_nz(cplx<T>* v, const cplx<T>* tw, int step) {
+  constexpr int A = first_factor(R), B = R / A;
+  if constexpr (NZ >= R || R <= 5 || NZ > B) {
+    dft_reg<T, R, DIR>(v, tw, step);
+  } else {
+    cplx<T> tmp[R];
+#pragma unroll
+    for (int j2 = 0; j2 < B; ++j2)
+#pragma unroll
+      for (int k1 = 0; k1 < A; ++k1) {
+        if (j2 >= NZ) {
+          tmp[j2 * A + k1] = {T(0), T(0)};
+        } else if (j2 * k1 == 0) {
+          tmp[j2 * A + k1] = v[j2];
+        } else {
+          cplx<T> w = tw[((j2 * k1) % R) * step];
+          if constexpr (DIR < 0) w.y = -w.y;
+          tmp[j2 * A + k1] = cmul(v[j2], w);
+        }
+      }
+#pragma unroll
+    for (int k1 = 0; k1 < A; ++k1) {
+      cplx<T> bb[B];
+#pragma unroll
+      for (int j2 = 0; j2 < B; ++j2) bb[j2] = tmp[j2 * A + k1];
+      dft_reg_nz<T, B, DIR, NZ>(bb, tw, step * A);
+#pragma unroll
+      for (int k2 = 0; k2 < B; ++k2) v[k1 + A * k2] = bb[k2];
+    }
+  }
+}
+
 // Split M = R1 * R2 with R1 (pass-2 threads per line, the heavier pass in the
 // convolution) >= R2, both at most 16.
 template <int M> struct Split;

@@ -398,6 +398,41 @@ static mlc_status build_spectrum(mlc_context* ctx, const double* G1, int Z, int 
   return MLC_OK;
 }
 
+// Geometry of the two far-field contractions (skeleton planes, coarse grid)
+// and of the zero-padded moment lattice they share.
+static void annulus_geoms(const mlc_plan_info& I, MfmaGeom* skel, MfmaGeom* coarse) {
+  auto cdiv_floor = [](int a, int b) { return a >= 0 ? a / b : -((-a + b - 1) / b); };
+  auto cdiv_ceil = [](int a, int b) { return a >= 0 ? (a + b - 1) / b : -((-a) / b); };
+  const int n = I.n, db = I.d_beta, ppa = I.patches_per_axis, K = I.K, KP = (K + 3) / 4 * 4;
+  auto rows64 = [](int r) { return (r + 63) / 64 * 64; };
+  MfmaGeom& gs = *skel;
+  gs = MfmaGeom{};
+  gs.ppa = ppa; gs.K = K; gs.KP = KP; gs.nr = n * n; gs.nrp = rows64(gs.nr);
+  gs.e0lo = cdiv_ceil(-db, n);
+  gs.ne0 = cdiv_floor(n + db, n) - gs.e0lo + 1;
+  gs.elo = cdiv_ceil(-db - (n - 1), n);
+  gs.ne = cdiv_floor(n + db, n) - gs.elo + 1;
+  gs.nk0 = gs.nk1 = gs.nk2 = ppa + 1;
+  gs.k0lo = gs.k1lo = gs.k2lo = 0;
+  MfmaGeom& gc = *coarse;
+  gc = MfmaGeom{};
+  const int q = n / NREF, cb = db / NREF;
+  gc.ppa = ppa; gc.K = K; gc.KP = KP; gc.nr = q * q * q; gc.nrp = rows64(gc.nr);
+  gc.elo = cdiv_ceil(-cb - (q - 1), q);
+  gc.ne = cdiv_floor((n + db) / NREF, q) - gc.elo + 1;
+  gc.e0lo = gc.elo; gc.ne0 = gc.ne;
+  gc.k0lo = gc.k1lo = gc.k2lo = cdiv_floor(I.S_lo, q);
+  gc.nk0 = gc.nk1 = gc.nk2 = cdiv_floor(I.S_lo + I.Ns - 1, q) - gc.k0lo + 1;
+  // padded lattice: patch coordinate k - E over both contractions, every axis
+  const int emax = std::max({gs.e0lo + gs.ne0 - 1, gs.elo + gs.ne - 1, gc.elo + gc.ne - 1});
+  const int emin = std::min({gs.e0lo, gs.elo, gc.elo});
+  const int kmin = std::min(0, gc.k0lo), kmax = std::max(ppa, gc.k0lo + gc.nk0 - 1);
+  const int padlo = std::max(emax - kmin, 0);
+  const int L = std::max(kmax - emin, ppa - 1) + padlo + 1;
+  gs.L = gc.L = L;
+  gs.padlo = gc.padlo = padlo;
+}
+
 static mlc_status build_tables(mlc_plan* P, const double* G1) {
   mlc_context* ctx = P->ctx;
   const mlc_plan_info& I = P->info;
@@ -441,34 +476,20 @@ static mlc_status build_tables(mlc_plan* P, const double* G1) {
   hipFree(work); hipFree(oct); hipFree(coarse); hipFree(planes);
   if (st != MLC_OK) return st;
   // MFMA layouts of both tables
-  auto cdiv_floor = [](int a, int b) { return a >= 0 ? a / b : -((-a + b - 1) / b); };
-  auto cdiv_ceil = [](int a, int b) { return a >= 0 ? (a + b - 1) / b : -((-a) / b); };
-  const int n = I.n, db = I.d_beta, ppa = I.patches_per_axis, KP = (K + 3) / 4 * 4;
+  annulus_geoms(I, &P->mg_skel, &P->mg_coarse);
+  const int n = I.n, db = I.d_beta;
   {
-    MfmaGeom& g = P->mg_skel;
-    g.ppa = ppa; g.K = K; g.KP = KP; g.nr = n * n;
-    g.e0lo = cdiv_ceil(-db, n);
-    g.ne0 = cdiv_floor(n + db, n) - g.e0lo + 1;
-    g.elo = cdiv_ceil(-db - (n - 1), n);
-    g.ne = cdiv_floor(n + db, n) - g.elo + 1;
-    g.nk0 = g.nk1 = g.nk2 = ppa + 1;
-    g.k0lo = g.k1lo = g.k2lo = 0;
-    int64_t total = int64_t(3) * g.ne0 * g.ne * g.ne * (KP / 4) * g.nr * 4;
+    const MfmaGeom& g = P->mg_skel;
+    int64_t total = int64_t(3) * g.ne0 * g.ne * g.ne * (g.KP / 4) * g.nrp * 4;
     if (hipMalloc(&P->Am, sizeof(double) * total) != hipSuccess)
       return fail(ctx, MLC_ERR_OUT_OF_MEMORY, "far-field MFMA table allocation failed");
     hipLaunchKernelGGL(skel_mfma_table_kernel, dim3(blocks_for(total)), dim3(256), 0, s, P->D, P->Am, n, db, P->P0b,
                        P->nplb, P->Wb, K, g);
   }
   {
-    MfmaGeom& g = P->mg_coarse;
-    const int q = n / NREF, cb = db / NREF;
-    g.ppa = ppa; g.K = K; g.KP = KP; g.nr = q * q * q;
-    g.elo = cdiv_ceil(-cb - (q - 1), q);
-    g.ne = cdiv_floor((n + db) / NREF, q) - g.elo + 1;
-    g.e0lo = g.elo; g.ne0 = g.ne;
-    g.k0lo = g.k1lo = g.k2lo = cdiv_floor(I.S_lo, q);
-    g.nk0 = g.nk1 = g.nk2 = cdiv_floor(I.S_lo + I.Ns - 1, q) - g.k0lo + 1;
-    int64_t total = int64_t(g.ne) * g.ne * g.ne * (KP / 4) * g.nr * 4;
+    const MfmaGeom& g = P->mg_coarse;
+    const int q = n / NREF;
+    int64_t total = int64_t(g.ne) * g.ne * g.ne * (g.KP / 4) * g.nrp * 4;
     if (hipMalloc(&P->Tm, sizeof(double) * total) != hipSuccess)
       return fail(ctx, MLC_ERR_OUT_OF_MEMORY, "far-field MFMA table allocation failed");
     hipLaunchKernelGGL(coarse_mfma_table_kernel, dim3(blocks_for(total)), dim3(256), 0, s, P->T, P->Tm, q, db,
@@ -497,7 +518,7 @@ static bool same_class(const mlc_plan* a, const mlc_plan* b) {
 //   phi^H, phi^B.
 struct Layout {
   size_t o_desc = 0, o_mom = 0, o_X = 0, o_Z = 0, o_cs = 0, o_pl = 0, o_dir = 0;
-  std::vector<size_t> o_F, o_tor, o_phiH, o_phiB;
+  std::vector<size_t> o_F, o_tor, o_phiH, o_phiB, o_cpad;
   std::vector<int> patch0;
   int total = 0, chunk = 0;
   size_t bytes = 0;
@@ -543,6 +564,16 @@ static Layout layout_of(const std::vector<const mlc_plan_info*>& g) {
   }
   for (int k = 0; k < np; ++k) L.o_phiH[k] = take(sizeof(double) * cube(g[k]->No));
   for (int k = 0; k < np; ++k) L.o_phiB[k] = take(sizeof(double) * cube(g[k]->N + 1));
+  L.o_cpad.resize(np);
+  for (int k = 0; k < np; ++k) {
+    size_t bytes = 0;
+    if (g[k]->d_beta > g[k]->d_alpha) {
+      MfmaGeom gs, gc;
+      annulus_geoms(*g[k], &gs, &gc);
+      bytes = sizeof(double) * cube(gs.L) * gs.KP;
+    }
+    L.o_cpad[k] = take(bytes);
+  }
   L.bytes = o;
   return L;
 }
@@ -857,6 +888,8 @@ static void launch_rest(const Group& G, hipStream_t s) {
                          cs + L.patch0[k] * csz, st, cg, F_of(k));
     }
   }
+  auto cpad_of = [&](int k) { return reinterpret_cast<double*>(G.ws + L.o_cpad[k]); };
+  constexpr int ANN_COLS = 16 * ANN_TILES;
   if (P0->Kann > 0) {
     TimedScope ts(P0, s, "coarse_annulus");
     const int q = I0.n / NREF;
@@ -864,9 +897,12 @@ static void launch_rest(const Group& G, hipStream_t s) {
       const mlc_plan* P = G.plans[k];
       const mlc_plan_info& I = P->info;
       const MfmaGeom& g = P->mg_coarse;
+      // moments into the zero-padded lattice both far-field sums read
+      hipLaunchKernelGGL(pad_moments_kernel, dim3(blocks_for(cube(g.L) * g.KP)), dim3(256), 0, s,
+                         mom + int64_t(L.patch0[k]) * I.K, cpad_of(k), g.ppa, g.K, g.KP, g.L, g.padlo);
       const int nk = g.nk0 * g.nk1 * g.nk2;
-      hipLaunchKernelGGL(coarse_annulus_mfma_kernel, dim3((g.nr + 63) / 64, (nk + 63) / 64), dim3(256), 0, s, P->Tm,
-                         mom + int64_t(L.patch0[k]) * I.K, g, q, I.S_lo, I.Ns, F_of(k));
+      hipLaunchKernelGGL(coarse_annulus_mfma_kernel, dim3(g.nrp / 64, (nk + ANN_COLS - 1) / ANN_COLS), dim3(256), 0,
+                         s, P->Tm, cpad_of(k), g, q, I.S_lo, I.Ns, F_of(k));
     }
   }
   // coarse solves, the FFTs batched over problems of equal coarse torus
@@ -912,8 +948,8 @@ static void launch_rest(const Group& G, hipStream_t s) {
       const mlc_plan_info& I = P->info;
       const MfmaGeom& g = P->mg_skel;
       const int nk = g.nk0 * g.nk1 * g.nk2;
-      hipLaunchKernelGGL(skeleton_annulus_mfma_kernel, dim3((g.nr + 63) / 64, (nk + 63) / 64, 3), dim3(256), 0, s,
-                         P->Am, mom + int64_t(L.patch0[k]) * I.K, g, I.n, I.N, phiB_of(k));
+      hipLaunchKernelGGL(skeleton_annulus_mfma_kernel, dim3(g.nrp / 64, (nk + ANN_COLS - 1) / ANN_COLS, 3), dim3(256),
+                         0, s, P->Am, cpad_of(k), g, I.n, I.N, phiB_of(k));
     }
   }
   {
@@ -937,8 +973,6 @@ static void launch_rest(const Group& G, hipStream_t s) {
     hipLaunchKernelGGL(dirichlet_mfma_kernel<0>, gd, dim3(256), 0, s, G.desc, np, dir, dg);
     hipLaunchKernelGGL(dirichlet_mfma_kernel<1>, gd, dim3(256), 0, s, G.desc, np, dir, dg);
     hipLaunchKernelGGL(dirichlet_mfma_kernel<2>, gd, dim3(256), 0, s, G.desc, np, dir, dg);
-    hipLaunchKernelGGL(dirichlet_mfma_kernel<3>, gd, dim3(256), 0, s, G.desc, np, dir, dg);
-    hipLaunchKernelGGL(dirichlet_mfma_kernel<4>, gd, dim3(256), 0, s, G.desc, np, dir, dg);
   }
 }
 

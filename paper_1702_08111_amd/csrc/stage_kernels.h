@@ -233,28 +233,47 @@ struct SkelGeom {
 // A fragment lane l = row (r) l%16, column p = l/16; B fragment lane l =
 // column (k) l%16, row p = l/16; accumulator lane l, register j holds
 // out[4 j + l/16][l%16].
+//
+// The moments are first copied into a zero-padded lattice Cpad[L^3][KP]
+// (patch i at slot i + padlo per axis), so that c[k - E] is one address
+// shifted by a uniform per-offset amount: no bounds tests in the inner loop.
 typedef double f64x4 __attribute__((ext_vector_type(4)));
 
 struct MfmaGeom {
   int ppa, K, KP;            // patches per axis, moments, moments padded to 4
-  int nr;                    // rows (intra-patch positions) of one orientation
+  int nr, nrp;               // rows (intra-patch positions) of one orientation; padded to 64
   int e0lo, ne0, elo, ne;    // offset box: first axis [e0lo, e0lo+ne0), others [elo, elo+ne)
   int nk0, nk1, nk2;         // lattice box sizes (k0 slowest)
   int k0lo, k1lo, k2lo;      // lattice box origins
+  int L, padlo;              // padded moment lattice
 };
 
+// Cpad[slot][p], slot = ((i0 + padlo) L + i1 + padlo) L + i2 + padlo.
+__global__ void pad_moments_kernel(const double* __restrict__ mom, double* __restrict__ Cpad, int ppa, int K,
+                                   int KP, int L, int padlo) {
+  int64_t idx = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (idx >= cube(L) * KP) return;
+  const int p = int(idx % KP);
+  const int64_t slot = idx / KP;
+  const int a2 = int(slot % L) - padlo, a1 = int((slot / L) % L) - padlo, a0 = int(slot / (int64_t(L) * L)) - padlo;
+  double v = 0.0;
+  if (p < K && a0 >= 0 && a0 < ppa && a1 >= 0 && a1 < ppa && a2 >= 0 && a2 < ppa)
+    v = mom[(int64_t(a0 * ppa + a1) * ppa + a2) * K + p];
+  Cpad[idx] = v;
+}
+
 // A rows for the skeleton: r = ra * n + rb over the face plane of normal d;
-// table Am[d][E][pc][r][4] (E = (E0, E1, E2) over the offset box), value
-// D[d][E0 plane][ra + n E1][rb + n E2][p] when inside the table, else 0.
+// table Am[d][E][pc][r][4] (E = (E0, E1, E2) over the offset box, r < nrp),
+// value D[d][E0 plane][ra + n E1][rb + n E2][p] when inside the table, else 0.
 __global__ void skel_mfma_table_kernel(const double* __restrict__ D, double* __restrict__ Am, int n, int db,
                                        int P0b, int nplb, int Wb, int K, MfmaGeom mg) {
   const int npc = mg.KP / 4;
-  const int64_t per_d = int64_t(mg.ne0) * mg.ne * mg.ne * npc * mg.nr * 4;
+  const int64_t per_d = int64_t(mg.ne0) * mg.ne * mg.ne * npc * mg.nrp * 4;
   int64_t idx = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
   if (idx >= 3 * per_d) return;
   int j = int(idx % 4);
   int64_t t = idx / 4;
-  int r = int(t % mg.nr); t /= mg.nr;
+  int r = int(t % mg.nrp); t /= mg.nrp;
   int pc = int(t % npc); t /= npc;
   int e2 = int(t % mg.ne); t /= mg.ne;
   int e1 = int(t % mg.ne); t /= mg.ne;
@@ -266,22 +285,22 @@ __global__ void skel_mfma_table_kernel(const double* __restrict__ D, double* __r
   int jb = (n * E0 - P0b) / n;
   int ub = ra + n * E1 + db, vb = rb + n * E2 + db;
   double v = 0.0;
-  if (p < K && jb >= 0 && jb < nplb && ub >= 0 && ub < Wb && vb >= 0 && vb < Wb)
+  if (r < mg.nr && p < K && jb >= 0 && jb < nplb && ub >= 0 && ub < Wb && vb >= 0 && vb < Wb)
     v = D[((((int64_t(d) * nplb + jb) * Wb + ub) * Wb) + vb) * K + p];
   Am[idx] = v;
 }
 
-// A rows for the coarse grid: rho = (r0, r1, r2) in [0, q)^3; table
+// A rows for the coarse grid: rho = (r0, r1, r2) in [0, q)^3 (r < nrp); table
 // Tm[E][pc][rho][4] = T[q E + rho][p] inside C(Omega_beta(0)), else 0.
 __global__ void coarse_mfma_table_kernel(const double* __restrict__ Tt, double* __restrict__ Tm, int q, int db,
                                          int Wbc, int K, MfmaGeom mg) {
   const int npc = mg.KP / 4;
-  const int64_t total = int64_t(mg.ne) * mg.ne * mg.ne * npc * mg.nr * 4;
+  const int64_t total = int64_t(mg.ne) * mg.ne * mg.ne * npc * mg.nrp * 4;
   int64_t idx = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
   if (idx >= total) return;
   int j = int(idx % 4);
   int64_t t = idx / 4;
-  int r = int(t % mg.nr); t /= mg.nr;
+  int r = int(t % mg.nrp); t /= mg.nrp;
   int pc = int(t % npc); t /= npc;
   int e2 = int(t % mg.ne); t /= mg.ne;
   int e1 = int(t % mg.ne);
@@ -291,7 +310,7 @@ __global__ void coarse_mfma_table_kernel(const double* __restrict__ Tt, double* 
   int E[3] = {mg.elo + e0, mg.elo + e1, mg.elo + e2};
   int ob = db / NREF;
   int c[3];
-  bool ok = p < K;
+  bool ok = r < mg.nr && p < K;
   for (int a = 0; a < 3; ++a) {
     c[a] = q * E[a] + rr[a] + ob;
     ok = ok && c[a] >= 0 && c[a] < Wbc;
@@ -299,87 +318,96 @@ __global__ void coarse_mfma_table_kernel(const double* __restrict__ Tt, double* 
   Tm[idx] = ok ? Tt[((int64_t(c[0]) * Wbc + c[1]) * Wbc + c[2]) * K + p] : 0.0;
 }
 
-// One wave: 16 rows x 64 lattice points (four 16-column tiles); a block of
-// four waves covers 64 rows.  `orient` selects the skeleton orientation
-// (grid z), or is -1 for the coarse grid.  Returns accumulators per tile.
-__device__ __forceinline__ void annulus_mfma_tiles(const double* __restrict__ Am, const double* __restrict__ mom,
+// Columns of one wave: ANN_TILES tiles of 16 consecutive lattice points.
+constexpr int ANN_TILES = 8;
+
+// One wave: 16 rows x 16*ANN_TILES lattice points; a block of four waves
+// covers 64 rows.  `d` selects the skeleton orientation, or is -1 for the
+// coarse grid.  Offsets whose patches all fall outside the lattice for the
+// wave's box of columns are skipped (a uniform test).
+__device__ __forceinline__ void annulus_mfma_tiles(const double* __restrict__ Am, const double* __restrict__ Cpad,
                                                    const MfmaGeom& mg, int d, int rowbase, int kbase,
-                                                   f64x4 acc[4]) {
+                                                   f64x4 (&acc)[ANN_TILES]) {
   const int lane = threadIdx.x & 63;
   const int rl = lane & 15, pj = lane >> 4;
   const int npc = mg.KP / 4;
-  const int nk = mg.nk0 * mg.nk1 * mg.nk2;
-  int kk0[4], kk1[4], kk2[4];
-  bool kin[4];
+  const int n12 = mg.nk1 * mg.nk2, nk = mg.nk0 * n12;
+  const int L = mg.L, pad = mg.padlo;
+  // strides of the lattice axes (normal or first, lower, upper) in the padded array
+  int st0, st1, st2;
+  if (d <= 0) { st0 = L * L; st1 = L; st2 = 1; }
+  else if (d == 1) { st0 = L; st1 = L * L; st2 = 1; }
+  else { st0 = 1; st1 = L * L; st2 = L; }
+  int64_t boff[ANN_TILES];
 #pragma unroll
-  for (int t = 0; t < 4; ++t) {
-    int k = kbase + 16 * t + rl;
-    kin[t] = k < nk;
-    int kc = kin[t] ? k : 0;
-    kk0[t] = mg.k0lo + kc / (mg.nk1 * mg.nk2);
-    kk1[t] = mg.k1lo + (kc / mg.nk2) % mg.nk1;
-    kk2[t] = mg.k2lo + kc % mg.nk2;
+  for (int t = 0; t < ANN_TILES; ++t) {
+    const int k = min(kbase + 16 * t + rl, nk - 1);
+    const int a = mg.k0lo + k / n12, b = mg.k1lo + (k / mg.nk2) % mg.nk1, c = mg.k2lo + k % mg.nk2;
+    boff[t] = int64_t((a + pad) * st0 + (b + pad) * st1 + (c + pad) * st2) * mg.KP + pj;
     acc[t] = f64x4{0.0, 0.0, 0.0, 0.0};
   }
-  const int ppa = mg.ppa, K = mg.K;
-  const int64_t per_d = int64_t(mg.ne0) * mg.ne * mg.ne * npc * mg.nr * 4;
-  const double* Ad = Am + (d > 0 ? d : 0) * per_d;
-  for (int e0 = 0; e0 < mg.ne0; ++e0)
-    for (int e1 = 0; e1 < mg.ne; ++e1)
+  // lattice box of the wave's columns
+  const int klast = min(kbase + 16 * ANN_TILES, nk) - 1;
+  int a_lo = kbase / n12, a_hi = klast / n12;
+  int b_lo = 0, b_hi = mg.nk1 - 1, c_lo = 0, c_hi = mg.nk2 - 1;
+  if (a_lo == a_hi) {
+    b_lo = (kbase / mg.nk2) % mg.nk1;
+    b_hi = (klast / mg.nk2) % mg.nk1;
+    if (b_lo == b_hi) { c_lo = kbase % mg.nk2; c_hi = klast % mg.nk2; }
+  }
+  a_lo += mg.k0lo; a_hi += mg.k0lo;
+  b_lo += mg.k1lo; b_hi += mg.k1lo;
+  c_lo += mg.k2lo; c_hi += mg.k2lo;
+  const int ppa = mg.ppa;
+  const int64_t per_d = int64_t(mg.ne0) * mg.ne * mg.ne * npc * mg.nrp * 4;
+  const double* Ad = Am + (d > 0 ? d : 0) * per_d + (rowbase + rl) * 4 + pj;
+  for (int e0 = 0; e0 < mg.ne0; ++e0) {
+    const int E0 = mg.e0lo + e0;
+    if (a_hi - E0 < 0 || a_lo - E0 > ppa - 1) continue;
+    for (int e1 = 0; e1 < mg.ne; ++e1) {
+      const int E1 = mg.elo + e1;
+      if (b_hi - E1 < 0 || b_lo - E1 > ppa - 1) continue;
       for (int e2 = 0; e2 < mg.ne; ++e2) {
-        const int E0 = mg.e0lo + e0, E1 = mg.elo + e1, E2 = mg.elo + e2;
-        // patch index of every column for this offset (or -1)
-        int ip[4];
-        bool any = false;
-#pragma unroll
-        for (int t = 0; t < 4; ++t) {
-          // lattice axes (k0, k1, k2) are (normal, lower in-plane, upper in-plane)
-          // for a skeleton orientation d, array axes for the coarse grid
-          int i0 = kk0[t] - E0, i1 = kk1[t] - E1, i2 = kk2[t] - E2;
-          bool v = kin[t] && i0 >= 0 && i0 < ppa && i1 >= 0 && i1 < ppa && i2 >= 0 && i2 < ppa;
-          int ia[3];
-          if (d <= 0) { ia[0] = i0; ia[1] = i1; ia[2] = i2; }
-          else if (d == 1) { ia[1] = i0; ia[0] = i1; ia[2] = i2; }
-          else { ia[2] = i0; ia[0] = i1; ia[1] = i2; }
-          ip[t] = v ? (ia[0] * ppa + ia[1]) * ppa + ia[2] : -1;
-          any = any || v;
-        }
-        if (!__any(any)) continue;
-        const double* Ae = Ad + ((int64_t(e0) * mg.ne + e1) * mg.ne + e2) * npc * mg.nr * 4;
+        const int E2 = mg.elo + e2;
+        if (c_hi - E2 < 0 || c_lo - E2 > ppa - 1) continue;
+        const int64_t off = int64_t(E0 * st0 + E1 * st1 + E2 * st2) * mg.KP;
+        const double* Ae = Ad + ((int64_t(e0) * mg.ne + e1) * mg.ne + e2) * npc * mg.nrp * 4;
         for (int pc = 0; pc < npc; ++pc) {
-          const double a = rowbase + rl < mg.nr ? Ae[(int64_t(pc) * mg.nr + rowbase + rl) * 4 + pj] : 0.0;
-          const int p = 4 * pc + pj;
+          const double a = Ae[int64_t(pc) * mg.nrp * 4];
 #pragma unroll
-          for (int t = 0; t < 4; ++t) {
-            const double b = (ip[t] >= 0 && p < K) ? mom[int64_t(ip[t]) * K + p] : 0.0;
+          for (int t = 0; t < ANN_TILES; ++t) {
+            const double b = Cpad[boff[t] - off + 4 * pc];
             acc[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc[t], 0, 0, 0);
           }
         }
       }
+    }
+  }
 }
 
 // Skeleton: rows r = ra * n + rb of the face plane of normal d = blockIdx.z,
 // columns k = (kd, ka, kb) in [0, ppa]^3; writes the far field into phiB at
 // every canonical skeleton node.
 __global__ void __launch_bounds__(256) skeleton_annulus_mfma_kernel(const double* __restrict__ Am,
-                                                                    const double* __restrict__ mom, MfmaGeom mg,
+                                                                    const double* __restrict__ Cpad, MfmaGeom mg,
                                                                     int n, int N, double* __restrict__ phiB) {
   const int d = blockIdx.z;
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int rowbase = blockIdx.x * 64 + wave * 16;
-  const int kbase = blockIdx.y * 64;
-  f64x4 acc[4];
-  annulus_mfma_tiles(Am, mom, mg, d, rowbase, kbase, acc);
+  const int kbase = blockIdx.y * 16 * ANN_TILES;
+  f64x4 acc[ANN_TILES];
+  annulus_mfma_tiles(Am, Cpad, mg, d, rowbase, kbase, acc);
   const int a0 = d == 0 ? 1 : 0, a1 = d == 2 ? 1 : 2, Np = N + 1;
   const int nk = mg.nk0 * mg.nk1 * mg.nk2;
 #pragma unroll
-  for (int t = 0; t < 4; ++t) {
+  for (int t = 0; t < ANN_TILES; ++t) {
     int k = kbase + 16 * t + (lane & 15);
     if (k >= nk) continue;
     int kd = k / (mg.nk1 * mg.nk2), ka = (k / mg.nk2) % mg.nk1, kb = k % mg.nk2;
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
       int r = rowbase + 4 * j + (lane >> 4);
+      if (r >= mg.nr) continue;
       int ra = r / n, rb = r % n;
       if ((a0 < d && ra == 0) || (a1 < d && rb == 0)) continue;     // not canonical
       int gg[3];
@@ -395,16 +423,16 @@ __global__ void __launch_bounds__(256) skeleton_annulus_mfma_kernel(const double
 // Coarse grid: rows rho in [0, q)^3, columns k over the lattice box; adds the
 // far field to F[c = q k + rho] inside the support box.
 __global__ void __launch_bounds__(256) coarse_annulus_mfma_kernel(const double* __restrict__ Tm,
-                                                                  const double* __restrict__ mom, MfmaGeom mg,
+                                                                  const double* __restrict__ Cpad, MfmaGeom mg,
                                                                   int q, int S_lo, int Ns, double* __restrict__ F) {
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int rowbase = blockIdx.x * 64 + wave * 16;
-  const int kbase = blockIdx.y * 64;
-  f64x4 acc[4];
-  annulus_mfma_tiles(Tm, mom, mg, -1, rowbase, kbase, acc);
+  const int kbase = blockIdx.y * 16 * ANN_TILES;
+  f64x4 acc[ANN_TILES];
+  annulus_mfma_tiles(Tm, Cpad, mg, -1, rowbase, kbase, acc);
   const int nk = mg.nk0 * mg.nk1 * mg.nk2;
 #pragma unroll
-  for (int t = 0; t < 4; ++t) {
+  for (int t = 0; t < ANN_TILES; ++t) {
     int k = kbase + 16 * t + (lane & 15);
     if (k >= nk) continue;
     int k0 = mg.k0lo + k / (mg.nk1 * mg.nk2), k1 = mg.k1lo + (k / mg.nk2) % mg.nk1, k2 = mg.k2lo + k % mg.nk2;
@@ -490,28 +518,58 @@ __global__ void __launch_bounds__(256) skeleton_kernel(const double* __restrict_
 // --------------------------------------------- Dirichlet solves on MFMA ----
 // The patch solve (sec. 4.1 eq. last_step_fulldiscr) diagonalises in the
 // DST-I basis of length m = n - 1: u = S^-1 (S rhs / lambda) with
-// S[k][j] = sin(pi (k+1)(j+1) / n) along each axis and S^-1 = (2/n) S.  Each
-// axis transform is, per slab (one wave, m x m padded to 32 x 32), the
-// product S (32 x 32) x slab (32 x 32) on v_mfma_f64_16x16x4f64.  Five passes:
-//   0: right-hand side h^2 f - (boundary terms), then forward along axis 2
-//   1: forward along axis 1
-//   2: forward along axis 0, divide by the symbol, inverse along axis 0
-//   3: inverse along axis 1
-//   4: inverse along axis 2, then phi = u + C2 h^2 f on the patch interior
+// S[k][j] = sin(pi (k+1)(j+1) / n) along each axis, S symmetric and
+// S^-1 = (2/n) S.  A slab (one wave, m x m padded to 32 x 32) is transformed
+// along both of its axes as S X S, along one as S X, each product on
+// v_mfma_f64_16x16x4f64.  Three passes over the patches' (n-1)^3 work arrays:
+//   0: slabs of fixed index 0: right-hand side h^2 f - (boundary terms), S X S
+//   1: slabs of fixed index 1: S X along index 0, divide by the symbol,
+//      S X again (times 2/n)
+//   2: slabs of fixed index 0: S X S (times (2/n)^2), then
+//      phi = u + C2 h^2 f on the patch interior
 struct DirGeom {
   int n, npatch;
-  double scale;   // 2/n per inverse pass
+  double scale;   // 2/n
   Stencil st;
 };
+
+// D = A B for 32 x 32 row-major LDS matrices of stride 33 (one wave).  D may
+// be A or B: every input is read before the first output is written.
+__device__ __forceinline__ void mm32(const double* A, const double* B, double* D, int lane) {
+  f64x4 acc[2][2];
+#pragma unroll
+  for (int it = 0; it < 2; ++it)
+#pragma unroll
+    for (int kt = 0; kt < 2; ++kt) acc[it][kt] = f64x4{0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+  for (int jj = 0; jj < 8; ++jj) {
+    const int jrow = 4 * jj + (lane >> 4);
+#pragma unroll
+    for (int it = 0; it < 2; ++it) {
+      const double a = A[(16 * it + (lane & 15)) * 33 + jrow];
+#pragma unroll
+      for (int kt = 0; kt < 2; ++kt) {
+        const double b = B[jrow * 33 + 16 * kt + (lane & 15)];
+        acc[it][kt] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc[it][kt], 0, 0, 0);
+      }
+    }
+  }
+#pragma unroll
+  for (int it = 0; it < 2; ++it)
+#pragma unroll
+    for (int kt = 0; kt < 2; ++kt)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) D[(16 * it + 4 * r + (lane >> 4)) * 33 + 16 * kt + (lane & 15)] = acc[it][kt][r];
+}
 
 template <int PASS>
 __global__ void __launch_bounds__(256) dirichlet_mfma_kernel(const ProbDesc* __restrict__ pd, int nprob,
                                                              double* __restrict__ work, DirGeom g) {
   __shared__ double Sm[32 * 33];
   __shared__ double Ls[4][32 * 33];
+  __shared__ double sn[2 * 32], cs[32];
   const int m = g.n - 1;
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  __shared__ double sn[2 * 32], cs[32];
   // sin(pi a / n) for a < 2n and cos(pi (k+1) / n): every entry of the
   // transform matrix and of the symbol is one of these
   if (threadIdx.x < 2 * g.n) sn[threadIdx.x] = sinpi(double(threadIdx.x) / double(g.n));
@@ -530,27 +588,25 @@ __global__ void __launch_bounds__(256) dirichlet_mfma_kernel(const ProbDesc* __r
   double* phi = D.phi;
   const int ppa = D.ppa, pl = p - D.patch0;
   const double h2 = D.h2;
-  const int axis = (PASS == 0 || PASS == 4) ? 2 : (PASS == 1 || PASS == 3) ? 1 : 0;
-  // element (j along the transform axis, w along the faster other axis) of slab u
+  // slab element (row i, column j):
+  //   passes 0, 2: node index (u, i, j); pass 1: node index (i, u, j)
   const int64_t M3 = int64_t(m) * m * m;
-  auto off = [&](int j, int w) -> int64_t {
-    if (axis == 2) return int64_t(u) * m * m + int64_t(w) * m + j;
-    if (axis == 1) return int64_t(u) * m * m + int64_t(j) * m + w;
-    return int64_t(j) * m * m + int64_t(u) * m + w;
+  auto off = [&](int i, int j) -> int64_t {
+    if (PASS == 1) return int64_t(i) * m * m + int64_t(u) * m + j;
+    return int64_t(u) * m * m + int64_t(i) * m + j;
   };
   double* wp = work + int64_t(p) * M3;
   const int i0 = pl / (ppa * ppa), i1 = (pl / ppa) % ppa, i2 = pl % ppa;
   const int64_t Np = D.N + 1;
   const int64_t pbase = (int64_t(g.n) * i0) * Np * Np + int64_t(g.n) * i1 * Np + int64_t(g.n) * i2;
   double* L = Ls[wave];
-  // load the slab (rows j, columns w), zero-padded to 32 x 32
-  for (int t = lane; t < 32 * 32; t += 64) {
-    int j = t / 32, w = t % 32;
+  // lanes 0..31 walk a row's columns, the two half-waves take alternate rows
+  const int jc = lane & 31, ih = lane >> 5;
+  for (int i = ih; i < 32; i += 2) {
     double v = 0.0;
-    if (live && j < m && w < m) {
+    if (live && i < m && jc < m) {
       if constexpr (PASS == 0) {
-        // node (l0, l1, l2) = (u, w, j) + 1 inside the patch
-        int l0 = u + 1, l1 = w + 1, l2 = j + 1;
+        const int l0 = u + 1, l1 = i + 1, l2 = jc + 1;
         v = h2 * f[pbase + (l0 * Np + l1) * Np + l2];
         if (l0 == 1 || l0 == g.n - 1 || l1 == 1 || l1 == g.n - 1 || l2 == 1 || l2 == g.n - 1) {
           for (int s0 = -1; s0 <= 1; ++s0)
@@ -563,72 +619,43 @@ __global__ void __launch_bounds__(256) dirichlet_mfma_kernel(const ProbDesc* __r
               }
         }
       } else {
-        v = wp[off(j, w)];
+        v = wp[off(i, jc)];
       }
     }
-    L[j * 33 + w] = v;
+    L[i * 33 + jc] = v;
   }
   __syncthreads();
-  // out[k][w] = sum_j S[k][j] L[j][w]; A lane = row l%16, col l/16; B lane = col l%16, row l/16
-  auto product = [&](double* dst) {
-    f64x4 acc[2][2];
-#pragma unroll
-    for (int kt = 0; kt < 2; ++kt)
-#pragma unroll
-      for (int wt = 0; wt < 2; ++wt) acc[kt][wt] = f64x4{0.0, 0.0, 0.0, 0.0};
-#pragma unroll
-    for (int jj = 0; jj < 8; ++jj) {
-      const int jrow = 4 * jj + (lane >> 4);
-#pragma unroll
-      for (int kt = 0; kt < 2; ++kt) {
-        const double a = Sm[(16 * kt + (lane & 15)) * 33 + jrow];
-#pragma unroll
-        for (int wt = 0; wt < 2; ++wt) {
-          const double b = L[jrow * 33 + 16 * wt + (lane & 15)];
-          acc[kt][wt] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc[kt][wt], 0, 0, 0);
-        }
-      }
-    }
-#pragma unroll
-    for (int kt = 0; kt < 2; ++kt)
-#pragma unroll
-      for (int wt = 0; wt < 2; ++wt)
-#pragma unroll
-        for (int r = 0; r < 4; ++r) dst[(16 * kt + 4 * r + (lane >> 4)) * 33 + 16 * wt + (lane & 15)] = acc[kt][wt][r];
-  };
-  // each wave's slab is its own: the product reads all of L into the MFMA
-  // accumulators before writing the result back over it
-  double* O = L;
-  product(O);
-  __syncthreads();
-  if constexpr (PASS == 2) {
-    // divide the coefficient (k0 = row, k1 = u, k2 = w) by the symbol, then inverse along axis 0
-    for (int t = lane; t < 32 * 32; t += 64) {
-      int k = t / 32, w = t % 32;
+  if constexpr (PASS == 1) {
+    mm32(Sm, L, L, lane);                 // forward along index 0
+    __syncthreads();
+    for (int i = ih; i < 32; i += 2) {    // divide by the symbol at (k0, k1, k2) = (i, u, jc)
       double v = 0.0;
-      if (k < m && w < m) {
-        double c0 = cs[k], c1 = cs[u], c2 = cs[w];
-        double lam = g.st.b[0] + 2.0 * g.st.b[1] * (c0 + c1 + c2) + 4.0 * g.st.b[2] * (c0 * c1 + c0 * c2 + c1 * c2) +
-                     8.0 * g.st.b[3] * c0 * c1 * c2;
-        v = O[k * 33 + w] / lam;
+      if (i < m && jc < m) {
+        const double c0 = cs[i], c1 = cs[u], c2 = cs[jc];
+        const double lam = g.st.b[0] + 2.0 * g.st.b[1] * (c0 + c1 + c2) +
+                           4.0 * g.st.b[2] * (c0 * c1 + c0 * c2 + c1 * c2) + 8.0 * g.st.b[3] * c0 * c1 * c2;
+        v = L[i * 33 + jc] / lam;
       }
-      L[k * 33 + w] = v;
+      L[i * 33 + jc] = v;
     }
     __syncthreads();
-    product(O);
+    mm32(Sm, L, L, lane);                 // inverse along index 0
+  } else {
+    mm32(Sm, L, L, lane);                 // along index 1 (rows)
     __syncthreads();
+    mm32(L, Sm, L, lane);                 // along index 2 (columns)
   }
-  const double sc = (PASS >= 2) ? g.scale : 1.0;
+  __syncthreads();
   if (!live) return;
-  for (int t = lane; t < m * m; t += 64) {
-    int k = t / m, w = t % m;
-    double v = sc * O[k * 33 + w];
-    if constexpr (PASS == 4) {
-      int l0 = u + 1, l1 = w + 1, l2 = k + 1;
-      int64_t node = pbase + (l0 * Np + l1) * Np + l2;
+  const double sc = PASS == 0 ? 1.0 : (PASS == 1 ? g.scale : g.scale * g.scale);
+  for (int i = ih; i < m; i += 2) {
+    if (jc >= m) continue;
+    const double v = sc * L[i * 33 + jc];
+    if constexpr (PASS == 2) {
+      const int64_t node = pbase + (int64_t(u + 1) * Np + (i + 1)) * Np + (jc + 1);
       phi[node] = v + (h2 / 12.0) * f[node];
     } else {
-      wp[off(k, w)] = v;
+      wp[off(i, jc)] = v;
     }
   }
 }
