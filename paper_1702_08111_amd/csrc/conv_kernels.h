@@ -70,12 +70,25 @@ template <typename T, int M> struct Batch {
   // odd padded line stride of the exchange buffer
   static constexpr int XL = (XLayout<M>::LINE % 2) ? XLayout<M>::LINE : XLayout<M>::LINE + 1;
 };
-// conv_out holds the whole (kx, y) plane in LDS, so one block fills a CU:
-// fp32 runs 512 threads (more lines per batch); fp64 fewer lines to fit.
+// conv_out holds the whole (kx, y) plane in LDS, so one block fills a CU.
+// fp32: 512 threads, each wave transforms its own lines (LW per step)
+// through a private slice of the exchange buffer, with no block barriers
+// between FFT passes; fp64 (twice the plane in LDS): 256 threads, CB lines
+// per block-wide batch.
 template <typename T, int M> struct OutBatch {
   static constexpr int NT = sizeof(T) == 4 ? 512 : 256;
-  static constexpr int CB = sizeof(T) == 4 ? NT / Batch<T, M>::RMAX : 4;
+  static constexpr bool WAVE = sizeof(T) == 4;
+  static constexpr int LW = 64 / Split<M>::R1;
+  static constexpr int CB = WAVE ? (NT / 64) * LW : 4;
 };
+
+// LDS ordering among the lanes of one wave (the wave's LDS operations are
+// executed in order; this keeps the compiler from moving them across).
+__device__ __forceinline__ void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
 
 template <typename T>
 __device__ __forceinline__ cplx<T> conjw(cplx<T> w) { return {w.x, -w.y}; }
@@ -251,19 +264,27 @@ __global__ void __launch_bounds__((OutBatch<T, M>::NT)) conv_out_kernel(const cp
   const int tid = threadIdx.x;
   const double hsq = pd[find_problem(pd, nprob, p)].h2;
   const cplx<T>* zin = Zb + (int64_t(pc) * Wp + zi) * Mh * M;
-  // issue the block's row loads first: all of them (fp32) or one batch ahead
-  constexpr int NBY = (Mh + CB - 1) / CB;
-  constexpr int PRE = sizeof(T) == 4 ? NBY : 1;
-  cplx<T> pre[PRE][R2];
-  {
+  constexpr bool WAVE = OutBatch<T, M>::WAVE;
+  constexpr int LW = OutBatch<T, M>::LW, NW = OutBatch<T, M>::NT / 64;
+  const int wave = tid >> 6, lane = tid & 63;
+  const int s1 = lane % R1, r1 = lane / R1, t2 = lane % R2, r2 = lane / R2;
+  const bool act1 = lane < LW * R1, act2 = lane < LW * R2;
+  // wave mode: the first step's lines, issued before the set-up below
+  cplx<T> u0[R2];
+  auto load_lines = [&](cplx<T>* dst, int kb) {
+    const int kx = kb + r1;
+#pragma unroll
+    for (int k2 = 0; k2 < R2; ++k2)
+      dst[k2] = (act1 && kx < Mh) ? zin[int64_t(kx) * M + s1 + R1 * k2] : cplx<T>{T(0), T(0)};
+  };
+  if constexpr (WAVE) load_lines(u0, wave * LW);
+  // block mode: the first batch's rows
+  cplx<T> pre[R2];
+  if constexpr (!WAVE) {
     const int s = tid % R1, r = tid / R1;
 #pragma unroll
-    for (int j = 0; j < PRE; ++j) {
-      const int kx = j * CB + r;
-#pragma unroll
-      for (int k2 = 0; k2 < R2; ++k2)
-        pre[j][k2] = (tid < CB * R1 && kx < Mh) ? zin[int64_t(kx) * M + s + R1 * k2] : cplx<T>{T(0), T(0)};
-    }
+    for (int k2 = 0; k2 < R2; ++k2)
+      pre[k2] = (tid < CB * R1 && r < Mh) ? zin[int64_t(r) * M + s + R1 * k2] : cplx<T>{T(0), T(0)};
   }
   fill_twiddles(tw, M);
   for (int m = tid; m < M; m += blockDim.x) omap[m] = -1;
@@ -303,58 +324,148 @@ __global__ void __launch_bounds__((OutBatch<T, M>::NT)) conv_out_kernel(const cp
       ncols = c;
     }
   }
-  // ---- inverse FFT along y for every kx (CB rows per batch) ----
+  // y pass, second half: one line's R1-point DFT in R2 lanes (lanes (t, r)),
+  // kept outputs into A
+  auto y_pass2 = [&](const cplx<T>* ex, int t, int r, int kx) {
+    cplx<T> v[R1];
+#pragma unroll
+    for (int s = 0; s < R1; ++s) v[s] = ex[r * XL + s * (R2 + 1) + t];
+    dft_reg<T, R1, -1>(v, tw, M / R1);
+    if (kx < Mh) {
+#pragma unroll
+      for (int j1 = 0; j1 < R1; ++j1) {
+        int yi = omap[t + R2 * j1];
+        if (yi >= 0) A[kx * Wp + yi] = v[j1];
+      }
+    }
+  };
+  // y pass, first half: R2-point DFT of one line's column s, twiddled, to ex
+  auto y_pass1 = [&](cplx<T>* u, cplx<T>* ex, int s, int r) {
+    dft_reg<T, R2, -1>(u, tw, M / R2);
+#pragma unroll
+    for (int t = 0; t < R2; ++t) {
+      cplx<T> w = (s && t) ? cmul(u[t], conjw(tw[t * s])) : u[t];
+      ex[r * XL + s * (R2 + 1) + t] = w;
+    }
+  };
+  __syncthreads();
+  // ---- inverse FFT along y for every kx ----
+  if constexpr (WAVE) {
+    cplx<T>* ex = Ex + wave * LW * XL;
 #pragma unroll 1
-  for (int kb = 0, jb = 0; kb < Mh; kb += CB, ++jb) {
-    if (tid < CB * R1) {
+    for (int kb = wave * LW; kb < Mh; kb += NW * LW) {
+      cplx<T> un[R2];
+      load_lines(un, kb + NW * LW);   // next step's lines in flight meanwhile
+      if (act1) y_pass1(u0, ex, s1, r1);
+      wave_sync();
+      if (act2) y_pass2(ex, t2, r2, kb + r2);
+      wave_sync();
+#pragma unroll
+      for (int k2 = 0; k2 < R2; ++k2) u0[k2] = un[k2];
+    }
+  } else {
+#pragma unroll 1
+    for (int kb = 0; kb < Mh; kb += CB) {
       const int s = tid % R1, r = tid / R1;
-      cplx<T> u[R2];
-      if constexpr (PRE == NBY) {
-        // fully prefetched: select batch jb from registers
+      if (tid < CB * R1) {
+        cplx<T> u[R2];
 #pragma unroll
-        for (int j = 0; j < PRE; ++j)
-          if (j == jb) {
-#pragma unroll
-            for (int k2 = 0; k2 < R2; ++k2) u[k2] = pre[j][k2];
-          }
-      } else {
-#pragma unroll
-        for (int k2 = 0; k2 < R2; ++k2) u[k2] = pre[0][k2];
+        for (int k2 = 0; k2 < R2; ++k2) u[k2] = pre[k2];
         const int kn = kb + CB + r;
 #pragma unroll
         for (int k2 = 0; k2 < R2; ++k2)
-          pre[0][k2] = kn < Mh ? zin[int64_t(kn) * M + s + R1 * k2] : cplx<T>{T(0), T(0)};
+          pre[k2] = kn < Mh ? zin[int64_t(kn) * M + s + R1 * k2] : cplx<T>{T(0), T(0)};
+        y_pass1(u, Ex, s, r);
       }
-      dft_reg<T, R2, -1>(u, tw, M / R2);
-#pragma unroll
-      for (int t = 0; t < R2; ++t) {
-        cplx<T> w = (s && t) ? cmul(u[t], conjw(tw[t * s])) : u[t];
-        Ex[r * XL + s * (R2 + 1) + t] = w;
-      }
+      __syncthreads();
+      if (tid < CB * R2) y_pass2(Ex, tid % R2, tid / R2, kb + tid / R2);
+      __syncthreads();
     }
-    __syncthreads();
-    if (tid < CB * R2) {
-      const int t = tid % R2, r = tid / R2, kx = kb + r;
-      cplx<T> v[R1];
-#pragma unroll
-      for (int s1 = 0; s1 < R1; ++s1) v[s1] = Ex[r * XL + s1 * (R2 + 1) + t];
-      dft_reg<T, R1, -1>(v, tw, M / R1);
-      if (kx < Mh) {
-#pragma unroll
-        for (int j1 = 0; j1 < R1; ++j1) {
-          int yi = omap[t + R2 * j1];
-          if (yi >= 0) A[kx * Wp + yi] = v[j1];
-        }
-      }
-    }
-    __syncthreads();
   }
+  __syncthreads();
   const int z = ocrd[zi];
   const bool zin_a = oflg[zi] & 1, zc = oflg[zi] & 2, zpl = oflg[zi] & 4;
   const int npl = g.npl, Wa = g.Wa, Wc = g.Wc;
   T* cbase = coarse + int64_t(p) * Wc * Wc * Wc;
   T* pbase = planes + int64_t(p) * 3 * npl * Wa * Wa;
   const int nf = nfull, ncl = ncols;
+  // ---- Hermitian inverse along x of the full rows: two real lines per complex line ----
+  // first half: pair-line c's column s (rows frow[2c], frow[2c+1])
+  auto x_pass1 = [&](cplx<T>* ex, int s, int c, int pi) {
+    const int i1 = 2 * pi;
+    const int y1 = i1 < nf ? frow[i1] : Wp, y2 = i1 + 1 < nf ? frow[i1 + 1] : Wp;
+    cplx<T> u[R2];
+#pragma unroll
+    for (int k2 = 0; k2 < R2; ++k2) {
+      int k = s + R1 * k2;
+      cplx<T> h1 = {T(0), T(0)}, h2 = {T(0), T(0)};
+      if (k < Mh) {
+        if (y1 < Wp) h1 = A[k * Wp + y1];
+        if (y2 < Wp) h2 = A[k * Wp + y2];
+      } else {
+        if (y1 < Wp) h1 = conjw(A[(M - k) * Wp + y1]);
+        if (y2 < Wp) h2 = conjw(A[(M - k) * Wp + y2]);
+      }
+      if (k == 0 || k == M / 2) { h1.y = T(0); h2.y = T(0); }   // real DC / Nyquist
+      u[k2] = {h1.x - h2.y, h1.y + h2.x};                        // h1 + i h2
+    }
+    dft_reg<T, R2, -1>(u, tw, M / R2);
+#pragma unroll
+    for (int t = 0; t < R2; ++t) {
+      cplx<T> w = (s && t) ? cmul(u[t], conjw(tw[t * s])) : u[t];
+      ex[c * XL + s * (R2 + 1) + t] = w;
+    }
+  };
+  // second half: outputs of pair-line c (global pair index pi)
+  auto x_pass2 = [&](const cplx<T>* ex, int t, int c, int pi) {
+    cplx<T> v[R1];
+#pragma unroll
+    for (int s = 0; s < R1; ++s) v[s] = ex[c * XL + s * (R2 + 1) + t];
+    dft_reg<T, R1, -1>(v, tw, M / R1);
+#pragma unroll
+    for (int j1 = 0; j1 < R1; ++j1) {
+      int xi = omap[t + R2 * j1];
+      if (xi < 0) continue;
+      const int x = ocrd[xi], xf = oflg[xi];
+#pragma unroll
+      for (int h = 0; h < 2; ++h) {
+        const int fi = 2 * pi + h;
+        if (fi >= nf) continue;
+        const int yi = frow[fi];
+        const int y = ocrd[yi], yf = oflg[yi];
+        T val = T(double(h ? v[j1].y : v[j1].x) * hsq);
+        if (zc && (xf & 2) && (yf & 2))
+          cbase[(int64_t((z + g.e) / NREF) * Wc + (y + g.e) / NREF) * Wc + (x + g.e) / NREF] = val;
+        if (zpl && (yf & 1) && (xf & 1))
+          pbase[((int64_t(0) * npl + (z - g.P0) / n) * Wa + (y + g.da)) * Wa + (x + g.da)] = val;
+        if (zin_a && (yf & 1) && (xf & 1)) {
+          if (yf & 4)
+            pbase[((int64_t(1) * npl + (y - g.P0) / n) * Wa + (z + g.da)) * Wa + (x + g.da)] = val;
+          if (xf & 4)
+            pbase[((int64_t(2) * npl + (x - g.P0) / n) * Wa + (z + g.da)) * Wa + (y + g.da)] = val;
+        }
+      }
+    }
+  };
+  const int npair = (nf + 1) / 2;
+  if constexpr (WAVE) {
+    cplx<T>* ex = Ex + wave * LW * XL;
+#pragma unroll 1
+    for (int pb = wave * LW; pb < npair; pb += NW * LW) {
+      if (act1) x_pass1(ex, s1, r1, pb + r1);
+      wave_sync();
+      if (act2) x_pass2(ex, t2, r2, pb + r2);
+      wave_sync();
+    }
+  } else {
+#pragma unroll 1
+    for (int pb = 0; pb < npair; pb += CB) {
+      if (tid < CB * R1) x_pass1(Ex, tid % R1, tid / R1, pb + tid / R1);
+      __syncthreads();
+      if (tid < CB * R2) x_pass2(Ex, tid % R2, tid / R2, pb + tid / R2);
+      __syncthreads();
+    }
+  }
   // ---- x-plane columns of the other rows: direct Hermitian sums ----
   //   f(x) = F_0 + (-1)^x F_{M/2} + 2 sum_{0<k<M/2} Re(F_k e^{2 pi i k x / M})
   for (int q = tid; q < ncl * npl; q += blockDim.x) {
@@ -384,68 +495,6 @@ __global__ void __launch_bounds__((OutBatch<T, M>::NT)) conv_out_kernel(const cp
     const T val = dc + ((xs & 1) ? -ny : ny) + T(2) * ((acc[0] + acc[1]) + (acc[2] + acc[3]));
     const int y = ocrd[yi];
     pbase[((int64_t(2) * npl + j) * Wa + (z + g.da)) * Wa + (y + g.da)] = T(double(val) * hsq);
-  }
-  // ---- Hermitian inverse along x of the full rows: two real lines per complex line ----
-#pragma unroll 1
-  for (int fb = 0; fb < nf; fb += 2 * CB) {
-    if (tid < CB * R1) {
-      const int s = tid % R1, c = tid / R1;
-      const int y1 = fb + 2 * c < nf ? frow[fb + 2 * c] : Wp, y2 = fb + 2 * c + 1 < nf ? frow[fb + 2 * c + 1] : Wp;
-      cplx<T> u[R2];
-#pragma unroll
-      for (int k2 = 0; k2 < R2; ++k2) {
-        int k = s + R1 * k2;
-        cplx<T> h1 = {T(0), T(0)}, h2 = {T(0), T(0)};
-        if (k < Mh) {
-          if (y1 < Wp) h1 = A[k * Wp + y1];
-          if (y2 < Wp) h2 = A[k * Wp + y2];
-        } else {
-          if (y1 < Wp) h1 = conjw(A[(M - k) * Wp + y1]);
-          if (y2 < Wp) h2 = conjw(A[(M - k) * Wp + y2]);
-        }
-        if (k == 0 || k == M / 2) { h1.y = T(0); h2.y = T(0); }   // real DC / Nyquist
-        u[k2] = {h1.x - h2.y, h1.y + h2.x};                        // h1 + i h2
-      }
-      dft_reg<T, R2, -1>(u, tw, M / R2);
-#pragma unroll
-      for (int t = 0; t < R2; ++t) {
-        cplx<T> w = (s && t) ? cmul(u[t], conjw(tw[t * s])) : u[t];
-        Ex[c * XL + s * (R2 + 1) + t] = w;
-      }
-    }
-    __syncthreads();
-    if (tid < CB * R2) {
-      const int t = tid % R2, c = tid / R2;
-      cplx<T> v[R1];
-#pragma unroll
-      for (int s1 = 0; s1 < R1; ++s1) v[s1] = Ex[c * XL + s1 * (R2 + 1) + t];
-      dft_reg<T, R1, -1>(v, tw, M / R1);
-#pragma unroll
-      for (int j1 = 0; j1 < R1; ++j1) {
-        int xi = omap[t + R2 * j1];
-        if (xi < 0) continue;
-        const int x = ocrd[xi], xf = oflg[xi];
-#pragma unroll
-        for (int h = 0; h < 2; ++h) {
-          const int fi = fb + 2 * c + h;
-          if (fi >= nf) continue;
-          const int yi = frow[fi];
-          const int y = ocrd[yi], yf = oflg[yi];
-          T val = T(double(h ? v[j1].y : v[j1].x) * hsq);
-          if (zc && (xf & 2) && (yf & 2))
-            cbase[(int64_t((z + g.e) / NREF) * Wc + (y + g.e) / NREF) * Wc + (x + g.e) / NREF] = val;
-          if (zpl && (yf & 1) && (xf & 1))
-            pbase[((int64_t(0) * npl + (z - g.P0) / n) * Wa + (y + g.da)) * Wa + (x + g.da)] = val;
-          if (zin_a && (yf & 1) && (xf & 1)) {
-            if (yf & 4)
-              pbase[((int64_t(1) * npl + (y - g.P0) / n) * Wa + (z + g.da)) * Wa + (x + g.da)] = val;
-            if (xf & 4)
-              pbase[((int64_t(2) * npl + (x - g.P0) / n) * Wa + (z + g.da)) * Wa + (y + g.da)] = val;
-          }
-        }
-      }
-    }
-    __syncthreads();
   }
 }
 
