@@ -67,6 +67,7 @@ template <typename T, int M> struct Batch {
   static constexpr int R1 = Split<M>::R1, R2 = Split<M>::R2;
   static constexpr int RMAX = R1 > R2 ? R1 : R2;
   static constexpr int CB = 256 / RMAX;
+  static constexpr int LC = 64 / RMAX;   // columns per wave step (conv_yz column phase)
   // odd padded line stride of the exchange buffer
   static constexpr int XL = (XLayout<M>::LINE % 2) ? XLayout<M>::LINE : XLayout<M>::LINE + 1;
 };
@@ -101,7 +102,10 @@ __global__ void __launch_bounds__(256) conv_yz_kernel(const cplx<T>* __restrict_
   constexpr int S = n + 1;
   constexpr int R1 = Split<M>::R1, R2 = Split<M>::R2;
   constexpr int CB = Batch<T, M>::CB, XL = Batch<T, M>::XL;
-  __shared__ cplx<T> Y[S * M];
+  // source rows after the y FFT; row stride M + 4 keeps the column reads of
+  // one wave on distinct LDS banks
+  constexpr int YS = M + 4;
+  __shared__ cplx<T> Y[S * YS];
   __shared__ cplx<T> Ex[CB * XL];
   __shared__ cplx<T> tw[M];
   __shared__ short zmap[M];
@@ -145,7 +149,7 @@ __global__ void __launch_bounds__(256) conv_yz_kernel(const cplx<T>* __restrict_
 #pragma unroll
           for (int j1 = 0; j1 < NJ; ++j1) v[j1] = xr[j][j1];
         }
-      dft_reg_nz<T, R1, 1, NJ>(v, tw, M / R1);
+      dft_reg_nz<T, R1, 1, NJ>(v);
       cplx<T>* ex = Ex + r * XL + t * (R1 + 1);
 #pragma unroll
       for (int k1 = 0; k1 < R1; ++k1) ex[k1] = (k1 == 0 || t == 0) ? v[k1] : cmul(v[k1], tw[t * k1]);
@@ -156,77 +160,84 @@ __global__ void __launch_bounds__(256) conv_yz_kernel(const cplx<T>* __restrict_
       cplx<T> u[R2];
 #pragma unroll
       for (int t = 0; t < R2; ++t) u[t] = Ex[r * XL + t * (R1 + 1) + s];
-      dft_reg<T, R2, 1>(u, tw, M / R2);
+      dft_reg<T, R2, 1>(u);
       if (sz < S) {
 #pragma unroll
-        for (int k2 = 0; k2 < R2; ++k2) Y[sz * M + s + R1 * k2] = u[k2];
+        for (int k2 = 0; k2 < R2; ++k2) Y[sz * YS + s + R1 * k2] = u[k2];
       }
     }
     __syncthreads();
   }
   // ---- per column ky: FFT along z, times the spectrum, inverse along z ----
+  // Each wave takes LC columns per step through its own slice of Ex, with
+  // no block barriers (wave_sync orders the wave's own LDS traffic).
   const T* sp = spec + int64_t(kx) * Mh * Mh;
   cplx<T>* zout = Zb + (int64_t(pc) * Wp * Mh + kx) * M;
+  constexpr int LC = Batch<T, M>::LC;
+  const int wave = tid >> 6, lane = tid & 63;
+  cplx<T>* ex = Ex + wave * LC * XL;
+  const int ca = lane % LC, ta = lane / LC;     // R1-point passes: R2 lanes per column (columns fastest)
+  const int sb = lane % R1, cb2 = lane / R1;    // R2-point passes: R1 lanes per column
+  const bool actA = lane < LC * R2, actB = lane < LC * R1;
 #pragma unroll 1
-  for (int cb = 0; cb < M; cb += CB) {
-    if (tid < CB * R2) {
-      const int c = tid % CB, t = tid / CB, ky = cb + c;
+  for (int c0 = wave * LC; c0 < M; c0 += (blockDim.x / 64) * LC) {
+    if (actA) {
+      const int ky = c0 + ca;
       cplx<T> v[R1];
 #pragma unroll
       for (int j1 = 0; j1 < R1; ++j1) {
-        int sz = t + R2 * j1;
-        v[j1] = (j1 < NJ && sz < S && ky < M) ? Y[sz * M + ky] : zero;
+        int sz = ta + R2 * j1;
+        v[j1] = (j1 < NJ && sz < S && ky < M) ? Y[sz * YS + ky] : zero;
       }
-      dft_reg_nz<T, R1, 1, NJ>(v, tw, M / R1);
-      cplx<T>* ex = Ex + c * XL + t * (R1 + 1);
+      dft_reg_nz<T, R1, 1, NJ>(v);
+      cplx<T>* e = ex + ca * XL + ta * (R1 + 1);
 #pragma unroll
-      for (int k1 = 0; k1 < R1; ++k1) ex[k1] = (k1 == 0 || t == 0) ? v[k1] : cmul(v[k1], tw[t * k1]);
+      for (int k1 = 0; k1 < R1; ++k1) e[k1] = (k1 == 0 || ta == 0) ? v[k1] : cmul(v[k1], tw[ta * k1]);
     }
-    __syncthreads();
-    const bool act = tid < CB * R1;
-    const int s = tid % R1, c2 = tid / R1;
+    wave_sync();
     cplx<T> u[R2];
-    if (act) {
-      const int ky = cb + c2;
+    if (actB) {
+      const int ky = c0 + cb2;
 #pragma unroll
-      for (int t = 0; t < R2; ++t) u[t] = Ex[c2 * XL + t * (R1 + 1) + s];
-      dft_reg<T, R2, 1>(u, tw, M / R2);
+      for (int t = 0; t < R2; ++t) u[t] = ex[cb2 * XL + t * (R1 + 1) + sb];
+      dft_reg<T, R2, 1>(u);
       const int ay = ky < M ? (ky <= M / 2 ? ky : M - ky) : 0;
       const T* srow = sp + ay * Mh;
 #pragma unroll
       for (int k2 = 0; k2 < R2; ++k2) {
-        int kz = s + R1 * k2;
-        T g = srow[kz <= M / 2 ? kz : M - kz];
-        u[k2] = {u[k2].x * g, u[k2].y * g};
+        int kz = sb + R1 * k2;
+        T gk = srow[kz <= M / 2 ? kz : M - kz];
+        u[k2] = {u[k2].x * gk, u[k2].y * gk};
       }
-      dft_reg<T, R2, -1>(u, tw, M / R2);
+      dft_reg<T, R2, -1>(u);
 #pragma unroll
       for (int t = 1; t < R2; ++t)
-        if (s) u[t] = cmul(u[t], conjw(tw[t * s]));
+        if (sb) u[t] = cmul(u[t], conjw(tw[t * sb]));
     }
-    __syncthreads();
-    if (act) {
+    wave_sync();
+    if (actB) {
 #pragma unroll
-      for (int t = 0; t < R2; ++t) Ex[c2 * XL + s * (R2 + 1) + t] = u[t];
+      for (int t = 0; t < R2; ++t) ex[cb2 * XL + sb * (R2 + 1) + t] = u[t];
     }
-    __syncthreads();
-    if (tid < CB * R2) {
-      const int c = tid % CB, t = tid / CB, ky = cb + c;
+    wave_sync();
+    if (actA) {
+      const int ky = c0 + ca;
       cplx<T> v[R1];
 #pragma unroll
-      for (int s1 = 0; s1 < R1; ++s1) v[s1] = Ex[c * XL + s1 * (R2 + 1) + t];
-      dft_reg<T, R1, -1>(v, tw, M / R1);
+      for (int s1 = 0; s1 < R1; ++s1) v[s1] = ex[ca * XL + s1 * (R2 + 1) + ta];
+      dft_reg<T, R1, -1>(v);
       if (ky < M) {
 #pragma unroll
         for (int j1 = 0; j1 < R1; ++j1) {
-          int zi = zmap[t + R2 * j1];
+          int zi = zmap[ta + R2 * j1];
           if (zi >= 0) zout[int64_t(zi) * Mh * M + ky] = v[j1];
         }
       }
     }
-    __syncthreads();
+    wave_sync();
   }
 }
+
 
 struct OutGeom {
   int n, e, da, b, Wa, Wp, Wc, P0, npl;
@@ -256,6 +267,10 @@ __global__ void __launch_bounds__((OutBatch<T, M>::NT)) conv_out_kernel(const cp
   // the x coordinates of skeleton planes
   __shared__ short frow[WPMAX], crow[WPMAX];
   __shared__ int nfull, ncols;
+  // per torus slot of the x axis: x + d_alpha if inside Omega_alpha, the
+  // coarse index (x + e)/4 if a coarse node, the plane index if a skeleton
+  // plane (each -1 otherwise), packed as three 16-bit fields
+  __shared__ uint64_t xinfo[M];
   // inverse twiddles of the skeleton-plane x coordinates: Wx[j][k] = w^(k x_j)
   constexpr int NPLMAX = 4;
   __shared__ cplx<T> Wx[NPLMAX * (M / 2)];
@@ -297,6 +312,17 @@ __global__ void __launch_bounds__((OutBatch<T, M>::NT)) conv_out_kernel(const cp
     oflg[k] = (ina ? 1 : 0) | (mod_pos(y, NREF) == 0 ? 2 : 0) | ((ina && mod_pos(y, n) == 0) ? 4 : 0);
   }
   __syncthreads();
+  for (int m = tid; m < M; m += blockDim.x) {
+    const int xi = omap[m];
+    int xda = -1, xcc = -1, xpl = -1;
+    if (xi >= 0) {
+      const int x = ocrd[xi], xf = oflg[xi];
+      if (xf & 1) xda = x + g.da;
+      if (xf & 2) xcc = (x + g.e) / NREF;
+      if (xf & 4) xpl = (x - g.P0) / n;
+    }
+    xinfo[m] = uint64_t(uint16_t(xda)) | (uint64_t(uint16_t(xcc)) << 16) | (uint64_t(uint16_t(xpl)) << 32);
+  }
   for (int t = tid; t < g.npl * (M / 2); t += blockDim.x) {
     const int j = t / (M / 2), k = t % (M / 2);
     const int x = g.P0 + j * n, xs = x < 0 ? x + M : x;
@@ -330,7 +356,7 @@ __global__ void __launch_bounds__((OutBatch<T, M>::NT)) conv_out_kernel(const cp
     cplx<T> v[R1];
 #pragma unroll
     for (int s = 0; s < R1; ++s) v[s] = ex[r * XL + s * (R2 + 1) + t];
-    dft_reg<T, R1, -1>(v, tw, M / R1);
+    dft_reg<T, R1, -1>(v);
     if (kx < Mh) {
 #pragma unroll
       for (int j1 = 0; j1 < R1; ++j1) {
@@ -341,7 +367,7 @@ __global__ void __launch_bounds__((OutBatch<T, M>::NT)) conv_out_kernel(const cp
   };
   // y pass, first half: R2-point DFT of one line's column s, twiddled, to ex
   auto y_pass1 = [&](cplx<T>* u, cplx<T>* ex, int s, int r) {
-    dft_reg<T, R2, -1>(u, tw, M / R2);
+    dft_reg<T, R2, -1>(u);
 #pragma unroll
     for (int t = 0; t < R2; ++t) {
       cplx<T> w = (s && t) ? cmul(u[t], conjw(tw[t * s])) : u[t];
@@ -409,41 +435,49 @@ __global__ void __launch_bounds__((OutBatch<T, M>::NT)) conv_out_kernel(const cp
       if (k == 0 || k == M / 2) { h1.y = T(0); h2.y = T(0); }   // real DC / Nyquist
       u[k2] = {h1.x - h2.y, h1.y + h2.x};                        // h1 + i h2
     }
-    dft_reg<T, R2, -1>(u, tw, M / R2);
+    dft_reg<T, R2, -1>(u);
 #pragma unroll
     for (int t = 0; t < R2; ++t) {
       cplx<T> w = (s && t) ? cmul(u[t], conjw(tw[t * s])) : u[t];
       ex[c * XL + s * (R2 + 1) + t] = w;
     }
   };
-  // second half: outputs of pair-line c (global pair index pi)
+  // second half: outputs of pair-line c (global pair index pi).  Per row,
+  // the base offsets of its destinations (or -1); per x slot, its offsets
+  // along the row (xinfo) -- so each output is a few adds and stores.
   auto x_pass2 = [&](const cplx<T>* ex, int t, int c, int pi) {
     cplx<T> v[R1];
 #pragma unroll
     for (int s = 0; s < R1; ++s) v[s] = ex[c * XL + s * (R2 + 1) + t];
-    dft_reg<T, R1, -1>(v, tw, M / R1);
+    dft_reg<T, R1, -1>(v);
+    int rowC[2], rowZ[2], rowY[2], rowX[2];
 #pragma unroll
-    for (int j1 = 0; j1 < R1; ++j1) {
-      int xi = omap[t + R2 * j1];
-      if (xi < 0) continue;
-      const int x = ocrd[xi], xf = oflg[xi];
-#pragma unroll
-      for (int h = 0; h < 2; ++h) {
-        const int fi = 2 * pi + h;
-        if (fi >= nf) continue;
+    for (int h = 0; h < 2; ++h) {
+      rowC[h] = rowZ[h] = rowY[h] = rowX[h] = -1;
+      const int fi = 2 * pi + h;
+      if (fi < nf) {
         const int yi = frow[fi];
         const int y = ocrd[yi], yf = oflg[yi];
-        T val = T(double(h ? v[j1].y : v[j1].x) * hsq);
-        if (zc && (xf & 2) && (yf & 2))
-          cbase[(int64_t((z + g.e) / NREF) * Wc + (y + g.e) / NREF) * Wc + (x + g.e) / NREF] = val;
-        if (zpl && (yf & 1) && (xf & 1))
-          pbase[((int64_t(0) * npl + (z - g.P0) / n) * Wa + (y + g.da)) * Wa + (x + g.da)] = val;
-        if (zin_a && (yf & 1) && (xf & 1)) {
-          if (yf & 4)
-            pbase[((int64_t(1) * npl + (y - g.P0) / n) * Wa + (z + g.da)) * Wa + (x + g.da)] = val;
-          if (xf & 4)
-            pbase[((int64_t(2) * npl + (x - g.P0) / n) * Wa + (z + g.da)) * Wa + (y + g.da)] = val;
+        if (zc && (yf & 2)) rowC[h] = (((z + g.e) / NREF) * Wc + (y + g.e) / NREF) * Wc;
+        if (zpl && (yf & 1)) rowZ[h] = ((z - g.P0) / n * Wa + (y + g.da)) * Wa;
+        if (zin_a && (yf & 1) && (yf & 4)) rowY[h] = ((npl + (y - g.P0) / n) * Wa + (z + g.da)) * Wa;
+        if (zin_a && (yf & 1)) rowX[h] = (2 * npl * Wa + (z + g.da)) * Wa + (y + g.da);
+      }
+    }
+#pragma unroll
+    for (int j1 = 0; j1 < R1; ++j1) {
+      const uint64_t xw = xinfo[t + R2 * j1];
+      const int xda = int(short(xw & 0xffff)), xcc = int(short((xw >> 16) & 0xffff));
+      const int xpl = int(short((xw >> 32) & 0xffff));
+#pragma unroll
+      for (int h = 0; h < 2; ++h) {
+        const T val = T(double(h ? v[j1].y : v[j1].x) * hsq);
+        if (rowC[h] >= 0 && xcc >= 0) cbase[rowC[h] + xcc] = val;
+        if (xda >= 0) {
+          if (rowZ[h] >= 0) pbase[rowZ[h] + xda] = val;
+          if (rowY[h] >= 0) pbase[rowY[h] + xda] = val;
         }
+        if (rowX[h] >= 0 && xpl >= 0) pbase[rowX[h] + xpl * Wa * Wa] = val;
       }
     }
   };

@@ -10,6 +10,8 @@
 // the first inverse pass all happen in the same registers, with one LDS
 // exchange per direction.
 #pragma once
+#include <utility>
+
 #include "fft.h"
 
 namespace mlc {
@@ -18,10 +20,128 @@ constexpr int first_factor(int R) {
   return (R % 4 == 0 && R != 4) ? 4 : (R % 5 == 0 ? 5 : (R % 3 == 0 ? 3 : 2));
 }
 
+// Compile-time twiddles w_R^m = exp(-2 pi i m / R): the angle is reduced to
+// a quadrant k and a remainder psi in [0, pi/2) with integer arithmetic, and
+// cos / sin of psi (or of pi/2 - psi, whichever is <= pi/4) are summed from
+// their Taylor series, which converge to double precision well within 12
+// terms there.
+constexpr double ce_pi = 3.141592653589793;
+// nested (Horner) form, innermost term first
+constexpr double ce_sin_series(double x) {
+  const double x2 = x * x;
+  double s = 1.0;
+  for (int k = 12; k >= 1; --k) s = 1.0 - x2 / double((2 * k) * (2 * k + 1)) * s;
+  return x * s;
+}
+constexpr double ce_cos_series(double x) {
+  const double x2 = x * x;
+  double s = 1.0;
+  for (int k = 12; k >= 1; --k) s = 1.0 - x2 / double((2 * k - 1) * (2 * k)) * s;
+  return s;
+}
+struct CosSin { double c, s; };
+constexpr CosSin ce_cossin_2pi(int m, int R) {   // cos, sin of 2 pi m / R
+  const int q = (4 * (m % R) + 4 * R) % (4 * R);  // angle in quarter turns, times R
+  const int k = q / R, rem = q % R;               // angle = (k + rem / R) pi / 2
+  double c0, s0;
+  if (2 * rem <= R) {
+    const double psi = (ce_pi / 2) * double(rem) / double(R);
+    c0 = ce_cos_series(psi);
+    s0 = ce_sin_series(psi);
+  } else {
+    const double phi = (ce_pi / 2) * double(R - rem) / double(R);
+    c0 = ce_sin_series(phi);
+    s0 = ce_cos_series(phi);
+  }
+  switch (k) {
+    case 0: return {c0, s0};
+    case 1: return {-s0, c0};
+    case 2: return {-c0, -s0};
+    default: return {s0, -c0};
+  }
+}
+template <int R> struct TwiddleTable {
+  double c[R], s[R];   // w_R^m = c[m] - i s[m]
+  constexpr TwiddleTable() : c(), s() {
+    for (int m = 0; m < R; ++m) {
+      const CosSin cs = ce_cossin_2pi(m, R);
+      c[m] = cs.c;
+      s[m] = cs.s;
+    }
+  }
+};
+template <int R> inline constexpr TwiddleTable<R> kTwiddle{};
+
+// w_R^m (forward, DIR > 0) or its conjugate (inverse), as constants
+template <typename T, int R, int DIR, int MM>
+__device__ __forceinline__ cplx<T> twc() {
+  constexpr int m = MM % R;
+  constexpr double c = kTwiddle<R>.c[m], sn = kTwiddle<R>.s[m];
+  return {T(c), T(DIR > 0 ? -sn : sn)};
+}
+
+// v * w_R^m with the trivial angles (multiples of a quarter turn) exact
+template <typename T, int R, int DIR, int MM>
+__device__ __forceinline__ cplx<T> twmul(cplx<T> a) {
+  constexpr int m = MM % R;
+  if constexpr (m == 0) {
+    return a;
+  } else if constexpr (4 * m == R) {
+    return rot90<T, DIR>(a);
+  } else if constexpr (2 * m == R) {
+    return {-a.x, -a.y};
+  } else if constexpr (4 * m == 3 * R) {
+    return rot90<T, -DIR>(a);
+  } else {
+    return cmul(a, twc<T, R, DIR, m>());
+  }
+}
+
+namespace detail {
+template <typename T, int R, int DIR, int A, int B, int J2, int K1>
+__device__ __forceinline__ void first_stage_entry(const cplx<T>* a, cplx<T>* tmp) {
+  tmp[J2 * A + K1] = twmul<T, R, DIR, J2 * K1>(a[K1]);
+}
+template <typename T, int R, int DIR, int A, int B, int J2, int... K1s>
+__device__ __forceinline__ void first_stage_row(const cplx<T>* a, cplx<T>* tmp, std::integer_sequence<int, K1s...>) {
+  (first_stage_entry<T, R, DIR, A, B, J2, K1s>(a, tmp), ...);
+}
+}  // namespace detail
+
 // In-place DFT of R values in registers, natural order in and out.
-// tw[m * step] must be w_R^m = exp(-2 pi i m / R) (forward convention).
 template <typename T, int R, int DIR>
-__device__ __forceinline__ void dft_reg(cplx<T>* v, const cplx<T>* tw, int step) {
+__device__ __forceinline__ void dft_reg(cplx<T>* v);
+
+namespace detail {
+template <typename T, int R, int DIR, int A, int B, int J2>
+__device__ __forceinline__ void dft_first(cplx<T>* v, cplx<T>* tmp) {
+  cplx<T> a[A];
+#pragma unroll
+  for (int j1 = 0; j1 < A; ++j1) a[j1] = v[J2 + B * j1];
+  dft_small<T, A, DIR>(a);
+  first_stage_row<T, R, DIR, A, B, J2>(a, tmp, std::make_integer_sequence<int, A>{});
+}
+template <typename T, int R, int DIR, int A, int B, int... J2s>
+__device__ __forceinline__ void dft_first_all(cplx<T>* v, cplx<T>* tmp, std::integer_sequence<int, J2s...>) {
+  (dft_first<T, R, DIR, A, B, J2s>(v, tmp), ...);
+}
+// pruned first stage: only v[J2] (J2 < NZ) nonzero, one input per first-stage DFT
+template <typename T, int R, int DIR, int A, int B, int NZ, int J2, int... K1s>
+__device__ __forceinline__ void first_nz_row(const cplx<T>* v, cplx<T>* tmp, std::integer_sequence<int, K1s...>) {
+  if constexpr (J2 < NZ) {
+    ((tmp[J2 * A + K1s] = twmul<T, R, DIR, J2 * K1s>(v[J2])), ...);
+  } else {
+    ((tmp[J2 * A + K1s] = cplx<T>{T(0), T(0)}), ...);
+  }
+}
+template <typename T, int R, int DIR, int A, int B, int NZ, int... J2s>
+__device__ __forceinline__ void first_nz_all(const cplx<T>* v, cplx<T>* tmp, std::integer_sequence<int, J2s...>) {
+  (first_nz_row<T, R, DIR, A, B, NZ, J2s>(v, tmp, std::make_integer_sequence<int, A>{}), ...);
+}
+}  // namespace detail
+
+template <typename T, int R, int DIR>
+__device__ __forceinline__ void dft_reg(cplx<T>* v) {
   if constexpr (R == 1) {
     return;
   } else if constexpr (R == 2 || R == 3 || R == 4 || R == 5) {
@@ -29,29 +149,13 @@ __device__ __forceinline__ void dft_reg(cplx<T>* v, const cplx<T>* tw, int step)
   } else {
     constexpr int A = first_factor(R), B = R / A;
     cplx<T> tmp[R];
-#pragma unroll
-    for (int j2 = 0; j2 < B; ++j2) {
-      cplx<T> a[A];
-#pragma unroll
-      for (int j1 = 0; j1 < A; ++j1) a[j1] = v[j2 + B * j1];
-      dft_small<T, A, DIR>(a);
-#pragma unroll
-      for (int k1 = 0; k1 < A; ++k1) {
-        if (j2 * k1 == 0) {
-          tmp[j2 * A + k1] = a[k1];
-        } else {
-          cplx<T> w = tw[((j2 * k1) % R) * step];
-          if constexpr (DIR < 0) w.y = -w.y;
-          tmp[j2 * A + k1] = cmul(a[k1], w);
-        }
-      }
-    }
+    detail::dft_first_all<T, R, DIR, A, B>(v, tmp, std::make_integer_sequence<int, B>{});
 #pragma unroll
     for (int k1 = 0; k1 < A; ++k1) {
       cplx<T> bb[B];
 #pragma unroll
       for (int j2 = 0; j2 < B; ++j2) bb[j2] = tmp[j2 * A + k1];
-      dft_reg<T, B, DIR>(bb, tw, step * A);
+      dft_reg<T, B, DIR>(bb);
 #pragma unroll
       for (int k2 = 0; k2 < B; ++k2) v[k1 + A * k2] = bb[k2];
     }
@@ -63,32 +167,19 @@ __device__ __forceinline__ void dft_reg(cplx<T>* v, const cplx<T>* tw, int step)
 // v[j2 + B j1] each see one input (j1 = 0), so they reduce to the twiddle
 // products, and the second-stage DFTs again have NZ leading inputs.
 template <typename T, int R, int DIR, int NZ>
-__device__ __forceinline__ void dft_reg_nz(cplx<T>* v, const cplx<T>* tw, int step) {
+__device__ __forceinline__ void dft_reg_nz(cplx<T>* v) {
   constexpr int A = first_factor(R), B = R / A;
   if constexpr (NZ >= R || R <= 5 || NZ > B) {
-    dft_reg<T, R, DIR>(v, tw, step);
+    dft_reg<T, R, DIR>(v);
   } else {
     cplx<T> tmp[R];
-#pragma unroll
-    for (int j2 = 0; j2 < B; ++j2)
-#pragma unroll
-      for (int k1 = 0; k1 < A; ++k1) {
-        if (j2 >= NZ) {
-          tmp[j2 * A + k1] = {T(0), T(0)};
-        } else if (j2 * k1 == 0) {
-          tmp[j2 * A + k1] = v[j2];
-        } else {
-          cplx<T> w = tw[((j2 * k1) % R) * step];
-          if constexpr (DIR < 0) w.y = -w.y;
-          tmp[j2 * A + k1] = cmul(v[j2], w);
-        }
-      }
+    detail::first_nz_all<T, R, DIR, A, B, NZ>(v, tmp, std::make_integer_sequence<int, B>{});
 #pragma unroll
     for (int k1 = 0; k1 < A; ++k1) {
       cplx<T> bb[B];
 #pragma unroll
       for (int j2 = 0; j2 < B; ++j2) bb[j2] = tmp[j2 * A + k1];
-      dft_reg_nz<T, B, DIR, NZ>(bb, tw, step * A);
+      dft_reg_nz<T, B, DIR, NZ>(bb);
 #pragma unroll
       for (int k2 = 0; k2 < B; ++k2) v[k1 + A * k2] = bb[k2];
     }
