@@ -179,6 +179,13 @@ __global__ void __launch_bounds__(256) conv_yz_kernel(const cplx<T>* __restrict_
   const int ca = lane % LC, ta = lane / LC;     // R1-point passes: R2 lanes per column (columns fastest)
   const int sb = lane % R1, cb2 = lane / R1;    // R2-point passes: R1 lanes per column
   const bool actA = lane < LC * R2, actB = lane < LC * R1;
+  __syncthreads();   // zmap
+  int zoff[R1];      // the lane's output rows: zi * Mh * M, or -1
+#pragma unroll
+  for (int j1 = 0; j1 < R1; ++j1) {
+    const int zi = zmap[ta + R2 * j1];
+    zoff[j1] = zi >= 0 ? zi * Mh * M : -1;
+  }
 #pragma unroll 1
   for (int c0 = wave * LC; c0 < M; c0 += (blockDim.x / 64) * LC) {
     if (actA) {
@@ -227,11 +234,10 @@ __global__ void __launch_bounds__(256) conv_yz_kernel(const cplx<T>* __restrict_
       for (int s1 = 0; s1 < R1; ++s1) v[s1] = ex[ca * XL + s1 * (R2 + 1) + ta];
       dft_reg<T, R1, -1>(v);
       if (ky < M) {
+        cplx<T>* col = zout + ky;
 #pragma unroll
-        for (int j1 = 0; j1 < R1; ++j1) {
-          int zi = zmap[ta + R2 * j1];
-          if (zi >= 0) zout[int64_t(zi) * Mh * M + ky] = v[j1];
-        }
+        for (int j1 = 0; j1 < R1; ++j1)
+          if (zoff[j1] >= 0) col[zoff[j1]] = v[j1];
       }
     }
     wave_sync();
@@ -352,17 +358,17 @@ __global__ void __launch_bounds__((OutBatch<T, M>::NT)) conv_out_kernel(const cp
   }
   // y pass, second half: one line's R1-point DFT in R2 lanes (lanes (t, r)),
   // kept outputs into A
-  auto y_pass2 = [&](const cplx<T>* ex, int t, int r, int kx) {
+  // (ymap[j1] = omap[t + R2 j1], the lane's output slots, held in registers)
+  auto y_pass2 = [&](const cplx<T>* ex, int t, int r, int kx, const short* ymap) {
     cplx<T> v[R1];
 #pragma unroll
     for (int s = 0; s < R1; ++s) v[s] = ex[r * XL + s * (R2 + 1) + t];
     dft_reg<T, R1, -1>(v);
     if (kx < Mh) {
+      cplx<T>* arow = A + kx * Wp;
 #pragma unroll
-      for (int j1 = 0; j1 < R1; ++j1) {
-        int yi = omap[t + R2 * j1];
-        if (yi >= 0) A[kx * Wp + yi] = v[j1];
-      }
+      for (int j1 = 0; j1 < R1; ++j1)
+        if (ymap[j1] >= 0) arow[ymap[j1]] = v[j1];
     }
   };
   // y pass, first half: R2-point DFT of one line's column s, twiddled, to ex
@@ -378,13 +384,16 @@ __global__ void __launch_bounds__((OutBatch<T, M>::NT)) conv_out_kernel(const cp
   // ---- inverse FFT along y for every kx ----
   if constexpr (WAVE) {
     cplx<T>* ex = Ex + wave * LW * XL;
+    short ymap[R1];
+#pragma unroll
+    for (int j1 = 0; j1 < R1; ++j1) ymap[j1] = omap[t2 + R2 * j1];
 #pragma unroll 1
     for (int kb = wave * LW; kb < Mh; kb += NW * LW) {
       cplx<T> un[R2];
       load_lines(un, kb + NW * LW);   // next step's lines in flight meanwhile
       if (act1) y_pass1(u0, ex, s1, r1);
       wave_sync();
-      if (act2) y_pass2(ex, t2, r2, kb + r2);
+      if (act2) y_pass2(ex, t2, r2, kb + r2, ymap);
       wave_sync();
 #pragma unroll
       for (int k2 = 0; k2 < R2; ++k2) u0[k2] = un[k2];
@@ -404,7 +413,12 @@ __global__ void __launch_bounds__((OutBatch<T, M>::NT)) conv_out_kernel(const cp
         y_pass1(u, Ex, s, r);
       }
       __syncthreads();
-      if (tid < CB * R2) y_pass2(Ex, tid % R2, tid / R2, kb + tid / R2);
+      if (tid < CB * R2) {
+        short ymap[R1];
+#pragma unroll
+        for (int j1 = 0; j1 < R1; ++j1) ymap[j1] = omap[tid % R2 + R2 * j1];
+        y_pass2(Ex, tid % R2, tid / R2, kb + tid / R2, ymap);
+      }
       __syncthreads();
     }
   }
