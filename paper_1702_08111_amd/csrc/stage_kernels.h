@@ -533,6 +533,14 @@ struct DirGeom {
   Stencil st;
 };
 
+// Orders one wave's LDS writes before its later LDS reads by other lanes
+// (the wave's LDS operations execute in order; this fences the compiler).
+__device__ __forceinline__ void wave_sync_lds() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
 // D = A B for 32 x 32 row-major LDS matrices of stride 33 (one wave).  D may
 // be A or B: every input is read before the first output is written.
 __device__ __forceinline__ void mm32(const double* A, const double* B, double* D, int lane) {
@@ -606,23 +614,44 @@ __global__ void __launch_bounds__(256) dirichlet_mfma_kernel(const ProbDesc* __r
     double v = 0.0;
     if (live && i < m && jc < m) {
       if constexpr (PASS == 0) {
-        const int l0 = u + 1, l1 = i + 1, l2 = jc + 1;
-        v = h2 * f[pbase + (l0 * Np + l1) * Np + l2];
-        if (l0 == 1 || l0 == g.n - 1 || l1 == 1 || l1 == g.n - 1 || l2 == 1 || l2 == g.n - 1) {
-          for (int s0 = -1; s0 <= 1; ++s0)
-            for (int s1 = -1; s1 <= 1; ++s1)
-              for (int s2 = -1; s2 <= 1; ++s2) {
-                int k0 = l0 + s0, k1 = l1 + s1, k2 = l2 + s2;
-                if (!(k0 == 0 || k0 == g.n || k1 == 0 || k1 == g.n || k2 == 0 || k2 == g.n)) continue;
-                int nz = (s0 != 0) + (s1 != 0) + (s2 != 0);
-                v -= g.st.b[nz] * phiB[pbase + (k0 * Np + k1) * Np + k2];
-              }
-        }
+        v = h2 * f[pbase + (int64_t(u + 1) * Np + (i + 1)) * Np + (jc + 1)];
       } else {
         v = wp[off(i, jc)];
       }
     }
     L[i * 33 + jc] = v;
+  }
+  if constexpr (PASS == 0) {
+    // boundary terms, only at nodes next to the patch boundary: the whole
+    // slab if it is the first or last, else its ring of 4(m-1) nodes
+    wave_sync_lds();
+    const bool end_slab = u == 0 || u == m - 1;
+    const int cnt = live ? (end_slab ? m * m : 4 * (m - 1)) : 0;
+    for (int q = lane; q < cnt; q += 64) {
+      int i, j;
+      if (end_slab) {
+        i = q / m;
+        j = q % m;
+      } else if (q < 2 * m) {
+        i = q < m ? 0 : m - 1;
+        j = q % m;
+      } else {
+        const int r = q - 2 * m;
+        i = 1 + r / 2;
+        j = (r & 1) ? m - 1 : 0;
+      }
+      const int l0 = u + 1, l1 = i + 1, l2 = j + 1;
+      double corr = 0.0;
+      for (int s0 = -1; s0 <= 1; ++s0)
+        for (int s1 = -1; s1 <= 1; ++s1)
+          for (int s2 = -1; s2 <= 1; ++s2) {
+            int k0 = l0 + s0, k1 = l1 + s1, k2 = l2 + s2;
+            if (!(k0 == 0 || k0 == g.n || k1 == 0 || k1 == g.n || k2 == 0 || k2 == g.n)) continue;
+            int nz = (s0 != 0) + (s1 != 0) + (s2 != 0);
+            corr += g.st.b[nz] * phiB[pbase + (int64_t(k0) * Np + k1) * Np + k2];
+          }
+      L[i * 33 + j] -= corr;
+    }
   }
   __syncthreads();
   if constexpr (PASS == 1) {
