@@ -123,9 +123,12 @@ def _cpu_baseline(name, budget, cores):
     N, n, Q, bumps = mi.workload(name)
     f = mi.bump_charge(N, bumps)
     prm = om.Params(N=N, n=n, alpha=3.0, beta=6.0, P=4, Q=Q, Z=128)
+    progress("CPU oracle: DGF table (plan time, not timed)")
     G1 = dgf(Q, 128)
+    progress("CPU oracle: far-field tables (plan time, not timed)")
     Phi, T, Phi_lo, _ = om.far_field_tables(G1, prm)
     tabs = om._annulus_plane_tables(Phi, Phi_lo, prm)
+    progress(f"CPU oracle: per-patch work for up to {budget:.0f} s")
     patches = om.patch_indices(N, n)
     order = np.random.default_rng(0).permutation(len(patches))
     S_lo, S_hi, O_lo, O_hi = om.coarse_boxes(prm)
@@ -149,6 +152,7 @@ def _cpu_baseline(name, budget, cores):
         om._accumulate_annulus(accum, c, tabs, lo, prm)
         done += 1
     t_patch = (time.perf_counter() - t0) / done
+    progress(f"CPU oracle: {done} patches sampled; coarse solve and Dirichlet solves")
     t1 = time.perf_counter()
     phiH = prm.H ** 2 * oconv.conv_hockney(G1, prm.Z, FH, np.full(3, O_lo - S_lo), np.full(3, O_hi - S_lo))
     phiB = accum + om._interp_coarse_everywhere(phiH, O_lo, prm)
@@ -164,6 +168,10 @@ def _cpu_baseline(name, budget, cores):
                    f"({t_patch:.3f} s/patch) + global coarse solve/interpolation/Dirichlet "
                    f"({t_global:.1f} s); full solve estimated {est:.1f} s"),
     }
+
+
+def progress(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
 def batch_bench(ctx, steps, dev):
@@ -337,8 +345,11 @@ def main():
             plan.set_timing(False)
         return (t1 - t0) * 1e3 / steps, lat, kt
 
+    progress(f"plans built; timing {args.steps} float32-convolution solves")
     ms32, lat32, kt32 = timed(p32, phi32, args.steps, args.warmup, True)
+    progress(f"float32 {ms32:.3f} ms/solve; timing {args.fp64_steps} float64 solves")
     ms64, lat64, _ = timed(p64, phi64, args.fp64_steps, 1, False)
+    progress(f"float64 {ms64:.3f} ms/solve")
     a32, a64 = phi32.cpu().numpy(), phi64.cpu().numpy()
     scale = np.abs(a64).max()
     err_32_64 = float(np.abs(a32 - a64).max() / scale)
@@ -375,11 +386,16 @@ def main():
         dst.copy_(src)
         torch.cuda.synchronize()
 
+    if args.batch_steps > 0:
+        progress("uneven 64-problem batch")
     batch = batch_bench(ctx, args.batch_steps, dev) if args.batch_steps > 0 else None
+    if args.serve_requests > 0:
+        progress("serving loop")
     serving = serving_bench(ctx, args.serve_requests, args.serve_load, dev) if args.serve_requests > 0 else None
 
     cpu = None
     if not args.no_cpu_baseline:
+        progress("CPU oracle baseline")
         cpu = cpu_baseline(args.workload, args.cpu_budget)
 
     value = N ** 3 / (ms32 * 1e-3)
@@ -394,7 +410,9 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f32 local convolutions, f64 elsewhere",
+        "dtype": "f32",
+        "dtype_detail": "f32 local convolutions (the dominant kernels); f64 moments, far fields, coarse solve, "
+                        "boundary values, Dirichlet solves",
         "data": "synthetic",
         "config": {"workload": f"two-level MLC, {N}^3 cells, {n}^3-cell patches ({N // n}^3 = "
                                f"{(N // n) ** 3}), L{19 if Q == 4 else 27} (Q={Q}), alpha=3, beta=6, P=4, "

@@ -112,3 +112,13 @@ def test_fft_size_autotune_flag():
     with pytest.raises(mlc.MLCError) as ei:
         mlc.problem_info(mlc.problem(64, 16, 3.0, 6.0, 4, 4, fft_size=-2))
     assert ei.value.status == mlc.MLC_ERR_INVALID_ARG
+
+
+def test_binding_fails_loudly_without_library(monkeypatch, tmp_path):
+    """No CPU fallback: without the built library every call raises."""
+    monkeypatch.setattr(mlc, "LIB_PATH", str(tmp_path / "missing.so"))
+    monkeypatch.setattr(mlc, "_lib", None)
+    with pytest.raises(RuntimeError):
+        mlc.problem_info(mlc.problem(32, 8))
+    with pytest.raises(RuntimeError):
+        mlc.Context(0)

@@ -45,6 +45,11 @@ def _case(name):
         "mlc0_32": (32, 8, 3.0, 3.0, 4, 4, 0, 64, mi.bumps(2, 8, radius=(0.15, 0.25))),
         "p1_32": (32, 8, 3.0, 6.0, 1, 4, 0, 64, mi.bumps(3, 9, radius=(0.1, 0.2))),
         "ragged48": (48, 16, 3.0, 6.0, 4, 4, 90, 128, mi.bumps(2, 11, radius=(0.12, 0.2))),
+        # one patch: every neighbour lattice is empty, the skeleton is the box surface
+        "single16": (16, 16, 3.0, 6.0, 4, 4, 0, 128, mi.bumps(2, 12, radius=(0.15, 0.3))),
+        # 4 and 10 Legendre modes (moment slices of 4 padded with zeros)
+        "p2_32": (32, 8, 3.0, 6.0, 2, 4, 0, 64, mi.bumps(2, 13, radius=(0.1, 0.25))),
+        "p3_32": (32, 8, 3.0, 6.0, 3, 4, 0, 64, mi.bumps(2, 14, radius=(0.1, 0.25))),
     }
     return cases[name]
 
@@ -75,15 +80,35 @@ def _check_all(name, conv):
     return errs
 
 
-@pytest.mark.parametrize("name", ["plain32", "plain32_q6", "mlc0_32", "p1_32", "ragged48"])
+@pytest.mark.parametrize("name", ["plain32", "plain32_q6", "mlc0_32", "p1_32", "ragged48", "single16", "p2_32",
+                                  "p3_32"])
 def test_fp64_parity(name):
     errs = _check_all(name, "fp64")
     for k, v in errs.items():
         assert v < TOL64, (k, v)
 
 
-@pytest.mark.parametrize("name", ["plain32", "plain32_q6", "ragged48"])
+@pytest.mark.parametrize("name", ["plain32", "plain32_q6", "mlc0_32", "p1_32", "ragged48", "single16"])
 def test_fp32_parity(name):
     errs = _check_all(name, "fp32")
     assert errs["phi"] < TOL32, errs
     assert errs["moments"] < TOL64
+
+
+@pytest.mark.parametrize("conv", ["fp64", "fp32"])
+def test_zero_charge_gives_zero(conv):
+    """Degenerate input: f = 0 gives phi = 0 exactly (every stage is linear)."""
+    f = np.zeros((33, 33, 33))
+    g = gpu_solve(gm.problem(32, 8, 3.0, 6.0, 4, 4, conv=conv, Z=64), f, keep=False)
+    assert np.array_equal(g["phi"], np.zeros_like(f))
+
+
+def test_linearity():
+    """phi(2 f1 - 3 f2) = 2 phi(f1) - 3 phi(f2) to rounding (float64 path)."""
+    prob = gm.problem(48, 16, 3.0, 6.0, 4, 4, conv="fp64")
+    f1 = mi.bump_charge(48, mi.bumps(2, 31))
+    f2 = mi.bump_charge(48, mi.bumps(3, 32))
+    p1 = gpu_solve(prob, f1, keep=False)["phi"]
+    p2 = gpu_solve(prob, f2, keep=False)["phi"]
+    p3 = gpu_solve(prob, 2 * f1 - 3 * f2, keep=False)["phi"]
+    assert rel(p3, 2 * p1 - 3 * p2) < 1e-13
