@@ -570,7 +570,7 @@ static Layout layout_of(const std::vector<const mlc_plan_info*>& g) {
     if (g[k]->d_beta > g[k]->d_alpha) {
       MfmaGeom gs, gc;
       annulus_geoms(*g[k], &gs, &gc);
-      bytes = sizeof(double) * cube(gs.L) * gs.KP;
+      bytes = 2 * sizeof(double) * cube(gs.L) * gs.KP;   // slot-major and mode-major copies
     }
     L.o_cpad[k] = take(bytes);
   }
@@ -888,8 +888,14 @@ static void launch_rest(const Group& G, hipStream_t s) {
                          cs + L.patch0[k] * csz, st, cg, F_of(k));
     }
   }
-  auto cpad_of = [&](int k) { return reinterpret_cast<double*>(G.ws + L.o_cpad[k]); };
-  constexpr int ANN_COLS = 16 * ANN_TILES;
+  // padded moment lattices: slot-major (skeleton sums), then mode-major (coarse sums)
+  auto cpad_s = [&](int k) { return reinterpret_cast<double*>(G.ws + L.o_cpad[k]); };
+  auto cpad_p = [&](int k) {
+    const MfmaGeom& g = G.plans[k]->mg_coarse;
+    return reinterpret_cast<double*>(G.ws + L.o_cpad[k]) + cube(g.L) * g.KP;
+  };
+  constexpr int SK_COLS = ann_block_cols<SkelTiling>(), SK_ROWS = ann_block_rows<SkelTiling>();
+  constexpr int CO_COLS = ann_block_cols<CoarseTiling>(), CO_ROWS = ann_block_rows<CoarseTiling>();
   if (P0->Kann > 0) {
     TimedScope ts(P0, s, "coarse_annulus");
     const int q = I0.n / NREF;
@@ -899,10 +905,10 @@ static void launch_rest(const Group& G, hipStream_t s) {
       const MfmaGeom& g = P->mg_coarse;
       // moments into the zero-padded lattice both far-field sums read
       hipLaunchKernelGGL(pad_moments_kernel, dim3(blocks_for(cube(g.L) * g.KP)), dim3(256), 0, s,
-                         mom + int64_t(L.patch0[k]) * I.K, cpad_of(k), g.ppa, g.K, g.KP, g.L, g.padlo);
+                         mom + int64_t(L.patch0[k]) * I.K, cpad_s(k), cpad_p(k), g.ppa, g.K, g.KP, g.L, g.padlo);
       const int nk = g.nk0 * g.nk1 * g.nk2;
-      hipLaunchKernelGGL(coarse_annulus_mfma_kernel, dim3(g.nrp / 64, (nk + ANN_COLS - 1) / ANN_COLS), dim3(256), 0,
-                         s, P->Tm, cpad_of(k), g, q, I.S_lo, I.Ns, F_of(k));
+      hipLaunchKernelGGL(coarse_annulus_mfma_kernel, dim3(g.nrp / CO_ROWS, (nk + CO_COLS - 1) / CO_COLS),
+                         dim3(64 * CoarseTiling::WAVES), 0, s, P->Tm, cpad_p(k), g, q, I.S_lo, I.Ns, F_of(k));
     }
   }
   // coarse solves, the FFTs batched over problems of equal coarse torus
@@ -948,8 +954,8 @@ static void launch_rest(const Group& G, hipStream_t s) {
       const mlc_plan_info& I = P->info;
       const MfmaGeom& g = P->mg_skel;
       const int nk = g.nk0 * g.nk1 * g.nk2;
-      hipLaunchKernelGGL(skeleton_annulus_mfma_kernel, dim3(g.nrp / 64, (nk + ANN_COLS - 1) / ANN_COLS, 3), dim3(256),
-                         0, s, P->Am, cpad_of(k), g, I.n, I.N, phiB_of(k));
+      hipLaunchKernelGGL(skeleton_annulus_mfma_kernel, dim3(g.nrp / SK_ROWS, (nk + SK_COLS - 1) / SK_COLS, 3),
+                         dim3(64 * SkelTiling::WAVES), 0, s, P->Am, cpad_s(k), g, I.n, I.N, phiB_of(k));
     }
   }
   {

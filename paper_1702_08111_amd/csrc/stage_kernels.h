@@ -234,9 +234,12 @@ struct SkelGeom {
 // column (k) l%16, row p = l/16; accumulator lane l, register j holds
 // out[4 j + l/16][l%16].
 //
-// The moments are first copied into a zero-padded lattice Cpad[L^3][KP]
-// (patch i at slot i + padlo per axis), so that c[k - E] is one address
-// shifted by a uniform per-offset amount: no bounds tests in the inner loop.
+// The moments are first copied into a zero-padded lattice (patch i at slot
+// i + padlo per axis), so that c[k - E] is one address shifted by a uniform
+// per-offset amount: no bounds tests in the inner loop.  Two layouts, each
+// faster for one of the contractions: slot-major Cpad[L^3][KP] and
+// mode-major Cpad[KP][L^3] (a tile's 16 consecutive columns of one mode are
+// one contiguous run).
 typedef double f64x4 __attribute__((ext_vector_type(4)));
 
 struct MfmaGeom {
@@ -248,18 +251,19 @@ struct MfmaGeom {
   int L, padlo;              // padded moment lattice
 };
 
-// Cpad[slot][p], slot = ((i0 + padlo) L + i1 + padlo) L + i2 + padlo.
-__global__ void pad_moments_kernel(const double* __restrict__ mom, double* __restrict__ Cpad, int ppa, int K,
-                                   int KP, int L, int padlo) {
+// Cs[slot][p] and Cp[p][slot], slot = ((i0 + padlo) L + i1 + padlo) L + i2 + padlo.
+__global__ void pad_moments_kernel(const double* __restrict__ mom, double* __restrict__ Cs, double* __restrict__ Cp,
+                                   int ppa, int K, int KP, int L, int padlo) {
   int64_t idx = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
   if (idx >= cube(L) * KP) return;
-  const int p = int(idx % KP);
-  const int64_t slot = idx / KP;
+  const int p = int(idx / cube(L));
+  const int64_t slot = idx % cube(L);
   const int a2 = int(slot % L) - padlo, a1 = int((slot / L) % L) - padlo, a0 = int(slot / (int64_t(L) * L)) - padlo;
   double v = 0.0;
   if (p < K && a0 >= 0 && a0 < ppa && a1 >= 0 && a1 < ppa && a2 >= 0 && a2 < ppa)
     v = mom[(int64_t(a0 * ppa + a1) * ppa + a2) * K + p];
-  Cpad[idx] = v;
+  Cp[idx] = v;
+  Cs[slot * KP + p] = v;
 }
 
 // A rows for the skeleton: r = ra * n + rb over the face plane of normal d;
@@ -318,13 +322,22 @@ __global__ void coarse_mfma_table_kernel(const double* __restrict__ Tt, double* 
   Tm[idx] = ok ? Tt[((int64_t(c[0]) * Wbc + c[1]) * Wbc + c[2]) * K + p] : 0.0;
 }
 
-// Columns of one wave: ANN_TILES tiles of 16 consecutive lattice points.
-constexpr int ANN_TILES = 8;
+// Two tilings, chosen per contraction by measurement:
+//   skeleton: a block is 4 waves on 4 consecutive 16-row tiles, each wave
+//     over the block's 8 column tiles (128 lattice points);
+//   coarse grid: a block is 8 waves on the same 16 rows (the streamed table
+//     fragments are shared through the CU's L1), each wave over its own 4
+//     column tiles.
+struct SkelTiling { static constexpr int TILES = 8, WAVES = 4; static constexpr bool SHARE_ROWS = false; };
+struct CoarseTiling { static constexpr int TILES = 4, WAVES = 8; static constexpr bool SHARE_ROWS = true; };
+// lattice points and rows covered by one block
+template <class TL> constexpr int ann_block_cols() { return TL::SHARE_ROWS ? 16 * TL::TILES * TL::WAVES : 16 * TL::TILES; }
+template <class TL> constexpr int ann_block_rows() { return TL::SHARE_ROWS ? 16 : 16 * TL::WAVES; }
 
-// One wave: 16 rows x 16*ANN_TILES lattice points; a block of four waves
-// covers 64 rows.  `d` selects the skeleton orientation, or is -1 for the
+// One wave: 16 rows x 16*ANN_TILES lattice points.  `d` selects the skeleton orientation, or is -1 for the
 // coarse grid.  Offsets whose patches all fall outside the lattice for the
 // wave's box of columns are skipped (a uniform test).
+template <int ANN_TILES, bool PMAJOR>
 __device__ __forceinline__ void annulus_mfma_tiles(const double* __restrict__ Am, const double* __restrict__ Cpad,
                                                    const MfmaGeom& mg, int d, int rowbase, int kbase,
                                                    f64x4 (&acc)[ANN_TILES]) {
@@ -343,7 +356,8 @@ __device__ __forceinline__ void annulus_mfma_tiles(const double* __restrict__ Am
   for (int t = 0; t < ANN_TILES; ++t) {
     const int k = min(kbase + 16 * t + rl, nk - 1);
     const int a = mg.k0lo + k / n12, b = mg.k1lo + (k / mg.nk2) % mg.nk1, c = mg.k2lo + k % mg.nk2;
-    boff[t] = int64_t((a + pad) * st0 + (b + pad) * st1 + (c + pad) * st2) * mg.KP + pj;
+    const int64_t slot = (a + pad) * st0 + (b + pad) * st1 + (c + pad) * st2;
+    boff[t] = PMAJOR ? slot + int64_t(pj) * L * L * L : slot * mg.KP + pj;
     acc[t] = f64x4{0.0, 0.0, 0.0, 0.0};
   }
   // lattice box of the wave's columns
@@ -370,13 +384,14 @@ __device__ __forceinline__ void annulus_mfma_tiles(const double* __restrict__ Am
       for (int e2 = 0; e2 < mg.ne; ++e2) {
         const int E2 = mg.elo + e2;
         if (c_hi - E2 < 0 || c_lo - E2 > ppa - 1) continue;
-        const int64_t off = int64_t(E0 * st0 + E1 * st1 + E2 * st2) * mg.KP;
+        const int64_t off = int64_t(E0 * st0 + E1 * st1 + E2 * st2) * (PMAJOR ? 1 : mg.KP);
         const double* Ae = Ad + ((int64_t(e0) * mg.ne + e1) * mg.ne + e2) * npc * mg.nrp * 4;
         for (int pc = 0; pc < npc; ++pc) {
           const double a = Ae[int64_t(pc) * mg.nrp * 4];
+          const double* Cp = Cpad + (PMAJOR ? int64_t(4 * pc) * L * L * L : int64_t(4 * pc)) - off;
 #pragma unroll
           for (int t = 0; t < ANN_TILES; ++t) {
-            const double b = Cpad[boff[t] - off + 4 * pc];
+            const double b = Cp[boff[t]];
             acc[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc[t], 0, 0, 0);
           }
         }
@@ -388,15 +403,17 @@ __device__ __forceinline__ void annulus_mfma_tiles(const double* __restrict__ Am
 // Skeleton: rows r = ra * n + rb of the face plane of normal d = blockIdx.z,
 // columns k = (kd, ka, kb) in [0, ppa]^3; writes the far field into phiB at
 // every canonical skeleton node.
-__global__ void __launch_bounds__(256) skeleton_annulus_mfma_kernel(const double* __restrict__ Am,
-                                                                    const double* __restrict__ Cpad, MfmaGeom mg,
-                                                                    int n, int N, double* __restrict__ phiB) {
+__global__ void __launch_bounds__(64 * SkelTiling::WAVES) skeleton_annulus_mfma_kernel(const double* __restrict__ Am,
+                                                                                     const double* __restrict__ Cpad,
+                                                                                     MfmaGeom mg, int n, int N,
+                                                                                     double* __restrict__ phiB) {
+  constexpr int ANN_TILES = SkelTiling::TILES;
   const int d = blockIdx.z;
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int rowbase = blockIdx.x * 64 + wave * 16;
   const int kbase = blockIdx.y * 16 * ANN_TILES;
   f64x4 acc[ANN_TILES];
-  annulus_mfma_tiles(Am, Cpad, mg, d, rowbase, kbase, acc);
+  annulus_mfma_tiles<ANN_TILES, false>(Am, Cpad, mg, d, rowbase, kbase, acc);
   const int a0 = d == 0 ? 1 : 0, a1 = d == 2 ? 1 : 2, Np = N + 1;
   const int nk = mg.nk0 * mg.nk1 * mg.nk2;
 #pragma unroll
@@ -422,14 +439,16 @@ __global__ void __launch_bounds__(256) skeleton_annulus_mfma_kernel(const double
 
 // Coarse grid: rows rho in [0, q)^3, columns k over the lattice box; adds the
 // far field to F[c = q k + rho] inside the support box.
-__global__ void __launch_bounds__(256) coarse_annulus_mfma_kernel(const double* __restrict__ Tm,
-                                                                  const double* __restrict__ Cpad, MfmaGeom mg,
-                                                                  int q, int S_lo, int Ns, double* __restrict__ F) {
+__global__ void __launch_bounds__(64 * CoarseTiling::WAVES) coarse_annulus_mfma_kernel(const double* __restrict__ Tm,
+                                                                                      const double* __restrict__ Cpad,
+                                                                                      MfmaGeom mg, int q, int S_lo,
+                                                                                      int Ns, double* __restrict__ F) {
+  constexpr int ANN_TILES = CoarseTiling::TILES, ANN_WAVES = CoarseTiling::WAVES;
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  const int rowbase = blockIdx.x * 64 + wave * 16;
-  const int kbase = blockIdx.y * 16 * ANN_TILES;
+  const int rowbase = blockIdx.x * 16;
+  const int kbase = (blockIdx.y * ANN_WAVES + wave) * 16 * ANN_TILES;
   f64x4 acc[ANN_TILES];
-  annulus_mfma_tiles(Tm, Cpad, mg, -1, rowbase, kbase, acc);
+  annulus_mfma_tiles<ANN_TILES, true>(Tm, Cpad, mg, -1, rowbase, kbase, acc);
   const int nk = mg.nk0 * mg.nk1 * mg.nk2;
 #pragma unroll
   for (int t = 0; t < ANN_TILES; ++t) {
