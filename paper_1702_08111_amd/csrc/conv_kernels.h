@@ -70,6 +70,10 @@ template <typename T, int M> struct Batch {
   static constexpr int LC = 64 / RMAX;   // columns per wave step (conv_yz column phase)
   // odd padded line stride of the exchange buffer
   static constexpr int XL = (XLayout<M>::LINE % 2) ? XLayout<M>::LINE : XLayout<M>::LINE + 1;
+  // conv_yz: line stride = 8 (mod 32) complex elements, so that the four
+  // columns of a wave step land on disjoint LDS bank sets in its widest
+  // exchange (the forward pass writes)
+  static constexpr int XLYZ = XLayout<M>::LINE + ((8 - XLayout<M>::LINE % 32) + 32) % 32;
 };
 // conv_out holds the whole (kx, y) plane in LDS, so one block fills a CU.
 // fp32: 512 threads, each wave transforms its own lines (LW per step)
@@ -101,7 +105,7 @@ __global__ void __launch_bounds__(256) conv_yz_kernel(const cplx<T>* __restrict_
   constexpr int Mh = M / 2 + 1;
   constexpr int S = n + 1;
   constexpr int R1 = Split<M>::R1, R2 = Split<M>::R2;
-  constexpr int CB = Batch<T, M>::CB, XL = Batch<T, M>::XL;
+  constexpr int CB = Batch<T, M>::CB, XL = Batch<T, M>::XLYZ;
   // source rows after the y FFT; row stride M + 4 keeps the column reads of
   // one wave on distinct LDS banks
   constexpr int YS = M + 4;
