@@ -328,8 +328,8 @@ __global__ void coarse_mfma_table_kernel(const double* __restrict__ Tt, double* 
 //   coarse grid: a block is 8 waves on the same 16 rows (the streamed table
 //     fragments are shared through the CU's L1), each wave over its own 4
 //     column tiles.
-struct SkelTiling { static constexpr int TILES = 4, WAVES = 4; static constexpr bool SHARE_ROWS = false; };
-struct CoarseTiling { static constexpr int TILES = 4, WAVES = 8; static constexpr bool SHARE_ROWS = true; };
+struct SkelTiling { static constexpr int TILES = 2, WAVES = 4; static constexpr bool SHARE_ROWS = false; };
+struct CoarseTiling { static constexpr int TILES = 2, WAVES = 8; static constexpr bool SHARE_ROWS = true; };
 // lattice points and rows covered by one block
 template <class TL> constexpr int ann_block_cols() { return TL::SHARE_ROWS ? 16 * TL::TILES * TL::WAVES : 16 * TL::TILES; }
 template <class TL> constexpr int ann_block_rows() { return TL::SHARE_ROWS ? 16 : 16 * TL::WAVES; }
