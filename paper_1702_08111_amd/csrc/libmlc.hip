@@ -294,8 +294,8 @@ static void fft3_impl(cplx<double>* data, int dir, hipStream_t s) {
   constexpr int NL = (M % 4 == 0) ? 4 : 2;
   dim3 grid(M / NL, M);
   for (int axis = 0; axis < 3; ++axis) {
-    if (dir > 0) hipLaunchKernelGGL((fft_axis_kernel<double, M, NL, 1>), grid, dim3(256), 0, s, data, axis);
-    else hipLaunchKernelGGL((fft_axis_kernel<double, M, NL, -1>), grid, dim3(256), 0, s, data, axis);
+    if (dir > 0) hipLaunchKernelGGL((fft_axis_kernel<double, M, NL, 1>), grid, dim3(256), 0, s, data, axis, 0, 0, M);
+    else hipLaunchKernelGGL((fft_axis_kernel<double, M, NL, -1>), grid, dim3(256), 0, s, data, axis, 0, 0, M);
   }
 }
 static bool fft3(cplx<double>* data, int M, int dir, hipStream_t s) {
@@ -776,18 +776,30 @@ struct Group {
   ProbDesc* desc = nullptr;
 };
 
+// Coarse Hockney transforms of a batch of nb tori.  Forward: the source
+// occupies slots [0, ns)^3, so the axis-2 pass skips lines outside
+// [0, ns)^2 and the axis-1 pass slabs k0 >= ns (all zero).  Inverse: only
+// slots (o0 + [0, no)) mod M of each axis are read afterwards, so the axis-1
+// pass is limited to those k0 and the axis-2 pass to those (k0, k1).
 template <int M>
-static void fft3_batch_impl(cplx<double>* data, int dir, int nb, hipStream_t s) {
+static void fft3_coarse_impl(cplx<double>* data, int dir, int nb, int ns, int o0, int no, hipStream_t s) {
   constexpr int NL = (M % 4 == 0) ? 4 : 2;
-  dim3 grid(M / NL, M, nb);
-  for (int axis = 0; axis < 3; ++axis) {
-    if (dir > 0) hipLaunchKernelGGL((fft_axis_kernel<double, M, NL, 1>), grid, dim3(256), 0, s, data, axis);
-    else hipLaunchKernelGGL((fft_axis_kernel<double, M, NL, -1>), grid, dim3(256), 0, s, data, axis);
+  auto blocks = [](int cnt) { return unsigned((cnt + NL - 1) / NL); };
+  if (dir > 0) {
+    hipLaunchKernelGGL((fft_axis_kernel<double, M, NL, 1>), dim3(blocks(ns), ns, nb), dim3(256), 0, s, data, 2, 0, 0, ns);
+    hipLaunchKernelGGL((fft_axis_kernel<double, M, NL, 1>), dim3(blocks(M), ns, nb), dim3(256), 0, s, data, 1, 0, 0, M);
+    hipLaunchKernelGGL((fft_axis_kernel<double, M, NL, 1>), dim3(blocks(M), M, nb), dim3(256), 0, s, data, 0, 0, 0, M);
+  } else {
+    hipLaunchKernelGGL((fft_axis_kernel<double, M, NL, -1>), dim3(blocks(M), M, nb), dim3(256), 0, s, data, 0, 0, 0, M);
+    hipLaunchKernelGGL((fft_axis_kernel<double, M, NL, -1>), dim3(blocks(M), no, nb), dim3(256), 0, s, data, 1, o0, 0,
+                       M);
+    hipLaunchKernelGGL((fft_axis_kernel<double, M, NL, -1>), dim3(blocks(no), no, nb), dim3(256), 0, s, data, 2, o0, o0,
+                       no);
   }
 }
-static bool fft3_batch(cplx<double>* data, int M, int dir, int nb, hipStream_t s) {
+static bool fft3_coarse(cplx<double>* data, int M, int dir, int nb, int ns, int o0, int no, hipStream_t s) {
   switch (M) {
-#define CASE(MM) case MM: fft3_batch_impl<MM>(data, dir, nb, s); return true;
+#define CASE(MM) case MM: fft3_coarse_impl<MM>(data, dir, nb, ns, o0, no, s); return true;
     MLC_FFT_SIZES(CASE)
 #undef CASE
   }
@@ -926,10 +938,30 @@ static void launch_rest(const Group& G, hipStream_t s) {
       int nb = 0;
       for (int j = k; j < np; ++j)
         if (!done[j] && G.plans[j]->info.M_coarse == Mc) { done[j] = 1; ++nb; }
-      fft3_batch(tor_of(k), Mc, 1, nb, s);
+      // every torus of the bucket has M_coarse = Mc; their source and output
+      // boxes differ with N, so the pruning uses the bucket's largest
+      int ns = 0, no = 0, o0 = 0;
+      for (int j = k; j < np; ++j) {
+        const mlc_plan_info& Ij = G.plans[j]->info;
+        if (Ij.M_coarse != Mc) continue;
+        ns = std::max(ns, Ij.Ns);
+      }
+      {
+        // output slots (O_lo - S_lo + [0, No)) mod Mc; O_lo - S_lo and No grow with N
+        int lo = Mc, hi = 0;
+        for (int j = k; j < np; ++j) {
+          const mlc_plan_info& Ij = G.plans[j]->info;
+          if (Ij.M_coarse != Mc) continue;
+          lo = std::min(lo, Ij.O_lo - Ij.S_lo);
+          hi = std::max(hi, Ij.O_lo - Ij.S_lo + Ij.No);
+        }
+        o0 = lo;
+        no = std::min(hi - lo, Mc);
+      }
+      fft3_coarse(tor_of(k), Mc, 1, nb, ns, o0, no, s);
       hipLaunchKernelGGL(mul_real_even_kernel, dim3(blocks_for(cube(Mc)), nb), dim3(256), 0, s, tor_of(k),
                          G.plans[k]->coarse_spec, Mc);
-      fft3_batch(tor_of(k), Mc, -1, nb, s);
+      fft3_coarse(tor_of(k), Mc, -1, nb, ns, o0, no, s);
     }
     for (int k = 0; k < np; ++k) {
       const mlc_plan_info& I = G.plans[k]->info;

@@ -105,9 +105,11 @@ __global__ void dgf_restrict_kernel(const double* u, double* table, int L, int Z
 // ------------------------------------------------- generic axis FFT ----
 // Complex M^3 array, transform along `axis`.  NL lines per block; lines
 // adjacent along the fastest other axis; blockIdx.z: array of a batch of
-// consecutive M^3 arrays.
+// consecutive M^3 arrays.  Only the lines (u, v) with u = uoff + blockIdx.y
+// and v = voff + j, j < vcount (both taken mod M) are transformed: callers
+// skip lines known to be zero on input or not needed on output.
 template <typename T, int M, int NL, int DIR>
-__global__ void __launch_bounds__(256) fft_axis_kernel(cplx<T>* data, int axis) {
+__global__ void __launch_bounds__(256) fft_axis_kernel(cplx<T>* data, int axis, int uoff, int voff, int vcount) {
   __shared__ cplx<T> buf[NL * M];
   __shared__ cplx<T> tw[M];
   fill_twiddles(tw, M);
@@ -115,19 +117,21 @@ __global__ void __launch_bounds__(256) fft_axis_kernel(cplx<T>* data, int axis) 
   const int64_t es = axis == 2 ? 1 : (axis == 1 ? M : int64_t(M) * M);
   const int64_t vs = axis == 2 ? M : 1;
   const int64_t us = axis == 0 ? M : int64_t(M) * M;
-  const int v0 = blockIdx.x * NL;
-  const int u = blockIdx.y;
+  const int j0 = blockIdx.x * NL;
+  const int u = (uoff + int(blockIdx.y)) % M;
   for (int t = threadIdx.x; t < NL * M; t += blockDim.x) {
     int r, m;
     if (axis == 2) { r = t / M; m = t % M; } else { r = t % NL; m = t / NL; }
-    buf[r * M + m] = data[u * us + (v0 + r) * vs + m * es];
+    const int v = (voff + j0 + r) % M;
+    buf[r * M + m] = j0 + r < vcount ? data[u * us + v * vs + m * es] : cplx<T>{T(0), T(0)};
   }
   __syncthreads();
   fft_lines<T, M, NL, 256, DIR, false>(buf, M, 1, tw);
   for (int t = threadIdx.x; t < NL * M; t += blockDim.x) {
     int r, m;
     if (axis == 2) { r = t / M; m = t % M; } else { r = t % NL; m = t / NL; }
-    data[u * us + (v0 + r) * vs + m * es] = buf[r * M + m];
+    const int v = (voff + j0 + r) % M;
+    if (j0 + r < vcount) data[u * us + v * vs + m * es] = buf[r * M + m];
   }
 }
 

@@ -329,7 +329,7 @@ __global__ void coarse_mfma_table_kernel(const double* __restrict__ Tt, double* 
 //     fragments are shared through the CU's L1), each wave over its own 4
 //     column tiles.
 struct SkelTiling { static constexpr int TILES = 2, WAVES = 4; static constexpr bool SHARE_ROWS = false; };
-struct CoarseTiling { static constexpr int TILES = 2, WAVES = 8; static constexpr bool SHARE_ROWS = true; };
+struct CoarseTiling { static constexpr int TILES = 1, WAVES = 8; static constexpr bool SHARE_ROWS = true; };
 // lattice points and rows covered by one block
 template <class TL> constexpr int ann_block_cols() { return TL::SHARE_ROWS ? 16 * TL::TILES * TL::WAVES : 16 * TL::TILES; }
 template <class TL> constexpr int ann_block_rows() { return TL::SHARE_ROWS ? 16 : 16 * TL::WAVES; }
