@@ -23,6 +23,28 @@ inline Stencil stencil_of(int Q) {
 
 __host__ __device__ inline int64_t cube(int64_t a) { return a * a * a; }
 
+// Orthonormal Legendre polynomial sqrt((2a+1)/2) P_a(t), a <= 3 (sec. 3).
+__host__ __device__ inline double qhat(int a, double t) {
+  switch (a) {
+    case 0: return 0.70710678118654752440;
+    case 1: return 1.22474487139158904910 * t;
+    case 2: return 1.58113883008418966600 * 0.5 * (3.0 * t * t - 1.0);
+    default: return 1.87082869338697069280 * 0.5 * (5.0 * t * t * t - 3.0 * t);
+  }
+}
+
+// Composite Boole weight of node j of [0, n] mapped to [-1, 1] (n % 4 == 0),
+// the quadrature of the moments (sec. 4.1, step 1).
+__host__ __device__ inline double boole_w(int j, int n) {
+  double base = 4.0 / (45.0 * n);   // (2 delta / 45), delta = 2/n
+  if (j == 0 || j == n) return 7.0 * base;
+  int r = j & 3;
+  return (r == 0 ? 14.0 : (r == 2 ? 12.0 : 32.0)) * base;
+}
+
+// Partial moment sums per patch z-plane: one per (a1, a2), a1, a2 <= 3.
+constexpr int PLANE_MOMENTS = 16;
+
 // Output-coordinate list of the local fields along one axis: b coarse nodes
 // below Omega_alpha, every node of Omega_alpha, b coarse nodes above.
 __host__ __device__ inline int out_coord(int i, int b, int Wa, int e, int da, int n) {

@@ -25,10 +25,14 @@ namespace mlc {
 
 template <typename T, int M>
 __global__ void __launch_bounds__(256) conv_xdft_kernel(const ProbDesc* __restrict__ pd, int nprob, int n,
-                                                        cplx<T>* __restrict__ X, int p0) {
+                                                        cplx<T>* __restrict__ X, double* __restrict__ mpart,
+                                                        int p0) {
   constexpr int Mh = M / 2 + 1;
   __shared__ T q[SMAX * SMAX];
   __shared__ cplx<T> tw[M];
+  __shared__ double fd[SMAX * SMAX];   // the plane of f as given (moment sums)
+  __shared__ double Bw[4][SMAX];       // Boole weight x qhat_a at each node
+  __shared__ double gx[4][SMAX];       // x-contracted moment sums per row
   const int S = n + 1;
   const int p = p0 + blockIdx.y, sz = blockIdx.x;
   const ProbDesc& D = pd[find_problem(pd, nprob, p)];
@@ -41,10 +45,23 @@ __global__ void __launch_bounds__(256) conv_xdft_kernel(const ProbDesc* __restri
   for (int t = threadIdx.x; t < S * S; t += blockDim.x) {
     int sy = t / S, sx = t % S;
     double c = cz * ((sy == 0 || sy == n) ? 0.5 : 1.0) * ((sx == 0 || sx == n) ? 0.5 : 1.0);
-    q[t] = T(c * fp[sy * Np + sx]);
+    const double v = fp[sy * Np + sx];
+    fd[t] = v;
+    q[t] = T(c * v);
+  }
+  for (int t = threadIdx.x; t < 4 * S; t += blockDim.x) {
+    int a = t / S, j = t % S;
+    Bw[a][j] = boole_w(j, n) * qhat(a, (j - 0.5 * n) / (0.5 * n));
   }
   fill_twiddles(tw, M);
   __syncthreads();
+  // Legendre moment sums of this plane (sec. 4.1, step 1), x axis first
+  if (int(threadIdx.x) < 4 * S) {
+    const int a = threadIdx.x / S, sy = threadIdx.x % S;
+    double acc = 0.0;
+    for (int sx = 0; sx < S; ++sx) acc += Bw[a][sx] * fd[sy * S + sx];
+    gx[a][sy] = acc;
+  }
   cplx<T>* out = X + (int64_t(p) * Mh * S + sz) * S;
   for (int o = threadIdx.x; o < Mh * S; o += blockDim.x) {
     int kx = o / S, sy = o % S;
@@ -59,6 +76,13 @@ __global__ void __launch_bounds__(256) conv_xdft_kernel(const ProbDesc* __restri
       if (idx >= M) idx -= M;
     }
     out[int64_t(kx) * S * S + sy] = {ar, ai};
+  }
+  __syncthreads();
+  if (threadIdx.x < PLANE_MOMENTS) {
+    const int a1 = threadIdx.x / 4, a2 = threadIdx.x % 4;
+    double acc = 0.0;
+    for (int sy = 0; sy < S; ++sy) acc += Bw[a1][sy] * gx[a2][sy];
+    mpart[(int64_t(p) * S + sz) * PLANE_MOMENTS + threadIdx.x] = acc;
   }
 }
 

@@ -512,12 +512,13 @@ static bool same_class(const mlc_plan* a, const mlc_plan* b) {
 }
 
 // Workspace of one class group, relative to the group's base:
-//   descriptors | per patch (all problems): moments, x-DFTs, one chunk of
+//   descriptors | per patch (all problems): moments, per-plane moment sums,
+//   x-DFTs, one chunk of
 //   z-transformed spectra, coarse samples, skeleton planes, Dirichlet work |
 //   per problem: F^H, coarse torus (consecutive within equal M_coarse),
 //   phi^H, phi^B.
 struct Layout {
-  size_t o_desc = 0, o_mom = 0, o_X = 0, o_Z = 0, o_cs = 0, o_pl = 0, o_dir = 0;
+  size_t o_desc = 0, o_mom = 0, o_mpart = 0, o_X = 0, o_Z = 0, o_cs = 0, o_pl = 0, o_dir = 0;
   std::vector<size_t> o_F, o_tor, o_phiH, o_phiB, o_cpad;
   std::vector<int> patch0;
   int total = 0, chunk = 0;
@@ -541,6 +542,7 @@ static Layout layout_of(const std::vector<const mlc_plan_info*>& g) {
   auto take = [&](size_t bytes) { size_t at = o; o = align_up(o + bytes); return at; };
   L.o_desc = take(sizeof(ProbDesc) * np);
   L.o_mom = take(sizeof(double) * T * I.K);
+  L.o_mpart = take(sizeof(double) * T * S * PLANE_MOMENTS);
   L.o_X = take(csz * T * Mh * S * S);
   // chunk so that one chunk's z-transformed spectra stay at most ~2 GB
   // (MLC_CONV_CHUNK overrides); smaller chunks measured no faster at 256^3
@@ -842,7 +844,7 @@ static void launch_conv(const Group& G, hipStream_t s) {
     TimedScope ts(P, s, "conv_xdft");
     for (int p0 = 0; p0 < L.total; p0 += kMaxGridY)
       hipLaunchKernelGGL((conv_xdft_kernel<T, M>), dim3(P->S, std::min(kMaxGridY, L.total - p0)), dim3(256), 0, s,
-                         G.desc, np, I.n, X, p0);
+                         G.desc, np, I.n, X, reinterpret_cast<double*>(G.ws + L.o_mpart), p0);
   }
   OutGeom g{I.n, I.e, I.d_alpha, I.b, I.Wa, P->Wp, I.Wc, P->P0, I.nplanes_a};
   // patches in chunks: the chunk's z-transformed spectra (Zb) stay small
@@ -1019,22 +1021,20 @@ static mlc_status enqueue_group(const Group& G, hipStream_t s) {
   const mlc_plan_info& I0 = P0->info;
   const int np = int(G.plans.size());
   upload_descs(G, s);
+  // the x-DFT pass of the local convolutions also leaves the per-plane
+  // moment sums, finished here before the coarse stages read the moments
+  const bool fp32 = I0.conv_precision == MLC_CONV_FP32;
+  const bool ok = fp32 ? dispatch_conv<float>(G, s) : dispatch_conv<double>(G, s);
+  if (!ok) return fail(P0->ctx, MLC_ERR_UNSUPPORTED, "local FFT size not built");
   {
     TimedScope ts(P0, s, "moments");
-    double* mom = reinterpret_cast<double*>(G.ws + G.L.o_mom);
-    for (int p0 = 0; p0 < G.L.total; p0 += kMaxGridY)
-      hipLaunchKernelGGL(moments_kernel, dim3(std::min(kMaxGridY, G.L.total - p0)), dim3(256), 0, s, G.desc, np,
-                         I0.n, P0->modes, mom, p0);
+    const int64_t work = int64_t(G.L.total) * I0.K;
+    hipLaunchKernelGGL(moments_finish_kernel, dim3(unsigned((work + 255) / 256)), dim3(256), 0, s, G.desc, np, I0.n,
+                       P0->modes, reinterpret_cast<const double*>(G.ws + G.L.o_mpart),
+                       reinterpret_cast<double*>(G.ws + G.L.o_mom), G.L.total);
   }
-  bool ok;
-  if (I0.conv_precision == MLC_CONV_FP32) {
-    ok = dispatch_conv<float>(G, s);
-    if (ok) launch_rest<float>(G, s);
-  } else {
-    ok = dispatch_conv<double>(G, s);
-    if (ok) launch_rest<double>(G, s);
-  }
-  if (!ok) return fail(P0->ctx, MLC_ERR_UNSUPPORTED, "local FFT size not built");
+  if (fp32) launch_rest<float>(G, s);
+  else launch_rest<double>(G, s);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return fail(P0->ctx, MLC_ERR_DEVICE, std::string("launch: ") + hipGetErrorString(e));
   return MLC_OK;

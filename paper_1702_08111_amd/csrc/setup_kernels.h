@@ -168,16 +168,6 @@ __global__ void spectrum_octant_kernel(const cplx<double>* full, T* spec, int M,
 }
 
 // ------------------------------------------------ far-field tables ----
-// Orthonormal Legendre polynomial sqrt((2a+1)/2) P_a(t), a <= 3.
-__host__ __device__ inline double qhat(int a, double t) {
-  switch (a) {
-    case 0: return 0.70710678118654752440;
-    case 1: return 1.22474487139158904910 * t;
-    case 2: return 1.58113883008418966600 * 0.5 * (3.0 * t * t - 1.0);
-    default: return 1.87082869338697069280 * 0.5 * (5.0 * t * t * t - 3.0 * t);
-  }
-}
-
 struct ModeList { int K; int p[KMAX][3]; };
 
 // chi_0 Q_p on the patch nodes [0, n]^3 placed at slots [0, n]^3 of a zeroed

@@ -12,68 +12,31 @@ namespace mlc {
 // c_{i,p} = R^{3/2} sum_j W_j f[j] qhat_p(t_j) / mu_p over the (n+1)^3 nodes of
 // the closed patch, W = tensor composite Boole weights on [-1, 1], and mu_p
 // the diagonal of the Boole Gram matrix (sec. 3 projection; sec. 4.1 step 1
-// quadrature).  For P <= 4 the Gram matrix is diagonal.
-__device__ inline double boole_w(int j, int n) {
-  double base = 4.0 / (45.0 * n);   // (2 delta / 45), delta = 2/n
-  if (j == 0 || j == n) return 7.0 * base;
-  int r = j & 3;
-  return (r == 0 ? 14.0 : (r == 2 ? 12.0 : 32.0)) * base;
-}
-
-__global__ void __launch_bounds__(256) moments_kernel(const ProbDesc* __restrict__ pd, int nprob, int n,
-                                                      ModeList modes, double* __restrict__ out, int p0) {
-  __shared__ double B[4][SMAXN];
-  __shared__ double mu1[4];
-  __shared__ double red[256];
-  const int S = n + 1;
-  const int p = p0 + blockIdx.x;
+// quadrature).  For P <= 4 the Gram matrix is diagonal.  The sums over the two
+// fastest axes are taken per z-plane by the x-DFT kernel of the local
+// convolutions (which loads every plane anyway): part[p][j0][4 a1 + a2] =
+// sum_{j1,j2} w_j1 qhat_a1 w_j2 qhat_a2 f.  This kernel contracts j0, one
+// thread per (patch, mode).
+__global__ void __launch_bounds__(256) moments_finish_kernel(const ProbDesc* __restrict__ pd, int nprob, int n,
+                                                             ModeList modes, const double* __restrict__ part,
+                                                             double* __restrict__ out, int total) {
+  const int64_t idx = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (idx >= int64_t(total) * modes.K) return;
+  const int p = int(idx / modes.K), k = int(idx % modes.K);
   const ProbDesc& D = pd[find_problem(pd, nprob, p)];
-  const double* f = D.f;
-  const int N = D.N, ppa = D.ppa, pl = p - D.patch0;
-  const double R15 = D.R15;
-  const int i0 = pl / (ppa * ppa), i1 = (pl / ppa) % ppa, i2 = pl % ppa;
-  for (int t = threadIdx.x; t < 4 * S; t += blockDim.x) {
-    int a = t / S, j = t % S;
-    double tt = (j - 0.5 * n) / (0.5 * n);
-    B[a][j] = boole_w(j, n) * qhat(a, tt);
+  const int a0 = modes.p[k][0], a1 = modes.p[k][1], a2 = modes.p[k][2];
+  const int S = n + 1;
+  const double* pp = part + int64_t(p) * S * PLANE_MOMENTS + 4 * a1 + a2;
+  double s = 0.0, mu0 = 0.0, mu1 = 0.0, mu2 = 0.0;
+  for (int j = 0; j < S; ++j) {
+    const double t = (j - 0.5 * n) / (0.5 * n), w = boole_w(j, n);
+    const double q0 = qhat(a0, t), q1 = qhat(a1, t), q2 = qhat(a2, t);
+    s += w * q0 * pp[j * PLANE_MOMENTS];
+    mu0 += w * q0 * q0;
+    mu1 += w * q1 * q1;
+    mu2 += w * q2 * q2;
   }
-  __syncthreads();
-  if (threadIdx.x < 4) {
-    int a = threadIdx.x;
-    double s = 0.0;
-    for (int j = 0; j < S; ++j) {
-      double tt = (j - 0.5 * n) / (0.5 * n);
-      s += B[a][j] * qhat(a, tt);
-    }
-    mu1[a] = s;
-  }
-  const int64_t Np = N + 1;
-  const double* fp = f + (int64_t(n) * i0) * Np * Np + int64_t(n) * i1 * Np + int64_t(n) * i2;
-  double acc[KMAX];
-  for (int k = 0; k < KMAX; ++k) acc[k] = 0.0;
-  for (int t = threadIdx.x; t < S * S * S; t += blockDim.x) {
-    int j2 = t % S, j1 = (t / S) % S, j0 = t / (S * S);
-    double v = fp[(j0 * Np + j1) * Np + j2];
-#pragma unroll
-    for (int k = 0; k < KMAX; ++k)
-      if (k < modes.K) acc[k] += v * B[modes.p[k][0]][j0] * B[modes.p[k][1]][j1] * B[modes.p[k][2]][j2];
-  }
-  __syncthreads();
-#pragma unroll
-  for (int k = 0; k < KMAX; ++k) {
-    if (k >= modes.K) break;
-    red[threadIdx.x] = acc[k];
-    __syncthreads();
-    for (int s = 128; s > 0; s >>= 1) {
-      if (threadIdx.x < s) red[threadIdx.x] += red[threadIdx.x + s];
-      __syncthreads();
-    }
-    if (threadIdx.x == 0) {
-      double mu = mu1[modes.p[k][0]] * mu1[modes.p[k][1]] * mu1[modes.p[k][2]];
-      out[int64_t(p) * modes.K + k] = R15 * red[0] / mu;
-    }
-    __syncthreads();
-  }
+  out[idx] = D.R15 * s / (mu0 * mu1 * mu2);
 }
 
 // ------------------------------------------------------- coarse rhs ----
