@@ -8,6 +8,7 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <functional>
 #include <map>
 #include <mutex>
 #include <new>
@@ -32,6 +33,11 @@ struct mlc_context {
   std::mutex build_mu;  // serialises plan and DGF builds (a server thread may build too)
   std::map<std::pair<int, int>, double*> dgf;   // (Q, Z) -> (2Z+1)^3 table
   std::map<std::vector<int>, int> tuned;          // autotuned local torus per patch-work class
+  // per caller stream: a second stream (default priority) for the stages
+  // that do not depend on the local convolutions, and the fork/join events
+  struct Side { hipStream_t stream = nullptr; hipEvent_t ev[3] = {nullptr, nullptr, nullptr}; };
+  std::mutex side_mu;
+  std::map<hipStream_t, Side> side;
 };
 
 struct mlc_plan {
@@ -281,6 +287,11 @@ extern "C" mlc_status mlc_context_create(int device, size_t hbm_budget_bytes, ml
 extern "C" mlc_status mlc_context_destroy(mlc_context* ctx) {
   if (!ctx) return MLC_ERR_INVALID_ARG;
   hipSetDevice(ctx->device);
+  for (auto& kv : ctx->side) {
+    hipStreamSynchronize(kv.second.stream);
+    hipStreamDestroy(kv.second.stream);
+    for (hipEvent_t e : kv.second.ev) hipEventDestroy(e);
+  }
   for (auto& kv : ctx->dgf) hipFree(kv.second);
   delete ctx;
   return MLC_OK;
@@ -830,8 +841,11 @@ static void upload_descs(const Group& G, hipStream_t s) {
   }
 }
 
+// phase 0: x-DFTs (and the per-plane moment sums); phase 1: the rest, in
+// patch chunks, calling after_yz (if set) once the first chunk's y/z pass
+// is enqueued
 template <typename T, int n, int M>
-static void launch_conv(const Group& G, hipStream_t s) {
+static void launch_conv(const Group& G, hipStream_t s, int phase, const std::function<void()>* after_yz) {
   const mlc_plan* P = G.plans[0];
   const mlc_plan_info& I = P->info;
   const Layout& L = G.L;
@@ -840,12 +854,13 @@ static void launch_conv(const Group& G, hipStream_t s) {
   cplx<T>* Zb = reinterpret_cast<cplx<T>*>(G.ws + L.o_Z);
   T* cs = reinterpret_cast<T*>(G.ws + L.o_cs);
   T* pl = reinterpret_cast<T*>(G.ws + L.o_pl);
-  {
+  if (phase == 0) {
     TimedScope ts(P, s, "conv_xdft");
     for (int p0 = 0; p0 < L.total; p0 += kMaxGridY)
       hipLaunchKernelGGL((conv_xdft_kernel<T, M>), dim3(P->S, std::min(kMaxGridY, L.total - p0)), dim3(256), 0, s,
                          G.desc, np, I.n, X, reinterpret_cast<double*>(G.ws + L.o_mpart), p0);
   }
+  if (phase == 0) return;
   OutGeom g{I.n, I.e, I.d_alpha, I.b, I.Wa, P->Wp, I.Wc, P->P0, I.nplanes_a};
   // patches in chunks: the chunk's z-transformed spectra (Zb) stay small
   // enough to be re-read from the last-level cache
@@ -856,6 +871,7 @@ static void launch_conv(const Group& G, hipStream_t s) {
       hipLaunchKernelGGL((conv_yz_kernel<T, n, M>), dim3(P->Mh, cnt), dim3(256), 0, s, X,
                          static_cast<const T*>(P->conv_spec), Zb, P->Wp, I.b, I.Wa, I.e, I.d_alpha, p0);
     }
+    if (p0 == 0 && after_yz) (*after_yz)();
     {
       TimedScope ts(P, s, "conv_out");
       hipLaunchKernelGGL((conv_out_kernel<T, n, M>), dim3(P->Wp, cnt), dim3(OutBatch<T, M>::NT), 0, s, Zb, cs,
@@ -865,17 +881,25 @@ static void launch_conv(const Group& G, hipStream_t s) {
 }
 
 template <typename T>
-static bool dispatch_conv(const Group& G, hipStream_t s) {
+static bool dispatch_conv(const Group& G, hipStream_t s, int phase,
+                          const std::function<void()>* after_yz = nullptr) {
   const int n = G.plans[0]->info.n, M = G.plans[0]->info.M;
-#define CASE(nn, MM) if (n == nn && M == MM) { launch_conv<T, nn, MM>(G, s); return true; }
+#define CASE(nn, MM) if (n == nn && M == MM) { launch_conv<T, nn, MM>(G, s, phase, after_yz); return true; }
   if constexpr (sizeof(T) == 4) { MLC_CONV_SIZES_F32(CASE) }
   else { MLC_CONV_SIZES_F64(CASE) }
 #undef CASE
   return false;
 }
 
+// Stages after the local convolutions' x-DFTs:
+//   FAR:    far-field sums (moments only) -- overlaps the convolutions
+//   COARSE: coarse right-hand side and coarse solve (coarse samples)
+//   PLANES: plane corrections delta_i (local fields on the planes)
+//   FINISH: skeleton boundary values, Dirichlet solves and correction
+enum Stage { FAR, COARSE, PLANES, FINISH };
+
 template <typename T>
-static void launch_rest(const Group& G, hipStream_t s) {
+static void launch_rest(const Group& G, hipStream_t s, Stage stage) {
   const mlc_plan* P0 = G.plans[0];
   const mlc_plan_info& I0 = P0->info;
   const Layout& L = G.L;
@@ -890,8 +914,14 @@ static void launch_rest(const Group& G, hipStream_t s) {
   auto phiH_of = [&](int k) { return reinterpret_cast<double*>(G.ws + L.o_phiH[k]); };
   auto phiB_of = [&](int k) { return reinterpret_cast<double*>(G.ws + L.o_phiB[k]); };
   const int64_t csz = cube(I0.Wc), plsz = int64_t(3) * I0.nplanes_a * I0.Wa * I0.Wa;
+  if (stage == FAR) {
+    // F^H starts at zero: the coarse far-field sums and the inner part add
+    for (int k = 0; k < np; ++k)
+      hipLaunchKernelGGL(fill_zero_kernel, dim3(blocks_for(cube(G.plans[k]->info.Ns))), dim3(256), 0, s, F_of(k),
+                         cube(G.plans[k]->info.Ns));
+  }
   // coarse right-hand side, per problem
-  {
+  if (stage == COARSE) {
     TimedScope ts(P0, s, "coarse_rhs");
     for (int k = 0; k < np; ++k) {
       const mlc_plan* P = G.plans[k];
@@ -910,7 +940,7 @@ static void launch_rest(const Group& G, hipStream_t s) {
   };
   constexpr int SK_COLS = ann_block_cols<SkelTiling>(), SK_ROWS = ann_block_rows<SkelTiling>();
   constexpr int CO_COLS = ann_block_cols<CoarseTiling>(), CO_ROWS = ann_block_rows<CoarseTiling>();
-  if (P0->Kann > 0) {
+  if (stage == FAR && P0->Kann > 0) {
     TimedScope ts(P0, s, "coarse_annulus");
     const int q = I0.n / NREF;
     for (int k = 0; k < np; ++k) {
@@ -926,7 +956,7 @@ static void launch_rest(const Group& G, hipStream_t s) {
     }
   }
   // coarse solves, the FFTs batched over problems of equal coarse torus
-  {
+  if (stage == COARSE) {
     TimedScope ts(P0, s, "coarse_solve");
     for (int k = 0; k < np; ++k) {
       const mlc_plan_info& I = G.plans[k]->info;
@@ -973,7 +1003,7 @@ static void launch_rest(const Group& G, hipStream_t s) {
     }
   }
   // local plane corrections delta_i = phi_i - I(phi_i), all patches
-  {
+  if (stage == PLANES) {
     TimedScope ts(P0, s, "plane_delta");
     PlaneGeom pg{I0.n, I0.e, I0.d_alpha, I0.Wa, I0.Wc, P0->P0, I0.nplanes_a, I0.b};
     for (int p0 = 0; p0 < L.total; p0 += kMaxGridY)
@@ -981,7 +1011,7 @@ static void launch_rest(const Group& G, hipStream_t s) {
                          0, s, pl, cs, pg, P0->lagw, p0);
   }
   // boundary values on the skeleton (+ phi there), per problem
-  if (P0->Kann > 0) {
+  if (stage == FAR && P0->Kann > 0) {
     TimedScope ts(P0, s, "skeleton_annulus");
     for (int k = 0; k < np; ++k) {
       const mlc_plan* P = G.plans[k];
@@ -992,7 +1022,7 @@ static void launch_rest(const Group& G, hipStream_t s) {
                          dim3(64 * SkelTiling::WAVES), 0, s, P->Am, cpad_s(k), g, I.n, I.N, phiB_of(k));
     }
   }
-  {
+  if (stage == FINISH) {
     TimedScope ts(P0, s, "skeleton");
     for (int k = 0; k < np; ++k) {
       const mlc_plan* P = G.plans[k];
@@ -1005,7 +1035,7 @@ static void launch_rest(const Group& G, hipStream_t s) {
     }
   }
   // Dirichlet solves + Mehrstellen correction on the patch interiors, all patches
-  {
+  if (stage == FINISH) {
     const int m = I0.n - 1;
     TimedScope ts(P0, s, "dirichlet");
     DirGeom dg{I0.n, L.total, 2.0 / I0.n, st};
@@ -1016,15 +1046,42 @@ static void launch_rest(const Group& G, hipStream_t s) {
   }
 }
 
+// The side stream of caller stream s (created on first use).
+static mlc_context::Side* side_of(mlc_context* ctx, hipStream_t s) {
+  std::lock_guard<std::mutex> lk(ctx->side_mu);
+  auto it = ctx->side.find(s);
+  if (it != ctx->side.end()) return &it->second;
+  mlc_context::Side sd;
+  if (hipStreamCreateWithFlags(&sd.stream, hipStreamNonBlocking) != hipSuccess) return nullptr;
+  for (hipEvent_t& e : sd.ev) {
+    if (hipEventCreateWithFlags(&e, hipEventDisableTiming) != hipSuccess) {
+      for (hipEvent_t x : sd.ev)
+        if (x) hipEventDestroy(x);
+      hipStreamDestroy(sd.stream);
+      return nullptr;
+    }
+  }
+  return &(ctx->side[s] = sd);
+}
+
+// Launch order on the caller stream s and its side stream:
+//   s:    descriptors, x-DFTs, moments, first chunk's y/z pass | fork |
+//         the other convolution passes | fork | plane corrections | join |
+//         skeleton, Dirichlet
+//   side: (after fork 1) far-field sums | (after fork 2) coarse rhs and solve
+// Every launch of one call has ended before the caller stream passes the
+// join, so consecutive calls on s may reuse the workspace.
 static mlc_status enqueue_group(const Group& G, hipStream_t s) {
   const mlc_plan* P0 = G.plans[0];
   const mlc_plan_info& I0 = P0->info;
   const int np = int(G.plans.size());
+  mlc_context::Side* sd = side_of(P0->ctx, s);
+  if (!sd) return fail(P0->ctx, MLC_ERR_DEVICE, "could not create the side stream");
+  const bool fp32 = I0.conv_precision == MLC_CONV_FP32;
   upload_descs(G, s);
   // the x-DFT pass of the local convolutions also leaves the per-plane
-  // moment sums, finished here before the coarse stages read the moments
-  const bool fp32 = I0.conv_precision == MLC_CONV_FP32;
-  const bool ok = fp32 ? dispatch_conv<float>(G, s) : dispatch_conv<double>(G, s);
+  // moment sums, finished here before the far-field sums read the moments
+  const bool ok = fp32 ? dispatch_conv<float>(G, s, 0) : dispatch_conv<double>(G, s, 0);
   if (!ok) return fail(P0->ctx, MLC_ERR_UNSUPPORTED, "local FFT size not built");
   {
     TimedScope ts(P0, s, "moments");
@@ -1033,9 +1090,33 @@ static mlc_status enqueue_group(const Group& G, hipStream_t s) {
                        P0->modes, reinterpret_cast<const double*>(G.ws + G.L.o_mpart),
                        reinterpret_cast<double*>(G.ws + G.L.o_mom), G.L.total);
   }
-  if (fp32) launch_rest<float>(G, s);
-  else launch_rest<double>(G, s);
-  hipError_t e = hipGetLastError();
+  // fork 1 after the first chunk's y/z pass: the far-field sums then share
+  // the chip with the output pass (one block per CU, LDS and registers to
+  // spare) rather than with the y/z pass (whose blocks fill the LDS)
+  hipError_t e = hipSuccess;
+  const std::function<void()> fork_far = [&]() {
+    e = hipEventRecord(sd->ev[0], s);
+    if (e == hipSuccess) e = hipStreamWaitEvent(sd->stream, sd->ev[0], 0);
+    if (e != hipSuccess) return;
+    if (fp32) launch_rest<float>(G, sd->stream, FAR);
+    else launch_rest<double>(G, sd->stream, FAR);
+  };
+  if (fp32) dispatch_conv<float>(G, s, 1, &fork_far);
+  else dispatch_conv<double>(G, s, 1, &fork_far);
+  if (e != hipSuccess) return fail(P0->ctx, MLC_ERR_DEVICE, std::string("fork: ") + hipGetErrorString(e));
+  e = hipEventRecord(sd->ev[1], s);
+  if (e == hipSuccess) e = hipStreamWaitEvent(sd->stream, sd->ev[1], 0);
+  if (e != hipSuccess) return fail(P0->ctx, MLC_ERR_DEVICE, std::string("fork: ") + hipGetErrorString(e));
+  if (fp32) launch_rest<float>(G, sd->stream, COARSE);
+  else launch_rest<double>(G, sd->stream, COARSE);
+  e = hipEventRecord(sd->ev[2], sd->stream);
+  if (fp32) launch_rest<float>(G, s, PLANES);
+  else launch_rest<double>(G, s, PLANES);
+  if (e == hipSuccess) e = hipStreamWaitEvent(s, sd->ev[2], 0);
+  if (e != hipSuccess) return fail(P0->ctx, MLC_ERR_DEVICE, std::string("join: ") + hipGetErrorString(e));
+  if (fp32) launch_rest<float>(G, s, FINISH);
+  else launch_rest<double>(G, s, FINISH);
+  e = hipGetLastError();
   if (e != hipSuccess) return fail(P0->ctx, MLC_ERR_DEVICE, std::string("launch: ") + hipGetErrorString(e));
   return MLC_OK;
 }
@@ -1161,9 +1242,12 @@ static double time_conv(mlc_context* ctx, const mlc_plan_info& I0, const double*
     G.desc = reinterpret_cast<ProbDesc*>(ws + L.o_desc);
     hipStream_t s = nullptr;
     upload_descs(G, s);
-    bool ok = dispatch_conv<T>(G, s);
+    bool ok = dispatch_conv<T>(G, s, 0) && dispatch_conv<T>(G, s, 1);
     hipEventRecord(a, s);
-    for (int r = 0; ok && r < 3; ++r) dispatch_conv<T>(G, s);
+    for (int r = 0; ok && r < 3; ++r) {
+      dispatch_conv<T>(G, s, 0);
+      dispatch_conv<T>(G, s, 1);
+    }
     hipEventRecord(b, s);
     float t = 0.f;
     if (ok && hipEventSynchronize(b) == hipSuccess && hipEventElapsedTime(&t, a, b) == hipSuccess) ms = t / 3.0;

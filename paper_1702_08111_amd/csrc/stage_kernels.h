@@ -45,7 +45,7 @@ struct CoarseGeom {
   double invH2;
 };
 
-// Inner part of F^H: F[c] = sum over patches i with c in C(Omega_alpha(i)) of
+// Inner part of F^H: F[c] += sum over patches i with c in C(Omega_alpha(i)) of
 // Delta^H of phi_i's coarse samples (sec. 4.1 eq. FDLD, first case), patches
 // visited in a fixed order.
 template <typename T>
@@ -83,7 +83,12 @@ __global__ void __launch_bounds__(256) coarse_rhs_kernel(const T* __restrict__ c
             }
         s += l * g.invH2;
       }
-  F[idx] = s;
+  F[idx] += s;   // F starts at zero; the far-field sums may add first
+}
+
+__global__ void fill_zero_kernel(double* __restrict__ p, int64_t count) {
+  const int64_t idx = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (idx < count) p[idx] = 0.0;
 }
 
 // Coarse Hockney solve: F^H on slots [0, Ns)^3 of a zeroed Mc^3 torus.
