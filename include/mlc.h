@@ -19,7 +19,11 @@
  *    the caller owns them and keeps them alive until the work enqueued on
  *    the given stream has completed.  "stream" is a hipStream_t (NULL = the
  *    default stream).  Work is enqueued asynchronously; no call synchronises
- *    the device except where stated.
+ *    the device except where stated.  A solve also runs some stages on a
+ *    second stream that the context creates for each caller stream (default
+ *    priority, kept until mlc_context_destroy); it forks from and joins back
+ *    into the caller stream with events, so when the caller stream passes a
+ *    solve, all of that solve's work has ended.
  *  - Arguments are validated before anything is enqueued; on an error
  *    nothing is written to any output.
  *  - A context is used from one host thread at a time; plans are immutable
@@ -165,7 +169,9 @@ mlc_status mlc_dgf_table(mlc_context* ctx, int32_t Q, int32_t Z, const double** 
 
 /* Per-kernel timing of solves (instrumentation, not part of the method).
  * While enabled, every kernel a solve with this plan enqueues is bracketed
- * by HIP events on the solve's stream.  mlc_plan_timing waits for the
+ * by HIP events on the stream it runs on (the caller stream, or the side
+ * stream for the stages that overlap the local convolutions, whose
+ * durations then include the sharing of the chip).  mlc_plan_timing waits for the
  * recorded events, then reports, per kernel name, the number of launches
  * and their summed duration in milliseconds since timing was enabled; it
  * fills at most `max` entries and sets *count to the number of distinct
