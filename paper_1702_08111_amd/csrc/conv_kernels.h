@@ -62,20 +62,53 @@ __global__ void __launch_bounds__(256) conv_xdft_kernel(const ProbDesc* __restri
     for (int sx = 0; sx < S; ++sx) acc += Bw[a][sx] * fd[sy * S + sx];
     gx[a][sy] = acc;
   }
+  // X[kx][sy] = sum_sx q[sy][sx] w^(kx sx): each thread a 4 x 4 register
+  // tile (kx = kg + NK a, sy = sg + NY b), so one twiddle and one sample
+  // read from LDS serve four products each
+  constexpr int TK = 4, TY = 4;
+  constexpr int NK = (Mh + TK - 1) / TK;
+  const int NY = (S + TY - 1) / TY;
   cplx<T>* out = X + (int64_t(p) * Mh * S + sz) * S;
-  for (int o = threadIdx.x; o < Mh * S; o += blockDim.x) {
-    int kx = o / S, sy = o % S;
-    T ar = 0, ai = 0;
-    const T* row = q + sy * S;
-    int idx = 0;
-    for (int sx = 0; sx < S; ++sx) {
-      cplx<T> w = tw[idx];
-      ar += row[sx] * w.x;
-      ai += row[sx] * w.y;
-      idx += kx;
-      if (idx >= M) idx -= M;
+  for (int o = threadIdx.x; o < NK * NY; o += blockDim.x) {
+    const int kg = o / NY, sg = o % NY;
+    int kx[TK], idx[TK], sy[TY];
+#pragma unroll
+    for (int a = 0; a < TK; ++a) {
+      kx[a] = min(kg + NK * a, Mh - 1);   // clamped lanes compute a duplicate, not stored
+      idx[a] = 0;
     }
-    out[int64_t(kx) * S * S + sy] = {ar, ai};
+#pragma unroll
+    for (int b = 0; b < TY; ++b) sy[b] = min(sg + NY * b, S - 1);
+    T ar[TK][TY], ai[TK][TY];
+#pragma unroll
+    for (int a = 0; a < TK; ++a)
+#pragma unroll
+      for (int b = 0; b < TY; ++b) ar[a][b] = ai[a][b] = T(0);
+    for (int sx = 0; sx < S; ++sx) {
+      cplx<T> w[TK];
+      T r[TY];
+#pragma unroll
+      for (int a = 0; a < TK; ++a) w[a] = tw[idx[a]];
+#pragma unroll
+      for (int b = 0; b < TY; ++b) r[b] = q[sy[b] * S + sx];
+#pragma unroll
+      for (int a = 0; a < TK; ++a)
+#pragma unroll
+        for (int b = 0; b < TY; ++b) {
+          ar[a][b] += r[b] * w[a].x;
+          ai[a][b] += r[b] * w[a].y;
+        }
+#pragma unroll
+      for (int a = 0; a < TK; ++a) {
+        idx[a] += kx[a];
+        if (idx[a] >= M) idx[a] -= M;
+      }
+    }
+#pragma unroll
+    for (int a = 0; a < TK; ++a)
+#pragma unroll
+      for (int b = 0; b < TY; ++b)
+        if (kg + NK * a < Mh && sg + NY * b < S) out[int64_t(kx[a]) * S * S + sy[b]] = {ar[a][b], ai[a][b]};
   }
   __syncthreads();
   if (threadIdx.x < PLANE_MOMENTS) {
@@ -307,7 +340,8 @@ __global__ void __launch_bounds__((OutBatch<T, M>::NT)) conv_out_kernel(const cp
   __shared__ uint64_t xinfo[M];
   // inverse twiddles of the skeleton-plane x coordinates: Wx[j][k] = w^(k x_j)
   constexpr int NPLMAX = 4;
-  __shared__ cplx<T> Wx[NPLMAX * (M / 2)];
+  constexpr int WXS = M / 2 + 1;   // row stride: the four rows on distinct LDS banks
+  __shared__ cplx<T> Wx[NPLMAX * WXS];
   const int zi = blockIdx.x, pc = blockIdx.y, p = p0 + pc;
   const int Wp = g.Wp;
   const int tid = threadIdx.x;
@@ -360,7 +394,7 @@ __global__ void __launch_bounds__((OutBatch<T, M>::NT)) conv_out_kernel(const cp
   for (int t = tid; t < g.npl * (M / 2); t += blockDim.x) {
     const int j = t / (M / 2), k = t % (M / 2);
     const int x = g.P0 + j * n, xs = x < 0 ? x + M : x;
-    Wx[t] = tw[(k * xs) % M];
+    Wx[j * WXS + k] = tw[(k * xs) % M];
   }
   if (tid < 64) {
     // compact the two row lists in ascending order with wave ballots
@@ -547,7 +581,7 @@ __global__ void __launch_bounds__((OutBatch<T, M>::NT)) conv_out_kernel(const cp
   for (int q = tid; q < ncl * npl; q += blockDim.x) {
     const int yi = crow[q / npl], j = q % npl;
     const int x = g.P0 + j * n, xs = x < 0 ? x + M : x;
-    const cplx<T>* wj = Wx + j * (M / 2);
+    const cplx<T>* wj = Wx + j * WXS;
     // four interleaved partial sums over k = 1 .. M/2 - 1
     constexpr int KT = M / 2 - 1;
     T acc[4] = {T(0), T(0), T(0), T(0)};
