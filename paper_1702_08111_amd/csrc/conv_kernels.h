@@ -320,9 +320,13 @@ __global__ void __launch_bounds__((OutBatch<T, M>::NT)) conv_out_kernel(const cp
                                                                       int p0) {
   constexpr int Mh = M / 2 + 1;
   constexpr int R1 = Split<M>::R1, R2 = Split<M>::R2;
-  constexpr int CB = OutBatch<T, M>::CB, XL = Batch<T, M>::XL;
+  constexpr int CB = OutBatch<T, M>::CB, XL = Batch<T, M>::XLYZ;
   constexpr int WPMAX = n + 2 * n + 1 + 2 * 4;  // Wa + 2b with d_alpha <= n, b <= 4
-  __shared__ cplx<T> A[Mh * WPMAX];
+  // fp32: A rows padded to a stride of 11 (mod 32) elements, so the lines
+  // of one wave step start on spread-out LDS banks (fp64: no room to pad)
+  constexpr bool PADA = sizeof(T) == 4;
+  constexpr int WQMAX = PADA ? WPMAX + ((11 - WPMAX % 32) + 32) % 32 : WPMAX;
+  __shared__ cplx<T> A[Mh * WQMAX];
   __shared__ cplx<T> Ex[CB * XL];
   __shared__ cplx<T> tw[M];
   __shared__ short omap[M];
@@ -344,6 +348,7 @@ __global__ void __launch_bounds__((OutBatch<T, M>::NT)) conv_out_kernel(const cp
   __shared__ cplx<T> Wx[NPLMAX * WXS];
   const int zi = blockIdx.x, pc = blockIdx.y, p = p0 + pc;
   const int Wp = g.Wp;
+  const int Wq = PADA ? Wp + ((11 - Wp % 32) + 32) % 32 : Wp;   // row stride of A
   const int tid = threadIdx.x;
   const double hsq = pd[find_problem(pd, nprob, p)].h2;
   const cplx<T>* zin = Zb + (int64_t(pc) * Wp + zi) * Mh * M;
@@ -427,7 +432,7 @@ __global__ void __launch_bounds__((OutBatch<T, M>::NT)) conv_out_kernel(const cp
     for (int s = 0; s < R1; ++s) v[s] = ex[r * XL + s * (R2 + 1) + t];
     dft_reg<T, R1, -1>(v);
     if (kx < Mh) {
-      cplx<T>* arow = A + kx * Wp;
+      cplx<T>* arow = A + kx * Wq;
 #pragma unroll
       for (int j1 = 0; j1 < R1; ++j1)
         if (ymap[j1] >= 0) arow[ymap[j1]] = v[j1];
@@ -502,11 +507,11 @@ __global__ void __launch_bounds__((OutBatch<T, M>::NT)) conv_out_kernel(const cp
       int k = s + R1 * k2;
       cplx<T> h1 = {T(0), T(0)}, h2 = {T(0), T(0)};
       if (k < Mh) {
-        if (y1 < Wp) h1 = A[k * Wp + y1];
-        if (y2 < Wp) h2 = A[k * Wp + y2];
+        if (y1 < Wp) h1 = A[k * Wq + y1];
+        if (y2 < Wp) h2 = A[k * Wq + y2];
       } else {
-        if (y1 < Wp) h1 = conjw(A[(M - k) * Wp + y1]);
-        if (y2 < Wp) h2 = conjw(A[(M - k) * Wp + y2]);
+        if (y1 < Wp) h1 = conjw(A[(M - k) * Wq + y1]);
+        if (y2 < Wp) h2 = conjw(A[(M - k) * Wq + y2]);
       }
       if (k == 0 || k == M / 2) { h1.y = T(0); h2.y = T(0); }   // real DC / Nyquist
       u[k2] = {h1.x - h2.y, h1.y + h2.x};                        // h1 + i h2
@@ -589,7 +594,7 @@ __global__ void __launch_bounds__((OutBatch<T, M>::NT)) conv_out_kernel(const cp
     for (int k0 = 1; k0 + 3 <= KT; k0 += 4) {
 #pragma unroll
       for (int u = 0; u < 4; ++u) {
-        const cplx<T> a = A[(k0 + u) * Wp + yi];
+        const cplx<T> a = A[(k0 + u) * Wq + yi];
         const cplx<T> w = wj[k0 + u];
         acc[u] += a.x * w.x + a.y * w.y;
       }
@@ -597,11 +602,11 @@ __global__ void __launch_bounds__((OutBatch<T, M>::NT)) conv_out_kernel(const cp
 #pragma unroll
     for (int u = 0; u < KT % 4; ++u) {
       const int k = KT - KT % 4 + 1 + u;
-      const cplx<T> a = A[k * Wp + yi];
+      const cplx<T> a = A[k * Wq + yi];
       const cplx<T> w = wj[k];
       acc[u] += a.x * w.x + a.y * w.y;
     }
-    const T dc = A[yi].x, ny = A[(M / 2) * Wp + yi].x;
+    const T dc = A[yi].x, ny = A[(M / 2) * Wq + yi].x;
     const T val = dc + ((xs & 1) ? -ny : ny) + T(2) * ((acc[0] + acc[1]) + (acc[2] + acc[3]));
     const int y = ocrd[yi];
     pbase[((int64_t(2) * npl + j) * Wa + (z + g.da)) * Wa + (y + g.da)] = T(double(val) * hsq);
