@@ -142,6 +142,10 @@ template <typename T, int M> struct OutBatch {
   static constexpr bool WAVE = sizeof(T) == 4;
   static constexpr int LW = 64 / Split<M>::R1;
   static constexpr int CB = WAVE ? (NT / 64) * LW : 4;
+  // z planes per block: the next plane's first lines load during the
+  // current plane's x pass, and the set-up is shared (measured: 3 for fp32;
+  // fp64 blocks are fastest alone)
+  static constexpr int ZPB = WAVE ? 3 : 1;
 };
 
 // LDS ordering among the lanes of one wave (the wave's LDS operations are
@@ -346,12 +350,13 @@ __global__ void __launch_bounds__((OutBatch<T, M>::NT)) conv_out_kernel(const cp
   constexpr int NPLMAX = 4;
   constexpr int WXS = M / 2 + 1;   // row stride: the four rows on distinct LDS banks
   __shared__ cplx<T> Wx[NPLMAX * WXS];
-  const int zi = blockIdx.x, pc = blockIdx.y, p = p0 + pc;
+  constexpr int ZPB = OutBatch<T, M>::ZPB;
+  const int zi0 = blockIdx.x * ZPB, pc = blockIdx.y, p = p0 + pc;
   const int Wp = g.Wp;
   const int Wq = PADA ? Wp + ((11 - Wp % 32) + 32) % 32 : Wp;   // row stride of A
   const int tid = threadIdx.x;
   const double hsq = pd[find_problem(pd, nprob, p)].h2;
-  const cplx<T>* zin = Zb + (int64_t(pc) * Wp + zi) * Mh * M;
+  const cplx<T>* zin = Zb + (int64_t(pc) * Wp + zi0) * Mh * M;   // the current plane
   constexpr bool WAVE = OutBatch<T, M>::WAVE;
   constexpr int LW = OutBatch<T, M>::LW, NW = OutBatch<T, M>::NT / 64;
   const int wave = tid >> 6, lane = tid & 63;
@@ -401,6 +406,10 @@ __global__ void __launch_bounds__((OutBatch<T, M>::NT)) conv_out_kernel(const cp
     const int x = g.P0 + j * n, xs = x < 0 ? x + M : x;
     Wx[j * WXS + k] = tw[(k * xs) % M];
   }
+#pragma unroll 1
+  for (int q = 0; q < ZPB; ++q) {
+  const int zi = zi0 + q;
+  if (zi >= Wp) break;   // uniform over the block
   if (tid < 64) {
     // compact the two row lists in ascending order with wave ballots
     const int zf = oflg[zi];
@@ -487,6 +496,18 @@ __global__ void __launch_bounds__((OutBatch<T, M>::NT)) conv_out_kernel(const cp
         y_pass2(Ex, tid % R2, tid / R2, kb + tid / R2, ymap);
       }
       __syncthreads();
+    }
+  }
+  // the next plane's first lines stay in flight through this plane's x pass
+  if (q + 1 < ZPB && zi + 1 < Wp) {
+    zin += int64_t(Mh) * M;
+    if constexpr (WAVE) {
+      load_lines(u0, wave * LW);
+    } else {
+      const int s = tid % R1, r = tid / R1;
+#pragma unroll
+      for (int k2 = 0; k2 < R2; ++k2)
+        pre[k2] = (tid < CB * R1 && r < Mh) ? zin[int64_t(r) * M + s + R1 * k2] : cplx<T>{T(0), T(0)};
     }
   }
   __syncthreads();
@@ -610,6 +631,8 @@ __global__ void __launch_bounds__((OutBatch<T, M>::NT)) conv_out_kernel(const cp
     const T val = dc + ((xs & 1) ? -ny : ny) + T(2) * ((acc[0] + acc[1]) + (acc[2] + acc[3]));
     const int y = ocrd[yi];
     pbase[((int64_t(2) * npl + j) * Wa + (z + g.da)) * Wa + (y + g.da)] = T(double(val) * hsq);
+  }
+  __syncthreads();   // A, Ex and the row lists are rewritten for the next plane
   }
 }
 

@@ -874,7 +874,9 @@ static void launch_conv(const Group& G, hipStream_t s, int phase, const std::fun
     if (p0 == 0 && after_yz) (*after_yz)();
     {
       TimedScope ts(P, s, "conv_out");
-      hipLaunchKernelGGL((conv_out_kernel<T, n, M>), dim3(P->Wp, cnt), dim3(OutBatch<T, M>::NT), 0, s, Zb, cs,
+      constexpr int zpb = OutBatch<T, M>::ZPB;
+      hipLaunchKernelGGL((conv_out_kernel<T, n, M>), dim3((P->Wp + zpb - 1) / zpb, cnt), dim3(OutBatch<T, M>::NT),
+                         0, s, Zb, cs,
                          pl, g, G.desc, np, p0);
     }
   }
