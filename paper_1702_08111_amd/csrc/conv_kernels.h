@@ -132,16 +132,21 @@ template <typename T, int M> struct Batch {
   // exchange (the forward pass writes)
   static constexpr int XLYZ = XLayout<M>::LINE + ((8 - XLayout<M>::LINE % 32) + 32) % 32;
 };
-// conv_out holds the whole (kx, y) plane in LDS, so one block fills a CU.
+// conv_out holds the (kx, y) plane in LDS, so one block fills a CU.
 // fp32: 512 threads, each wave transforms its own lines (LW per step)
 // through a private slice of the exchange buffer, with no block barriers
-// between FFT passes; fp64 (twice the plane in LDS): 256 threads, CB lines
-// per block-wide batch.
+// between FFT passes; fp64 (twice the bytes): 256 threads, CB lines per
+// block-wide batch, half of the plane's output rows per block.
 template <typename T, int M> struct OutBatch {
   static constexpr int NT = sizeof(T) == 4 ? 512 : 256;
   static constexpr bool WAVE = sizeof(T) == 4;
   static constexpr int LW = 64 / Split<M>::R1;
-  static constexpr int CB = WAVE ? (NT / 64) * LW : 4;
+  // fp64: the output rows of a plane split over two blocks, each keeping
+  // its half of the (kx, y) plane in LDS, which leaves room for a 16-line
+  // exchange (every thread busy in the y pass; each block repeats the
+  // plane's y FFTs)
+  static constexpr int YSPL = WAVE ? 1 : 2;
+  static constexpr int CB = WAVE ? (NT / 64) * LW : 16;
   // z planes per block: the next plane's first lines load during the
   // current plane's x pass, and the set-up is shared (measured: 3 for fp32;
   // fp64 blocks are fastest alone)
@@ -329,7 +334,9 @@ __global__ void __launch_bounds__((OutBatch<T, M>::NT)) conv_out_kernel(const cp
   // fp32: A rows padded to a stride of 11 (mod 32) elements, so the lines
   // of one wave step start on spread-out LDS banks (fp64: no room to pad)
   constexpr bool PADA = sizeof(T) == 4;
-  constexpr int WQMAX = PADA ? WPMAX + ((11 - WPMAX % 32) + 32) % 32 : WPMAX;
+  constexpr int YSPL = OutBatch<T, M>::YSPL;
+  constexpr int WHMAX = (WPMAX + YSPL - 1) / YSPL;
+  constexpr int WQMAX = PADA ? WHMAX + ((11 - WHMAX % 32) + 32) % 32 : WHMAX;
   __shared__ cplx<T> A[Mh * WQMAX];
   __shared__ cplx<T> Ex[CB * XL];
   __shared__ cplx<T> tw[M];
@@ -351,9 +358,11 @@ __global__ void __launch_bounds__((OutBatch<T, M>::NT)) conv_out_kernel(const cp
   constexpr int WXS = M / 2 + 1;   // row stride: the four rows on distinct LDS banks
   __shared__ cplx<T> Wx[NPLMAX * WXS];
   constexpr int ZPB = OutBatch<T, M>::ZPB;
-  const int zi0 = blockIdx.x * ZPB, pc = blockIdx.y, p = p0 + pc;
+  const int zi0 = (blockIdx.x / YSPL) * ZPB, pc = blockIdx.y, p = p0 + pc;
   const int Wp = g.Wp;
-  const int Wq = PADA ? Wp + ((11 - Wp % 32) + 32) % 32 : Wp;   // row stride of A
+  // this block's output rows [ylo, yhi) of each plane
+  const int Wh = (Wp + YSPL - 1) / YSPL, ylo = int(blockIdx.x % YSPL) * Wh, yhi = min(Wp, ylo + Wh);
+  const int Wq = PADA ? Wh + ((11 - Wh % 32) + 32) % 32 : Wh;   // row stride of A
   const int tid = threadIdx.x;
   const double hsq = pd[find_problem(pd, nprob, p)].h2;
   const cplx<T>* zin = Zb + (int64_t(pc) * Wp + zi0) * Mh * M;   // the current plane
@@ -415,9 +424,9 @@ __global__ void __launch_bounds__((OutBatch<T, M>::NT)) conv_out_kernel(const cp
     const int zf = oflg[zi];
     int a = 0, c = 0;
     const uint64_t below = (uint64_t(1) << tid) - 1;
-    for (int base = 0; base < Wp; base += 64) {
+    for (int base = ylo; base < yhi; base += 64) {
       const int yi = base + tid;
-      const int yf = yi < Wp ? oflg[yi] : 0;
+      const int yf = yi < yhi ? oflg[yi] : 0;
       // z-plane rows in Omega_alpha, coarse rows of a coarse z, y-plane rows
       const bool full = ((zf & 4) && (yf & 1)) || ((zf & 2) && (yf & 2)) || ((zf & 1) && (yf & 4));
       const bool col = !full && (zf & 1) && (yf & 1);   // x-plane columns only
@@ -462,7 +471,10 @@ __global__ void __launch_bounds__((OutBatch<T, M>::NT)) conv_out_kernel(const cp
     cplx<T>* ex = Ex + wave * LW * XL;
     short ymap[R1];
 #pragma unroll
-    for (int j1 = 0; j1 < R1; ++j1) ymap[j1] = omap[t2 + R2 * j1];
+    for (int j1 = 0; j1 < R1; ++j1) {
+      const int k = omap[t2 + R2 * j1];
+      ymap[j1] = (k >= ylo && k < yhi) ? short(k - ylo) : short(-1);
+    }
 #pragma unroll 1
     for (int kb = wave * LW; kb < Mh; kb += NW * LW) {
       cplx<T> un[R2];
@@ -492,7 +504,10 @@ __global__ void __launch_bounds__((OutBatch<T, M>::NT)) conv_out_kernel(const cp
       if (tid < CB * R2) {
         short ymap[R1];
 #pragma unroll
-        for (int j1 = 0; j1 < R1; ++j1) ymap[j1] = omap[tid % R2 + R2 * j1];
+        for (int j1 = 0; j1 < R1; ++j1) {
+          const int k = omap[tid % R2 + R2 * j1];
+          ymap[j1] = (k >= ylo && k < yhi) ? short(k - ylo) : short(-1);
+        }
         y_pass2(Ex, tid % R2, tid / R2, kb + tid / R2, ymap);
       }
       __syncthreads();
@@ -528,11 +543,11 @@ __global__ void __launch_bounds__((OutBatch<T, M>::NT)) conv_out_kernel(const cp
       int k = s + R1 * k2;
       cplx<T> h1 = {T(0), T(0)}, h2 = {T(0), T(0)};
       if (k < Mh) {
-        if (y1 < Wp) h1 = A[k * Wq + y1];
-        if (y2 < Wp) h2 = A[k * Wq + y2];
+        if (y1 < Wp) h1 = A[k * Wq + (y1 - ylo)];
+        if (y2 < Wp) h2 = A[k * Wq + (y2 - ylo)];
       } else {
-        if (y1 < Wp) h1 = conjw(A[(M - k) * Wq + y1]);
-        if (y2 < Wp) h2 = conjw(A[(M - k) * Wq + y2]);
+        if (y1 < Wp) h1 = conjw(A[(M - k) * Wq + (y1 - ylo)]);
+        if (y2 < Wp) h2 = conjw(A[(M - k) * Wq + (y2 - ylo)]);
       }
       if (k == 0 || k == M / 2) { h1.y = T(0); h2.y = T(0); }   // real DC / Nyquist
       u[k2] = {h1.x - h2.y, h1.y + h2.x};                        // h1 + i h2
@@ -615,7 +630,7 @@ __global__ void __launch_bounds__((OutBatch<T, M>::NT)) conv_out_kernel(const cp
     for (int k0 = 1; k0 + 3 <= KT; k0 += 4) {
 #pragma unroll
       for (int u = 0; u < 4; ++u) {
-        const cplx<T> a = A[(k0 + u) * Wq + yi];
+        const cplx<T> a = A[(k0 + u) * Wq + (yi - ylo)];
         const cplx<T> w = wj[k0 + u];
         acc[u] += a.x * w.x + a.y * w.y;
       }
@@ -623,11 +638,11 @@ __global__ void __launch_bounds__((OutBatch<T, M>::NT)) conv_out_kernel(const cp
 #pragma unroll
     for (int u = 0; u < KT % 4; ++u) {
       const int k = KT - KT % 4 + 1 + u;
-      const cplx<T> a = A[k * Wq + yi];
+      const cplx<T> a = A[k * Wq + (yi - ylo)];
       const cplx<T> w = wj[k];
       acc[u] += a.x * w.x + a.y * w.y;
     }
-    const T dc = A[yi].x, ny = A[(M / 2) * Wq + yi].x;
+    const T dc = A[yi - ylo].x, ny = A[(M / 2) * Wq + (yi - ylo)].x;
     const T val = dc + ((xs & 1) ? -ny : ny) + T(2) * ((acc[0] + acc[1]) + (acc[2] + acc[3]));
     const int y = ocrd[yi];
     pbase[((int64_t(2) * npl + j) * Wa + (z + g.da)) * Wa + (y + g.da)] = T(double(val) * hsq);

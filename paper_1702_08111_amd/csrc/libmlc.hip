@@ -875,7 +875,8 @@ static void launch_conv(const Group& G, hipStream_t s, int phase, const std::fun
     {
       TimedScope ts(P, s, "conv_out");
       constexpr int zpb = OutBatch<T, M>::ZPB;
-      hipLaunchKernelGGL((conv_out_kernel<T, n, M>), dim3((P->Wp + zpb - 1) / zpb, cnt), dim3(OutBatch<T, M>::NT),
+      constexpr int yspl = OutBatch<T, M>::YSPL;
+      hipLaunchKernelGGL((conv_out_kernel<T, n, M>), dim3((P->Wp + zpb - 1) / zpb * yspl, cnt), dim3(OutBatch<T, M>::NT),
                          0, s, Zb, cs,
                          pl, g, G.desc, np, p0);
     }
