@@ -132,25 +132,22 @@ template <typename T, int M> struct Batch {
   // exchange (the forward pass writes)
   static constexpr int XLYZ = XLayout<M>::LINE + ((8 - XLayout<M>::LINE % 32) + 32) % 32;
 };
-// conv_out holds the (kx, y) plane in LDS, so one block fills a CU.
-// fp32: 512 threads, each wave transforms its own lines (LW per step)
-// through a private slice of the exchange buffer, with no block barriers
-// between FFT passes; fp64 (twice the bytes): 256 threads, CB lines per
-// block-wide batch, half of the plane's output rows per block.
+// conv_out holds the (kx, y) plane in LDS, so one block fills a CU.  Each
+// wave transforms its own lines (LW per step) through a private slice of
+// the exchange buffer, with no block barriers between FFT passes.
 template <typename T, int M> struct OutBatch {
-  static constexpr int NT = sizeof(T) == 4 ? 512 : 256;
-  static constexpr bool WAVE = sizeof(T) == 4;
+  static constexpr bool F32 = sizeof(T) == 4;
+  static constexpr int NT = F32 ? 512 : 256;
   static constexpr int LW = 64 / Split<M>::R1;
-  // fp64: the output rows of a plane split over two blocks, each keeping
-  // its half of the (kx, y) plane in LDS, which leaves room for a 16-line
-  // exchange (every thread busy in the y pass; each block repeats the
-  // plane's y FFTs)
-  static constexpr int YSPL = WAVE ? 1 : 2;
-  static constexpr int CB = WAVE ? (NT / 64) * LW : 16;
+  static constexpr int CB = (NT / 64) * LW;   // exchange lines of the block
+  // fp64: the output rows of a plane split over two blocks, each keeping its
+  // half of the (kx, y) plane in LDS (room for the exchange slices; each
+  // block repeats the plane's y FFTs)
+  static constexpr int YSPL = F32 ? 1 : 2;
   // z planes per block: the next plane's first lines load during the
   // current plane's x pass, and the set-up is shared (measured: 3 for fp32;
-  // fp64 blocks are fastest alone)
-  static constexpr int ZPB = WAVE ? 3 : 1;
+  // fp64 blocks are fastest with one)
+  static constexpr int ZPB = F32 ? 3 : 1;
 };
 
 // LDS ordering among the lanes of one wave (the wave's LDS operations are
@@ -366,12 +363,12 @@ __global__ void __launch_bounds__((OutBatch<T, M>::NT)) conv_out_kernel(const cp
   const int tid = threadIdx.x;
   const double hsq = pd[find_problem(pd, nprob, p)].h2;
   const cplx<T>* zin = Zb + (int64_t(pc) * Wp + zi0) * Mh * M;   // the current plane
-  constexpr bool WAVE = OutBatch<T, M>::WAVE;
   constexpr int LW = OutBatch<T, M>::LW, NW = OutBatch<T, M>::NT / 64;
   const int wave = tid >> 6, lane = tid & 63;
   const int s1 = lane % R1, r1 = lane / R1, t2 = lane % R2, r2 = lane / R2;
   const bool act1 = lane < LW * R1, act2 = lane < LW * R2;
-  // wave mode: the first step's lines, issued before the set-up below
+  cplx<T>* ex = Ex + wave * LW * XL;   // this wave's exchange slice
+  // the first step's lines, issued before the set-up below
   cplx<T> u0[R2];
   auto load_lines = [&](cplx<T>* dst, int kb) {
     const int kx = kb + r1;
@@ -379,15 +376,7 @@ __global__ void __launch_bounds__((OutBatch<T, M>::NT)) conv_out_kernel(const cp
     for (int k2 = 0; k2 < R2; ++k2)
       dst[k2] = (act1 && kx < Mh) ? zin[int64_t(kx) * M + s1 + R1 * k2] : cplx<T>{T(0), T(0)};
   };
-  if constexpr (WAVE) load_lines(u0, wave * LW);
-  // block mode: the first batch's rows
-  cplx<T> pre[R2];
-  if constexpr (!WAVE) {
-    const int s = tid % R1, r = tid / R1;
-#pragma unroll
-    for (int k2 = 0; k2 < R2; ++k2)
-      pre[k2] = (tid < CB * R1 && r < Mh) ? zin[int64_t(r) * M + s + R1 * k2] : cplx<T>{T(0), T(0)};
-  }
+  load_lines(u0, wave * LW);
   fill_twiddles(tw, M);
   for (int m = tid; m < M; m += blockDim.x) omap[m] = -1;
   __syncthreads();
@@ -467,8 +456,7 @@ __global__ void __launch_bounds__((OutBatch<T, M>::NT)) conv_out_kernel(const cp
   };
   __syncthreads();
   // ---- inverse FFT along y for every kx ----
-  if constexpr (WAVE) {
-    cplx<T>* ex = Ex + wave * LW * XL;
+  {
     short ymap[R1];
 #pragma unroll
     for (int j1 = 0; j1 < R1; ++j1) {
@@ -486,44 +474,11 @@ __global__ void __launch_bounds__((OutBatch<T, M>::NT)) conv_out_kernel(const cp
 #pragma unroll
       for (int k2 = 0; k2 < R2; ++k2) u0[k2] = un[k2];
     }
-  } else {
-#pragma unroll 1
-    for (int kb = 0; kb < Mh; kb += CB) {
-      const int s = tid % R1, r = tid / R1;
-      if (tid < CB * R1) {
-        cplx<T> u[R2];
-#pragma unroll
-        for (int k2 = 0; k2 < R2; ++k2) u[k2] = pre[k2];
-        const int kn = kb + CB + r;
-#pragma unroll
-        for (int k2 = 0; k2 < R2; ++k2)
-          pre[k2] = kn < Mh ? zin[int64_t(kn) * M + s + R1 * k2] : cplx<T>{T(0), T(0)};
-        y_pass1(u, Ex, s, r);
-      }
-      __syncthreads();
-      if (tid < CB * R2) {
-        short ymap[R1];
-#pragma unroll
-        for (int j1 = 0; j1 < R1; ++j1) {
-          const int k = omap[tid % R2 + R2 * j1];
-          ymap[j1] = (k >= ylo && k < yhi) ? short(k - ylo) : short(-1);
-        }
-        y_pass2(Ex, tid % R2, tid / R2, kb + tid / R2, ymap);
-      }
-      __syncthreads();
-    }
   }
   // the next plane's first lines stay in flight through this plane's x pass
   if (q + 1 < ZPB && zi + 1 < Wp) {
     zin += int64_t(Mh) * M;
-    if constexpr (WAVE) {
-      load_lines(u0, wave * LW);
-    } else {
-      const int s = tid % R1, r = tid / R1;
-#pragma unroll
-      for (int k2 = 0; k2 < R2; ++k2)
-        pre[k2] = (tid < CB * R1 && r < Mh) ? zin[int64_t(r) * M + s + R1 * k2] : cplx<T>{T(0), T(0)};
-    }
+    load_lines(u0, wave * LW);
   }
   __syncthreads();
   const int z = ocrd[zi];
@@ -599,23 +554,12 @@ __global__ void __launch_bounds__((OutBatch<T, M>::NT)) conv_out_kernel(const cp
     }
   };
   const int npair = (nf + 1) / 2;
-  if constexpr (WAVE) {
-    cplx<T>* ex = Ex + wave * LW * XL;
 #pragma unroll 1
-    for (int pb = wave * LW; pb < npair; pb += NW * LW) {
-      if (act1) x_pass1(ex, s1, r1, pb + r1);
-      wave_sync();
-      if (act2) x_pass2(ex, t2, r2, pb + r2);
-      wave_sync();
-    }
-  } else {
-#pragma unroll 1
-    for (int pb = 0; pb < npair; pb += CB) {
-      if (tid < CB * R1) x_pass1(Ex, tid % R1, tid / R1, pb + tid / R1);
-      __syncthreads();
-      if (tid < CB * R2) x_pass2(Ex, tid % R2, tid / R2, pb + tid / R2);
-      __syncthreads();
-    }
+  for (int pb = wave * LW; pb < npair; pb += NW * LW) {
+    if (act1) x_pass1(ex, s1, r1, pb + r1);
+    wave_sync();
+    if (act2) x_pass2(ex, t2, r2, pb + r2);
+    wave_sync();
   }
   // ---- x-plane columns of the other rows: direct Hermitian sums ----
   //   f(x) = F_0 + (-1)^x F_{M/2} + 2 sum_{0<k<M/2} Re(F_k e^{2 pi i k x / M})
