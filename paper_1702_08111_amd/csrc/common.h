@@ -42,6 +42,13 @@ __host__ __device__ inline double boole_w(int j, int n) {
   return (r == 0 ? 14.0 : (r == 2 ? 12.0 : 32.0)) * base;
 }
 
+// A pointer taken from a descriptor as a global-memory pointer, so that its
+// accesses compile to global (not flat) instructions.
+template <typename T>
+__device__ __forceinline__ __attribute__((address_space(1))) T* gbl(T* p) {
+  return (__attribute__((address_space(1))) T*)p;
+}
+
 // Partial moment sums per patch z-plane: one per (a1, a2), a1, a2 <= 3.
 constexpr int PLANE_MOMENTS = 16;
 

@@ -36,12 +36,12 @@ __global__ void __launch_bounds__(256) conv_xdft_kernel(const ProbDesc* __restri
   const int S = n + 1;
   const int p = p0 + blockIdx.y, sz = blockIdx.x;
   const ProbDesc& D = pd[find_problem(pd, nprob, p)];
-  const double* f = D.f;
+  const auto* f = gbl(D.f);
   const int ppa = D.ppa, pl = p - D.patch0;
   const int i0 = pl / (ppa * ppa), i1 = (pl / ppa) % ppa, i2 = pl % ppa;
   const int64_t Np = D.N + 1;
   const double cz = (sz == 0 || sz == n) ? 0.5 : 1.0;
-  const double* fp = f + (int64_t(n) * i0 + sz) * Np * Np + int64_t(n) * i1 * Np + int64_t(n) * i2;
+  const auto* fp = f + (int64_t(n) * i0 + sz) * Np * Np + int64_t(n) * i1 * Np + int64_t(n) * i2;
   for (int t = threadIdx.x; t < S * S; t += blockDim.x) {
     int sy = t / S, sx = t % S;
     double c = cz * ((sy == 0 || sy == n) ? 0.5 : 1.0) * ((sx == 0 || sx == n) ? 0.5 : 1.0);
@@ -199,7 +199,11 @@ __global__ void __launch_bounds__(256) conv_yz_kernel(const cplx<T>* __restrict_
 #pragma unroll
       for (int j1 = 0; j1 < NJ; ++j1) {
         int sz = j * CB + r, sy = t + R2 * j1;
-        xr[j][j1] = (tid < CB * R2 && sz < S && sy < S) ? xin[sz * S + sy] : zero;
+        // (a loaded-or-zero value: a select between the load's address and
+        // a local zero would turn the load into a flat one)
+        cplx<T> x = zero;
+        if (tid < CB * R2 && sz < S && sy < S) x = xin[sz * S + sy];
+        xr[j][j1] = x;
       }
   }
   // ---- FFT along y of the S source rows (CB rows per batch) ----
@@ -261,7 +265,9 @@ __global__ void __launch_bounds__(256) conv_yz_kernel(const cplx<T>* __restrict_
 #pragma unroll
       for (int j1 = 0; j1 < R1; ++j1) {
         int sz = ta + R2 * j1;
-        v[j1] = (j1 < NJ && sz < S && ky < M) ? Y[sz * YS + ky] : zero;
+        cplx<T> y = zero;
+        if (j1 < NJ && sz < S && ky < M) y = Y[sz * YS + ky];
+        v[j1] = y;
       }
       dft_reg_nz<T, R1, 1, NJ>(v);
       cplx<T>* e = ex + ca * XL + ta * (R1 + 1);

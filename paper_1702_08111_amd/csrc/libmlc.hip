@@ -1042,10 +1042,10 @@ static void launch_rest(const Group& G, hipStream_t s, Stage stage) {
     const int m = I0.n - 1;
     TimedScope ts(P0, s, "dirichlet");
     DirGeom dg{I0.n, L.total, 2.0 / I0.n, st};
-    dim3 gd(unsigned((int64_t(L.total) * m + 3) / 4));
-    hipLaunchKernelGGL(dirichlet_mfma_kernel<0>, gd, dim3(256), 0, s, G.desc, np, dir, dg);
-    hipLaunchKernelGGL(dirichlet_mfma_kernel<1>, gd, dim3(256), 0, s, G.desc, np, dir, dg);
-    hipLaunchKernelGGL(dirichlet_mfma_kernel<2>, gd, dim3(256), 0, s, G.desc, np, dir, dg);
+    dim3 gd(unsigned((int64_t(L.total) * m + DIR_WAVES - 1) / DIR_WAVES));
+    hipLaunchKernelGGL(dirichlet_mfma_kernel<0>, gd, dim3(64 * DIR_WAVES), 0, s, G.desc, np, dir, dg);
+    hipLaunchKernelGGL(dirichlet_mfma_kernel<1>, gd, dim3(64 * DIR_WAVES), 0, s, G.desc, np, dir, dg);
+    hipLaunchKernelGGL(dirichlet_mfma_kernel<2>, gd, dim3(64 * DIR_WAVES), 0, s, G.desc, np, dir, dg);
   }
 }
 

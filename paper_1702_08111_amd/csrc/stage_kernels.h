@@ -557,11 +557,14 @@ __device__ __forceinline__ void mm32(const double* A, const double* B, double* D
       for (int r = 0; r < 4; ++r) D[(16 * it + 4 * r + (lane >> 4)) * 33 + 16 * kt + (lane & 15)] = acc[it][kt][r];
 }
 
+// Slabs (waves) per block of the Dirichlet passes.
+constexpr int DIR_WAVES = 8;
+
 template <int PASS>
-__global__ void __launch_bounds__(256) dirichlet_mfma_kernel(const ProbDesc* __restrict__ pd, int nprob,
-                                                             double* __restrict__ work, DirGeom g) {
+__global__ void __launch_bounds__(64 * DIR_WAVES) dirichlet_mfma_kernel(const ProbDesc* __restrict__ pd, int nprob,
+                                                                        double* __restrict__ work, DirGeom g) {
   __shared__ double Sm[32 * 33];
-  __shared__ double Ls[4][32 * 33];
+  __shared__ double Ls[DIR_WAVES][32 * 33];
   __shared__ double sn[2 * 32], cs[32];
   const int m = g.n - 1;
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
@@ -574,13 +577,13 @@ __global__ void __launch_bounds__(256) dirichlet_mfma_kernel(const ProbDesc* __r
     int k = t / 32, j = t % 32;
     Sm[k * 33 + j] = (k < m && j < m) ? sn[((k + 1) * (j + 1)) % (2 * g.n)] : 0.0;
   }
-  const int slab = blockIdx.x * 4 + wave;     // over patches x m
+  const int slab = blockIdx.x * DIR_WAVES + wave;     // over patches x m
   const int p = slab / m, u = slab % m;
   const bool live = p < g.npatch;
   const ProbDesc& D = pd[find_problem(pd, nprob, live ? p : 0)];
-  const double* f = D.f;
-  const double* phiB = D.phiB;
-  double* phi = D.phi;
+  const auto* f = gbl(D.f);
+  const auto* phiB = gbl(D.phiB);
+  auto* phi = gbl(D.phi);
   const int ppa = D.ppa, pl = p - D.patch0;
   const double h2 = D.h2;
   // slab element (row i, column j):
@@ -595,9 +598,14 @@ __global__ void __launch_bounds__(256) dirichlet_mfma_kernel(const ProbDesc* __r
   const int64_t Np = D.N + 1;
   const int64_t pbase = (int64_t(g.n) * i0) * Np * Np + int64_t(g.n) * i1 * Np + int64_t(g.n) * i2;
   double* L = Ls[wave];
-  // lanes 0..31 walk a row's columns, the two half-waves take alternate rows
+  // lanes 0..31 walk a row's columns, the two half-waves take alternate
+  // rows; all 16 rows of a lane are loaded before the first LDS write, so
+  // the loads overlap
   const int jc = lane & 31, ih = lane >> 5;
-  for (int i = ih; i < 32; i += 2) {
+  double rows[16];
+#pragma unroll
+  for (int r = 0; r < 16; ++r) {
+    const int i = ih + 2 * r;
     double v = 0.0;
     if (live && i < m && jc < m) {
       if constexpr (PASS == 0) {
@@ -606,8 +614,10 @@ __global__ void __launch_bounds__(256) dirichlet_mfma_kernel(const ProbDesc* __r
         v = wp[off(i, jc)];
       }
     }
-    L[i * 33 + jc] = v;
+    rows[r] = v;
   }
+#pragma unroll
+  for (int r = 0; r < 16; ++r) L[(ih + 2 * r) * 33 + jc] = rows[r];
   if constexpr (PASS == 0) {
     // boundary terms, only at nodes next to the patch boundary: the whole
     // slab if it is the first or last, else its ring of 4(m-1) nodes
@@ -640,10 +650,10 @@ __global__ void __launch_bounds__(256) dirichlet_mfma_kernel(const ProbDesc* __r
       L[i * 33 + j] -= corr;
     }
   }
-  __syncthreads();
+  __syncthreads();   // Sm; from here on each wave touches only its own slab
   if constexpr (PASS == 1) {
     mm32(Sm, L, L, lane);                 // forward along index 0
-    __syncthreads();
+    wave_sync_lds();
     for (int i = ih; i < 32; i += 2) {    // divide by the symbol at (k0, k1, k2) = (i, u, jc)
       double v = 0.0;
       if (i < m && jc < m) {
@@ -654,14 +664,14 @@ __global__ void __launch_bounds__(256) dirichlet_mfma_kernel(const ProbDesc* __r
       }
       L[i * 33 + jc] = v;
     }
-    __syncthreads();
+    wave_sync_lds();
     mm32(Sm, L, L, lane);                 // inverse along index 0
   } else {
     mm32(Sm, L, L, lane);                 // along index 1 (rows)
-    __syncthreads();
+    wave_sync_lds();
     mm32(L, Sm, L, lane);                 // along index 2 (columns)
   }
-  __syncthreads();
+  wave_sync_lds();
   if (!live) return;
   const double sc = PASS == 0 ? 1.0 : (PASS == 1 ? g.scale : g.scale * g.scale);
   for (int i = ih; i < m; i += 2) {
