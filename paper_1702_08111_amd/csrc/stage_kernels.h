@@ -172,6 +172,7 @@ __global__ void __launch_bounds__(256) plane_delta_kernel(T* __restrict__ planes
   __syncthreads();
   T* out = planes + ((int64_t(p) * 3 + d) * g.npl + j) * Wa * Wa;
   for (int t = threadIdx.x; t < Wa * Wa; t += blockDim.x) {
+    const T old = out[t];   // in flight during the interpolation below
     int u = t / Wa, v = t % Wa;
     int xu = -g.da + u, U0 = floor4(xu), tu = xu - NREF * U0;
     const double* col = R + (U0 + o) * Wa + v;
@@ -182,7 +183,7 @@ __global__ void __launch_bounds__(256) plane_delta_kernel(T* __restrict__ planes
       s = 0.0;
       for (int k = -b; k <= b + 1; ++k) s += W[tu][k + b] * col[k * Wa];
     }
-    out[t] = T(double(out[t]) - s);
+    out[t] = T(double(old) - s);
   }
 }
 
