@@ -523,13 +523,14 @@ static bool same_class(const mlc_plan* a, const mlc_plan* b) {
 }
 
 // Workspace of one class group, relative to the group's base:
-//   descriptors | per patch (all problems): moments, per-plane moment sums,
+//   descriptors (per-patch stages, far fields) | per patch (all problems):
+//   moments, per-plane moment sums,
 //   x-DFTs, one chunk of
 //   z-transformed spectra, coarse samples, skeleton planes, Dirichlet work |
 //   per problem: F^H, coarse torus (consecutive within equal M_coarse),
 //   phi^H, phi^B.
 struct Layout {
-  size_t o_desc = 0, o_mom = 0, o_mpart = 0, o_X = 0, o_Z = 0, o_cs = 0, o_pl = 0, o_dir = 0;
+  size_t o_desc = 0, o_ann = 0, o_mom = 0, o_mpart = 0, o_X = 0, o_Z = 0, o_cs = 0, o_pl = 0, o_dir = 0;
   std::vector<size_t> o_F, o_tor, o_phiH, o_phiB, o_cpad;
   std::vector<int> patch0;
   int total = 0, chunk = 0;
@@ -552,6 +553,7 @@ static Layout layout_of(const std::vector<const mlc_plan_info*>& g) {
   size_t o = 0;
   auto take = [&](size_t bytes) { size_t at = o; o = align_up(o + bytes); return at; };
   L.o_desc = take(sizeof(ProbDesc) * np);
+  L.o_ann = take(2 * sizeof(AnnProb) * np);   // far-field descriptors: skeleton, coarse
   L.o_mom = take(sizeof(double) * T * I.K);
   L.o_mpart = take(sizeof(double) * T * S * PLANE_MOMENTS);
   L.o_X = take(csz * T * Mh * S * S);
@@ -946,19 +948,52 @@ static void launch_rest(const Group& G, hipStream_t s, Stage stage) {
   };
   constexpr int SK_COLS = ann_block_cols<SkelTiling>(), SK_ROWS = ann_block_rows<SkelTiling>();
   constexpr int CO_COLS = ann_block_cols<CoarseTiling>(), CO_ROWS = ann_block_rows<CoarseTiling>();
+  // far-field sums of every problem in one launch per contraction
   if (stage == FAR && P0->Kann > 0) {
-    TimedScope ts(P0, s, "coarse_annulus");
-    const int q = I0.n / NREF;
+    AnnProb* ap_s = reinterpret_cast<AnnProb*>(G.ws + L.o_ann);
+    AnnProb* ap_c = ap_s + np;
+    std::vector<AnnProb> vs(np), vc(np);
+    int bs = 0, bc = 0;
     for (int k = 0; k < np; ++k) {
       const mlc_plan* P = G.plans[k];
       const mlc_plan_info& I = P->info;
-      const MfmaGeom& g = P->mg_coarse;
-      // moments into the zero-padded lattice both far-field sums read
-      hipLaunchKernelGGL(pad_moments_kernel, dim3(blocks_for(cube(g.L) * g.KP)), dim3(256), 0, s,
-                         mom + int64_t(L.patch0[k]) * I.K, cpad_s(k), cpad_p(k), g.ppa, g.K, g.KP, g.L, g.padlo);
-      const int nk = g.nk0 * g.nk1 * g.nk2;
-      hipLaunchKernelGGL(coarse_annulus_mfma_kernel, dim3(g.nrp / CO_ROWS, (nk + CO_COLS - 1) / CO_COLS),
-                         dim3(64 * CoarseTiling::WAVES), 0, s, P->Tm, cpad_p(k), g, q, I.S_lo, I.Ns, F_of(k));
+      const MfmaGeom& gs = P->mg_skel;
+      const MfmaGeom& gc = P->mg_coarse;
+      vs[k] = AnnProb{P->Am, cpad_s(k), phiB_of(k), gs.ppa, gs.nk0, gs.nk1, gs.nk2, gs.k0lo, gs.k1lo, gs.k2lo, gs.L,
+                      gs.padlo, I.N, I.S_lo, I.Ns, bs};
+      bs += (gs.nk0 * gs.nk1 * gs.nk2 + SK_COLS - 1) / SK_COLS;
+      vc[k] = AnnProb{P->Tm, cpad_p(k), F_of(k), gc.ppa, gc.nk0, gc.nk1, gc.nk2, gc.k0lo, gc.k1lo, gc.k2lo, gc.L,
+                      gc.padlo, I.N, I.S_lo, I.Ns, bc};
+      bc += (gc.nk0 * gc.nk1 * gc.nk2 + CO_COLS - 1) / CO_COLS;
+    }
+    for (int k0 = 0; k0 < np; k0 += ANN_PACK) {
+      AnnPack ps{}, pcq{};
+      ps.count = pcq.count = std::min(ANN_PACK, np - k0);
+      for (int j = 0; j < ps.count; ++j) {
+        ps.d[j] = vs[k0 + j];
+        pcq.d[j] = vc[k0 + j];
+      }
+      hipLaunchKernelGGL(ann_upload_kernel, dim3(1), dim3(ANN_PACK), 0, s, ap_s + k0, ps);
+      hipLaunchKernelGGL(ann_upload_kernel, dim3(1), dim3(ANN_PACK), 0, s, ap_c + k0, pcq);
+    }
+    {
+      TimedScope ts(P0, s, "coarse_annulus");
+      // moments into the zero-padded lattices both far-field sums read
+      for (int k = 0; k < np; ++k) {
+        const mlc_plan_info& I = G.plans[k]->info;
+        const MfmaGeom& g = G.plans[k]->mg_coarse;
+        hipLaunchKernelGGL(pad_moments_kernel, dim3(blocks_for(cube(g.L) * g.KP)), dim3(256), 0, s,
+                           mom + int64_t(L.patch0[k]) * I.K, cpad_s(k), cpad_p(k), g.ppa, g.K, g.KP, g.L, g.padlo);
+      }
+      const MfmaGeom& g = P0->mg_coarse;
+      hipLaunchKernelGGL(coarse_annulus_mfma_kernel, dim3(g.nrp / CO_ROWS, bc), dim3(64 * CoarseTiling::WAVES), 0, s,
+                         ap_c, np, g, I0.n / NREF);
+    }
+    {
+      TimedScope ts(P0, s, "skeleton_annulus");
+      const MfmaGeom& g = P0->mg_skel;
+      hipLaunchKernelGGL(skeleton_annulus_mfma_kernel, dim3(g.nrp / SK_ROWS, bs, 3), dim3(64 * SkelTiling::WAVES), 0,
+                         s, ap_s, np, g, I0.n);
     }
   }
   // coarse solves, the FFTs batched over problems of equal coarse torus
@@ -1017,17 +1052,6 @@ static void launch_rest(const Group& G, hipStream_t s, Stage stage) {
                          0, s, pl, cs, pg, P0->lagw, p0);
   }
   // boundary values on the skeleton (+ phi there), per problem
-  if (stage == FAR && P0->Kann > 0) {
-    TimedScope ts(P0, s, "skeleton_annulus");
-    for (int k = 0; k < np; ++k) {
-      const mlc_plan* P = G.plans[k];
-      const mlc_plan_info& I = P->info;
-      const MfmaGeom& g = P->mg_skel;
-      const int nk = g.nk0 * g.nk1 * g.nk2;
-      hipLaunchKernelGGL(skeleton_annulus_mfma_kernel, dim3(g.nrp / SK_ROWS, (nk + SK_COLS - 1) / SK_COLS, 3),
-                         dim3(64 * SkelTiling::WAVES), 0, s, P->Am, cpad_s(k), g, I.n, I.N, phiB_of(k));
-    }
-  }
   if (stage == FINISH) {
     TimedScope ts(P0, s, "skeleton");
     for (int k = 0; k < np; ++k) {

@@ -369,20 +369,55 @@ __device__ __forceinline__ void annulus_mfma_tiles(const double* __restrict__ Am
   }
 }
 
+// One problem of a batched far-field launch: its far-field table (same
+// layout across a class, values scaled by the problem's h), the lattice
+// geometry that differs between the problems of a class, its padded moments
+// and output, and its first column block (problems' column blocks are
+// consecutive).
+struct AnnProb {
+  const double* tab;    // Am (skeleton) or Tm (coarse)
+  const double* cpad;   // slot-major (skeleton) or mode-major (coarse) moments
+  double* out;          // phi^B (skeleton) or F^H (coarse)
+  int ppa, nk0, nk1, nk2, k0lo, k1lo, k2lo, L, padlo;
+  int N, S_lo, Ns;
+  int blk0;
+};
+constexpr int ANN_PACK = 8;
+struct AnnPack { AnnProb d[ANN_PACK]; int count; };
+__global__ void ann_upload_kernel(AnnProb* __restrict__ dst, AnnPack pk) {
+  if (int(threadIdx.x) < pk.count) dst[threadIdx.x] = pk.d[threadIdx.x];
+}
+// The problem owning column block b, and the class geometry completed with it.
+__device__ __forceinline__ const AnnProb& ann_problem(const AnnProb* __restrict__ ap, int np, int b, MfmaGeom& mg) {
+  int lo = 0, hi = np - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (ap[mid].blk0 <= b) lo = mid; else hi = mid - 1;
+  }
+  const AnnProb& A = ap[lo];
+  mg.ppa = A.ppa;
+  mg.nk0 = A.nk0; mg.nk1 = A.nk1; mg.nk2 = A.nk2;
+  mg.k0lo = A.k0lo; mg.k1lo = A.k1lo; mg.k2lo = A.k2lo;
+  mg.L = A.L; mg.padlo = A.padlo;
+  return A;
+}
+
 // Skeleton: rows r = ra * n + rb of the face plane of normal d = blockIdx.z,
-// columns k = (kd, ka, kb) in [0, ppa]^3; writes the far field into phiB at
-// every canonical skeleton node.
-__global__ void __launch_bounds__(64 * SkelTiling::WAVES) skeleton_annulus_mfma_kernel(const double* __restrict__ Am,
-                                                                                     const double* __restrict__ Cpad,
-                                                                                     MfmaGeom mg, int n, int N,
-                                                                                     double* __restrict__ phiB) {
+// columns k = (kd, ka, kb) in [0, ppa]^3 of the problem owning column block
+// blockIdx.y; writes the far field into its phiB at every canonical
+// skeleton node.
+__global__ void __launch_bounds__(64 * SkelTiling::WAVES) skeleton_annulus_mfma_kernel(const AnnProb* __restrict__ ap,
+                                                                                     int np, MfmaGeom mg, int n) {
   constexpr int ANN_TILES = SkelTiling::TILES;
   const int d = blockIdx.z;
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const AnnProb& A = ann_problem(ap, np, blockIdx.y, mg);
+  const int N = A.N;
+  double* __restrict__ phiB = A.out;
   const int rowbase = blockIdx.x * 64 + wave * 16;
-  const int kbase = blockIdx.y * 16 * ANN_TILES;
+  const int kbase = (int(blockIdx.y) - A.blk0) * 16 * ANN_TILES;
   f64x4 acc[ANN_TILES];
-  annulus_mfma_tiles<ANN_TILES, false>(Am, Cpad, mg, d, rowbase, kbase, acc);
+  annulus_mfma_tiles<ANN_TILES, false>(A.tab, A.cpad, mg, d, rowbase, kbase, acc);
   const int a0 = d == 0 ? 1 : 0, a1 = d == 2 ? 1 : 2, Np = N + 1;
   const int nk = mg.nk0 * mg.nk1 * mg.nk2;
 #pragma unroll
@@ -406,18 +441,20 @@ __global__ void __launch_bounds__(64 * SkelTiling::WAVES) skeleton_annulus_mfma_
   }
 }
 
-// Coarse grid: rows rho in [0, q)^3, columns k over the lattice box; adds the
-// far field to F[c = q k + rho] inside the support box.
-__global__ void __launch_bounds__(64 * CoarseTiling::WAVES) coarse_annulus_mfma_kernel(const double* __restrict__ Tm,
-                                                                                      const double* __restrict__ Cpad,
-                                                                                      MfmaGeom mg, int q, int S_lo,
-                                                                                      int Ns, double* __restrict__ F) {
+// Coarse grid: rows rho in [0, q)^3, columns k over the lattice box of the
+// problem owning column block blockIdx.y; adds the far field to its
+// F[c = q k + rho] inside the support box.
+__global__ void __launch_bounds__(64 * CoarseTiling::WAVES) coarse_annulus_mfma_kernel(const AnnProb* __restrict__ ap,
+                                                                                      int np, MfmaGeom mg, int q) {
   constexpr int ANN_TILES = CoarseTiling::TILES, ANN_WAVES = CoarseTiling::WAVES;
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const AnnProb& A = ann_problem(ap, np, blockIdx.y, mg);
+  const int S_lo = A.S_lo, Ns = A.Ns;
+  double* __restrict__ F = A.out;
   const int rowbase = blockIdx.x * 16;
-  const int kbase = (blockIdx.y * ANN_WAVES + wave) * 16 * ANN_TILES;
+  const int kbase = ((int(blockIdx.y) - A.blk0) * ANN_WAVES + wave) * 16 * ANN_TILES;
   f64x4 acc[ANN_TILES];
-  annulus_mfma_tiles<ANN_TILES, true>(Tm, Cpad, mg, -1, rowbase, kbase, acc);
+  annulus_mfma_tiles<ANN_TILES, true>(A.tab, A.cpad, mg, -1, rowbase, kbase, acc);
   const int nk = mg.nk0 * mg.nk1 * mg.nk2;
 #pragma unroll
   for (int t = 0; t < ANN_TILES; ++t) {
