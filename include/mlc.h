@@ -113,7 +113,7 @@ mlc_status mlc_last_error(mlc_context* ctx, char* buf, size_t len);
 /* Build a plan: validates the problem, then builds (or reuses, per Q and Z)
  * the resident DGF table (appendix A.1), the DGF spectra of the local and
  * coarse convolutions and the far-field tables of the Legendre modes
- * (sec. 4.1: "computed once and stored").  Synchronises the device. */
+ * (sec. 4.1: built once, kept for every solve).  Synchronises the device. */
 mlc_status mlc_plan_create(mlc_context* ctx, const mlc_problem* prob, mlc_plan** out);
 mlc_status mlc_plan_destroy(mlc_plan* plan);
 mlc_status mlc_plan_get_info(const mlc_plan* plan, mlc_plan_info* out);

@@ -1,6 +1,6 @@
 // Setup kernels: the DGF table (appendix A.1), batched axis FFTs of cubic
 // arrays, DGF spectra for Hockney's method (appendix A.2) and the far-field
-// tables of the Legendre modes (sec. 4.1, "computed once and stored").
+// tables of the Legendre modes (sec. 4.1: built once, kept for every solve).
 #pragma once
 #include "common.h"
 
