@@ -530,7 +530,7 @@ static bool same_class(const mlc_plan* a, const mlc_plan* b) {
 //   per problem: F^H, coarse torus (consecutive within equal M_coarse),
 //   phi^H, phi^B.
 struct Layout {
-  size_t o_desc = 0, o_ann = 0, o_mom = 0, o_mpart = 0, o_X = 0, o_Z = 0, o_cs = 0, o_pl = 0, o_dir = 0;
+  size_t o_desc = 0, o_ann = 0, o_flat = 0, o_mom = 0, o_mpart = 0, o_X = 0, o_Z = 0, o_cs = 0, o_pl = 0, o_dir = 0;
   std::vector<size_t> o_F, o_tor, o_phiH, o_phiB, o_cpad;
   std::vector<int> patch0;
   int total = 0, chunk = 0;
@@ -538,6 +538,16 @@ struct Layout {
 };
 
 static const int kMaxGridY = 65535;
+
+// MLC_CONV_CHUNK (largest patch chunk of the local convolutions), read once
+// per process so that every layout of a plan agrees with its workspace size.
+static int conv_chunk_override() {
+  static const int v = [] {
+    const char* e = std::getenv("MLC_CONV_CHUNK");
+    return e ? std::max(1, std::atoi(e)) : 0;
+  }();
+  return v;
+}
 
 static Layout layout_of(const std::vector<const mlc_plan_info*>& g) {
   Layout L;
@@ -554,6 +564,8 @@ static Layout layout_of(const std::vector<const mlc_plan_info*>& g) {
   auto take = [&](size_t bytes) { size_t at = o; o = align_up(o + bytes); return at; };
   L.o_desc = take(sizeof(ProbDesc) * np);
   L.o_ann = take(2 * sizeof(AnnProb) * np);   // far-field descriptors: skeleton, coarse
+  // coarse right-hand side and skeleton descriptors
+  L.o_flat = take((sizeof(CoarseRhsProb<double>) + sizeof(SkelProb<double>)) * np);
   L.o_mom = take(sizeof(double) * T * I.K);
   L.o_mpart = take(sizeof(double) * T * S * PLANE_MOMENTS);
   L.o_X = take(csz * T * Mh * S * S);
@@ -562,7 +574,7 @@ static Layout layout_of(const std::vector<const mlc_plan_info*>& g) {
   // patches one chunk holds every patch, measured faster than two or three
   const size_t per_patch = csz * size_t(Wp) * Mh * I.M;
   int chunk = int(std::max<size_t>(1, (size_t(6) << 30) / per_patch));
-  if (const char* env = std::getenv("MLC_CONV_CHUNK")) chunk = std::max(1, std::atoi(env));
+  if (const int c = conv_chunk_override()) chunk = c;
   chunk = std::min(std::min(chunk, L.total), kMaxGridY);
   const int nchunks = (L.total + chunk - 1) / chunk;
   L.chunk = (L.total + nchunks - 1) / nchunks;
@@ -824,6 +836,17 @@ static bool fft3_coarse(cplx<double>* data, int M, int dir, int nb, int ns, int 
   return false;
 }
 
+// Descriptor tables travel as kernel arguments, FLAT_PACK at a time.
+template <typename D>
+static void upload_flat(D* dst, const std::vector<D>& v, hipStream_t s) {
+  for (size_t k0 = 0; k0 < v.size(); k0 += FLAT_PACK) {
+    FlatPack<D> pk{};
+    pk.count = int(std::min<size_t>(FLAT_PACK, v.size() - k0));
+    for (int j = 0; j < pk.count; ++j) pk.d[j] = v[k0 + j];
+    hipLaunchKernelGGL(flat_upload_kernel<D>, dim3(1), dim3(FLAT_PACK), 0, s, dst + k0, pk);
+  }
+}
+
 static void upload_descs(const Group& G, hipStream_t s) {
   const int np = int(G.plans.size());
   for (int k0 = 0; k0 < np; k0 += DESC_PACK) {
@@ -928,17 +951,22 @@ static void launch_rest(const Group& G, hipStream_t s, Stage stage) {
       hipLaunchKernelGGL(fill_zero_kernel, dim3(blocks_for(cube(G.plans[k]->info.Ns))), dim3(256), 0, s, F_of(k),
                          cube(G.plans[k]->info.Ns));
   }
-  // coarse right-hand side, per problem
+  // coarse right-hand side, every problem in one launch
   if (stage == COARSE) {
-    TimedScope ts(P0, s, "coarse_rhs");
+    auto* pr = reinterpret_cast<CoarseRhsProb<T>*>(G.ws + L.o_flat);
+    std::vector<CoarseRhsProb<T>> v(np);
+    int64_t total = 0;
     for (int k = 0; k < np; ++k) {
       const mlc_plan* P = G.plans[k];
       const mlc_plan_info& I = P->info;
       CoarseGeom cg{I.n, I.patches_per_axis, P->Kann, I.d_alpha, I.d_beta, I.e, I.Wc, I.S_lo, I.Ns, P->Wbc,
                     1.0 / (I.H * I.H)};
-      hipLaunchKernelGGL(coarse_rhs_kernel<T>, dim3(blocks_for(cube(I.Ns))), dim3(256), 0, s,
-                         cs + L.patch0[k] * csz, st, cg, F_of(k));
+      v[k] = CoarseRhsProb<T>{cs + L.patch0[k] * csz, F_of(k), cg, total};
+      total += cube(I.Ns);
     }
+    upload_flat(pr, v, s);
+    TimedScope ts(P0, s, "coarse_rhs");
+    hipLaunchKernelGGL(coarse_rhs_kernel<T>, dim3(blocks_for(total)), dim3(256), 0, s, pr, np, total, st);
   }
   // padded moment lattices: slot-major (skeleton sums), then mode-major (coarse sums)
   auto cpad_s = [&](int k) { return reinterpret_cast<double*>(G.ws + L.o_cpad[k]); };
@@ -1052,17 +1080,23 @@ static void launch_rest(const Group& G, hipStream_t s, Stage stage) {
                          0, s, pl, cs, pg, P0->lagw, p0);
   }
   // boundary values on the skeleton (+ phi there), per problem
+  // skeleton boundary values (+ phi there), every problem in one launch
   if (stage == FINISH) {
-    TimedScope ts(P0, s, "skeleton");
+    auto* pr = reinterpret_cast<SkelProb<T>*>(G.ws + L.o_flat + sizeof(CoarseRhsProb<double>) * np);
+    std::vector<SkelProb<T>> v(np);
+    int64_t total = 0;
     for (int k = 0; k < np; ++k) {
       const mlc_plan* P = G.plans[k];
       const mlc_plan_info& I = P->info;
       SkelGeom sg{I.N, I.n, I.patches_per_axis, P->Kann, I.d_alpha, I.d_beta, I.b, I.Wa, P->P0, I.nplanes_a, P->Wb,
                   P->P0b, P->nplb, I.O_lo, I.No, I.h * I.h / 12.0};
-      int64_t cnt = int64_t(3) * (I.N / I.n + 1) * (I.N + 1) * (I.N + 1);
-      hipLaunchKernelGGL(skeleton_kernel<T>, dim3(blocks_for(cnt)), dim3(256), 0, s, phiH_of(k),
-                         pl + L.patch0[k] * plsz, G.f[k], sg, P->lagw, P->Kann > 0 ? 1 : 0, phiB_of(k), G.phi[k]);
+      v[k] = SkelProb<T>{phiH_of(k), pl + L.patch0[k] * plsz, G.f[k], phiB_of(k), G.phi[k], sg, total};
+      total += int64_t(3) * (I.N / I.n + 1) * (I.N + 1) * (I.N + 1);
     }
+    upload_flat(pr, v, s);
+    TimedScope ts(P0, s, "skeleton");
+    hipLaunchKernelGGL(skeleton_kernel<T>, dim3(blocks_for(total)), dim3(256), 0, s, pr, np, total, P0->lagw,
+                       P0->Kann > 0 ? 1 : 0);
   }
   // Dirichlet solves + Mehrstellen correction on the patch interiors, all patches
   if (stage == FINISH) {
@@ -1163,6 +1197,7 @@ extern "C" mlc_status mlc_solve(mlc_plan* plan, const double* f, double* phi, vo
   G.f = {f};
   G.phi = {phi};
   G.L = layout_of(infos_of(G.plans));
+  if (ws_bytes < G.L.bytes) return fail(plan->ctx, MLC_ERR_INVALID_ARG, "workspace too small");
   G.ws = static_cast<char*>(workspace);
   G.desc = reinterpret_cast<ProbDesc*>(G.ws + G.L.o_desc);
   return enqueue_group(G, static_cast<hipStream_t>(stream));

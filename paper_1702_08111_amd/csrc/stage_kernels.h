@@ -45,14 +45,44 @@ struct CoarseGeom {
   double invH2;
 };
 
+// Per-problem data of the kernels that run over all problems of a batch in
+// one flat launch: problem k owns the thread indices [start_k, start_{k+1}).
+template <typename D>
+__device__ __forceinline__ const D& flat_problem(const D* __restrict__ pr, int np, int64_t idx) {
+  int lo = 0, hi = np - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (pr[mid].start <= idx) lo = mid; else hi = mid - 1;
+  }
+  return pr[lo];
+}
+constexpr int FLAT_PACK = 8;
+template <typename D> struct FlatPack { D d[FLAT_PACK]; int count; };
+template <typename D>
+__global__ void flat_upload_kernel(D* __restrict__ dst, FlatPack<D> pk) {
+  if (int(threadIdx.x) < pk.count) dst[threadIdx.x] = pk.d[threadIdx.x];
+}
+
+template <typename T> struct CoarseRhsProb {
+  const T* cs;      // the problem's patches' coarse samples
+  double* F;        // its F^H
+  CoarseGeom g;
+  int64_t start;
+};
+
 // Inner part of F^H: F[c] += sum over patches i with c in C(Omega_alpha(i)) of
 // Delta^H of phi_i's coarse samples (sec. 4.1 eq. FDLD, first case), patches
-// visited in a fixed order.
+// visited in a fixed order.  One thread per coarse point of every problem.
 template <typename T>
-__global__ void __launch_bounds__(256) coarse_rhs_kernel(const T* __restrict__ cs, Stencil st, CoarseGeom g,
-                                                         double* __restrict__ F) {
-  int64_t idx = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-  if (idx >= cube(g.Ns)) return;
+__global__ void __launch_bounds__(256) coarse_rhs_kernel(const CoarseRhsProb<T>* __restrict__ pr, int np,
+                                                         int64_t total, Stencil st) {
+  const int64_t gidx = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (gidx >= total) return;
+  const CoarseRhsProb<T>& pb = flat_problem(pr, np, gidx);
+  const CoarseGeom g = pb.g;
+  const T* __restrict__ cs = pb.cs;
+  double* __restrict__ F = pb.F;
+  const int64_t idx = gidx - pb.start;
   int c[3];
   c[2] = g.S_lo + int(idx % g.Ns);
   c[1] = g.S_lo + int((idx / g.Ns) % g.Ns);
@@ -191,6 +221,15 @@ __global__ void __launch_bounds__(256) plane_delta_kernel(T* __restrict__ planes
 struct SkelGeom {
   int N, n, ppa, K, da, db, b, Wa, P0, npl, Wb, P0b, nplb, O_lo, No;
   double c2h2;   // C2 h^2
+};
+template <typename T> struct SkelProb {
+  const double* phiH;
+  const T* delta;   // the problem's patches' plane corrections
+  const double* f;
+  double* phiB;
+  double* phi;
+  SkelGeom g;
+  int64_t start;
 };
 
 // ---------------------------------------------- annulus sums on MFMA ----
@@ -478,14 +517,20 @@ __global__ void __launch_bounds__(64 * CoarseTiling::WAVES) coarse_annulus_mfma_
 // phi[g] = phi^B[g] + C2 h^2 f[g] (sec. 4.1 eqs. mlcfulldiscr,
 // mcapplicationfulldiscr).
 template <typename T>
-__global__ void __launch_bounds__(256) skeleton_kernel(const double* __restrict__ phiH, const T* __restrict__ delta,
-                                                       const double* __restrict__ f, SkelGeom g, LagW lw,
-                                                       int annulus, double* __restrict__ phiB,
-                                                       double* __restrict__ phi) {
+__global__ void __launch_bounds__(256) skeleton_kernel(const SkelProb<T>* __restrict__ pr, int np, int64_t total,
+                                                       LagW lw, int annulus) {
+  const int64_t gidx = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (gidx >= total) return;
+  const SkelProb<T>& pb = flat_problem(pr, np, gidx);
+  const SkelGeom g = pb.g;
+  const double* __restrict__ phiH = pb.phiH;
+  const T* __restrict__ delta = pb.delta;
+  const double* __restrict__ f = pb.f;
+  double* __restrict__ phiB = pb.phiB;
+  double* __restrict__ phi = pb.phi;
   const int N = g.N, n = g.n, Np = N + 1;
   const int planes = N / n + 1;
-  int64_t idx = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-  if (idx >= int64_t(3) * planes * Np * Np) return;
+  const int64_t idx = gidx - pb.start;
   int v = int(idx % Np), u = int((idx / Np) % Np), j = int((idx / (int64_t(Np) * Np)) % planes);
   int d = int(idx / (int64_t(Np) * Np * planes));
   int a0 = d == 0 ? 1 : 0, a1 = d == 2 ? 1 : 2;
