@@ -257,6 +257,13 @@ __global__ void __launch_bounds__(256) conv_yz_kernel(const cplx<T>* __restrict_
     const int zi = zmap[ta + R2 * j1];
     zoff[j1] = zi >= 0 ? zi * Mh * M : -1;
   }
+  // the lane's twiddles, the same at every column step, held in registers:
+  // w^(ta k1) after the R1-point pass, w^(-t sb) after the R2-point pass
+  cplx<T> twA[R1], twB[R2];
+#pragma unroll
+  for (int k1 = 0; k1 < R1; ++k1) twA[k1] = ta < R2 ? tw[ta * k1] : cplx<T>{T(1), T(0)};
+#pragma unroll
+  for (int t = 0; t < R2; ++t) twB[t] = conjw(tw[t * sb]);
 #pragma unroll 1
   for (int c0 = wave * LC; c0 < M; c0 += (blockDim.x / 64) * LC) {
     if (actA) {
@@ -272,7 +279,7 @@ __global__ void __launch_bounds__(256) conv_yz_kernel(const cplx<T>* __restrict_
       dft_reg_nz<T, R1, 1, NJ>(v);
       cplx<T>* e = ex + ca * XL + ta * (R1 + 1);
 #pragma unroll
-      for (int k1 = 0; k1 < R1; ++k1) e[k1] = (k1 == 0 || ta == 0) ? v[k1] : cmul(v[k1], tw[ta * k1]);
+      for (int k1 = 0; k1 < R1; ++k1) e[k1] = (k1 == 0 || ta == 0) ? v[k1] : cmul(v[k1], twA[k1]);
     }
     wave_sync();
     cplx<T> u[R2];
@@ -292,7 +299,7 @@ __global__ void __launch_bounds__(256) conv_yz_kernel(const cplx<T>* __restrict_
       dft_reg<T, R2, -1>(u);
 #pragma unroll
       for (int t = 1; t < R2; ++t)
-        if (sb) u[t] = cmul(u[t], conjw(tw[t * sb]));
+        if (sb) u[t] = cmul(u[t], twB[t]);
     }
     wave_sync();
     if (actB) {
@@ -451,12 +458,17 @@ __global__ void __launch_bounds__((OutBatch<T, M>::NT)) conv_out_kernel(const cp
         if (ymap[j1] >= 0) arow[ymap[j1]] = v[j1];
     }
   };
-  // y pass, first half: R2-point DFT of one line's column s, twiddled, to ex
+  // the lane's inverse twiddles w^(-t s1) of both first-half passes, held in
+  // registers
+  cplx<T> tws[R2];
+#pragma unroll
+  for (int t = 0; t < R2; ++t) tws[t] = conjw(tw[t * s1]);
+  // y pass, first half: R2-point DFT of one line's column s (= s1), twiddled, to ex
   auto y_pass1 = [&](cplx<T>* u, cplx<T>* ex, int s, int r) {
     dft_reg<T, R2, -1>(u);
 #pragma unroll
     for (int t = 0; t < R2; ++t) {
-      cplx<T> w = (s && t) ? cmul(u[t], conjw(tw[t * s])) : u[t];
+      cplx<T> w = (s && t) ? cmul(u[t], tws[t]) : u[t];
       ex[r * XL + s * (R2 + 1) + t] = w;
     }
   };
@@ -516,7 +528,7 @@ __global__ void __launch_bounds__((OutBatch<T, M>::NT)) conv_out_kernel(const cp
     dft_reg<T, R2, -1>(u);
 #pragma unroll
     for (int t = 0; t < R2; ++t) {
-      cplx<T> w = (s && t) ? cmul(u[t], conjw(tw[t * s])) : u[t];
+      cplx<T> w = (s && t) ? cmul(u[t], tws[t]) : u[t];
       ex[c * XL + s * (R2 + 1) + t] = w;
     }
   };
