@@ -207,6 +207,10 @@ __global__ void __launch_bounds__(256) conv_yz_kernel(const cplx<T>* __restrict_
       }
   }
   // ---- FFT along y of the S source rows (CB rows per batch) ----
+  // the thread's twiddles w^(t k1) of every batch, held in registers
+  cplx<T> twY[R1];
+#pragma unroll
+  for (int k1 = 0; k1 < R1; ++k1) twY[k1] = tw[(tid % R2) * k1];
 #pragma unroll 1
   for (int rb = 0, jr = 0; rb < S; rb += CB, ++jr) {
     if (tid < CB * R2) {
@@ -223,7 +227,7 @@ __global__ void __launch_bounds__(256) conv_yz_kernel(const cplx<T>* __restrict_
       dft_reg_nz<T, R1, 1, NJ>(v);
       cplx<T>* ex = Ex + r * XL + t * (R1 + 1);
 #pragma unroll
-      for (int k1 = 0; k1 < R1; ++k1) ex[k1] = (k1 == 0 || t == 0) ? v[k1] : cmul(v[k1], tw[t * k1]);
+      for (int k1 = 0; k1 < R1; ++k1) ex[k1] = (k1 == 0 || t == 0) ? v[k1] : cmul(v[k1], twY[k1]);
     }
     __syncthreads();
     if (tid < CB * R1) {
