@@ -721,14 +721,21 @@ __global__ void __launch_bounds__(64 * DIR_WAVES) dirichlet_mfma_kernel(const Pr
         j = (r & 1) ? m - 1 : 0;
       }
       const int l0 = u + 1, l1 = i + 1, l2 = j + 1;
+      // every neighbour is a node of the patch box, so all 27 loads are
+      // issued together; those off the boundary (whose phi^B is not
+      // defined) are selected away, the boundary ones summed in order
       double corr = 0.0;
+#pragma unroll
       for (int s0 = -1; s0 <= 1; ++s0)
+#pragma unroll
         for (int s1 = -1; s1 <= 1; ++s1)
+#pragma unroll
           for (int s2 = -1; s2 <= 1; ++s2) {
-            int k0 = l0 + s0, k1 = l1 + s1, k2 = l2 + s2;
-            if (!(k0 == 0 || k0 == g.n || k1 == 0 || k1 == g.n || k2 == 0 || k2 == g.n)) continue;
-            int nz = (s0 != 0) + (s1 != 0) + (s2 != 0);
-            corr += g.st.b[nz] * phiB[pbase + (int64_t(k0) * Np + k1) * Np + k2];
+            const int k0 = l0 + s0, k1 = l1 + s1, k2 = l2 + s2;
+            const bool bnd = k0 == 0 || k0 == g.n || k1 == 0 || k1 == g.n || k2 == 0 || k2 == g.n;
+            const int nz = (s0 != 0) + (s1 != 0) + (s2 != 0);
+            const double x = phiB[pbase + (int64_t(k0) * Np + k1) * Np + k2];
+            corr = fma(bnd ? g.st.b[nz] : 0.0, bnd ? x : 0.0, corr);
           }
       L[i * 33 + j] -= corr;
     }
