@@ -703,13 +703,30 @@ __global__ void __launch_bounds__(64 * DIR_WAVES) dirichlet_mfma_kernel(const Pr
   for (int r = 0; r < 16; ++r) L[(ih + 2 * r) * 33 + jc] = rows[r];
   if constexpr (PASS == 0) {
     // boundary terms, only at nodes next to the patch boundary: the whole
-    // slab if it is the first or last, else its ring of 4(m-1) nodes
-    wave_sync_lds();
-    const bool end_slab = u == 0 || u == m - 1;
-    const int cnt = live ? (end_slab ? m * m : 4 * (m - 1)) : 0;
-    for (int q = lane; q < cnt; q += 64) {
+    // slab if it is the first or last of its patch, else its ring of
+    // 4(m-1) nodes.  The block's threads share the node lists of all its
+    // slabs (a first or last slab has eight times the nodes of the others).
+    __shared__ const double* sl_phiB[DIR_WAVES];
+    __shared__ int64_t sl_base[DIR_WAVES], sl_Np[DIR_WAVES];
+    __shared__ int sl_u[DIR_WAVES], sl_cnt[DIR_WAVES];
+    if (lane == 0) {
+      const bool end_slab = u == 0 || u == m - 1;
+      sl_phiB[wave] = D.phiB;
+      sl_base[wave] = pbase;
+      sl_Np[wave] = Np;
+      sl_u[wave] = u;
+      sl_cnt[wave] = live ? (end_slab ? m * m : 4 * (m - 1)) : 0;
+    }
+    __syncthreads();   // every slab's L and the node lists
+    int total = 0;
+#pragma unroll
+    for (int w = 0; w < DIR_WAVES; ++w) total += sl_cnt[w];
+    for (int q0 = threadIdx.x; q0 < total; q0 += blockDim.x) {
+      int w = 0, q = q0;
+      while (q >= sl_cnt[w]) q -= sl_cnt[w++];
+      const int uw = sl_u[w];
       int i, j;
-      if (end_slab) {
+      if (uw == 0 || uw == m - 1) {
         i = q / m;
         j = q % m;
       } else if (q < 2 * m) {
@@ -720,7 +737,9 @@ __global__ void __launch_bounds__(64 * DIR_WAVES) dirichlet_mfma_kernel(const Pr
         i = 1 + r / 2;
         j = (r & 1) ? m - 1 : 0;
       }
-      const int l0 = u + 1, l1 = i + 1, l2 = j + 1;
+      const auto* phiBw = gbl(sl_phiB[w]);
+      const int64_t base = sl_base[w], Npw = sl_Np[w];
+      const int l0 = uw + 1, l1 = i + 1, l2 = j + 1;
       // every neighbour is a node of the patch box, so all 27 loads are
       // issued together; those off the boundary (whose phi^B is not
       // defined) are selected away, the boundary ones summed in order
@@ -734,10 +753,10 @@ __global__ void __launch_bounds__(64 * DIR_WAVES) dirichlet_mfma_kernel(const Pr
             const int k0 = l0 + s0, k1 = l1 + s1, k2 = l2 + s2;
             const bool bnd = k0 == 0 || k0 == g.n || k1 == 0 || k1 == g.n || k2 == 0 || k2 == g.n;
             const int nz = (s0 != 0) + (s1 != 0) + (s2 != 0);
-            const double x = phiB[pbase + (int64_t(k0) * Np + k1) * Np + k2];
+            const double x = phiBw[base + (int64_t(k0) * Npw + k1) * Npw + k2];
             corr = fma(bnd ? g.st.b[nz] : 0.0, bnd ? x : 0.0, corr);
           }
-      L[i * 33 + j] -= corr;
+      Ls[w][i * 33 + j] -= corr;
     }
   }
   __syncthreads();   // Sm; from here on each wave touches only its own slab
