@@ -552,12 +552,20 @@ __global__ void __launch_bounds__(256) skeleton_kernel(const SkelProb<T>* __rest
     double s = 0.0;
     for (int ku = ku0; ku <= ku1; ++ku) {
       double rs = 0.0;
-      for (int kv = kv0; kv <= kv1; ++kv) {
-        int c[3];
-        c[d] = cd;
-        c[a0] = U0 + ku - g.O_lo;
-        c[a1] = V0 + kv - g.O_lo;
-        rs += wv[kv + g.b] * phiH[(int64_t(c[0]) * g.No + c[1]) * g.No + c[2]];
+      // four taps at a time (loads issued together); a slot past kv1
+      // repeats that tap with weight zero
+      for (int kvb = kv0; kvb <= kv1; kvb += 4) {
+#pragma unroll
+        for (int t = 0; t < 4; ++t) {
+          const bool valid = kvb + t <= kv1;
+          const int kv = valid ? kvb + t : kv1;
+          int c[3];
+          c[d] = cd;
+          c[a0] = U0 + ku - g.O_lo;
+          c[a1] = V0 + kv - g.O_lo;
+          const double x = phiH[(int64_t(c[0]) * g.No + c[1]) * g.No + c[2]];
+          rs = fma(valid ? wv[kv + g.b] : 0.0, valid ? x : 0.0, rs);
+        }
       }
       s += wu[ku + g.b] * rs;
     }
@@ -573,11 +581,20 @@ __global__ void __launch_bounds__(256) skeleton_kernel(const SkelProb<T>* __rest
   const int Wa = g.Wa;
   for (int i0 = lo[0]; i0 <= hi[0]; ++i0)
     for (int i1 = lo[1]; i1 <= hi[1]; ++i1)
-      for (int i2 = lo[2]; i2 <= hi[2]; ++i2) {
-        int r[3] = {gg[0] - n * i0, gg[1] - n * i1, gg[2] - n * i2};
-        int pidx = (i0 * g.ppa + i1) * g.ppa + i2;
-        int jj = (r[d] - g.P0) / n;
-        val += double(delta[((((int64_t(pidx) * 3 + d) * g.npl + jj) * Wa + (r[a0] + g.da)) * Wa) + (r[a1] + g.da)]);
+      // four patches of the last axis at a time (loads issued together); a
+      // slot past hi[2] repeats that patch and adds an exact zero
+      for (int i2b = lo[2]; i2b <= hi[2]; i2b += 4) {
+#pragma unroll
+        for (int t2 = 0; t2 < 4; ++t2) {
+          const bool valid = i2b + t2 <= hi[2];
+          const int i2 = valid ? i2b + t2 : hi[2];
+          const int r[3] = {gg[0] - n * i0, gg[1] - n * i1, gg[2] - n * i2};
+          const int pidx = (i0 * g.ppa + i1) * g.ppa + i2;
+          const int jj = (r[d] - g.P0) / n;
+          const double x =
+              double(delta[((((int64_t(pidx) * 3 + d) * g.npl + jj) * Wa + (r[a0] + g.da)) * Wa) + (r[a1] + g.da)]);
+          val += valid ? x : 0.0;
+        }
       }
   int64_t node = (int64_t(gg[0]) * Np + gg[1]) * Np + gg[2];
   if (annulus) val += phiB[node];
