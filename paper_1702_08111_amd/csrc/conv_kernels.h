@@ -423,197 +423,197 @@ __global__ void __launch_bounds__((OutBatch<T, M>::NT)) conv_out_kernel(const cp
   }
 #pragma unroll 1
   for (int q = 0; q < ZPB; ++q) {
-  const int zi = zi0 + q;
-  if (zi >= Wp) break;   // uniform over the block
-  if (tid < 64) {
-    // compact the two row lists in ascending order with wave ballots
-    const int zf = oflg[zi];
-    int a = 0, c = 0;
-    const uint64_t below = (uint64_t(1) << tid) - 1;
-    for (int base = ylo; base < yhi; base += 64) {
-      const int yi = base + tid;
-      const int yf = yi < yhi ? oflg[yi] : 0;
-      // z-plane rows in Omega_alpha, coarse rows of a coarse z, y-plane rows
-      const bool full = ((zf & 4) && (yf & 1)) || ((zf & 2) && (yf & 2)) || ((zf & 1) && (yf & 4));
-      const bool col = !full && (zf & 1) && (yf & 1);   // x-plane columns only
-      const uint64_t mf = __ballot(full), mc = __ballot(col);
-      if (full) frow[a + __popcll(mf & below)] = short(yi);
-      if (col) crow[c + __popcll(mc & below)] = short(yi);
-      a += __popcll(mf);
-      c += __popcll(mc);
+    const int zi = zi0 + q;
+    if (zi >= Wp) break;   // uniform over the block
+    if (tid < 64) {
+      // compact the two row lists in ascending order with wave ballots
+      const int zf = oflg[zi];
+      int a = 0, c = 0;
+      const uint64_t below = (uint64_t(1) << tid) - 1;
+      for (int base = ylo; base < yhi; base += 64) {
+        const int yi = base + tid;
+        const int yf = yi < yhi ? oflg[yi] : 0;
+        // z-plane rows in Omega_alpha, coarse rows of a coarse z, y-plane rows
+        const bool full = ((zf & 4) && (yf & 1)) || ((zf & 2) && (yf & 2)) || ((zf & 1) && (yf & 4));
+        const bool col = !full && (zf & 1) && (yf & 1);   // x-plane columns only
+        const uint64_t mf = __ballot(full), mc = __ballot(col);
+        if (full) frow[a + __popcll(mf & below)] = short(yi);
+        if (col) crow[c + __popcll(mc & below)] = short(yi);
+        a += __popcll(mf);
+        c += __popcll(mc);
+      }
+      if (tid == 0) {
+        nfull = a;
+        ncols = c;
+      }
     }
-    if (tid == 0) {
-      nfull = a;
-      ncols = c;
-    }
-  }
-  // y pass, second half: one line's R1-point DFT in R2 lanes (lanes (t, r)),
-  // kept outputs into A
-  // (ymap[j1] = omap[t + R2 j1], the lane's output slots, held in registers)
-  auto y_pass2 = [&](const cplx<T>* ex, int t, int r, int kx, const short* ymap) {
-    cplx<T> v[R1];
+    // y pass, second half: one line's R1-point DFT in R2 lanes (lanes (t, r)),
+    // kept outputs into A
+    // (ymap[j1] = omap[t + R2 j1], the lane's output slots, held in registers)
+    auto y_pass2 = [&](const cplx<T>* ex, int t, int r, int kx, const short* ymap) {
+      cplx<T> v[R1];
 #pragma unroll
-    for (int s = 0; s < R1; ++s) v[s] = ex[r * XL + s * (R2 + 1) + t];
-    dft_reg<T, R1, -1>(v);
-    if (kx < Mh) {
-      cplx<T>* arow = A + kx * Wq;
+      for (int s = 0; s < R1; ++s) v[s] = ex[r * XL + s * (R2 + 1) + t];
+      dft_reg<T, R1, -1>(v);
+      if (kx < Mh) {
+        cplx<T>* arow = A + kx * Wq;
 #pragma unroll
-      for (int j1 = 0; j1 < R1; ++j1)
-        if (ymap[j1] >= 0) arow[ymap[j1]] = v[j1];
-    }
-  };
-  // the lane's inverse twiddles w^(-t s1) of both first-half passes, held in
-  // registers
-  cplx<T> tws[R2];
+        for (int j1 = 0; j1 < R1; ++j1)
+          if (ymap[j1] >= 0) arow[ymap[j1]] = v[j1];
+      }
+    };
+    // the lane's inverse twiddles w^(-t s1) of both first-half passes, held in
+    // registers
+    cplx<T> tws[R2];
 #pragma unroll
-  for (int t = 0; t < R2; ++t) tws[t] = conjw(tw[t * s1]);
-  // y pass, first half: R2-point DFT of one line's column s (= s1), twiddled, to ex
-  auto y_pass1 = [&](cplx<T>* u, cplx<T>* ex, int s, int r) {
-    dft_reg<T, R2, -1>(u);
+    for (int t = 0; t < R2; ++t) tws[t] = conjw(tw[t * s1]);
+    // y pass, first half: R2-point DFT of one line's column s (= s1), twiddled, to ex
+    auto y_pass1 = [&](cplx<T>* u, cplx<T>* ex, int s, int r) {
+      dft_reg<T, R2, -1>(u);
 #pragma unroll
-    for (int t = 0; t < R2; ++t) {
-      cplx<T> w = (s && t) ? cmul(u[t], tws[t]) : u[t];
-      ex[r * XL + s * (R2 + 1) + t] = w;
-    }
-  };
-  __syncthreads();
-  // ---- inverse FFT along y for every kx ----
-  {
-    short ymap[R1];
+      for (int t = 0; t < R2; ++t) {
+        cplx<T> w = (s && t) ? cmul(u[t], tws[t]) : u[t];
+        ex[r * XL + s * (R2 + 1) + t] = w;
+      }
+    };
+    __syncthreads();
+    // ---- inverse FFT along y for every kx ----
+    {
+      short ymap[R1];
 #pragma unroll
-    for (int j1 = 0; j1 < R1; ++j1) {
-      const int k = omap[t2 + R2 * j1];
-      ymap[j1] = (k >= ylo && k < yhi) ? short(k - ylo) : short(-1);
-    }
+      for (int j1 = 0; j1 < R1; ++j1) {
+        const int k = omap[t2 + R2 * j1];
+        ymap[j1] = (k >= ylo && k < yhi) ? short(k - ylo) : short(-1);
+      }
 #pragma unroll 1
-    for (int kb = wave * LW; kb < Mh; kb += NW * LW) {
-      cplx<T> un[R2];
-      load_lines(un, kb + NW * LW);   // next step's lines in flight meanwhile
-      if (act1) y_pass1(u0, ex, s1, r1);
-      wave_sync();
-      if (act2) y_pass2(ex, t2, r2, kb + r2, ymap);
-      wave_sync();
+      for (int kb = wave * LW; kb < Mh; kb += NW * LW) {
+        cplx<T> un[R2];
+        load_lines(un, kb + NW * LW);   // next step's lines in flight meanwhile
+        if (act1) y_pass1(u0, ex, s1, r1);
+        wave_sync();
+        if (act2) y_pass2(ex, t2, r2, kb + r2, ymap);
+        wave_sync();
 #pragma unroll
-      for (int k2 = 0; k2 < R2; ++k2) u0[k2] = un[k2];
-    }
-  }
-  // the next plane's first lines stay in flight through this plane's x pass
-  if (q + 1 < ZPB && zi + 1 < Wp) {
-    zin += int64_t(Mh) * M;
-    load_lines(u0, wave * LW);
-  }
-  __syncthreads();
-  const int z = ocrd[zi];
-  const bool zin_a = oflg[zi] & 1, zc = oflg[zi] & 2, zpl = oflg[zi] & 4;
-  const int npl = g.npl, Wa = g.Wa, Wc = g.Wc;
-  T* cbase = coarse + int64_t(p) * Wc * Wc * Wc;
-  T* pbase = planes + int64_t(p) * 3 * npl * Wa * Wa;
-  const int nf = nfull, ncl = ncols;
-  // ---- Hermitian inverse along x of the full rows: two real lines per complex line ----
-  // first half: pair-line c's column s (rows frow[2c], frow[2c+1])
-  auto x_pass1 = [&](cplx<T>* ex, int s, int c, int pi) {
-    const int i1 = 2 * pi;
-    const int y1 = i1 < nf ? frow[i1] : Wp, y2 = i1 + 1 < nf ? frow[i1 + 1] : Wp;
-    cplx<T> u[R2];
-#pragma unroll
-    for (int k2 = 0; k2 < R2; ++k2) {
-      int k = s + R1 * k2;
-      cplx<T> h1 = {T(0), T(0)}, h2 = {T(0), T(0)};
-      if (k < Mh) {
-        if (y1 < Wp) h1 = A[k * Wq + (y1 - ylo)];
-        if (y2 < Wp) h2 = A[k * Wq + (y2 - ylo)];
-      } else {
-        if (y1 < Wp) h1 = conjw(A[(M - k) * Wq + (y1 - ylo)]);
-        if (y2 < Wp) h2 = conjw(A[(M - k) * Wq + (y2 - ylo)]);
-      }
-      if (k == 0 || k == M / 2) { h1.y = T(0); h2.y = T(0); }   // real DC / Nyquist
-      u[k2] = {h1.x - h2.y, h1.y + h2.x};                        // h1 + i h2
-    }
-    dft_reg<T, R2, -1>(u);
-#pragma unroll
-    for (int t = 0; t < R2; ++t) {
-      cplx<T> w = (s && t) ? cmul(u[t], tws[t]) : u[t];
-      ex[c * XL + s * (R2 + 1) + t] = w;
-    }
-  };
-  // second half: outputs of pair-line c (global pair index pi).  Per row,
-  // the base offsets of its destinations (or -1); per x slot, its offsets
-  // along the row (xinfo) -- so each output is a few adds and stores.
-  auto x_pass2 = [&](const cplx<T>* ex, int t, int c, int pi) {
-    cplx<T> v[R1];
-#pragma unroll
-    for (int s = 0; s < R1; ++s) v[s] = ex[c * XL + s * (R2 + 1) + t];
-    dft_reg<T, R1, -1>(v);
-    int rowC[2], rowZ[2], rowY[2], rowX[2];
-#pragma unroll
-    for (int h = 0; h < 2; ++h) {
-      rowC[h] = rowZ[h] = rowY[h] = rowX[h] = -1;
-      const int fi = 2 * pi + h;
-      if (fi < nf) {
-        const int yi = frow[fi];
-        const int y = ocrd[yi], yf = oflg[yi];
-        if (zc && (yf & 2)) rowC[h] = (((z + g.e) / NREF) * Wc + (y + g.e) / NREF) * Wc;
-        if (zpl && (yf & 1)) rowZ[h] = ((z - g.P0) / n * Wa + (y + g.da)) * Wa;
-        if (zin_a && (yf & 1) && (yf & 4)) rowY[h] = ((npl + (y - g.P0) / n) * Wa + (z + g.da)) * Wa;
-        if (zin_a && (yf & 1)) rowX[h] = (2 * npl * Wa + (z + g.da)) * Wa + (y + g.da);
+        for (int k2 = 0; k2 < R2; ++k2) u0[k2] = un[k2];
       }
     }
+    // the next plane's first lines stay in flight through this plane's x pass
+    if (q + 1 < ZPB && zi + 1 < Wp) {
+      zin += int64_t(Mh) * M;
+      load_lines(u0, wave * LW);
+    }
+    __syncthreads();
+    const int z = ocrd[zi];
+    const bool zin_a = oflg[zi] & 1, zc = oflg[zi] & 2, zpl = oflg[zi] & 4;
+    const int npl = g.npl, Wa = g.Wa, Wc = g.Wc;
+    T* cbase = coarse + int64_t(p) * Wc * Wc * Wc;
+    T* pbase = planes + int64_t(p) * 3 * npl * Wa * Wa;
+    const int nf = nfull, ncl = ncols;
+    // ---- Hermitian inverse along x of the full rows: two real lines per complex line ----
+    // first half: pair-line c's column s (rows frow[2c], frow[2c+1])
+    auto x_pass1 = [&](cplx<T>* ex, int s, int c, int pi) {
+      const int i1 = 2 * pi;
+      const int y1 = i1 < nf ? frow[i1] : Wp, y2 = i1 + 1 < nf ? frow[i1 + 1] : Wp;
+      cplx<T> u[R2];
 #pragma unroll
-    for (int j1 = 0; j1 < R1; ++j1) {
-      const uint64_t xw = xinfo[t + R2 * j1];
-      const int xda = int(short(xw & 0xffff)), xcc = int(short((xw >> 16) & 0xffff));
-      const int xpl = int(short((xw >> 32) & 0xffff));
+      for (int k2 = 0; k2 < R2; ++k2) {
+        int k = s + R1 * k2;
+        cplx<T> h1 = {T(0), T(0)}, h2 = {T(0), T(0)};
+        if (k < Mh) {
+          if (y1 < Wp) h1 = A[k * Wq + (y1 - ylo)];
+          if (y2 < Wp) h2 = A[k * Wq + (y2 - ylo)];
+        } else {
+          if (y1 < Wp) h1 = conjw(A[(M - k) * Wq + (y1 - ylo)]);
+          if (y2 < Wp) h2 = conjw(A[(M - k) * Wq + (y2 - ylo)]);
+        }
+        if (k == 0 || k == M / 2) { h1.y = T(0); h2.y = T(0); }   // real DC / Nyquist
+        u[k2] = {h1.x - h2.y, h1.y + h2.x};                        // h1 + i h2
+      }
+      dft_reg<T, R2, -1>(u);
+#pragma unroll
+      for (int t = 0; t < R2; ++t) {
+        cplx<T> w = (s && t) ? cmul(u[t], tws[t]) : u[t];
+        ex[c * XL + s * (R2 + 1) + t] = w;
+      }
+    };
+    // second half: outputs of pair-line c (global pair index pi).  Per row,
+    // the base offsets of its destinations (or -1); per x slot, its offsets
+    // along the row (xinfo) -- so each output is a few adds and stores.
+    auto x_pass2 = [&](const cplx<T>* ex, int t, int c, int pi) {
+      cplx<T> v[R1];
+#pragma unroll
+      for (int s = 0; s < R1; ++s) v[s] = ex[c * XL + s * (R2 + 1) + t];
+      dft_reg<T, R1, -1>(v);
+      int rowC[2], rowZ[2], rowY[2], rowX[2];
 #pragma unroll
       for (int h = 0; h < 2; ++h) {
-        const T val = T(double(h ? v[j1].y : v[j1].x) * hsq);
-        if (rowC[h] >= 0 && xcc >= 0) cbase[rowC[h] + xcc] = val;
-        if (xda >= 0) {
-          if (rowZ[h] >= 0) pbase[rowZ[h] + xda] = val;
-          if (rowY[h] >= 0) pbase[rowY[h] + xda] = val;
+        rowC[h] = rowZ[h] = rowY[h] = rowX[h] = -1;
+        const int fi = 2 * pi + h;
+        if (fi < nf) {
+          const int yi = frow[fi];
+          const int y = ocrd[yi], yf = oflg[yi];
+          if (zc && (yf & 2)) rowC[h] = (((z + g.e) / NREF) * Wc + (y + g.e) / NREF) * Wc;
+          if (zpl && (yf & 1)) rowZ[h] = ((z - g.P0) / n * Wa + (y + g.da)) * Wa;
+          if (zin_a && (yf & 1) && (yf & 4)) rowY[h] = ((npl + (y - g.P0) / n) * Wa + (z + g.da)) * Wa;
+          if (zin_a && (yf & 1)) rowX[h] = (2 * npl * Wa + (z + g.da)) * Wa + (y + g.da);
         }
-        if (rowX[h] >= 0 && xpl >= 0) pbase[rowX[h] + xpl * Wa * Wa] = val;
       }
-    }
-  };
-  const int npair = (nf + 1) / 2;
-#pragma unroll 1
-  for (int pb = wave * LW; pb < npair; pb += NW * LW) {
-    if (act1) x_pass1(ex, s1, r1, pb + r1);
-    wave_sync();
-    if (act2) x_pass2(ex, t2, r2, pb + r2);
-    wave_sync();
-  }
-  // ---- x-plane columns of the other rows: direct Hermitian sums ----
-  //   f(x) = F_0 + (-1)^x F_{M/2} + 2 sum_{0<k<M/2} Re(F_k e^{2 pi i k x / M})
-  for (int q = tid; q < ncl * npl; q += blockDim.x) {
-    const int yi = crow[q / npl], j = q % npl;
-    const int x = g.P0 + j * n, xs = x < 0 ? x + M : x;
-    const cplx<T>* wj = Wx + j * WXS;
-    // four interleaved partial sums over k = 1 .. M/2 - 1
-    constexpr int KT = M / 2 - 1;
-    T acc[4] = {T(0), T(0), T(0), T(0)};
-#pragma unroll 2
-    for (int k0 = 1; k0 + 3 <= KT; k0 += 4) {
 #pragma unroll
-      for (int u = 0; u < 4; ++u) {
-        const cplx<T> a = A[(k0 + u) * Wq + (yi - ylo)];
-        const cplx<T> w = wj[k0 + u];
+      for (int j1 = 0; j1 < R1; ++j1) {
+        const uint64_t xw = xinfo[t + R2 * j1];
+        const int xda = int(short(xw & 0xffff)), xcc = int(short((xw >> 16) & 0xffff));
+        const int xpl = int(short((xw >> 32) & 0xffff));
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+          const T val = T(double(h ? v[j1].y : v[j1].x) * hsq);
+          if (rowC[h] >= 0 && xcc >= 0) cbase[rowC[h] + xcc] = val;
+          if (xda >= 0) {
+            if (rowZ[h] >= 0) pbase[rowZ[h] + xda] = val;
+            if (rowY[h] >= 0) pbase[rowY[h] + xda] = val;
+          }
+          if (rowX[h] >= 0 && xpl >= 0) pbase[rowX[h] + xpl * Wa * Wa] = val;
+        }
+      }
+    };
+    const int npair = (nf + 1) / 2;
+#pragma unroll 1
+    for (int pb = wave * LW; pb < npair; pb += NW * LW) {
+      if (act1) x_pass1(ex, s1, r1, pb + r1);
+      wave_sync();
+      if (act2) x_pass2(ex, t2, r2, pb + r2);
+      wave_sync();
+    }
+    // ---- x-plane columns of the other rows: direct Hermitian sums ----
+    //   f(x) = F_0 + (-1)^x F_{M/2} + 2 sum_{0<k<M/2} Re(F_k e^{2 pi i k x / M})
+    for (int q = tid; q < ncl * npl; q += blockDim.x) {
+      const int yi = crow[q / npl], j = q % npl;
+      const int x = g.P0 + j * n, xs = x < 0 ? x + M : x;
+      const cplx<T>* wj = Wx + j * WXS;
+      // four interleaved partial sums over k = 1 .. M/2 - 1
+      constexpr int KT = M / 2 - 1;
+      T acc[4] = {T(0), T(0), T(0), T(0)};
+#pragma unroll 2
+      for (int k0 = 1; k0 + 3 <= KT; k0 += 4) {
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          const cplx<T> a = A[(k0 + u) * Wq + (yi - ylo)];
+          const cplx<T> w = wj[k0 + u];
+          acc[u] += a.x * w.x + a.y * w.y;
+        }
+      }
+#pragma unroll
+      for (int u = 0; u < KT % 4; ++u) {
+        const int k = KT - KT % 4 + 1 + u;
+        const cplx<T> a = A[k * Wq + (yi - ylo)];
+        const cplx<T> w = wj[k];
         acc[u] += a.x * w.x + a.y * w.y;
       }
+      const T dc = A[yi - ylo].x, ny = A[(M / 2) * Wq + (yi - ylo)].x;
+      const T val = dc + ((xs & 1) ? -ny : ny) + T(2) * ((acc[0] + acc[1]) + (acc[2] + acc[3]));
+      const int y = ocrd[yi];
+      pbase[((int64_t(2) * npl + j) * Wa + (z + g.da)) * Wa + (y + g.da)] = T(double(val) * hsq);
     }
-#pragma unroll
-    for (int u = 0; u < KT % 4; ++u) {
-      const int k = KT - KT % 4 + 1 + u;
-      const cplx<T> a = A[k * Wq + (yi - ylo)];
-      const cplx<T> w = wj[k];
-      acc[u] += a.x * w.x + a.y * w.y;
-    }
-    const T dc = A[yi - ylo].x, ny = A[(M / 2) * Wq + (yi - ylo)].x;
-    const T val = dc + ((xs & 1) ? -ny : ny) + T(2) * ((acc[0] + acc[1]) + (acc[2] + acc[3]));
-    const int y = ocrd[yi];
-    pbase[((int64_t(2) * npl + j) * Wa + (z + g.da)) * Wa + (y + g.da)] = T(double(val) * hsq);
-  }
-  __syncthreads();   // A, Ex and the row lists are rewritten for the next plane
+    __syncthreads();   // A, Ex and the row lists are rewritten for the next plane
   }
 }
 
