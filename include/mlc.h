@@ -118,7 +118,10 @@ mlc_status mlc_plan_create(mlc_context* ctx, const mlc_problem* prob, mlc_plan**
 mlc_status mlc_plan_destroy(mlc_plan* plan);
 mlc_status mlc_plan_get_info(const mlc_plan* plan, mlc_plan_info* out);
 
-/* Bytes of device workspace a solve with this plan needs. */
+/* Bytes of device workspace a solve with this plan needs.  It includes one
+ * chunk of the local convolutions' z-transformed spectra (equal patch
+ * chunks of at most 6 GB; the environment variable MLC_CONV_CHUNK, read once
+ * per process, caps the patches per chunk instead). */
 mlc_status mlc_plan_workspace_bytes(const mlc_plan* plan, size_t* bytes);
 
 /* The same figure computed from the problem alone, on the host (no device
