@@ -50,14 +50,22 @@ def _case(name):
         # 4 and 10 Legendre modes (moment slices of 4 padded with zeros)
         "p2_32": (32, 8, 3.0, 6.0, 2, 4, 0, 64, mi.bumps(2, 13, radius=(0.1, 0.25))),
         "p3_32": (32, 8, 3.0, 6.0, 3, 4, 0, 64, mi.bumps(2, 14, radius=(0.1, 0.25))),
+        # the smallest and largest coplanar interpolation radius (output boxes
+        # of widths Wa + 2 and Wa + 8, tori 50 and 72)
+        "b1_32": (32, 8, 3.0, 6.0, 4, 4, 0, 64, mi.bumps(2, 15, radius=(0.1, 0.25))),
+        "b4_32": (32, 8, 3.0, 6.0, 4, 6, 0, 64, mi.bumps(2, 16, radius=(0.1, 0.25))),
     }
     return cases[name]
+
+
+# interpolation radius b of a case (0: the default Q/2)
+B_OF = {"b1_32": 1, "b4_32": 4}
 
 
 def _check_all(name, conv):
     N, n, alpha, beta, P, Q, fft, Z, bumps = _case(name)
     f = mi.bump_charge(N, bumps)
-    prob = gm.problem(N, n, alpha, beta, P, Q, conv=conv, fft_size=fft, Z=Z)
+    prob = gm.problem(N, n, alpha, beta, P, Q, b=B_OF.get(name, 0), conv=conv, fft_size=fft, Z=Z)
     g = gpu_solve(prob, f)
     prm = oracle_params(g["info"], alpha, beta)
     phi, o = omlc.mlc_solve(f, prm, dgf_cached(Q, Z), keep=True)
@@ -81,14 +89,15 @@ def _check_all(name, conv):
 
 
 @pytest.mark.parametrize("name", ["plain32", "plain32_q6", "mlc0_32", "p1_32", "ragged48", "single16", "p2_32",
-                                  "p3_32"])
+                                  "p3_32", "b1_32", "b4_32"])
 def test_fp64_parity(name):
     errs = _check_all(name, "fp64")
     for k, v in errs.items():
         assert v < TOL64, (k, v)
 
 
-@pytest.mark.parametrize("name", ["plain32", "plain32_q6", "mlc0_32", "p1_32", "ragged48", "single16"])
+@pytest.mark.parametrize("name", ["plain32", "plain32_q6", "mlc0_32", "p1_32", "ragged48", "single16", "b1_32",
+                                  "b4_32"])
 def test_fp32_parity(name):
     errs = _check_all(name, "fp32")
     assert errs["phi"] < TOL32, errs
