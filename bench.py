@@ -68,6 +68,32 @@ def kernel_model(info):
     }
 
 
+def solve_model(info):
+    """Whole-solve model of the path (independent of how the kernels are
+    split): compulsory HBM bytes if each patch's two pruned spectral
+    intermediates make one round trip, and nominal FFT flops.
+      bytes = patches x [2((n+1)^2 + W^2)(M/2+1) c + (coarse samples + planes) o]
+              + 3 (N+1)^3 8 + 5 M_c^3 16 (the coarse torus: fill and pruned passes)
+      flops = patches x [(n+1)^2 F_r + (n+1)(M/2+1) F_c + M(M/2+1) F_c   (forward)
+                         + 2 M^2 (M/2+1)                                  (DGF multiply)
+                         + M(M/2+1) F_c + W(M/2+1) F_c + W^2 F_r]         (inverse)
+    with W = n + 2 d_alpha + 8b + 1 the local field box, F_c = 5 M log2 M per
+    complex line and F_r = F_c / 2 per real line."""
+    conv = 4 if info["conv_precision"] == 1 else 8
+    c = 2 * conv
+    n, M, P, N = info["n"], info["M"], info["npatch"], info["N"]
+    W = n + 2 * info["d_alpha"] + 8 * info["b"] + 1
+    Mh = M // 2 + 1
+    outs = info["Wc"] ** 3 + 3 * info["nplanes_a"] * info["Wa"] ** 2
+    nbytes = P * (2 * ((n + 1) ** 2 + W ** 2) * Mh * c + outs * conv) + 3 * (N + 1) ** 3 * 8 \
+        + 5 * info["M_coarse"] ** 3 * 16
+    Fc = 5.0 * M * np.log2(M)
+    Fr = Fc / 2
+    flops = P * ((n + 1) ** 2 * Fr + (n + 1) * Mh * Fc + M * Mh * Fc + 2.0 * M * M * Mh
+                 + M * Mh * Fc + W * Mh * Fc + W * W * Fr)
+    return nbytes, flops
+
+
 KERNEL_SOURCES = ["paper_1702_08111_amd/csrc/conv_kernels.h", "paper_1702_08111_amd/csrc/fft_reg.h",
                   "paper_1702_08111_amd/csrc/fft.h", "paper_1702_08111_amd/csrc/common.h"]
 
@@ -361,7 +387,10 @@ def main():
     # ms per solve of each kernel (a kernel may be launched once per patch chunk)
     per_kernel = {k: v[1] / args.steps for k, v in kt32.items()}
     launches = {k: v[0] / args.steps for k, v in kt32.items()}
-    dom = max(per_kernel, key=per_kernel.get)
+    # (the longest kernel the model covers; at 256^3 it is the longest of all)
+    longest = max(per_kernel, key=per_kernel.get)
+    modeled = [k for k in per_kernel if k in model]
+    dom = max(modeled, key=per_kernel.get) if modeled else longest
     roof = None
     if dom in model:
         t = per_kernel[dom] * 1e-3
@@ -374,11 +403,21 @@ def main():
             roof = {"bound": "alu", "achieved": round(tfs, 2), "peak": FP32_PEAK_TFLOPS, "unit": "TFLOP/s",
                     "frac": round(tfs / FP32_PEAK_TFLOPS, 4), "traffic": None}
         roof["kernel"] = dom
+        roof["longest_kernel"] = longest
         roof["launches_per_solve"] = launches[dom]
         roof["ms_per_launch"] = round(per_kernel[dom] / launches[dom], 4)
         tr = measured_traffic(dom, args.workload)
         roof["traffic"] = tr
         roof["algorithmic_bytes_per_launch"] = model[dom]["bytes"] / launches[dom]
+
+    # whole-solve fractions of the HBM and fp32 vector roofs (model above)
+    sb, sf = solve_model(p32.info)
+    t32 = ms32 * 1e-3
+    solve_roof = {"bytes_model": sb, "flops_model": sf,
+                  "hbm_frac": round(sb / t32 / (HBM_PEAK_GBS * 1e9), 4),
+                  "alu_frac": round(sf / t32 / (FP32_PEAK_TFLOPS * 1e12), 4),
+                  "basis": "compulsory bytes with one round trip of the pruned spectral intermediates; "
+                           "nominal FFT flops; fp32 vector peak"}
 
     if args.copy_calibration:
         src = torch.empty(256 * 1024 * 1024, dtype=torch.uint8, device=dev)
@@ -427,6 +466,7 @@ def main():
                   "fp32_vs_closed_form": err32_exact},
         "kernels_ms": {k: round(v, 4) for k, v in sorted(per_kernel.items(), key=lambda kv: -kv[1])},
         "roofline": roof,
+        "solve_roofline": solve_roof,
         "cpu_baseline": cpu,
         "batch": batch,
         "serving": serving,

@@ -25,7 +25,10 @@
  *    into the caller stream with events, so when the caller stream passes a
  *    solve, all of that solve's work has ended.
  *  - Arguments are validated before anything is enqueued; on an error
- *    nothing is written to any output.
+ *    nothing is written to any output.  With MLC_CHECK=1 in the environment,
+ *    mlc_solve and mlc_solve_batched also check on the device that each f
+ *    vanishes on the outer boundary nodes (MLC_ERR_INVALID_ARG otherwise);
+ *    that check synchronises the caller's stream.
  *  - A context is used from one host thread at a time; plans are immutable
  *    after creation and may be used by several solves in sequence.
  */

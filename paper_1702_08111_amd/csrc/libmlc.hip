@@ -38,6 +38,7 @@ struct mlc_context {
   struct Side { hipStream_t stream = nullptr; hipEvent_t ev[3] = {nullptr, nullptr, nullptr}; };
   std::mutex side_mu;
   std::map<hipStream_t, Side> side;
+  int* check_flag = nullptr;   // MLC_CHECK: set when f is nonzero on the outer boundary
 };
 
 struct mlc_plan {
@@ -293,6 +294,7 @@ extern "C" mlc_status mlc_context_destroy(mlc_context* ctx) {
     for (hipEvent_t e : kv.second.ev) hipEventDestroy(e);
   }
   for (auto& kv : ctx->dgf) hipFree(kv.second);
+  if (ctx->check_flag) hipFree(ctx->check_flag);
   delete ctx;
   return MLC_OK;
 }
@@ -1185,6 +1187,31 @@ static mlc_status enqueue_group(const Group& G, hipStream_t s) {
   return MLC_OK;
 }
 
+// With MLC_CHECK=1 in the environment, each f of a solve is checked on the
+// device to vanish on the outer boundary nodes (the charge must be supported
+// inside the domain, sec. 4); the check synchronises the stream.  Off by
+// default.
+static bool check_enabled() {
+  const char* e = std::getenv("MLC_CHECK");
+  return e && e[0] == '1';
+}
+
+static mlc_status check_boundary(mlc_context* ctx, const double* f, int N, hipStream_t s) {
+  if (!ctx->check_flag && hipMalloc(&ctx->check_flag, sizeof(int)) != hipSuccess) {
+    ctx->check_flag = nullptr;
+    return fail(ctx, MLC_ERR_OUT_OF_MEMORY, "check flag allocation failed");
+  }
+  const int64_t faces = int64_t(6) * (N + 1) * (N + 1);
+  hipLaunchKernelGGL(set_flag_kernel, dim3(1), dim3(1), 0, s, ctx->check_flag, 0);
+  hipLaunchKernelGGL(boundary_check_kernel, dim3(blocks_for(faces)), dim3(256), 0, s, f, N, ctx->check_flag);
+  int h = 0;
+  hipError_t e = hipMemcpyAsync(&h, ctx->check_flag, sizeof(int), hipMemcpyDeviceToHost, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  if (e != hipSuccess) return fail(ctx, MLC_ERR_DEVICE, std::string("boundary check: ") + hipGetErrorString(e));
+  if (h) return fail(ctx, MLC_ERR_INVALID_ARG, "f is nonzero on the outer boundary (MLC_CHECK)");
+  return MLC_OK;
+}
+
 extern "C" mlc_status mlc_solve(mlc_plan* plan, const double* f, double* phi, void* workspace, size_t ws_bytes,
                                 void* stream) {
   if (!plan || !f || !phi || !workspace) return fail(plan ? plan->ctx : nullptr, MLC_ERR_INVALID_ARG, "null argument");
@@ -1198,6 +1225,10 @@ extern "C" mlc_status mlc_solve(mlc_plan* plan, const double* f, double* phi, vo
   G.phi = {phi};
   G.L = layout_of(infos_of(G.plans));
   if (ws_bytes < G.L.bytes) return fail(plan->ctx, MLC_ERR_INVALID_ARG, "workspace too small");
+  if (check_enabled()) {
+    const mlc_status cs = check_boundary(plan->ctx, f, plan->info.N, static_cast<hipStream_t>(stream));
+    if (cs != MLC_OK) return cs;
+  }
   G.ws = static_cast<char*>(workspace);
   G.desc = reinterpret_cast<ProbDesc*>(G.ws + G.L.o_desc);
   return enqueue_group(G, static_cast<hipStream_t>(stream));
@@ -1249,6 +1280,12 @@ extern "C" mlc_status mlc_solve_batched(int32_t count, mlc_plan* const* plans, c
   for (int k = 0; k < count; ++k)
     if (!f[k] || !phi[k]) return fail(ctx, MLC_ERR_INVALID_ARG, "null array in batch");
   HIP_TRY(ctx, hipSetDevice(ctx->device));
+  if (check_enabled()) {
+    for (int k = 0; k < count; ++k) {
+      st = check_boundary(ctx, f[k], plans[k]->info.N, static_cast<hipStream_t>(stream));
+      if (st != MLC_OK) return st;
+    }
+  }
   char* base = static_cast<char*>(workspace);
   for (auto& G : groups) {
     for (int k : G.pos) {

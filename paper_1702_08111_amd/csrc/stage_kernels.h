@@ -116,6 +116,23 @@ __global__ void __launch_bounds__(256) coarse_rhs_kernel(const CoarseRhsProb<T>*
   F[idx] += s;   // F starts at zero; the far-field sums may add first
 }
 
+// The optional input check: flag = 1 if f is nonzero at any node of the six
+// outer faces of the (N+1)^3 node box.
+__global__ void set_flag_kernel(int* __restrict__ flag, int v) { *flag = v; }
+__global__ void boundary_check_kernel(const double* __restrict__ f, int N, int* __restrict__ flag) {
+  const int64_t Np = N + 1;
+  const int64_t idx = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (idx >= 6 * Np * Np) return;
+  const int face = int(idx / (Np * Np));
+  const int64_t a = (idx / Np) % Np, b = idx % Np;
+  const int64_t e = (face & 1) ? N : 0;
+  int64_t g0, g1, g2;
+  if (face < 2) { g0 = e; g1 = a; g2 = b; }
+  else if (face < 4) { g0 = a; g1 = e; g2 = b; }
+  else { g0 = a; g1 = b; g2 = e; }
+  if (f[(g0 * Np + g1) * Np + g2] != 0.0) *flag = 1;
+}
+
 __global__ void fill_zero_kernel(double* __restrict__ p, int64_t count) {
   const int64_t idx = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
   if (idx < count) p[idx] = 0.0;
