@@ -446,6 +446,36 @@ static void annulus_geoms(const mlc_plan_info& I, MfmaGeom* skel, MfmaGeom* coar
   gs.padlo = gc.padlo = padlo;
 }
 
+// Offset chunks of a problem's far-field sums: a problem whose sums cover
+// too few blocks to fill the chip (small N) splits its offset planes over up
+// to ne0 chunks, each written as partial sums and added in order by a
+// reduction.  The count depends on the problem alone, so a problem gives the
+// same result solved alone or in a batch.
+struct AnnSplit {
+  int es_s = 1, es_c = 1;   // chunks: skeleton, coarse grid
+  int ncb_s = 0, ncb_c = 0; // column blocks of one chunk
+  size_t part = 0;          // doubles of partial sums (shared by both sums)
+};
+static AnnSplit ann_split(const mlc_plan_info& I) {
+  AnnSplit a;
+  MfmaGeom gs, gc;
+  annulus_geoms(I, &gs, &gc);
+  constexpr int SK_COLS = ann_block_cols<SkelTiling>(), SK_ROWS = ann_block_rows<SkelTiling>();
+  constexpr int CO_COLS = ann_block_cols<CoarseTiling>(), CO_ROWS = ann_block_rows<CoarseTiling>();
+  constexpr int TARGET_WAVES = 4096;
+  const int64_t nks = int64_t(gs.nk0) * gs.nk1 * gs.nk2, nkc = int64_t(gc.nk0) * gc.nk1 * gc.nk2;
+  a.ncb_s = int((nks + SK_COLS - 1) / SK_COLS);
+  a.ncb_c = int((nkc + CO_COLS - 1) / CO_COLS);
+  const int64_t ws = int64_t(gs.nrp / SK_ROWS) * a.ncb_s * 3 * SkelTiling::WAVES;
+  const int64_t wc = int64_t(gc.nrp / CO_ROWS) * a.ncb_c * CoarseTiling::WAVES;
+  a.es_s = int(std::min<int64_t>(gs.ne0, std::max<int64_t>(1, (TARGET_WAVES + ws - 1) / ws)));
+  a.es_c = int(std::min<int64_t>(gc.ne0, std::max<int64_t>(1, (TARGET_WAVES + wc - 1) / wc)));
+  const size_t ps = a.es_s > 1 ? size_t(a.es_s) * 3 * gs.nrp * nks : 0;
+  const size_t pc = a.es_c > 1 ? size_t(a.es_c) * gc.nrp * nkc : 0;
+  a.part = std::max(ps, pc);
+  return a;
+}
+
 static mlc_status build_tables(mlc_plan* P, const double* G1) {
   mlc_context* ctx = P->ctx;
   const mlc_plan_info& I = P->info;
@@ -602,7 +632,9 @@ static Layout layout_of(const std::vector<const mlc_plan_info*>& g) {
     if (g[k]->d_beta > g[k]->d_alpha) {
       MfmaGeom gs, gc;
       annulus_geoms(*g[k], &gs, &gc);
-      bytes = 2 * sizeof(double) * cube(gs.L) * gs.KP;   // slot-major and mode-major copies
+      // slot-major and mode-major moment copies, then the partial sums of
+      // split far-field sums
+      bytes = 2 * sizeof(double) * cube(gs.L) * gs.KP + sizeof(double) * ann_split(*g[k]).part;
     }
     L.o_cpad[k] = take(bytes);
   }
@@ -984,17 +1016,22 @@ static void launch_rest(const Group& G, hipStream_t s, Stage stage) {
     AnnProb* ap_c = ap_s + np;
     std::vector<AnnProb> vs(np), vc(np);
     int bs = 0, bc = 0;
+    int64_t rs = 0, rc = 0;   // threads of the reductions
     for (int k = 0; k < np; ++k) {
       const mlc_plan* P = G.plans[k];
       const mlc_plan_info& I = P->info;
       const MfmaGeom& gs = P->mg_skel;
       const MfmaGeom& gc = P->mg_coarse;
+      const AnnSplit sp = ann_split(I);
+      double* part = cpad_s(k) + 2 * cube(gs.L) * gs.KP;
       vs[k] = AnnProb{P->Am, cpad_s(k), phiB_of(k), gs.ppa, gs.nk0, gs.nk1, gs.nk2, gs.k0lo, gs.k1lo, gs.k2lo, gs.L,
-                      gs.padlo, I.N, I.S_lo, I.Ns, bs};
-      bs += (gs.nk0 * gs.nk1 * gs.nk2 + SK_COLS - 1) / SK_COLS;
+                      gs.padlo, I.N, I.S_lo, I.Ns, bs, sp.ncb_s, sp.es_s, part, rs};
+      bs += sp.ncb_s * sp.es_s;
+      if (sp.es_s > 1) rs += int64_t(3) * gs.nr * gs.nk0 * gs.nk1 * gs.nk2;
       vc[k] = AnnProb{P->Tm, cpad_p(k), F_of(k), gc.ppa, gc.nk0, gc.nk1, gc.nk2, gc.k0lo, gc.k1lo, gc.k2lo, gc.L,
-                      gc.padlo, I.N, I.S_lo, I.Ns, bc};
-      bc += (gc.nk0 * gc.nk1 * gc.nk2 + CO_COLS - 1) / CO_COLS;
+                      gc.padlo, I.N, I.S_lo, I.Ns, bc, sp.ncb_c, sp.es_c, part, rc};
+      bc += sp.ncb_c * sp.es_c;
+      if (sp.es_c > 1) rc += int64_t(gc.nr) * gc.nk0 * gc.nk1 * gc.nk2;
     }
     for (int k0 = 0; k0 < np; k0 += ANN_PACK) {
       AnnPack ps{}, pcq{};
@@ -1018,12 +1055,16 @@ static void launch_rest(const Group& G, hipStream_t s, Stage stage) {
       const MfmaGeom& g = P0->mg_coarse;
       hipLaunchKernelGGL(coarse_annulus_mfma_kernel, dim3(g.nrp / CO_ROWS, bc), dim3(64 * CoarseTiling::WAVES), 0, s,
                          ap_c, np, g, I0.n / NREF);
+      if (rc > 0)
+        hipLaunchKernelGGL(coarse_reduce_kernel, dim3(blocks_for(rc)), dim3(256), 0, s, ap_c, np, rc, g, I0.n / NREF);
     }
     {
       TimedScope ts(P0, s, "skeleton_annulus");
       const MfmaGeom& g = P0->mg_skel;
       hipLaunchKernelGGL(skeleton_annulus_mfma_kernel, dim3(g.nrp / SK_ROWS, bs, 3), dim3(64 * SkelTiling::WAVES), 0,
                          s, ap_s, np, g, I0.n);
+      if (rs > 0)
+        hipLaunchKernelGGL(skeleton_reduce_kernel, dim3(blocks_for(rs)), dim3(256), 0, s, ap_s, np, rs, g, I0.n);
     }
   }
   // coarse solves, the FFTs batched over problems of equal coarse torus

@@ -364,8 +364,8 @@ template <class TL> constexpr int ann_block_rows() { return TL::SHARE_ROWS ? 16 
 // wave's box of columns are skipped (a uniform test).
 template <int ANN_TILES, bool PMAJOR>
 __device__ __forceinline__ void annulus_mfma_tiles(const double* __restrict__ Am, const double* __restrict__ Cpad,
-                                                   const MfmaGeom& mg, int d, int rowbase, int kbase,
-                                                   f64x4 (&acc)[ANN_TILES]) {
+                                                   const MfmaGeom& mg, int d, int rowbase, int kbase, int e0b,
+                                                   int e0e, f64x4 (&acc)[ANN_TILES]) {
   const int lane = threadIdx.x & 63;
   const int rl = lane & 15, pj = lane >> 4;
   const int npc = mg.KP / 4;
@@ -400,7 +400,7 @@ __device__ __forceinline__ void annulus_mfma_tiles(const double* __restrict__ Am
   const int ppa = mg.ppa;
   const int64_t per_d = int64_t(mg.ne0) * mg.ne * mg.ne * npc * mg.nrp * 4;
   const double* Ad = Am + (d > 0 ? d : 0) * per_d + (rowbase + rl) * 4 + pj;
-  for (int e0 = 0; e0 < mg.ne0; ++e0) {
+  for (int e0 = e0b; e0 < e0e; ++e0) {
     const int E0 = mg.e0lo + e0;
     if (a_hi - E0 < 0 || a_lo - E0 > ppa - 1) continue;
     for (int e1 = 0; e1 < mg.ne; ++e1) {
@@ -436,7 +436,11 @@ struct AnnProb {
   double* out;          // phi^B (skeleton) or F^H (coarse)
   int ppa, nk0, nk1, nk2, k0lo, k1lo, k2lo, L, padlo;
   int N, S_lo, Ns;
-  int blk0;
+  int blk0;       // first block (along the launch's column-block axis)
+  int ncb;        // column blocks of one offset chunk
+  int esplit;     // offset chunks: blocks blk0 + c ncb + j take chunk c
+  double* part;   // esplit > 1: partial sums [chunk][(d)][row][column]
+  int64_t start;  // first thread of the problem in the reduction launch
 };
 constexpr int ANN_PACK = 8;
 struct AnnPack { AnnProb d[ANN_PACK]; int count; };
@@ -457,6 +461,11 @@ __device__ __forceinline__ const AnnProb& ann_problem(const AnnProb* __restrict_
   mg.L = A.L; mg.padlo = A.padlo;
   return A;
 }
+// The e0 range [e0b, e0e) of offset chunk c of esplit over ne0 planes.
+__device__ __forceinline__ void ann_chunk(int c, int esplit, int ne0, int* e0b, int* e0e) {
+  *e0b = c * ne0 / esplit;
+  *e0e = (c + 1) * ne0 / esplit;
+}
 
 // Skeleton: rows r = ra * n + rb of the face plane of normal d = blockIdx.z,
 // columns k = (kd, ka, kb) in [0, ppa]^3 of the problem owning column block
@@ -470,12 +479,27 @@ __global__ void __launch_bounds__(64 * SkelTiling::WAVES) skeleton_annulus_mfma_
   const AnnProb& A = ann_problem(ap, np, blockIdx.y, mg);
   const int N = A.N;
   double* __restrict__ phiB = A.out;
+  const int local = int(blockIdx.y) - A.blk0, chunk = local / A.ncb;
   const int rowbase = blockIdx.x * 64 + wave * 16;
-  const int kbase = (int(blockIdx.y) - A.blk0) * 16 * ANN_TILES;
+  const int kbase = (local % A.ncb) * 16 * ANN_TILES;
+  int e0b, e0e;
+  ann_chunk(chunk, A.esplit, mg.ne0, &e0b, &e0e);
   f64x4 acc[ANN_TILES];
-  annulus_mfma_tiles<ANN_TILES, false>(A.tab, A.cpad, mg, d, rowbase, kbase, acc);
+  annulus_mfma_tiles<ANN_TILES, false>(A.tab, A.cpad, mg, d, rowbase, kbase, e0b, e0e, acc);
   const int a0 = d == 0 ? 1 : 0, a1 = d == 2 ? 1 : 2, Np = N + 1;
   const int nk = mg.nk0 * mg.nk1 * mg.nk2;
+  if (A.esplit > 1) {
+    // partial sums of this offset chunk; skeleton_reduce_kernel adds them
+    double* part = A.part + (int64_t(chunk) * 3 + d) * mg.nrp * nk;
+#pragma unroll
+    for (int t = 0; t < ANN_TILES; ++t) {
+      const int k = kbase + 16 * t + (lane & 15);
+      if (k >= nk) continue;
+#pragma unroll
+      for (int j = 0; j < 4; ++j) part[int64_t(rowbase + 4 * j + (lane >> 4)) * nk + k] = acc[t][j];
+    }
+    return;
+  }
 #pragma unroll
   for (int t = 0; t < ANN_TILES; ++t) {
     int k = kbase + 16 * t + (lane & 15);
@@ -507,11 +531,26 @@ __global__ void __launch_bounds__(64 * CoarseTiling::WAVES) coarse_annulus_mfma_
   const AnnProb& A = ann_problem(ap, np, blockIdx.y, mg);
   const int S_lo = A.S_lo, Ns = A.Ns;
   double* __restrict__ F = A.out;
+  const int local = int(blockIdx.y) - A.blk0, chunk = local / A.ncb;
   const int rowbase = blockIdx.x * 16;
-  const int kbase = ((int(blockIdx.y) - A.blk0) * ANN_WAVES + wave) * 16 * ANN_TILES;
+  const int kbase = ((local % A.ncb) * ANN_WAVES + wave) * 16 * ANN_TILES;
+  int e0b, e0e;
+  ann_chunk(chunk, A.esplit, mg.ne0, &e0b, &e0e);
   f64x4 acc[ANN_TILES];
-  annulus_mfma_tiles<ANN_TILES, true>(A.tab, A.cpad, mg, -1, rowbase, kbase, acc);
+  annulus_mfma_tiles<ANN_TILES, true>(A.tab, A.cpad, mg, -1, rowbase, kbase, e0b, e0e, acc);
   const int nk = mg.nk0 * mg.nk1 * mg.nk2;
+  if (A.esplit > 1) {
+    // partial sums of this offset chunk; coarse_reduce_kernel adds them
+    double* part = A.part + int64_t(chunk) * mg.nrp * nk;
+#pragma unroll
+    for (int t = 0; t < ANN_TILES; ++t) {
+      const int k = kbase + 16 * t + (lane & 15);
+      if (k >= nk) continue;
+#pragma unroll
+      for (int j = 0; j < 4; ++j) part[int64_t(rowbase + 4 * j + (lane >> 4)) * nk + k] = acc[t][j];
+    }
+    return;
+  }
 #pragma unroll
   for (int t = 0; t < ANN_TILES; ++t) {
     int k = kbase + 16 * t + (lane & 15);
@@ -526,6 +565,49 @@ __global__ void __launch_bounds__(64 * CoarseTiling::WAVES) coarse_annulus_mfma_
       F[(int64_t(c0 - S_lo) * Ns + (c1 - S_lo)) * Ns + (c2 - S_lo)] += acc[t][j];
     }
   }
+}
+
+// Sums of the offset chunks of problems whose far-field sums were split
+// (AnnProb::esplit > 1), chunk by chunk in order; one thread per (d, row,
+// column) of every such problem.  Same outputs as the unsplit kernels.
+__global__ void __launch_bounds__(256) skeleton_reduce_kernel(const AnnProb* __restrict__ ap, int np, int64_t total,
+                                                              MfmaGeom mg, int n) {
+  const int64_t gidx = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (gidx >= total) return;
+  const AnnProb& A = flat_problem(ap, np, gidx);
+  mg.nk0 = A.nk0; mg.nk1 = A.nk1; mg.nk2 = A.nk2;
+  const int nk = mg.nk0 * mg.nk1 * mg.nk2;
+  const int64_t idx = gidx - A.start;
+  const int k = int(idx % nk), r = int((idx / nk) % mg.nr), d = int(idx / (int64_t(nk) * mg.nr));
+  const int a0 = d == 0 ? 1 : 0, a1 = d == 2 ? 1 : 2, N = A.N, Np = N + 1;
+  const int kd = k / (mg.nk1 * mg.nk2), ka = (k / mg.nk2) % mg.nk1, kb = k % mg.nk2;
+  const int ra = r / n, rb = r % n;
+  if ((a0 < d && ra == 0) || (a1 < d && rb == 0)) return;     // not canonical
+  int gg[3];
+  gg[d] = n * kd;
+  gg[a0] = n * ka + ra;
+  gg[a1] = n * kb + rb;
+  if (gg[a0] > N || gg[a1] > N) return;
+  double s = 0.0;
+  for (int c = 0; c < A.esplit; ++c) s += A.part[((int64_t(c) * 3 + d) * mg.nrp + r) * nk + k];
+  A.out[(int64_t(gg[0]) * Np + gg[1]) * Np + gg[2]] = s;
+}
+
+__global__ void __launch_bounds__(256) coarse_reduce_kernel(const AnnProb* __restrict__ ap, int np, int64_t total,
+                                                            MfmaGeom mg, int q) {
+  const int64_t gidx = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (gidx >= total) return;
+  const AnnProb& A = flat_problem(ap, np, gidx);
+  const int nk1 = A.nk1, nk2 = A.nk2, nk = A.nk0 * nk1 * nk2;
+  const int64_t idx = gidx - A.start;
+  const int k = int(idx % nk), r = int(idx / nk);
+  const int S_lo = A.S_lo, Ns = A.Ns;
+  const int k0 = A.k0lo + k / (nk1 * nk2), k1 = A.k1lo + (k / nk2) % nk1, k2 = A.k2lo + k % nk2;
+  const int c0 = q * k0 + r / (q * q), c1 = q * k1 + (r / q) % q, c2 = q * k2 + r % q;
+  if (c0 < S_lo || c0 >= S_lo + Ns || c1 < S_lo || c1 >= S_lo + Ns || c2 < S_lo || c2 >= S_lo + Ns) return;
+  double s = 0.0;
+  for (int c = 0; c < A.esplit; ++c) s += A.part[(int64_t(c) * mg.nrp + r) * nk + k];
+  A.out[(int64_t(c0 - S_lo) * Ns + (c1 - S_lo)) * Ns + (c2 - S_lo)] += s;
 }
 
 // phi^B[g] = I(phi^H)(g) + sum_{i in S_alpha(g)} delta_i[g] (+ the annulus
