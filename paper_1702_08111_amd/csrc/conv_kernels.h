@@ -363,12 +363,11 @@ __global__ void __launch_bounds__((OutBatch<T, M>::NT)) conv_out_kernel(const cp
   // the x coordinates of skeleton planes
   __shared__ short frow[WPMAX], crow[WPMAX];
   __shared__ int nfull, ncols;
-  // per torus slot of the x axis: x + d_alpha if inside Omega_alpha, the
-  // coarse index (x + e)/4 if a coarse node, the plane index if a skeleton
-  // plane (each -1 otherwise), packed as three 16-bit fields
-  __shared__ uint64_t xinfo[M];
   // inverse twiddles of the skeleton-plane x coordinates: Wx[j][k] = w^(k x_j)
   constexpr int NPLMAX = 4;
+  // torus slots of the x outputs (or -1): of x + d_alpha over Omega_alpha, of
+  // the coarse nodes (x + e)/4, of the skeleton planes
+  __shared__ short xs_a[WPMAX], xs_c[WPMAX], xs_p[NPLMAX];
   constexpr int WXS = M / 2 + 1;   // row stride: the four rows on distinct LDS banks
   __shared__ cplx<T> Wx[NPLMAX * WXS];
   constexpr int ZPB = OutBatch<T, M>::ZPB;
@@ -378,7 +377,9 @@ __global__ void __launch_bounds__((OutBatch<T, M>::NT)) conv_out_kernel(const cp
   const int Wh = (Wp + YSPL - 1) / YSPL, ylo = int(blockIdx.x % YSPL) * Wh, yhi = min(Wp, ylo + Wh);
   const int Wq = PADA ? Wh + ((11 - Wh % 32) + 32) % 32 : Wh;   // row stride of A
   const int tid = threadIdx.x;
-  const double hsq = pd[find_problem(pd, nprob, p)].h2;
+  // h^2 in the kernel's precision (for the fp32 kernel: one rounding of h^2,
+  // none when h is a power of two)
+  const T hsq = T(pd[find_problem(pd, nprob, p)].h2);
   const cplx<T>* zin = Zb + (int64_t(pc) * Wp + zi0) * Mh * M;   // the current plane
   constexpr int LW = OutBatch<T, M>::LW, NW = OutBatch<T, M>::NT / 64;
   const int wave = tid >> 6, lane = tid & 63;
@@ -396,6 +397,8 @@ __global__ void __launch_bounds__((OutBatch<T, M>::NT)) conv_out_kernel(const cp
   load_lines(u0, wave * LW);
   fill_twiddles(tw, M);
   for (int m = tid; m < M; m += blockDim.x) omap[m] = -1;
+  for (int i = tid; i < WPMAX; i += blockDim.x) xs_a[i] = xs_c[i] = -1;
+  if (tid < NPLMAX) xs_p[tid] = -1;
   __syncthreads();
   for (int k = tid; k < Wp; k += blockDim.x) {
     int y = out_coord(k, g.b, g.Wa, g.e, g.da, n);
@@ -407,14 +410,13 @@ __global__ void __launch_bounds__((OutBatch<T, M>::NT)) conv_out_kernel(const cp
   __syncthreads();
   for (int m = tid; m < M; m += blockDim.x) {
     const int xi = omap[m];
-    int xda = -1, xcc = -1, xpl = -1;
     if (xi >= 0) {
       const int x = ocrd[xi], xf = oflg[xi];
-      if (xf & 1) xda = x + g.da;
-      if (xf & 2) xcc = (x + g.e) / NREF;
-      if (xf & 4) xpl = (x - g.P0) / n;
+      const int xda = x + g.da, xcc = (x + g.e) / NREF, xpl = (x - g.P0) / n;
+      if ((xf & 1) && xda < WPMAX) xs_a[xda] = short(m);
+      if ((xf & 2) && xcc < WPMAX) xs_c[xcc] = short(m);
+      if ((xf & 4) && xpl < NPLMAX) xs_p[xpl] = short(m);
     }
-    xinfo[m] = uint64_t(uint16_t(xda)) | (uint64_t(uint16_t(xcc)) << 16) | (uint64_t(uint16_t(xpl)) << 32);
   }
   for (int t = tid; t < g.npl * (M / 2); t += blockDim.x) {
     const int j = t / (M / 2), k = t % (M / 2);
@@ -536,51 +538,71 @@ __global__ void __launch_bounds__((OutBatch<T, M>::NT)) conv_out_kernel(const cp
         ex[c * XL + s * (R2 + 1) + t] = w;
       }
     };
-    // second half: outputs of pair-line c (global pair index pi).  Per row,
-    // the base offsets of its destinations (or -1); per x slot, its offsets
-    // along the row (xinfo) -- so each output is a few adds and stores.
-    auto x_pass2 = [&](const cplx<T>* ex, int t, int c, int pi) {
-      cplx<T> v[R1];
+    // second half: pair-line c's R1-point DFT in R2 lanes (lanes (t, c));
+    // the line's two real output rows (real and imaginary parts) then go back
+    // to the slice in torus order
+    auto x_pass2 = [&](const cplx<T>* ex, int t, int c, cplx<T>* v) {
 #pragma unroll
       for (int s = 0; s < R1; ++s) v[s] = ex[c * XL + s * (R2 + 1) + t];
       dft_reg<T, R1, -1>(v);
-      int rowC[2], rowZ[2], rowY[2], rowX[2];
-#pragma unroll
-      for (int h = 0; h < 2; ++h) {
-        rowC[h] = rowZ[h] = rowY[h] = rowX[h] = -1;
-        const int fi = 2 * pi + h;
-        if (fi < nf) {
-          const int yi = frow[fi];
-          const int y = ocrd[yi], yf = oflg[yi];
-          if (zc && (yf & 2)) rowC[h] = (((z + g.e) / NREF) * Wc + (y + g.e) / NREF) * Wc;
-          if (zpl && (yf & 1)) rowZ[h] = ((z - g.P0) / n * Wa + (y + g.da)) * Wa;
-          if (zin_a && (yf & 1) && (yf & 4)) rowY[h] = ((npl + (y - g.P0) / n) * Wa + (z + g.da)) * Wa;
-          if (zin_a && (yf & 1)) rowX[h] = (2 * npl * Wa + (z + g.da)) * Wa + (y + g.da);
-        }
-      }
-#pragma unroll
-      for (int j1 = 0; j1 < R1; ++j1) {
-        const uint64_t xw = xinfo[t + R2 * j1];
-        const int xda = int(short(xw & 0xffff)), xcc = int(short((xw >> 16) & 0xffff));
-        const int xpl = int(short((xw >> 32) & 0xffff));
-#pragma unroll
-        for (int h = 0; h < 2; ++h) {
-          const T val = T(double(h ? v[j1].y : v[j1].x) * hsq);
-          if (rowC[h] >= 0 && xcc >= 0) cbase[rowC[h] + xcc] = val;
-          if (xda >= 0) {
-            if (rowZ[h] >= 0) pbase[rowZ[h] + xda] = val;
-            if (rowY[h] >= 0) pbase[rowY[h] + xda] = val;
-          }
-          if (rowX[h] >= 0 && xpl >= 0) pbase[rowX[h] + xpl * Wa * Wa] = val;
-        }
-      }
     };
+    // torus slots of the lane's x outputs (the same lists for every row)
+    constexpr int NXC = (WPMAX + 63) / 64;
+    int mA[NXC], mC[NXC];
+#pragma unroll
+    for (int a = 0; a < NXC; ++a) {
+      const int i = lane + 64 * a;
+      mA[a] = i < WPMAX ? xs_a[i] : -1;
+      mC[a] = i < WPMAX ? xs_c[i] : -1;
+    }
+    const int mP = lane < NPLMAX ? xs_p[lane] : -1;
+    const int Wa2 = Wa * Wa;
     const int npair = (nf + 1) / 2;
 #pragma unroll 1
     for (int pb = wave * LW; pb < npair; pb += NW * LW) {
+      // lane rr < 2 LW: destination bases of row 2 pb + rr (or -1), read by
+      // every lane below with readlane
+      int rZ = -1, rY = -1, rC = -1, rX = -1;
+      if (lane < 2 * LW && 2 * pb + lane < nf) {
+        const int yi = frow[2 * pb + lane];
+        const int y = ocrd[yi], yf = oflg[yi];
+        if (zpl && (yf & 1)) rZ = ((z - g.P0) / n * Wa + (y + g.da)) * Wa;
+        if (zin_a && (yf & 1) && (yf & 4)) rY = ((npl + (y - g.P0) / n) * Wa + (z + g.da)) * Wa;
+        if (zc && (yf & 2)) rC = (((z + g.e) / NREF) * Wc + (y + g.e) / NREF) * Wc;
+        if (zin_a && (yf & 1)) rX = (2 * npl * Wa + (z + g.da)) * Wa + (y + g.da);
+      }
       if (act1) x_pass1(ex, s1, r1, pb + r1);
       wave_sync();
-      if (act2) x_pass2(ex, t2, r2, pb + r2);
+      cplx<T> v[R1];
+      if (act2) x_pass2(ex, t2, r2, v);
+      wave_sync();
+      if (act2) {
+#pragma unroll
+        for (int j1 = 0; j1 < R1; ++j1) ex[r2 * XL + t2 + R2 * j1] = v[j1];
+      }
+      wave_sync();
+      // outputs, one row at a time, the lanes along its destinations
+#pragma unroll
+      for (int rr = 0; rr < 2 * LW; ++rr) {
+        const int rowZ = __builtin_amdgcn_readlane(rZ, rr), rowY = __builtin_amdgcn_readlane(rY, rr);
+        const int rowC = __builtin_amdgcn_readlane(rC, rr), rowX = __builtin_amdgcn_readlane(rX, rr);
+        const T* line = reinterpret_cast<const T*>(ex + (rr >> 1) * XL) + (rr & 1);
+        if (rowZ >= 0 || rowY >= 0) {
+#pragma unroll
+          for (int a = 0; a < NXC; ++a) {
+            if (mA[a] < 0) continue;
+            const T val = line[2 * mA[a]] * hsq;
+            if (rowZ >= 0) pbase[rowZ + lane + 64 * a] = val;
+            if (rowY >= 0) pbase[rowY + lane + 64 * a] = val;
+          }
+        }
+        if (rowC >= 0) {
+#pragma unroll
+          for (int a = 0; a < NXC; ++a)
+            if (mC[a] >= 0) cbase[rowC + lane + 64 * a] = line[2 * mC[a]] * hsq;
+        }
+        if (rowX >= 0 && mP >= 0) pbase[rowX + lane * Wa2] = line[2 * mP] * hsq;
+      }
       wave_sync();
     }
     // ---- x-plane columns of the other rows: direct Hermitian sums ----
@@ -611,7 +633,7 @@ __global__ void __launch_bounds__((OutBatch<T, M>::NT)) conv_out_kernel(const cp
       const T dc = A[yi - ylo].x, ny = A[(M / 2) * Wq + (yi - ylo)].x;
       const T val = dc + ((xs & 1) ? -ny : ny) + T(2) * ((acc[0] + acc[1]) + (acc[2] + acc[3]));
       const int y = ocrd[yi];
-      pbase[((int64_t(2) * npl + j) * Wa + (z + g.da)) * Wa + (y + g.da)] = T(double(val) * hsq);
+      pbase[((int64_t(2) * npl + j) * Wa + (z + g.da)) * Wa + (y + g.da)] = val * hsq;
     }
     __syncthreads();   // A, Ex and the row lists are rewritten for the next plane
   }
