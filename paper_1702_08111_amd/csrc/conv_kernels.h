@@ -558,8 +558,10 @@ __global__ void __launch_bounds__((OutBatch<T, M>::NT)) conv_out_kernel(const cp
     const int mP = lane < NPLMAX ? xs_p[lane] : -1;
     const int Wa2 = Wa * Wa;
     const int npair = (nf + 1) / 2;
+    // pair lines from the last wave down, the direct sums below from the
+    // first thread up: on most planes the two go to different waves
 #pragma unroll 1
-    for (int pb = wave * LW; pb < npair; pb += NW * LW) {
+    for (int pb = (NW - 1 - wave) * LW; pb < npair; pb += NW * LW) {
       // lane rr < 2 LW: destination bases of row 2 pb + rr (or -1), read by
       // every lane below with readlane
       int rZ = -1, rY = -1, rC = -1, rX = -1;
