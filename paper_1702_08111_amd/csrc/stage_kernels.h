@@ -480,8 +480,11 @@ __global__ void __launch_bounds__(64 * SkelTiling::WAVES) skeleton_annulus_mfma_
   const int N = A.N;
   double* __restrict__ phiB = A.out;
   const int local = int(blockIdx.y) - A.blk0, chunk = local / A.ncb;
-  const int rowbase = blockIdx.x * 64 + wave * 16;
-  const int kbase = (local % A.ncb) * 16 * ANN_TILES;
+  // a block's waves take consecutive row tiles of the same columns, or (rows
+  // shared) consecutive column tiles of the same rows
+  constexpr bool SHARE = SkelTiling::SHARE_ROWS;
+  const int rowbase = blockIdx.x * ann_block_rows<SkelTiling>() + (SHARE ? 0 : wave * 16);
+  const int kbase = (local % A.ncb) * ann_block_cols<SkelTiling>() + (SHARE ? wave * 16 * ANN_TILES : 0);
   int e0b, e0e;
   ann_chunk(chunk, A.esplit, mg.ne0, &e0b, &e0e);
   f64x4 acc[ANN_TILES];
