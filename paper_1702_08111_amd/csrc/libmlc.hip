@@ -600,7 +600,10 @@ static Layout layout_of(const std::vector<const mlc_plan_info*>& g) {
   L.o_flat = take((sizeof(CoarseRhsProb<double>) + sizeof(SkelProb<double>)) * np);
   L.o_mom = take(sizeof(double) * T * I.K);
   L.o_mpart = take(sizeof(double) * T * S * PLANE_MOMENTS);
-  L.o_X = take(csz * T * Mh * S * S);
+  // the x-DFT spectra; once the last y/z pass has read them, the same bytes
+  // hold the coarse Laplacians of the patches' coarse samples (at most as
+  // many bytes, since alpha <= 3)
+  L.o_X = take(std::max(csz * T * Mh * S * S, sizeof(double) * T * size_t(cube(I.Wc - 2 * I.b))));
   // patch chunks of equal size whose z-transformed spectra stay within
   // 6 GB (MLC_CONV_CHUNK overrides the largest chunk): at 256^3 with 32^3
   // patches one chunk holds every patch, measured faster than two or three
@@ -988,6 +991,11 @@ static void launch_rest(const Group& G, hipStream_t s, Stage stage) {
   // coarse right-hand side, every problem in one launch
   if (stage == COARSE) {
     auto* pr = reinterpret_cast<CoarseRhsProb<T>*>(G.ws + L.o_flat);
+    // coarse Laplacians of every patch's coarse samples, in the x-DFT region
+    // (free once the convolutions are done)
+    double* lap = reinterpret_cast<double*>(G.ws + L.o_X);
+    const int Li = I0.Wc - 2 * I0.b;
+    const int64_t lsz = cube(Li);
     std::vector<CoarseRhsProb<T>> v(np);
     int64_t total = 0;
     for (int k = 0; k < np; ++k) {
@@ -995,12 +1003,14 @@ static void launch_rest(const Group& G, hipStream_t s, Stage stage) {
       const mlc_plan_info& I = P->info;
       CoarseGeom cg{I.n, I.patches_per_axis, P->Kann, I.d_alpha, I.d_beta, I.e, I.Wc, I.S_lo, I.Ns, P->Wbc,
                     1.0 / (I.H * I.H)};
-      v[k] = CoarseRhsProb<T>{cs + L.patch0[k] * csz, F_of(k), cg, total};
+      v[k] = CoarseRhsProb<T>{lap + L.patch0[k] * lsz, F_of(k), cg, total};
       total += cube(I.Ns);
     }
     upload_flat(pr, v, s);
     TimedScope ts(P0, s, "coarse_rhs");
-    hipLaunchKernelGGL(coarse_rhs_kernel<T>, dim3(blocks_for(total)), dim3(256), 0, s, pr, np, total, st);
+    const int64_t nlap = int64_t(L.total) * lsz;
+    hipLaunchKernelGGL(coarse_lap_kernel<T>, dim3(blocks_for(nlap)), dim3(256), 0, s, cs, lap, nlap, I0.Wc, I0.b, st);
+    hipLaunchKernelGGL(coarse_rhs_kernel<T>, dim3(blocks_for(total)), dim3(256), 0, s, pr, np, total, I0.b);
   }
   // padded moment lattices: slot-major (skeleton sums), then mode-major (coarse sums)
   auto cpad_s = [&](int k) { return reinterpret_cast<double*>(G.ws + L.o_cpad[k]); };

@@ -64,23 +64,48 @@ __global__ void flat_upload_kernel(D* __restrict__ dst, FlatPack<D> pk) {
 }
 
 template <typename T> struct CoarseRhsProb {
-  const T* cs;      // the problem's patches' coarse samples
-  double* F;        // its F^H
+  const double* lap;   // coarse Laplacians of the problem's patches' coarse samples
+  double* F;           // its F^H
   CoarseGeom g;
   int64_t start;
 };
+
+// Delta^H of each patch's coarse samples at the points r in [b, Wc - b)^3 of
+// its coarse box (those of C(Omega_alpha), the only ones the right-hand side
+// reads; their 27-point neighbourhoods stay inside the box since b >= 1), in
+// float64: lap[patch][r - b].  One thread per point of every patch.
+template <typename T>
+__global__ void __launch_bounds__(256) coarse_lap_kernel(const T* __restrict__ cs, double* __restrict__ lap,
+                                                         int64_t total, int Wc, int b, Stencil st) {
+  const int64_t gidx = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (gidx >= total) return;
+  const int Li = Wc - 2 * b;
+  const int64_t lsz = int64_t(Li) * Li * Li;
+  const int64_t p = gidx / lsz;
+  const int i = int(gidx - p * lsz);
+  const int r0 = b + i / (Li * Li), r1 = b + (i / Li) % Li, r2 = b + i % Li;
+  const T* base = cs + p * Wc * Wc * Wc;
+  double l = 0.0;
+  for (int s0 = -1; s0 <= 1; ++s0)
+    for (int s1 = -1; s1 <= 1; ++s1)
+      for (int s2 = -1; s2 <= 1; ++s2) {
+        const int nz = (s0 != 0) + (s1 != 0) + (s2 != 0);
+        l += st.b[nz] * double(base[(int64_t(r0 + s0) * Wc + (r1 + s1)) * Wc + (r2 + s2)]);
+      }
+  lap[gidx] = l;
+}
 
 // Inner part of F^H: F[c] += sum over patches i with c in C(Omega_alpha(i)) of
 // Delta^H of phi_i's coarse samples (sec. 4.1 eq. FDLD, first case), patches
 // visited in a fixed order.  One thread per coarse point of every problem.
 template <typename T>
 __global__ void __launch_bounds__(256) coarse_rhs_kernel(const CoarseRhsProb<T>* __restrict__ pr, int np,
-                                                         int64_t total, Stencil st) {
+                                                         int64_t total, int b) {
   const int64_t gidx = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
   if (gidx >= total) return;
   const CoarseRhsProb<T>& pb = flat_problem(pr, np, gidx);
   const CoarseGeom g = pb.g;
-  const T* __restrict__ cs = pb.cs;
+  const double* __restrict__ lap = pb.lap;
   double* __restrict__ F = pb.F;
   const int64_t idx = gidx - pb.start;
   int c[3];
@@ -96,22 +121,14 @@ __global__ void __launch_bounds__(256) coarse_rhs_kernel(const CoarseRhsProb<T>*
     int bnd = NREF * c[d] + g.da;
     hi[d] = min(bnd >= 0 ? bnd / n : -((-bnd + n - 1) / n), g.ppa - 1);
   }
-  const int Wc = g.Wc, o = g.e / NREF;
+  const int Li = g.Wc - 2 * b, o = g.e / NREF - b;
   double s = 0.0;
   for (int a0 = lo[0]; a0 <= hi[0]; ++a0)
     for (int a1 = lo[1]; a1 <= hi[1]; ++a1)
       for (int a2 = lo[2]; a2 <= hi[2]; ++a2) {
-        int r0 = c[0] - q * a0 + o, r1 = c[1] - q * a1 + o, r2 = c[2] - q * a2 + o;
-        int pidx = (a0 * g.ppa + a1) * g.ppa + a2;
-        const T* base = cs + int64_t(pidx) * Wc * Wc * Wc;
-        double l = 0.0;
-        for (int s0 = -1; s0 <= 1; ++s0)
-          for (int s1 = -1; s1 <= 1; ++s1)
-            for (int s2 = -1; s2 <= 1; ++s2) {
-              int nz = (s0 != 0) + (s1 != 0) + (s2 != 0);
-              l += st.b[nz] * double(base[(int64_t(r0 + s0) * Wc + (r1 + s1)) * Wc + (r2 + s2)]);
-            }
-        s += l * g.invH2;
+        const int i0 = c[0] - q * a0 + o, i1 = c[1] - q * a1 + o, i2 = c[2] - q * a2 + o;
+        const int pidx = (a0 * g.ppa + a1) * g.ppa + a2;
+        s += lap[(int64_t(pidx) * Li + i0) * Li * Li + int64_t(i1) * Li + i2] * g.invH2;
       }
   F[idx] += s;   // F starts at zero; the far-field sums may add first
 }
