@@ -1007,9 +1007,14 @@ static void launch_rest(const Group& G, hipStream_t s, Stage stage) {
       total += cube(I.Ns);
     }
     upload_flat(pr, v, s);
+    {
+      TimedScope ts(P0, s, "coarse_lap");
+      const size_t lds = 3 * sizeof(T) * size_t(I0.Wc) * I0.Wc;   // <= 26 KB (Wc <= 33)
+      for (int p0 = 0; p0 < L.total; p0 += kMaxGridY)
+        hipLaunchKernelGGL(coarse_lap_kernel<T>, dim3(Li, std::min(kMaxGridY, L.total - p0)), dim3(256), lds, s, cs, lap,
+                           I0.Wc, I0.b, st, p0);
+    }
     TimedScope ts(P0, s, "coarse_rhs");
-    const int64_t nlap = int64_t(L.total) * lsz;
-    hipLaunchKernelGGL(coarse_lap_kernel<T>, dim3(blocks_for(nlap)), dim3(256), 0, s, cs, lap, nlap, I0.Wc, I0.b, st);
     hipLaunchKernelGGL(coarse_rhs_kernel<T>, dim3(blocks_for(total)), dim3(256), 0, s, pr, np, total, I0.b);
   }
   // padded moment lattices: slot-major (skeleton sums), then mode-major (coarse sums)
@@ -1128,9 +1133,10 @@ static void launch_rest(const Group& G, hipStream_t s, Stage stage) {
   if (stage == PLANES) {
     TimedScope ts(P0, s, "plane_delta");
     PlaneGeom pg{I0.n, I0.e, I0.d_alpha, I0.Wa, I0.Wc, P0->P0, I0.nplanes_a, I0.b};
+    const size_t lds = sizeof(double) * (size_t(I0.Wc) * I0.Wc + size_t(I0.Wc) * I0.Wa);   // <= 35 KB (Wc <= 33, Wa <= 97)
     for (int p0 = 0; p0 < L.total; p0 += kMaxGridY)
       hipLaunchKernelGGL(plane_delta_kernel<T>, dim3(3 * I0.nplanes_a, std::min(kMaxGridY, L.total - p0)), dim3(256),
-                         0, s, pl, cs, pg, P0->lagw, p0);
+                         lds, s, pl, cs, pg, P0->lagw, p0);
   }
   // boundary values on the skeleton (+ phi there), per problem
   // skeleton boundary values (+ phi there), every problem in one launch

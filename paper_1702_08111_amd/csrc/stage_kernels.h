@@ -73,26 +73,34 @@ template <typename T> struct CoarseRhsProb {
 // Delta^H of each patch's coarse samples at the points r in [b, Wc - b)^3 of
 // its coarse box (those of C(Omega_alpha), the only ones the right-hand side
 // reads; their 27-point neighbourhoods stay inside the box since b >= 1), in
-// float64: lap[patch][r - b].  One thread per point of every patch.
+// float64: lap[patch][r - b].  Block (output plane r0 - b, patch): the three
+// sample planes r0 - 1 .. r0 + 1 go to dynamic LDS (3 Wc^2 values), then one
+// thread per output point.
 template <typename T>
-__global__ void __launch_bounds__(256) coarse_lap_kernel(const T* __restrict__ cs, double* __restrict__ lap,
-                                                         int64_t total, int Wc, int b, Stencil st) {
-  const int64_t gidx = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-  if (gidx >= total) return;
-  const int Li = Wc - 2 * b;
-  const int64_t lsz = int64_t(Li) * Li * Li;
-  const int64_t p = gidx / lsz;
-  const int i = int(gidx - p * lsz);
-  const int r0 = b + i / (Li * Li), r1 = b + (i / Li) % Li, r2 = b + i % Li;
-  const T* base = cs + p * Wc * Wc * Wc;
-  double l = 0.0;
-  for (int s0 = -1; s0 <= 1; ++s0)
-    for (int s1 = -1; s1 <= 1; ++s1)
-      for (int s2 = -1; s2 <= 1; ++s2) {
-        const int nz = (s0 != 0) + (s1 != 0) + (s2 != 0);
-        l += st.b[nz] * double(base[(int64_t(r0 + s0) * Wc + (r1 + s1)) * Wc + (r2 + s2)]);
-      }
-  lap[gidx] = l;
+__global__ void __launch_bounds__(256) coarse_lap_kernel(const T* __restrict__ cs, double* __restrict__ lap, int Wc,
+                                                         int b, Stencil st, int p0) {
+  extern __shared__ unsigned char lap_lds[];
+  T* sm = reinterpret_cast<T*>(lap_lds);
+  const int Li = Wc - 2 * b, i0 = blockIdx.x, W2 = Wc * Wc;
+  const int64_t p = p0 + int64_t(blockIdx.y);
+  const T* src = cs + (p * Wc + (b + i0 - 1)) * W2;   // planes r0 - 1 .. r0 + 1 are consecutive
+  for (int t = threadIdx.x; t < 3 * W2; t += blockDim.x) sm[t] = src[t];
+  __syncthreads();
+  double* dst = lap + (p * Li + i0) * Li * Li;
+  for (int t = threadIdx.x; t < Li * Li; t += blockDim.x) {
+    const int r1 = b + t / Li, r2 = b + t % Li;
+    double l = 0.0;
+#pragma unroll
+    for (int s0 = -1; s0 <= 1; ++s0)
+#pragma unroll
+      for (int s1 = -1; s1 <= 1; ++s1)
+#pragma unroll
+        for (int s2 = -1; s2 <= 1; ++s2) {
+          const int nz = (s0 != 0) + (s1 != 0) + (s2 != 0);
+          l += st.b[nz] * double(sm[((1 + s0) * Wc + (r1 + s1)) * Wc + (r2 + s2)]);
+        }
+    dst[t] = l;
+  }
 }
 
 // Inner part of F^H: F[c] += sum over patches i with c in C(Omega_alpha(i)) of
@@ -122,14 +130,31 @@ __global__ void __launch_bounds__(256) coarse_rhs_kernel(const CoarseRhsProb<T>*
     hi[d] = min(bnd >= 0 ? bnd / n : -((-bnd + n - 1) / n), g.ppa - 1);
   }
   const int Li = g.Wc - 2 * b, o = g.e / NREF - b;
+  // at most 4 covering patches per axis (their C(Omega_alpha) spans n + 2 da
+  // <= 3n fine cells); the 16 values of one a0 are loaded together, then
+  // added in (a0, a1, a2) order
+  constexpr int PA = 4;
   double s = 0.0;
-  for (int a0 = lo[0]; a0 <= hi[0]; ++a0)
-    for (int a1 = lo[1]; a1 <= hi[1]; ++a1)
-      for (int a2 = lo[2]; a2 <= hi[2]; ++a2) {
-        const int i0 = c[0] - q * a0 + o, i1 = c[1] - q * a1 + o, i2 = c[2] - q * a2 + o;
-        const int pidx = (a0 * g.ppa + a1) * g.ppa + a2;
-        s += lap[(int64_t(pidx) * Li + i0) * Li * Li + int64_t(i1) * Li + i2] * g.invH2;
+  for (int a0 = lo[0]; a0 <= hi[0]; ++a0) {
+    double v[PA][PA];
+#pragma unroll
+    for (int j1 = 0; j1 < PA; ++j1)
+#pragma unroll
+      for (int j2 = 0; j2 < PA; ++j2) {
+        const int a1 = lo[1] + j1, a2 = lo[2] + j2;
+        v[j1][j2] = 0.0;
+        if (a1 <= hi[1] && a2 <= hi[2]) {
+          const int i0 = c[0] - q * a0 + o, i1 = c[1] - q * a1 + o, i2 = c[2] - q * a2 + o;
+          const int pidx = (a0 * g.ppa + a1) * g.ppa + a2;
+          v[j1][j2] = lap[(int64_t(pidx) * Li + i0) * Li * Li + int64_t(i1) * Li + i2];
+        }
       }
+#pragma unroll
+    for (int j1 = 0; j1 < PA; ++j1)
+#pragma unroll
+      for (int j2 = 0; j2 < PA; ++j2)
+        if (lo[1] + j1 <= hi[1] && lo[2] + j2 <= hi[2]) s += v[j1][j2] * g.invH2;
+  }
   F[idx] += s;   // F starts at zero; the far-field sums may add first
 }
 
@@ -191,7 +216,6 @@ inline LagW make_lagw(int b) {
 
 __device__ __forceinline__ int floor4(int x) { return x >= 0 ? x / NREF : -((-x + NREF - 1) / NREF); }
 
-constexpr int WCMAX = 40, WAMAX = 97;
 
 struct PlaneGeom { int n, e, da, Wa, Wc, P0, npl, b; };
 
@@ -202,8 +226,11 @@ struct PlaneGeom { int n, e, da, Wa, Wc, P0, npl, b; };
 template <typename T>
 __global__ void __launch_bounds__(256) plane_delta_kernel(T* __restrict__ planes, const T* __restrict__ cs,
                                                           PlaneGeom g, LagW lw, int p0) {
-  __shared__ double C[WCMAX * WCMAX];
-  __shared__ double R[WCMAX * WAMAX];
+  // dynamic LDS of (Wc^2 + Wc Wa) doubles: the coarse samples C, then the
+  // rows interpolated along the faster axis R
+  extern __shared__ double plane_lds[];
+  double* C = plane_lds;
+  double* R = plane_lds + g.Wc * g.Wc;
   __shared__ double W[4][10];
   if (threadIdx.x < 40) W[threadIdx.x / 10][threadIdx.x % 10] = lw.w[threadIdx.x / 10][threadIdx.x % 10];
   const int pl = blockIdx.x, p = p0 + blockIdx.y;
@@ -211,13 +238,27 @@ __global__ void __launch_bounds__(256) plane_delta_kernel(T* __restrict__ planes
   const int n = g.n, Wc = g.Wc, Wa = g.Wa, b = g.b, o = g.e / NREF;
   const int cd = (g.P0 + j * n + g.e) / NREF;
   const T* cb = cs + int64_t(p) * Wc * Wc * Wc;
-  for (int t = threadIdx.x; t < Wc * Wc; t += blockDim.x) {
-    int cu = t / Wc, cv = t % Wc;
-    int c[3];
-    c[d] = cd;
-    c[d == 0 ? 1 : 0] = cu;
-    c[d == 2 ? 1 : 2] = cv;
-    C[t] = double(cb[(int64_t(c[0]) * Wc + c[1]) * Wc + c[2]]);
+  // the plane's coarse samples, four loads in flight per thread
+  constexpr int UC = 4;
+  for (int t0 = threadIdx.x; t0 < Wc * Wc; t0 += UC * blockDim.x) {
+    T cv4[UC];
+#pragma unroll
+    for (int u = 0; u < UC; ++u) {
+      const int t = t0 + u * int(blockDim.x);
+      cv4[u] = T(0);
+      if (t < Wc * Wc) {
+        int c[3];
+        c[d] = cd;
+        c[d == 0 ? 1 : 0] = t / Wc;
+        c[d == 2 ? 1 : 2] = t % Wc;
+        cv4[u] = cb[(int64_t(c[0]) * Wc + c[1]) * Wc + c[2]];
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < UC; ++u) {
+      const int t = t0 + u * int(blockDim.x);
+      if (t < Wc * Wc) C[t] = double(cv4[u]);
+    }
   }
   __syncthreads();
   for (int t = threadIdx.x; t < Wc * Wa; t += blockDim.x) {
@@ -235,19 +276,34 @@ __global__ void __launch_bounds__(256) plane_delta_kernel(T* __restrict__ planes
   }
   __syncthreads();
   T* out = planes + ((int64_t(p) * 3 + d) * g.npl + j) * Wa * Wa;
-  for (int t = threadIdx.x; t < Wa * Wa; t += blockDim.x) {
-    const T old = out[t];   // in flight during the interpolation below
-    int u = t / Wa, v = t % Wa;
-    int xu = -g.da + u, U0 = floor4(xu), tu = xu - NREF * U0;
-    const double* col = R + (U0 + o) * Wa + v;
-    double s;
-    if (tu == 0) {
-      s = col[0];
-    } else {
-      s = 0.0;
-      for (int k = -b; k <= b + 1; ++k) s += W[tu][k + b] * col[k * Wa];
+  // eight of the thread's points at a time: their old values in flight
+  // during the interpolation
+  constexpr int UO = 8;
+  const int WW = Wa * Wa;
+  for (int t0 = threadIdx.x; t0 < WW; t0 += UO * blockDim.x) {
+    T old[UO];
+#pragma unroll
+    for (int q = 0; q < UO; ++q) {
+      const int t = t0 + q * int(blockDim.x);
+      old[q] = T(0);
+      if (t < WW) old[q] = out[t];
     }
-    out[t] = T(double(old) - s);
+#pragma unroll
+    for (int q = 0; q < UO; ++q) {
+      const int t = t0 + q * int(blockDim.x);
+      if (t >= WW) continue;
+      int u = t / Wa, v = t % Wa;
+      int xu = -g.da + u, U0 = floor4(xu), tu = xu - NREF * U0;
+      const double* col = R + (U0 + o) * Wa + v;
+      double s;
+      if (tu == 0) {
+        s = col[0];
+      } else {
+        s = 0.0;
+        for (int k = -b; k <= b + 1; ++k) s += W[tu][k + b] * col[k * Wa];
+      }
+      out[t] = T(double(old[q]) - s);
+    }
   }
 }
 
