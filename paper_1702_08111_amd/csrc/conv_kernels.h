@@ -227,7 +227,7 @@ __global__ void __launch_bounds__(256) conv_yz_kernel(const cplx<T>* __restrict_
       dft_reg_nz<T, R1, 1, NJ>(v);
       cplx<T>* ex = Ex + r * XL + t * (R1 + 1);
 #pragma unroll
-      for (int k1 = 0; k1 < R1; ++k1) ex[k1] = (k1 == 0 || t == 0) ? v[k1] : cmul(v[k1], twY[k1]);
+      for (int k1 = 0; k1 < R1; ++k1) ex[k1] = k1 == 0 ? v[k1] : cmul(v[k1], twY[k1]);
     }
     __syncthreads();
     if (tid < CB * R1) {
@@ -283,7 +283,7 @@ __global__ void __launch_bounds__(256) conv_yz_kernel(const cplx<T>* __restrict_
       dft_reg_nz<T, R1, 1, NJ>(v);
       cplx<T>* e = ex + ca * XL + ta * (R1 + 1);
 #pragma unroll
-      for (int k1 = 0; k1 < R1; ++k1) e[k1] = (k1 == 0 || ta == 0) ? v[k1] : cmul(v[k1], twA[k1]);
+      for (int k1 = 0; k1 < R1; ++k1) e[k1] = k1 == 0 ? v[k1] : cmul(v[k1], twA[k1]);
     }
     wave_sync();
     cplx<T> u[R2];
@@ -303,7 +303,7 @@ __global__ void __launch_bounds__(256) conv_yz_kernel(const cplx<T>* __restrict_
       dft_reg<T, R2, -1>(u);
 #pragma unroll
       for (int t = 1; t < R2; ++t)
-        if (sb) u[t] = cmul(u[t], twB[t]);
+        u[t] = cmul(u[t], twB[t]);
     }
     wave_sync();
     if (actB) {
@@ -474,7 +474,7 @@ __global__ void __launch_bounds__((OutBatch<T, M>::NT)) conv_out_kernel(const cp
       dft_reg<T, R2, -1>(u);
 #pragma unroll
       for (int t = 0; t < R2; ++t) {
-        cplx<T> w = (s && t) ? cmul(u[t], tws[t]) : u[t];
+        cplx<T> w = t ? cmul(u[t], tws[t]) : u[t];
         ex[r * XL + s * (R2 + 1) + t] = w;
       }
     };
@@ -534,7 +534,7 @@ __global__ void __launch_bounds__((OutBatch<T, M>::NT)) conv_out_kernel(const cp
       dft_reg<T, R2, -1>(u);
 #pragma unroll
       for (int t = 0; t < R2; ++t) {
-        cplx<T> w = (s && t) ? cmul(u[t], tws[t]) : u[t];
+        cplx<T> w = t ? cmul(u[t], tws[t]) : u[t];
         ex[c * XL + s * (R2 + 1) + t] = w;
       }
     };
