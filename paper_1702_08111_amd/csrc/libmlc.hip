@@ -447,10 +447,10 @@ static void annulus_geoms(const mlc_plan_info& I, MfmaGeom* skel, MfmaGeom* coar
 }
 
 // Offset chunks of a problem's far-field sums: a problem whose sums cover
-// too few blocks to fill the chip (small N) splits its offset planes over up
-// to ne0 chunks, each written as partial sums and added in order by a
-// reduction.  The count depends on the problem alone, so a problem gives the
-// same result solved alone or in a batch.
+// too few waves to fill the chip splits its offset planes over up to ne0
+// chunks, each written as partial sums and added in order by a reduction.
+// The count depends on the problem alone, so a problem gives the same result
+// solved alone or in a batch.
 struct AnnSplit {
   int es_s = 1, es_c = 1;   // chunks: skeleton, coarse grid
   int ncb_s = 0, ncb_c = 0; // column blocks of one chunk
@@ -462,7 +462,11 @@ static AnnSplit ann_split(const mlc_plan_info& I) {
   annulus_geoms(I, &gs, &gc);
   constexpr int SK_COLS = ann_block_cols<SkelTiling>(), SK_ROWS = ann_block_rows<SkelTiling>();
   constexpr int CO_COLS = ann_block_cols<CoarseTiling>(), CO_ROWS = ann_block_rows<CoarseTiling>();
-  constexpr int TARGET_WAVES = 4096;
+  // waves to aim for: with float32 convolutions the far-field sums span most
+  // of the output pass beside them, so they take more of the chip (measured
+  // at 256^3: 7.00 -> 6.89 ms); with float64 ones the output pass outlasts
+  // them anyway and a larger share only slows it
+  const int TARGET_WAVES = I.conv_precision == MLC_CONV_FP32 ? 8192 : 4096;
   const int64_t nks = int64_t(gs.nk0) * gs.nk1 * gs.nk2, nkc = int64_t(gc.nk0) * gc.nk1 * gc.nk2;
   a.ncb_s = int((nks + SK_COLS - 1) / SK_COLS);
   a.ncb_c = int((nkc + CO_COLS - 1) / CO_COLS);
