@@ -567,6 +567,7 @@ static bool same_class(const mlc_plan* a, const mlc_plan* b) {
 //   phi^H, phi^B.
 struct Layout {
   size_t o_desc = 0, o_ann = 0, o_flat = 0, o_mom = 0, o_mpart = 0, o_X = 0, o_Z = 0, o_cs = 0, o_pl = 0, o_dir = 0;
+  size_t o_dsum = 0;   // per skeleton thread: the sum of the plane corrections
   std::vector<size_t> o_F, o_tor, o_phiH, o_phiB, o_cpad;
   std::vector<int> patch0;
   int total = 0, chunk = 0;
@@ -621,6 +622,11 @@ static Layout layout_of(const std::vector<const mlc_plan_info*>& g) {
   L.o_cs = take(tsz * T * cube(I.Wc));
   L.o_pl = take(tsz * T * 3 * I.nplanes_a * I.Wa * I.Wa);
   L.o_dir = take(sizeof(double) * T * cube(I.n - 1));
+  {
+    size_t nsk = 0;
+    for (int k = 0; k < np; ++k) nsk += size_t(3) * (g[k]->N / g[k]->n + 1) * size_t(g[k]->N + 1) * (g[k]->N + 1);
+    L.o_dsum = take(sizeof(double) * nsk);
+  }
   L.o_F.resize(np); L.o_tor.resize(np); L.o_phiH.resize(np); L.o_phiB.resize(np);
   for (int k = 0; k < np; ++k) L.o_F[k] = take(sizeof(double) * cube(g[k]->Ns));
   std::vector<int> done(np, 0);
@@ -1142,12 +1148,14 @@ static void launch_rest(const Group& G, hipStream_t s, Stage stage) {
       hipLaunchKernelGGL(plane_delta_kernel<T>, dim3(3 * I0.nplanes_a, std::min(kMaxGridY, L.total - p0)), dim3(256),
                          lds, s, pl, cs, pg, P0->lagw, p0);
   }
-  // boundary values on the skeleton (+ phi there), per problem
-  // skeleton boundary values (+ phi there), every problem in one launch
-  if (stage == FINISH) {
+  // skeleton boundary values (+ phi there), every problem in one launch each
+  // part: the plane-correction sums right after plane_delta (they need no
+  // coarse solution), the interpolated coarse solution after the join
+  if (stage == PLANES || stage == FINISH) {
     auto* pr = reinterpret_cast<SkelProb<T>*>(G.ws + L.o_flat + sizeof(CoarseRhsProb<double>) * np);
-    std::vector<SkelProb<T>> v(np);
+    double* dsum = reinterpret_cast<double*>(G.ws + L.o_dsum);
     int64_t total = 0;
+    std::vector<SkelProb<T>> v(np);
     for (int k = 0; k < np; ++k) {
       const mlc_plan* P = G.plans[k];
       const mlc_plan_info& I = P->info;
@@ -1156,10 +1164,16 @@ static void launch_rest(const Group& G, hipStream_t s, Stage stage) {
       v[k] = SkelProb<T>{phiH_of(k), pl + L.patch0[k] * plsz, G.f[k], phiB_of(k), G.phi[k], sg, total};
       total += int64_t(3) * (I.N / I.n + 1) * (I.N + 1) * (I.N + 1);
     }
-    upload_flat(pr, v, s);
-    TimedScope ts(P0, s, "skeleton");
-    hipLaunchKernelGGL(skeleton_kernel<T>, dim3(blocks_for(total)), dim3(256), 0, s, pr, np, total, P0->lagw,
-                       P0->Kann > 0 ? 1 : 0);
+    if (stage == PLANES) {
+      upload_flat(pr, v, s);   // read by both parts
+      TimedScope ts(P0, s, "skeleton_deltas");
+      hipLaunchKernelGGL((skeleton_kernel<T, 0>), dim3(blocks_for(total)), dim3(256), 0, s, pr, np, total, P0->lagw,
+                         P0->Kann > 0 ? 1 : 0, dsum);
+    } else {
+      TimedScope ts(P0, s, "skeleton");
+      hipLaunchKernelGGL((skeleton_kernel<T, 1>), dim3(blocks_for(total)), dim3(256), 0, s, pr, np, total, P0->lagw,
+                         P0->Kann > 0 ? 1 : 0, dsum);
+    }
   }
   // Dirichlet solves + Mehrstellen correction on the patch interiors, all patches
   if (stage == FINISH) {
@@ -1193,8 +1207,8 @@ static mlc_context::Side* side_of(mlc_context* ctx, hipStream_t s) {
 
 // Launch order on the caller stream s and its side stream:
 //   s:    descriptors, x-DFTs, moments, first chunk's y/z pass | fork |
-//         the other convolution passes | fork | plane corrections | join |
-//         skeleton, Dirichlet
+//         the other convolution passes | fork | plane corrections and their
+//         sums at the skeleton nodes | join | skeleton, Dirichlet
 //   side: (after fork 1) far-field sums | (after fork 2) coarse rhs and solve
 // Every launch of one call has ended before the caller stream passes the
 // join, so consecutive calls on s may reuse the workspace.

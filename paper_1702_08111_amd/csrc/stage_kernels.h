@@ -690,10 +690,13 @@ __global__ void __launch_bounds__(256) coarse_reduce_kernel(const AnnProb* __res
 // far field already in phiB when `annulus`) for every skeleton node g (taken
 // once, on its lowest face-normal axis); also writes
 // phi[g] = phi^B[g] + C2 h^2 f[g] (sec. 4.1 eqs. mlcfulldiscr,
-// mcapplicationfulldiscr).
-template <typename T>
+// mcapplicationfulldiscr).  In two launches over the same thread range:
+// PART 0 (needs only the plane corrections) writes the sum of the delta_i
+// to dsum[thread]; PART 1 (needs phi^H) adds the interpolation and the far
+// field, so the first can run while the coarse solve is still going.
+template <typename T, int PART>
 __global__ void __launch_bounds__(256) skeleton_kernel(const SkelProb<T>* __restrict__ pr, int np, int64_t total,
-                                                       LagW lw, int annulus) {
+                                                       LagW lw, int annulus, double* __restrict__ dsum) {
   const int64_t gidx = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
   if (gidx >= total) return;
   const SkelProb<T>& pb = flat_problem(pr, np, gidx);
@@ -716,6 +719,36 @@ __global__ void __launch_bounds__(256) skeleton_kernel(const SkelProb<T>* __rest
   gg[d] = j * n;
   gg[a0] = u;
   gg[a1] = v;
+  if constexpr (PART == 0) {
+    // patches with g in Omega_alpha(i): n i - da <= g <= n i + n + da
+    int lo[3], hi[3];
+    for (int a = 0; a < 3; ++a) {
+      int x = gg[a] - n - g.da;
+      lo[a] = max(x >= 0 ? (x + n - 1) / n : -((-x) / n), 0);
+      hi[a] = min((gg[a] + g.da) / n, g.ppa - 1);
+    }
+    const int Wa = g.Wa;
+    double sd = 0.0;
+    for (int i0 = lo[0]; i0 <= hi[0]; ++i0)
+      for (int i1 = lo[1]; i1 <= hi[1]; ++i1)
+        // four patches of the last axis at a time (loads issued together); a
+        // slot past hi[2] repeats that patch and adds an exact zero
+        for (int i2b = lo[2]; i2b <= hi[2]; i2b += 4) {
+#pragma unroll
+          for (int t2 = 0; t2 < 4; ++t2) {
+            const bool valid = i2b + t2 <= hi[2];
+            const int i2 = valid ? i2b + t2 : hi[2];
+            const int r[3] = {gg[0] - n * i0, gg[1] - n * i1, gg[2] - n * i2};
+            const int pidx = (i0 * g.ppa + i1) * g.ppa + i2;
+            const int jj = (r[d] - g.P0) / n;
+            const double x =
+                double(delta[((((int64_t(pidx) * 3 + d) * g.npl + jj) * Wa + (r[a0] + g.da)) * Wa) + (r[a1] + g.da)]);
+            sd += valid ? x : 0.0;
+          }
+        }
+    dsum[gidx] = sd;
+    return;
+  }
   // coarse interpolation of phi^H in the plane x_d = g_d
   double val;
   {
@@ -746,31 +779,7 @@ __global__ void __launch_bounds__(256) skeleton_kernel(const SkelProb<T>* __rest
     }
     val = s;
   }
-  // patches with g in Omega_alpha(i): n i - da <= g <= n i + n + da
-  int lo[3], hi[3];
-  for (int a = 0; a < 3; ++a) {
-    int x = gg[a] - n - g.da;
-    lo[a] = max(x >= 0 ? (x + n - 1) / n : -((-x) / n), 0);
-    hi[a] = min((gg[a] + g.da) / n, g.ppa - 1);
-  }
-  const int Wa = g.Wa;
-  for (int i0 = lo[0]; i0 <= hi[0]; ++i0)
-    for (int i1 = lo[1]; i1 <= hi[1]; ++i1)
-      // four patches of the last axis at a time (loads issued together); a
-      // slot past hi[2] repeats that patch and adds an exact zero
-      for (int i2b = lo[2]; i2b <= hi[2]; i2b += 4) {
-#pragma unroll
-        for (int t2 = 0; t2 < 4; ++t2) {
-          const bool valid = i2b + t2 <= hi[2];
-          const int i2 = valid ? i2b + t2 : hi[2];
-          const int r[3] = {gg[0] - n * i0, gg[1] - n * i1, gg[2] - n * i2};
-          const int pidx = (i0 * g.ppa + i1) * g.ppa + i2;
-          const int jj = (r[d] - g.P0) / n;
-          const double x =
-              double(delta[((((int64_t(pidx) * 3 + d) * g.npl + jj) * Wa + (r[a0] + g.da)) * Wa) + (r[a1] + g.da)]);
-          val += valid ? x : 0.0;
-        }
-      }
+  val += dsum[gidx];
   int64_t node = (int64_t(gg[0]) * Np + gg[1]) * Np + gg[2];
   if (annulus) val += phiB[node];
   phiB[node] = val;
