@@ -420,17 +420,25 @@ __global__ void coarse_mfma_table_kernel(const double* __restrict__ Tt, double* 
   Tm[idx] = ok ? Tt[((int64_t(c[0]) * Wbc + c[1]) * Wbc + c[2]) * K + p] : 0.0;
 }
 
-// Two tilings, chosen per contraction by measurement:
-//   skeleton: a block is 4 waves on 4 consecutive 16-row tiles, each wave
-//     over the block's 8 column tiles (128 lattice points);
-//   coarse grid: a block is 8 waves on the same 16 rows (the streamed table
-//     fragments are shared through the CU's L1), each wave over its own 4
-//     column tiles.
-struct SkelTiling { static constexpr int TILES = 2, WAVES = 4; static constexpr bool SHARE_ROWS = false; };
-struct CoarseTiling { static constexpr int TILES = 1, WAVES = 8; static constexpr bool SHARE_ROWS = true; };
+// A wave computes 16 rows x TILES column tiles (16 lattice points each); a
+// block's WAVES waves form ROWW tiles of 16 rows by WAVES / ROWW column
+// groups (waves on the same rows share the streamed table fragments through
+// the CU's L1, waves on the same columns share the moments).  Chosen per
+// contraction by measurement:
+//   skeleton: 4 waves on 4 consecutive 16-row tiles of the same 32 points;
+//   coarse grid: 8 waves on the same 16 rows, 16 points each.
+struct SkelTiling { static constexpr int TILES = 2, WAVES = 4, ROWW = 4; };
+struct CoarseTiling { static constexpr int TILES = 1, WAVES = 8, ROWW = 1; };
 // lattice points and rows covered by one block
-template <class TL> constexpr int ann_block_cols() { return TL::SHARE_ROWS ? 16 * TL::TILES * TL::WAVES : 16 * TL::TILES; }
-template <class TL> constexpr int ann_block_rows() { return TL::SHARE_ROWS ? 16 : 16 * TL::WAVES; }
+template <class TL> constexpr int ann_block_cols() { return 16 * TL::TILES * (TL::WAVES / TL::ROWW); }
+template <class TL> constexpr int ann_block_rows() { return 16 * TL::ROWW; }
+// first row and first lattice point of wave `wave` in column block `cb`
+template <class TL> __device__ __forceinline__ int ann_rowbase(int bx, int wave) {
+  return bx * ann_block_rows<TL>() + (wave % TL::ROWW) * 16;
+}
+template <class TL> __device__ __forceinline__ int ann_kbase(int cb, int wave) {
+  return cb * ann_block_cols<TL>() + (wave / TL::ROWW) * 16 * TL::TILES;
+}
 
 // One wave: 16 rows x 16*ANN_TILES lattice points.  `d` selects the skeleton orientation, or is -1 for the
 // coarse grid.  Offsets whose patches all fall outside the lattice for the
@@ -553,11 +561,8 @@ __global__ void __launch_bounds__(64 * SkelTiling::WAVES) skeleton_annulus_mfma_
   const int N = A.N;
   double* __restrict__ phiB = A.out;
   const int local = int(blockIdx.y) - A.blk0, chunk = local / A.ncb;
-  // a block's waves take consecutive row tiles of the same columns, or (rows
-  // shared) consecutive column tiles of the same rows
-  constexpr bool SHARE = SkelTiling::SHARE_ROWS;
-  const int rowbase = blockIdx.x * ann_block_rows<SkelTiling>() + (SHARE ? 0 : wave * 16);
-  const int kbase = (local % A.ncb) * ann_block_cols<SkelTiling>() + (SHARE ? wave * 16 * ANN_TILES : 0);
+  const int rowbase = ann_rowbase<SkelTiling>(blockIdx.x, wave);
+  const int kbase = ann_kbase<SkelTiling>(local % A.ncb, wave);
   int e0b, e0e;
   ann_chunk(chunk, A.esplit, mg.ne0, &e0b, &e0e);
   f64x4 acc[ANN_TILES];
@@ -602,14 +607,14 @@ __global__ void __launch_bounds__(64 * SkelTiling::WAVES) skeleton_annulus_mfma_
 // F[c = q k + rho] inside the support box.
 __global__ void __launch_bounds__(64 * CoarseTiling::WAVES) coarse_annulus_mfma_kernel(const AnnProb* __restrict__ ap,
                                                                                       int np, MfmaGeom mg, int q) {
-  constexpr int ANN_TILES = CoarseTiling::TILES, ANN_WAVES = CoarseTiling::WAVES;
+  constexpr int ANN_TILES = CoarseTiling::TILES;
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const AnnProb& A = ann_problem(ap, np, blockIdx.y, mg);
   const int S_lo = A.S_lo, Ns = A.Ns;
   double* __restrict__ F = A.out;
   const int local = int(blockIdx.y) - A.blk0, chunk = local / A.ncb;
-  const int rowbase = blockIdx.x * 16;
-  const int kbase = ((local % A.ncb) * ANN_WAVES + wave) * 16 * ANN_TILES;
+  const int rowbase = ann_rowbase<CoarseTiling>(blockIdx.x, wave);
+  const int kbase = ann_kbase<CoarseTiling>(local % A.ncb, wave);
   int e0b, e0e;
   ann_chunk(chunk, A.esplit, mg.ne0, &e0b, &e0e);
   f64x4 acc[ANN_TILES];
