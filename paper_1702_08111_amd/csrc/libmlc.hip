@@ -413,6 +413,16 @@ static mlc_status build_spectrum(mlc_context* ctx, const double* G1, int Z, int 
 
 // Geometry of the two far-field contractions (skeleton planes, coarse grid)
 // and of the zero-padded moment lattice they share.
+// Rows of one block of the skeleton far-field tiling used for patches of n
+// cells per side (32-row strips per wave unless the face has fewer than 128
+// rows), and the lattice points of one block (the same for both tilings).
+static int skel_block_rows(int n) {
+  return n * n >= ann_block_rows<SkelTiling>() ? ann_block_rows<SkelTiling>() : ann_block_rows<SkelTilingSmall>();
+}
+constexpr int kSkelCols = ann_block_cols<SkelTiling>();
+static_assert(ann_block_cols<SkelTilingSmall>() == kSkelCols && SkelTilingSmall::WAVES == SkelTiling::WAVES,
+              "both skeleton tilings cover the same lattice points with the same waves");
+
 static void annulus_geoms(const mlc_plan_info& I, MfmaGeom* skel, MfmaGeom* coarse) {
   auto cdiv_floor = [](int a, int b) { return a >= 0 ? a / b : -((-a + b - 1) / b); };
   auto cdiv_ceil = [](int a, int b) { return a >= 0 ? (a + b - 1) / b : -((-a) / b); };
@@ -420,7 +430,9 @@ static void annulus_geoms(const mlc_plan_info& I, MfmaGeom* skel, MfmaGeom* coar
   auto rows64 = [](int r) { return (r + 63) / 64 * 64; };
   MfmaGeom& gs = *skel;
   gs = MfmaGeom{};
-  gs.ppa = ppa; gs.K = K; gs.KP = KP; gs.nr = n * n; gs.nrp = rows64(gs.nr);
+  // skeleton rows padded to whole blocks of the skeleton tiling (zero rows)
+  const int SKR = skel_block_rows(n);
+  gs.ppa = ppa; gs.K = K; gs.KP = KP; gs.nr = n * n; gs.nrp = std::max(rows64(gs.nr), (gs.nr + SKR - 1) / SKR * SKR);
   gs.e0lo = cdiv_ceil(-db, n);
   gs.ne0 = cdiv_floor(n + db, n) - gs.e0lo + 1;
   gs.elo = cdiv_ceil(-db - (n - 1), n);
@@ -460,7 +472,7 @@ static AnnSplit ann_split(const mlc_plan_info& I) {
   AnnSplit a;
   MfmaGeom gs, gc;
   annulus_geoms(I, &gs, &gc);
-  constexpr int SK_COLS = ann_block_cols<SkelTiling>(), SK_ROWS = ann_block_rows<SkelTiling>();
+  const int SK_COLS = kSkelCols, SK_ROWS = skel_block_rows(I.n);
   constexpr int CO_COLS = ann_block_cols<CoarseTiling>(), CO_ROWS = ann_block_rows<CoarseTiling>();
   // waves to aim for: with float32 convolutions the far-field sums span most
   // of the output pass beside them, so they take more of the chip (measured
@@ -1033,7 +1045,7 @@ static void launch_rest(const Group& G, hipStream_t s, Stage stage) {
     const MfmaGeom& g = G.plans[k]->mg_coarse;
     return reinterpret_cast<double*>(G.ws + L.o_cpad[k]) + cube(g.L) * g.KP;
   };
-  constexpr int SK_COLS = ann_block_cols<SkelTiling>(), SK_ROWS = ann_block_rows<SkelTiling>();
+  const int SK_COLS = kSkelCols, SK_ROWS = skel_block_rows(I0.n);
   constexpr int CO_COLS = ann_block_cols<CoarseTiling>(), CO_ROWS = ann_block_rows<CoarseTiling>();
   // far-field sums of every problem in one launch per contraction
   if (stage == FAR && P0->Kann > 0) {
@@ -1086,8 +1098,12 @@ static void launch_rest(const Group& G, hipStream_t s, Stage stage) {
     {
       TimedScope ts(P0, s, "skeleton_annulus");
       const MfmaGeom& g = P0->mg_skel;
-      hipLaunchKernelGGL(skeleton_annulus_mfma_kernel, dim3(g.nrp / SK_ROWS, bs, 3), dim3(64 * SkelTiling::WAVES), 0,
-                         s, ap_s, np, g, I0.n);
+      if (SK_ROWS == ann_block_rows<SkelTiling>())
+        hipLaunchKernelGGL(skeleton_annulus_mfma_kernel<SkelTiling>, dim3(g.nrp / SK_ROWS, bs, 3),
+                           dim3(64 * SkelTiling::WAVES), 0, s, ap_s, np, g, I0.n);
+      else
+        hipLaunchKernelGGL(skeleton_annulus_mfma_kernel<SkelTilingSmall>, dim3(g.nrp / SK_ROWS, bs, 3),
+                           dim3(64 * SkelTilingSmall::WAVES), 0, s, ap_s, np, g, I0.n);
       if (rs > 0)
         hipLaunchKernelGGL(skeleton_reduce_kernel, dim3(blocks_for(rs)), dim3(256), 0, s, ap_s, np, rs, g, I0.n);
     }

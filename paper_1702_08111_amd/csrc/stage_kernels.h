@@ -420,21 +420,25 @@ __global__ void coarse_mfma_table_kernel(const double* __restrict__ Tt, double* 
   Tm[idx] = ok ? Tt[((int64_t(c[0]) * Wbc + c[1]) * Wbc + c[2]) * K + p] : 0.0;
 }
 
-// A wave computes 16 rows x TILES column tiles (16 lattice points each); a
+// A wave computes RT tiles of 16 rows x TILES column tiles (16 lattice
+// points each); a
 // block's WAVES waves form ROWW tiles of 16 rows by WAVES / ROWW column
 // groups (waves on the same rows share the streamed table fragments through
 // the CU's L1, waves on the same columns share the moments).  Chosen per
 // contraction by measurement:
-//   skeleton: 4 waves on 4 consecutive 16-row tiles of the same 32 points;
+//   skeleton: 4 waves on 4 consecutive 32-row strips of the same 32
+//     points, each wave 2 x 2 tiles (every fragment load serves two MFMAs);
+//     faces of fewer than 128 rows (n = 8) take 16-row strips instead;
 //   coarse grid: 8 waves on the same 16 rows, 16 points each.
-struct SkelTiling { static constexpr int TILES = 2, WAVES = 4, ROWW = 4; };
-struct CoarseTiling { static constexpr int TILES = 1, WAVES = 8, ROWW = 1; };
-// lattice points and rows covered by one block
+struct SkelTiling { static constexpr int TILES = 2, WAVES = 4, ROWW = 4, RT = 2; };
+struct SkelTilingSmall { static constexpr int TILES = 2, WAVES = 4, ROWW = 4, RT = 1; };
+struct CoarseTiling { static constexpr int TILES = 1, WAVES = 8, ROWW = 1, RT = 1; };
+// lattice points and rows covered by one block (a wave: 16 RT rows)
 template <class TL> constexpr int ann_block_cols() { return 16 * TL::TILES * (TL::WAVES / TL::ROWW); }
-template <class TL> constexpr int ann_block_rows() { return 16 * TL::ROWW; }
+template <class TL> constexpr int ann_block_rows() { return 16 * TL::RT * TL::ROWW; }
 // first row and first lattice point of wave `wave` in column block `cb`
 template <class TL> __device__ __forceinline__ int ann_rowbase(int bx, int wave) {
-  return bx * ann_block_rows<TL>() + (wave % TL::ROWW) * 16;
+  return bx * ann_block_rows<TL>() + (wave % TL::ROWW) * 16 * TL::RT;
 }
 template <class TL> __device__ __forceinline__ int ann_kbase(int cb, int wave) {
   return cb * ann_block_cols<TL>() + (wave / TL::ROWW) * 16 * TL::TILES;
@@ -443,10 +447,10 @@ template <class TL> __device__ __forceinline__ int ann_kbase(int cb, int wave) {
 // One wave: 16 rows x 16*ANN_TILES lattice points.  `d` selects the skeleton orientation, or is -1 for the
 // coarse grid.  Offsets whose patches all fall outside the lattice for the
 // wave's box of columns are skipped (a uniform test).
-template <int ANN_TILES, bool PMAJOR>
+template <int ANN_TILES, bool PMAJOR, int RT>
 __device__ __forceinline__ void annulus_mfma_tiles(const double* __restrict__ Am, const double* __restrict__ Cpad,
                                                    const MfmaGeom& mg, int d, int rowbase, int kbase, int e0b,
-                                                   int e0e, f64x4 (&acc)[ANN_TILES]) {
+                                                   int e0e, f64x4 (&acc)[RT][ANN_TILES]) {
   const int lane = threadIdx.x & 63;
   const int rl = lane & 15, pj = lane >> 4;
   const int npc = mg.KP / 4;
@@ -464,7 +468,8 @@ __device__ __forceinline__ void annulus_mfma_tiles(const double* __restrict__ Am
     const int a = mg.k0lo + k / n12, b = mg.k1lo + (k / mg.nk2) % mg.nk1, c = mg.k2lo + k % mg.nk2;
     const int64_t slot = (a + pad) * st0 + (b + pad) * st1 + (c + pad) * st2;
     boff[t] = PMAJOR ? slot + int64_t(pj) * L * L * L : slot * mg.KP + pj;
-    acc[t] = f64x4{0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+    for (int rt = 0; rt < RT; ++rt) acc[rt][t] = f64x4{0.0, 0.0, 0.0, 0.0};
   }
   // lattice box of the wave's columns
   const int klast = min(kbase + 16 * ANN_TILES, nk) - 1;
@@ -493,12 +498,18 @@ __device__ __forceinline__ void annulus_mfma_tiles(const double* __restrict__ Am
         const int64_t off = int64_t(E0 * st0 + E1 * st1 + E2 * st2) * (PMAJOR ? 1 : mg.KP);
         const double* Ae = Ad + ((int64_t(e0) * mg.ne + e1) * mg.ne + e2) * npc * mg.nrp * 4;
         for (int pc = 0; pc < npc; ++pc) {
-          const double a = Ae[int64_t(pc) * mg.nrp * 4];
+          // the RT row tiles' table fragments (16 rows apart) and the
+          // moments fragments, each used RT or ANN_TILES times
+          double a[RT];
+#pragma unroll
+          for (int rt = 0; rt < RT; ++rt) a[rt] = Ae[int64_t(pc) * mg.nrp * 4 + 64 * rt];
           const double* Cp = Cpad + (PMAJOR ? int64_t(4 * pc) * L * L * L : int64_t(4 * pc)) - off;
 #pragma unroll
           for (int t = 0; t < ANN_TILES; ++t) {
             const double b = Cp[boff[t]];
-            acc[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc[t], 0, 0, 0);
+#pragma unroll
+            for (int rt = 0; rt < RT; ++rt)
+              acc[rt][t] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[rt], b, acc[rt][t], 0, 0, 0);
           }
         }
       }
@@ -552,35 +563,41 @@ __device__ __forceinline__ void ann_chunk(int c, int esplit, int ne0, int* e0b, 
 // columns k = (kd, ka, kb) in [0, ppa]^3 of the problem owning column block
 // blockIdx.y; writes the far field into its phiB at every canonical
 // skeleton node.
-__global__ void __launch_bounds__(64 * SkelTiling::WAVES) skeleton_annulus_mfma_kernel(const AnnProb* __restrict__ ap,
-                                                                                     int np, MfmaGeom mg, int n) {
-  constexpr int ANN_TILES = SkelTiling::TILES;
+template <class TL>
+__global__ void __launch_bounds__(64 * TL::WAVES) skeleton_annulus_mfma_kernel(const AnnProb* __restrict__ ap, int np,
+                                                                             MfmaGeom mg, int n) {
+  constexpr int ANN_TILES = TL::TILES, RT = TL::RT;
   const int d = blockIdx.z;
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const AnnProb& A = ann_problem(ap, np, blockIdx.y, mg);
   const int N = A.N;
   double* __restrict__ phiB = A.out;
   const int local = int(blockIdx.y) - A.blk0, chunk = local / A.ncb;
-  const int rowbase = ann_rowbase<SkelTiling>(blockIdx.x, wave);
-  const int kbase = ann_kbase<SkelTiling>(local % A.ncb, wave);
+  const int rowbase = ann_rowbase<TL>(blockIdx.x, wave);
+  const int kbase = ann_kbase<TL>(local % A.ncb, wave);
   int e0b, e0e;
   ann_chunk(chunk, A.esplit, mg.ne0, &e0b, &e0e);
-  f64x4 acc[ANN_TILES];
-  annulus_mfma_tiles<ANN_TILES, false>(A.tab, A.cpad, mg, d, rowbase, kbase, e0b, e0e, acc);
+  f64x4 acc[RT][ANN_TILES];
+  annulus_mfma_tiles<ANN_TILES, false, RT>(A.tab, A.cpad, mg, d, rowbase, kbase, e0b, e0e, acc);
   const int a0 = d == 0 ? 1 : 0, a1 = d == 2 ? 1 : 2, Np = N + 1;
   const int nk = mg.nk0 * mg.nk1 * mg.nk2;
   if (A.esplit > 1) {
     // partial sums of this offset chunk; skeleton_reduce_kernel adds them
     double* part = A.part + (int64_t(chunk) * 3 + d) * mg.nrp * nk;
 #pragma unroll
-    for (int t = 0; t < ANN_TILES; ++t) {
-      const int k = kbase + 16 * t + (lane & 15);
-      if (k >= nk) continue;
+    for (int rt = 0; rt < RT; ++rt)
 #pragma unroll
-      for (int j = 0; j < 4; ++j) part[int64_t(rowbase + 4 * j + (lane >> 4)) * nk + k] = acc[t][j];
-    }
+      for (int t = 0; t < ANN_TILES; ++t) {
+        const int k = kbase + 16 * t + (lane & 15);
+        if (k >= nk) continue;
+#pragma unroll
+        for (int j = 0; j < 4; ++j)
+          part[int64_t(rowbase + 16 * rt + 4 * j + (lane >> 4)) * nk + k] = acc[rt][t][j];
+      }
     return;
   }
+#pragma unroll
+  for (int rt = 0; rt < RT; ++rt)
 #pragma unroll
   for (int t = 0; t < ANN_TILES; ++t) {
     int k = kbase + 16 * t + (lane & 15);
@@ -588,7 +605,7 @@ __global__ void __launch_bounds__(64 * SkelTiling::WAVES) skeleton_annulus_mfma_
     int kd = k / (mg.nk1 * mg.nk2), ka = (k / mg.nk2) % mg.nk1, kb = k % mg.nk2;
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
-      int r = rowbase + 4 * j + (lane >> 4);
+      int r = rowbase + 16 * rt + 4 * j + (lane >> 4);
       if (r >= mg.nr) continue;
       int ra = r / n, rb = r % n;
       if ((a0 < d && ra == 0) || (a1 < d && rb == 0)) continue;     // not canonical
@@ -597,7 +614,7 @@ __global__ void __launch_bounds__(64 * SkelTiling::WAVES) skeleton_annulus_mfma_
       gg[a0] = n * ka + ra;
       gg[a1] = n * kb + rb;
       if (gg[a0] > N || gg[a1] > N) continue;
-      phiB[(int64_t(gg[0]) * Np + gg[1]) * Np + gg[2]] = acc[t][j];
+      phiB[(int64_t(gg[0]) * Np + gg[1]) * Np + gg[2]] = acc[rt][t][j];
     }
   }
 }
@@ -617,8 +634,10 @@ __global__ void __launch_bounds__(64 * CoarseTiling::WAVES) coarse_annulus_mfma_
   const int kbase = ann_kbase<CoarseTiling>(local % A.ncb, wave);
   int e0b, e0e;
   ann_chunk(chunk, A.esplit, mg.ne0, &e0b, &e0e);
-  f64x4 acc[ANN_TILES];
-  annulus_mfma_tiles<ANN_TILES, true>(A.tab, A.cpad, mg, -1, rowbase, kbase, e0b, e0e, acc);
+  static_assert(CoarseTiling::RT == 1, "the coarse-grid contraction takes one row tile per wave");
+  f64x4 acc2[1][ANN_TILES];
+  annulus_mfma_tiles<ANN_TILES, true, 1>(A.tab, A.cpad, mg, -1, rowbase, kbase, e0b, e0e, acc2);
+  f64x4 (&acc)[ANN_TILES] = acc2[0];
   const int nk = mg.nk0 * mg.nk1 * mg.nk2;
   if (A.esplit > 1) {
     // partial sums of this offset chunk; coarse_reduce_kernel adds them
