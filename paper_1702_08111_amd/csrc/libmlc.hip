@@ -411,11 +411,10 @@ static mlc_status build_spectrum(mlc_context* ctx, const double* G1, int Z, int 
   return MLC_OK;
 }
 
-// Geometry of the two far-field contractions (skeleton planes, coarse grid)
-// and of the zero-padded moment lattice they share.
 // Rows of one block of the skeleton far-field tiling used for patches of n
-// cells per side (32-row strips per wave unless the face has fewer than 128
-// rows), and the lattice points of one block (the same for both tilings).
+// cells per side (the strips of SkelTiling unless the face has fewer rows
+// than one block), and the lattice points of one block (the same for both
+// tilings).
 static int skel_block_rows(int n) {
   return n * n >= ann_block_rows<SkelTiling>() ? ann_block_rows<SkelTiling>() : ann_block_rows<SkelTilingSmall>();
 }
@@ -423,6 +422,8 @@ constexpr int kSkelCols = ann_block_cols<SkelTiling>();
 static_assert(ann_block_cols<SkelTilingSmall>() == kSkelCols && SkelTilingSmall::WAVES == SkelTiling::WAVES,
               "both skeleton tilings cover the same lattice points with the same waves");
 
+// Geometry of the two far-field contractions (skeleton planes, coarse grid)
+// and of the zero-padded moment lattice they share.
 static void annulus_geoms(const mlc_plan_info& I, MfmaGeom* skel, MfmaGeom* coarse) {
   auto cdiv_floor = [](int a, int b) { return a >= 0 ? a / b : -((-a + b - 1) / b); };
   auto cdiv_ceil = [](int a, int b) { return a >= 0 ? (a + b - 1) / b : -((-a) / b); };
@@ -442,7 +443,8 @@ static void annulus_geoms(const mlc_plan_info& I, MfmaGeom* skel, MfmaGeom* coar
   MfmaGeom& gc = *coarse;
   gc = MfmaGeom{};
   const int q = n / NREF, cb = db / NREF;
-  gc.ppa = ppa; gc.K = K; gc.KP = KP; gc.nr = q * q * q; gc.nrp = rows64(gc.nr);
+  constexpr int COR = ann_block_rows<CoarseTiling>();
+  gc.ppa = ppa; gc.K = K; gc.KP = KP; gc.nr = q * q * q; gc.nrp = std::max(rows64(gc.nr), (gc.nr + COR - 1) / COR * COR);
   gc.elo = cdiv_ceil(-cb - (q - 1), q);
   gc.ne = cdiv_floor((n + db) / NREF, q) - gc.elo + 1;
   gc.e0lo = gc.elo; gc.ne0 = gc.ne;

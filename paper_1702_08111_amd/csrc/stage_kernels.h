@@ -426,11 +426,12 @@ __global__ void coarse_mfma_table_kernel(const double* __restrict__ Tt, double* 
 // groups (waves on the same rows share the streamed table fragments through
 // the CU's L1, waves on the same columns share the moments).  Chosen per
 // contraction by measurement:
-//   skeleton: 4 waves on 4 consecutive 32-row strips of the same 32
-//     points, each wave 2 x 2 tiles (every fragment load serves two MFMAs);
-//     faces of fewer than 128 rows (n = 8) take 16-row strips instead;
+//   skeleton: 4 waves on 4 consecutive 64-row strips of the same 32
+//     points, each wave 4 x 2 tiles (a table fragment serves two MFMAs, a
+//     moments fragment four); faces of fewer than 256 rows (n = 8) take
+//     16-row strips instead;
 //   coarse grid: 8 waves on the same 16 rows, 16 points each.
-struct SkelTiling { static constexpr int TILES = 2, WAVES = 4, ROWW = 4, RT = 2; };
+struct SkelTiling { static constexpr int TILES = 2, WAVES = 4, ROWW = 4, RT = 4; };
 struct SkelTilingSmall { static constexpr int TILES = 2, WAVES = 4, ROWW = 4, RT = 1; };
 struct CoarseTiling { static constexpr int TILES = 1, WAVES = 8, ROWW = 1, RT = 1; };
 // lattice points and rows covered by one block (a wave: 16 RT rows)
@@ -624,7 +625,7 @@ __global__ void __launch_bounds__(64 * TL::WAVES) skeleton_annulus_mfma_kernel(c
 // F[c = q k + rho] inside the support box.
 __global__ void __launch_bounds__(64 * CoarseTiling::WAVES) coarse_annulus_mfma_kernel(const AnnProb* __restrict__ ap,
                                                                                       int np, MfmaGeom mg, int q) {
-  constexpr int ANN_TILES = CoarseTiling::TILES;
+  constexpr int ANN_TILES = CoarseTiling::TILES, RT = CoarseTiling::RT;
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const AnnProb& A = ann_problem(ap, np, blockIdx.y, mg);
   const int S_lo = A.S_lo, Ns = A.Ns;
@@ -634,23 +635,26 @@ __global__ void __launch_bounds__(64 * CoarseTiling::WAVES) coarse_annulus_mfma_
   const int kbase = ann_kbase<CoarseTiling>(local % A.ncb, wave);
   int e0b, e0e;
   ann_chunk(chunk, A.esplit, mg.ne0, &e0b, &e0e);
-  static_assert(CoarseTiling::RT == 1, "the coarse-grid contraction takes one row tile per wave");
-  f64x4 acc2[1][ANN_TILES];
-  annulus_mfma_tiles<ANN_TILES, true, 1>(A.tab, A.cpad, mg, -1, rowbase, kbase, e0b, e0e, acc2);
-  f64x4 (&acc)[ANN_TILES] = acc2[0];
+  f64x4 acc[RT][ANN_TILES];
+  annulus_mfma_tiles<ANN_TILES, true, RT>(A.tab, A.cpad, mg, -1, rowbase, kbase, e0b, e0e, acc);
   const int nk = mg.nk0 * mg.nk1 * mg.nk2;
   if (A.esplit > 1) {
     // partial sums of this offset chunk; coarse_reduce_kernel adds them
     double* part = A.part + int64_t(chunk) * mg.nrp * nk;
 #pragma unroll
-    for (int t = 0; t < ANN_TILES; ++t) {
-      const int k = kbase + 16 * t + (lane & 15);
-      if (k >= nk) continue;
+    for (int rt = 0; rt < RT; ++rt)
 #pragma unroll
-      for (int j = 0; j < 4; ++j) part[int64_t(rowbase + 4 * j + (lane >> 4)) * nk + k] = acc[t][j];
-    }
+      for (int t = 0; t < ANN_TILES; ++t) {
+        const int k = kbase + 16 * t + (lane & 15);
+        if (k >= nk) continue;
+#pragma unroll
+        for (int j = 0; j < 4; ++j)
+          part[int64_t(rowbase + 16 * rt + 4 * j + (lane >> 4)) * nk + k] = acc[rt][t][j];
+      }
     return;
   }
+#pragma unroll
+  for (int rt = 0; rt < RT; ++rt)
 #pragma unroll
   for (int t = 0; t < ANN_TILES; ++t) {
     int k = kbase + 16 * t + (lane & 15);
@@ -658,11 +662,11 @@ __global__ void __launch_bounds__(64 * CoarseTiling::WAVES) coarse_annulus_mfma_
     int k0 = mg.k0lo + k / (mg.nk1 * mg.nk2), k1 = mg.k1lo + (k / mg.nk2) % mg.nk1, k2 = mg.k2lo + k % mg.nk2;
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
-      int r = rowbase + 4 * j + (lane >> 4);
+      int r = rowbase + 16 * rt + 4 * j + (lane >> 4);
       if (r >= mg.nr) continue;
       int c0 = q * k0 + r / (q * q), c1 = q * k1 + (r / q) % q, c2 = q * k2 + r % q;
       if (c0 < S_lo || c0 >= S_lo + Ns || c1 < S_lo || c1 >= S_lo + Ns || c2 < S_lo || c2 >= S_lo + Ns) continue;
-      F[(int64_t(c0 - S_lo) * Ns + (c1 - S_lo)) * Ns + (c2 - S_lo)] += acc[t][j];
+      F[(int64_t(c0 - S_lo) * Ns + (c1 - S_lo)) * Ns + (c2 - S_lo)] += acc[rt][t][j];
     }
   }
 }
