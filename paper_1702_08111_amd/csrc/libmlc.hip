@@ -419,6 +419,15 @@ static int skel_block_rows(int n) {
   return n * n >= ann_block_rows<SkelTiling>() ? ann_block_rows<SkelTiling>() : ann_block_rows<SkelTilingSmall>();
 }
 constexpr int kSkelCols = ann_block_cols<SkelTiling>();
+// The same for the coarse-grid contraction, by q = n / 4 (q^3 rows); its two
+// tilings may differ in both rows and lattice points per block.
+static bool coarse_big(int q) { return q * q * q >= ann_block_rows<CoarseTiling>() && q >= 4; }
+static int coarse_block_rows(int q) {
+  return coarse_big(q) ? ann_block_rows<CoarseTiling>() : ann_block_rows<CoarseTilingSmall>();
+}
+static int coarse_block_cols(int q) {
+  return coarse_big(q) ? ann_block_cols<CoarseTiling>() : ann_block_cols<CoarseTilingSmall>();
+}
 static_assert(ann_block_cols<SkelTilingSmall>() == kSkelCols && SkelTilingSmall::WAVES == SkelTiling::WAVES,
               "both skeleton tilings cover the same lattice points with the same waves");
 
@@ -443,7 +452,7 @@ static void annulus_geoms(const mlc_plan_info& I, MfmaGeom* skel, MfmaGeom* coar
   MfmaGeom& gc = *coarse;
   gc = MfmaGeom{};
   const int q = n / NREF, cb = db / NREF;
-  constexpr int COR = ann_block_rows<CoarseTiling>();
+  const int COR = coarse_block_rows(n / NREF);
   gc.ppa = ppa; gc.K = K; gc.KP = KP; gc.nr = q * q * q; gc.nrp = std::max(rows64(gc.nr), (gc.nr + COR - 1) / COR * COR);
   gc.elo = cdiv_ceil(-cb - (q - 1), q);
   gc.ne = cdiv_floor((n + db) / NREF, q) - gc.elo + 1;
@@ -475,7 +484,7 @@ static AnnSplit ann_split(const mlc_plan_info& I) {
   MfmaGeom gs, gc;
   annulus_geoms(I, &gs, &gc);
   const int SK_COLS = kSkelCols, SK_ROWS = skel_block_rows(I.n);
-  constexpr int CO_COLS = ann_block_cols<CoarseTiling>(), CO_ROWS = ann_block_rows<CoarseTiling>();
+  const int CO_COLS = coarse_block_cols(I.n / NREF), CO_ROWS = coarse_block_rows(I.n / NREF);
   // waves to aim for: with float32 convolutions the far-field sums span most
   // of the output pass beside them, so they take more of the chip (measured
   // at 256^3: 7.00 -> 6.89 ms); with float64 ones the output pass outlasts
@@ -485,6 +494,7 @@ static AnnSplit ann_split(const mlc_plan_info& I) {
   a.ncb_s = int((nks + SK_COLS - 1) / SK_COLS);
   a.ncb_c = int((nkc + CO_COLS - 1) / CO_COLS);
   const int64_t ws = int64_t(gs.nrp / SK_ROWS) * a.ncb_s * 3 * SkelTiling::WAVES;
+  static_assert(CoarseTiling::WAVES == CoarseTilingSmall::WAVES, "both coarse tilings launch the same waves");
   const int64_t wc = int64_t(gc.nrp / CO_ROWS) * a.ncb_c * CoarseTiling::WAVES;
   a.es_s = int(std::min<int64_t>(gs.ne0, std::max<int64_t>(1, (TARGET_WAVES + ws - 1) / ws)));
   a.es_c = int(std::min<int64_t>(gc.ne0, std::max<int64_t>(1, (TARGET_WAVES + wc - 1) / wc)));
@@ -1048,7 +1058,7 @@ static void launch_rest(const Group& G, hipStream_t s, Stage stage) {
     return reinterpret_cast<double*>(G.ws + L.o_cpad[k]) + cube(g.L) * g.KP;
   };
   const int SK_COLS = kSkelCols, SK_ROWS = skel_block_rows(I0.n);
-  constexpr int CO_COLS = ann_block_cols<CoarseTiling>(), CO_ROWS = ann_block_rows<CoarseTiling>();
+  const int CO_COLS = coarse_block_cols(I0.n / NREF), CO_ROWS = coarse_block_rows(I0.n / NREF);
   // far-field sums of every problem in one launch per contraction
   if (stage == FAR && P0->Kann > 0) {
     AnnProb* ap_s = reinterpret_cast<AnnProb*>(G.ws + L.o_ann);
@@ -1092,8 +1102,12 @@ static void launch_rest(const Group& G, hipStream_t s, Stage stage) {
                            mom + int64_t(L.patch0[k]) * I.K, cpad_s(k), cpad_p(k), g.ppa, g.K, g.KP, g.L, g.padlo);
       }
       const MfmaGeom& g = P0->mg_coarse;
-      hipLaunchKernelGGL(coarse_annulus_mfma_kernel, dim3(g.nrp / CO_ROWS, bc), dim3(64 * CoarseTiling::WAVES), 0, s,
-                         ap_c, np, g, I0.n / NREF);
+      if (coarse_big(I0.n / NREF))
+        hipLaunchKernelGGL(coarse_annulus_mfma_kernel<CoarseTiling>, dim3(g.nrp / CO_ROWS, bc),
+                           dim3(64 * CoarseTiling::WAVES), 0, s, ap_c, np, g, I0.n / NREF);
+      else
+        hipLaunchKernelGGL(coarse_annulus_mfma_kernel<CoarseTilingSmall>, dim3(g.nrp / CO_ROWS, bc),
+                           dim3(64 * CoarseTilingSmall::WAVES), 0, s, ap_c, np, g, I0.n / NREF);
       if (rc > 0)
         hipLaunchKernelGGL(coarse_reduce_kernel, dim3(blocks_for(rc)), dim3(256), 0, s, ap_c, np, rc, g, I0.n / NREF);
     }

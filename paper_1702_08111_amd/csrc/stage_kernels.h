@@ -430,10 +430,12 @@ __global__ void coarse_mfma_table_kernel(const double* __restrict__ Tt, double* 
 //     points, each wave 4 x 2 tiles (a table fragment serves two MFMAs, a
 //     moments fragment four); faces of fewer than 256 rows (n = 8) take
 //     16-row strips instead;
-//   coarse grid: 8 waves on the same 16 rows, 16 points each.
+//   coarse grid: 8 waves on the same 32 rows, 16 points each (2 x 1 tiles);
+//     at q = 2 (8 rows) 16 rows, which keeps more blocks in flight.
 struct SkelTiling { static constexpr int TILES = 2, WAVES = 4, ROWW = 4, RT = 4; };
 struct SkelTilingSmall { static constexpr int TILES = 2, WAVES = 4, ROWW = 4, RT = 1; };
-struct CoarseTiling { static constexpr int TILES = 1, WAVES = 8, ROWW = 1, RT = 1; };
+struct CoarseTiling { static constexpr int TILES = 1, WAVES = 8, ROWW = 1, RT = 2; };
+struct CoarseTilingSmall { static constexpr int TILES = 1, WAVES = 8, ROWW = 1, RT = 1; };
 // lattice points and rows covered by one block (a wave: 16 RT rows)
 template <class TL> constexpr int ann_block_cols() { return 16 * TL::TILES * (TL::WAVES / TL::ROWW); }
 template <class TL> constexpr int ann_block_rows() { return 16 * TL::RT * TL::ROWW; }
@@ -623,16 +625,17 @@ __global__ void __launch_bounds__(64 * TL::WAVES) skeleton_annulus_mfma_kernel(c
 // Coarse grid: rows rho in [0, q)^3, columns k over the lattice box of the
 // problem owning column block blockIdx.y; adds the far field to its
 // F[c = q k + rho] inside the support box.
-__global__ void __launch_bounds__(64 * CoarseTiling::WAVES) coarse_annulus_mfma_kernel(const AnnProb* __restrict__ ap,
+template <class TL>
+__global__ void __launch_bounds__(64 * TL::WAVES) coarse_annulus_mfma_kernel(const AnnProb* __restrict__ ap,
                                                                                       int np, MfmaGeom mg, int q) {
-  constexpr int ANN_TILES = CoarseTiling::TILES, RT = CoarseTiling::RT;
+  constexpr int ANN_TILES = TL::TILES, RT = TL::RT;
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const AnnProb& A = ann_problem(ap, np, blockIdx.y, mg);
   const int S_lo = A.S_lo, Ns = A.Ns;
   double* __restrict__ F = A.out;
   const int local = int(blockIdx.y) - A.blk0, chunk = local / A.ncb;
-  const int rowbase = ann_rowbase<CoarseTiling>(blockIdx.x, wave);
-  const int kbase = ann_kbase<CoarseTiling>(local % A.ncb, wave);
+  const int rowbase = ann_rowbase<TL>(blockIdx.x, wave);
+  const int kbase = ann_kbase<TL>(local % A.ncb, wave);
   int e0b, e0e;
   ann_chunk(chunk, A.esplit, mg.ne0, &e0b, &e0e);
   f64x4 acc[RT][ANN_TILES];
