@@ -877,30 +877,28 @@ struct Group {
   ProbDesc* desc = nullptr;
 };
 
-// Coarse Hockney transforms of a batch of nb tori.  Forward: the source
-// occupies slots [0, ns)^3, so the axis-2 pass skips lines outside
+// Coarse Hockney convolution of a batch of nb tori with the real-even
+// spectrum `oct` (octant layout): forward along axes 2 and 1, one sweep along
+// axis 0 (forward, product, inverse), inverse along axes 1 and 2.  Forward:
+// the source occupies slots [0, ns)^3, so the axis-2 pass skips lines outside
 // [0, ns)^2 and the axis-1 pass slabs k0 >= ns (all zero).  Inverse: only
 // slots (o0 + [0, no)) mod M of each axis are read afterwards, so the axis-1
 // pass is limited to those k0 and the axis-2 pass to those (k0, k1).
 template <int M>
-static void fft3_coarse_impl(cplx<double>* data, int dir, int nb, int ns, int o0, int no, hipStream_t s) {
+static void conv3_coarse_impl(cplx<double>* data, const double* oct, int nb, int ns, int o0, int no,
+                              hipStream_t s) {
   constexpr int NL = (M % 4 == 0) ? 4 : 2;
   auto blocks = [](int cnt) { return unsigned((cnt + NL - 1) / NL); };
-  if (dir > 0) {
-    hipLaunchKernelGGL((fft_axis_kernel<double, M, NL, 1>), dim3(blocks(ns), ns, nb), dim3(256), 0, s, data, 2, 0, 0, ns);
-    hipLaunchKernelGGL((fft_axis_kernel<double, M, NL, 1>), dim3(blocks(M), ns, nb), dim3(256), 0, s, data, 1, 0, 0, M);
-    hipLaunchKernelGGL((fft_axis_kernel<double, M, NL, 1>), dim3(blocks(M), M, nb), dim3(256), 0, s, data, 0, 0, 0, M);
-  } else {
-    hipLaunchKernelGGL((fft_axis_kernel<double, M, NL, -1>), dim3(blocks(M), M, nb), dim3(256), 0, s, data, 0, 0, 0, M);
-    hipLaunchKernelGGL((fft_axis_kernel<double, M, NL, -1>), dim3(blocks(M), no, nb), dim3(256), 0, s, data, 1, o0, 0,
-                       M);
-    hipLaunchKernelGGL((fft_axis_kernel<double, M, NL, -1>), dim3(blocks(no), no, nb), dim3(256), 0, s, data, 2, o0, o0,
-                       no);
-  }
+  hipLaunchKernelGGL((fft_axis_kernel<double, M, NL, 1>), dim3(blocks(ns), ns, nb), dim3(256), 0, s, data, 2, 0, 0, ns);
+  hipLaunchKernelGGL((fft_axis_kernel<double, M, NL, 1>), dim3(blocks(M), ns, nb), dim3(256), 0, s, data, 1, 0, 0, M);
+  hipLaunchKernelGGL((fft_axis0_conv_kernel<double, M, NL>), dim3(blocks(M), M, nb), dim3(256), 0, s, data, oct);
+  hipLaunchKernelGGL((fft_axis_kernel<double, M, NL, -1>), dim3(blocks(M), no, nb), dim3(256), 0, s, data, 1, o0, 0, M);
+  hipLaunchKernelGGL((fft_axis_kernel<double, M, NL, -1>), dim3(blocks(no), no, nb), dim3(256), 0, s, data, 2, o0, o0,
+                     no);
 }
-static bool fft3_coarse(cplx<double>* data, int M, int dir, int nb, int ns, int o0, int no, hipStream_t s) {
+static bool conv3_coarse(cplx<double>* data, const double* oct, int M, int nb, int ns, int o0, int no, hipStream_t s) {
   switch (M) {
-#define CASE(MM) case MM: fft3_coarse_impl<MM>(data, dir, nb, ns, o0, no, s); return true;
+#define CASE(MM) case MM: conv3_coarse_impl<MM>(data, oct, nb, ns, o0, no, s); return true;
     MLC_FFT_SIZES(CASE)
 #undef CASE
   }
@@ -1159,10 +1157,7 @@ static void launch_rest(const Group& G, hipStream_t s, Stage stage) {
         o0 = lo;
         no = std::min(hi - lo, Mc);
       }
-      fft3_coarse(tor_of(k), Mc, 1, nb, ns, o0, no, s);
-      hipLaunchKernelGGL(mul_real_even_kernel, dim3(blocks_for(cube(Mc)), nb), dim3(256), 0, s, tor_of(k),
-                         G.plans[k]->coarse_spec, Mc);
-      fft3_coarse(tor_of(k), Mc, -1, nb, ns, o0, no, s);
+      conv3_coarse(tor_of(k), G.plans[k]->coarse_spec, Mc, nb, ns, o0, no, s);
     }
     for (int k = 0; k < np; ++k) {
       const mlc_plan_info& I = G.plans[k]->info;

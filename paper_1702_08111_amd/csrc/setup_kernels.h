@@ -135,6 +135,42 @@ __global__ void __launch_bounds__(256) fft_axis_kernel(cplx<T>* data, int axis, 
   }
 }
 
+// One sweep along axis 0 of a batch of complex M^3 arrays: forward
+// transform, times a real-even spectrum stored as its octant [Mh]^3 (layout
+// k0, k1, k2), inverse transform.  The last forward pass, the product and the
+// first inverse pass of a torus convolution, with the same arithmetic as
+// fft_axis_kernel, mul_real_even_kernel, fft_axis_kernel in turn.  Block:
+// NL lines (k1 = blockIdx.y, consecutive k2); blockIdx.z: array.
+template <typename T, int M, int NL>
+__global__ void __launch_bounds__(256) fft_axis0_conv_kernel(cplx<T>* data, const double* oct) {
+  __shared__ cplx<T> buf[NL * M];
+  __shared__ cplx<T> tw[M];
+  constexpr int Mh = M / 2 + 1;
+  fill_twiddles(tw, M);
+  data += int64_t(blockIdx.z) * M * M * M;
+  const int64_t es = int64_t(M) * M;
+  const int j0 = blockIdx.x * NL, u = blockIdx.y;
+  for (int t = threadIdx.x; t < NL * M; t += blockDim.x) {
+    const int r = t % NL, m = t / NL, v = j0 + r;
+    buf[r * M + m] = v < M ? data[int64_t(u) * M + v + m * es] : cplx<T>{T(0), T(0)};
+  }
+  __syncthreads();
+  fft_lines<T, M, NL, 256, 1, false>(buf, M, 1, tw);
+  const int a1 = min(u, M - u);
+  for (int t = threadIdx.x; t < NL * M; t += blockDim.x) {
+    const int r = t % NL, m = t / NL, v = j0 + r;
+    if (v >= M) continue;
+    const double g = oct[(int64_t(min(m, M - m)) * Mh + a1) * Mh + min(v, M - v)];
+    buf[r * M + m] = {buf[r * M + m].x * g, buf[r * M + m].y * g};
+  }
+  __syncthreads();
+  fft_lines<T, M, NL, 256, -1, false>(buf, M, 1, tw);
+  for (int t = threadIdx.x; t < NL * M; t += blockDim.x) {
+    const int r = t % NL, m = t / NL, v = j0 + r;
+    if (v < M) data[int64_t(u) * M + v + m * es] = buf[r * M + m];
+  }
+}
+
 // Periodised DGF on an M^3 torus, "symmetric fill": slot k holds G1 at the
 // signed offset k~ in (-M/2, M/2] (zero where the table ends).  The kernel
 // is real and even, so its DFT is real and even.
