@@ -146,9 +146,10 @@ template <typename T, int M> struct OutBatch {
   // block repeats the plane's y FFTs)
   static constexpr int YSPL = F32 ? 1 : 2;
   // z planes per block: the next plane's first lines load during the
-  // current plane's x pass, and the set-up is shared (measured: 5 for fp32
-  // at M >= 150, against 2, 3, 4 and 6; one for the smaller tori and for fp64)
-  static constexpr int ZPB = (F32 && M >= 150) ? 5 : 1;
+  // current plane's x pass, and the set-up is shared (measured: 5 at
+  // M >= 150, against 2, 3, 4 and 6 for fp32 and 2 to 4 for fp64; one for the
+  // smaller tori)
+  static constexpr int ZPB = M >= 150 ? 5 : 1;
 };
 
 // LDS ordering among the lanes of one wave (the wave's LDS operations are
