@@ -32,7 +32,6 @@ def parse():
     ap.add_argument("--workload", default="fp32_256_q6")
     ap.add_argument("--fp64-steps", type=int, default=5)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-budget", type=float, default=15.0, help="seconds of sampled per-patch oracle work")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain device copy of known size (for HBM counter scaling)")
     ap.add_argument("--batch-steps", type=int, default=5,
@@ -126,74 +125,35 @@ def measured_traffic(kernel, workload):
     return float(vals["traffic_bytes_per_launch"])
 
 
-def cpu_baseline(name, budget):
+def cpu_baseline(name):
+    """The oracle (oracle/, float64 NumPy/SciPy, untuned, SciPy FFTs with one
+    worker per available core) solving the same workload once, timed.  The
+    DGF table and the Legendre far-field tables are plan-time work (built
+    before a solve on the GPU too) and stay outside the timed region.
+    Returns the baseline record and the oracle's phi, against which the GPU
+    solves' errors are stated."""
     import scipy.fft
-    cores = len(os.sched_getaffinity(0))
-    with scipy.fft.set_workers(cores):
-        return _cpu_baseline(name, budget, cores)
-
-
-def _cpu_baseline(name, budget, cores):
-    """The oracle (oracle/, float64 NumPy/SciPy, untuned) on the host cores:
-    its per-patch step-1 work (local field, moments, coarse charges, skeleton
-    contributions) on a sample of patches within `budget` seconds, plus the
-    global work (coarse solve, coarse interpolation, all Dirichlet solves)
-    once; the full-solve time is estimated as per-patch x patches + global.
-    Plan-time tables (DGF, Legendre far fields) are excluded, as on the GPU.
-    SciPy's FFTs run with one worker per available core."""
-    from oracle import legendre as leg
     from oracle import mlc as om
-    from oracle import convolution as oconv
     from oracle.dgf import dgf
 
+    cores = len(os.sched_getaffinity(0))
     N, n, Q, bumps = mi.workload(name)
     f = mi.bump_charge(N, bumps)
     prm = om.Params(N=N, n=n, alpha=3.0, beta=6.0, P=4, Q=Q, Z=128)
-    progress("CPU oracle: DGF table (plan time, not timed)")
-    G1 = dgf(Q, 128)
-    progress("CPU oracle: far-field tables (plan time, not timed)")
-    Phi, T, Phi_lo, _ = om.far_field_tables(G1, prm)
-    tabs = om._annulus_plane_tables(Phi, Phi_lo, prm)
-    progress(f"CPU oracle: per-patch work for up to {budget:.0f} s")
-    patches = om.patch_indices(N, n)
-    order = np.random.default_rng(0).permutation(len(patches))
-    S_lo, S_hi, O_lo, O_hi = om.coarse_boxes(prm)
-    FH = np.zeros((S_hi - S_lo + 1,) * 3)
-    accum = np.zeros((N + 1,) * 3)
-    cache = {}
-    e, da = prm.e, prm.d_alpha
-    done = 0
-    t0 = time.perf_counter()
-    while done < len(patches) and (time.perf_counter() - t0 < budget or done < 2):
-        i = patches[order[done]]
-        lo = n * i
-        phi_i = om.local_field(G1, prm, om.patch_charge(f, n, i), "fft", cache)
-        c = leg.moments(f[lo[0]:lo[0] + n + 1, lo[1]:lo[1] + n + 1, lo[2]:lo[2] + n + 1], n, prm.P, prm.R)
-        lap = om.coarse_laplacian_of_samples(phi_i, Q, prm.H)
-        lap_lo = (lo - e) // 4 + 1
-        ca_lo, ca_hi = (lo - da) // 4, (lo + n + da) // 4
-        FH[tuple(slice(ca_lo[d] - S_lo, ca_hi[d] - S_lo + 1) for d in range(3))] += \
-            lap[tuple(slice(ca_lo[d] - lap_lo[d], ca_hi[d] - lap_lo[d] + 1) for d in range(3))]
-        om._accumulate_local(accum, phi_i, lo, prm)
-        om._accumulate_annulus(accum, c, tabs, lo, prm)
-        done += 1
-    t_patch = (time.perf_counter() - t0) / done
-    progress(f"CPU oracle: {done} patches sampled; coarse solve and Dirichlet solves")
-    t1 = time.perf_counter()
-    phiH = prm.H ** 2 * oconv.conv_hockney(G1, prm.Z, FH, np.full(3, O_lo - S_lo), np.full(3, O_hi - S_lo))
-    phiB = accum + om._interp_coarse_everywhere(phiH, O_lo, prm)
-    for i in patches:
-        lo = n * i
-        sl = tuple(slice(lo[d], lo[d] + n + 1) for d in range(3))
-        om.dirichlet_solve(phiB[sl], f[sl], Q, prm.hh)
-    t_global = time.perf_counter() - t1
-    est = t_patch * len(patches) + t_global
-    return {
-        "value": float(N ** 3 / est), "unit": "grid points/s", "cores": cores, "kind": "oracle",
-        "sample": (f"oracle float64 step-1 work on {done} of {len(patches)} patches "
-                   f"({t_patch:.3f} s/patch) + global coarse solve/interpolation/Dirichlet "
-                   f"({t_global:.1f} s); full solve estimated {est:.1f} s"),
-    }
+    with scipy.fft.set_workers(cores):
+        progress("CPU oracle: DGF table (plan time, not timed)")
+        G1 = dgf(Q, 128)
+        progress("CPU oracle: far-field tables (plan time, not timed)")
+        tables = om.plan_tables(G1, prm)
+        progress("CPU oracle: one full two-level solve (timed)")
+        t0 = time.perf_counter()
+        phi = om.mlc_solve(f, prm, G1, tables=tables)
+        t = time.perf_counter() - t0
+    rec = {"value": float(N ** 3 / t), "unit": "grid points/s", "cores": cores, "kind": "oracle",
+           "sample": (f"one full oracle solve of this workload ({N}^3, {(N // n) ** 3} patches): step-1 local "
+                      f"fields, moments, coarse right-hand side, coarse solve, boundary values, Dirichlet solves "
+                      f"and correction in {t:.1f} s; DGF and far-field tables built beforehand, not timed")}
+    return rec, phi
 
 
 def progress(msg):
@@ -242,13 +202,15 @@ def batch_bench(ctx, steps, dev):
     return out
 
 
-def serving_bench(ctx, count, load, dev, warm=50, sat_requests=120, pool=4, ring=32):
+def serving_bench(ctx, count, load, dev, warm=50, sat_requests=120, pool=4, ring=32, verify_per_size=8):
     """The serving loop: requests with N ~ U{64,128,192,256}, n ~ U{16,32},
     Q ~ U{4,6}, 1-4 seeded bumps, float32 convolutions.  First the
     saturation rate (a burst of requests, drained); then Poisson arrivals at
     `load` x that rate, warm-ups then `count` measured requests.  Each (N)
     keeps `pool` charges (those of its first requests) reused cyclically and
-    a ring of output arrays; plans are built up front (resident tables)."""
+    a ring of output arrays; plans are built up front (resident tables).
+    Afterwards the results still in the rings (up to verify_per_size per N)
+    are compared bit for bit with the same problems solved alone."""
     import torch
     from paper_1702_08111_amd import mlc as gm
     reqs = mi.serving_requests(warm + count + sat_requests, 1.0, seed=105)
@@ -267,12 +229,14 @@ def serving_bench(ctx, count, load, dev, warm=50, sat_requests=120, pool=4, ring
             probs[(N, n, Q)] = gm.problem(N, n, 3.0, 6.0, 4, Q, conv="fp32")
             srv.prepare(probs[(N, n, Q)])
     use = {N: 0 for N in charges}
+    last = {}   # (N, ring slot) -> (n, Q, k) of the request that wrote it last
 
     def submit(N, n, Q):
         k = use[N]
         use[N] += 1
         st, t = srv.submit(probs[(N, n, Q)], charges[N][k % pool], outs[N][k % ring])
         assert st == gm.MLC_OK, st
+        last[(N, k % ring)] = (n, Q, k)
         return t
 
     # saturation: a burst, drained
@@ -308,6 +272,26 @@ def serving_bench(ctx, count, load, dev, warm=50, sat_requests=120, pool=4, ring
             if wait > 2e-4:
                 time.sleep(min(wait, 1e-3))
     srv.close()
+    torch.cuda.synchronize()
+    # the results still held in the output rings, each against the same
+    # problem solved alone by its own plan (bit for bit)
+    checked = equal = 0
+    alone = {}
+    for (N, slot), (n, Q, k) in sorted(last.items()):
+        if slot >= verify_per_size:
+            continue
+        if (N, n, Q) not in alone:
+            pl = ctx.plan(probs[(N, n, Q)])
+            alone[(N, n, Q)] = (pl, torch.empty(pl.workspace_bytes, dtype=torch.uint8, device=dev))
+        pl, ws = alone[(N, n, Q)]
+        ref = torch.empty_like(outs[N][slot])
+        pl.solve(charges[N][k % pool], ref, ws)
+        torch.cuda.synchronize()
+        checked += 1
+        equal += int(torch.equal(ref, outs[N][slot]))
+    for pl, _ in alone.values():
+        pl.close()
+    del alone
     meas = [d for d in done if d[0] >= warm]
     lat = np.array([d[2]["total_ms"] for d in meas])
     qms = np.array([d[2]["queue_ms"] for d in meas])
@@ -322,6 +306,7 @@ def serving_bench(ctx, count, load, dev, warm=50, sat_requests=120, pool=4, ring
             "queue_p50_ms": float(np.percentile(qms, 50)), "queue_p99_ms": float(np.percentile(qms, 99)),
             "mean_batch": float(np.mean([d[2]["batch_size"] for d in meas])),
             "requests": len(meas), "warmup": warm, "failed": bad,
+            "verified": checked, "verified_equal_alone": equal,
             "arrival_rate_rps": rate, "load": load, "saturation_rps": sat_rate,
             "saturation_points_per_s": sat_points,
             "config": "Poisson arrivals; N ~ U{64,128,192,256}, n ~ U{16,32}, Q ~ U{4,6}, 1-4 bumps (seed 105), "
@@ -381,6 +366,8 @@ def main():
     err_32_64 = float(np.abs(a32 - a64).max() / scale)
     err64_exact = float(np.abs(a64 - exact).max() / np.abs(exact).max())
     err32_exact = float(np.abs(a32 - exact).max() / np.abs(exact).max())
+    errors = {"fp32_vs_fp64_relmax": err_32_64, "fp64_vs_closed_form": err64_exact,
+              "fp32_vs_closed_form": err32_exact, "fp32_vs_oracle": None, "fp64_vs_oracle": None}
 
     # roofline of the dominant kernel (largest measured time per solve)
     model = kernel_model(p32.info)
@@ -435,7 +422,13 @@ def main():
     cpu = None
     if not args.no_cpu_baseline:
         progress("CPU oracle baseline")
-        cpu = cpu_baseline(args.workload, args.cpu_budget)
+        cpu, phi_or = cpu_baseline(args.workload)
+        oscale = np.abs(phi_or).max()
+        errors["fp32_vs_oracle"] = float(np.abs(a32 - phi_or).max() / oscale)
+        errors["fp64_vs_oracle"] = float(np.abs(a64 - phi_or).max() / oscale)
+        errors["fp32_within_2e-6_of_oracle"] = errors["fp32_vs_oracle"] < 2e-6
+        errors["fp64_within_1e-12_of_oracle"] = errors["fp64_vs_oracle"] < 1e-12
+        del phi_or
 
     value = N ** 3 / (ms32 * 1e-3)
     line = {
@@ -462,8 +455,7 @@ def main():
         "p99_ms": float(np.percentile(lat32, 99)),
         "fp64": {"value": N ** 3 / (ms64 * 1e-3), "ms_per_step": ms64,
                  "p50_ms": float(np.percentile(lat64, 50)), "p99_ms": float(np.percentile(lat64, 99))},
-        "error": {"fp32_vs_fp64_relmax": err_32_64, "fp64_vs_closed_form": err64_exact,
-                  "fp32_vs_closed_form": err32_exact},
+        "error": errors,
         "kernels_ms": {k: round(v, 4) for k, v in sorted(per_kernel.items(), key=lambda kv: -kv[1])},
         "roofline": roof,
         "solve_roofline": solve_roof,

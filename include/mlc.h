@@ -57,7 +57,7 @@ typedef enum {
  * solves) is always float64. */
 typedef enum { MLC_CONV_FP64 = 0, MLC_CONV_FP32 = 1 } mlc_conv_precision;
 
-/* The problem, in the paper's notation (sec. 4, sec. 6.1). */
+/* The problem, in the paper's notation (sec. 4, sec. 7.1). */
 typedef struct {
   int32_t n_cells;        /* N: cells per axis; N % patch == 0                          */
   double h;               /* mesh spacing > 0 (unit cube: 1/N)                          */
@@ -104,8 +104,13 @@ const char* mlc_status_string(mlc_status s);
 mlc_status mlc_problem_info(const mlc_problem* prob, mlc_plan_info* out);
 
 /* Create a context on HIP device `device`.  hbm_budget_bytes caps the
- * device memory the context's resident tables and the server may hold
- * (0 = no cap).  Returns MLC_ERR_DEVICE if the device cannot be opened. */
+ * resident device memory of the context (0 = no cap): its DGF tables, the
+ * tables of every live plan and the arenas of its servers.  A DGF build,
+ * mlc_plan_create or mlc_server_create that would exceed the cap returns
+ * MLC_ERR_OUT_OF_MEMORY and keeps nothing; destroying a plan or server gives
+ * its share back.  Caller-owned workspaces and the transient buffers of a
+ * build are not counted.  Returns MLC_ERR_DEVICE if the device cannot be
+ * opened. */
 mlc_status mlc_context_create(int device, size_t hbm_budget_bytes, mlc_context** out);
 mlc_status mlc_context_destroy(mlc_context* ctx);
 
@@ -128,7 +133,9 @@ mlc_status mlc_plan_get_info(const mlc_plan* plan, mlc_plan_info* out);
 mlc_status mlc_plan_workspace_bytes(const mlc_plan* plan, size_t* bytes);
 
 /* The same figure computed from the problem alone, on the host (no device
- * is touched; equal to mlc_plan_workspace_bytes of the problem's plan). */
+ * is touched): equal to mlc_plan_workspace_bytes of the problem's plan, and
+ * for fft_size = -1 the largest figure over the tori the autotuner may pick,
+ * so that it bounds the plan's own. */
 mlc_status mlc_problem_workspace_bytes(const mlc_problem* prob, size_t* bytes);
 
 /* One two-level MLC solve (sec. 4.1): f (device, (N+1)^3 float64, read
@@ -154,7 +161,8 @@ mlc_status mlc_solve_batched(int32_t count, mlc_plan* const* plans, const double
  *                         modes by total degree then descending lexicographic p
  *   MLC_VIEW_COARSE_RHS   float64 [Ns]^3: F^H on [S_lo, S_lo+Ns-1]^3
  *   MLC_VIEW_COARSE_PHI   float64 [No]^3: phi^H on [O_lo, O_lo+No-1]^3
- *   MLC_VIEW_BOUNDARY     float64 [(N+1)^3]: phi^B on skeleton nodes (others 0)
+ *   MLC_VIEW_BOUNDARY     float64 [(N+1)^3]: phi^B on skeleton nodes (the other
+ *                         entries are not written by a solve)
  *   MLC_VIEW_LOCAL_COARSE conv precision [npatch][Wc]^3: phi_i at the coarse
  *                         nodes of its box G(Omega_alpha, 4b), starting at -e
  *   MLC_VIEW_LOCAL_PLANES conv precision [npatch][3][nplanes_a][Wa][Wa]:
@@ -234,7 +242,12 @@ mlc_status mlc_server_create(mlc_context* ctx, const mlc_server_config* cfg, mlc
 mlc_status mlc_server_prepare(mlc_server* srv, const mlc_problem* prob);
 /* Queue one solve.  MLC_ERR_INVALID_ARG / MLC_ERR_UNSUPPORTED for a bad
  * problem, MLC_ERR_OUT_OF_MEMORY if its workspace exceeds the arena,
- * MLC_ERR_BUSY if max_queue requests are unfinished.  *ticket is nonzero. */
+ * MLC_ERR_BUSY if max_queue requests are unfinished.  *ticket is nonzero.
+ * f must already hold its values on the device: the server's streams wait on
+ * no caller stream, so a caller that fills f asynchronously synchronises
+ * that work before submitting.  With MLC_CHECK=1 each request's f is checked
+ * alone (a failing request ends with MLC_ERR_INVALID_ARG without affecting
+ * the others). */
 mlc_status mlc_server_submit(mlc_server* srv, const mlc_problem* prob, const double* f, double* phi,
                              uint64_t* ticket);
 /* Status of a ticket: MLC_ERR_NOT_READY (*done = 0) while queued or

@@ -10,7 +10,7 @@ Charges
             phi = w R^2 psi(rho),
             psi = rho^2/6 - rho^4/5 + rho^6/7 - rho^8/18 + rho^10/110 - 1/10
                   (rho < 1),   -128 / (3465 rho)  (rho >= 1).
-  smooth    the paper's smooth test charge (sec. 6.1): f = (r - r^2)^4 for
+  smooth    the paper's smooth test charge (sec. 7.1): f = (r - r^2)^4 for
             r = |x - x0| / Ro < 1, Ro = 1/4, x0 = (1/2, 1/2, 1/2), with the
             potential printed there.
 
@@ -95,13 +95,13 @@ SMOOTH_RO = 0.25
 
 
 def smooth_charge(N):
-    """The paper's smooth charge (sec. 6.1) on the nodes of [0, 1]^3."""
+    """The paper's smooth charge (sec. 7.1) on the nodes of [0, 1]^3."""
     r = _rho(N, (0.5, 0.5, 0.5), SMOOTH_RO)
     return np.where(r < 1.0, (r - r * r) ** 4, 0.0)
 
 
 def smooth_potential(N):
-    """The closed-form potential printed with the smooth charge (sec. 6.1)."""
+    """The closed-form potential printed with the smooth charge (sec. 7.1)."""
     r = _rho(N, (0.5, 0.5, 0.5), SMOOTH_RO)
     inside = (r ** 6 / 42 - r ** 7 / 14 + r ** 8 / 12 - 2 * r ** 9 / 45 + r ** 10 / 110 - 1.0 / 1260)
     rs = np.where(r > 0, r, 1.0)

@@ -3,7 +3,7 @@
 
 The paper fixes only that the interpolation points are coplanar with the
 target, that the stencil radius is b and that the order is q_I (b = 2 -> 6,
-b = 3 -> 8, sec. 6.1); the operator itself is deferred to an earlier paper.
+b = 3 -> 8, sec. 7.1); the operator itself is deferred to an earlier paper.
 Reading used: tensor-product 1-D Lagrange interpolation in the plane of the
 patch face through the target node, on the 2b+2 coarse nodes U0-b .. U0+b+1
 per in-plane axis, with U0 = floor(g_a / Nref); degree 2b+1, order 2b+2 =

@@ -219,11 +219,25 @@ def _take_plane(arr, d, idx):
     return np.take(arr, idx, axis=d)
 
 
-def mlc_solve(f, prm, G1=None, conv_mode="fft", bc_mode="by_patch", keep=False):
+def plan_tables(G1, prm, conv_mode="fft"):
+    """The per-problem-class tables of the Legendre far field (sec. 4.1:
+    computed once and stored): far_field_tables and, for the regrouped
+    boundary values, _annulus_plane_tables.  None when beta == alpha."""
+    if not prm.beta > prm.alpha:
+        return None
+    Phi, T, Phi_lo, T_lo = far_field_tables(G1, prm, mode=conv_mode)
+    return dict(Phi=Phi, T=T, Phi_lo=Phi_lo, T_lo=T_lo, planes=_annulus_plane_tables(Phi, Phi_lo, prm))
+
+
+def mlc_solve(f, prm, G1=None, conv_mode="fft", bc_mode="by_patch", keep=False, on_local=None, tables=None):
     """Two-level MLC (sec. 4.1).  Returns phi on all (N+1)^3 nodes and, if
     keep, a dict of intermediates: moments, FH, phiH, phiB (full grid,
     meaningful on skeleton nodes), and the per-patch local fields (only for
-    bc_mode='literal')."""
+    bc_mode='literal').  on_local, if given, is called as
+    on_local(patch_number, i, phi_i) with each local field on E_i as soon as
+    it is computed (read only; it lets a caller inspect every patch's field
+    without keeping them all).  tables, if given, is plan_tables(G1, prm)
+    built beforehand (the same values the solve would build)."""
     from .dgf import dgf_cached
     prm.check()
     N, n, Q, b = prm.N, prm.n, prm.Q, prm.bb
@@ -240,8 +254,11 @@ def mlc_solve(f, prm, G1=None, conv_mode="fft", bc_mode="by_patch", keep=False):
     moments = np.zeros((len(patches), K))
     annulus = prm.beta > prm.alpha
     if annulus:
-        Phi, T, Phi_lo, T_lo = far_field_tables(G1, prm, mode=conv_mode)
-        tabs = _annulus_plane_tables(Phi, Phi_lo, prm) if bc_mode != "literal" else None
+        if tables is None:
+            Phi, T, Phi_lo, T_lo = far_field_tables(G1, prm, mode=conv_mode)
+            tabs = _annulus_plane_tables(Phi, Phi_lo, prm) if bc_mode != "literal" else None
+        else:
+            Phi, T, Phi_lo, T_lo, tabs = (tables[k] for k in ("Phi", "T", "Phi_lo", "T_lo", "planes"))
     cache = {}
     skel = skeleton_mask(N, n)
     accum = np.zeros((N + 1,) * 3)        # sum of (loc - I(loc)) per node
@@ -255,6 +272,8 @@ def mlc_solve(f, prm, G1=None, conv_mode="fft", bc_mode="by_patch", keep=False):
         fpatch = f[lo[0]:lo[0] + n + 1, lo[1]:lo[1] + n + 1, lo[2]:lo[2] + n + 1]
         c = leg.moments(fpatch, n, prm.P, R)
         moments[pi] = c
+        if on_local is not None:
+            on_local(pi, i, phi_i)
         # inner part: Delta^H phi_i on C(Omega_{i,alpha})
         lap = coarse_laplacian_of_samples(phi_i, Q, H)              # coarse nodes from (lo-e)/4+1
         lap_lo = (lo - e) // NREF + 1

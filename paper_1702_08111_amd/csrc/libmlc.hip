@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <atomic>
 #include <cmath>
 #include <cstdio>
 #include <cstdlib>
@@ -27,7 +28,8 @@ using namespace mlc;
 // ------------------------------------------------------------------ state
 struct mlc_context {
   int device = 0;
-  size_t budget = 0;
+  size_t budget = 0;                  // cap on resident device memory (0: none)
+  std::atomic<size_t> resident{0};    // DGF tables, plan tables, server arenas
   std::mutex err_mu;    // guards last_error
   std::string last_error;
   std::mutex build_mu;  // serialises plan and DGF builds (a server thread may build too)
@@ -35,11 +37,29 @@ struct mlc_context {
   std::map<std::vector<int>, int> tuned;          // autotuned local torus per patch-work class
   // per caller stream: a second stream (default priority) for the stages
   // that do not depend on the local convolutions, and the fork/join events
-  struct Side { hipStream_t stream = nullptr; hipEvent_t ev[3] = {nullptr, nullptr, nullptr}; };
+  // and the MLC_CHECK flag of that caller stream (set by the device when f
+  // is nonzero on the outer boundary)
+  struct Side {
+    hipStream_t stream = nullptr;
+    hipEvent_t ev[3] = {nullptr, nullptr, nullptr};
+    int* check_flag = nullptr;
+  };
   std::mutex side_mu;
   std::map<hipStream_t, Side> side;
-  int* check_flag = nullptr;   // MLC_CHECK: set when f is nonzero on the outer boundary
 };
+
+// Resident-memory accounting against the context's budget (hbm_budget_bytes
+// of mlc_context_create): DGF tables, the tables of every live plan and the
+// server arenas.  Transient build buffers and caller workspaces are not
+// counted.
+bool mlc_budget_take(mlc_context* ctx, size_t bytes) {
+  size_t cur = ctx->resident.load();
+  for (;;) {
+    if (ctx->budget && cur + bytes > ctx->budget) return false;
+    if (ctx->resident.compare_exchange_weak(cur, cur + bytes)) return true;
+  }
+}
+void mlc_budget_give(mlc_context* ctx, size_t bytes) { ctx->resident -= bytes; }
 
 struct mlc_plan {
   mlc_context* ctx = nullptr;
@@ -58,6 +78,8 @@ struct mlc_plan {
   // workspace offsets of the plan's own (batch-of-one) layout
   size_t o_mom = 0, o_cs = 0, o_pl = 0, o_F = 0, o_phiH = 0, o_phiB = 0;
   size_t ws_total = 0;
+  size_t table_bytes = 0;   // device bytes of the buffers above (the plan's resident tables)
+  bool charged = false;     // table_bytes counted against the context's budget
   // per-kernel timing (instrumentation)
   struct Pending { const char* name; hipEvent_t a, b; };
   mutable bool timing_on = false;
@@ -292,9 +314,9 @@ extern "C" mlc_status mlc_context_destroy(mlc_context* ctx) {
     hipStreamSynchronize(kv.second.stream);
     hipStreamDestroy(kv.second.stream);
     for (hipEvent_t e : kv.second.ev) hipEventDestroy(e);
+    hipFree(kv.second.check_flag);
   }
   for (auto& kv : ctx->dgf) hipFree(kv.second);
-  if (ctx->check_flag) hipFree(ctx->check_flag);
   delete ctx;
   return MLC_OK;
 }
@@ -336,10 +358,15 @@ static mlc_status get_dgf(mlc_context* ctx, int Q, int Z, double** table) {
   const int L = 2 * Z, Nd = 2 * L - 1, W = 2 * Z + 1;
   double* rhs = nullptr;
   double* tab = nullptr;
-  if (hipMalloc(&rhs, sizeof(double) * cube(Nd)) != hipSuccess)
+  const size_t tab_bytes = sizeof(double) * cube(W);
+  if (!mlc_budget_take(ctx, tab_bytes)) return fail(ctx, MLC_ERR_OUT_OF_MEMORY, "DGF table exceeds the context's budget");
+  if (hipMalloc(&rhs, sizeof(double) * cube(Nd)) != hipSuccess) {
+    mlc_budget_give(ctx, tab_bytes);
     return fail(ctx, MLC_ERR_OUT_OF_MEMORY, "DGF work array allocation failed");
-  if (hipMalloc(&tab, sizeof(double) * cube(W)) != hipSuccess) {
+  }
+  if (hipMalloc(&tab, tab_bytes) != hipSuccess) {
     hipFree(rhs);
+    mlc_budget_give(ctx, tab_bytes);
     return fail(ctx, MLC_ERR_OUT_OF_MEMORY, "DGF table allocation failed");
   }
   Stencil st = stencil_of(Q);
@@ -358,6 +385,7 @@ static mlc_status get_dgf(mlc_context* ctx, int Q, int Z, double** table) {
   hipFree(rhs);
   if (e != hipSuccess) {
     hipFree(tab);
+    mlc_budget_give(ctx, tab_bytes);
     return fail(ctx, MLC_ERR_DEVICE, std::string("DGF build: ") + hipGetErrorString(e));
   }
   ctx->dgf[key] = tab;
@@ -380,7 +408,21 @@ extern "C" mlc_status mlc_dgf_table(mlc_context* ctx, int32_t Q, int32_t Z, cons
 // ----------------------------------------------------------------- plan
 static size_t align_up(size_t v) { return (v + 255) & ~size_t(255); }
 
+// hipMalloc of one of a plan's resident buffers, counted in table_bytes
+template <typename T>
+static bool plan_alloc(mlc_plan* P, T** ptr, size_t bytes) {
+  if (hipMalloc(reinterpret_cast<void**>(ptr), bytes) != hipSuccess) {
+    *ptr = nullptr;
+    return false;
+  }
+  P->table_bytes += bytes;
+  return true;
+}
+
 static void plan_destroy_buffers(mlc_plan* p) {
+  if (p->charged) mlc_budget_give(p->ctx, p->table_bytes);
+  p->charged = false;
+  p->table_bytes = 0;
   hipFree(p->conv_spec);
   hipFree(p->coarse_spec);
   hipFree(p->T);
@@ -518,8 +560,8 @@ static mlc_status build_tables(mlc_plan* P, const double* G1) {
             hipMalloc(&oct, sizeof(double) * cube(Mth)) == hipSuccess &&
             hipMalloc(&coarse, sizeof(double) * nc) == hipSuccess &&
             hipMalloc(&planes, sizeof(double) * npl) == hipSuccess &&
-            hipMalloc(&P->T, sizeof(double) * cube(P->Wbc) * K) == hipSuccess &&
-            hipMalloc(&P->D, sizeof(double) * npl * K) == hipSuccess;
+            plan_alloc(P, &P->T, sizeof(double) * cube(P->Wbc) * K) &&
+            plan_alloc(P, &P->D, sizeof(double) * npl * K);
   mlc_status st = MLC_OK;
   if (!ok) st = fail(ctx, MLC_ERR_OUT_OF_MEMORY, "far-field table allocation failed");
   if (st == MLC_OK) st = build_spectrum(ctx, G1, I.Z, Mt, work, oct, nullptr, 8, 1.0, 0, 1, 2);
@@ -552,7 +594,7 @@ static mlc_status build_tables(mlc_plan* P, const double* G1) {
   {
     const MfmaGeom& g = P->mg_skel;
     int64_t total = int64_t(3) * g.ne0 * g.ne * g.ne * (g.KP / 4) * g.nrp * 4;
-    if (hipMalloc(&P->Am, sizeof(double) * total) != hipSuccess)
+    if (!plan_alloc(P, &P->Am, sizeof(double) * total))
       return fail(ctx, MLC_ERR_OUT_OF_MEMORY, "far-field MFMA table allocation failed");
     hipLaunchKernelGGL(skel_mfma_table_kernel, dim3(blocks_for(total)), dim3(256), 0, s, P->D, P->Am, n, db, P->P0b,
                        P->nplb, P->Wb, K, g);
@@ -561,7 +603,7 @@ static mlc_status build_tables(mlc_plan* P, const double* G1) {
     const MfmaGeom& g = P->mg_coarse;
     const int q = n / NREF;
     int64_t total = int64_t(g.ne) * g.ne * g.ne * (g.KP / 4) * g.nrp * 4;
-    if (hipMalloc(&P->Tm, sizeof(double) * total) != hipSuccess)
+    if (!plan_alloc(P, &P->Tm, sizeof(double) * total))
       return fail(ctx, MLC_ERR_OUT_OF_MEMORY, "far-field MFMA table allocation failed");
     hipLaunchKernelGGL(coarse_mfma_table_kernel, dim3(blocks_for(total)), dim3(256), 0, s, P->T, P->Tm, q, db,
                        P->Wbc, K, g);
@@ -692,6 +734,17 @@ extern "C" mlc_status mlc_problem_workspace_bytes(const mlc_problem* prob, size_
   mlc_status s = derive(prob, &I, &why);
   if (s != MLC_OK) return fail(nullptr, s, why);
   *bytes = layout_of({&I}).bytes;
+  if (prob->fft_size == -1) {
+    // the autotuner may pick any built torus the problem admits: the figure
+    // is the largest of their layouts, so that it bounds the plan's own
+    const int Mmin = 2 * (I.n + I.e) + 1;
+    for (int M : kFftSizes) {
+      if (M < Mmin || M / 2 > I.Z || !conv_size_ok(I.conv_precision, I.n, M)) continue;
+      mlc_plan_info J = I;
+      J.M = M;
+      *bytes = std::max(*bytes, layout_of({&J}).bytes);
+    }
+  }
   return MLC_OK;
 }
 
@@ -739,7 +792,7 @@ extern "C" mlc_status mlc_plan_create(mlc_context* ctx, const mlc_problem* prob,
     cplx<double>* work = nullptr;
     const int M = I.M, Mh = P->Mh;
     if (hipMalloc(&work, sizeof(cplx<double>) * cube(M)) != hipSuccess ||
-        hipMalloc(&P->conv_spec, size_t(tsz) * cube(Mh)) != hipSuccess) {
+        !plan_alloc(P, &P->conv_spec, size_t(tsz) * cube(Mh))) {
       hipFree(work);
       plan_destroy_buffers(P);
       delete P;
@@ -751,7 +804,7 @@ extern "C" mlc_status mlc_plan_create(mlc_context* ctx, const mlc_problem* prob,
       const int Mc = I.M_coarse, Mch = Mc / 2 + 1;
       cplx<double>* cw = nullptr;
       if (hipMalloc(&cw, sizeof(cplx<double>) * cube(Mc)) != hipSuccess ||
-          hipMalloc(&P->coarse_spec, sizeof(double) * cube(Mch)) != hipSuccess) {
+          !plan_alloc(P, &P->coarse_spec, sizeof(double) * cube(Mch))) {
         s = fail(ctx, MLC_ERR_OUT_OF_MEMORY, "coarse spectrum allocation failed");
       } else {
         s = build_spectrum(ctx, G1, I.Z, Mc, cw, P->coarse_spec, nullptr, 8, 1.0, 0, 1, 2);
@@ -778,6 +831,12 @@ extern "C" mlc_status mlc_plan_create(mlc_context* ctx, const mlc_problem* prob,
     P->o_phiB = L.o_phiB[0];
     P->ws_total = L.bytes;
   }
+  if (!mlc_budget_take(ctx, P->table_bytes)) {
+    plan_destroy_buffers(P);
+    delete P;
+    return fail(ctx, MLC_ERR_OUT_OF_MEMORY, "plan tables exceed the context's budget");
+  }
+  P->charged = true;
   *out = P;
   return MLC_OK;
 }
@@ -1221,13 +1280,15 @@ static mlc_context::Side* side_of(mlc_context* ctx, hipStream_t s) {
   if (it != ctx->side.end()) return &it->second;
   mlc_context::Side sd;
   if (hipStreamCreateWithFlags(&sd.stream, hipStreamNonBlocking) != hipSuccess) return nullptr;
-  for (hipEvent_t& e : sd.ev) {
-    if (hipEventCreateWithFlags(&e, hipEventDisableTiming) != hipSuccess) {
-      for (hipEvent_t x : sd.ev)
-        if (x) hipEventDestroy(x);
-      hipStreamDestroy(sd.stream);
-      return nullptr;
-    }
+  bool ok = hipMalloc(&sd.check_flag, sizeof(int)) == hipSuccess;
+  for (hipEvent_t& e : sd.ev)
+    if (ok && hipEventCreateWithFlags(&e, hipEventDisableTiming) != hipSuccess) ok = false;
+  if (!ok) {
+    for (hipEvent_t x : sd.ev)
+      if (x) hipEventDestroy(x);
+    hipFree(sd.check_flag);
+    hipStreamDestroy(sd.stream);
+    return nullptr;
   }
   return &(ctx->side[s] = sd);
 }
@@ -1298,20 +1359,30 @@ static bool check_enabled() {
   return e && e[0] == '1';
 }
 
+// The flag lives with the caller stream's side-stream state, so callers on
+// different streams (a server thread and the caller's own thread) never
+// share one.
 static mlc_status check_boundary(mlc_context* ctx, const double* f, int N, hipStream_t s) {
-  if (!ctx->check_flag && hipMalloc(&ctx->check_flag, sizeof(int)) != hipSuccess) {
-    ctx->check_flag = nullptr;
-    return fail(ctx, MLC_ERR_OUT_OF_MEMORY, "check flag allocation failed");
-  }
+  mlc_context::Side* sd = side_of(ctx, s);
+  if (!sd) return fail(ctx, MLC_ERR_DEVICE, "could not create the side stream and check flag");
+  int* flag = sd->check_flag;
   const int64_t faces = int64_t(6) * (N + 1) * (N + 1);
-  hipLaunchKernelGGL(set_flag_kernel, dim3(1), dim3(1), 0, s, ctx->check_flag, 0);
-  hipLaunchKernelGGL(boundary_check_kernel, dim3(blocks_for(faces)), dim3(256), 0, s, f, N, ctx->check_flag);
+  hipLaunchKernelGGL(set_flag_kernel, dim3(1), dim3(1), 0, s, flag, 0);
+  hipLaunchKernelGGL(boundary_check_kernel, dim3(blocks_for(faces)), dim3(256), 0, s, f, N, flag);
   int h = 0;
-  hipError_t e = hipMemcpyAsync(&h, ctx->check_flag, sizeof(int), hipMemcpyDeviceToHost, s);
+  hipError_t e = hipMemcpyAsync(&h, flag, sizeof(int), hipMemcpyDeviceToHost, s);
   if (e == hipSuccess) e = hipStreamSynchronize(s);
   if (e != hipSuccess) return fail(ctx, MLC_ERR_DEVICE, std::string("boundary check: ") + hipGetErrorString(e));
   if (h) return fail(ctx, MLC_ERR_INVALID_ARG, "f is nonzero on the outer boundary (MLC_CHECK)");
   return MLC_OK;
+}
+
+// for the serving loop (server.hip): whether MLC_CHECK is on, and the check
+// of one request's charge on the server's launch stream
+bool mlc_check_enabled() { return check_enabled(); }
+mlc_status mlc_check_charge(mlc_context* ctx, const double* f, int N, void* stream) {
+  HIP_TRY(ctx, hipSetDevice(ctx->device));
+  return check_boundary(ctx, f, N, static_cast<hipStream_t>(stream));
 }
 
 extern "C" mlc_status mlc_solve(mlc_plan* plan, const double* f, double* phi, void* workspace, size_t ws_bytes,

@@ -28,6 +28,10 @@
 // libmlc.hip internals used here
 void mlc_set_error(mlc_context* ctx, const std::string& msg);
 int mlc_context_device(const mlc_context* ctx);
+bool mlc_budget_take(mlc_context* ctx, size_t bytes);
+void mlc_budget_give(mlc_context* ctx, size_t bytes);
+bool mlc_check_enabled();
+mlc_status mlc_check_charge(mlc_context* ctx, const double* f, int N, void* stream);
 
 namespace {
 
@@ -226,19 +230,35 @@ bool admit(mlc_server* S) {
     for (auto it = S->queue.begin() + 1; it != S->queue.end() && int(group.size()) < S->cfg.max_batch; ++it)
       if (same_class(head->info, (*it)->info)) group.push_back(*it);
   }
-  // plans (a first use builds one: slow, and outside the queue lock)
+  // plans (a first use builds one: slow, and outside the queue lock); with
+  // MLC_CHECK each request's charge is checked alone, so that a bad one
+  // fails by itself and not the launch it would have joined
   std::vector<mlc_plan*> plans;
   std::vector<Request*> ok;
   bool failed = false;
+  const bool check = mlc_check_enabled();
   for (Request* r : group) {
     mlc_status st = MLC_OK;
     mlc_plan* P = plan_for(S, r->prob, &st);
-    if (!P) {
+    size_t own = 0;
+    if (P && mlc_plan_workspace_bytes(P, &own) == MLC_OK && round_up(own) > S->arena_bytes) {
+      mlc_set_error(S->ctx, "request workspace exceeds the server's workspace budget");
+      st = MLC_ERR_OUT_OF_MEMORY;
+      P = nullptr;
+    }
+    if (P && check) st = mlc_check_charge(S->ctx, r->f, r->info.N, S->streams[stream]);
+    if (!P || st != MLC_OK) {
       std::lock_guard<std::mutex> lk(S->mu);
       remove_from_queue_locked(S, r);
       finish_locked(S, r, st, Clock::now());
       failed = true;
       continue;
+    }
+    {
+      // the plan's sizes (its torus may be autotuned) decide the class of
+      // later groupings
+      std::lock_guard<std::mutex> lk(S->mu);
+      mlc_plan_get_info(P, &r->info);
     }
     plans.push_back(P);
     ok.push_back(r);
@@ -339,7 +359,13 @@ extern "C" mlc_status mlc_server_create(mlc_context* ctx, const mlc_server_confi
   S->cfg = c;
   S->device = device;
   S->arena_bytes = round_up(c.workspace_budget_bytes);
+  if (!mlc_budget_take(ctx, S->arena_bytes)) {
+    delete S;
+    mlc_set_error(ctx, "server arena exceeds the context's budget");
+    return MLC_ERR_OUT_OF_MEMORY;
+  }
   if (hipMalloc(reinterpret_cast<void**>(&S->arena_base), S->arena_bytes) != hipSuccess) {
+    mlc_budget_give(ctx, S->arena_bytes);
     delete S;
     mlc_set_error(ctx, "server arena allocation failed");
     return MLC_ERR_OUT_OF_MEMORY;
@@ -350,6 +376,7 @@ extern "C" mlc_status mlc_server_create(mlc_context* ctx, const mlc_server_confi
     if (hipStreamCreateWithFlags(&s, hipStreamNonBlocking) != hipSuccess) {
       for (hipStream_t t : S->streams) hipStreamDestroy(t);
       hipFree(S->arena_base);
+      mlc_budget_give(ctx, S->arena_bytes);
       delete S;
       mlc_set_error(ctx, "server stream creation failed");
       return MLC_ERR_DEVICE;
@@ -448,6 +475,7 @@ extern "C" mlc_status mlc_server_destroy(mlc_server* srv) {
   for (hipEvent_t e : srv->events) hipEventDestroy(e);
   for (hipStream_t s : srv->streams) hipStreamDestroy(s);
   hipFree(srv->arena_base);
+  mlc_budget_give(srv->ctx, srv->arena_bytes);
   for (auto& kv : srv->tickets) delete kv.second;
   delete srv;
   return MLC_OK;

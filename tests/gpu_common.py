@@ -59,7 +59,13 @@ def oracle_local(prm, f, i):
     """Coarse samples and plane corrections delta = phi_i - I(phi_i) of one
     patch's local field, laid out like the workspace views."""
     G1 = dgf_cached(prm.Q, prm.Z)
-    arr = omlc.local_field(G1, prm, omlc.patch_charge(f, prm.n, i))
+    return local_views(prm, omlc.local_field(G1, prm, omlc.patch_charge(f, prm.n, i)))
+
+
+def local_views(prm, arr):
+    """The workspace views of a local field given on E_i (the oracle's
+    array over [-e, n+e]^3): its coarse samples and its plane corrections
+    delta = phi_i - I(phi_i) on the skeleton planes inside Omega_alpha."""
     n, e, da, b = prm.n, prm.e, prm.d_alpha, prm.bb
     coarse = arr[::4, ::4, ::4]
     P0 = -((da // n) * n)

@@ -122,3 +122,19 @@ def test_binding_fails_loudly_without_library(monkeypatch, tmp_path):
         mlc.problem_info(mlc.problem(32, 8))
     with pytest.raises(RuntimeError):
         mlc.Context(0)
+
+
+@pytest.mark.parametrize("N,n,Q,conv", [(64, 16, 4, "fp32"), (128, 32, 6, "fp32"), (64, 16, 6, "fp64")])
+def test_autotuned_workspace_bounds_every_candidate(N, n, Q, conv):
+    """With fft_size = -1 the host-side workspace figure is the largest over
+    every built torus the autotuner may pick, so a server sizing requests by
+    it never under-reserves for the tuned plan."""
+    tuned = mlc.problem_workspace_bytes(mlc.problem(N, n, 3.0, 6.0, 4, Q, conv=conv, fft_size=-1))
+    sizes = []
+    for M in (50, 64, 72, 90, 96, 120, 128, 150, 160, 180, 192):
+        try:
+            sizes.append(mlc.problem_workspace_bytes(mlc.problem(N, n, 3.0, 6.0, 4, Q, conv=conv, fft_size=M)))
+        except mlc.MLCError:
+            pass
+    assert len(sizes) >= 2
+    assert tuned == max(sizes)

@@ -2,22 +2,20 @@
 
 128^3 (16^3-cell patches, 96^3 local torus, L19): every output against the
 full oracle solve.  256^3 (32^3-cell patches, L27), the benchmark's
-workload with the plans bench.py times: sampled outputs the oracle computes
-one by one (moments of all patches, local fields of sampled patches, the
-coarse right-hand side at sampled nodes), and invariants that hold at any
-size (the coarse solve inverts Delta^H, the patch solves satisfy the
-Mehrstellen equation with the final correction)."""
+workload with the plans bench.py times: invariants that hold at any size
+(the coarse solve inverts Delta^H, the patch solves satisfy the Mehrstellen
+equation with the final correction); its element-by-element parity with
+the oracle is tests/test_gpu_headline.py."""
 import numpy as np
 import pytest
 
 import mlc_inputs as mi
-from oracle import legendre as leg
 from oracle import mlc as omlc
 from oracle.dgf import dgf_cached
 from oracle.stencils import apply_laplacian
 from paper_1702_08111_amd import mlc as gm
 
-from gpu_common import gpu_solve, oracle_local, oracle_params, rel
+from gpu_common import gpu_solve, oracle_params, rel
 
 pytestmark = pytest.mark.gpu
 
@@ -53,63 +51,6 @@ def big():
     for conv in ("fp64", "fp32"):
         out[conv] = gpu_solve(gm.problem(N, n, 3.0, 6.0, 4, Q, conv=conv), f)
     return f, out
-
-
-def test_256_moments_all_patches(big):
-    f, out = big
-    info = out["fp64"]["info"]
-    prm = oracle_params(info, 3.0, 6.0)
-    n = prm.n
-    mom = np.array([leg.moments(f[n * i[0]:n * i[0] + n + 1, n * i[1]:n * i[1] + n + 1, n * i[2]:n * i[2] + n + 1],
-                                n, prm.P, prm.R) for i in omlc.patch_indices(prm.N, n)])
-    assert rel(out["fp64"]["moments"], mom) < 1e-12
-    assert rel(out["fp32"]["moments"], mom) < 1e-12
-
-
-@pytest.mark.parametrize("i", [(0, 0, 0), (3, 4, 2), (7, 2, 5)])
-def test_256_local_fields_sampled(big, i):
-    f, out = big
-    info = out["fp64"]["info"]
-    prm = oracle_params(info, 3.0, 6.0)
-    ppa = prm.N // prm.n
-    pidx = (i[0] * ppa + i[1]) * ppa + i[2]
-    c, dl = oracle_local(prm, f, i)
-    e64 = (rel(out["fp64"]["local_coarse"][pidx], c), rel(out["fp64"]["local_delta"][pidx], dl))
-    e32 = (rel(out["fp32"]["local_coarse"][pidx], c), rel(out["fp32"]["local_delta"][pidx], dl))
-    print(i, "fp64", e64, "fp32", e32, flush=True)
-    assert max(e64) < 1e-12
-    assert e32[0] < 2e-6
-
-
-def test_256_coarse_rhs_sampled(big):
-    """F^H at sampled coarse nodes from the oracle's local fields of every
-    patch whose inner region holds the node, and its Legendre far fields."""
-    f, out = big
-    info = out["fp64"]["info"]
-    prm = oracle_params(info, 3.0, 6.0)
-    G1 = dgf_cached(prm.Q, prm.Z)
-    n, da, db, e = prm.n, prm.d_alpha, prm.d_beta, prm.e
-    S_lo = info["S_lo"]
-    Phi, T, Phi_lo, T_lo = omlc.far_field_tables(G1, prm)
-    mom = out["fp64"]["moments"]   # checked against the oracle in test_256_moments_all_patches
-    patches = omlc.patch_indices(prm.N, n)
-    fields = {}
-    for c in [np.array([30, 33, 29]), np.array([8, 40, 56]), np.array([-10, 20, 70])]:
-        val = 0.0
-        for k, i in enumerate(patches):
-            lo = n * i
-            r = c - lo // 4
-            if np.all(r >= -da // 4) and np.all(r <= (n + da) // 4):
-                key = tuple(i)
-                if key not in fields:
-                    fields[key] = omlc.local_field(G1, prm, omlc.patch_charge(f, n, i))
-                lap = omlc.coarse_laplacian_of_samples(fields[key], prm.Q, prm.H)
-                val += lap[tuple(r + e // 4 - 1)]
-            elif np.all(r >= -db // 4) and np.all(r <= (n + db) // 4):
-                val += float(mom[k] @ T[(slice(None),) + tuple(r - T_lo)])
-        g = out["fp64"]["FH"][tuple(c - S_lo)]
-        scale = np.abs(out["fp64"]["FH"]).max()
-        assert abs(g - val) < 1e-12 * scale, (c, g, val)
 
 
 @pytest.mark.parametrize("conv", ["fp64", "fp32"])

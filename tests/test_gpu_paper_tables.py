@@ -1,10 +1,12 @@
-"""The paper's own error tables for the smooth charge (sec. 6.1), reproduced
+"""The paper's own error tables for the smooth charge (sec. 7.1), reproduced
 by the float64 GPU path at N = 256 (MI355X only).
 
 Loose pin: the interpolation operator I^H is a reading of the paper (it
 defers the operator to earlier work), so exact agreement is not expected;
 each error must be within a factor 4 of the printed value, and the trends the
-paper reports must hold (tests/golden/smooth_charge_two_level_errors.txt)."""
+paper reports must hold (tests/golden/smooth_charge_two_level_errors.txt).
+The rows with the Legendre far field at P = 4 (beta > alpha), whose error is
+not dominated by the interpolation, must agree within 20 %."""
 import os
 
 import numpy as np
@@ -46,6 +48,13 @@ def errors():
 def test_same_order_as_paper(errors):
     for key, (e, paper) in errors.items():
         assert paper / 4 < e < paper * 4, (key, e, paper)
+
+
+def test_far_field_rows_within_20_percent(errors):
+    rows = [(k, v) for k, v in errors.items() if k[4] == 4 and k[3] > k[2]]
+    assert rows
+    for key, (e, paper) in rows:
+        assert abs(e / paper - 1.0) < 0.2, (key, e, paper)
 
 
 def test_paper_trends(errors):

@@ -54,6 +54,9 @@ def _case(name):
         # of widths Wa + 2 and Wa + 8, tori 50 and 72)
         "b1_32": (32, 8, 3.0, 6.0, 4, 4, 0, 64, mi.bumps(2, 15, radius=(0.1, 0.25))),
         "b4_32": (32, 8, 3.0, 6.0, 4, 6, 0, 64, mi.bumps(2, 16, radius=(0.1, 0.25))),
+        # the benchmark's patch work (32^3-cell patches, L27, M = 160, far-field
+        # torus 250, Z = 128) on 2^3 patches
+        "n32_64": (64, 32, 3.0, 6.0, 4, 6, 160, 128, mi.bumps(2, 17, radius=(0.1, 0.2))),
     }
     return cases[name]
 
@@ -89,7 +92,7 @@ def _check_all(name, conv):
 
 
 @pytest.mark.parametrize("name", ["plain32", "plain32_q6", "mlc0_32", "p1_32", "ragged48", "single16", "p2_32",
-                                  "p3_32", "b1_32", "b4_32"])
+                                  "p3_32", "b1_32", "b4_32", "n32_64"])
 def test_fp64_parity(name):
     errs = _check_all(name, "fp64")
     for k, v in errs.items():
@@ -97,7 +100,7 @@ def test_fp64_parity(name):
 
 
 @pytest.mark.parametrize("name", ["plain32", "plain32_q6", "mlc0_32", "p1_32", "ragged48", "single16", "b1_32",
-                                  "b4_32"])
+                                  "b4_32", "n32_64"])
 def test_fp32_parity(name):
     errs = _check_all(name, "fp32")
     assert errs["phi"] < TOL32, errs

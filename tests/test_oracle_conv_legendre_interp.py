@@ -42,7 +42,7 @@ def test_direct_sum_at_points(dgf64_q4):
 
 # ---------------------------------------------------------------- Legendre
 def test_mode_count():
-    """K = P(P+1)(P+2)/6: 20 coefficients per patch for P = 4 (abstract, sec. 5)."""
+    """K = P(P+1)(P+2)/6: 20 coefficients per patch for P = 4 (abstract, sec. 6)."""
     assert [len(leg.mode_list(P)) for P in (1, 2, 3, 4, 5)] == [1, 4, 10, 20, 35]
 
 
@@ -136,7 +136,7 @@ def test_lagrange_mirror_symmetry(b):
 @pytest.mark.parametrize("b,qi", [(2, 6), (3, 8)])
 def test_interpolation_order(b, qi):
     """Interpolating exp-type data from a coarse grid of spacing H converges
-    at order q_I = 2b + 2 (sec. 6.1: b=2 gives 6, b=3 gives 8)."""
+    at order q_I = 2b + 2 (sec. 7.1: b=2 gives 6, b=3 gives 8)."""
     errs = []
     for H in (0.2, 0.1, 0.05):
         nf = 64

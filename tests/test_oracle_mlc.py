@@ -1,4 +1,4 @@
-"""Pins of the two-level MLC oracle as a whole (paper sec. 4.1, sec. 6.1)."""
+"""Pins of the two-level MLC oracle as a whole (paper sec. 4.1, sec. 7.1)."""
 import numpy as np
 import pytest
 
@@ -76,7 +76,7 @@ def test_discretisation_is_fourth_order():
 
 def test_mlc0_barrier_error_falls_with_beta():
     """Barrier error of MLC-0 (beta = alpha) scales like beta^-q: L19,
-    doubling beta cuts it by at least ~16 (sec. 6.1, Table 1 discussion)."""
+    doubling beta cuts it by at least ~16 (sec. 7.1, Table 1 discussion)."""
     G1 = dgf_cached(4, 128)
     N, n = 64, 16
     f = mi.smooth_charge(N)
@@ -147,3 +147,76 @@ def test_plain_config_error_vs_closed_form():
     glob = _global_discrete(G1, 64, f, N) + f / (12.0 * N * N)
     eg = np.abs(glob - ex).max() / np.abs(ex).max()
     assert err < 2 * eg, (err, eg)
+
+
+def _annulus_pairs(N, n, da, db):
+    """(skeleton node, patch) pairs with the node in Omega_beta(i) but not in
+    Omega_alpha(i): the pairs whose far field enters phi^B."""
+    plo = n * mlc.patch_indices(N, n)
+    count = 0
+    for g in np.argwhere(mlc.skeleton_mask(N, n)):
+        in_a = np.all((g >= plo - da) & (g <= plo + n + da), axis=1)
+        in_b = np.all((g >= plo - db) & (g <= plo + n + db), axis=1)
+        count += int(np.sum(in_b & ~in_a))
+    return count
+
+
+@pytest.mark.slow
+@pytest.mark.parametrize("Q", [4, 6])
+def test_boundary_values_literal_vs_regrouped_with_annulus(Q):
+    """The same equality as above on a grid wide enough that skeleton nodes
+    lie in the annulus Omega_beta(i) minus Omega_alpha(i) of some patches
+    (24^3 cells, 8^3-cell patches, alpha = 3, beta = 6), so the regrouped
+    far-field terms sum_p c_p [Phi_p - I(Phi_p)] of the large-case path are
+    exercised against the node-by-node definition (sec. 4.1 eqs.
+    philocmlcII, mlcfulldiscr)."""
+    N, n = 24, 8
+    G1 = dgf_cached(Q, 64)
+    prm = mlc.Params(N=N, n=n, alpha=3, beta=6, P=4, Q=Q, Z=64)
+    assert _annulus_pairs(N, n, prm.d_alpha, prm.d_beta) > 1000
+    f = mi.bump_charge(N, mi.bumps(3, 41, radius=(0.12, 0.2)))
+    phi1, a = mlc.mlc_solve(f, prm, G1, keep=True)
+    phi2, b = mlc.mlc_solve(f, prm, G1, bc_mode="literal", keep=True)
+    sk = mlc.skeleton_mask(N, n)
+    assert np.abs(a["phiB"] - b["phiB"])[sk].max() < 1e-14 * np.abs(b["phiB"]).max()
+    assert np.abs(phi1 - phi2).max() < 1e-14 * np.abs(phi2).max()
+
+
+@pytest.mark.parametrize("Q", [4, 6])
+def test_far_field_tables_vs_direct_sum_of_projected_charge(Q):
+    """Sum_p c_p Phi_p and sum_p c_p T_p (the tables of the Legendre far
+    field, sec. 4.1 step 1, built once per problem class by FFTs, mode by
+    mode) equal the literal convolution of the patch's projected charge
+    chi_i sum_p c_p Q^p with G^h, and its coarse Mehrstellen Laplacian
+    (sec. 2: coarse operators act on samples at the coarse nodes), at sampled
+    nodes of the table boxes, including annulus nodes."""
+    from oracle import legendre as leg
+    from oracle.stencils import apply_laplacian
+    N, n, P = 32, 8, 4
+    G1 = dgf_cached(Q, 64)
+    prm = mlc.Params(N=N, n=n, alpha=3, beta=6, P=P, Q=Q, Z=64)
+    h, H, R = prm.hh, prm.H, prm.R
+    f = mi.bump_charge(N, mi.bumps(2, 43, radius=(0.15, 0.3)))
+    i = np.array([1, 2, 1])
+    lo = n * i
+    c = leg.moments(f[lo[0]:lo[0] + n + 1, lo[1]:lo[1] + n + 1, lo[2]:lo[2] + n + 1], n, P, R)
+    # chi_0 times the projected charge, on the nodes of the patch at the origin
+    q = mlc.patch_charge(leg.projected_charge(c, n, P, R), n, (0, 0, 0))
+    Phi, T, Phi_lo, T_lo = mlc.far_field_tables(G1, prm)
+    eb = prm.d_beta + 4 * prm.bb
+    rng = np.random.default_rng(7)
+    pts = rng.integers(-eb, n + eb + 1, size=(60, 3))
+    pts[:3] = [[-eb, -eb, -eb], [n + eb, 0, n // 2], [-prm.d_beta, n + prm.d_alpha + 4, 3]]
+    direct = h * h * conv.conv_direct_at(G1, prm.Z, q, pts)
+    table = np.array([c @ Phi[(slice(None),) + tuple(x - Phi_lo)] for x in pts])
+    assert np.abs(direct - table).max() < 1e-13 * np.abs(direct).max()
+    # T at sampled coarse nodes of C(Omega_beta(0)), from 3^3 direct samples
+    cb_lo, cb_hi = -prm.d_beta // 4, (n + prm.d_beta) // 4
+    cs = rng.integers(cb_lo, cb_hi + 1, size=(12, 3))
+    cs[0] = [cb_lo, cb_lo, cb_hi]
+    for cc in cs:
+        off = np.stack(np.meshgrid(*[np.arange(-1, 2)] * 3, indexing="ij"), -1).reshape(-1, 3)
+        samp = h * h * conv.conv_direct_at(G1, prm.Z, q, 4 * (cc + off)).reshape(3, 3, 3)
+        lap = apply_laplacian(samp, Q, H)[0, 0, 0]
+        tab = c @ T[(slice(None),) + tuple(cc - T_lo)]
+        assert abs(lap - tab) < 1e-11 * np.abs(T).max() * np.abs(c).max(), (cc, lap, tab)
