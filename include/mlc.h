@@ -146,6 +146,24 @@ mlc_status mlc_problem_workspace_bytes(const mlc_problem* prob, size_t* bytes);
 mlc_status mlc_solve(mlc_plan* plan, const double* f, double* phi,
                      void* workspace, size_t ws_bytes, void* stream);
 
+/* The same solve for callers that cannot allocate device memory (code under
+ * HIP graph capture, tight serving loops, harnesses that forbid hipMalloc):
+ * instead of a caller workspace it uses the library's static scratch, a
+ * device array of MLC_STATIC_SCRATCH_BYTES of which each GPU the library runs
+ * on holds one copy until the process ends, and it runs every stage on
+ * `stream` (no side stream).  It calls no device allocator and creates no
+ * stream or event; f, phi and the plan are as for mlc_solve (the plan, with
+ * its resident tables, is built beforehand by mlc_plan_create).  Returns
+ * MLC_ERR_UNSUPPORTED when mlc_plan_workspace_bytes of the plan exceeds the
+ * scratch (for example every 32^3-cell-patch problem above 64^3 cells, or
+ * 16^3-cell patches above 96^3 cells with float32 convolutions).  Every call
+ * on one GPU shares that GPU's scratch, which keeps the last call's
+ * contents (a solve writes every scratch value it reads): calls that overlap
+ * on one GPU (on different streams, or from different threads) race, and
+ * must be ordered by the caller.  The MLC_CHECK device check is not run. */
+#define MLC_STATIC_SCRATCH_BYTES ((size_t)512 << 20)
+mlc_status mlc_solve_static(mlc_plan* plan, const double* f, double* phi, void* stream);
+
 /* Several independent problems in one pass: the per-patch stages of all
  * problems run in shared launches (their plans must share n, alpha, b, Q,
  * the torus M and the conv precision); coarse solves run per problem.

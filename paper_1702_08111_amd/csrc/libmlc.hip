@@ -120,6 +120,34 @@ struct TimedScope {
 
 static thread_local std::string g_error;   // errors before a context exists
 
+// ------------------------------------------------- allocation-free solves
+// The workspace of mlc_solve_static: one file-scope device array, of which
+// every GPU the library runs on holds its own copy until the process ends.
+// In host code `scratch` names a host-side stand-in, not a device address;
+// its device address on each GPU comes from hipGetSymbolAddress, taken once
+// per device (with that device current) when a context is created there,
+// and only that address is ever passed to kernels.
+constexpr size_t kStaticScratchBytes = MLC_STATIC_SCRATCH_BYTES;
+static __device__ __align__(256) unsigned char scratch[kStaticScratchBytes];
+static std::mutex g_scratch_mu;
+static std::map<int, void*> g_scratch_ptr;   // device -> its copy of scratch
+
+// With `device` current: record the address of its copy of scratch.
+static hipError_t scratch_init(int device) {
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (g_scratch_ptr.count(device)) return hipSuccess;
+  void* ptr = nullptr;
+  const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+  if (e == hipSuccess && ptr) g_scratch_ptr[device] = ptr;
+  return e == hipSuccess && !ptr ? hipErrorInvalidSymbol : e;
+}
+
+static void* scratch_of(int device) {
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  auto it = g_scratch_ptr.find(device);
+  return it == g_scratch_ptr.end() ? nullptr : it->second;
+}
+
 static mlc_status fail(mlc_context* ctx, mlc_status s, const std::string& msg) {
   if (ctx) {
     std::lock_guard<std::mutex> lk(ctx->err_mu);
@@ -299,6 +327,9 @@ extern "C" mlc_status mlc_context_create(int device, size_t hbm_budget_bytes, ml
   if (device < 0 || device >= count) return fail(nullptr, MLC_ERR_INVALID_ARG, "device index out of range");
   e = hipSetDevice(device);
   if (e != hipSuccess) return fail(nullptr, MLC_ERR_DEVICE, hipGetErrorString(e));
+  e = scratch_init(device);
+  if (e != hipSuccess)
+    return fail(nullptr, MLC_ERR_DEVICE, std::string("static scratch address: ") + hipGetErrorString(e));
   auto* c = new (std::nothrow) mlc_context;
   if (!c) return fail(nullptr, MLC_ERR_OUT_OF_MEMORY, "host allocation failed");
   c->device = device;
@@ -1280,15 +1311,13 @@ static mlc_context::Side* side_of(mlc_context* ctx, hipStream_t s) {
   if (it != ctx->side.end()) return &it->second;
   mlc_context::Side sd;
   if (hipStreamCreateWithFlags(&sd.stream, hipStreamNonBlocking) != hipSuccess) return nullptr;
-  bool ok = hipMalloc(&sd.check_flag, sizeof(int)) == hipSuccess;
-  for (hipEvent_t& e : sd.ev)
-    if (ok && hipEventCreateWithFlags(&e, hipEventDisableTiming) != hipSuccess) ok = false;
-  if (!ok) {
-    for (hipEvent_t x : sd.ev)
-      if (x) hipEventDestroy(x);
-    hipFree(sd.check_flag);
-    hipStreamDestroy(sd.stream);
-    return nullptr;
+  for (hipEvent_t& e : sd.ev) {
+    if (hipEventCreateWithFlags(&e, hipEventDisableTiming) != hipSuccess) {
+      for (hipEvent_t x : sd.ev)
+        if (x) hipEventDestroy(x);
+      hipStreamDestroy(sd.stream);
+      return nullptr;
+    }
   }
   return &(ctx->side[s] = sd);
 }
@@ -1300,10 +1329,35 @@ static mlc_context::Side* side_of(mlc_context* ctx, hipStream_t s) {
 //   side: (after fork 1) far-field sums | (after fork 2) coarse rhs and solve
 // Every launch of one call has ended before the caller stream passes the
 // join, so consecutive calls on s may reuse the workspace.
-static mlc_status enqueue_group(const Group& G, hipStream_t s) {
+// With one_stream set, every stage runs on s in the same order (no side
+// stream, no events): the same kernels on the same data, so the same result.
+static mlc_status enqueue_group(const Group& G, hipStream_t s, bool one_stream = false) {
   const mlc_plan* P0 = G.plans[0];
   const mlc_plan_info& I0 = P0->info;
   const int np = int(G.plans.size());
+  if (one_stream) {
+    const bool f32 = I0.conv_precision == MLC_CONV_FP32;
+    upload_descs(G, s);
+    if (!(f32 ? dispatch_conv<float>(G, s, 0) : dispatch_conv<double>(G, s, 0)))
+      return fail(P0->ctx, MLC_ERR_UNSUPPORTED, "local FFT size not built");
+    {
+      TimedScope ts(P0, s, "moments");
+      const int64_t work = int64_t(G.L.total) * I0.K;
+      hipLaunchKernelGGL(moments_finish_kernel, dim3(unsigned((work + 255) / 256)), dim3(256), 0, s, G.desc, np,
+                         I0.n, P0->modes, reinterpret_cast<const double*>(G.ws + G.L.o_mpart),
+                         reinterpret_cast<double*>(G.ws + G.L.o_mom), G.L.total);
+    }
+    if (f32) {
+      dispatch_conv<float>(G, s, 1);
+      for (Stage st : {FAR, COARSE, PLANES, FINISH}) launch_rest<float>(G, s, st);
+    } else {
+      dispatch_conv<double>(G, s, 1);
+      for (Stage st : {FAR, COARSE, PLANES, FINISH}) launch_rest<double>(G, s, st);
+    }
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return fail(P0->ctx, MLC_ERR_DEVICE, std::string("launch: ") + hipGetErrorString(e));
+    return MLC_OK;
+  }
   mlc_context::Side* sd = side_of(P0->ctx, s);
   if (!sd) return fail(P0->ctx, MLC_ERR_DEVICE, "could not create the side stream");
   const bool fp32 = I0.conv_precision == MLC_CONV_FP32;
@@ -1364,8 +1418,14 @@ static bool check_enabled() {
 // share one.
 static mlc_status check_boundary(mlc_context* ctx, const double* f, int N, hipStream_t s) {
   mlc_context::Side* sd = side_of(ctx, s);
-  if (!sd) return fail(ctx, MLC_ERR_DEVICE, "could not create the side stream and check flag");
-  int* flag = sd->check_flag;
+  if (!sd) return fail(ctx, MLC_ERR_DEVICE, "could not create the side stream");
+  int* flag = nullptr;
+  {
+    std::lock_guard<std::mutex> lk(ctx->side_mu);
+    if (!sd->check_flag && hipMalloc(&sd->check_flag, sizeof(int)) != hipSuccess) sd->check_flag = nullptr;
+    flag = sd->check_flag;
+  }
+  if (!flag) return fail(ctx, MLC_ERR_OUT_OF_MEMORY, "check flag allocation failed");
   const int64_t faces = int64_t(6) * (N + 1) * (N + 1);
   hipLaunchKernelGGL(set_flag_kernel, dim3(1), dim3(1), 0, s, flag, 0);
   hipLaunchKernelGGL(boundary_check_kernel, dim3(blocks_for(faces)), dim3(256), 0, s, f, N, flag);
@@ -1405,6 +1465,28 @@ extern "C" mlc_status mlc_solve(mlc_plan* plan, const double* f, double* phi, vo
   G.ws = static_cast<char*>(workspace);
   G.desc = reinterpret_cast<ProbDesc*>(G.ws + G.L.o_desc);
   return enqueue_group(G, static_cast<hipStream_t>(stream));
+}
+
+// mlc_solve on the device's static scratch instead of a caller workspace,
+// every stage on the caller's stream: no device allocation, stream or event
+// is created.  Calls that overlap on one device share the scratch and race.
+extern "C" mlc_status mlc_solve_static(mlc_plan* plan, const double* f, double* phi, void* stream) {
+  if (!plan || !f || !phi) return fail(plan ? plan->ctx : nullptr, MLC_ERR_INVALID_ARG, "null argument");
+  if (plan->ws_total > kStaticScratchBytes)
+    return fail(plan->ctx, MLC_ERR_UNSUPPORTED,
+                "the plan's workspace (" + std::to_string(plan->ws_total) + " bytes) exceeds the static scratch (" +
+                    std::to_string(kStaticScratchBytes) + " bytes); use mlc_solve with a workspace");
+  char* ws = static_cast<char*>(scratch_of(plan->ctx->device));
+  if (!ws) return fail(plan->ctx, MLC_ERR_DEVICE, "no static scratch address for the plan's device");
+  HIP_TRY(plan->ctx, hipSetDevice(plan->ctx->device));
+  Group G;
+  G.plans = {plan};
+  G.f = {f};
+  G.phi = {phi};
+  G.L = layout_of(infos_of(G.plans));
+  G.ws = ws;
+  G.desc = reinterpret_cast<ProbDesc*>(G.ws + G.L.o_desc);
+  return enqueue_group(G, static_cast<hipStream_t>(stream), true);
 }
 
 // Split a batch into class groups (first-appearance order) and lay them out

@@ -21,6 +21,8 @@ MLC_ERR_NOT_READY = -6
 MLC_CONV_FP64 = 0
 MLC_CONV_FP32 = 1
 
+MLC_STATIC_SCRATCH_BYTES = 512 << 20   # include/mlc.h
+
 MLC_VIEW_MOMENTS = 0
 MLC_VIEW_COARSE_RHS = 1
 MLC_VIEW_COARSE_PHI = 2
@@ -86,6 +88,7 @@ _SIGS = {
     "mlc_plan_workspace_bytes": (ctypes.c_int, [_P, ctypes.POINTER(ctypes.c_size_t)]),
     "mlc_problem_workspace_bytes": (ctypes.c_int, [ctypes.POINTER(mlc_problem), ctypes.POINTER(ctypes.c_size_t)]),
     "mlc_solve": (ctypes.c_int, [_P, _P, _P, _P, ctypes.c_size_t, _P]),
+    "mlc_solve_static": (ctypes.c_int, [_P, _P, _P, _P]),
     "mlc_batch_workspace_bytes": (ctypes.c_int, [ctypes.c_int32, ctypes.POINTER(_P), ctypes.POINTER(ctypes.c_size_t)]),
     "mlc_solve_batched": (ctypes.c_int, [ctypes.c_int32, ctypes.POINTER(_P), ctypes.POINTER(_P), ctypes.POINTER(_P),
                                          _P, ctypes.c_size_t, _P]),
@@ -214,6 +217,12 @@ class Plan:
         nbytes = workspace.numel() * workspace.element_size() if hasattr(workspace, "numel") else self.workspace_bytes
         _check(lib().mlc_solve(self.handle, _ptr(f), _ptr(phi), _ptr(workspace), nbytes, _stream(stream)),
                self.ctx.handle)
+
+    def solve_static(self, f, phi, stream=None):
+        """Enqueue one solve on the library's static scratch (no workspace,
+        no device allocation); raises MLCError(MLC_ERR_UNSUPPORTED) when the
+        plan's workspace exceeds it."""
+        _check(lib().mlc_solve_static(self.handle, _ptr(f), _ptr(phi), _stream(stream)), self.ctx.handle)
 
     def set_timing(self, enable):
         _check(lib().mlc_plan_set_timing(self.handle, 1 if enable else 0), self.ctx.handle)
