@@ -39,31 +39,41 @@ def parse():
     ap.add_argument("--serve-requests", type=int, default=1000,
                     help="measured requests of the serving loop after 50 warm-ups (0: skip)")
     ap.add_argument("--serve-load", type=float, default=0.7, help="arrival rate / saturation rate")
+    ap.add_argument("--osc-steps", type=int, default=5,
+                    help="timed steps of the oscillatory 384^3 workload per path (0: skip)")
     return ap.parse_args()
 
 
 def kernel_model(info):
     """Algorithmic bytes and flops per launch of each local-convolution kernel
-    (whole batch of patches).  Bytes: the kernel's compulsory reads and writes
-    in HBM (inputs once, outputs once).  Flops: nominal FFT counts
+    (whole batch of patches), split from the whole-solve model below: per
+    patch, the forward intermediate (n+1)^2 (M/2+1) complex values and the
+    output-side one W^2 (M/2+1), W = n + 2 d_alpha + 8b + 1 the local field
+    box, each written once and read once, plus the patch charge in and the
+    coarse samples and skeleton planes out:
+      conv_xdft  (n+1)^3 8 (f) + (n+1)^2 (M/2+1) c
+      conv_yz    (n+1)^2 (M/2+1) c + W^2 (M/2+1) c + the DGF spectrum once
+      conv_out   W^2 (M/2+1) c + (Wc^3 + 3 planes Wa^2) o
+    (c = complex, o = real conv-precision bytes).  Flops: nominal FFT counts
     5 L log2 L per complex line of length L, 4 per real x complex MAC,
     2 per real x complex product."""
     conv = 4 if info["conv_precision"] == 1 else 8       # bytes per real in conv precision
     cb = 2 * conv                                        # complex
     n, M, P = info["n"], info["M"], info["npatch"]
     S, Mh = n + 1, M // 2 + 1
+    W = n + 2 * info["d_alpha"] + 8 * info["b"] + 1
     Wp = info["Wa"] + 2 * info["b"]
     Wc, Wa, npl = info["Wc"], info["Wa"], info["nplanes_a"]
     lg = np.log2(M)
     fft = 5.0 * M * lg
     X = P * Mh * S * S * cb
-    Zb = P * Wp * Mh * M * cb
+    Zw = P * W * W * Mh * cb
     outs = P * (Wc ** 3 + 3 * npl * Wa * Wa) * conv
     return {
         "conv_xdft": dict(bytes=P * S ** 3 * 8 + X, flops=P * S * Mh * S * S * 4.0),
-        "conv_yz": dict(bytes=X + Zb + Mh ** 3 * conv,
+        "conv_yz": dict(bytes=X + Zw + Mh ** 3 * conv,
                         flops=P * Mh * (S * fft + M * 2 * fft + 2.0 * M * M)),
-        "conv_out": dict(bytes=Zb + outs, flops=P * Wp * (Mh * fft + ((Wp + 1) // 2) * fft)),
+        "conv_out": dict(bytes=Zw + outs, flops=P * Wp * (Mh * fft + ((Wp + 1) // 2) * fft)),
     }
 
 
@@ -198,6 +208,39 @@ def batch_bench(ctx, steps, dev):
     del ws, fs, phis
     for p in plans_by_n.values():
         p.close()
+    torch.cuda.empty_cache()
+    return out
+
+
+def oscillatory_bench(ctx, steps, dev, N=384, n=32, Q=6):
+    """The oscillatory three-charge workload of sec. 7.2 (gamma = 28 pi,
+    Ro = 1/20) at the largest convenient two-level size (384^3, 32^3-cell
+    patches, L27): float32 and float64 solves timed, errors against the
+    closed form and between the two paths."""
+    import torch
+    from paper_1702_08111_amd import mlc as gm
+    f = torch.from_numpy(mi.oscillatory_charge(N)).to(dev)
+    exact = mi.oscillatory_potential(N)
+    out = {"config": f"oscillatory three-charge charge (sec. 7.2), {N}^3, {n}^3-cell patches "
+                     f"({(N // n) ** 3}), L27, alpha=3, beta=6, P=4"}
+    phis = {}
+    for conv in ("fp32", "fp64"):
+        plan = ctx.plan(gm.problem(N, n, 3.0, 6.0, 4, Q, conv=conv))
+        ws = torch.empty(plan.workspace_bytes, dtype=torch.uint8, device=dev)
+        phi = torch.empty_like(f)
+        plan.solve(f, phi, ws)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            plan.solve(f, phi, ws)
+        torch.cuda.synchronize()
+        ms = (time.perf_counter() - t0) * 1e3 / steps
+        phis[conv] = phi.cpu().numpy()
+        out[conv] = {"ms_per_step": ms, "value": N ** 3 / (ms * 1e-3), "unit": "grid points/s",
+                     "vs_closed_form": float(np.abs(phis[conv] - exact).max() / np.abs(exact).max())}
+        del ws
+        plan.close()
+    out["fp32_vs_fp64_relmax"] = float(np.abs(phis["fp32"] - phis["fp64"]).max() / np.abs(phis["fp64"]).max())
     torch.cuda.empty_cache()
     return out
 
@@ -415,6 +458,10 @@ def main():
     if args.batch_steps > 0:
         progress("uneven 64-problem batch")
     batch = batch_bench(ctx, args.batch_steps, dev) if args.batch_steps > 0 else None
+    osc = None
+    if args.osc_steps > 0:
+        progress("oscillatory workload, 384^3")
+        osc = oscillatory_bench(ctx, args.osc_steps, dev)
     if args.serve_requests > 0:
         progress("serving loop")
     serving = serving_bench(ctx, args.serve_requests, args.serve_load, dev) if args.serve_requests > 0 else None
@@ -461,6 +508,7 @@ def main():
         "solve_roofline": solve_roof,
         "cpu_baseline": cpu,
         "batch": batch,
+        "oscillatory": osc,
         "serving": serving,
     }
     print(json.dumps(line), flush=True)

@@ -13,6 +13,9 @@ Charges
   smooth    the paper's smooth test charge (sec. 7.1): f = (r - r^2)^4 for
             r = |x - x0| / Ro < 1, Ro = 1/4, x0 = (1/2, 1/2, 1/2), with the
             potential printed there.
+  oscillatory  the three oscillatory charges of sec. 7.2:
+            f = Ro^-3 (r - r^2)^2 sin^2(gamma r / 2), Ro = 1/20,
+            gamma = 28 pi, centres printed there, with the printed potential.
 
 Workloads (seeded with numpy's PCG64; per bump: centre (3 uniforms),
 radius, weight, in that order):
@@ -107,6 +110,61 @@ def smooth_potential(N):
     rs = np.where(r > 0, r, 1.0)
     outside = -1.0 / (2310.0 * rs)
     return SMOOTH_RO ** 2 * np.where(r < 1.0, inside, outside)
+
+
+# The oscillatory three-charge test of sec. 7.2: each charge is supported in
+# a ball of radius OSC_RO, with gamma = 4 mu pi, mu = 7.
+OSC_RO = 0.05
+OSC_GAMMA = 28.0 * np.pi
+OSC_CENTRES = ((3 / 16, 7 / 16, 13 / 16), (7 / 16, 13 / 16, 3 / 16), (13 / 16, 3 / 16, 7 / 16))
+
+
+def _osc_profile(r, g=OSC_GAMMA):
+    """(r - r^2)^2 sin^2(g r / 2) inside the unit ball, 0 outside."""
+    return np.where(r < 1.0, (r - r * r) ** 2 * np.sin(0.5 * g * r) ** 2, 0.0)
+
+
+def _osc_psi(r, g=OSC_GAMMA):
+    """The dimensionless potential of one oscillatory charge (sec. 7.2): the
+    potential is psi(|x - x_o| / Ro) / Ro."""
+    r = np.asarray(r, dtype=np.float64)
+    rs = np.where(r > 0, r, 1.0)
+    c, sn = np.cos(g * rs), np.sin(g * rs)
+    inside = (rs ** 6 / 84 - rs ** 5 / 30 + rs ** 4 / 40 + 60 / g ** 6 - 9 / g ** 4 - 1 / 120 + 120 / (g ** 6 * rs)
+              + (-120 / (g ** 6 * rs) - 9 / g ** 4 + 300 / g ** 6 + 36 * rs / g ** 4 + rs ** 2 / (2 * g ** 2)
+                 - 30 * rs ** 2 / g ** 4 - rs ** 3 / g ** 2 + rs ** 4 / (2 * g ** 2)) * c
+              + (12 / (g ** 5 * rs) - 360 / (g ** 7 * rs) - 96 / g ** 5 + 120 * rs / g ** 5 - 3 * rs / g ** 3
+                 + 8 * rs ** 2 / g ** 3 - 5 * rs ** 3 / g ** 3) * sn)
+    outside = (-1.0 / 210 - 12 / g ** 4 + 360 / g ** 6) / rs
+    at0 = -1.0 / 120 - 6 / g ** 4
+    return np.where(r == 0, at0, np.where(r < 1.0, inside, outside))
+
+
+def oscillatory_charge(N):
+    """The sum of the three oscillatory charges of sec. 7.2 on the (N+1)^3
+    nodes of [0, 1]^3: f = Ro^-3 (r - r^2)^2 sin^2(gamma r / 2), r = |x - c| / Ro."""
+    f = np.zeros((N + 1,) * 3)
+    ax = np.arange(N + 1) / N
+    for c in OSC_CENTRES:
+        box = []
+        for d in range(3):
+            lo = max(int(np.floor((c[d] - OSC_RO) * N)) - 1, 0)
+            hi = min(int(np.ceil((c[d] + OSC_RO) * N)) + 1, N)
+            box.append(slice(lo, hi + 1))
+        d0 = (ax[box[0]] - c[0])[:, None, None]
+        d1 = (ax[box[1]] - c[1])[None, :, None]
+        d2 = (ax[box[2]] - c[2])[None, None, :]
+        r = np.sqrt(d0 * d0 + d1 * d1 + d2 * d2) / OSC_RO
+        f[tuple(box)] += _osc_profile(r) / OSC_RO ** 3
+    return f
+
+
+def oscillatory_potential(N):
+    """The closed-form potential of oscillatory_charge on the same nodes."""
+    phi = np.zeros((N + 1,) * 3)
+    for c in OSC_CENTRES:
+        phi += _osc_psi(_rho(N, c, OSC_RO)) / OSC_RO
+    return phi
 
 
 def one_bump():
