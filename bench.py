@@ -199,7 +199,19 @@ def batch_bench(ctx, steps, dev):
     ms = (time.perf_counter() - t0) * 1e3 / steps
     lat = np.array([a.elapsed_time(b) for a, b in ev])
     points = sum(N ** 3 for N, _ in probs)
+    # the same batch captured once by the library and replayed as one graph
+    g = gm.BatchGraph(plans, fs, phis, ws)
+    g.launch(stream)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        g.launch(stream)
+    torch.cuda.synchronize()
+    gms = (time.perf_counter() - t0) * 1e3 / steps
+    g.close()
     out = {"value": points / (ms * 1e-3), "unit": "grid points/s", "ms_per_step": ms,
+           "graph_ms_per_step": gms, "graph_value": points / (gms * 1e-3),
+           "out_planes_autotuned": plans[0].info["out_planes"],
            "p50_ms": float(np.percentile(lat, 50)), "p99_ms": float(np.percentile(lat, 99)),
            "problems": len(probs), "patches": int(sum(p.info["npatch"] for p in plans)),
            "workspace_gb": round(ws.numel() / 1e9, 2), "fft_size_autotuned": plans[0].info["M"],

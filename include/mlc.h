@@ -70,9 +70,11 @@ typedef struct {
   int32_t conv_precision; /* mlc_conv_precision                                        */
   int32_t fft_size;       /* Hockney torus edge M of the local convolutions: > 0 exact;
                              0 -> the smallest built size >= 2(n+e)+1; -1 -> autotuned:
-                             plan creation times every built size on a probe grid and
-                             keeps the fastest (cached per patch-work class in the
-                             context; mlc_problem_info reports the smallest)          */
+                             plan creation times every built size, each with every
+                             count of output planes per block in {1, 2, 3, 5, 8}, on a
+                             probe grid and keeps the fastest pair (cached per
+                             patch-work class in the context; mlc_problem_info
+                             reports the smallest size and the default count)       */
   int32_t dgf_half_width; /* Z of the DGF table [-Z, Z]^3 (solved on [-2Z, 2Z]^3); 0 -> 128 */
 } mlc_problem;
 
@@ -90,6 +92,8 @@ typedef struct {
   int32_t Z;                         /* DGF table half-width                             */
   int32_t conv_precision;
   double h, H;                       /* fine and coarse (4h) spacing                     */
+  int32_t out_planes;                /* z planes per block of the local convolutions'
+                                        output pass (tuned with fft_size = -1)           */
 } mlc_plan_info;
 
 typedef struct mlc_context mlc_context;
@@ -173,7 +177,24 @@ mlc_status mlc_batch_workspace_bytes(int32_t count, mlc_plan* const* plans, size
 mlc_status mlc_solve_batched(int32_t count, mlc_plan* const* plans, const double* const* f,
                              double* const* phi, void* workspace, size_t ws_bytes, void* stream);
 
-/* Intermediates of the last solve held in a workspace (device pointers into
+/* A batched solve captured once into a HIP graph and replayed: the arguments
+ * are those of mlc_solve_batched and stay bound to the graph (the caller keeps
+ * the plans, arrays and workspace alive and unmoved while the graph exists;
+ * a replay reads the current contents of f).  mlc_graph_create captures the
+ * launches of the batch (both streams' branches) on a stream of its own and
+ * instantiates the graph, enqueueing no work; mlc_graph_launch enqueues one
+ * replay on `stream`, equal bit for bit to mlc_solve_batched with the same
+ * arguments; replays of one graph, or of graphs sharing a workspace, must be
+ * ordered by the caller.  Per-kernel timing must be off for the captured
+ * plans (MLC_ERR_INVALID_ARG otherwise) and the MLC_CHECK device check is not
+ * part of a graph. */
+typedef struct mlc_graph mlc_graph;
+mlc_status mlc_graph_create(int32_t count, mlc_plan* const* plans, const double* const* f, double* const* phi,
+                            void* workspace, size_t ws_bytes, mlc_graph** out);
+mlc_status mlc_graph_launch(mlc_graph* graph, void* stream);
+mlc_status mlc_graph_destroy(mlc_graph* graph);
+
+/* Intermediates of the last solve held in a workspace/* Intermediates of the last solve held in a workspace (device pointers into
  * it; valid until the workspace is reused):
  *   MLC_VIEW_MOMENTS      float64 [npatch][K]: c_{i,p}, patches in C order of i,
  *                         modes by total degree then descending lexicographic p

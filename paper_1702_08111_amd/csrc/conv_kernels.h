@@ -145,12 +145,14 @@ template <typename T, int M> struct OutBatch {
   // half of the (kx, y) plane in LDS (room for the exchange slices; each
   // block repeats the plane's y FFTs)
   static constexpr int YSPL = F32 ? 1 : 2;
-  // z planes per block: the next plane's first lines load during the
-  // current plane's x pass, and the set-up is shared (measured: 5 at
-  // M >= 150, against 2, 3, 4 and 6 for fp32 and 2 to 4 for fp64; one for the
-  // smaller tori)
-  static constexpr int ZPB = M >= 150 ? 5 : 1;
 };
+
+// z planes per output block when no tuned value is given: the next plane's
+// first lines load during the current plane's x pass, and the set-up is
+// shared (measured at 256^3: 5 at M >= 150, against 2, 3, 4 and 6 for fp32
+// and 2 to 4 for fp64; one for the smaller tori).  The count only decides
+// which block computes a plane, never the arithmetic of a plane.
+__host__ __device__ constexpr int default_out_planes(int M) { return M >= 150 ? 5 : 1; }
 
 // LDS ordering among the lanes of one wave (the wave's LDS operations are
 // executed in order; this keeps the compiler from moving them across).
@@ -337,12 +339,15 @@ struct OutGeom {
 
 __device__ __forceinline__ int mod_pos(int a, int m) { int r = a % m; return r < 0 ? r + m : r; }
 
-template <typename T, int n, int M>
+// MULTI = false: one z plane per block, a compile-time count (the plane
+// loop and the next plane's prefetch compile away); MULTI = true: zpb >= 2
+// planes per block.
+template <typename T, int n, int M, bool MULTI>
 __global__ void __launch_bounds__((OutBatch<T, M>::NT)) conv_out_kernel(const cplx<T>* __restrict__ Zb,
                                                                       T* __restrict__ coarse,
                                                                       T* __restrict__ planes, OutGeom g,
                                                                       const ProbDesc* __restrict__ pd, int nprob,
-                                                                      int p0) {
+                                                                      int p0, int zpb_arg) {
   constexpr int Mh = M / 2 + 1;
   constexpr int R1 = Split<M>::R1, R2 = Split<M>::R2;
   constexpr int CB = OutBatch<T, M>::CB, XL = Batch<T, M>::XLYZ;
@@ -372,8 +377,8 @@ __global__ void __launch_bounds__((OutBatch<T, M>::NT)) conv_out_kernel(const cp
   __shared__ short xs_a[WPMAX], xs_c[WPMAX], xs_p[NPLMAX];
   constexpr int WXS = M / 2 + 1;   // row stride: the four rows on distinct LDS banks
   __shared__ cplx<T> Wx[NPLMAX * WXS];
-  constexpr int ZPB = OutBatch<T, M>::ZPB;
-  const int zi0 = (blockIdx.x / YSPL) * ZPB, pc = blockIdx.y, p = p0 + pc;
+  const int zpb = MULTI ? zpb_arg : 1;
+  const int zi0 = (blockIdx.x / YSPL) * zpb, pc = blockIdx.y, p = p0 + pc;
   const int Wp = g.Wp;
   // this block's output rows [ylo, yhi) of each plane
   const int Wh = (Wp + YSPL - 1) / YSPL, ylo = int(blockIdx.x % YSPL) * Wh, yhi = min(Wp, ylo + Wh);
@@ -426,7 +431,7 @@ __global__ void __launch_bounds__((OutBatch<T, M>::NT)) conv_out_kernel(const cp
     Wx[j * WXS + k] = tw[(k * xs) % M];
   }
 #pragma unroll 1
-  for (int q = 0; q < ZPB; ++q) {
+  for (int q = 0; q < zpb; ++q) {
     const int zi = zi0 + q;
     if (zi >= Wp) break;   // uniform over the block
     if (tid < 64) {
@@ -502,7 +507,7 @@ __global__ void __launch_bounds__((OutBatch<T, M>::NT)) conv_out_kernel(const cp
       }
     }
     // the next plane's first lines stay in flight through this plane's x pass
-    if (q + 1 < ZPB && zi + 1 < Wp) {
+    if (q + 1 < zpb && zi + 1 < Wp) {
       zin += int64_t(Mh) * M;
       load_lines(u0, wave * LW);
     }

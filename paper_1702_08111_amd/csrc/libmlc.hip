@@ -34,7 +34,8 @@ struct mlc_context {
   std::string last_error;
   std::mutex build_mu;  // serialises plan and DGF builds (a server thread may build too)
   std::map<std::pair<int, int>, double*> dgf;   // (Q, Z) -> (2Z+1)^3 table
-  std::map<std::vector<int>, int> tuned;          // autotuned local torus per patch-work class
+  // autotuned (local torus, output planes per block) per patch-work class
+  std::map<std::vector<int>, std::pair<int, int>> tuned;
   // per caller stream: a second stream (default priority) for the stages
   // that do not depend on the local convolutions, and the fork/join events
   // and the MLC_CHECK flag of that caller stream (set by the device when f
@@ -276,6 +277,7 @@ static mlc_status derive(const mlc_problem* p, mlc_plan_info* o, std::string* wh
     if (I.M < 0) { *why = "no built local FFT size fits this problem"; return MLC_ERR_UNSUPPORTED; }
   }
   if (I.M / 2 > I.Z) { *why = "DGF table too small for the local torus"; return MLC_ERR_UNSUPPORTED; }
+  I.out_planes = default_out_planes(I.M);
   I.Wc = (I.n + 2 * I.e) / NREF + 1;
   I.Wa = I.n + 2 * I.d_alpha + 1;
   {
@@ -779,7 +781,7 @@ extern "C" mlc_status mlc_problem_workspace_bytes(const mlc_problem* prob, size_
   return MLC_OK;
 }
 
-static int autotune_conv(mlc_context* ctx, const mlc_plan_info& I, const double* G1);
+static std::pair<int, int> autotune_conv(mlc_context* ctx, const mlc_plan_info& I, const double* G1);
 
 extern "C" mlc_status mlc_plan_create(mlc_context* ctx, const mlc_problem* prob, mlc_plan** out) {
   if (!ctx || !prob || !out) return fail(ctx, MLC_ERR_INVALID_ARG, "null argument");
@@ -811,11 +813,12 @@ extern "C" mlc_status mlc_plan_create(mlc_context* ctx, const mlc_problem* prob,
   s = get_dgf(ctx, I.Q, I.Z, &G1);
   if (s != MLC_OK) { delete P; return s; }
   if (prob->fft_size == -1) {
-    const int M = autotune_conv(ctx, I, G1);
-    if (M < 0) { delete P; return fail(ctx, MLC_ERR_DEVICE, "local FFT autotune failed"); }
-    I.M = M;
+    const std::pair<int, int> t = autotune_conv(ctx, I, G1);
+    if (t.first < 0) { delete P; return fail(ctx, MLC_ERR_DEVICE, "local FFT autotune failed"); }
+    I.M = t.first;
+    I.out_planes = t.second;
     P->info = I;
-    P->Mh = M / 2 + 1;
+    P->Mh = I.M / 2 + 1;
   }
   const int tsz = I.conv_precision == MLC_CONV_FP32 ? 4 : 8;
   // local-convolution spectrum: layout [kx][ky'][kz'] (kx: fastest array axis)
@@ -1061,11 +1064,15 @@ static void launch_conv(const Group& G, hipStream_t s, int phase, const std::fun
     if (p0 == 0 && after_yz) (*after_yz)();
     {
       TimedScope ts(P, s, "conv_out");
-      constexpr int zpb = OutBatch<T, M>::ZPB;
+      const int zpb = I.out_planes;
       constexpr int yspl = OutBatch<T, M>::YSPL;
-      hipLaunchKernelGGL((conv_out_kernel<T, n, M>), dim3((P->Wp + zpb - 1) / zpb * yspl, cnt), dim3(OutBatch<T, M>::NT),
-                         0, s, Zb, cs,
-                         pl, g, G.desc, np, p0);
+      const dim3 grid((P->Wp + zpb - 1) / zpb * yspl, cnt);
+      if (zpb == 1)
+        hipLaunchKernelGGL((conv_out_kernel<T, n, M, false>), grid, dim3(OutBatch<T, M>::NT), 0, s, Zb, cs, pl, g,
+                           G.desc, np, p0, 1);
+      else
+        hipLaunchKernelGGL((conv_out_kernel<T, n, M, true>), grid, dim3(OutBatch<T, M>::NT), 0, s, Zb, cs, pl, g,
+                           G.desc, np, p0, zpb);
     }
   }
 }
@@ -1557,20 +1564,121 @@ extern "C" mlc_status mlc_solve_batched(int32_t count, mlc_plan* const* plans, c
   return MLC_OK;
 }
 
+// ---------------------------------------------------------- batch graphs
+// One batched solve (fixed plans, arrays and workspace) captured once into a
+// HIP graph: the launches of every class group, the side-stream fork and join
+// included (they become parallel branches of the graph), so that a replay
+// re-runs the whole batch with one launch call.  The solve path enqueues
+// kernels only (no memsets, no host synchronisation), so it captures as is.
+struct mlc_graph {
+  mlc_context* ctx = nullptr;
+  hipStream_t cap = nullptr;     // the stream the batch was captured on (kept for its side stream)
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+};
+
+extern "C" mlc_status mlc_graph_create(int32_t count, mlc_plan* const* plans, const double* const* f,
+                                       double* const* phi, void* workspace, size_t ws_bytes, mlc_graph** out) {
+  if (!out) return fail(nullptr, MLC_ERR_INVALID_ARG, "null output pointer");
+  size_t need = 0;
+  std::vector<Group> groups;
+  mlc_status st = make_groups(count, plans, &groups, &need);
+  if (st != MLC_OK) return st;
+  mlc_context* ctx = plans[0]->ctx;
+  if (!f || !phi || !workspace) return fail(ctx, MLC_ERR_INVALID_ARG, "null argument");
+  if (ws_bytes < need) return fail(ctx, MLC_ERR_INVALID_ARG, "workspace too small");
+  if (reinterpret_cast<uintptr_t>(workspace) % 256)
+    return fail(ctx, MLC_ERR_INVALID_ARG, "workspace must be 256-byte aligned");
+  for (int k = 0; k < count; ++k) {
+    if (!f[k] || !phi[k]) return fail(ctx, MLC_ERR_INVALID_ARG, "null array in batch");
+    if (plans[k]->timing_on) return fail(ctx, MLC_ERR_INVALID_ARG, "per-kernel timing must be off while capturing");
+  }
+  HIP_TRY(ctx, hipSetDevice(ctx->device));
+  auto* g = new (std::nothrow) mlc_graph;
+  if (!g) return fail(ctx, MLC_ERR_OUT_OF_MEMORY, "host allocation failed");
+  g->ctx = ctx;
+  auto cleanup = [&](mlc_status s, const std::string& msg) {
+    if (g->exec) hipGraphExecDestroy(g->exec);
+    if (g->graph) hipGraphDestroy(g->graph);
+    if (g->cap) hipStreamDestroy(g->cap);
+    delete g;
+    return fail(ctx, s, msg);
+  };
+  if (hipStreamCreateWithFlags(&g->cap, hipStreamNonBlocking) != hipSuccess) {
+    g->cap = nullptr;
+    return cleanup(MLC_ERR_DEVICE, "capture stream creation failed");
+  }
+  // the capture stream's side stream and events exist before the capture
+  if (!side_of(ctx, g->cap)) return cleanup(MLC_ERR_DEVICE, "could not create the side stream");
+  char* base = static_cast<char*>(workspace);
+  for (auto& G : groups) {
+    for (int k : G.pos) {
+      G.f.push_back(f[k]);
+      G.phi.push_back(phi[k]);
+    }
+    G.ws = base + G.off;
+    G.desc = reinterpret_cast<ProbDesc*>(G.ws + G.L.o_desc);
+  }
+  hipError_t e = hipStreamBeginCapture(g->cap, hipStreamCaptureModeThreadLocal);
+  if (e != hipSuccess) return cleanup(MLC_ERR_DEVICE, std::string("begin capture: ") + hipGetErrorString(e));
+  for (auto& G : groups) {
+    st = enqueue_group(G, g->cap);
+    if (st != MLC_OK) break;
+  }
+  hipGraph_t graph = nullptr;
+  e = hipStreamEndCapture(g->cap, &graph);
+  g->graph = graph;
+  if (st != MLC_OK) return cleanup(st, "capture: a stage could not be enqueued");
+  if (e != hipSuccess) return cleanup(MLC_ERR_DEVICE, std::string("end capture: ") + hipGetErrorString(e));
+  e = hipGraphInstantiate(&g->exec, g->graph, nullptr, nullptr, 0);
+  if (e != hipSuccess) {
+    g->exec = nullptr;
+    return cleanup(MLC_ERR_DEVICE, std::string("graph instantiation: ") + hipGetErrorString(e));
+  }
+  *out = g;
+  return MLC_OK;
+}
+
+extern "C" mlc_status mlc_graph_launch(mlc_graph* g, void* stream) {
+  if (!g) return fail(nullptr, MLC_ERR_INVALID_ARG, "null graph");
+  HIP_TRY(g->ctx, hipSetDevice(g->ctx->device));
+  HIP_TRY(g->ctx, hipGraphLaunch(g->exec, static_cast<hipStream_t>(stream)));
+  return MLC_OK;
+}
+
+extern "C" mlc_status mlc_graph_destroy(mlc_graph* g) {
+  if (!g) return MLC_ERR_INVALID_ARG;
+  hipSetDevice(g->ctx->device);
+  if (g->exec) hipGraphExecDestroy(g->exec);
+  if (g->graph) hipGraphDestroy(g->graph);
+  if (g->cap) {
+    hipStreamSynchronize(g->cap);
+    hipStreamDestroy(g->cap);
+  }
+  delete g;
+  return MLC_OK;
+}
+
 // ------------------------------------------------------------- autotune
-// Local torus edge M for fft_size = -1: every built size >= the Hockney
-// minimum (and within the DGF table) is timed on a 4x4x4-patch probe grid
-// (the three local-convolution kernels, zero charge), and the fastest is
-// kept per patch-work class in the context.  Synchronises the device.
+// Local torus edge M and output planes per block for fft_size = -1: every
+// built size >= the Hockney minimum (and within the DGF table), with each
+// planes-per-block count, is timed on an 8x8x8-patch probe grid (the three
+// local-convolution kernels, zero charge), and the fastest pair is kept per
+// patch-work class in the context.  The planes per block never change a
+// result (each output plane is computed the same way by whichever block
+// holds it).  Synchronises the device.
 template <typename T>
-static double time_conv(mlc_context* ctx, const mlc_plan_info& I0, const double* G1, int M) {
+static double time_conv(mlc_context* ctx, const mlc_plan_info& I0, const double* G1, int M, int zpb) {
   mlc_plan Pt;
   Pt.ctx = ctx;
   Pt.info = I0;
   Pt.info.M = M;
-  Pt.info.N = 4 * I0.n;
-  Pt.info.patches_per_axis = 4;
-  Pt.info.npatch = 64;
+  Pt.info.out_planes = zpb;
+  // an 8^3-patch probe: as many blocks per launch as a full-size problem, so
+  // that the tiling's effect on how the chip fills is seen
+  Pt.info.N = 8 * I0.n;
+  Pt.info.patches_per_axis = 8;
+  Pt.info.npatch = 512;
   Pt.S = I0.n + 1;
   Pt.Mh = M / 2 + 1;
   Pt.Wp = I0.Wa + 2 * I0.b;
@@ -1600,14 +1708,22 @@ static double time_conv(mlc_context* ctx, const mlc_plan_info& I0, const double*
     hipStream_t s = nullptr;
     upload_descs(G, s);
     bool ok = dispatch_conv<T>(G, s, 0) && dispatch_conv<T>(G, s, 1);
-    hipEventRecord(a, s);
-    for (int r = 0; ok && r < 3; ++r) {
-      dispatch_conv<T>(G, s, 0);
-      dispatch_conv<T>(G, s, 1);
+    // the best of three timings of two passes each
+    for (int trial = 0; ok && trial < 3; ++trial) {
+      hipEventRecord(a, s);
+      for (int r = 0; r < 2; ++r) {
+        dispatch_conv<T>(G, s, 0);
+        dispatch_conv<T>(G, s, 1);
+      }
+      hipEventRecord(b, s);
+      float t = 0.f;
+      if (hipEventSynchronize(b) != hipSuccess || hipEventElapsedTime(&t, a, b) != hipSuccess) {
+        ok = false;
+        break;
+      }
+      if (ms < 0.0 || t / 2.0 < ms) ms = t / 2.0;
     }
-    hipEventRecord(b, s);
-    float t = 0.f;
-    if (ok && hipEventSynchronize(b) == hipSuccess && hipEventElapsedTime(&t, a, b) == hipSuccess) ms = t / 3.0;
+    if (!ok) ms = -1.0;
   }
   hipDeviceSynchronize();
   if (a) hipEventDestroy(a);
@@ -1620,19 +1736,24 @@ static double time_conv(mlc_context* ctx, const mlc_plan_info& I0, const double*
   return ms;
 }
 
-static int autotune_conv(mlc_context* ctx, const mlc_plan_info& I, const double* G1) {
+static std::pair<int, int> autotune_conv(mlc_context* ctx, const mlc_plan_info& I, const double* G1) {
   const std::vector<int> key{I.n, I.e, I.conv_precision, I.Q, I.Z};
   auto it = ctx->tuned.find(key);
   if (it != ctx->tuned.end()) return it->second;
-  const int Mmin = 2 * (I.n + I.e) + 1;
-  int best = -1;
+  const int Mmin = 2 * (I.n + I.e) + 1, Wp = I.Wa + 2 * I.b;
+  std::pair<int, int> best{-1, 1};
   double best_ms = 0.0;
+  // every built torus, and for each the z planes per block of the output
+  // pass (the tile of output planes a block walks through)
   for (int M : kFftSizes) {
     if (M < Mmin || M / 2 > I.Z || !conv_size_ok(I.conv_precision, I.n, M)) continue;
-    const double ms = I.conv_precision == MLC_CONV_FP32 ? time_conv<float>(ctx, I, G1, M)
-                                                          : time_conv<double>(ctx, I, G1, M);
-    if (ms > 0.0 && (best < 0 || ms < best_ms)) { best = M; best_ms = ms; }
+    for (int zpb : {1, 2, 3, 5, 8}) {
+      if (zpb > Wp) continue;
+      const double ms = I.conv_precision == MLC_CONV_FP32 ? time_conv<float>(ctx, I, G1, M, zpb)
+                                                            : time_conv<double>(ctx, I, G1, M, zpb);
+      if (ms > 0.0 && (best.first < 0 || ms < best_ms)) { best = {M, zpb}; best_ms = ms; }
+    }
   }
-  if (best > 0) ctx->tuned[key] = best;
+  if (best.first > 0) ctx->tuned[key] = best;
   return best;
 }

@@ -51,7 +51,7 @@ class mlc_plan_info(ctypes.Structure):
     _fields_ = [(name, ctypes.c_int32) for name in (
         "N", "n", "P", "Q", "b", "K", "d_alpha", "d_beta", "e", "patches_per_axis", "npatch",
         "M", "M_coarse", "M_table", "Wc", "Wa", "nplanes_a", "S_lo", "Ns", "O_lo", "No", "Z",
-        "conv_precision")] + [("h", ctypes.c_double), ("H", ctypes.c_double)]
+        "conv_precision")] + [("h", ctypes.c_double), ("H", ctypes.c_double), ("out_planes", ctypes.c_int32)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -92,6 +92,10 @@ _SIGS = {
     "mlc_batch_workspace_bytes": (ctypes.c_int, [ctypes.c_int32, ctypes.POINTER(_P), ctypes.POINTER(ctypes.c_size_t)]),
     "mlc_solve_batched": (ctypes.c_int, [ctypes.c_int32, ctypes.POINTER(_P), ctypes.POINTER(_P), ctypes.POINTER(_P),
                                          _P, ctypes.c_size_t, _P]),
+    "mlc_graph_create": (ctypes.c_int, [ctypes.c_int32, ctypes.POINTER(_P), ctypes.POINTER(_P), ctypes.POINTER(_P),
+                                        _P, ctypes.c_size_t, ctypes.POINTER(_P)]),
+    "mlc_graph_launch": (ctypes.c_int, [_P, _P]),
+    "mlc_graph_destroy": (ctypes.c_int, [_P]),
     "mlc_workspace_view": (ctypes.c_int, [_P, _P, ctypes.c_int32, ctypes.POINTER(_P), ctypes.POINTER(ctypes.c_size_t)]),
     "mlc_dgf_table": (ctypes.c_int, [_P, ctypes.c_int32, ctypes.c_int32, ctypes.POINTER(_P)]),
     "mlc_plan_set_timing": (ctypes.c_int, [_P, ctypes.c_int32]),
@@ -251,6 +255,33 @@ def solve_batched(plans, fs, phis, workspace, stream=None):
     pp = PA(*[_ptr(x) for x in phis])
     nbytes = workspace.numel() * workspace.element_size()
     _check(lib().mlc_solve_batched(k, hp, fp, pp, _ptr(workspace), nbytes, _stream(stream)), plans[0].ctx.handle)
+
+
+class BatchGraph:
+    """One batched solve captured into a HIP graph (mlc_graph_*): launch()
+    replays it; the plans, arrays and workspace stay bound to it."""
+
+    def __init__(self, plans, fs, phis, workspace):
+        k = len(plans)
+        PA = ctypes.c_void_p * k
+        hp = PA(*[p.handle.value for p in plans])
+        fp = PA(*[_ptr(x) for x in fs])
+        pp = PA(*[_ptr(x) for x in phis])
+        nbytes = workspace.numel() * workspace.element_size()
+        h = ctypes.c_void_p()
+        self.ctx = plans[0].ctx
+        _check(lib().mlc_graph_create(k, hp, fp, pp, _ptr(workspace), nbytes, ctypes.byref(h)), self.ctx.handle)
+        self.handle = h
+        self._keep = (plans, fs, phis, workspace)
+
+    def launch(self, stream=None):
+        _check(lib().mlc_graph_launch(self.handle, _stream(stream)), self.ctx.handle)
+
+    def close(self):
+        if self.handle:
+            lib().mlc_graph_destroy(self.handle)
+            self.handle = None
+            self._keep = None
 
 
 def batch_workspace_bytes(plans):

@@ -114,14 +114,66 @@ def test_autotuned_torus():
     prob = gm.problem(64, 16, 3.0, 6.0, 4, 4, conv="fp32", fft_size=-1)
     p1 = ctx.plan(prob)
     p2 = ctx.plan(prob)
-    M = p1.info["M"]
-    print("autotuned M", M, flush=True)
-    assert M in (90, 96, 120, 128) and p2.info["M"] == M
+    M, zpb = p1.info["M"], p1.info["out_planes"]
+    print("autotuned M", M, "output planes per block", zpb, flush=True)
+    assert M in (90, 96, 120, 128) and p2.info["M"] == M and p2.info["out_planes"] == zpb
+    assert zpb in (1, 2, 3, 5, 8)
     f_np = mi.bump_charge(64, mi.bumps(2, 41))
     f = torch.from_numpy(f_np).cuda()
     got = _alone(p1, f)
     prm = oracle_params(p1.info, 3.0, 6.0)
     ref = omlc.mlc_solve(f_np, prm, dgf_cached(4, 128))
     assert rel(got, ref) < 2e-6
+    # the planes per block decide which block computes an output plane, not
+    # how: the plan of the same torus with the default tiling gives the same
+    # result bit for bit
+    p3 = ctx.plan(gm.problem(64, 16, 3.0, 6.0, 4, 4, conv="fp32", fft_size=M))
+    assert p3.info["out_planes"] == (5 if M >= 150 else 1)
+    assert np.array_equal(_alone(p3, f), got)
     p1.close()
     p2.close()
+    p3.close()
+
+
+@pytest.mark.parametrize("conv", ["fp32", "fp64"])
+def test_batch_graph_replay(conv):
+    """A batch of two classes captured once by the library (mlc_graph_create)
+    and replayed: every replay equals the eager batched solve bit for bit,
+    with eager work and synchronisations between replays, and a replay reads
+    the charges' current contents."""
+    import torch
+    P = Plans()
+    spec = [(32, 16, mi.bumps(2, 61)), (48, 16, mi.bumps(3, 62)), (32, 8, mi.bumps(2, 63, radius=(0.15, 0.25))),
+            (64, 16, mi.bumps(1, 64))]
+    plans = [P.get(N, n, 4, conv) for N, n, _ in spec]
+    fs = [torch.from_numpy(mi.bump_charge(N, b)).cuda() for N, _, b in spec]
+    fs2 = [torch.from_numpy(mi.bump_charge(N, mi.bumps(2, 70 + k))).cuda() for k, (N, _, _) in enumerate(spec)]
+    ref = _batch(plans, fs)
+    ref2 = _batch(plans, fs2)
+    ws = torch.empty(gm.batch_workspace_bytes(plans), dtype=torch.uint8, device="cuda")
+    phis = [torch.empty_like(f) for f in fs]
+    src = [f.clone() for f in fs]
+    torch.cuda.synchronize()
+    g = gm.BatchGraph(plans, src, phis, ws)
+    try:
+        for r in range(4):
+            for p in phis:
+                p.fill_(float("nan"))
+            torch.cuda.synchronize()
+            g.launch()
+            torch.cuda.synchronize()
+            for k in range(len(spec)):
+                assert np.array_equal(phis[k].cpu().numpy(), ref[k]), (r, k)
+            # eager work between replays, on its own workspace
+            assert all(np.array_equal(a, b) for a, b in zip(_batch(plans, fs2), ref2))
+        # new charges in the same arrays: the replay solves them
+        for a, b in zip(src, fs2):
+            a.copy_(b)
+        torch.cuda.synchronize()
+        g.launch()
+        torch.cuda.synchronize()
+        for k in range(len(spec)):
+            assert np.array_equal(phis[k].cpu().numpy(), ref2[k]), k
+    finally:
+        g.close()
+    torch.cuda.synchronize()
