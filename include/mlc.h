@@ -64,7 +64,7 @@ typedef struct {
   int32_t patch;          /* n: cells per patch edge; n % 4 == 0, n >= 8                */
   double alpha, beta;     /* localisation radii in units of R = n h / 2; 1 <= alpha <= beta;
                              the margins ceil((r-1) n / 2) must be multiples of 4 (Nref)  */
-  int32_t P;              /* Legendre truncation: modes with |p|_1 < P; 1 <= P <= 4     */
+  int32_t P;              /* Legendre truncation: modes with |p|_1 < P; 1 <= P <= 9     */
   int32_t Q;              /* Mehrstellen operator: 4 -> L19, 6 -> L27                   */
   int32_t interp_b;       /* coplanar interpolation radius b (order 2b+2); 0 -> Q/2     */
   int32_t conv_precision; /* mlc_conv_precision                                        */

@@ -10,7 +10,8 @@
 namespace mlc {
 
 constexpr int NREF = 4;     // fine/coarse refinement ratio
-constexpr int KMAX = 20;    // Legendre moments for P <= 4
+constexpr int PMAX = 9;     // Legendre truncation order built (modes of total degree < P)
+constexpr int KMAX = PMAX * (PMAX + 1) * (PMAX + 2) / 6;   // 165 moments at P = 9
 constexpr int SMAX = 33;    // patch nodes per axis, n <= 32
 constexpr int SMAXN = SMAX;
 
@@ -23,13 +24,24 @@ inline Stencil stencil_of(int Q) {
 
 __host__ __device__ inline int64_t cube(int64_t a) { return a * a * a; }
 
-// Orthonormal Legendre polynomial sqrt((2a+1)/2) P_a(t), a <= 3 (sec. 3).
+// Orthonormal Legendre polynomial sqrt((2a+1)/2) P_a(t) (sec. 3): closed
+// forms up to degree 3, Bonnet's recurrence (k+1) P_{k+1} = (2k+1) t P_k -
+// k P_{k-1} above.
 __host__ __device__ inline double qhat(int a, double t) {
   switch (a) {
     case 0: return 0.70710678118654752440;
     case 1: return 1.22474487139158904910 * t;
     case 2: return 1.58113883008418966600 * 0.5 * (3.0 * t * t - 1.0);
-    default: return 1.87082869338697069280 * 0.5 * (5.0 * t * t * t - 3.0 * t);
+    case 3: return 1.87082869338697069280 * 0.5 * (5.0 * t * t * t - 3.0 * t);
+    default: {
+      double pm = 1.0, pk = t;
+      for (int k = 1; k < a; ++k) {
+        const double pn = ((2 * k + 1) * t * pk - k * pm) / (k + 1);
+        pm = pk;
+        pk = pn;
+      }
+      return sqrt((2 * a + 1) * 0.5) * pk;
+    }
   }
 }
 
@@ -49,8 +61,8 @@ __device__ __forceinline__ __attribute__((address_space(1))) T* gbl(T* p) {
   return (__attribute__((address_space(1))) T*)p;
 }
 
-// Partial moment sums per patch z-plane: one per (a1, a2), a1, a2 <= 3.
-constexpr int PLANE_MOMENTS = 16;
+// Partial moment sums per patch z-plane: one per (a1, a2), a1, a2 < P, at
+// index a1 P + a2.
 
 // Output-coordinate list of the local fields along one axis: b coarse nodes
 // below Omega_alpha, every node of Omega_alpha, b coarse nodes above.

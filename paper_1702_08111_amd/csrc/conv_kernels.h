@@ -24,15 +24,15 @@
 namespace mlc {
 
 template <typename T, int M>
-__global__ void __launch_bounds__(256) conv_xdft_kernel(const ProbDesc* __restrict__ pd, int nprob, int n,
+__global__ void __launch_bounds__(256) conv_xdft_kernel(const ProbDesc* __restrict__ pd, int nprob, int n, int P,
                                                         cplx<T>* __restrict__ X, double* __restrict__ mpart,
                                                         int p0) {
   constexpr int Mh = M / 2 + 1;
   __shared__ T q[SMAX * SMAX];
   __shared__ cplx<T> tw[M];
   __shared__ double fd[SMAX * SMAX];   // the plane of f as given (moment sums)
-  __shared__ double Bw[4][SMAX];       // Boole weight x qhat_a at each node
-  __shared__ double gx[4][SMAX];       // x-contracted moment sums per row
+  __shared__ double Bw[PMAX][SMAX];    // Boole weight x qhat_a at each node, a < P
+  __shared__ double gx[PMAX][SMAX];    // x-contracted moment sums per row
   const int S = n + 1;
   const int p = p0 + blockIdx.y, sz = blockIdx.x;
   const ProbDesc& D = pd[find_problem(pd, nprob, p)];
@@ -49,15 +49,15 @@ __global__ void __launch_bounds__(256) conv_xdft_kernel(const ProbDesc* __restri
     fd[t] = v;
     q[t] = T(c * v);
   }
-  for (int t = threadIdx.x; t < 4 * S; t += blockDim.x) {
+  for (int t = threadIdx.x; t < P * S; t += blockDim.x) {
     int a = t / S, j = t % S;
     Bw[a][j] = boole_w(j, n) * qhat(a, (j - 0.5 * n) / (0.5 * n));
   }
   fill_twiddles(tw, M);
   __syncthreads();
   // Legendre moment sums of this plane (sec. 4.1, step 1), x axis first
-  if (int(threadIdx.x) < 4 * S) {
-    const int a = threadIdx.x / S, sy = threadIdx.x % S;
+  for (int t = threadIdx.x; t < P * S; t += blockDim.x) {
+    const int a = t / S, sy = t % S;
     double acc = 0.0;
     for (int sx = 0; sx < S; ++sx) acc += Bw[a][sx] * fd[sy * S + sx];
     gx[a][sy] = acc;
@@ -112,11 +112,11 @@ __global__ void __launch_bounds__(256) conv_xdft_kernel(const ProbDesc* __restri
         if (kg + NK * a < Mh && sg + NY * b < S) out[int64_t(kx[a]) * S * S + sy[b]] = {ar[a][b], ai[a][b]};
   }
   __syncthreads();
-  if (threadIdx.x < PLANE_MOMENTS) {
-    const int a1 = threadIdx.x / 4, a2 = threadIdx.x % 4;
+  if (int(threadIdx.x) < P * P) {
+    const int a1 = threadIdx.x / P, a2 = threadIdx.x % P;
     double acc = 0.0;
     for (int sy = 0; sy < S; ++sy) acc += Bw[a1][sy] * gx[a2][sy];
-    mpart[(int64_t(p) * S + sz) * PLANE_MOMENTS + threadIdx.x] = acc;
+    mpart[(int64_t(p) * S + sz) * (P * P) + threadIdx.x] = acc;
   }
 }
 
@@ -136,8 +136,10 @@ template <typename T, int M> struct Batch {
 // conv_out holds the (kx, y) plane in LDS, so one block fills a CU.  Each
 // wave transforms its own lines (LW per step) through a private slice of
 // the exchange buffer, with no block barriers between FFT passes.
-template <typename T, int M> struct OutBatch {
+template <typename T, int M, bool MULTI = true> struct OutBatch {
   static constexpr bool F32 = sizeof(T) == 4;
+  // (12-wave single-plane blocks, which fit three waves per SIMD, measured
+  // slower: 128^3 output pass 0.58 -> 0.94 ms)
   static constexpr int NT = F32 ? 512 : 256;
   static constexpr int LW = 64 / Split<M>::R1;
   static constexpr int CB = (NT / 64) * LW;   // exchange lines of the block
@@ -343,14 +345,14 @@ __device__ __forceinline__ int mod_pos(int a, int m) { int r = a % m; return r <
 // loop and the next plane's prefetch compile away); MULTI = true: zpb >= 2
 // planes per block.
 template <typename T, int n, int M, bool MULTI>
-__global__ void __launch_bounds__((OutBatch<T, M>::NT)) conv_out_kernel(const cplx<T>* __restrict__ Zb,
+__global__ void __launch_bounds__((OutBatch<T, M, MULTI>::NT)) conv_out_kernel(const cplx<T>* __restrict__ Zb,
                                                                       T* __restrict__ coarse,
                                                                       T* __restrict__ planes, OutGeom g,
                                                                       const ProbDesc* __restrict__ pd, int nprob,
                                                                       int p0, int zpb_arg) {
   constexpr int Mh = M / 2 + 1;
   constexpr int R1 = Split<M>::R1, R2 = Split<M>::R2;
-  constexpr int CB = OutBatch<T, M>::CB, XL = Batch<T, M>::XLYZ;
+  constexpr int CB = OutBatch<T, M, MULTI>::CB, XL = Batch<T, M>::XLYZ;
   constexpr int WPMAX = n + 2 * n + 1 + 2 * 4;  // Wa + 2b with d_alpha <= n, b <= 4
   // fp32: A rows padded to a stride of 11 (mod 32) elements, so the lines
   // of one wave step start on spread-out LDS banks (fp64: no room to pad)
@@ -388,7 +390,7 @@ __global__ void __launch_bounds__((OutBatch<T, M>::NT)) conv_out_kernel(const cp
   // none when h is a power of two)
   const T hsq = T(pd[find_problem(pd, nprob, p)].h2);
   const cplx<T>* zin = Zb + (int64_t(pc) * Wp + zi0) * Mh * M;   // the current plane
-  constexpr int LW = OutBatch<T, M>::LW, NW = OutBatch<T, M>::NT / 64;
+  constexpr int LW = OutBatch<T, M, MULTI>::LW, NW = OutBatch<T, M, MULTI>::NT / 64;
   const int wave = tid >> 6, lane = tid & 63;
   const int s1 = lane % R1, r1 = lane / R1, t2 = lane % R2, r2 = lane / R2;
   const bool act1 = lane < LW * R1, act2 = lane < LW * R2;

@@ -75,6 +75,7 @@ struct mlc_plan {
   double* D = nullptr;
   double* Am = nullptr;   // skeleton far-field table laid out for MFMA
   double* Tm = nullptr;   // coarse far-field table laid out for MFMA
+  double* gram_inv = nullptr;   // P >= 5: inverse Boole Gram matrix of the modes, K x K
   MfmaGeom mg_skel{}, mg_coarse{};
   // workspace offsets of the plan's own (batch-of-one) layout
   size_t o_mom = 0, o_cs = 0, o_pl = 0, o_F = 0, o_phiH = 0, o_phiB = 0;
@@ -255,7 +256,7 @@ static mlc_status derive(const mlc_problem* p, mlc_plan_info* o, std::string* wh
   if (I.Q != 4 && I.Q != 6) { *why = "Q must be 4 (L19) or 6 (L27)"; return MLC_ERR_UNSUPPORTED; }
   if (p->conv_precision != MLC_CONV_FP32 && p->conv_precision != MLC_CONV_FP64) { *why = "bad conv_precision"; return MLC_ERR_INVALID_ARG; }
   if (I.b < 1 || I.b > 4) { *why = "interpolation radius must be in [1, 4]"; return MLC_ERR_UNSUPPORTED; }
-  if (I.P > 4) { *why = "P > 4 is not built (the Boole Gram matrix is then not diagonal)"; return MLC_ERR_UNSUPPORTED; }
+  if (I.P > PMAX) { *why = "P above 9 is not built"; return MLC_ERR_UNSUPPORTED; }
   if (I.n > 32) { *why = "patch size above 32 is not built"; return MLC_ERR_UNSUPPORTED; }
   if (I.Z != 32 && I.Z != 64 && I.Z != 128) { *why = "DGF half-width must be 32, 64 or 128"; return MLC_ERR_UNSUPPORTED; }
   I.K = I.P * (I.P + 1) * (I.P + 2) / 6;
@@ -462,7 +463,9 @@ static void plan_destroy_buffers(mlc_plan* p) {
   hipFree(p->D);
   hipFree(p->Am);
   hipFree(p->Tm);
+  hipFree(p->gram_inv);
   p->conv_spec = nullptr; p->coarse_spec = nullptr; p->T = nullptr; p->D = nullptr; p->Am = nullptr; p->Tm = nullptr;
+  p->gram_inv = nullptr;
 }
 
 // spectrum of the periodised DGF on an M^3 torus -> real octant (fp64 work)
@@ -665,7 +668,8 @@ static bool same_class(const mlc_plan* a, const mlc_plan* b) {
 //   per problem: F^H, coarse torus (consecutive within equal M_coarse),
 //   phi^H, phi^B.
 struct Layout {
-  size_t o_desc = 0, o_ann = 0, o_flat = 0, o_mom = 0, o_mpart = 0, o_X = 0, o_Z = 0, o_cs = 0, o_pl = 0, o_dir = 0;
+  size_t o_desc = 0, o_ann = 0, o_flat = 0, o_mom = 0, o_mpart = 0, o_mraw = 0, o_X = 0, o_Z = 0, o_cs = 0, o_pl = 0,
+         o_dir = 0;
   size_t o_dsum = 0;   // per skeleton thread: the sum of the plane corrections
   std::vector<size_t> o_F, o_tor, o_phiH, o_phiB, o_cpad;
   std::vector<int> patch0;
@@ -703,7 +707,8 @@ static Layout layout_of(const std::vector<const mlc_plan_info*>& g) {
   // coarse right-hand side and skeleton descriptors
   L.o_flat = take((sizeof(CoarseRhsProb<double>) + sizeof(SkelProb<double>)) * np);
   L.o_mom = take(sizeof(double) * T * I.K);
-  L.o_mpart = take(sizeof(double) * T * S * PLANE_MOMENTS);
+  L.o_mpart = take(sizeof(double) * T * S * I.P * I.P);
+  L.o_mraw = take(I.P >= 5 ? sizeof(double) * T * I.K : 0);
   // the x-DFT spectra; once the last y/z pass has read them, the same bytes
   // hold the coarse Laplacians of the patches' coarse samples (at most as
   // many bytes, since alpha <= 3)
@@ -781,6 +786,52 @@ extern "C" mlc_status mlc_problem_workspace_bytes(const mlc_problem* prob, size_
   return MLC_OK;
 }
 
+// Inverse of the Boole Gram matrix of the modes (sec. 3 projection in the
+// discrete inner product of the composite Boole rule): G[r][s] =
+// prod_d g1(p_r,d, p_s,d), g1(a, b) = sum_j w_j qhat_a(t_j) qhat_b(t_j); Gauss-Jordan
+// elimination with partial pivoting (G is symmetric positive definite and
+// close to the identity).  Row-major K x K.
+static bool gram_inverse(int n, int P, const ModeList& m, std::vector<double>* out) {
+  std::vector<double> g1(size_t(P) * P, 0.0);
+  for (int a = 0; a < P; ++a)
+    for (int b = 0; b < P; ++b) {
+      double acc = 0.0;
+      for (int j = 0; j <= n; ++j) {
+        const double t = (j - 0.5 * n) / (0.5 * n);
+        acc += boole_w(j, n) * qhat(a, t) * qhat(b, t);
+      }
+      g1[size_t(a) * P + b] = acc;
+    }
+  const int K = m.K;
+  std::vector<double> A(size_t(K) * 2 * K, 0.0);   // [G | I]
+  for (int r = 0; r < K; ++r) {
+    for (int c = 0; c < K; ++c)
+      A[size_t(r) * 2 * K + c] = g1[size_t(m.p[r][0]) * P + m.p[c][0]] * g1[size_t(m.p[r][1]) * P + m.p[c][1]] *
+                                 g1[size_t(m.p[r][2]) * P + m.p[c][2]];
+    A[size_t(r) * 2 * K + K + r] = 1.0;
+  }
+  for (int c = 0; c < K; ++c) {
+    int piv = c;
+    for (int r = c + 1; r < K; ++r)
+      if (std::fabs(A[size_t(r) * 2 * K + c]) > std::fabs(A[size_t(piv) * 2 * K + c])) piv = r;
+    if (!(std::fabs(A[size_t(piv) * 2 * K + c]) > 0.0)) return false;
+    if (piv != c)
+      for (int j = 0; j < 2 * K; ++j) std::swap(A[size_t(c) * 2 * K + j], A[size_t(piv) * 2 * K + j]);
+    const double d = A[size_t(c) * 2 * K + c];
+    for (int j = 0; j < 2 * K; ++j) A[size_t(c) * 2 * K + j] /= d;
+    for (int r = 0; r < K; ++r) {
+      if (r == c) continue;
+      const double f = A[size_t(r) * 2 * K + c];
+      if (f == 0.0) continue;
+      for (int j = 0; j < 2 * K; ++j) A[size_t(r) * 2 * K + j] -= f * A[size_t(c) * 2 * K + j];
+    }
+  }
+  out->assign(size_t(K) * K, 0.0);
+  for (int r = 0; r < K; ++r)
+    for (int c = 0; c < K; ++c) (*out)[size_t(r) * K + c] = A[size_t(r) * 2 * K + K + c];
+  return true;
+}
+
 static std::pair<int, int> autotune_conv(mlc_context* ctx, const mlc_plan_info& I, const double* G1);
 
 extern "C" mlc_status mlc_plan_create(mlc_context* ctx, const mlc_problem* prob, mlc_plan** out) {
@@ -853,6 +904,20 @@ extern "C" mlc_status mlc_plan_create(mlc_context* ctx, const mlc_problem* prob,
   if (P->Kann > 0) {
     s = build_tables(P, G1);
     if (s != MLC_OK) { plan_destroy_buffers(P); delete P; return s; }
+  }
+  if (I.P >= 5) {
+    std::vector<double> gi;
+    if (!gram_inverse(I.n, I.P, P->modes, &gi)) {
+      plan_destroy_buffers(P);
+      delete P;
+      return fail(ctx, MLC_ERR_UNSUPPORTED, "singular Boole Gram matrix of the Legendre modes");
+    }
+    if (!plan_alloc(P, &P->gram_inv, sizeof(double) * gi.size()) ||
+        hipMemcpy(P->gram_inv, gi.data(), sizeof(double) * gi.size(), hipMemcpyHostToDevice) != hipSuccess) {
+      plan_destroy_buffers(P);
+      delete P;
+      return fail(ctx, MLC_ERR_OUT_OF_MEMORY, "Gram matrix upload failed");
+    }
   }
   // workspace layout (a batch of one)
   {
@@ -1048,7 +1113,7 @@ static void launch_conv(const Group& G, hipStream_t s, int phase, const std::fun
     TimedScope ts(P, s, "conv_xdft");
     for (int p0 = 0; p0 < L.total; p0 += kMaxGridY)
       hipLaunchKernelGGL((conv_xdft_kernel<T, M>), dim3(P->S, std::min(kMaxGridY, L.total - p0)), dim3(256), 0, s,
-                         G.desc, np, I.n, X, reinterpret_cast<double*>(G.ws + L.o_mpart), p0);
+                         G.desc, np, I.n, I.P, X, reinterpret_cast<double*>(G.ws + L.o_mpart), p0);
   }
   if (phase == 0) return;
   OutGeom g{I.n, I.e, I.d_alpha, I.b, I.Wa, P->Wp, I.Wc, P->P0, I.nplanes_a};
@@ -1068,10 +1133,10 @@ static void launch_conv(const Group& G, hipStream_t s, int phase, const std::fun
       constexpr int yspl = OutBatch<T, M>::YSPL;
       const dim3 grid((P->Wp + zpb - 1) / zpb * yspl, cnt);
       if (zpb == 1)
-        hipLaunchKernelGGL((conv_out_kernel<T, n, M, false>), grid, dim3(OutBatch<T, M>::NT), 0, s, Zb, cs, pl, g,
+        hipLaunchKernelGGL((conv_out_kernel<T, n, M, false>), grid, dim3(OutBatch<T, M, false>::NT), 0, s, Zb, cs, pl, g,
                            G.desc, np, p0, 1);
       else
-        hipLaunchKernelGGL((conv_out_kernel<T, n, M, true>), grid, dim3(OutBatch<T, M>::NT), 0, s, Zb, cs, pl, g,
+        hipLaunchKernelGGL((conv_out_kernel<T, n, M, true>), grid, dim3(OutBatch<T, M, true>::NT), 0, s, Zb, cs, pl, g,
                            G.desc, np, p0, zpb);
     }
   }
@@ -1336,6 +1401,26 @@ static mlc_context::Side* side_of(mlc_context* ctx, hipStream_t s) {
 //   side: (after fork 1) far-field sums | (after fork 2) coarse rhs and solve
 // Every launch of one call has ended before the caller stream passes the
 // join, so consecutive calls on s may reuse the workspace.
+// The Legendre moments of every patch of a group from the per-plane sums of
+// the x-DFT pass: divided by the diagonal Boole Gram matrix (P <= 4), or
+// raw and then multiplied by the plan's inverse Gram matrix (P >= 5).
+static void launch_moments(const Group& G, hipStream_t s) {
+  const mlc_plan* P0 = G.plans[0];
+  const mlc_plan_info& I0 = P0->info;
+  const int np = int(G.plans.size());
+  TimedScope ts(P0, s, "moments");
+  const int64_t work = int64_t(G.L.total) * I0.K;
+  const bool diag = I0.P <= 4;
+  double* mom = reinterpret_cast<double*>(G.ws + G.L.o_mom);
+  double* raw = reinterpret_cast<double*>(G.ws + G.L.o_mraw);
+  hipLaunchKernelGGL(moments_finish_kernel, dim3(unsigned((work + 255) / 256)), dim3(256), 0, s, G.desc, np, I0.n,
+                     I0.P, P0->modes, reinterpret_cast<const double*>(G.ws + G.L.o_mpart), diag ? mom : raw,
+                     G.L.total, diag ? 1 : 0);
+  if (!diag)
+    hipLaunchKernelGGL(moments_gram_kernel, dim3(unsigned((work + 255) / 256)), dim3(256), 0, s, raw, P0->gram_inv,
+                       I0.K, mom, G.L.total);
+}
+
 // With one_stream set, every stage runs on s in the same order (no side
 // stream, no events): the same kernels on the same data, so the same result.
 static mlc_status enqueue_group(const Group& G, hipStream_t s, bool one_stream = false) {
@@ -1347,13 +1432,7 @@ static mlc_status enqueue_group(const Group& G, hipStream_t s, bool one_stream =
     upload_descs(G, s);
     if (!(f32 ? dispatch_conv<float>(G, s, 0) : dispatch_conv<double>(G, s, 0)))
       return fail(P0->ctx, MLC_ERR_UNSUPPORTED, "local FFT size not built");
-    {
-      TimedScope ts(P0, s, "moments");
-      const int64_t work = int64_t(G.L.total) * I0.K;
-      hipLaunchKernelGGL(moments_finish_kernel, dim3(unsigned((work + 255) / 256)), dim3(256), 0, s, G.desc, np,
-                         I0.n, P0->modes, reinterpret_cast<const double*>(G.ws + G.L.o_mpart),
-                         reinterpret_cast<double*>(G.ws + G.L.o_mom), G.L.total);
-    }
+    launch_moments(G, s);
     if (f32) {
       dispatch_conv<float>(G, s, 1);
       for (Stage st : {FAR, COARSE, PLANES, FINISH}) launch_rest<float>(G, s, st);
@@ -1373,13 +1452,7 @@ static mlc_status enqueue_group(const Group& G, hipStream_t s, bool one_stream =
   // moment sums, finished here before the far-field sums read the moments
   const bool ok = fp32 ? dispatch_conv<float>(G, s, 0) : dispatch_conv<double>(G, s, 0);
   if (!ok) return fail(P0->ctx, MLC_ERR_UNSUPPORTED, "local FFT size not built");
-  {
-    TimedScope ts(P0, s, "moments");
-    const int64_t work = int64_t(G.L.total) * I0.K;
-    hipLaunchKernelGGL(moments_finish_kernel, dim3(unsigned((work + 255) / 256)), dim3(256), 0, s, G.desc, np, I0.n,
-                       P0->modes, reinterpret_cast<const double*>(G.ws + G.L.o_mpart),
-                       reinterpret_cast<double*>(G.ws + G.L.o_mom), G.L.total);
-  }
+  launch_moments(G, s);
   // fork 1 after the first chunk's y/z pass: the far-field sums then share
   // the chip with the output pass (one block per CU, LDS and registers to
   // spare) rather than with the y/z pass (whose blocks fill the LDS)

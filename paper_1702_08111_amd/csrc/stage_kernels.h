@@ -9,34 +9,54 @@
 namespace mlc {
 
 // ------------------------------------------------------------ moments ----
-// c_{i,p} = R^{3/2} sum_j W_j f[j] qhat_p(t_j) / mu_p over the (n+1)^3 nodes of
-// the closed patch, W = tensor composite Boole weights on [-1, 1], and mu_p
-// the diagonal of the Boole Gram matrix (sec. 3 projection; sec. 4.1 step 1
-// quadrature).  For P <= 4 the Gram matrix is diagonal.  The sums over the two
-// fastest axes are taken per z-plane by the x-DFT kernel of the local
-// convolutions (which loads every plane anyway): part[p][j0][4 a1 + a2] =
+// c_{i,p}: the raw moments m_p = R^{3/2} sum_j W_j f[j] qhat_p(t_j) over the
+// (n+1)^3 nodes of the closed patch, W = tensor composite Boole weights on
+// [-1, 1] (sec. 4.1 step 1 quadrature), projected with the Boole Gram matrix
+// of the modes, c = Gram^{-1} m (sec. 3 projection).  For P <= 4 the Gram
+// matrix is diagonal, mu_p = prod_d sum_j w_j qhat_{p_d}(t_j)^2, and the
+// kernel divides (diag = 1); for P >= 5 it writes m and
+// moments_gram_kernel applies the inverse.  The sums over the two fastest
+// axes are taken per z-plane by the x-DFT kernel of the local convolutions
+// (which loads every plane anyway): part[p][j0][a1 P + a2] =
 // sum_{j1,j2} w_j1 qhat_a1 w_j2 qhat_a2 f.  This kernel contracts j0, one
 // thread per (patch, mode).
 __global__ void __launch_bounds__(256) moments_finish_kernel(const ProbDesc* __restrict__ pd, int nprob, int n,
-                                                             ModeList modes, const double* __restrict__ part,
-                                                             double* __restrict__ out, int total) {
+                                                             int P, ModeList modes, const double* __restrict__ part,
+                                                             double* __restrict__ out, int total, int diag) {
   const int64_t idx = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
   if (idx >= int64_t(total) * modes.K) return;
   const int p = int(idx / modes.K), k = int(idx % modes.K);
   const ProbDesc& D = pd[find_problem(pd, nprob, p)];
   const int a0 = modes.p[k][0], a1 = modes.p[k][1], a2 = modes.p[k][2];
-  const int S = n + 1;
-  const double* pp = part + int64_t(p) * S * PLANE_MOMENTS + 4 * a1 + a2;
+  const int S = n + 1, PP = P * P;
+  const double* pp = part + int64_t(p) * S * PP + P * a1 + a2;
   double s = 0.0, mu0 = 0.0, mu1 = 0.0, mu2 = 0.0;
   for (int j = 0; j < S; ++j) {
     const double t = (j - 0.5 * n) / (0.5 * n), w = boole_w(j, n);
     const double q0 = qhat(a0, t), q1 = qhat(a1, t), q2 = qhat(a2, t);
-    s += w * q0 * pp[j * PLANE_MOMENTS];
+    s += w * q0 * pp[j * PP];
     mu0 += w * q0 * q0;
     mu1 += w * q1 * q1;
     mu2 += w * q2 * q2;
   }
-  out[idx] = D.R15 * s / (mu0 * mu1 * mu2);
+  out[idx] = diag ? D.R15 * s / (mu0 * mu1 * mu2) : D.R15 * s;
+}
+
+// c = Gram^{-1} m per patch (P >= 5, where the Boole Gram matrix of the modes
+// is no longer diagonal): one thread per (patch, mode), the row of the
+// inverse (K x K, row-major, built on the host) against the patch's raw
+// moments, summed in mode order.
+__global__ void __launch_bounds__(256) moments_gram_kernel(const double* __restrict__ raw,
+                                                           const double* __restrict__ ginv, int K,
+                                                           double* __restrict__ out, int total) {
+  const int64_t idx = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (idx >= int64_t(total) * K) return;
+  const int p = int(idx / K), k = int(idx % K);
+  const double* m = raw + int64_t(p) * K;
+  const double* g = ginv + int64_t(k) * K;
+  double s = 0.0;
+  for (int q = 0; q < K; ++q) s += g[q] * m[q];
+  out[idx] = s;
 }
 
 // ------------------------------------------------------- coarse rhs ----

@@ -48,7 +48,7 @@ def test_derived_sizes(name, N, n, Q, fft, expect):
     (dict(N=36, n=6), mlc.MLC_ERR_INVALID_ARG),          # n % 4
     (dict(N=32, n=8, alpha=3, beta=2), mlc.MLC_ERR_INVALID_ARG),
     (dict(N=32, n=8, Q=5), mlc.MLC_ERR_UNSUPPORTED),
-    (dict(N=32, n=8, P=5), mlc.MLC_ERR_UNSUPPORTED),
+    (dict(N=32, n=8, P=10), mlc.MLC_ERR_UNSUPPORTED),
     (dict(N=32, n=8, alpha=1.5, beta=1.5), mlc.MLC_ERR_UNSUPPORTED),   # margin 2 not a multiple of 4
     (dict(N=32, n=8, fft_size=40), mlc.MLC_ERR_INVALID_ARG),           # below 2(n+e)+1
     (dict(N=32, n=8, Z=100), mlc.MLC_ERR_UNSUPPORTED),

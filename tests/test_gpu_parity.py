@@ -57,6 +57,14 @@ def _case(name):
         # the benchmark's patch work (32^3-cell patches, L27, M = 160, far-field
         # torus 250, Z = 128) on 2^3 patches
         "n32_64": (64, 32, 3.0, 6.0, 4, 6, 160, 128, mi.bumps(2, 17, radius=(0.1, 0.2))),
+        # P >= 5: 35, 56 and 165 Legendre modes, projected with the full Boole
+        # Gram matrix
+        "p5_32": (32, 8, 3.0, 6.0, 5, 4, 0, 64, mi.bumps(2, 18, radius=(0.1, 0.25))),
+        "p6_32_q6": (32, 8, 3.0, 6.0, 6, 6, 0, 64, mi.bumps(2, 19, radius=(0.1, 0.25))),
+        "p9_32": (32, 8, 3.0, 6.0, 9, 4, 0, 64, mi.bumps(2, 20, radius=(0.1, 0.25))),
+        # the parameters of the paper's Table 7 (L27, alpha 1.75, beta 3.25,
+        # P = 9) with 32^3-cell patches
+        "t7_64": (64, 32, 1.75, 3.25, 9, 6, 0, 128, mi.bumps(2, 21, radius=(0.1, 0.2))),
     }
     return cases[name]
 
@@ -92,7 +100,7 @@ def _check_all(name, conv):
 
 
 @pytest.mark.parametrize("name", ["plain32", "plain32_q6", "mlc0_32", "p1_32", "ragged48", "single16", "p2_32",
-                                  "p3_32", "b1_32", "b4_32", "n32_64"])
+                                  "p3_32", "b1_32", "b4_32", "n32_64", "p5_32", "p6_32_q6", "p9_32", "t7_64"])
 def test_fp64_parity(name):
     errs = _check_all(name, "fp64")
     for k, v in errs.items():
@@ -100,7 +108,7 @@ def test_fp64_parity(name):
 
 
 @pytest.mark.parametrize("name", ["plain32", "plain32_q6", "mlc0_32", "p1_32", "ragged48", "single16", "b1_32",
-                                  "b4_32", "n32_64"])
+                                  "b4_32", "n32_64", "p5_32", "p9_32"])
 def test_fp32_parity(name):
     errs = _check_all(name, "fp32")
     assert errs["phi"] < TOL32, errs

@@ -70,13 +70,13 @@ def test_boole_exactness(n):
 def test_orthonormal_basis_by_gauss():
     """Qhat_a are orthonormal on [-1, 1] (Gauss-Legendre, independent of Boole)."""
     x, wg = np.polynomial.legendre.leggauss(12)
-    for a in range(6):
-        for c in range(6):
+    for a in range(9):
+        for c in range(9):
             v = np.sum(wg * leg.qhat(a, x) * leg.qhat(c, x))
             assert abs(v - (a == c)) < 1e-14
 
 
-@pytest.mark.parametrize("P", [1, 2, 4])
+@pytest.mark.parametrize("P", [1, 2, 4, 5, 6, 9])
 def test_projection_reproduces_polynomials(P):
     """P(pi) = pi for polynomials of total degree < P (sec. 3.2 error
     analysis uses this); with the Boole Gram correction this holds exactly."""
@@ -87,6 +87,23 @@ def test_projection_reproduces_polynomials(P):
     c2 = leg.moments(poly, n, P, R)
     assert np.abs(c2 - c).max() < 1e-12
     assert np.abs(leg.projected_charge(c2, n, P, R) - poly).max() < 1e-12 * np.abs(poly).max()
+
+
+@pytest.mark.parametrize("P", [5, 6, 9])
+def test_gram_not_diagonal_above_p4(P):
+    """From P = 5 on the Boole rule no longer integrates every product of two
+    modes exactly: same-parity pairs of total degree >= 6 couple, so the
+    projection needs the full Gram matrix (the moments are not the raw Boole
+    moments divided by a diagonal); the coupling vanishes as the patch is
+    refined."""
+    offs = []
+    for n in (8, 16, 32):
+        G = leg.gram(n, P)
+        off = np.abs(G - np.diag(np.diag(G))).max()
+        offs.append(off)
+        assert np.abs(G - G.T).max() < 1e-14
+    assert offs[0] > 1e-6
+    assert offs[0] > offs[1] > offs[2]
 
 
 def test_gram_diagonal_for_p4():
