@@ -183,6 +183,9 @@ __global__ void __launch_bounds__(256) conv_yz_kernel(const cplx<T>* __restrict_
   __shared__ cplx<T> tw[M];
   __shared__ short zmap[M];
   // p: patch; pc: its slot in the chunk-local Zb (patches p0 .. p0 + gridDim.y - 1)
+  // (a grid padded to 88 wavenumbers, so that each XCD sees only kx = x
+  // (mod 8) and holds fewer spectrum slices in its L2, measured slower:
+  // 2.20 -> 2.38 ms at 256^3)
   const int kx = blockIdx.x, pc = blockIdx.y, p = p0 + pc;
   const int tid = threadIdx.x;
   fill_twiddles(tw, M);
