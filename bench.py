@@ -39,6 +39,7 @@ def parse():
     ap.add_argument("--serve-requests", type=int, default=1000,
                     help="measured requests of the serving loop after 50 warm-ups (0: skip)")
     ap.add_argument("--serve-load", type=float, default=0.7, help="arrival rate / saturation rate")
+    ap.add_argument("--no-sweep", action="store_true", help="skip the (alpha, beta, P, Q) sweep")
     ap.add_argument("--osc-steps", type=int, default=5,
                     help="timed steps of the oscillatory 384^3 workload per path (0: skip)")
     return ap.parse_args()
@@ -257,6 +258,51 @@ def oscillatory_bench(ctx, steps, dev, N=384, n=32, Q=6):
     return out
 
 
+SWEEP = [
+    # (alpha, beta, P, Q, b): MLC-0 (beta = alpha) and MLC, the 19- and 27-point operators
+    (1.5, 1.5, 4, 4, 2), (3.0, 3.0, 4, 4, 2), (1.5, 3.0, 4, 4, 2), (1.5, 6.0, 4, 4, 2), (3.0, 6.0, 4, 4, 2),
+    (2.0, 2.0, 4, 6, 3), (1.5, 2.0, 4, 6, 2), (1.75, 3.25, 4, 6, 3), (1.75, 3.25, 9, 6, 3), (3.0, 6.0, 4, 6, 3),
+]
+
+
+def sweep_bench(ctx, dev, steps=3, N=256, n=32):
+    """Cost and accuracy over (alpha, beta, P, Q) for the smooth charge of
+    sec. 7.1 at 256^3 (32^3-cell patches): per setting the float64 and
+    float32 solve times and errors against the closed form, and for one
+    setting the same charge given analytically (Gauss-integrated moments)."""
+    import torch
+    from paper_1702_08111_amd import mlc as gm
+    f = torch.from_numpy(mi.smooth_charge(N)).to(dev)
+    exact = mi.smooth_potential(N)
+    scale = np.abs(exact).max()
+    rows = []
+    for a, bt, P, Q, b in SWEEP:
+        row = {"alpha": a, "beta": bt, "P": P, "Q": Q, "b": b, "mlc0": a == bt}
+        for conv in ("fp64", "fp32"):
+            plan = ctx.plan(gm.problem(N, n, a, bt, P, Q, b=b, conv=conv))
+            ws = torch.empty(plan.workspace_bytes, dtype=torch.uint8, device=dev)
+            phi = torch.empty_like(f)
+            plan.solve(f, phi, ws)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(steps):
+                plan.solve(f, phi, ws)
+            torch.cuda.synchronize()
+            row[conv + "_ms"] = round((time.perf_counter() - t0) * 1e3 / steps, 3)
+            row[conv + "_err"] = float(np.abs(phi.cpu().numpy() - exact).max() / scale)
+            if conv == "fp64" and (a, bt, P, Q) == (1.75, 3.25, 4, 6):
+                fa = torch.empty_like(f)
+                plan.solve_analytic([(t[0], t[1], t[2], t[3], t[4]) for t in mi.smooth_terms()], 4, fa, phi, ws)
+                torch.cuda.synchronize()
+                row["fp64_gauss_moments_err"] = float(np.abs(phi.cpu().numpy() - exact).max() / scale)
+            del ws
+            plan.close()
+        rows.append(row)
+    torch.cuda.empty_cache()
+    return {"config": f"smooth charge of sec. 7.1, {N}^3, {n}^3-cell patches; error = max|phi - closed form| / "
+                      "max|closed form|", "rows": rows}
+
+
 def serving_bench(ctx, count, load, dev, warm=50, sat_requests=120, pool=4, ring=32, verify_per_size=8):
     """The serving loop: requests with N ~ U{64,128,192,256}, n ~ U{16,32},
     Q ~ U{4,6}, 1-4 seeded bumps, float32 convolutions.  First the
@@ -470,6 +516,10 @@ def main():
     if args.batch_steps > 0:
         progress("uneven 64-problem batch")
     batch = batch_bench(ctx, args.batch_steps, dev) if args.batch_steps > 0 else None
+    sweep = None
+    if not args.no_sweep:
+        progress("(alpha, beta, P, Q) sweep, 256^3 smooth charge")
+        sweep = sweep_bench(ctx, dev)
     osc = None
     if args.osc_steps > 0:
         progress("oscillatory workload, 384^3")
@@ -521,6 +571,7 @@ def main():
         "cpu_baseline": cpu,
         "batch": batch,
         "oscillatory": osc,
+        "sweep": sweep,
         "serving": serving,
     }
     print(json.dumps(line), flush=True)

@@ -168,6 +168,38 @@ mlc_status mlc_solve(mlc_plan* plan, const double* f, double* phi,
 #define MLC_STATIC_SCRATCH_BYTES ((size_t)512 << 20)
 mlc_status mlc_solve_static(mlc_plan* plan, const double* f, double* phi, void* stream);
 
+/* Charges given analytically (sec. 4.1 step 1: the Legendre coefficients
+ * are then computed by Gauss integration instead of Boole's rule): a sum of
+ * radial terms f(x) = weight * profile(|x - centre| / radius), each zero for
+ * |x - centre| >= radius, in the physical coordinates of the grid (node g at
+ * g h).  Profiles, r = |x - centre| / radius < 1:
+ *   MLC_PROFILE_BUMP         (1 - r^2)^4
+ *   MLC_PROFILE_SMOOTH       (r - r^2)^4            (sec. 7.1's charge)
+ *   MLC_PROFILE_OSCILLATORY  (r - r^2)^2 sin^2(param r / 2)   (sec. 7.2's, param = gamma) */
+typedef enum { MLC_PROFILE_BUMP = 0, MLC_PROFILE_SMOOTH = 1, MLC_PROFILE_OSCILLATORY = 2 } mlc_profile;
+typedef struct {
+  double centre[3];
+  double radius;          /* > 0 */
+  double weight;
+  double param;           /* oscillatory: gamma; ignored otherwise */
+  int32_t profile;        /* mlc_profile */
+} mlc_radial_charge;
+#define MLC_MAX_RADIAL_TERMS 16
+
+/* mlc_solve for a charge given as nterms (1..MLC_MAX_RADIAL_TERMS) radial
+ * terms (host array, read during the call).  The library samples the charge
+ * on the (N+1)^3 nodes into f (device, caller-owned, fully overwritten; it
+ * must vanish on the outer boundary nodes: MLC_ERR_INVALID_ARG if a term's
+ * support reaches them) and solves with it, except that each patch's Legendre
+ * coefficients are the composite Gauss-Legendre integrals
+ *   c_p = R^{3/2} sum_k W_k f(x_k) qhat_p(t_k)
+ * over gauss_points (1..4) points per cell per axis of the patch's n cells
+ * (the inner products <Q^p, f> of the L2 projection, sec. 3; for products of
+ * modes up to degree 2 gauss_points - 1 per cell the rule is exact, so no
+ * Gram correction is applied).  Workspace and stream as for mlc_solve. */
+mlc_status mlc_solve_analytic(mlc_plan* plan, int32_t nterms, const mlc_radial_charge* terms, int32_t gauss_points,
+                              double* f, double* phi, void* workspace, size_t ws_bytes, void* stream);
+
 /* Several independent problems in one pass: the per-patch stages of all
  * problems run in shared launches (their plans must share n, alpha, b, Q,
  * the torus M and the conv precision); coarse solves run per problem.

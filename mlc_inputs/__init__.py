@@ -167,6 +167,51 @@ def oscillatory_potential(N):
     return phi
 
 
+# Charges as sums of radial terms (centre, radius, weight, param, profile):
+# f(x) = weight * profile(|x - centre| / radius) inside the ball, 0 outside.
+PROFILE_BUMP, PROFILE_SMOOTH, PROFILE_OSCILLATORY = 0, 1, 2
+
+
+def _profile(kind, r, param):
+    if kind == PROFILE_BUMP:
+        v = (1.0 - r * r) ** 4
+    elif kind == PROFILE_SMOOTH:
+        v = (r - r * r) ** 4
+    else:
+        v = (r - r * r) ** 2 * np.sin(0.5 * param * r) ** 2
+    return np.where(r < 1.0, v, 0.0)
+
+
+def radial_charge_at(x0, x1, x2, terms):
+    """f at points with coordinates x0, x1, x2 (arrays that broadcast)."""
+    f = 0.0
+    for c, R, w, param, kind in terms:
+        r = np.sqrt((x0 - c[0]) ** 2 + (x1 - c[1]) ** 2 + (x2 - c[2]) ** 2) / R
+        f = f + w * _profile(kind, r, param)
+    return f
+
+
+def radial_charge_nodes(N, terms):
+    """f on the (N+1)^3 nodes g / N of [0, 1]^3."""
+    ax = np.arange(N + 1) / N
+    return np.asarray(radial_charge_at(ax[:, None, None], ax[None, :, None], ax[None, None, :], terms),
+                      dtype=np.float64) * np.ones((N + 1,) * 3)
+
+
+def bump_terms(bumps):
+    return [(b.centre, b.radius, b.weight, 0.0, PROFILE_BUMP) for b in bumps]
+
+
+def smooth_terms():
+    """The smooth charge of sec. 7.1 as one radial term."""
+    return [((0.5, 0.5, 0.5), SMOOTH_RO, 1.0, 0.0, PROFILE_SMOOTH)]
+
+
+def oscillatory_terms():
+    """The three oscillatory charges of sec. 7.2 as radial terms."""
+    return [(c, OSC_RO, OSC_RO ** -3, OSC_GAMMA, PROFILE_OSCILLATORY) for c in OSC_CENTRES]
+
+
 def one_bump():
     return [Bump((0.5, 0.5, 0.5), 0.35, 1.0)]
 

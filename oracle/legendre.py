@@ -95,3 +95,37 @@ def projected_charge(c, n, P, R):
     """sum_p c_p Q^p(x_j) on the patch nodes (no chi weighting)."""
     B = basis_on_patch(n, P)
     return R ** -1.5 * np.einsum("k,kabc->abc", c, B)
+
+
+def gauss_cell_rule(g):
+    """Composite Gauss-Legendre rule on [-1, 1] split into n cells of width
+    2/n, g points per cell: returns a function n -> (t, w)."""
+    xi, om = np.polynomial.legendre.leggauss(g)
+
+    def rule(n):
+        cells = np.arange(n)[:, None]
+        t = (cells + 0.5 * (1.0 + xi[None, :])) * (2.0 / n) - 1.0
+        w = np.broadcast_to(om[None, :] / n, t.shape)
+        return t.reshape(-1), w.reshape(-1)
+    return rule
+
+
+def moments_gauss(fun, corner, n, h, P, R, g):
+    """Legendre coefficients of an analytically given charge on the patch
+    corner + [0, n h]^3 by composite Gauss integration (sec. 4.1 step 1, for
+    f specified analytically): c_p = R^{3/2} sum_k W_k f(x_k) Qhat_p(t_k), the
+    Gauss value of the inner product <Q^p, f> of the orthogonal projection
+    (sec. 3); g points per cell and axis.  fun(x0, x1, x2) takes arrays that
+    broadcast."""
+    t, w = gauss_cell_rule(g)(n)
+    x = [corner[d] + (t + 1.0) * (n * h / 2.0) for d in range(3)]
+    F = fun(x[0][:, None, None], x[1][None, :, None], x[2][None, None, :])
+    F = np.asarray(F, dtype=np.float64) * np.ones((len(t),) * 3)
+    W = w[:, None, None] * w[None, :, None] * w[None, None, :]
+    vals = [qhat(a, t) for a in range(P)]
+    out = []
+    for p in mode_list(P):
+        B = vals[p[0]][:, None, None] * vals[p[1]][None, :, None] * vals[p[2]][None, None, :]
+        out.append(R ** 1.5 * np.sum(W * B * F))
+    return np.array(out)
+

@@ -229,7 +229,8 @@ def plan_tables(G1, prm, conv_mode="fft"):
     return dict(Phi=Phi, T=T, Phi_lo=Phi_lo, T_lo=T_lo, planes=_annulus_plane_tables(Phi, Phi_lo, prm))
 
 
-def mlc_solve(f, prm, G1=None, conv_mode="fft", bc_mode="by_patch", keep=False, on_local=None, tables=None):
+def mlc_solve(f, prm, G1=None, conv_mode="fft", bc_mode="by_patch", keep=False, on_local=None, tables=None,
+              moments_fn=None):
     """Two-level MLC (sec. 4.1).  Returns phi on all (N+1)^3 nodes and, if
     keep, a dict of intermediates: moments, FH, phiH, phiB (full grid,
     meaningful on skeleton nodes), and the per-patch local fields (only for
@@ -237,7 +238,10 @@ def mlc_solve(f, prm, G1=None, conv_mode="fft", bc_mode="by_patch", keep=False, 
     on_local(patch_number, i, phi_i) with each local field on E_i as soon as
     it is computed (read only; it lets a caller inspect every patch's field
     without keeping them all).  tables, if given, is plan_tables(G1, prm)
-    built beforehand (the same values the solve would build)."""
+    built beforehand (the same values the solve would build).  moments_fn,
+    if given, returns the Legendre coefficients of patch i (moments_fn(i)),
+    e.g. legendre.moments_gauss for a charge given analytically (sec. 4.1
+    step 1); otherwise they come from the node values by Boole's rule."""
     from .dgf import dgf_cached
     prm.check()
     N, n, Q, b = prm.N, prm.n, prm.Q, prm.bb
@@ -270,7 +274,7 @@ def mlc_solve(f, prm, G1=None, conv_mode="fft", bc_mode="by_patch", keep=False, 
         q = patch_charge(f, n, i)
         phi_i = local_field(G1, prm, q, conv_mode, cache)          # on [lo-e, lo+n+e]
         fpatch = f[lo[0]:lo[0] + n + 1, lo[1]:lo[1] + n + 1, lo[2]:lo[2] + n + 1]
-        c = leg.moments(fpatch, n, prm.P, R)
+        c = leg.moments(fpatch, n, prm.P, R) if moments_fn is None else moments_fn(i)
         moments[pi] = c
         if on_local is not None:
             on_local(pi, i, phi_i)

@@ -22,6 +22,7 @@
 #include "conv_kernels.h"
 #include "setup_kernels.h"
 #include "stage_kernels.h"
+#include "analytic_kernels.h"
 
 using namespace mlc;
 
@@ -1421,18 +1422,55 @@ static void launch_moments(const Group& G, hipStream_t s) {
                        I0.K, mom, G.L.total);
 }
 
+// A charge given analytically: sampled into f before the convolutions, and
+// the moments by Gauss integration instead of Boole's rule.
+struct AnalyticInput {
+  RadialCharge q;
+  GaussRule rule;
+  double* f;   // the caller's node array the samples go to
+};
+
+static void launch_analytic_fill(const Group& G, hipStream_t s, const AnalyticInput& an) {
+  const mlc_plan_info& I = G.plans[0]->info;
+  const int64_t nodes = cube(I.N + 1);
+  hipLaunchKernelGGL(analytic_fill_kernel, dim3(unsigned((nodes + 255) / 256)), dim3(256), 0, s, an.q, I.N, I.h, an.f);
+}
+
+static void launch_gauss_moments(const Group& G, hipStream_t s, const AnalyticInput& an) {
+  const mlc_plan* P0 = G.plans[0];
+  const mlc_plan_info& I0 = P0->info;
+  const int np = int(G.plans.size());
+  TimedScope ts(P0, s, "moments_gauss");
+  double* mom = reinterpret_cast<double*>(G.ws + G.L.o_mom);
+  for (int p0 = 0; p0 < G.L.total; p0 += kMaxGridY) {
+    const dim3 grid(unsigned(std::min(kMaxGridY, G.L.total - p0)));
+    switch (I0.P) {
+#define CASE(PP)                                                                                                  \
+  case PP:                                                                                                        \
+    hipLaunchKernelGGL(gauss_moments_kernel<PP>, grid, dim3(GAUSS_THREADS), 0, s, G.desc, np, I0.n, an.q, an.rule, \
+                       P0->modes, mom, p0);                                                                      \
+    break;
+      CASE(1) CASE(2) CASE(3) CASE(4) CASE(5) CASE(6) CASE(7) CASE(8) CASE(9)
+#undef CASE
+    }
+  }
+}
+
 // With one_stream set, every stage runs on s in the same order (no side
 // stream, no events): the same kernels on the same data, so the same result.
-static mlc_status enqueue_group(const Group& G, hipStream_t s, bool one_stream = false) {
+static mlc_status enqueue_group(const Group& G, hipStream_t s, bool one_stream = false,
+                                const AnalyticInput* an = nullptr) {
   const mlc_plan* P0 = G.plans[0];
   const mlc_plan_info& I0 = P0->info;
   const int np = int(G.plans.size());
   if (one_stream) {
     const bool f32 = I0.conv_precision == MLC_CONV_FP32;
     upload_descs(G, s);
+    if (an) launch_analytic_fill(G, s, *an);
     if (!(f32 ? dispatch_conv<float>(G, s, 0) : dispatch_conv<double>(G, s, 0)))
       return fail(P0->ctx, MLC_ERR_UNSUPPORTED, "local FFT size not built");
-    launch_moments(G, s);
+    if (an) launch_gauss_moments(G, s, *an);
+    else launch_moments(G, s);
     if (f32) {
       dispatch_conv<float>(G, s, 1);
       for (Stage st : {FAR, COARSE, PLANES, FINISH}) launch_rest<float>(G, s, st);
@@ -1448,11 +1486,13 @@ static mlc_status enqueue_group(const Group& G, hipStream_t s, bool one_stream =
   if (!sd) return fail(P0->ctx, MLC_ERR_DEVICE, "could not create the side stream");
   const bool fp32 = I0.conv_precision == MLC_CONV_FP32;
   upload_descs(G, s);
+  if (an) launch_analytic_fill(G, s, *an);
   // the x-DFT pass of the local convolutions also leaves the per-plane
   // moment sums, finished here before the far-field sums read the moments
   const bool ok = fp32 ? dispatch_conv<float>(G, s, 0) : dispatch_conv<double>(G, s, 0);
   if (!ok) return fail(P0->ctx, MLC_ERR_UNSUPPORTED, "local FFT size not built");
-  launch_moments(G, s);
+  if (an) launch_gauss_moments(G, s, *an);
+  else launch_moments(G, s);
   // fork 1 after the first chunk's y/z pass: the far-field sums then share
   // the chip with the output pass (one block per CU, LDS and registers to
   // spare) rather than with the y/z pass (whose blocks fill the LDS)
@@ -1545,6 +1585,71 @@ extern "C" mlc_status mlc_solve(mlc_plan* plan, const double* f, double* phi, vo
   G.ws = static_cast<char*>(workspace);
   G.desc = reinterpret_cast<ProbDesc*>(G.ws + G.L.o_desc);
   return enqueue_group(G, static_cast<hipStream_t>(stream));
+}
+
+// Gauss-Legendre nodes and weights on [-1, 1], gp = 1..4
+static GaussRule gauss_rule(int gp) {
+  GaussRule r{};
+  r.gp = gp;
+  switch (gp) {
+    case 1: r.xi[0] = 0.0; r.om[0] = 2.0; break;
+    case 2: r.xi[0] = -1.0 / std::sqrt(3.0); r.xi[1] = -r.xi[0]; r.om[0] = r.om[1] = 1.0; break;
+    case 3:
+      r.xi[0] = -std::sqrt(0.6); r.xi[1] = 0.0; r.xi[2] = std::sqrt(0.6);
+      r.om[0] = r.om[2] = 5.0 / 9.0; r.om[1] = 8.0 / 9.0;
+      break;
+    default: {
+      const double a = std::sqrt(3.0 / 7.0 - 2.0 / 7.0 * std::sqrt(1.2)), b = std::sqrt(3.0 / 7.0 + 2.0 / 7.0 * std::sqrt(1.2));
+      const double wa = (18.0 + std::sqrt(30.0)) / 36.0, wb = (18.0 - std::sqrt(30.0)) / 36.0;
+      r.xi[0] = -b; r.xi[1] = -a; r.xi[2] = a; r.xi[3] = b;
+      r.om[0] = wb; r.om[1] = wa; r.om[2] = wa; r.om[3] = wb;
+    }
+  }
+  return r;
+}
+
+extern "C" mlc_status mlc_solve_analytic(mlc_plan* plan, int32_t nterms, const mlc_radial_charge* terms,
+                                         int32_t gauss_points, double* f, double* phi, void* workspace,
+                                         size_t ws_bytes, void* stream) {
+  mlc_context* ctx = plan ? plan->ctx : nullptr;
+  if (!plan || !terms || !f || !phi || !workspace) return fail(ctx, MLC_ERR_INVALID_ARG, "null argument");
+  if (nterms < 1 || nterms > MLC_MAX_RADIAL_TERMS)
+    return fail(ctx, MLC_ERR_INVALID_ARG, "nterms must be in [1, MLC_MAX_RADIAL_TERMS]");
+  if (gauss_points < 1 || gauss_points > 4) return fail(ctx, MLC_ERR_INVALID_ARG, "gauss_points must be in [1, 4]");
+  if (ws_bytes < plan->ws_total) return fail(ctx, MLC_ERR_INVALID_ARG, "workspace too small");
+  if (reinterpret_cast<uintptr_t>(workspace) % 256)
+    return fail(ctx, MLC_ERR_INVALID_ARG, "workspace must be 256-byte aligned");
+  const mlc_plan_info& I = plan->info;
+  const double L = I.N * I.h;
+  AnalyticInput an{};
+  an.q.count = nterms;
+  for (int k = 0; k < nterms; ++k) {
+    const mlc_radial_charge& t = terms[k];
+    if (!(t.radius > 0.0) || !std::isfinite(t.radius) || !std::isfinite(t.weight) || !std::isfinite(t.param) ||
+        t.profile < MLC_PROFILE_BUMP || t.profile > MLC_PROFILE_OSCILLATORY)
+      return fail(ctx, MLC_ERR_INVALID_ARG, "radial term " + std::to_string(k) + " is malformed");
+    for (int d = 0; d < 3; ++d)
+      if (!(t.centre[d] - t.radius >= 0.0) || !(t.centre[d] + t.radius <= L))
+        return fail(ctx, MLC_ERR_INVALID_ARG,
+                    "radial term " + std::to_string(k) + " reaches the outer boundary (f must vanish there)");
+    RadialTerm& r = an.q.t[k];
+    for (int d = 0; d < 3; ++d) r.c[d] = t.centre[d];
+    r.R = t.radius;
+    r.w = t.weight;
+    r.param = t.param;
+    r.profile = t.profile;
+  }
+  an.rule = gauss_rule(gauss_points);
+  an.f = f;
+  HIP_TRY(ctx, hipSetDevice(ctx->device));
+  Group G;
+  G.plans = {plan};
+  G.f = {f};
+  G.phi = {phi};
+  G.L = layout_of(infos_of(G.plans));
+  G.ws = static_cast<char*>(workspace);
+  G.desc = reinterpret_cast<ProbDesc*>(G.ws + G.L.o_desc);
+  return enqueue_group(G, static_cast<hipStream_t>(stream), false, &an);
 }
 
 // mlc_solve on the device's static scratch instead of a caller workspace,

@@ -47,6 +47,17 @@ class mlc_problem(ctypes.Structure):
     ]
 
 
+MLC_PROFILE_BUMP = 0
+MLC_PROFILE_SMOOTH = 1
+MLC_PROFILE_OSCILLATORY = 2
+MLC_MAX_RADIAL_TERMS = 16
+
+
+class mlc_radial_charge(ctypes.Structure):
+    _fields_ = [("centre", ctypes.c_double * 3), ("radius", ctypes.c_double), ("weight", ctypes.c_double),
+                ("param", ctypes.c_double), ("profile", ctypes.c_int32)]
+
+
 class mlc_plan_info(ctypes.Structure):
     _fields_ = [(name, ctypes.c_int32) for name in (
         "N", "n", "P", "Q", "b", "K", "d_alpha", "d_beta", "e", "patches_per_axis", "npatch",
@@ -89,6 +100,8 @@ _SIGS = {
     "mlc_problem_workspace_bytes": (ctypes.c_int, [ctypes.POINTER(mlc_problem), ctypes.POINTER(ctypes.c_size_t)]),
     "mlc_solve": (ctypes.c_int, [_P, _P, _P, _P, ctypes.c_size_t, _P]),
     "mlc_solve_static": (ctypes.c_int, [_P, _P, _P, _P]),
+    "mlc_solve_analytic": (ctypes.c_int, [_P, ctypes.c_int32, ctypes.POINTER(mlc_radial_charge), ctypes.c_int32,
+                                          _P, _P, _P, ctypes.c_size_t, _P]),
     "mlc_batch_workspace_bytes": (ctypes.c_int, [ctypes.c_int32, ctypes.POINTER(_P), ctypes.POINTER(ctypes.c_size_t)]),
     "mlc_solve_batched": (ctypes.c_int, [ctypes.c_int32, ctypes.POINTER(_P), ctypes.POINTER(_P), ctypes.POINTER(_P),
                                          _P, ctypes.c_size_t, _P]),
@@ -227,6 +240,18 @@ class Plan:
         no device allocation); raises MLCError(MLC_ERR_UNSUPPORTED) when the
         plan's workspace exceeds it."""
         _check(lib().mlc_solve_static(self.handle, _ptr(f), _ptr(phi), _stream(stream)), self.ctx.handle)
+
+    def solve_analytic(self, terms, gauss_points, f, phi, workspace, stream=None):
+        """Enqueue one solve of a charge given as radial terms [(centre, radius,
+        weight, param, profile)]: the library samples it into f (device
+        array, overwritten) and takes the moments by Gauss integration."""
+        arr = (mlc_radial_charge * len(terms))()
+        for k, (c, R, w, prm, prof) in enumerate(terms):
+            arr[k].centre[:] = [float(v) for v in c]
+            arr[k].radius, arr[k].weight, arr[k].param, arr[k].profile = float(R), float(w), float(prm), int(prof)
+        nbytes = workspace.numel() * workspace.element_size()
+        _check(lib().mlc_solve_analytic(self.handle, len(terms), arr, gauss_points, _ptr(f), _ptr(phi),
+                                        _ptr(workspace), nbytes, _stream(stream)), self.ctx.handle)
 
     def set_timing(self, enable):
         _check(lib().mlc_plan_set_timing(self.handle, 1 if enable else 0), self.ctx.handle)
