@@ -230,7 +230,7 @@ def plan_tables(G1, prm, conv_mode="fft"):
 
 
 def mlc_solve(f, prm, G1=None, conv_mode="fft", bc_mode="by_patch", keep=False, on_local=None, tables=None,
-              moments_fn=None):
+              moments_fn=None, coarse_fn=None):
     """Two-level MLC (sec. 4.1).  Returns phi on all (N+1)^3 nodes and, if
     keep, a dict of intermediates: moments, FH, phiH, phiB (full grid,
     meaningful on skeleton nodes), and the per-patch local fields (only for
@@ -241,7 +241,10 @@ def mlc_solve(f, prm, G1=None, conv_mode="fft", bc_mode="by_patch", keep=False, 
     built beforehand (the same values the solve would build).  moments_fn,
     if given, returns the Legendre coefficients of patch i (moments_fn(i)),
     e.g. legendre.moments_gauss for a charge given analytically (sec. 4.1
-    step 1); otherwise they come from the node values by Boole's rule."""
+    step 1); otherwise they come from the node values by Boole's rule.
+    coarse_fn, if given, replaces the coarse convolution of step 2:
+    coarse_fn(FH, S_lo, O_lo, O_hi) returns phi^H on [O_lo, O_hi]^3 (the
+    multilevel method solves the coarse charge by MLC one level up, sec. 5)."""
     from .dgf import dgf_cached
     prm.check()
     N, n, Q, b = prm.N, prm.n, prm.Q, prm.bb
@@ -307,7 +310,10 @@ def mlc_solve(f, prm, G1=None, conv_mode="fft", bc_mode="by_patch", keep=False, 
                 _accumulate_annulus(accum, c, tabs, lo, prm)
 
     # ---- step 2: coarse solve phi^H = G^H * F^H on [O_lo, O_hi] ----
-    phiH = H ** 2 * conv.conv_hockney(G1, prm.Z, FH, np.full(3, O_lo - S_lo), np.full(3, O_hi - S_lo))
+    if coarse_fn is None:
+        phiH = H ** 2 * conv.conv_hockney(G1, prm.Z, FH, np.full(3, O_lo - S_lo), np.full(3, O_hi - S_lo))
+    else:
+        phiH = coarse_fn(FH, S_lo, O_lo, O_hi)
 
     # ---- step 3: boundary values on the skeleton ----
     if bc_mode == "literal":
@@ -474,3 +480,61 @@ def _boundary_literal(fields, moments, patches, Phi, Phi_lo, phiH, O_lo, prm):
                     val += W[k, l] * (phiH[tuple(c - O_lo)] - loc(NREF * c))
         out[tuple(g)] = val
     return out
+
+
+def level_box_margin(prm):
+    """Cells of the next coarser level by which its patch box extends past the
+    coarsened domain [0, N/Nref] on each side: whole patches, enough that the
+    coarse charge (supported on the coarsened Omega_beta regions, margin
+    d_beta/Nref) vanishes on the box's outer nodes and its grown region
+    (G(C(Omega_beta), b), the interpolation stencils) lies inside it -- the
+    proper nesting condition of sec. 5."""
+    need = prm.d_beta // NREF + prm.bb + 1
+    return -(-need // prm.n) * prm.n
+
+
+def mlc_solve_multilevel(f, prm, levels, G1=None):
+    """Multilevel MLC (sec. 5) with `levels` levels (2 = the two-level method):
+    the two-level steps at the finest level, with the coarse convolution
+    replaced by the same method applied one level up to the coarse charge F^H
+    (spacing Nref h, the same n, alpha, beta, P, Q, b), placed in a patch box
+    that extends level_box_margin(prm) cells past the coarsened domain; the
+    coarsest level is a single convolution.  Every level takes its boundary
+    values from the uncorrected discrete solution (phi-tilde) of the level
+    below it (sec. 5 eq. mlcmultilevel); the Mehrstellen correction is added
+    at the finest level.  Returns phi and, from the finest level down, the
+    per-level results (phi-tilde on the level's nodes, or phi^H of the final
+    convolution on its output box; the physical coordinate of the array's
+    first node; the level's spacing; the level's node charge f-tilde, None
+    for the final convolution)."""
+    from .dgf import dgf_cached
+    if G1 is None:
+        G1 = dgf_cached(prm.Q, prm.Z)
+    if levels < 2:
+        raise ValueError("levels must be >= 2")
+    trail = {}
+
+    def solve(fl, p, lv, depth, x0):
+        # lv: levels left (2 = this level's coarse solve is a convolution)
+        if lv == 2:
+            phi, out = mlc_solve(fl, p, G1, keep=True)
+            trail[depth + 1] = (out["phiH"], x0 + out["O_lo"] * p.H, p.H, None)
+        else:
+            m = level_box_margin(p)
+            N1 = p.N // NREF + 2 * m
+            p1 = Params(N=N1, n=p.n, alpha=p.alpha, beta=p.beta, P=p.P, Q=p.Q, b=p.b, h=NREF * p.hh, Z=p.Z)
+
+            def coarse(FH, S_lo, O_lo, O_hi):
+                f1 = np.zeros((N1 + 1,) * 3)
+                a = S_lo + m                                  # F^H's first node in the level box
+                f1[tuple(slice(a, a + FH.shape[d]) for d in range(3))] = FH
+                _, out1 = solve(f1, p1, lv - 1, depth + 1, x0 - m * p1.hh)
+                o, w = O_lo + m, O_hi - O_lo + 1
+                return out1["phitilde"][o:o + w, o:o + w, o:o + w].copy()
+
+            phi, out = mlc_solve(fl, p, G1, keep=True, coarse_fn=coarse)
+        trail[depth] = (out["phitilde"], x0, p.hh, fl)
+        return phi, out
+
+    phi, _ = solve(f, prm, levels, 0, 0.0)
+    return phi, [trail[k] for k in sorted(trail)]

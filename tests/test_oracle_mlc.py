@@ -6,6 +6,7 @@ import mlc_inputs as mi
 from oracle import convolution as conv
 from oracle import mlc
 from oracle.dgf import dgf_cached
+from oracle.stencils import apply_laplacian
 
 
 def _global_discrete(G1, Z, f, N):
@@ -220,3 +221,65 @@ def test_far_field_tables_vs_direct_sum_of_projected_charge(Q):
         lap = apply_laplacian(samp, Q, H)[0, 0, 0]
         tab = c @ T[(slice(None),) + tuple(cc - T_lo)]
         assert abs(lap - tab) < 1e-11 * np.abs(T).max() * np.abs(c).max(), (cc, lap, tab)
+
+
+def test_multilevel_two_levels_is_the_two_level_method():
+    """mlc_solve_multilevel with two levels is mlc_solve (sec. 5 with
+    l_max = 1 is the algorithm of sec. 4.1)."""
+    N, n = 32, 8
+    G1 = dgf_cached(4, 64)
+    prm = mlc.Params(N=N, n=n, alpha=3, beta=6, P=4, Q=4, Z=64)
+    f = mi.bump_charge(N, mi.one_bump())
+    phi, trail = mlc.mlc_solve_multilevel(f, prm, 2, G1)
+    assert np.array_equal(phi, mlc.mlc_solve(f, prm, G1))
+    assert len(trail) == 2 and trail[1][2] == prm.H
+
+
+def _three_vs_two(N, n, alpha, beta, Q, Z):
+    G1 = dgf_cached(Q, Z)
+    f = mi.smooth_charge(N)
+    prm = mlc.Params(N=N, n=n, alpha=alpha, beta=beta, P=4, Q=Q, Z=Z)
+    p2, o2 = mlc.mlc_solve(f, prm, G1, keep=True)
+    p3, trail = mlc.mlc_solve_multilevel(f, prm, 3, G1)
+    # the level-1 MLC solution against the exact coarse convolution phi^H it
+    # replaces, on phi^H's box
+    phiH, O_lo = o2["phiH"], o2["O_lo"]
+    m = mlc.level_box_margin(prm)
+    o, w = O_lo + m, phiH.shape[0]
+    d1 = np.abs(trail[1][0][o:o + w, o:o + w, o:o + w] - phiH).max()
+    return f, prm, p2, p3, trail, d1
+
+
+def test_multilevel_error_propagation_bound():
+    """Three levels (sec. 5): the only change from two levels is the coarse
+    solution the boundary values interpolate, so the fine-level difference is
+    bounded by the level-1 MLC's deviation from the convolution it replaces
+    (times the interpolation's and the discrete maximum principle's constants);
+    the level box satisfies the proper nesting condition; each level's
+    phi-tilde solves its own patch Dirichlet problems."""
+    f, prm, p2, p3, trail, d1 = _three_vs_two(64, 8, 3.0, 6.0, 6, 64)
+    assert d1 > 1e-12 * np.abs(p2).max()            # the level-1 solve is a real MLC, not exact
+    assert np.abs(p3 - p2).max() < 3.0 * d1
+    m, N1 = mlc.level_box_margin(prm), trail[1][0].shape[0] - 1
+    assert m % prm.n == 0 and N1 == prm.N // 4 + 2 * m
+    # F^H (supported on the coarsened Omega_beta regions) vanishes on the box's outer nodes
+    fl = trail[1][3]
+    assert np.all(fl[0] == 0) and np.all(fl[-1] == 0) and np.all(fl[:, 0] == 0) and np.all(fl[:, :, -1] == 0)
+    # level 1: Delta^{h1} phi-tilde = f-tilde at the interior nodes of its patches
+    t1, _, h1, _ = trail[1]
+    lap = apply_laplacian(t1, prm.Q, h1)
+    inner = ~mlc.skeleton_mask(N1, prm.n)[1:-1, 1:-1, 1:-1]
+    assert np.abs(lap[inner] - fl[1:-1, 1:-1, 1:-1][inner]).max() < 1e-9 * np.abs(fl).max()
+
+
+@pytest.mark.slow
+def test_multilevel_matches_two_level_when_the_coarse_level_resolves():
+    """At 128^3 (16^3-cell patches, L27, alpha 3, beta 6) the level-1 MLC is
+    accurate to 2e-6 of phi^H and three levels give the two-level error
+    against the closed form within 5 % (sec. 7.1: more levels leave the
+    error unchanged when every level is resolved)."""
+    f, prm, p2, p3, trail, d1 = _three_vs_two(128, 16, 3.0, 6.0, 6, 128)
+    ex = mi.smooth_potential(128)
+    e2 = np.abs(p2 - ex).max() / np.abs(ex).max()
+    e3 = np.abs(p3 - ex).max() / np.abs(ex).max()
+    assert abs(e3 / e2 - 1.0) < 0.05, (e2, e3)
