@@ -76,6 +76,12 @@ typedef struct {
                              patch-work class in the context; mlc_problem_info
                              reports the smallest size and the default count)       */
   int32_t dgf_half_width; /* Z of the DGF table [-Z, Z]^3 (solved on [-2Z, 2Z]^3); 0 -> 128 */
+  int32_t levels;         /* levels of the method (sec. 5): 0 or 2 -> the two-level method;
+                             3 or 4 -> multilevel: the coarse convolution is replaced by
+                             the method one level up (spacing 4h, the same n, radii, P,
+                             Q, b, precision) on a patch box extending m = the smallest
+                             multiple of n >= d_beta/4 + b + 1 cells past [0, N/4]
+                             (proper nesting), recursively; needs (N/4) % n == 0     */
 } mlc_problem;
 
 /* Sizes derived from an mlc_problem (all counts per axis unless noted). */
@@ -94,6 +100,9 @@ typedef struct {
   double h, H;                       /* fine and coarse (4h) spacing                     */
   int32_t out_planes;                /* z planes per block of the local convolutions'
                                         output pass (tuned with fft_size = -1)           */
+  int32_t levels;                    /* levels of the method (2: two-level)              */
+  int32_t level_margin, level_N;     /* multilevel: the next level's box [-m, N/4 + m],
+                                        m = level_margin, of level_N cells; else 0     */
 } mlc_plan_info;
 
 typedef struct mlc_context mlc_context;
@@ -239,11 +248,23 @@ mlc_status mlc_graph_destroy(mlc_graph* graph);
  *   MLC_VIEW_LOCAL_PLANES conv precision [npatch][3][nplanes_a][Wa][Wa]:
  *                         phi_i on its skeleton planes inside Omega_alpha,
  *                         plane normal d, planes at -d_alpha rounded up to a
- *                         multiple of n, in-plane axes ascending from -d_alpha */
+ *                         multiple of n, in-plane axes ascending from -d_alpha
+ *   multilevel plans only (levels > 2), the next coarser level:
+ *   MLC_VIEW_LEVEL_CHARGE float64 [(level_N+1)^3]: its node charge (F^H placed
+ *                         in its box; node 0 at coarse coordinate -level_margin)
+ *   MLC_VIEW_LEVEL_PHI    float64 [(level_N+1)^3]: its uncorrected solution
+ *   MLC_VIEW_LEVEL_WORKSPACE  the workspace of its own solve (for the views of
+ *                         mlc_plan_coarse_level's plan, recursively)
+ * (MLC_VIEW_COARSE_PHI of a multilevel plan is that solution on [O_lo,
+ * O_lo+No-1]^3, the values the boundary interpolation reads.) */
 enum {
   MLC_VIEW_MOMENTS = 0, MLC_VIEW_COARSE_RHS = 1, MLC_VIEW_COARSE_PHI = 2,
-  MLC_VIEW_BOUNDARY = 3, MLC_VIEW_LOCAL_COARSE = 4, MLC_VIEW_LOCAL_PLANES = 5
+  MLC_VIEW_BOUNDARY = 3, MLC_VIEW_LOCAL_COARSE = 4, MLC_VIEW_LOCAL_PLANES = 5,
+  MLC_VIEW_LEVEL_CHARGE = 6, MLC_VIEW_LEVEL_PHI = 7, MLC_VIEW_LEVEL_WORKSPACE = 8
 };
+/* The plan of the next coarser level of a multilevel plan (owned by it;
+ * MLC_ERR_INVALID_ARG for a two-level plan). */
+mlc_status mlc_plan_coarse_level(const mlc_plan* plan, const mlc_plan** level);
 mlc_status mlc_workspace_view(const mlc_plan* plan, void* workspace, int32_t which,
                               void** ptr, size_t* bytes);
 

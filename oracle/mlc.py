@@ -482,15 +482,20 @@ def _boundary_literal(fields, moments, patches, Phi, Phi_lo, phiH, O_lo, prm):
     return out
 
 
-def level_box_margin(prm):
+def level_box_margin(prm, deeper=False):
     """Cells of the next coarser level by which its patch box extends past the
     coarsened domain [0, N/Nref] on each side: whole patches, enough that the
     coarse charge (supported on the coarsened Omega_beta regions, margin
     d_beta/Nref) vanishes on the box's outer nodes and its grown region
     (G(C(Omega_beta), b), the interpolation stencils) lies inside it -- the
-    proper nesting condition of sec. 5."""
+    proper nesting condition of sec. 5.  When that level has a coarser level
+    of its own (deeper), its box must be Nref-aligned in patches as well."""
     need = prm.d_beta // NREF + prm.bb + 1
-    return -(-need // prm.n) * prm.n
+    m = -(-need // prm.n) * prm.n
+    if deeper:
+        while ((prm.N // NREF + 2 * m) // NREF) % prm.n or (prm.N // NREF + 2 * m) % NREF:
+            m += prm.n
+    return m
 
 
 def mlc_solve_multilevel(f, prm, levels, G1=None):
@@ -520,7 +525,7 @@ def mlc_solve_multilevel(f, prm, levels, G1=None):
             phi, out = mlc_solve(fl, p, G1, keep=True)
             trail[depth + 1] = (out["phiH"], x0 + out["O_lo"] * p.H, p.H, None)
         else:
-            m = level_box_margin(p)
+            m = level_box_margin(p, deeper=lv > 3)
             N1 = p.N // NREF + 2 * m
             p1 = Params(N=N1, n=p.n, alpha=p.alpha, beta=p.beta, P=p.P, Q=p.Q, b=p.b, h=NREF * p.hh, Z=p.Z)
 

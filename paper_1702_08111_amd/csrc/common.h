@@ -82,6 +82,7 @@ struct ProbDesc {
   int N, ppa, patch0, pad;
   double h2;    // h^2
   double R15;   // (n h / 2)^{3/2}, the Legendre basis scale
+  double c2h2;  // C2 h^2 of the final correction, 0 for a coarser level of the multilevel method
 };
 
 // Index of the problem owning global patch slot g (descriptors sorted by

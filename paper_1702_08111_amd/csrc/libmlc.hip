@@ -77,6 +77,9 @@ struct mlc_plan {
   double* Am = nullptr;   // skeleton far-field table laid out for MFMA
   double* Tm = nullptr;   // coarse far-field table laid out for MFMA
   double* gram_inv = nullptr;   // P >= 5: inverse Boole Gram matrix of the modes, K x K
+  mlc_plan* child = nullptr;    // multilevel: the plan of the next coarser level
+  bool correct = true;          // add the final Mehrstellen correction (false at coarser levels)
+  size_t o_lf = 0, o_lphi = 0, o_lws = 0;   // multilevel: the next level's charge, solution, workspace
   MfmaGeom mg_skel{}, mg_coarse{};
   // workspace offsets of the plan's own (batch-of-one) layout
   size_t o_mom = 0, o_cs = 0, o_pl = 0, o_F = 0, o_phiH = 0, o_phiB = 0;
@@ -240,6 +243,41 @@ extern "C" const char* mlc_status_string(mlc_status s) {
   return "MLC_ERR_UNKNOWN";
 }
 
+// The next coarser level of a multilevel problem (sec. 5): its box
+// [-m, N/4 + m] in coarse cells, m the smallest multiple of n with m >=
+// d_beta/4 + b + 1 (F^H, supported on the coarsened Omega_beta regions,
+// vanishes on the box's outer nodes, and its b-grown support lies inside: the
+// proper nesting condition) -- and, when that level has a coarser level of
+// its own, with (N/4 + 2m)/4 a multiple of n -- at spacing Nref h, everything
+// else the same.
+static void set_level_box(mlc_plan_info* I) {
+  const int need = I->d_beta / NREF + I->b + 1;
+  int m = (need + I->n - 1) / I->n * I->n;
+  // a box that is itself multilevel must be 4-aligned in patches too
+  if (I->levels > 3)
+    while (((I->N / NREF + 2 * m) / NREF) % I->n || (I->N / NREF + 2 * m) % NREF) m += I->n;
+  I->level_margin = m;
+  I->level_N = I->N / NREF + 2 * m;
+  I->M_coarse = 0;   // no coarse convolution at a level with a coarser level below
+}
+static mlc_plan_info level_info(const mlc_plan_info& I) {
+  mlc_plan_info C = I;
+  C.N = I.level_N;
+  C.h = NREF * I.h;
+  C.H = NREF * C.h;
+  C.patches_per_axis = C.N / C.n;
+  C.npatch = C.patches_per_axis * C.patches_per_axis * C.patches_per_axis;
+  C.S_lo = -C.d_beta / NREF;
+  C.Ns = (C.N + 2 * C.d_beta) / NREF + 1;
+  C.O_lo = -C.b;
+  C.No = C.N / NREF + 2 * C.b + 1;
+  C.levels = I.levels - 1;
+  C.level_margin = C.level_N = 0;
+  if (C.levels > 2) set_level_box(&C);
+  else C.M_coarse = pick_fft(C.Ns + C.No - 1, 2 * C.Z);
+  return C;
+}
+
 static mlc_status derive(const mlc_problem* p, mlc_plan_info* o, std::string* why) {
   if (!p || !o) { *why = "null argument"; return MLC_ERR_INVALID_ARG; }
   mlc_plan_info I{};
@@ -249,6 +287,8 @@ static mlc_status derive(const mlc_problem* p, mlc_plan_info* o, std::string* wh
   I.h = p->h;
   I.H = NREF * p->h;
   I.Z = p->dgf_half_width ? p->dgf_half_width : 128;
+  I.levels = p->levels ? p->levels : 2;
+  if (I.levels < 2 || I.levels > 4) { *why = "levels must be 2, 3 or 4"; return MLC_ERR_UNSUPPORTED; }
   if (I.N <= 0 || I.n <= 0 || !(p->h > 0) || !std::isfinite(p->h)) { *why = "N, n and h must be positive"; return MLC_ERR_INVALID_ARG; }
   if (I.N % I.n) { *why = "N must be a multiple of the patch size"; return MLC_ERR_INVALID_ARG; }
   if (I.n % NREF || I.n < 8) { *why = "patch size must be a multiple of 4 and >= 8"; return MLC_ERR_INVALID_ARG; }
@@ -290,8 +330,21 @@ static mlc_status derive(const mlc_problem* p, mlc_plan_info* o, std::string* wh
   I.Ns = (I.N + 2 * I.d_beta) / NREF + 1;
   I.O_lo = -I.b;
   I.No = I.N / NREF + 2 * I.b + 1;
-  I.M_coarse = pick_fft(I.Ns + I.No - 1, 2 * I.Z);
-  if (I.M_coarse < 0) { *why = "coarse grid too large for the built FFT sizes / DGF table"; return MLC_ERR_UNSUPPORTED; }
+  if (I.levels > 2) {
+    if ((I.N / NREF) % I.n) { *why = "multilevel: N/4 must be a multiple of the patch size"; return MLC_ERR_UNSUPPORTED; }
+    set_level_box(&I);
+    // every coarser level must be built too
+    for (mlc_plan_info C = level_info(I);; C = level_info(C)) {
+      if (C.levels > 2 && (C.N / NREF) % C.n) { *why = "multilevel: a coarser level's N/4 is not a multiple of the patch size"; return MLC_ERR_UNSUPPORTED; }
+      if (C.levels == 2) {
+        if (C.M_coarse < 0) { *why = "coarsest level too large for the built FFT sizes / DGF table"; return MLC_ERR_UNSUPPORTED; }
+        break;
+      }
+    }
+  } else {
+    I.M_coarse = pick_fft(I.Ns + I.No - 1, 2 * I.Z);
+    if (I.M_coarse < 0) { *why = "coarse grid too large for the built FFT sizes / DGF table (more levels lift this)"; return MLC_ERR_UNSUPPORTED; }
+  }
   const int eb = I.d_beta + NREF * I.b;
   if (I.d_beta > I.d_alpha) {
     int Wt = I.n + 2 * eb + 1;
@@ -673,6 +726,7 @@ struct Layout {
          o_dir = 0;
   size_t o_dsum = 0;   // per skeleton thread: the sum of the plane corrections
   std::vector<size_t> o_F, o_tor, o_phiH, o_phiB, o_cpad;
+  std::vector<size_t> o_lf, o_lphi, o_lws;   // multilevel problems: the next level's charge, solution, workspace
   std::vector<int> patch0;
   int total = 0, chunk = 0;
   size_t bytes = 0;
@@ -756,6 +810,14 @@ static Layout layout_of(const std::vector<const mlc_plan_info*>& g) {
     }
     L.o_cpad[k] = take(bytes);
   }
+  L.o_lf.assign(np, 0); L.o_lphi.assign(np, 0); L.o_lws.assign(np, 0);
+  for (int k = 0; k < np; ++k) {
+    if (g[k]->levels <= 2) continue;
+    const mlc_plan_info C = level_info(*g[k]);
+    L.o_lf[k] = take(sizeof(double) * cube(C.N + 1));
+    L.o_lphi[k] = take(sizeof(double) * cube(C.N + 1));
+    L.o_lws[k] = take(layout_of({&C}).bytes);
+  }
   L.bytes = o;
   return L;
 }
@@ -835,19 +897,22 @@ static bool gram_inverse(int n, int P, const ModeList& m, std::vector<double>* o
 
 static std::pair<int, int> autotune_conv(mlc_context* ctx, const mlc_plan_info& I, const double* G1);
 
-extern "C" mlc_status mlc_plan_create(mlc_context* ctx, const mlc_problem* prob, mlc_plan** out) {
-  if (!ctx || !prob || !out) return fail(ctx, MLC_ERR_INVALID_ARG, "null argument");
+static void plan_free(mlc_plan* plan);
+
+// Builds a plan (the context's build lock held); `correct` = false for the
+// coarser levels of a multilevel plan, which return the uncorrected
+// solution.
+static mlc_status plan_create_impl(mlc_context* ctx, const mlc_problem* prob, bool correct, mlc_plan** out) {
   std::string why;
   mlc_plan_info I{};
   mlc_status s = derive(prob, &I, &why);
   if (s != MLC_OK) return fail(ctx, s, why);
-  HIP_TRY(ctx, hipSetDevice(ctx->device));
-  std::lock_guard<std::mutex> lk(ctx->build_mu);
   auto* P = new (std::nothrow) mlc_plan;
   if (!P) return fail(ctx, MLC_ERR_OUT_OF_MEMORY, "host allocation failed");
   P->ctx = ctx;
   P->prob = *prob;
   P->info = I;
+  P->correct = correct;
   P->S = I.n + 1;
   P->Mh = I.M / 2 + 1;
   P->Wp = I.Wa + 2 * I.b;
@@ -885,7 +950,7 @@ extern "C" mlc_status mlc_plan_create(mlc_context* ctx, const mlc_problem* prob,
       return fail(ctx, MLC_ERR_OUT_OF_MEMORY, "spectrum allocation failed");
     }
     s = build_spectrum(ctx, G1, I.Z, M, work, nullptr, P->conv_spec, tsz, 1.0 / (double(M) * M * M), 2, 1, 0);
-    if (s == MLC_OK) {
+    if (s == MLC_OK && I.M_coarse > 0) {
       // coarse spectrum (fp64 octant, layout k0 k1 k2)
       const int Mc = I.M_coarse, Mch = Mc / 2 + 1;
       cplx<double>* cw = nullptr;
@@ -929,6 +994,9 @@ extern "C" mlc_status mlc_plan_create(mlc_context* ctx, const mlc_problem* prob,
     P->o_F = L.o_F[0];
     P->o_phiH = L.o_phiH[0];
     P->o_phiB = L.o_phiB[0];
+    P->o_lf = L.o_lf[0];
+    P->o_lphi = L.o_lphi[0];
+    P->o_lws = L.o_lws[0];
     P->ws_total = L.bytes;
   }
   if (!mlc_budget_take(ctx, P->table_bytes)) {
@@ -937,8 +1005,29 @@ extern "C" mlc_status mlc_plan_create(mlc_context* ctx, const mlc_problem* prob,
     return fail(ctx, MLC_ERR_OUT_OF_MEMORY, "plan tables exceed the context's budget");
   }
   P->charged = true;
+  if (I.levels > 2) {
+    // the next coarser level: the same method on the level box at spacing
+    // Nref h, with this plan's torus (so an autotuned torus is not tuned again)
+    mlc_problem c = *prob;
+    c.n_cells = I.level_N;
+    c.h = NREF * prob->h;
+    c.levels = I.levels - 1;
+    c.fft_size = I.M;
+    s = plan_create_impl(ctx, &c, false, &P->child);
+    if (s != MLC_OK) {
+      plan_free(P);
+      return s;
+    }
+  }
   *out = P;
   return MLC_OK;
+}
+
+extern "C" mlc_status mlc_plan_create(mlc_context* ctx, const mlc_problem* prob, mlc_plan** out) {
+  if (!ctx || !prob || !out) return fail(ctx, MLC_ERR_INVALID_ARG, "null argument");
+  HIP_TRY(ctx, hipSetDevice(ctx->device));
+  std::lock_guard<std::mutex> lk(ctx->build_mu);
+  return plan_create_impl(ctx, prob, true, out);
 }
 
 static void drain_timing(const mlc_plan* P) {
@@ -980,13 +1069,25 @@ extern "C" mlc_status mlc_plan_timing(mlc_plan* plan, mlc_kernel_time* out, int3
   return MLC_OK;
 }
 
-extern "C" mlc_status mlc_plan_destroy(mlc_plan* plan) {
-  if (!plan) return MLC_ERR_INVALID_ARG;
-  hipSetDevice(plan->ctx->device);
+static void plan_free(mlc_plan* plan) {
+  if (plan->child) plan_free(plan->child);
   drain_timing(plan);
   for (hipEvent_t e : plan->event_pool) hipEventDestroy(e);
   plan_destroy_buffers(plan);
   delete plan;
+}
+
+extern "C" mlc_status mlc_plan_destroy(mlc_plan* plan) {
+  if (!plan) return MLC_ERR_INVALID_ARG;
+  hipSetDevice(plan->ctx->device);
+  plan_free(plan);
+  return MLC_OK;
+}
+
+extern "C" mlc_status mlc_plan_coarse_level(const mlc_plan* plan, const mlc_plan** level) {
+  if (!plan || !level) return fail(nullptr, MLC_ERR_INVALID_ARG, "null argument");
+  if (!plan->child) return fail(plan->ctx, MLC_ERR_INVALID_ARG, "a two-level plan has no coarser level");
+  *level = plan->child;
   return MLC_OK;
 }
 
@@ -1016,6 +1117,13 @@ extern "C" mlc_status mlc_workspace_view(const mlc_plan* plan, void* ws, int32_t
     case MLC_VIEW_BOUNDARY: at = plan->o_phiB; len = sizeof(double) * cube(I.N + 1); break;
     case MLC_VIEW_LOCAL_COARSE: at = plan->o_cs; len = tsz * I.npatch * cube(I.Wc); break;
     case MLC_VIEW_LOCAL_PLANES: at = plan->o_pl; len = tsz * I.npatch * 3 * I.nplanes_a * I.Wa * I.Wa; break;
+    case MLC_VIEW_LEVEL_CHARGE:
+    case MLC_VIEW_LEVEL_PHI:
+    case MLC_VIEW_LEVEL_WORKSPACE:
+      if (!plan->child) return fail(plan->ctx, MLC_ERR_INVALID_ARG, "a two-level plan has no coarser level");
+      at = which == MLC_VIEW_LEVEL_CHARGE ? plan->o_lf : (which == MLC_VIEW_LEVEL_PHI ? plan->o_lphi : plan->o_lws);
+      len = which == MLC_VIEW_LEVEL_WORKSPACE ? plan->child->ws_total : sizeof(double) * cube(I.level_N + 1);
+      break;
     default: return fail(plan->ctx, MLC_ERR_INVALID_ARG, "unknown workspace view");
   }
   *ptr = b + at;
@@ -1034,6 +1142,7 @@ struct Group {
   size_t off = 0;         // the group's region of the workspace
   char* ws = nullptr;
   ProbDesc* desc = nullptr;
+  bool one_stream = false;   // every stage on the caller's stream (no side stream)
 };
 
 // Coarse Hockney convolution of a batch of nb tori with the real-even
@@ -1092,6 +1201,7 @@ static void upload_descs(const Group& G, hipStream_t s) {
       d.patch0 = G.L.patch0[k];
       d.h2 = I.h * I.h;
       d.R15 = std::pow(I.n * I.h / 2.0, 1.5);
+      d.c2h2 = G.plans[k]->correct ? I.h * I.h / 12.0 : 0.0;
     }
     hipLaunchKernelGGL(desc_upload_kernel, dim3(1), dim3(DESC_PACK), 0, s, G.desc + k0, pk);
   }
@@ -1161,8 +1271,11 @@ static bool dispatch_conv(const Group& G, hipStream_t s, int phase,
 //   FINISH: skeleton boundary values, Dirichlet solves and correction
 enum Stage { FAR, COARSE, PLANES, FINISH };
 
+struct AnalyticInput;
+static mlc_status enqueue_group(const Group& G, hipStream_t s, const AnalyticInput* an = nullptr);
+
 template <typename T>
-static void launch_rest(const Group& G, hipStream_t s, Stage stage) {
+static mlc_status launch_rest(const Group& G, hipStream_t s, Stage stage) {
   const mlc_plan* P0 = G.plans[0];
   const mlc_plan_info& I0 = P0->info;
   const Layout& L = G.L;
@@ -1290,10 +1403,13 @@ static void launch_rest(const Group& G, hipStream_t s, Stage stage) {
     TimedScope ts(P0, s, "coarse_solve");
     for (int k = 0; k < np; ++k) {
       const mlc_plan_info& I = G.plans[k]->info;
+      if (I.levels > 2) continue;
       hipLaunchKernelGGL(coarse_fill_kernel, dim3(blocks_for(cube(I.M_coarse))), dim3(256), 0, s, F_of(k), tor_of(k),
                          I.Ns, I.M_coarse);
     }
     std::vector<int> done(np, 0);
+    for (int k = 0; k < np; ++k)
+      if (G.plans[k]->info.levels > 2) done[k] = 1;
     for (int k = 0; k < np; ++k) {
       if (done[k]) continue;
       const int Mc = G.plans[k]->info.M_coarse;
@@ -1324,11 +1440,39 @@ static void launch_rest(const Group& G, hipStream_t s, Stage stage) {
     }
     for (int k = 0; k < np; ++k) {
       const mlc_plan_info& I = G.plans[k]->info;
+      if (I.levels > 2) continue;
       const int Mc = I.M_coarse;
       hipLaunchKernelGGL(coarse_extract_kernel, dim3(blocks_for(cube(I.No))), dim3(256), 0, s, tor_of(k), phiH_of(k),
                          Mc, I.S_lo, I.O_lo, I.No, I.H * I.H / (double(Mc) * Mc * Mc));
     }
-  }
+      // multilevel problems (sec. 5): the coarse charge is solved by the method
+    // one level up, on that level's box, and its uncorrected solution read
+    // back onto the coarse output box
+    for (int k = 0; k < np; ++k) {
+      const mlc_plan* P = G.plans[k];
+      const mlc_plan_info& I = P->info;
+      if (I.levels <= 2) continue;
+      const mlc_plan* C = P->child;
+      const int m = I.level_margin, E = I.level_N + 1;
+      double* f1 = reinterpret_cast<double*>(G.ws + L.o_lf[k]);
+      double* phi1 = reinterpret_cast<double*>(G.ws + L.o_lphi[k]);
+      hipLaunchKernelGGL(fill_zero_kernel, dim3(blocks_for(cube(E))), dim3(256), 0, s, f1, cube(E));
+      hipLaunchKernelGGL(box_copy_kernel, dim3(blocks_for(cube(I.Ns))), dim3(256), 0, s, F_of(k), I.Ns, 0, f1, E,
+                         I.S_lo + m, I.Ns);
+      Group G1;
+      G1.plans = {const_cast<mlc_plan*>(C)};
+      G1.f = {f1};
+      G1.phi = {phi1};
+      G1.L = layout_of({&C->info});
+      G1.ws = G.ws + L.o_lws[k];
+      G1.desc = reinterpret_cast<ProbDesc*>(G1.ws + G1.L.o_desc);
+      G1.one_stream = G.one_stream;
+      const mlc_status st1 = enqueue_group(G1, s);
+      if (st1 != MLC_OK) return st1;
+      hipLaunchKernelGGL(box_copy_kernel, dim3(blocks_for(cube(I.No))), dim3(256), 0, s, phi1, E, I.O_lo + m,
+                         phiH_of(k), I.No, 0, I.No);
+    }
+}
   // local plane corrections delta_i = phi_i - I(phi_i), all patches
   if (stage == PLANES) {
     TimedScope ts(P0, s, "plane_delta");
@@ -1350,7 +1494,7 @@ static void launch_rest(const Group& G, hipStream_t s, Stage stage) {
       const mlc_plan* P = G.plans[k];
       const mlc_plan_info& I = P->info;
       SkelGeom sg{I.N, I.n, I.patches_per_axis, P->Kann, I.d_alpha, I.d_beta, I.b, I.Wa, P->P0, I.nplanes_a, P->Wb,
-                  P->P0b, P->nplb, I.O_lo, I.No, I.h * I.h / 12.0};
+                  P->P0b, P->nplb, I.O_lo, I.No, P->correct ? I.h * I.h / 12.0 : 0.0};
       v[k] = SkelProb<T>{phiH_of(k), pl + L.patch0[k] * plsz, G.f[k], phiB_of(k), G.phi[k], sg, total};
       total += int64_t(3) * (I.N / I.n + 1) * (I.N + 1) * (I.N + 1);
     }
@@ -1375,6 +1519,7 @@ static void launch_rest(const Group& G, hipStream_t s, Stage stage) {
     hipLaunchKernelGGL(dirichlet_mfma_kernel<1>, gd, dim3(64 * DIR_WAVES), 0, s, G.desc, np, dir, dg);
     hipLaunchKernelGGL(dirichlet_mfma_kernel<2>, gd, dim3(64 * DIR_WAVES), 0, s, G.desc, np, dir, dg);
   }
+  return MLC_OK;
 }
 
 // The side stream of caller stream s (created on first use).
@@ -1456,14 +1601,13 @@ static void launch_gauss_moments(const Group& G, hipStream_t s, const AnalyticIn
   }
 }
 
-// With one_stream set, every stage runs on s in the same order (no side
+// With G.one_stream set, every stage runs on s in the same order (no side
 // stream, no events): the same kernels on the same data, so the same result.
-static mlc_status enqueue_group(const Group& G, hipStream_t s, bool one_stream = false,
-                                const AnalyticInput* an = nullptr) {
+static mlc_status enqueue_group(const Group& G, hipStream_t s, const AnalyticInput* an) {
   const mlc_plan* P0 = G.plans[0];
   const mlc_plan_info& I0 = P0->info;
   const int np = int(G.plans.size());
-  if (one_stream) {
+  if (G.one_stream) {
     const bool f32 = I0.conv_precision == MLC_CONV_FP32;
     upload_descs(G, s);
     if (an) launch_analytic_fill(G, s, *an);
@@ -1471,12 +1615,11 @@ static mlc_status enqueue_group(const Group& G, hipStream_t s, bool one_stream =
       return fail(P0->ctx, MLC_ERR_UNSUPPORTED, "local FFT size not built");
     if (an) launch_gauss_moments(G, s, *an);
     else launch_moments(G, s);
-    if (f32) {
-      dispatch_conv<float>(G, s, 1);
-      for (Stage st : {FAR, COARSE, PLANES, FINISH}) launch_rest<float>(G, s, st);
-    } else {
-      dispatch_conv<double>(G, s, 1);
-      for (Stage st : {FAR, COARSE, PLANES, FINISH}) launch_rest<double>(G, s, st);
+    if (f32) dispatch_conv<float>(G, s, 1);
+    else dispatch_conv<double>(G, s, 1);
+    for (Stage st : {FAR, COARSE, PLANES, FINISH}) {
+      const mlc_status r = f32 ? launch_rest<float>(G, s, st) : launch_rest<double>(G, s, st);
+      if (r != MLC_OK) return r;
     }
     const hipError_t e = hipGetLastError();
     if (e != hipSuccess) return fail(P0->ctx, MLC_ERR_DEVICE, std::string("launch: ") + hipGetErrorString(e));
@@ -1510,8 +1653,8 @@ static mlc_status enqueue_group(const Group& G, hipStream_t s, bool one_stream =
   e = hipEventRecord(sd->ev[1], s);
   if (e == hipSuccess) e = hipStreamWaitEvent(sd->stream, sd->ev[1], 0);
   if (e != hipSuccess) return fail(P0->ctx, MLC_ERR_DEVICE, std::string("fork: ") + hipGetErrorString(e));
-  if (fp32) launch_rest<float>(G, sd->stream, COARSE);
-  else launch_rest<double>(G, sd->stream, COARSE);
+  const mlc_status rc = fp32 ? launch_rest<float>(G, sd->stream, COARSE) : launch_rest<double>(G, sd->stream, COARSE);
+  if (rc != MLC_OK) return rc;
   e = hipEventRecord(sd->ev[2], sd->stream);
   if (fp32) launch_rest<float>(G, s, PLANES);
   else launch_rest<double>(G, s, PLANES);
@@ -1649,7 +1792,7 @@ extern "C" mlc_status mlc_solve_analytic(mlc_plan* plan, int32_t nterms, const m
   G.L = layout_of(infos_of(G.plans));
   G.ws = static_cast<char*>(workspace);
   G.desc = reinterpret_cast<ProbDesc*>(G.ws + G.L.o_desc);
-  return enqueue_group(G, static_cast<hipStream_t>(stream), false, &an);
+  return enqueue_group(G, static_cast<hipStream_t>(stream), &an);
 }
 
 // mlc_solve on the device's static scratch instead of a caller workspace,
@@ -1671,7 +1814,8 @@ extern "C" mlc_status mlc_solve_static(mlc_plan* plan, const double* f, double* 
   G.L = layout_of(infos_of(G.plans));
   G.ws = ws;
   G.desc = reinterpret_cast<ProbDesc*>(G.ws + G.L.o_desc);
-  return enqueue_group(G, static_cast<hipStream_t>(stream), true);
+  G.one_stream = true;
+  return enqueue_group(G, static_cast<hipStream_t>(stream));
 }
 
 // Split a batch into class groups (first-appearance order) and lay them out
@@ -1852,6 +1996,8 @@ static double time_conv(mlc_context* ctx, const mlc_plan_info& I0, const double*
   Pt.info = I0;
   Pt.info.M = M;
   Pt.info.out_planes = zpb;
+  Pt.info.levels = 2;
+  Pt.info.level_margin = Pt.info.level_N = 0;
   // an 8^3-patch probe: as many blocks per launch as a full-size problem, so
   // that the tiling's effect on how the chip fills is seen
   Pt.info.N = 8 * I0.n;

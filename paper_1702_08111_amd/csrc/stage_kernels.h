@@ -59,6 +59,18 @@ __global__ void __launch_bounds__(256) moments_gram_kernel(const double* __restr
   out[idx] = s;
 }
 
+// dst[d + i] = src[s + i] for i in [0, w)^3 (cubic node arrays of edges sn,
+// dn; s and d per-axis offsets): the coarse charge into the next level's
+// box, and that level's solution back onto the coarse output box.
+__global__ void box_copy_kernel(const double* __restrict__ src, int sn, int soff, double* __restrict__ dst, int dn,
+                                int doff, int w) {
+  const int64_t idx = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (idx >= int64_t(w) * w * w) return;
+  const int i2 = int(idx % w), i1 = int((idx / w) % w), i0 = int(idx / (int64_t(w) * w));
+  dst[(int64_t(doff + i0) * dn + (doff + i1)) * dn + (doff + i2)] =
+      src[(int64_t(soff + i0) * sn + (soff + i1)) * sn + (soff + i2)];
+}
+
 // ------------------------------------------------------- coarse rhs ----
 struct CoarseGeom {
   int n, ppa, K, da, db, e, Wc, S_lo, Ns, Wbc;
@@ -1040,7 +1052,7 @@ __global__ void __launch_bounds__(64 * DIR_WAVES) dirichlet_mfma_kernel(const Pr
     const double v = sc * L[i * 33 + jc];
     if constexpr (PASS == 2) {
       const int64_t node = pbase + (int64_t(u + 1) * Np + (i + 1)) * Np + (jc + 1);
-      phi[node] = v + (h2 / 12.0) * f[node];
+      phi[node] = v + D.c2h2 * f[node];
     } else {
       wp[off(i, jc)] = v;
     }

@@ -29,6 +29,9 @@ MLC_VIEW_COARSE_PHI = 2
 MLC_VIEW_BOUNDARY = 3
 MLC_VIEW_LOCAL_COARSE = 4
 MLC_VIEW_LOCAL_PLANES = 5
+MLC_VIEW_LEVEL_CHARGE = 6
+MLC_VIEW_LEVEL_PHI = 7
+MLC_VIEW_LEVEL_WORKSPACE = 8
 
 
 class mlc_problem(ctypes.Structure):
@@ -44,6 +47,7 @@ class mlc_problem(ctypes.Structure):
         ("conv_precision", ctypes.c_int32),
         ("fft_size", ctypes.c_int32),
         ("dgf_half_width", ctypes.c_int32),
+        ("levels", ctypes.c_int32),
     ]
 
 
@@ -62,7 +66,9 @@ class mlc_plan_info(ctypes.Structure):
     _fields_ = [(name, ctypes.c_int32) for name in (
         "N", "n", "P", "Q", "b", "K", "d_alpha", "d_beta", "e", "patches_per_axis", "npatch",
         "M", "M_coarse", "M_table", "Wc", "Wa", "nplanes_a", "S_lo", "Ns", "O_lo", "No", "Z",
-        "conv_precision")] + [("h", ctypes.c_double), ("H", ctypes.c_double), ("out_planes", ctypes.c_int32)]
+        "conv_precision")] + [("h", ctypes.c_double), ("H", ctypes.c_double), ("out_planes", ctypes.c_int32),
+                              ("levels", ctypes.c_int32), ("level_margin", ctypes.c_int32),
+                              ("level_N", ctypes.c_int32)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -109,6 +115,7 @@ _SIGS = {
                                         _P, ctypes.c_size_t, ctypes.POINTER(_P)]),
     "mlc_graph_launch": (ctypes.c_int, [_P, _P]),
     "mlc_graph_destroy": (ctypes.c_int, [_P]),
+    "mlc_plan_coarse_level": (ctypes.c_int, [_P, ctypes.POINTER(_P)]),
     "mlc_workspace_view": (ctypes.c_int, [_P, _P, ctypes.c_int32, ctypes.POINTER(_P), ctypes.POINTER(ctypes.c_size_t)]),
     "mlc_dgf_table": (ctypes.c_int, [_P, ctypes.c_int32, ctypes.c_int32, ctypes.POINTER(_P)]),
     "mlc_plan_set_timing": (ctypes.c_int, [_P, ctypes.c_int32]),
@@ -174,9 +181,9 @@ def _stream(s):
     return s.cuda_stream
 
 
-def problem(N, n, alpha=3.0, beta=6.0, P=4, Q=4, b=0, h=None, conv="fp32", fft_size=0, Z=0):
+def problem(N, n, alpha=3.0, beta=6.0, P=4, Q=4, b=0, h=None, conv="fp32", fft_size=0, Z=0, levels=0):
     return mlc_problem(N, (1.0 / N) if h is None else h, n, alpha, beta, P, Q, b,
-                       MLC_CONV_FP32 if conv == "fp32" else MLC_CONV_FP64, fft_size, Z)
+                       MLC_CONV_FP32 if conv == "fp32" else MLC_CONV_FP64, fft_size, Z, levels)
 
 
 def problem_workspace_bytes(prob):
@@ -263,6 +270,13 @@ class Plan:
         _check(lib().mlc_plan_timing(self.handle, arr, 64, ctypes.byref(cnt)), self.ctx.handle)
         return {arr[k].name.decode(): (arr[k].launches, arr[k].total_ms) for k in range(min(cnt.value, 64))}
 
+    def coarse_level(self):
+        """The plan of the next coarser level of a multilevel plan (a
+        read-only view: owned by this plan)."""
+        h = ctypes.c_void_p()
+        _check(lib().mlc_plan_coarse_level(self.handle, ctypes.byref(h)), self.ctx.handle)
+        return _PlanView(self.ctx, h)
+
     def view(self, workspace, which):
         """(device pointer, bytes) of an intermediate held in the workspace."""
         p = ctypes.c_void_p()
@@ -270,6 +284,23 @@ class Plan:
         _check(lib().mlc_workspace_view(self.handle, _ptr(workspace), which, ctypes.byref(p), ctypes.byref(n)),
                self.ctx.handle)
         return p.value, n.value
+
+
+class _PlanView(Plan):
+    """A plan owned by another plan (a coarser level): info and views only."""
+
+    def __init__(self, ctx, handle):
+        self.ctx = ctx
+        self.handle = handle
+        info = mlc_plan_info()
+        _check(lib().mlc_plan_get_info(handle, ctypes.byref(info)), ctx.handle)
+        self.info = info.as_dict()
+        nb = ctypes.c_size_t()
+        _check(lib().mlc_plan_workspace_bytes(handle, ctypes.byref(nb)), ctx.handle)
+        self.workspace_bytes = nb.value
+
+    def close(self):
+        self.handle = None
 
 
 def solve_batched(plans, fs, phis, workspace, stream=None):
