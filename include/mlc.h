@@ -82,6 +82,12 @@ typedef struct {
                              Q, b, precision) on a patch box extending m = the smallest
                              multiple of n >= d_beta/4 + b + 1 cells past [0, N/4]
                              (proper nesting), recursively; needs (N/4) % n == 0     */
+  double level_alpha[3];  /* multilevel: the inner radius alpha at the coarser levels that
+                             are solved by the method (sec. 7.2 raises it there to bound
+                             the error of the truncated Legendre expansions):
+                             level_alpha[k] at k+1 levels above the finest; 0 -> the
+                             radius of the next finer level; same rules as alpha;
+                             entries past levels - 2 are ignored                     */
 } mlc_problem;
 
 /* Sizes derived from an mlc_problem (all counts per axis unless noted). */
@@ -103,6 +109,8 @@ typedef struct {
   int32_t levels;                    /* levels of the method (2: two-level)              */
   int32_t level_margin, level_N;     /* multilevel: the next level's box [-m, N/4 + m],
                                         m = level_margin, of level_N cells; else 0     */
+  double alpha, beta;                /* localisation radii of this level                 */
+  double level_alpha[3];             /* alpha at 1, 2, 3 levels above (resolved: no 0)  */
 } mlc_plan_info;
 
 typedef struct mlc_context mlc_context;
@@ -235,7 +243,7 @@ mlc_status mlc_graph_create(int32_t count, mlc_plan* const* plans, const double*
 mlc_status mlc_graph_launch(mlc_graph* graph, void* stream);
 mlc_status mlc_graph_destroy(mlc_graph* graph);
 
-/* Intermediates of the last solve held in a workspace/* Intermediates of the last solve held in a workspace (device pointers into
+/* Intermediates of the last solve held in a workspace (device pointers into
  * it; valid until the workspace is reused):
  *   MLC_VIEW_MOMENTS      float64 [npatch][K]: c_{i,p}, patches in C order of i,
  *                         modes by total degree then descending lexicographic p

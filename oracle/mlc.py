@@ -498,13 +498,16 @@ def level_box_margin(prm, deeper=False):
     return m
 
 
-def mlc_solve_multilevel(f, prm, levels, G1=None):
+def mlc_solve_multilevel(f, prm, levels, G1=None, level_alpha=()):
     """Multilevel MLC (sec. 5) with `levels` levels (2 = the two-level method):
     the two-level steps at the finest level, with the coarse convolution
     replaced by the same method applied one level up to the coarse charge F^H
-    (spacing Nref h, the same n, alpha, beta, P, Q, b), placed in a patch box
-    that extends level_box_margin(prm) cells past the coarsened domain; the
-    coarsest level is a single convolution.  Every level takes its boundary
+    (spacing Nref h, the same n, beta, P, Q, b), placed in a patch box that
+    extends level_box_margin(prm) cells past the coarsened domain; the
+    coarsest level is a single convolution.  The inner radius of the level k
+    levels above the finest is level_alpha[k-1] when given and nonzero, else
+    that of the next finer level (sec. 7.2 raises alpha at the coarser levels
+    to bound the error of the truncated Legendre expansions there).  Every level takes its boundary
     values from the uncorrected discrete solution (phi-tilde) of the level
     below it (sec. 5 eq. mlcmultilevel); the Mehrstellen correction is added
     at the finest level.  Returns phi and, from the finest level down, the
@@ -527,7 +530,8 @@ def mlc_solve_multilevel(f, prm, levels, G1=None):
         else:
             m = level_box_margin(p, deeper=lv > 3)
             N1 = p.N // NREF + 2 * m
-            p1 = Params(N=N1, n=p.n, alpha=p.alpha, beta=p.beta, P=p.P, Q=p.Q, b=p.b, h=NREF * p.hh, Z=p.Z)
+            a1 = level_alpha[depth] if depth < len(level_alpha) and level_alpha[depth] else p.alpha
+            p1 = Params(N=N1, n=p.n, alpha=a1, beta=p.beta, P=p.P, Q=p.Q, b=p.b, h=NREF * p.hh, Z=p.Z)
 
             def coarse(FH, S_lo, O_lo, O_hi):
                 f1 = np.zeros((N1 + 1,) * 3)

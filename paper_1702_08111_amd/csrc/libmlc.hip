@@ -260,21 +260,41 @@ static void set_level_box(mlc_plan_info* I) {
   I->level_N = I->N / NREF + 2 * m;
   I->M_coarse = 0;   // no coarse convolution at a level with a coarser level below
 }
+
+static mlc_status derive(const mlc_problem* p, mlc_plan_info* o, std::string* why);
+
+// The problem the next coarser level solves: the level box at spacing Nref h,
+// its own inner radius (level_alpha[0]), the coarser radii shifted down, and
+// this level's local torus when it is large enough for that radius (so an
+// autotuned torus is not tuned again), else the smallest built one.
+static mlc_problem child_problem(const mlc_plan_info& I) {
+  mlc_problem c{};
+  c.n_cells = I.level_N;
+  c.h = NREF * I.h;
+  c.patch = I.n;
+  c.alpha = I.level_alpha[0];
+  c.beta = I.beta;
+  c.P = I.P;
+  c.Q = I.Q;
+  c.interp_b = I.b;
+  c.conv_precision = I.conv_precision;
+  c.dgf_half_width = I.Z;
+  c.levels = I.levels - 1;
+  c.level_alpha[0] = I.level_alpha[1];
+  c.level_alpha[1] = I.level_alpha[2];
+  c.level_alpha[2] = 0.0;
+  const int e = margin_of(c.alpha, I.n) + NREF * I.b;
+  c.fft_size = (I.M >= 2 * (I.n + e) + 1 && conv_size_ok(I.conv_precision, I.n, I.M)) ? I.M : 0;
+  return c;
+}
+
+// Sizes of the next coarser level (derive of child_problem, which the caller
+// has validated).
 static mlc_plan_info level_info(const mlc_plan_info& I) {
-  mlc_plan_info C = I;
-  C.N = I.level_N;
-  C.h = NREF * I.h;
-  C.H = NREF * C.h;
-  C.patches_per_axis = C.N / C.n;
-  C.npatch = C.patches_per_axis * C.patches_per_axis * C.patches_per_axis;
-  C.S_lo = -C.d_beta / NREF;
-  C.Ns = (C.N + 2 * C.d_beta) / NREF + 1;
-  C.O_lo = -C.b;
-  C.No = C.N / NREF + 2 * C.b + 1;
-  C.levels = I.levels - 1;
-  C.level_margin = C.level_N = 0;
-  if (C.levels > 2) set_level_box(&C);
-  else C.M_coarse = pick_fft(C.Ns + C.No - 1, 2 * C.Z);
+  const mlc_problem c = child_problem(I);
+  mlc_plan_info C{};
+  std::string why;
+  derive(&c, &C, &why);
   return C;
 }
 
@@ -301,6 +321,13 @@ static mlc_status derive(const mlc_problem* p, mlc_plan_info* o, std::string* wh
   if (I.n > 32) { *why = "patch size above 32 is not built"; return MLC_ERR_UNSUPPORTED; }
   if (I.Z != 32 && I.Z != 64 && I.Z != 128) { *why = "DGF half-width must be 32, 64 or 128"; return MLC_ERR_UNSUPPORTED; }
   I.K = I.P * (I.P + 1) * (I.P + 2) / 6;
+  I.alpha = p->alpha;
+  I.beta = p->beta;
+  for (int k = 0; k < 3; ++k) {
+    const double a = p->level_alpha[k];
+    if (a != 0.0 && !(a >= 1.0 && a <= p->beta)) { *why = "level_alpha entries must be 0 or in [1, beta]"; return MLC_ERR_INVALID_ARG; }
+    I.level_alpha[k] = a != 0.0 ? a : (k ? I.level_alpha[k - 1] : p->alpha);
+  }
   I.d_alpha = margin_of(p->alpha, I.n);
   I.d_beta = margin_of(p->beta, I.n);
   if (I.d_alpha % NREF || I.d_beta % NREF) { *why = "localisation margins must be multiples of 4"; return MLC_ERR_UNSUPPORTED; }
@@ -333,13 +360,14 @@ static mlc_status derive(const mlc_problem* p, mlc_plan_info* o, std::string* wh
   if (I.levels > 2) {
     if ((I.N / NREF) % I.n) { *why = "multilevel: N/4 must be a multiple of the patch size"; return MLC_ERR_UNSUPPORTED; }
     set_level_box(&I);
-    // every coarser level must be built too
-    for (mlc_plan_info C = level_info(I);; C = level_info(C)) {
-      if (C.levels > 2 && (C.N / NREF) % C.n) { *why = "multilevel: a coarser level's N/4 is not a multiple of the patch size"; return MLC_ERR_UNSUPPORTED; }
-      if (C.levels == 2) {
-        if (C.M_coarse < 0) { *why = "coarsest level too large for the built FFT sizes / DGF table"; return MLC_ERR_UNSUPPORTED; }
-        break;
-      }
+    // every coarser level must be built too (derive recurses through them)
+    const mlc_problem c = child_problem(I);
+    mlc_plan_info C{};
+    std::string cwhy;
+    const mlc_status cs = derive(&c, &C, &cwhy);
+    if (cs != MLC_OK) {
+      *why = "multilevel, level " + std::to_string(I.levels - 2) + ": " + cwhy;
+      return cs;
     }
   } else {
     I.M_coarse = pick_fft(I.Ns + I.No - 1, 2 * I.Z);
@@ -1007,12 +1035,8 @@ static mlc_status plan_create_impl(mlc_context* ctx, const mlc_problem* prob, bo
   P->charged = true;
   if (I.levels > 2) {
     // the next coarser level: the same method on the level box at spacing
-    // Nref h, with this plan's torus (so an autotuned torus is not tuned again)
-    mlc_problem c = *prob;
-    c.n_cells = I.level_N;
-    c.h = NREF * prob->h;
-    c.levels = I.levels - 1;
-    c.fft_size = I.M;
+    // Nref h with that level's inner radius
+    const mlc_problem c = child_problem(I);
     s = plan_create_impl(ctx, &c, false, &P->child);
     if (s != MLC_OK) {
       plan_free(P);
@@ -1165,6 +1189,8 @@ static void conv3_coarse_impl(cplx<double>* data, const double* oct, int nb, int
                      no);
 }
 static bool conv3_coarse(cplx<double>* data, const double* oct, int M, int nb, int ns, int o0, int no, hipStream_t s) {
+  // the passes index lines o0 .. o0 + no - 1 and 0 .. ns - 1 of each torus
+  if (o0 < 0 || no < 1 || o0 + no > M || ns < 1 || ns > M) return false;
   switch (M) {
 #define CASE(MM) case MM: conv3_coarse_impl<MM>(data, oct, nb, ns, o0, no, s); return true;
     MLC_FFT_SIZES(CASE)
@@ -1433,10 +1459,19 @@ static mlc_status launch_rest(const Group& G, hipStream_t s, Stage stage) {
           lo = std::min(lo, Ij.O_lo - Ij.S_lo);
           hi = std::max(hi, Ij.O_lo - Ij.S_lo + Ij.No);
         }
-        o0 = lo;
-        no = std::min(hi - lo, Mc);
+        // with d_beta / 4 < b the output box starts below the source box
+        // (O_lo < S_lo): its slots wrap around the torus end, so the inverse
+        // passes cover every slot
+        if (lo < 0 || hi > Mc) {
+          o0 = 0;
+          no = Mc;
+        } else {
+          o0 = lo;
+          no = hi - lo;
+        }
       }
-      conv3_coarse(tor_of(k), G.plans[k]->coarse_spec, Mc, nb, ns, o0, no, s);
+      if (!conv3_coarse(tor_of(k), G.plans[k]->coarse_spec, Mc, nb, ns, o0, no, s))
+        return fail(P0->ctx, MLC_ERR_UNSUPPORTED, "coarse torus size or output range not built");
     }
     for (int k = 0; k < np; ++k) {
       const mlc_plan_info& I = G.plans[k]->info;

@@ -48,6 +48,7 @@ class mlc_problem(ctypes.Structure):
         ("fft_size", ctypes.c_int32),
         ("dgf_half_width", ctypes.c_int32),
         ("levels", ctypes.c_int32),
+        ("level_alpha", ctypes.c_double * 3),
     ]
 
 
@@ -68,10 +69,13 @@ class mlc_plan_info(ctypes.Structure):
         "M", "M_coarse", "M_table", "Wc", "Wa", "nplanes_a", "S_lo", "Ns", "O_lo", "No", "Z",
         "conv_precision")] + [("h", ctypes.c_double), ("H", ctypes.c_double), ("out_planes", ctypes.c_int32),
                               ("levels", ctypes.c_int32), ("level_margin", ctypes.c_int32),
-                              ("level_N", ctypes.c_int32)]
+                              ("level_N", ctypes.c_int32), ("alpha", ctypes.c_double),
+                              ("beta", ctypes.c_double), ("level_alpha", ctypes.c_double * 3)]
 
     def as_dict(self):
-        return {k: getattr(self, k) for k, _ in self._fields_}
+        d = {k: getattr(self, k) for k, _ in self._fields_}
+        d["level_alpha"] = list(d["level_alpha"])
+        return d
 
 
 class mlc_kernel_time(ctypes.Structure):
@@ -181,9 +185,12 @@ def _stream(s):
     return s.cuda_stream
 
 
-def problem(N, n, alpha=3.0, beta=6.0, P=4, Q=4, b=0, h=None, conv="fp32", fft_size=0, Z=0, levels=0):
+def problem(N, n, alpha=3.0, beta=6.0, P=4, Q=4, b=0, h=None, conv="fp32", fft_size=0, Z=0, levels=0,
+            level_alpha=()):
+    la = list(level_alpha) + [0.0] * (3 - len(level_alpha))
     return mlc_problem(N, (1.0 / N) if h is None else h, n, alpha, beta, P, Q, b,
-                       MLC_CONV_FP32 if conv == "fp32" else MLC_CONV_FP64, fft_size, Z, levels)
+                       MLC_CONV_FP32 if conv == "fp32" else MLC_CONV_FP64, fft_size, Z, levels,
+                       (ctypes.c_double * 3)(*la[:3]))
 
 
 def problem_workspace_bytes(prob):

@@ -65,6 +65,11 @@ def _case(name):
         # the parameters of the paper's Table 7 (L27, alpha 1.75, beta 3.25,
         # P = 9) with 32^3-cell patches
         "t7_64": (64, 32, 1.75, 3.25, 9, 6, 0, 128, mi.bumps(2, 21, radius=(0.1, 0.2))),
+        # beta margins below 4b (d_beta / 4 < b): the coarse output box starts
+        # below the right-hand side's box, its torus slots wrap around
+        "mlc0_32_q6": (32, 8, 3.0, 3.0, 4, 6, 0, 64, mi.bumps(2, 22, radius=(0.1, 0.25))),
+        "narrow_beta_q6": (32, 8, 2.0, 3.0, 4, 6, 0, 64, mi.bumps(2, 23, radius=(0.1, 0.25))),
+        "mlc0_64_n16": (64, 16, 2.0, 2.0, 4, 6, 0, 64, mi.bumps(2, 24, radius=(0.1, 0.2))),
     }
     return cases[name]
 
@@ -100,7 +105,8 @@ def _check_all(name, conv):
 
 
 @pytest.mark.parametrize("name", ["plain32", "plain32_q6", "mlc0_32", "p1_32", "ragged48", "single16", "p2_32",
-                                  "p3_32", "b1_32", "b4_32", "n32_64", "p5_32", "p6_32_q6", "p9_32", "t7_64"])
+                                  "p3_32", "b1_32", "b4_32", "n32_64", "p5_32", "p6_32_q6", "p9_32", "t7_64",
+                                  "mlc0_32_q6", "narrow_beta_q6", "mlc0_64_n16"])
 def test_fp64_parity(name):
     errs = _check_all(name, "fp64")
     for k, v in errs.items():
@@ -108,7 +114,7 @@ def test_fp64_parity(name):
 
 
 @pytest.mark.parametrize("name", ["plain32", "plain32_q6", "mlc0_32", "p1_32", "ragged48", "single16", "b1_32",
-                                  "b4_32", "n32_64", "p5_32", "p9_32"])
+                                  "b4_32", "n32_64", "p5_32", "p9_32", "mlc0_32_q6"])
 def test_fp32_parity(name):
     errs = _check_all(name, "fp32")
     assert errs["phi"] < TOL32, errs

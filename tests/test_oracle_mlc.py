@@ -283,3 +283,33 @@ def test_multilevel_matches_two_level_when_the_coarse_level_resolves():
     e2 = np.abs(p2 - ex).max() / np.abs(ex).max()
     e3 = np.abs(p3 - ex).max() / np.abs(ex).max()
     assert abs(e3 / e2 - 1.0) < 0.05, (e2, e3)
+
+
+def test_multilevel_coarse_alpha_reduces_level_error():
+    """A larger inner radius at the coarser level (sec. 7.2, the remedy for
+    the error of the truncated expansions there) leaves that level's charge
+    unchanged (F^H depends on the finest level's radii only), reduces the
+    level-1 MLC's deviation from the convolution it replaces, and brings the
+    fine-level solution to the two-level one (alpha = 2, beta = 3 at the
+    finest level; alpha 2 or 3 at level 1: the difference falls by more than
+    10, the level-1 deviation over its whole output box by more than 20 %)."""
+    N, n, Q, Z = 64, 8, 6, 64
+    G1 = dgf_cached(Q, Z)
+    f = mi.smooth_charge(N)
+    prm = mlc.Params(N=N, n=n, alpha=2.0, beta=3.0, P=4, Q=Q, Z=Z)
+    p2, o2 = mlc.mlc_solve(f, prm, G1, keep=True)
+    phiH, O_lo = o2["phiH"], o2["O_lo"]
+    m = mlc.level_box_margin(prm)
+    o, w = O_lo + m, phiH.shape[0]
+    res = {}
+    for la in ((), (3.0,)):
+        p3, trail = mlc.mlc_solve_multilevel(f, prm, 3, G1, level_alpha=la)
+        d1 = np.abs(trail[1][0][o:o + w, o:o + w, o:o + w] - phiH).max()
+        res[la] = (p3, trail[1][3], d1, np.abs(p3 - p2).max())
+    same, wide = res[()], res[(3.0,)]
+    assert np.array_equal(same[1], wide[1])
+    assert wide[2] < 0.8 * same[2], (same[2], wide[2])
+    assert wide[3] < 0.1 * same[3], (same[3], wide[3])
+    # an explicit radius equal to the finest level's is the default
+    p3, _ = mlc.mlc_solve_multilevel(f, prm, 3, G1, level_alpha=(2.0,))
+    assert np.array_equal(p3, same[0])
