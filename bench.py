@@ -40,6 +40,8 @@ def parse():
                     help="measured requests of the serving loop after 50 warm-ups (0: skip)")
     ap.add_argument("--serve-load", type=float, default=0.7, help="arrival rate / saturation rate")
     ap.add_argument("--no-sweep", action="store_true", help="skip the (alpha, beta, P, Q) sweep")
+    ap.add_argument("--ml-steps", type=int, default=3,
+                    help="timed solves per multilevel workload (512^3 three levels, 1024^3 four levels); 0 skips")
     ap.add_argument("--osc-steps", type=int, default=5,
                     help="timed steps of the oscillatory 384^3 workload per path (0: skip)")
     return ap.parse_args()
@@ -254,6 +256,77 @@ def oscillatory_bench(ctx, steps, dev, N=384, n=32, Q=6):
         del ws
         plan.close()
     out["fp32_vs_fp64_relmax"] = float(np.abs(phis["fp32"] - phis["fp64"]).max() / np.abs(phis["fp64"]).max())
+    torch.cuda.empty_cache()
+    return out
+
+
+def multilevel_bench(ctx, steps, dev):
+    """The multilevel method (sec. 5): the smooth charge of sec. 7.1 at 512^3
+    with three levels (alpha = 1.75 at the finest level and 3 at the next,
+    sec. 7.2's remedy; beta = 3.25, P = 4, L27), float64 and float32 local
+    convolutions, errors against the closed form; and the oscillatory
+    charges of sec. 7.2 at 1024^3 with four levels (alpha = 1.75, 2, 2.25
+    from the finest level up), float32 convolutions, the charge sampled on the
+    device from its radial terms, the error taken on every fourth node."""
+    import torch
+    from paper_1702_08111_amd import mlc as gm
+
+    def timed(plan, f, phi, ws):
+        plan.solve(f, phi, ws)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            plan.solve(f, phi, ws)
+        torch.cuda.synchronize()
+        return (time.perf_counter() - t0) * 1e3 / steps
+
+    out = {}
+    N = 512
+    f = torch.from_numpy(mi.smooth_charge(N)).to(dev)
+    exact = mi.smooth_potential(N)
+    scale = np.abs(exact).max()
+    rows = {}
+    for conv in ("fp64", "fp32"):
+        plan = ctx.plan(gm.problem(N, 32, 1.75, 3.25, 4, 6, conv=conv, levels=3, level_alpha=(3.0,)))
+        ws = torch.empty(plan.workspace_bytes, dtype=torch.uint8, device=dev)
+        phi = torch.empty_like(f)
+        ms = timed(plan, f, phi, ws)
+        rows[conv] = {"ms_per_step": ms, "value": N ** 3 / (ms * 1e-3), "unit": "grid points/s",
+                      "vs_closed_form": float(np.abs(phi.cpu().numpy() - exact).max() / scale),
+                      "workspace_GiB": plan.workspace_bytes / 2 ** 30}
+        del ws, phi
+        plan.close()
+        torch.cuda.empty_cache()
+    out["smooth_512_three_levels"] = {
+        "config": "smooth charge (sec. 7.1), 512^3, 32^3-cell patches, L27, 3 levels, alpha 1.75 (3 at level 1), "
+                  "beta 3.25, P 4; the paper's two-level error for these finest-level parameters (Table 7) "
+                  "is 9.17e-9", **rows}
+    del f
+    torch.cuda.empty_cache()
+    progress("multilevel: oscillatory workload, 1024^3, four levels")
+    N, stride = 1024, 4
+    plan = ctx.plan(gm.problem(N, 32, 1.75, 3.25, 4, 6, conv="fp32", levels=4, level_alpha=(2.0, 2.25)))
+    ws = torch.empty(plan.workspace_bytes, dtype=torch.uint8, device=dev)
+    f = torch.empty((N + 1,) * 3, dtype=torch.float64, device=dev)
+    phi = torch.empty_like(f)
+    # the library samples the radial terms into f (the solve it runs here is a warmup)
+    plan.solve_analytic(mi.oscillatory_terms(), 2, f, phi, ws)
+    ms = timed(plan, f, phi, ws)
+    got = phi[::stride, ::stride, ::stride].cpu().numpy()
+    ax = np.arange(0, N + 1, stride) / N
+    exact = np.zeros(got.shape)
+    for c in mi.OSC_CENTRES:
+        r = np.sqrt((ax[:, None, None] - c[0]) ** 2 + (ax[None, :, None] - c[1]) ** 2
+                    + (ax[None, None, :] - c[2]) ** 2) / mi.OSC_RO
+        exact += mi._osc_psi(r) / mi.OSC_RO
+    out["oscillatory_1024_four_levels"] = {
+        "config": "oscillatory charges (sec. 7.2), 1024^3, 32^3-cell patches, L27, 4 levels, alpha 1.75 / 2 / 2.25 "
+                  "from the finest level up, beta 3.25, P 4, float32 local convolutions; error on every 4th node",
+        "ms_per_step": ms, "value": N ** 3 / (ms * 1e-3), "unit": "grid points/s",
+        "vs_closed_form_sampled": float(np.abs(got - exact).max() / np.abs(exact).max()),
+        "workspace_GiB": plan.workspace_bytes / 2 ** 30}
+    del ws, f, phi
+    plan.close()
     torch.cuda.empty_cache()
     return out
 
@@ -524,6 +597,10 @@ def main():
     if args.osc_steps > 0:
         progress("oscillatory workload, 384^3")
         osc = oscillatory_bench(ctx, args.osc_steps, dev)
+    ml = None
+    if args.ml_steps > 0:
+        progress("multilevel: smooth charge, 512^3, three levels")
+        ml = multilevel_bench(ctx, args.ml_steps, dev)
     if args.serve_requests > 0:
         progress("serving loop")
     serving = serving_bench(ctx, args.serve_requests, args.serve_load, dev) if args.serve_requests > 0 else None
@@ -571,6 +648,7 @@ def main():
         "cpu_baseline": cpu,
         "batch": batch,
         "oscillatory": osc,
+        "multilevel": ml,
         "sweep": sweep,
         "serving": serving,
     }
