@@ -88,6 +88,18 @@ typedef struct {
                              level_alpha[k] at k+1 levels above the finest; 0 -> the
                              radius of the next finer level; same rules as alpha;
                              entries past levels - 2 are ignored                     */
+  int32_t rhs_order;      /* 0 or 4: the fourth-order method, phi = phi~ + C2 h^2 f (sec.
+                             4.1, final step); 6 (Q = 6 only): the method applied to the
+                             modified right-hand side of sec. 2 eq. msCorr, with the
+                             27-point operator's h^4 term from its truncation error
+                             (appendix A.1): f~ = f + (h^2/12) (Delta f)_4 + (h^4/360)
+                             (Delta^2 + 2 (d_xxyy + d_yyzz + d_zzxx)) f by differences of
+                             f (fourth order for Delta f, second for the h^4 term), and
+                             no final correction: sixth order in h up to the method's
+                             own errors.  f must vanish within two nodes of the faces
+                             (MLC_CHECK then checks the three outer node layers); the
+                             workspace holds f~, (N+1)^3 doubles more;
+                             mlc_solve_analytic refuses it                           */
 } mlc_problem;
 
 /* Sizes derived from an mlc_problem (all counts per axis unless noted). */
@@ -111,6 +123,7 @@ typedef struct {
                                         m = level_margin, of level_N cells; else 0     */
   double alpha, beta;                /* localisation radii of this level                 */
   double level_alpha[3];             /* alpha at 1, 2, 3 levels above (resolved: no 0)  */
+  int32_t rhs_order;                 /* 4 or 6 (mlc_problem.rhs_order, 0 -> 4)           */
 } mlc_plan_info;
 
 typedef struct mlc_context mlc_context;
@@ -264,11 +277,15 @@ mlc_status mlc_graph_destroy(mlc_graph* graph);
  *   MLC_VIEW_LEVEL_WORKSPACE  the workspace of its own solve (for the views of
  *                         mlc_plan_coarse_level's plan, recursively)
  * (MLC_VIEW_COARSE_PHI of a multilevel plan is that solution on [O_lo,
- * O_lo+No-1]^3, the values the boundary interpolation reads.) */
+ * O_lo+No-1]^3, the values the boundary interpolation reads.)
+ *   sixth-order plans only (rhs_order 6):
+ *   MLC_VIEW_CHARGE       float64 [(N+1)^3]: the modified right-hand side f~
+ *                         the method solved */
 enum {
   MLC_VIEW_MOMENTS = 0, MLC_VIEW_COARSE_RHS = 1, MLC_VIEW_COARSE_PHI = 2,
   MLC_VIEW_BOUNDARY = 3, MLC_VIEW_LOCAL_COARSE = 4, MLC_VIEW_LOCAL_PLANES = 5,
-  MLC_VIEW_LEVEL_CHARGE = 6, MLC_VIEW_LEVEL_PHI = 7, MLC_VIEW_LEVEL_WORKSPACE = 8
+  MLC_VIEW_LEVEL_CHARGE = 6, MLC_VIEW_LEVEL_PHI = 7, MLC_VIEW_LEVEL_WORKSPACE = 8,
+  MLC_VIEW_CHARGE = 9
 };
 /* The plan of the next coarser level of a multilevel plan (owned by it;
  * MLC_ERR_INVALID_ARG for a two-level plan). */

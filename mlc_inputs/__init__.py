@@ -112,6 +112,35 @@ def smooth_potential(N):
     return SMOOTH_RO ** 2 * np.where(r < 1.0, inside, outside)
 
 
+# A smoother radial charge for order-of-accuracy checks beyond fourth order:
+# f = (1 - rho^2)^k inside the ball rho = |x - c| / R < 1 (C^(k-1) across its
+# surface), with the potential of Delta phi = f that decays at infinity,
+#   phi(r) = -(1/r) int_0^min(r,R) f s^2 ds - int_min(r,R)^R f s ds,
+# integrated exactly as polynomials in s.
+def _poly_profile_integrals(k):
+    from numpy.polynomial import polynomial as npoly
+    base = npoly.polypow([1.0, 0.0, -1.0], k)          # (1 - u^2)^k in u = s / R
+    m2 = npoly.polyint(npoly.polymul(base, [0.0, 0.0, 1.0]))   # int_0^u t^2 f dt
+    m1 = npoly.polyint(npoly.polymul(base, [0.0, 1.0]))        # int_0^u t f dt
+    return m2, m1
+
+
+def poly_charge(N, k=10, centre=(0.5, 0.5, 0.5), R=0.3):
+    r = _rho(N, centre, R)
+    return np.where(r < 1.0, (1.0 - r * r) ** k, 0.0)
+
+
+def poly_potential(N, k=10, centre=(0.5, 0.5, 0.5), R=0.3):
+    from numpy.polynomial import polynomial as npoly
+    m2, m1 = _poly_profile_integrals(k)
+    u = np.minimum(_rho(N, centre, R), 1.0)
+    r = _rho(N, centre, R)
+    rs = np.where(r > 0, r, 1.0)
+    inner = np.where(r > 0, npoly.polyval(u, m2) / rs, 0.0)     # (1/u) int_0^u t^2 f dt (in units of R)
+    outer = npoly.polyval(1.0, m1) - npoly.polyval(u, m1)        # int_u^1 t f dt
+    return -R * R * (inner + outer)
+
+
 # The oscillatory three-charge test of sec. 7.2: each charge is supported in
 # a ball of radius OSC_RO, with gamma = 4 mu pi, mu = 7.
 OSC_RO = 0.05

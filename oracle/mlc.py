@@ -230,7 +230,7 @@ def plan_tables(G1, prm, conv_mode="fft"):
 
 
 def mlc_solve(f, prm, G1=None, conv_mode="fft", bc_mode="by_patch", keep=False, on_local=None, tables=None,
-              moments_fn=None, coarse_fn=None):
+              moments_fn=None, coarse_fn=None, correct=True):
     """Two-level MLC (sec. 4.1).  Returns phi on all (N+1)^3 nodes and, if
     keep, a dict of intermediates: moments, FH, phiH, phiB (full grid,
     meaningful on skeleton nodes), and the per-patch local fields (only for
@@ -244,7 +244,9 @@ def mlc_solve(f, prm, G1=None, conv_mode="fft", bc_mode="by_patch", keep=False, 
     step 1); otherwise they come from the node values by Boole's rule.
     coarse_fn, if given, replaces the coarse convolution of step 2:
     coarse_fn(FH, S_lo, O_lo, O_hi) returns phi^H on [O_lo, O_hi]^3 (the
-    multilevel method solves the coarse charge by MLC one level up, sec. 5)."""
+    multilevel method solves the coarse charge by MLC one level up, sec. 5).
+    correct=False leaves out the final C2 h^2 f (the charge is then a
+    modified right-hand side, see mlc_solve_sixth)."""
     from .dgf import dgf_cached
     prm.check()
     N, n, Q, b = prm.N, prm.n, prm.Q, prm.bb
@@ -329,7 +331,7 @@ def mlc_solve(f, prm, G1=None, conv_mode="fft", bc_mode="by_patch", keep=False, 
         lo = n * i
         sl = tuple(slice(lo[d], lo[d] + n + 1) for d in range(3))
         phit[sl][1:-1, 1:-1, 1:-1] = dirichlet_solve(phiB[sl], f[sl], Q, h)
-    phi = phit + C2 * h * h * f
+    phi = phit + C2 * h * h * f if correct else phit.copy()
     if not keep:
         return phi
     out = dict(moments=moments, FH=FH, S_lo=S_lo, phiH=phiH, O_lo=O_lo, phiB=phiB, phitilde=phit)
@@ -498,7 +500,7 @@ def level_box_margin(prm, deeper=False):
     return m
 
 
-def mlc_solve_multilevel(f, prm, levels, G1=None, level_alpha=()):
+def mlc_solve_multilevel(f, prm, levels, G1=None, level_alpha=(), rhs_order=4):
     """Multilevel MLC (sec. 5) with `levels` levels (2 = the two-level method):
     the two-level steps at the finest level, with the coarse convolution
     replaced by the same method applied one level up to the coarse charge F^H
@@ -507,7 +509,10 @@ def mlc_solve_multilevel(f, prm, levels, G1=None, level_alpha=()):
     coarsest level is a single convolution.  The inner radius of the level k
     levels above the finest is level_alpha[k-1] when given and nonzero, else
     that of the next finer level (sec. 7.2 raises alpha at the coarser levels
-    to bound the error of the truncated Legendre expansions there).  Every level takes its boundary
+    to bound the error of the truncated Legendre expansions there).
+    rhs_order=6 solves the sixth-order right-hand side of the 27-point
+    operator at the finest level instead (see mlc_solve_sixth): the coarser
+    levels are unchanged.  Every level takes its boundary
     values from the uncorrected discrete solution (phi-tilde) of the level
     below it (sec. 5 eq. mlcmultilevel); the Mehrstellen correction is added
     at the finest level.  Returns phi and, from the finest level down, the
@@ -524,8 +529,14 @@ def mlc_solve_multilevel(f, prm, levels, G1=None, level_alpha=()):
 
     def solve(fl, p, lv, depth, x0):
         # lv: levels left (2 = this level's coarse solve is a convolution)
+        sixth = depth == 0 and rhs_order == 6
+        if sixth:
+            from .stencils import sixth_order_rhs
+            if p.Q != 6:
+                raise ValueError("the sixth-order right-hand side is that of the 27-point operator (Q = 6)")
+            fl = sixth_order_rhs(fl)
         if lv == 2:
-            phi, out = mlc_solve(fl, p, G1, keep=True)
+            phi, out = mlc_solve(fl, p, G1, keep=True, correct=not sixth)
             trail[depth + 1] = (out["phiH"], x0 + out["O_lo"] * p.H, p.H, None)
         else:
             m = level_box_margin(p, deeper=lv > 3)
@@ -541,9 +552,21 @@ def mlc_solve_multilevel(f, prm, levels, G1=None, level_alpha=()):
                 o, w = O_lo + m, O_hi - O_lo + 1
                 return out1["phitilde"][o:o + w, o:o + w, o:o + w].copy()
 
-            phi, out = mlc_solve(fl, p, G1, keep=True, coarse_fn=coarse)
+            phi, out = mlc_solve(fl, p, G1, keep=True, coarse_fn=coarse, correct=not sixth)
         trail[depth] = (out["phitilde"], x0, p.hh, fl)
         return phi, out
 
     phi, _ = solve(f, prm, levels, 0, 0.0)
     return phi, [trail[k] for k in sorted(trail)]
+
+
+def mlc_solve_sixth(f, prm, G1=None, **kw):
+    """Sixth-order variant for the 27-point operator (sec. 2 eq. msCorr; the
+    paper specialises its algorithm to fourth order for the simple final
+    correction and notes the higher-order form): the method applied to the
+    modified right-hand side f~ = stencils.sixth_order_rhs(f), with no final
+    correction.  f must vanish within two nodes of the domain's faces."""
+    from .stencils import sixth_order_rhs
+    if prm.Q != 6:
+        raise ValueError("the sixth-order right-hand side is that of the 27-point operator (Q = 6)")
+    return mlc_solve(sixth_order_rhs(f), prm, G1, correct=False, **kw)

@@ -66,3 +66,50 @@ def symbol(Q, c0, c1, c2):
     return (b[0] + 2.0 * b[1] * (c0 + c1 + c2)
             + 4.0 * b[2] * (c0 * c1 + c0 * c2 + c1 * c2)
             + 8.0 * b[3] * c0 * c1 * c2)
+
+
+def _shift(u, d, k):
+    """u[g + k e_d] with zeros beyond the array (f extended by zero)."""
+    out = np.zeros_like(u)
+    n = u.shape[d]
+    src = [slice(None)] * 3
+    dst = [slice(None)] * 3
+    if k >= 0:
+        src[d] = slice(k, n)
+        dst[d] = slice(0, n - k)
+    else:
+        src[d] = slice(0, n + k)
+        dst[d] = slice(-k, n)
+    out[tuple(dst)] = u[tuple(src)]
+    return out
+
+
+def sixth_order_rhs(f):
+    """The modified right-hand side of sec. 2 eq. msCorr for the 27-point
+    operator (q = 6), with the h^4 operator read off its truncation error in
+    appendix A.1:
+        f~ = f + C2 h^2 (Delta f)_4 + (h^4 / 360) (Delta^2 + 2 (d_xxyy + d_yyzz + d_zzxx)) f,
+    (Delta f)_4 the fourth-order central differences along each axis, the h^4
+    term second-order differences (d_dd d_ee f as products of second
+    differences).  Then Delta^h phi = f~ + O(h^6), so G^h * f~ is sixth-order
+    accurate with no final correction.  Every difference is in units of h (the
+    result does not depend on h).  f is extended by zero past the array; it
+    must vanish within two nodes of the array's faces so that f~ vanishes on
+    them."""
+    f = np.asarray(f, dtype=np.float64)
+    for d in range(3):
+        for k in (0, 1, 2, -1, -2, -3):
+            if np.any(np.take(f, k, axis=d) != 0.0):
+                raise ValueError("f must vanish within two nodes of the faces")
+    return sixth_order_rhs_stencil(f)
+
+
+def sixth_order_rhs_stencil(f):
+    """The differences of sixth_order_rhs on every node, f extended by zero
+    (exact at the nodes two or more from the array's faces for any f)."""
+    d2 = [_shift(f, d, 1) - 2.0 * f + _shift(f, d, -1) for d in range(3)]
+    lap4 = sum((-_shift(f, d, 2) + 16.0 * _shift(f, d, 1) - 30.0 * f + 16.0 * _shift(f, d, -1) - _shift(f, d, -2))
+               / 12.0 for d in range(3))
+    quart = sum(_shift(d2[d], d, 1) - 2.0 * d2[d] + _shift(d2[d], d, -1) for d in range(3))
+    mixed = sum(_shift(d2[d], e, 1) - 2.0 * d2[d] + _shift(d2[d], e, -1) for d in range(3) for e in range(d + 1, 3))
+    return f + C2 * lap4 + (quart + 4.0 * mixed) / 360.0

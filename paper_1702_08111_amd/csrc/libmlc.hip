@@ -80,6 +80,7 @@ struct mlc_plan {
   mlc_plan* child = nullptr;    // multilevel: the plan of the next coarser level
   bool correct = true;          // add the final Mehrstellen correction (false at coarser levels)
   size_t o_lf = 0, o_lphi = 0, o_lws = 0;   // multilevel: the next level's charge, solution, workspace
+  size_t o_ft = 0;                          // sixth-order right-hand side
   MfmaGeom mg_skel{}, mg_coarse{};
   // workspace offsets of the plan's own (batch-of-one) layout
   size_t o_mom = 0, o_cs = 0, o_pl = 0, o_F = 0, o_phiH = 0, o_phiB = 0;
@@ -283,6 +284,7 @@ static mlc_problem child_problem(const mlc_plan_info& I) {
   c.level_alpha[0] = I.level_alpha[1];
   c.level_alpha[1] = I.level_alpha[2];
   c.level_alpha[2] = 0.0;
+  c.rhs_order = 0;   // the coarser levels solve their node charge as it is
   const int e = margin_of(c.alpha, I.n) + NREF * I.b;
   c.fft_size = (I.M >= 2 * (I.n + e) + 1 && conv_size_ok(I.conv_precision, I.n, I.M)) ? I.M : 0;
   return c;
@@ -320,6 +322,9 @@ static mlc_status derive(const mlc_problem* p, mlc_plan_info* o, std::string* wh
   if (I.P > PMAX) { *why = "P above 9 is not built"; return MLC_ERR_UNSUPPORTED; }
   if (I.n > 32) { *why = "patch size above 32 is not built"; return MLC_ERR_UNSUPPORTED; }
   if (I.Z != 32 && I.Z != 64 && I.Z != 128) { *why = "DGF half-width must be 32, 64 or 128"; return MLC_ERR_UNSUPPORTED; }
+  if (p->rhs_order != 0 && p->rhs_order != 4 && p->rhs_order != 6) { *why = "rhs_order must be 0, 4 or 6"; return MLC_ERR_INVALID_ARG; }
+  if (p->rhs_order == 6 && I.Q != 6) { *why = "rhs_order 6 is the 27-point operator's (Q = 6)"; return MLC_ERR_UNSUPPORTED; }
+  I.rhs_order = p->rhs_order == 6 ? 6 : 4;
   I.K = I.P * (I.P + 1) * (I.P + 2) / 6;
   I.alpha = p->alpha;
   I.beta = p->beta;
@@ -755,6 +760,7 @@ struct Layout {
   size_t o_dsum = 0;   // per skeleton thread: the sum of the plane corrections
   std::vector<size_t> o_F, o_tor, o_phiH, o_phiB, o_cpad;
   std::vector<size_t> o_lf, o_lphi, o_lws;   // multilevel problems: the next level's charge, solution, workspace
+  std::vector<size_t> o_ft;                  // sixth-order problems: the modified right-hand side
   std::vector<int> patch0;
   int total = 0, chunk = 0;
   size_t bytes = 0;
@@ -838,6 +844,9 @@ static Layout layout_of(const std::vector<const mlc_plan_info*>& g) {
     }
     L.o_cpad[k] = take(bytes);
   }
+  L.o_ft.assign(np, 0);
+  for (int k = 0; k < np; ++k)
+    if (g[k]->rhs_order == 6) L.o_ft[k] = take(sizeof(double) * cube(g[k]->N + 1));
   L.o_lf.assign(np, 0); L.o_lphi.assign(np, 0); L.o_lws.assign(np, 0);
   for (int k = 0; k < np; ++k) {
     if (g[k]->levels <= 2) continue;
@@ -1025,6 +1034,7 @@ static mlc_status plan_create_impl(mlc_context* ctx, const mlc_problem* prob, bo
     P->o_lf = L.o_lf[0];
     P->o_lphi = L.o_lphi[0];
     P->o_lws = L.o_lws[0];
+    P->o_ft = L.o_ft[0];
     P->ws_total = L.bytes;
   }
   if (!mlc_budget_take(ctx, P->table_bytes)) {
@@ -1148,6 +1158,11 @@ extern "C" mlc_status mlc_workspace_view(const mlc_plan* plan, void* ws, int32_t
       at = which == MLC_VIEW_LEVEL_CHARGE ? plan->o_lf : (which == MLC_VIEW_LEVEL_PHI ? plan->o_lphi : plan->o_lws);
       len = which == MLC_VIEW_LEVEL_WORKSPACE ? plan->child->ws_total : sizeof(double) * cube(I.level_N + 1);
       break;
+    case MLC_VIEW_CHARGE:
+      if (I.rhs_order != 6) return fail(plan->ctx, MLC_ERR_INVALID_ARG, "only a sixth-order plan keeps its charge");
+      at = plan->o_ft;
+      len = sizeof(double) * cube(I.N + 1);
+      break;
     default: return fail(plan->ctx, MLC_ERR_INVALID_ARG, "unknown workspace view");
   }
   *ptr = b + at;
@@ -1210,6 +1225,26 @@ static void upload_flat(D* dst, const std::vector<D>& v, hipStream_t s) {
   }
 }
 
+// The charge the method solves for member k: f, or for a sixth-order problem
+// the modified right-hand side in the workspace (written by launch_sixth_rhs).
+static const double* charge_of(const Group& G, int k) {
+  if (G.plans[k]->info.rhs_order == 6) return reinterpret_cast<const double*>(G.ws + G.L.o_ft[k]);
+  return G.f[k];
+}
+// C2 h^2 of the final correction (sec. 4.1): none at the coarser levels of a
+// multilevel solve, none for the sixth-order right-hand side
+static double final_c2h2(const mlc_plan& P) {
+  return (P.correct && P.info.rhs_order != 6) ? P.info.h * P.info.h / 12.0 : 0.0;
+}
+static void launch_sixth_rhs(const Group& G, hipStream_t s) {
+  for (size_t k = 0; k < G.plans.size(); ++k) {
+    const mlc_plan_info& I = G.plans[k]->info;
+    if (I.rhs_order != 6) continue;
+    hipLaunchKernelGGL(sixth_rhs_kernel, dim3(blocks_for(cube(I.N + 1))), dim3(256), 0, s, G.f[k], I.N,
+                       const_cast<double*>(charge_of(G, int(k))));
+  }
+}
+
 static void upload_descs(const Group& G, hipStream_t s) {
   const int np = int(G.plans.size());
   for (int k0 = 0; k0 < np; k0 += DESC_PACK) {
@@ -1219,7 +1254,7 @@ static void upload_descs(const Group& G, hipStream_t s) {
       const int k = k0 + j;
       const mlc_plan_info& I = G.plans[k]->info;
       ProbDesc& d = pk.d[j];
-      d.f = G.f[k];
+      d.f = charge_of(G, k);
       d.phi = G.phi[k];
       d.phiB = reinterpret_cast<double*>(G.ws + G.L.o_phiB[k]);
       d.N = I.N;
@@ -1227,7 +1262,7 @@ static void upload_descs(const Group& G, hipStream_t s) {
       d.patch0 = G.L.patch0[k];
       d.h2 = I.h * I.h;
       d.R15 = std::pow(I.n * I.h / 2.0, 1.5);
-      d.c2h2 = G.plans[k]->correct ? I.h * I.h / 12.0 : 0.0;
+      d.c2h2 = final_c2h2(*G.plans[k]);
     }
     hipLaunchKernelGGL(desc_upload_kernel, dim3(1), dim3(DESC_PACK), 0, s, G.desc + k0, pk);
   }
@@ -1529,8 +1564,8 @@ static mlc_status launch_rest(const Group& G, hipStream_t s, Stage stage) {
       const mlc_plan* P = G.plans[k];
       const mlc_plan_info& I = P->info;
       SkelGeom sg{I.N, I.n, I.patches_per_axis, P->Kann, I.d_alpha, I.d_beta, I.b, I.Wa, P->P0, I.nplanes_a, P->Wb,
-                  P->P0b, P->nplb, I.O_lo, I.No, P->correct ? I.h * I.h / 12.0 : 0.0};
-      v[k] = SkelProb<T>{phiH_of(k), pl + L.patch0[k] * plsz, G.f[k], phiB_of(k), G.phi[k], sg, total};
+                  P->P0b, P->nplb, I.O_lo, I.No, final_c2h2(*P)};
+      v[k] = SkelProb<T>{phiH_of(k), pl + L.patch0[k] * plsz, charge_of(G, k), phiB_of(k), G.phi[k], sg, total};
       total += int64_t(3) * (I.N / I.n + 1) * (I.N + 1) * (I.N + 1);
     }
     if (stage == PLANES) {
@@ -1646,6 +1681,7 @@ static mlc_status enqueue_group(const Group& G, hipStream_t s, const AnalyticInp
     const bool f32 = I0.conv_precision == MLC_CONV_FP32;
     upload_descs(G, s);
     if (an) launch_analytic_fill(G, s, *an);
+    launch_sixth_rhs(G, s);
     if (!(f32 ? dispatch_conv<float>(G, s, 0) : dispatch_conv<double>(G, s, 0)))
       return fail(P0->ctx, MLC_ERR_UNSUPPORTED, "local FFT size not built");
     if (an) launch_gauss_moments(G, s, *an);
@@ -1665,6 +1701,7 @@ static mlc_status enqueue_group(const Group& G, hipStream_t s, const AnalyticInp
   const bool fp32 = I0.conv_precision == MLC_CONV_FP32;
   upload_descs(G, s);
   if (an) launch_analytic_fill(G, s, *an);
+  launch_sixth_rhs(G, s);
   // the x-DFT pass of the local convolutions also leaves the per-plane
   // moment sums, finished here before the far-field sums read the moments
   const bool ok = fp32 ? dispatch_conv<float>(G, s, 0) : dispatch_conv<double>(G, s, 0);
@@ -1714,7 +1751,7 @@ static bool check_enabled() {
 // The flag lives with the caller stream's side-stream state, so callers on
 // different streams (a server thread and the caller's own thread) never
 // share one.
-static mlc_status check_boundary(mlc_context* ctx, const double* f, int N, hipStream_t s) {
+static mlc_status check_boundary(mlc_context* ctx, const double* f, int N, int layers, hipStream_t s) {
   mlc_context::Side* sd = side_of(ctx, s);
   if (!sd) return fail(ctx, MLC_ERR_DEVICE, "could not create the side stream");
   int* flag = nullptr;
@@ -1724,23 +1761,29 @@ static mlc_status check_boundary(mlc_context* ctx, const double* f, int N, hipSt
     flag = sd->check_flag;
   }
   if (!flag) return fail(ctx, MLC_ERR_OUT_OF_MEMORY, "check flag allocation failed");
-  const int64_t faces = int64_t(6) * (N + 1) * (N + 1);
+  const int64_t faces = int64_t(6) * layers * (N + 1) * (N + 1);
   hipLaunchKernelGGL(set_flag_kernel, dim3(1), dim3(1), 0, s, flag, 0);
-  hipLaunchKernelGGL(boundary_check_kernel, dim3(blocks_for(faces)), dim3(256), 0, s, f, N, flag);
+  hipLaunchKernelGGL(boundary_check_kernel, dim3(blocks_for(faces)), dim3(256), 0, s, f, N, layers, flag);
   int h = 0;
   hipError_t e = hipMemcpyAsync(&h, flag, sizeof(int), hipMemcpyDeviceToHost, s);
   if (e == hipSuccess) e = hipStreamSynchronize(s);
   if (e != hipSuccess) return fail(ctx, MLC_ERR_DEVICE, std::string("boundary check: ") + hipGetErrorString(e));
-  if (h) return fail(ctx, MLC_ERR_INVALID_ARG, "f is nonzero on the outer boundary (MLC_CHECK)");
+  if (h)
+    return fail(ctx, MLC_ERR_INVALID_ARG,
+                layers > 1 ? "f is nonzero within two nodes of the outer boundary (MLC_CHECK, rhs_order 6)"
+                           : "f is nonzero on the outer boundary (MLC_CHECK)");
   return MLC_OK;
 }
 
 // for the serving loop (server.hip): whether MLC_CHECK is on, and the check
 // of one request's charge on the server's launch stream
 bool mlc_check_enabled() { return check_enabled(); }
-mlc_status mlc_check_charge(mlc_context* ctx, const double* f, int N, void* stream) {
+// layers of the outer faces a charge must vanish on: one, three for the
+// sixth-order right-hand side
+int mlc_check_layers(const mlc_plan_info& I) { return I.rhs_order == 6 ? 3 : 1; }
+mlc_status mlc_check_charge(mlc_context* ctx, const double* f, int N, int layers, void* stream) {
   HIP_TRY(ctx, hipSetDevice(ctx->device));
-  return check_boundary(ctx, f, N, static_cast<hipStream_t>(stream));
+  return check_boundary(ctx, f, N, layers, static_cast<hipStream_t>(stream));
 }
 
 extern "C" mlc_status mlc_solve(mlc_plan* plan, const double* f, double* phi, void* workspace, size_t ws_bytes,
@@ -1757,7 +1800,8 @@ extern "C" mlc_status mlc_solve(mlc_plan* plan, const double* f, double* phi, vo
   G.L = layout_of(infos_of(G.plans));
   if (ws_bytes < G.L.bytes) return fail(plan->ctx, MLC_ERR_INVALID_ARG, "workspace too small");
   if (check_enabled()) {
-    const mlc_status cs = check_boundary(plan->ctx, f, plan->info.N, static_cast<hipStream_t>(stream));
+    const mlc_status cs =
+        check_boundary(plan->ctx, f, plan->info.N, mlc_check_layers(plan->info), static_cast<hipStream_t>(stream));
     if (cs != MLC_OK) return cs;
   }
   G.ws = static_cast<char*>(workspace);
@@ -1794,6 +1838,8 @@ extern "C" mlc_status mlc_solve_analytic(mlc_plan* plan, int32_t nterms, const m
   if (nterms < 1 || nterms > MLC_MAX_RADIAL_TERMS)
     return fail(ctx, MLC_ERR_INVALID_ARG, "nterms must be in [1, MLC_MAX_RADIAL_TERMS]");
   if (gauss_points < 1 || gauss_points > 4) return fail(ctx, MLC_ERR_INVALID_ARG, "gauss_points must be in [1, 4]");
+  if (plan->info.rhs_order == 6)
+    return fail(ctx, MLC_ERR_UNSUPPORTED, "the Gauss moments are those of f, not of the sixth-order right-hand side");
   if (ws_bytes < plan->ws_total) return fail(ctx, MLC_ERR_INVALID_ARG, "workspace too small");
   if (reinterpret_cast<uintptr_t>(workspace) % 256)
     return fail(ctx, MLC_ERR_INVALID_ARG, "workspace must be 256-byte aligned");
@@ -1901,7 +1947,7 @@ extern "C" mlc_status mlc_solve_batched(int32_t count, mlc_plan* const* plans, c
   HIP_TRY(ctx, hipSetDevice(ctx->device));
   if (check_enabled()) {
     for (int k = 0; k < count; ++k) {
-      st = check_boundary(ctx, f[k], plans[k]->info.N, static_cast<hipStream_t>(stream));
+      st = check_boundary(ctx, f[k], plans[k]->info.N, mlc_check_layers(plans[k]->info), static_cast<hipStream_t>(stream));
       if (st != MLC_OK) return st;
     }
   }

@@ -190,21 +190,52 @@ __global__ void __launch_bounds__(256) coarse_rhs_kernel(const CoarseRhsProb<T>*
   F[idx] += s;   // F starts at zero; the far-field sums may add first
 }
 
-// The optional input check: flag = 1 if f is nonzero at any node of the six
-// outer faces of the (N+1)^3 node box.
+// The optional input check: flag = 1 if f is nonzero at any node within
+// `layers` node layers of the six outer faces of the (N+1)^3 node box.
 __global__ void set_flag_kernel(int* __restrict__ flag, int v) { *flag = v; }
-__global__ void boundary_check_kernel(const double* __restrict__ f, int N, int* __restrict__ flag) {
+__global__ void boundary_check_kernel(const double* __restrict__ f, int N, int layers, int* __restrict__ flag) {
   const int64_t Np = N + 1;
   const int64_t idx = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-  if (idx >= 6 * Np * Np) return;
-  const int face = int(idx / (Np * Np));
+  if (idx >= 6 * layers * Np * Np) return;
+  const int face = int(idx / (layers * Np * Np));
+  const int layer = int((idx / (Np * Np)) % layers);
   const int64_t a = (idx / Np) % Np, b = idx % Np;
-  const int64_t e = (face & 1) ? N : 0;
+  const int64_t e = (face & 1) ? N - layer : layer;
   int64_t g0, g1, g2;
   if (face < 2) { g0 = e; g1 = a; g2 = b; }
   else if (face < 4) { g0 = a; g1 = e; g2 = b; }
   else { g0 = a; g1 = b; g2 = e; }
   if (f[(g0 * Np + g1) * Np + g2] != 0.0) *flag = 1;
+}
+
+// The modified right-hand side of the sixth-order variant for the 27-point
+// operator (sec. 2 eq. msCorr; the h^4 operator is the one in that
+// operator's truncation error, appendix A.1):
+//   f~ = f + (1/12) sum_d (-f[+-2 e_d] + 16 f[+-1 e_d] - 30 f) / 12
+//          + (1/360) (sum_d (f[+-2 e_d] - 4 f[+-1 e_d] + 6 f) + 4 sum_{d<e} dd_d dd_e f),
+// dd the second difference (h = 1 units; the result does not depend on h).
+// Collected per offset class: centre 1 - 90/144 + (18 + 48)/360 = 67/120;
+// axis +-1: 16/144 + (-4 - 2 * 2 * 4)/360 = 1/18; axis +-2: -1/144 + 1/360 =
+// -1/240; in-plane diagonals (+-1, +-1, 0): 4/360 = 1/90; the sum is 1.
+// f is taken as zero past the node box.  One thread per node.
+__global__ void sixth_rhs_kernel(const double* __restrict__ f, int N, double* __restrict__ ft) {
+  const int64_t Np = N + 1;
+  const int64_t idx = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (idx >= Np * Np * Np) return;
+  const int g2 = int(idx % Np), g1 = int((idx / Np) % Np), g0 = int(idx / (Np * Np));
+  auto at = [&](int a, int b, int c) -> double {
+    if (a < 0 || a > N || b < 0 || b > N || c < 0 || c > N) return 0.0;
+    return f[(int64_t(a) * Np + b) * Np + c];
+  };
+  const double ax1 = at(g0 - 1, g1, g2) + at(g0 + 1, g1, g2) + at(g0, g1 - 1, g2) + at(g0, g1 + 1, g2) +
+                     at(g0, g1, g2 - 1) + at(g0, g1, g2 + 1);
+  const double ax2 = at(g0 - 2, g1, g2) + at(g0 + 2, g1, g2) + at(g0, g1 - 2, g2) + at(g0, g1 + 2, g2) +
+                     at(g0, g1, g2 - 2) + at(g0, g1, g2 + 2);
+  double dg = 0.0;
+  for (int s = -1; s <= 1; s += 2)
+    for (int t = -1; t <= 1; t += 2)
+      dg += at(g0 + s, g1 + t, g2) + at(g0 + s, g1, g2 + t) + at(g0, g1 + s, g2 + t);
+  ft[idx] = (67.0 / 120.0) * at(g0, g1, g2) + (1.0 / 18.0) * ax1 - (1.0 / 240.0) * ax2 + (1.0 / 90.0) * dg;
 }
 
 __global__ void fill_zero_kernel(double* __restrict__ p, int64_t count) {

@@ -32,6 +32,7 @@ MLC_VIEW_LOCAL_PLANES = 5
 MLC_VIEW_LEVEL_CHARGE = 6
 MLC_VIEW_LEVEL_PHI = 7
 MLC_VIEW_LEVEL_WORKSPACE = 8
+MLC_VIEW_CHARGE = 9
 
 
 class mlc_problem(ctypes.Structure):
@@ -49,6 +50,7 @@ class mlc_problem(ctypes.Structure):
         ("dgf_half_width", ctypes.c_int32),
         ("levels", ctypes.c_int32),
         ("level_alpha", ctypes.c_double * 3),
+        ("rhs_order", ctypes.c_int32),
     ]
 
 
@@ -70,7 +72,8 @@ class mlc_plan_info(ctypes.Structure):
         "conv_precision")] + [("h", ctypes.c_double), ("H", ctypes.c_double), ("out_planes", ctypes.c_int32),
                               ("levels", ctypes.c_int32), ("level_margin", ctypes.c_int32),
                               ("level_N", ctypes.c_int32), ("alpha", ctypes.c_double),
-                              ("beta", ctypes.c_double), ("level_alpha", ctypes.c_double * 3)]
+                              ("beta", ctypes.c_double), ("level_alpha", ctypes.c_double * 3),
+                              ("rhs_order", ctypes.c_int32)]
 
     def as_dict(self):
         d = {k: getattr(self, k) for k, _ in self._fields_}
@@ -186,11 +189,11 @@ def _stream(s):
 
 
 def problem(N, n, alpha=3.0, beta=6.0, P=4, Q=4, b=0, h=None, conv="fp32", fft_size=0, Z=0, levels=0,
-            level_alpha=()):
+            level_alpha=(), rhs_order=0):
     la = list(level_alpha) + [0.0] * (3 - len(level_alpha))
     return mlc_problem(N, (1.0 / N) if h is None else h, n, alpha, beta, P, Q, b,
                        MLC_CONV_FP32 if conv == "fp32" else MLC_CONV_FP64, fft_size, Z, levels,
-                       (ctypes.c_double * 3)(*la[:3]))
+                       (ctypes.c_double * 3)(*la[:3]), rhs_order)
 
 
 def problem_workspace_bytes(prob):

@@ -52,6 +52,11 @@ def test_derived_sizes(name, N, n, Q, fft, expect):
     (dict(N=32, n=8, alpha=1.5, beta=1.5), mlc.MLC_ERR_UNSUPPORTED),   # margin 2 not a multiple of 4
     (dict(N=32, n=8, fft_size=40), mlc.MLC_ERR_INVALID_ARG),           # below 2(n+e)+1
     (dict(N=32, n=8, Z=100), mlc.MLC_ERR_UNSUPPORTED),
+    (dict(N=32, n=8, rhs_order=5), mlc.MLC_ERR_INVALID_ARG),
+    (dict(N=32, n=8, Q=4, rhs_order=6), mlc.MLC_ERR_UNSUPPORTED),      # the 27-point operator's
+    (dict(N=64, n=8, levels=3, level_alpha=(3.5,)), mlc.MLC_ERR_UNSUPPORTED),  # level-1 margin 10
+    (dict(N=64, n=8, levels=3, level_alpha=(0.5,)), mlc.MLC_ERR_INVALID_ARG),    # below 1
+    (dict(N=64, n=8, alpha=2.0, beta=3.0, levels=3, level_alpha=(4.0,)), mlc.MLC_ERR_INVALID_ARG),  # above beta
 ])
 def test_validation(kw, status):
     args = dict(N=32, n=8, alpha=3.0, beta=6.0, P=4, Q=4)
@@ -138,3 +143,13 @@ def test_autotuned_workspace_bounds_every_candidate(N, n, Q, conv):
             pass
     assert len(sizes) >= 2
     assert tuned == max(sizes)
+
+
+def test_sixth_order_sizes():
+    """rhs_order 6 adds the modified right-hand side, (N+1)^3 doubles, to the
+    workspace and nothing else; the info reports the order."""
+    base = mlc.problem(32, 8, 3.0, 6.0, 4, 6, conv="fp64", Z=64)
+    six = mlc.problem(32, 8, 3.0, 6.0, 4, 6, conv="fp64", Z=64, rhs_order=6)
+    assert mlc.problem_info(base)["rhs_order"] == 4 and mlc.problem_info(six)["rhs_order"] == 6
+    extra = mlc.problem_workspace_bytes(six) - mlc.problem_workspace_bytes(base)
+    assert 33 ** 3 * 8 <= extra < 33 ** 3 * 8 + 512
