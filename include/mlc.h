@@ -29,6 +29,11 @@
  *    mlc_solve and mlc_solve_batched also check on the device that each f
  *    vanishes on the outer boundary nodes (MLC_ERR_INVALID_ARG otherwise);
  *    that check synchronises the caller's stream.
+ *  - With MLC_TRACE=<file> in the environment, each mlc_solve and
+ *    mlc_solve_batched call appends one JSON line to <file>: its status,
+ *    wall time, problems, and per stage timer the launches and device
+ *    milliseconds, at every level of a multilevel plan ("L1." prefixes the
+ *    next coarser level).  A traced call synchronises the caller's stream.
  *  - A context is used from one host thread at a time; plans are immutable
  *    after creation and may be used by several solves in sequence.
  */

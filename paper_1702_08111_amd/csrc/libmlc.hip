@@ -5,6 +5,7 @@
 
 #include <algorithm>
 #include <atomic>
+#include <chrono>
 #include <cmath>
 #include <cstdio>
 #include <cstdlib>
@@ -1786,6 +1787,99 @@ mlc_status mlc_check_charge(mlc_context* ctx, const double* f, int N, int layers
   return check_boundary(ctx, f, N, layers, static_cast<hipStream_t>(stream));
 }
 
+// ----------------------------------------------------------------- trace
+// MLC_TRACE=<file>: every mlc_solve and mlc_solve_batched call appends one
+// JSON line to the file: the problems, the call's status and wall time, and
+// per stage timer its launches and device milliseconds, at every level of a
+// multilevel plan ("L1." prefixes the next coarser level).  A traced call
+// waits for its stream before it returns: tracing is for diagnosis, not for
+// timing runs.
+static const char* trace_path() {
+  const char* e = std::getenv("MLC_TRACE");
+  return (e && *e) ? e : nullptr;
+}
+struct Trace {
+  struct Entry {
+    mlc_plan* plan;
+    int depth;
+    bool was_on;
+    std::vector<std::pair<std::string, std::pair<int, double>>> before;
+  };
+  std::vector<Entry> e;
+  std::vector<const mlc_plan*> roots;
+  std::chrono::steady_clock::time_point t0;
+};
+static std::mutex g_trace_mu;
+
+static void trace_begin(Trace* T, mlc_plan* const* plans, int count) {
+  T->t0 = std::chrono::steady_clock::now();
+  for (int k = 0; k < count; ++k) {
+    T->roots.push_back(plans[k]);
+    int depth = 0;
+    for (mlc_plan* q = plans[k]; q; q = q->child, ++depth) {
+      bool seen = false;
+      for (auto& x : T->e) seen = seen || x.plan == q;
+      if (seen) continue;
+      drain_timing(q);
+      T->e.push_back({q, depth, q->timing_on, q->acc});
+      q->timing_on = true;
+    }
+  }
+}
+
+static void trace_end(Trace* T, const char* entry, hipStream_t s, mlc_status st) {
+  const hipError_t se = hipStreamSynchronize(s);
+  const double wall = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - T->t0).count();
+  std::map<std::string, std::pair<int, double>> stages;
+  for (auto& x : T->e) {
+    drain_timing(x.plan);
+    const std::string pre = x.depth ? "L" + std::to_string(x.depth) + "." : "";
+    for (auto& kv : x.plan->acc) {
+      int l = kv.second.first;
+      double ms = kv.second.second;
+      for (auto& b : x.before)
+        if (b.first == kv.first) { l -= b.second.first; ms -= b.second.second; }
+      if (l > 0) {
+        auto& d = stages[pre + kv.first];
+        d.first += l;
+        d.second += ms;
+      }
+    }
+    if (!x.was_on) {
+      x.plan->acc = x.before;
+      x.plan->timing_on = false;
+    }
+  }
+  std::string line = std::string("{\"entry\": \"") + entry + "\", \"status\": \"" + mlc_status_string(st) + "\"";
+  if (se != hipSuccess) line += std::string(", \"stream_error\": \"") + hipGetErrorString(se) + "\"";
+  char buf[256];
+  std::snprintf(buf, sizeof(buf), ", \"wall_ms\": %.4f, \"problems\": [", wall);
+  line += buf;
+  for (size_t k = 0; k < T->roots.size(); ++k) {
+    const mlc_plan_info& I = T->roots[k]->info;
+    std::snprintf(buf, sizeof(buf),
+                  "%s{\"N\": %d, \"n\": %d, \"alpha\": %g, \"beta\": %g, \"P\": %d, \"Q\": %d, \"levels\": %d, "
+                  "\"conv\": \"%s\", \"rhs_order\": %d}",
+                  k ? ", " : "", I.N, I.n, I.alpha, I.beta, I.P, I.Q, I.levels,
+                  I.conv_precision == MLC_CONV_FP32 ? "fp32" : "fp64", I.rhs_order);
+    line += buf;
+  }
+  line += "], \"stages\": {";
+  bool first = true;
+  for (auto& kv : stages) {
+    std::snprintf(buf, sizeof(buf), "%s\"%s\": [%d, %.5f]", first ? "" : ", ", kv.first.c_str(), kv.second.first,
+                  kv.second.second);
+    line += buf;
+    first = false;
+  }
+  line += "}}\n";
+  std::lock_guard<std::mutex> lk(g_trace_mu);
+  if (FILE* fp = std::fopen(trace_path(), "a")) {
+    std::fputs(line.c_str(), fp);
+    std::fclose(fp);
+  }
+}
+
 extern "C" mlc_status mlc_solve(mlc_plan* plan, const double* f, double* phi, void* workspace, size_t ws_bytes,
                                 void* stream) {
   if (!plan || !f || !phi || !workspace) return fail(plan ? plan->ctx : nullptr, MLC_ERR_INVALID_ARG, "null argument");
@@ -1806,7 +1900,12 @@ extern "C" mlc_status mlc_solve(mlc_plan* plan, const double* f, double* phi, vo
   }
   G.ws = static_cast<char*>(workspace);
   G.desc = reinterpret_cast<ProbDesc*>(G.ws + G.L.o_desc);
-  return enqueue_group(G, static_cast<hipStream_t>(stream));
+  if (!trace_path()) return enqueue_group(G, static_cast<hipStream_t>(stream));
+  Trace T;
+  trace_begin(&T, &plan, 1);
+  const mlc_status st = enqueue_group(G, static_cast<hipStream_t>(stream));
+  trace_end(&T, "mlc_solve", static_cast<hipStream_t>(stream), st);
+  return st;
 }
 
 // Gauss-Legendre nodes and weights on [-1, 1], gp = 1..4
@@ -1960,11 +2059,15 @@ extern "C" mlc_status mlc_solve_batched(int32_t count, mlc_plan* const* plans, c
     G.ws = base + G.off;
     G.desc = reinterpret_cast<ProbDesc*>(G.ws + G.L.o_desc);
   }
+  Trace T;
+  const bool traced = trace_path() != nullptr;
+  if (traced) trace_begin(&T, plans, count);
   for (auto& G : groups) {
     st = enqueue_group(G, static_cast<hipStream_t>(stream));
-    if (st != MLC_OK) return st;
+    if (st != MLC_OK) break;
   }
-  return MLC_OK;
+  if (traced) trace_end(&T, "mlc_solve_batched", static_cast<hipStream_t>(stream), st);
+  return st;
 }
 
 // ---------------------------------------------------------- batch graphs

@@ -8,7 +8,9 @@ import ctypes
 import os
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_HERE, "libmlc.so")
+# MLC_LIBRARY names another build of the same library (e.g. the
+# host-sanitized libmlc_san.so for the CPU-side ABI checks)
+LIB_PATH = os.environ.get("MLC_LIBRARY") or os.path.join(_HERE, "libmlc.so")
 
 MLC_OK = 0
 MLC_ERR_INVALID_ARG = -1
@@ -144,7 +146,7 @@ def lib():
     global _lib
     if _lib is None:
         if not os.path.exists(LIB_PATH):
-            raise RuntimeError("libmlc.so is not built (run __graft_entry__.build())")
+            raise RuntimeError(f"{LIB_PATH} is not built (run __graft_entry__.build())")
         L = ctypes.CDLL(LIB_PATH)
         for name, (res, args) in _SIGS.items():
             fn = getattr(L, name)
