@@ -139,14 +139,18 @@ template <typename T, int M> struct Batch {
 template <typename T, int M, bool MULTI = true> struct OutBatch {
   static constexpr bool F32 = sizeof(T) == 4;
   // (12-wave single-plane blocks, which fit three waves per SIMD, measured
-  // slower: 128^3 output pass 0.58 -> 0.94 ms)
+  // slower: 128^3 output pass 0.58 -> 0.94 ms; 6-wave fp64 blocks too:
+  // 256^3 fp64 output pass 6.0 -> 12.9 ms per solve)
   static constexpr int NT = F32 ? 512 : 256;
   static constexpr int LW = 64 / Split<M>::R1;
   static constexpr int CB = (NT / 64) * LW;   // exchange lines of the block
-  // fp64: the output rows of a plane split over two blocks, each keeping its
-  // half of the (kx, y) plane in LDS (room for the exchange slices; each
-  // block repeats the plane's y FFTs)
-  static constexpr int YSPL = F32 ? 1 : 2;
+  // fp64: a plane's (kx, y) half-spectrum does not fit in LDS beside the
+  // exchange slices, so its wavenumbers split over two blocks, each keeping
+  // its kx rows: every block reads its part of the plane's spectra once and
+  // transforms the x lines with the other part taken as zero, and the two
+  // partial outputs are added into zeroed buffers with float64 atomics (two
+  // terms added onto zero give the same sum in either order)
+  static constexpr int KSPL = F32 ? 1 : 2;
 };
 
 // z planes per output block when no tuned value is given: the next plane's
@@ -360,10 +364,10 @@ __global__ void __launch_bounds__((OutBatch<T, M, MULTI>::NT)) conv_out_kernel(c
   // fp32: A rows padded to a stride of 11 (mod 32) elements, so the lines
   // of one wave step start on spread-out LDS banks (fp64: no room to pad)
   constexpr bool PADA = sizeof(T) == 4;
-  constexpr int YSPL = OutBatch<T, M>::YSPL;
-  constexpr int WHMAX = (WPMAX + YSPL - 1) / YSPL;
-  constexpr int WQMAX = PADA ? WHMAX + ((11 - WHMAX % 32) + 32) % 32 : WHMAX;
-  __shared__ cplx<T> A[Mh * WQMAX];
+  constexpr int KSPL = OutBatch<T, M>::KSPL;
+  constexpr int KXH = (Mh + KSPL - 1) / KSPL;   // wavenumbers per block
+  constexpr int WQMAX = PADA ? WPMAX + ((11 - WPMAX % 32) + 32) % 32 : WPMAX;
+  __shared__ cplx<T> A[KXH * WQMAX];
   __shared__ cplx<T> Ex[CB * XL];
   __shared__ cplx<T> tw[M];
   __shared__ short omap[M];
@@ -383,11 +387,11 @@ __global__ void __launch_bounds__((OutBatch<T, M, MULTI>::NT)) conv_out_kernel(c
   constexpr int WXS = M / 2 + 1;   // row stride: the four rows on distinct LDS banks
   __shared__ cplx<T> Wx[NPLMAX * WXS];
   const int zpb = MULTI ? zpb_arg : 1;
-  const int zi0 = (blockIdx.x / YSPL) * zpb, pc = blockIdx.y, p = p0 + pc;
+  const int zi0 = (blockIdx.x / KSPL) * zpb, pc = blockIdx.y, p = p0 + pc;
   const int Wp = g.Wp;
-  // this block's output rows [ylo, yhi) of each plane
-  const int Wh = (Wp + YSPL - 1) / YSPL, ylo = int(blockIdx.x % YSPL) * Wh, yhi = min(Wp, ylo + Wh);
-  const int Wq = PADA ? Wh + ((11 - Wh % 32) + 32) % 32 : Wh;   // row stride of A
+  // this block's wavenumbers [kx_lo, kx_hi) (all of them in fp32)
+  const int kx_lo = int(blockIdx.x % KSPL) * KXH, kx_hi = min(Mh, kx_lo + KXH);
+  const int Wq = PADA ? Wp + ((11 - Wp % 32) + 32) % 32 : Wp;   // row stride of A
   const int tid = threadIdx.x;
   // h^2 in the kernel's precision (for the fp32 kernel: one rounding of h^2,
   // none when h is a power of two)
@@ -404,9 +408,14 @@ __global__ void __launch_bounds__((OutBatch<T, M, MULTI>::NT)) conv_out_kernel(c
     const int kx = kb + r1;
 #pragma unroll
     for (int k2 = 0; k2 < R2; ++k2)
-      dst[k2] = (act1 && kx < Mh) ? zin[int64_t(kx) * M + s1 + R1 * k2] : cplx<T>{T(0), T(0)};
+      dst[k2] = (act1 && kx < kx_hi) ? zin[int64_t(kx) * M + s1 + R1 * k2] : cplx<T>{T(0), T(0)};
   };
-  load_lines(u0, wave * LW);
+  // an output value: stored, or (wavenumbers split) added to the zeroed buffer
+  auto put = [&](T* dst, T v) {
+    if constexpr (KSPL > 1) unsafeAtomicAdd(dst, v);
+    else *dst = v;
+  };
+  load_lines(u0, kx_lo + wave * LW);
   fill_twiddles(tw, M);
   for (int m = tid; m < M; m += blockDim.x) omap[m] = -1;
   for (int i = tid; i < WPMAX; i += blockDim.x) xs_a[i] = xs_c[i] = -1;
@@ -444,9 +453,9 @@ __global__ void __launch_bounds__((OutBatch<T, M, MULTI>::NT)) conv_out_kernel(c
       const int zf = oflg[zi];
       int a = 0, c = 0;
       const uint64_t below = (uint64_t(1) << tid) - 1;
-      for (int base = ylo; base < yhi; base += 64) {
+      for (int base = 0; base < Wp; base += 64) {
         const int yi = base + tid;
-        const int yf = yi < yhi ? oflg[yi] : 0;
+        const int yf = yi < Wp ? oflg[yi] : 0;
         // z-plane rows in Omega_alpha, coarse rows of a coarse z, y-plane rows
         const bool full = ((zf & 4) && (yf & 1)) || ((zf & 2) && (yf & 2)) || ((zf & 1) && (yf & 4));
         const bool col = !full && (zf & 1) && (yf & 1);   // x-plane columns only
@@ -469,8 +478,8 @@ __global__ void __launch_bounds__((OutBatch<T, M, MULTI>::NT)) conv_out_kernel(c
 #pragma unroll
       for (int s = 0; s < R1; ++s) v[s] = ex[r * XL + s * (R2 + 1) + t];
       dft_reg<T, R1, -1>(v);
-      if (kx < Mh) {
-        cplx<T>* arow = A + kx * Wq;
+      if (kx < kx_hi) {
+        cplx<T>* arow = A + (kx - kx_lo) * Wq;
 #pragma unroll
         for (int j1 = 0; j1 < R1; ++j1)
           if (ymap[j1] >= 0) arow[ymap[j1]] = v[j1];
@@ -496,11 +505,10 @@ __global__ void __launch_bounds__((OutBatch<T, M, MULTI>::NT)) conv_out_kernel(c
       short ymap[R1];
 #pragma unroll
       for (int j1 = 0; j1 < R1; ++j1) {
-        const int k = omap[t2 + R2 * j1];
-        ymap[j1] = (k >= ylo && k < yhi) ? short(k - ylo) : short(-1);
+        ymap[j1] = omap[t2 + R2 * j1];
       }
 #pragma unroll 1
-      for (int kb = wave * LW; kb < Mh; kb += NW * LW) {
+      for (int kb = kx_lo + wave * LW; kb < kx_hi; kb += NW * LW) {
         cplx<T> un[R2];
         load_lines(un, kb + NW * LW);   // next step's lines in flight meanwhile
         if (act1) y_pass1(u0, ex, s1, r1);
@@ -514,7 +522,7 @@ __global__ void __launch_bounds__((OutBatch<T, M, MULTI>::NT)) conv_out_kernel(c
     // the next plane's first lines stay in flight through this plane's x pass
     if (q + 1 < zpb && zi + 1 < Wp) {
       zin += int64_t(Mh) * M;
-      load_lines(u0, wave * LW);
+      load_lines(u0, kx_lo + wave * LW);
     }
     __syncthreads();
     const int z = ocrd[zi];
@@ -533,12 +541,14 @@ __global__ void __launch_bounds__((OutBatch<T, M, MULTI>::NT)) conv_out_kernel(c
       for (int k2 = 0; k2 < R2; ++k2) {
         int k = s + R1 * k2;
         cplx<T> h1 = {T(0), T(0)}, h2 = {T(0), T(0)};
-        if (k < Mh) {
-          if (y1 < Wp) h1 = A[k * Wq + (y1 - ylo)];
-          if (y2 < Wp) h2 = A[k * Wq + (y2 - ylo)];
-        } else {
-          if (y1 < Wp) h1 = conjw(A[(M - k) * Wq + (y1 - ylo)]);
-          if (y2 < Wp) h2 = conjw(A[(M - k) * Wq + (y2 - ylo)]);
+        // the line's half-spectrum entry (mirrored and conjugated above M/2),
+        // zero for wavenumbers of the other block
+        const bool lo = k < Mh;
+        const int kk = lo ? k : M - k;
+        if (kk >= kx_lo && kk < kx_hi) {
+          const cplx<T>* ar = A + (kk - kx_lo) * Wq;
+          if (y1 < Wp) h1 = lo ? ar[y1] : conjw(ar[y1]);
+          if (y2 < Wp) h2 = lo ? ar[y2] : conjw(ar[y2]);
         }
         if (k == 0 || k == M / 2) { h1.y = T(0); h2.y = T(0); }   // real DC / Nyquist
         u[k2] = {h1.x - h2.y, h1.y + h2.x};                        // h1 + i h2
@@ -606,16 +616,16 @@ __global__ void __launch_bounds__((OutBatch<T, M, MULTI>::NT)) conv_out_kernel(c
           for (int a = 0; a < NXC; ++a) {
             if (mA[a] < 0) continue;
             const T val = line[2 * mA[a]] * hsq;
-            if (rowZ >= 0) pbase[rowZ + lane + 64 * a] = val;
-            if (rowY >= 0) pbase[rowY + lane + 64 * a] = val;
+            if (rowZ >= 0) put(pbase + rowZ + lane + 64 * a, val);
+            if (rowY >= 0) put(pbase + rowY + lane + 64 * a, val);
           }
         }
         if (rowC >= 0) {
 #pragma unroll
           for (int a = 0; a < NXC; ++a)
-            if (mC[a] >= 0) cbase[rowC + lane + 64 * a] = line[2 * mC[a]] * hsq;
+            if (mC[a] >= 0) put(cbase + rowC + lane + 64 * a, line[2 * mC[a]] * hsq);
         }
-        if (rowX >= 0 && mP >= 0) pbase[rowX + lane * Wa2] = line[2 * mP] * hsq;
+        if (rowX >= 0 && mP >= 0) put(pbase + rowX + lane * Wa2, line[2 * mP] * hsq);
       }
       wave_sync();
     }
@@ -625,29 +635,33 @@ __global__ void __launch_bounds__((OutBatch<T, M, MULTI>::NT)) conv_out_kernel(c
       const int yi = crow[q / npl], j = q % npl;
       const int x = g.P0 + j * n, xs = x < 0 ? x + M : x;
       const cplx<T>* wj = Wx + j * WXS;
-      // four interleaved partial sums over k = 1 .. M/2 - 1
-      constexpr int KT = M / 2 - 1;
+      // four interleaved partial sums over the block's k in 1 .. M/2 - 1
+      const int k_first = max(1, kx_lo), k_last = min(M / 2 - 1, kx_hi - 1);
+      auto ay = [&](int k) { return A[(k - kx_lo) * Wq + yi]; };   // the entry of wavenumber k
       T acc[4] = {T(0), T(0), T(0), T(0)};
+      int k0 = k_first;
 #pragma unroll 2
-      for (int k0 = 1; k0 + 3 <= KT; k0 += 4) {
+      for (; k0 + 3 <= k_last; k0 += 4) {
 #pragma unroll
         for (int u = 0; u < 4; ++u) {
-          const cplx<T> a = A[(k0 + u) * Wq + (yi - ylo)];
+          const cplx<T> a = ay(k0 + u);
           const cplx<T> w = wj[k0 + u];
           acc[u] += a.x * w.x + a.y * w.y;
         }
       }
 #pragma unroll
-      for (int u = 0; u < KT % 4; ++u) {
-        const int k = KT - KT % 4 + 1 + u;
-        const cplx<T> a = A[k * Wq + (yi - ylo)];
-        const cplx<T> w = wj[k];
-        acc[u] += a.x * w.x + a.y * w.y;
+      for (int u = 0; u < 3; ++u) {
+        if (k0 + u <= k_last) {
+          const cplx<T> a = ay(k0 + u);
+          const cplx<T> w = wj[k0 + u];
+          acc[u] += a.x * w.x + a.y * w.y;
+        }
       }
-      const T dc = A[yi - ylo].x, ny = A[(M / 2) * Wq + (yi - ylo)].x;
+      const T dc = kx_lo == 0 ? ay(0).x : T(0);
+      const T ny = (M / 2 >= kx_lo && M / 2 < kx_hi) ? ay(M / 2).x : T(0);
       const T val = dc + ((xs & 1) ? -ny : ny) + T(2) * ((acc[0] + acc[1]) + (acc[2] + acc[3]));
       const int y = ocrd[yi];
-      pbase[((int64_t(2) * npl + j) * Wa + (z + g.da)) * Wa + (y + g.da)] = val * hsq;
+      put(pbase + ((int64_t(2) * npl + j) * Wa + (z + g.da)) * Wa + (y + g.da), val * hsq);
     }
     __syncthreads();   // A, Ex and the row lists are rewritten for the next plane
   }

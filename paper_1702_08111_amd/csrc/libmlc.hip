@@ -1303,8 +1303,15 @@ static void launch_conv(const Group& G, hipStream_t s, int phase, const std::fun
     {
       TimedScope ts(P, s, "conv_out");
       const int zpb = I.out_planes;
-      constexpr int yspl = OutBatch<T, M>::YSPL;
-      const dim3 grid((P->Wp + zpb - 1) / zpb * yspl, cnt);
+      constexpr int kspl = OutBatch<T, M>::KSPL;
+      if (kspl > 1) {
+        // the blocks of a plane add their partial outputs: start from zero
+        const int64_t nc = cube(I.Wc), npl = int64_t(3) * I.nplanes_a * I.Wa * I.Wa;
+        hipLaunchKernelGGL(fill_zero_t_kernel<T>, dim3(blocks_for(nc * cnt)), dim3(256), 0, s, cs + p0 * nc, nc * cnt);
+        hipLaunchKernelGGL(fill_zero_t_kernel<T>, dim3(blocks_for(npl * cnt)), dim3(256), 0, s, pl + p0 * npl,
+                           npl * cnt);
+      }
+      const dim3 grid((P->Wp + zpb - 1) / zpb * kspl, cnt);
       if (zpb == 1)
         hipLaunchKernelGGL((conv_out_kernel<T, n, M, false>), grid, dim3(OutBatch<T, M, false>::NT), 0, s, Zb, cs, pl, g,
                            G.desc, np, p0, 1);

@@ -238,6 +238,12 @@ __global__ void sixth_rhs_kernel(const double* __restrict__ f, int N, double* __
   ft[idx] = (67.0 / 120.0) * at(g0, g1, g2) + (1.0 / 18.0) * ax1 - (1.0 / 240.0) * ax2 + (1.0 / 90.0) * dg;
 }
 
+template <typename T>
+__global__ void fill_zero_t_kernel(T* __restrict__ p, int64_t count) {
+  const int64_t idx = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (idx < count) p[idx] = T(0);
+}
+
 __global__ void fill_zero_kernel(double* __restrict__ p, int64_t count) {
   const int64_t idx = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
   if (idx < count) p[idx] = 0.0;
