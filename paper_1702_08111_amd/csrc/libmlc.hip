@@ -1544,7 +1544,10 @@ static mlc_status launch_rest(const Group& G, hipStream_t s, Stage stage) {
       G1.L = layout_of({&C->info});
       G1.ws = G.ws + L.o_lws[k];
       G1.desc = reinterpret_cast<ProbDesc*>(G1.ws + G1.L.o_desc);
-      G1.one_stream = G.one_stream;
+      // the coarser level's stages in order on this stream, with no side
+      // stream of its own: a solve never creates a stream or an event after
+      // its first call on a caller stream (graph capture forbids it)
+      G1.one_stream = true;
       const mlc_status st1 = enqueue_group(G1, s);
       if (st1 != MLC_OK) return st1;
       hipLaunchKernelGGL(box_copy_kernel, dim3(blocks_for(cube(I.No))), dim3(256), 0, s, phi1, E, I.O_lo + m,
