@@ -70,6 +70,9 @@ def _case(name):
         "mlc0_32_q6": (32, 8, 3.0, 3.0, 4, 6, 0, 64, mi.bumps(2, 22, radius=(0.1, 0.25))),
         "narrow_beta_q6": (32, 8, 2.0, 3.0, 4, 6, 0, 64, mi.bumps(2, 23, radius=(0.1, 0.25))),
         "mlc0_64_n16": (64, 16, 2.0, 2.0, 4, 6, 0, 64, mi.bumps(2, 24, radius=(0.1, 0.2))),
+        # the smallest inner radius: Omega_alpha is the patch itself (d_alpha = 0)
+        "alpha1_32": (32, 8, 1.0, 3.0, 4, 4, 0, 64, mi.bumps(2, 25, radius=(0.1, 0.25))),
+        "mlc0_alpha1_32": (32, 8, 1.0, 1.0, 4, 6, 0, 64, mi.bumps(2, 26, radius=(0.1, 0.25))),
     }
     return cases[name]
 
@@ -106,7 +109,7 @@ def _check_all(name, conv):
 
 @pytest.mark.parametrize("name", ["plain32", "plain32_q6", "mlc0_32", "p1_32", "ragged48", "single16", "p2_32",
                                   "p3_32", "b1_32", "b4_32", "n32_64", "p5_32", "p6_32_q6", "p9_32", "t7_64",
-                                  "mlc0_32_q6", "narrow_beta_q6", "mlc0_64_n16"])
+                                  "mlc0_32_q6", "narrow_beta_q6", "mlc0_64_n16", "alpha1_32", "mlc0_alpha1_32"])
 def test_fp64_parity(name):
     errs = _check_all(name, "fp64")
     for k, v in errs.items():
