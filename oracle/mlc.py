@@ -500,7 +500,7 @@ def level_box_margin(prm, deeper=False):
     return m
 
 
-def mlc_solve_multilevel(f, prm, levels, G1=None, level_alpha=(), rhs_order=4):
+def mlc_solve_multilevel(f, prm, levels, G1=None, level_alpha=(), rhs_order=4, moments_fn=None):
     """Multilevel MLC (sec. 5) with `levels` levels (2 = the two-level method):
     the two-level steps at the finest level, with the coarse convolution
     replaced by the same method applied one level up to the coarse charge F^H
@@ -512,7 +512,9 @@ def mlc_solve_multilevel(f, prm, levels, G1=None, level_alpha=(), rhs_order=4):
     to bound the error of the truncated Legendre expansions there).
     rhs_order=6 solves the sixth-order right-hand side of the 27-point
     operator at the finest level instead (see mlc_solve_sixth): the coarser
-    levels are unchanged.  Every level takes its boundary
+    levels are unchanged.  moments_fn, if given, supplies the finest level's
+    Legendre coefficients as in mlc_solve (the coarser levels take theirs
+    from their node charges by Boole's rule).  Every level takes its boundary
     values from the uncorrected discrete solution (phi-tilde) of the level
     below it (sec. 5 eq. mlcmultilevel); the Mehrstellen correction is added
     at the finest level.  Returns phi and, from the finest level down, the
@@ -535,8 +537,9 @@ def mlc_solve_multilevel(f, prm, levels, G1=None, level_alpha=(), rhs_order=4):
             if p.Q != 6:
                 raise ValueError("the sixth-order right-hand side is that of the 27-point operator (Q = 6)")
             fl = sixth_order_rhs(fl)
+        mfn = moments_fn if depth == 0 else None
         if lv == 2:
-            phi, out = mlc_solve(fl, p, G1, keep=True, correct=not sixth)
+            phi, out = mlc_solve(fl, p, G1, keep=True, correct=not sixth, moments_fn=mfn)
             trail[depth + 1] = (out["phiH"], x0 + out["O_lo"] * p.H, p.H, None)
         else:
             m = level_box_margin(p, deeper=lv > 3)
@@ -552,7 +555,7 @@ def mlc_solve_multilevel(f, prm, levels, G1=None, level_alpha=(), rhs_order=4):
                 o, w = O_lo + m, O_hi - O_lo + 1
                 return out1["phitilde"][o:o + w, o:o + w, o:o + w].copy()
 
-            phi, out = mlc_solve(fl, p, G1, keep=True, coarse_fn=coarse, correct=not sixth)
+            phi, out = mlc_solve(fl, p, G1, keep=True, coarse_fn=coarse, correct=not sixth, moments_fn=mfn)
         trail[depth] = (out["phitilde"], x0, p.hh, fl)
         return phi, out
 

@@ -98,3 +98,34 @@ def test_analytic_refuses_a_charge_on_the_boundary():
         plan.solve_analytic([((0.1, 0.5, 0.5), 0.2, 1.0, 0.0, gm.MLC_PROFILE_BUMP)], 4, f, phi, ws)
     assert ei.value.status == gm.MLC_ERR_INVALID_ARG
     plan.close()
+
+
+def test_analytic_multilevel_parity():
+    """A charge given analytically on a three-level plan: the finest level's
+    coefficients by Gauss integration, the coarser level from its node
+    charge; against the oracle's multilevel solve with the same Gauss
+    coefficients at the finest level."""
+    import torch
+    N, n, Q, Z, g = 64, 8, 6, 64, 3
+    terms = mi.smooth_terms()
+    plan = context().plan(gm.problem(N, n, 3.0, 6.0, 4, Q, conv="fp64", Z=Z, levels=3))
+    f = torch.full(((N + 1),) * 3, float("nan"), dtype=torch.float64, device="cuda")
+    phi = torch.empty_like(f)
+    ws = torch.empty(plan.workspace_bytes, dtype=torch.uint8, device="cuda")
+    plan.solve_analytic(terms, g, f, phi, ws)
+    torch.cuda.synchronize()
+    got = phi.cpu().numpy()
+    plan.close()
+    prm = omlc.Params(N=N, n=n, alpha=3.0, beta=6.0, P=4, Q=Q, Z=Z)
+    h, R = prm.hh, prm.R
+
+    def gauss(i):
+        corner = n * np.asarray(i) * h
+        return leg.moments_gauss(lambda a, b, c: mi.radial_charge_at(a, b, c, terms), corner, n, h, prm.P, R, g)
+
+    with scipy.fft.set_workers(len(os.sched_getaffinity(0))):
+        ref, _ = omlc.mlc_solve_multilevel(mi.radial_charge_nodes(N, terms), prm, 3, dgf_cached(Q, Z),
+                                           moments_fn=gauss)
+    e = rel(got, ref)
+    print(f"analytic charge, three levels: {e:.2e}", flush=True)
+    assert e < 1e-12
