@@ -105,6 +105,12 @@ typedef struct {
                              (MLC_CHECK then checks the three outer node layers); the
                              workspace holds f~, (N+1)^3 doubles more;
                              mlc_solve_analytic refuses it                           */
+  int32_t skip_empty;     /* 1: patches whose node charge (all (n+1)^3 nodes of the closed
+                             patch) is zero skip their local convolutions, found on the
+                             device at every solve; their local fields and moments are
+                             zero, so the result is the same as with 0 (the method only
+                             needs patches over the support of f, sec. 1).  0: every
+                             patch is convolved                                      */
 } mlc_problem;
 
 /* Sizes derived from an mlc_problem (all counts per axis unless noted). */
@@ -129,6 +135,7 @@ typedef struct {
   double alpha, beta;                /* localisation radii of this level                 */
   double level_alpha[3];             /* alpha at 1, 2, 3 levels above (resolved: no 0)  */
   int32_t rhs_order;                 /* 4 or 6 (mlc_problem.rhs_order, 0 -> 4)           */
+  int32_t skip_empty;                /* mlc_problem.skip_empty                           */
 } mlc_plan_info;
 
 typedef struct mlc_context mlc_context;

@@ -79,7 +79,8 @@ struct ProbDesc {
   const double* f;
   double* phi;
   double* phiB;
-  int N, ppa, patch0, pad;
+  int N, ppa, patch0;
+  int skip;     // 1: patches whose node charge is all zero skip their local convolutions
   double h2;    // h^2
   double R15;   // (n h / 2)^{3/2}, the Legendre basis scale
   double c2h2;  // C2 h^2 of the final correction, 0 for a coarser level of the multilevel method

@@ -26,7 +26,7 @@ namespace mlc {
 template <typename T, int M>
 __global__ void __launch_bounds__(256) conv_xdft_kernel(const ProbDesc* __restrict__ pd, int nprob, int n, int P,
                                                         cplx<T>* __restrict__ X, double* __restrict__ mpart,
-                                                        int p0) {
+                                                        const int* __restrict__ live, int p0) {
   constexpr int Mh = M / 2 + 1;
   __shared__ T q[SMAX * SMAX];
   __shared__ cplx<T> tw[M];
@@ -35,6 +35,11 @@ __global__ void __launch_bounds__(256) conv_xdft_kernel(const ProbDesc* __restri
   __shared__ double gx[PMAX][SMAX];    // x-contracted moment sums per row
   const int S = n + 1;
   const int p = p0 + blockIdx.y, sz = blockIdx.x;
+  if (live && !live[p]) {
+    // an empty patch: zero moment sums; its x-DFT is never read
+    if (int(threadIdx.x) < P * P) mpart[(int64_t(p) * (n + 1) + sz) * (P * P) + threadIdx.x] = 0.0;
+    return;
+  }
   const ProbDesc& D = pd[find_problem(pd, nprob, p)];
   const auto* f = gbl(D.f);
   const int ppa = D.ppa, pl = p - D.patch0;
@@ -174,7 +179,7 @@ __device__ __forceinline__ cplx<T> conjw(cplx<T> w) { return {w.x, -w.y}; }
 template <typename T, int n, int M>
 __global__ void __launch_bounds__(256) conv_yz_kernel(const cplx<T>* __restrict__ X, const T* __restrict__ spec,
                                                       cplx<T>* __restrict__ Zb, int Wp, int b, int Wa, int e, int da,
-                                                      int p0) {
+                                                      const int* __restrict__ live, int p0) {
   constexpr int Mh = M / 2 + 1;
   constexpr int S = n + 1;
   constexpr int R1 = Split<M>::R1, R2 = Split<M>::R2;
@@ -191,6 +196,7 @@ __global__ void __launch_bounds__(256) conv_yz_kernel(const cplx<T>* __restrict_
   // (mod 8) and holds fewer spectrum slices in its L2, measured slower:
   // 2.20 -> 2.38 ms at 256^3)
   const int kx = blockIdx.x, pc = blockIdx.y, p = p0 + pc;
+  if (live && !live[p]) return;   // an empty patch: its spectra are never read
   const int tid = threadIdx.x;
   fill_twiddles(tw, M);
   for (int m = tid; m < M; m += blockDim.x) zmap[m] = -1;
@@ -356,7 +362,8 @@ __global__ void __launch_bounds__((OutBatch<T, M, MULTI>::NT)) conv_out_kernel(c
                                                                       T* __restrict__ coarse,
                                                                       T* __restrict__ planes, OutGeom g,
                                                                       const ProbDesc* __restrict__ pd, int nprob,
-                                                                      int p0, int zpb_arg) {
+                                                                      const int* __restrict__ live, int p0,
+                                                                      int zpb_arg) {
   constexpr int Mh = M / 2 + 1;
   constexpr int R1 = Split<M>::R1, R2 = Split<M>::R2;
   constexpr int CB = OutBatch<T, M, MULTI>::CB, XL = Batch<T, M>::XLYZ;
@@ -389,6 +396,17 @@ __global__ void __launch_bounds__((OutBatch<T, M, MULTI>::NT)) conv_out_kernel(c
   const int zpb = MULTI ? zpb_arg : 1;
   const int zi0 = (blockIdx.x / KSPL) * zpb, pc = blockIdx.y, p = p0 + pc;
   const int Wp = g.Wp;
+  if (live && !live[p]) {
+    // an empty patch: its local field is zero (the first block writes the
+    // zeros; split blocks add into buffers already zeroed)
+    if (KSPL == 1 && blockIdx.x == 0) {
+      T* cz = coarse + int64_t(p) * g.Wc * g.Wc * g.Wc;
+      T* pz = planes + int64_t(p) * 3 * g.npl * g.Wa * g.Wa;
+      for (int i = threadIdx.x; i < g.Wc * g.Wc * g.Wc; i += blockDim.x) cz[i] = T(0);
+      for (int i = threadIdx.x; i < 3 * g.npl * g.Wa * g.Wa; i += blockDim.x) pz[i] = T(0);
+    }
+    return;
+  }
   // this block's wavenumbers [kx_lo, kx_hi) (all of them in fp32)
   const int kx_lo = int(blockIdx.x % KSPL) * KXH, kx_hi = min(Mh, kx_lo + KXH);
   const int Wq = PADA ? Wp + ((11 - Wp % 32) + 32) % 32 : Wp;   // row stride of A

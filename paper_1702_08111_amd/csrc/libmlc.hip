@@ -286,6 +286,7 @@ static mlc_problem child_problem(const mlc_plan_info& I) {
   c.level_alpha[1] = I.level_alpha[2];
   c.level_alpha[2] = 0.0;
   c.rhs_order = 0;   // the coarser levels solve their node charge as it is
+  c.skip_empty = I.skip_empty;
   const int e = margin_of(c.alpha, I.n) + NREF * I.b;
   c.fft_size = (I.M >= 2 * (I.n + e) + 1 && conv_size_ok(I.conv_precision, I.n, I.M)) ? I.M : 0;
   return c;
@@ -326,6 +327,8 @@ static mlc_status derive(const mlc_problem* p, mlc_plan_info* o, std::string* wh
   if (p->rhs_order != 0 && p->rhs_order != 4 && p->rhs_order != 6) { *why = "rhs_order must be 0, 4 or 6"; return MLC_ERR_INVALID_ARG; }
   if (p->rhs_order == 6 && I.Q != 6) { *why = "rhs_order 6 is the 27-point operator's (Q = 6)"; return MLC_ERR_UNSUPPORTED; }
   I.rhs_order = p->rhs_order == 6 ? 6 : 4;
+  if (p->skip_empty != 0 && p->skip_empty != 1) { *why = "skip_empty must be 0 or 1"; return MLC_ERR_INVALID_ARG; }
+  I.skip_empty = p->skip_empty;
   I.K = I.P * (I.P + 1) * (I.P + 2) / 6;
   I.alpha = p->alpha;
   I.beta = p->beta;
@@ -762,6 +765,8 @@ struct Layout {
   std::vector<size_t> o_F, o_tor, o_phiH, o_phiB, o_cpad;
   std::vector<size_t> o_lf, o_lphi, o_lws;   // multilevel problems: the next level's charge, solution, workspace
   std::vector<size_t> o_ft;                  // sixth-order problems: the modified right-hand side
+  size_t o_live = 0;                         // per patch: 1 unless skipped as empty (int)
+  bool any_skip = false;                     // some problem skips empty patches
   std::vector<int> patch0;
   int total = 0, chunk = 0;
   size_t bytes = 0;
@@ -796,6 +801,8 @@ static Layout layout_of(const std::vector<const mlc_plan_info*>& g) {
   L.o_ann = take(2 * sizeof(AnnProb) * np);   // far-field descriptors: skeleton, coarse
   // coarse right-hand side and skeleton descriptors
   L.o_flat = take((sizeof(CoarseRhsProb<double>) + sizeof(SkelProb<double>)) * np);
+  L.o_live = take(sizeof(int) * T);
+  for (int k = 0; k < np; ++k) L.any_skip = L.any_skip || g[k]->skip_empty;
   L.o_mom = take(sizeof(double) * T * I.K);
   L.o_mpart = take(sizeof(double) * T * S * I.P * I.P);
   L.o_mraw = take(I.P >= 5 ? sizeof(double) * T * I.K : 0);
@@ -1264,6 +1271,7 @@ static void upload_descs(const Group& G, hipStream_t s) {
       d.h2 = I.h * I.h;
       d.R15 = std::pow(I.n * I.h / 2.0, 1.5);
       d.c2h2 = final_c2h2(*G.plans[k]);
+      d.skip = I.skip_empty;
     }
     hipLaunchKernelGGL(desc_upload_kernel, dim3(1), dim3(DESC_PACK), 0, s, G.desc + k0, pk);
   }
@@ -1282,11 +1290,17 @@ static void launch_conv(const Group& G, hipStream_t s, int phase, const std::fun
   cplx<T>* Zb = reinterpret_cast<cplx<T>*>(G.ws + L.o_Z);
   T* cs = reinterpret_cast<T*>(G.ws + L.o_cs);
   T* pl = reinterpret_cast<T*>(G.ws + L.o_pl);
+  // which patches carry charge (only when some problem skips empty ones)
+  int* live = L.any_skip ? reinterpret_cast<int*>(G.ws + L.o_live) : nullptr;
   if (phase == 0) {
+    if (live) {
+      TimedScope ts(P, s, "patch_live");
+      hipLaunchKernelGGL(patch_live_kernel, dim3(L.total), dim3(256), 0, s, G.desc, np, I.n, live, 0);
+    }
     TimedScope ts(P, s, "conv_xdft");
     for (int p0 = 0; p0 < L.total; p0 += kMaxGridY)
       hipLaunchKernelGGL((conv_xdft_kernel<T, M>), dim3(P->S, std::min(kMaxGridY, L.total - p0)), dim3(256), 0, s,
-                         G.desc, np, I.n, I.P, X, reinterpret_cast<double*>(G.ws + L.o_mpart), p0);
+                         G.desc, np, I.n, I.P, X, reinterpret_cast<double*>(G.ws + L.o_mpart), live, p0);
   }
   if (phase == 0) return;
   OutGeom g{I.n, I.e, I.d_alpha, I.b, I.Wa, P->Wp, I.Wc, P->P0, I.nplanes_a};
@@ -1297,7 +1311,7 @@ static void launch_conv(const Group& G, hipStream_t s, int phase, const std::fun
     {
       TimedScope ts(P, s, "conv_yz");
       hipLaunchKernelGGL((conv_yz_kernel<T, n, M>), dim3(P->Mh, cnt), dim3(256), 0, s, X,
-                         static_cast<const T*>(P->conv_spec), Zb, P->Wp, I.b, I.Wa, I.e, I.d_alpha, p0);
+                         static_cast<const T*>(P->conv_spec), Zb, P->Wp, I.b, I.Wa, I.e, I.d_alpha, live, p0);
     }
     if (p0 == 0 && after_yz) (*after_yz)();
     {
@@ -1314,10 +1328,10 @@ static void launch_conv(const Group& G, hipStream_t s, int phase, const std::fun
       const dim3 grid((P->Wp + zpb - 1) / zpb * kspl, cnt);
       if (zpb == 1)
         hipLaunchKernelGGL((conv_out_kernel<T, n, M, false>), grid, dim3(OutBatch<T, M, false>::NT), 0, s, Zb, cs, pl, g,
-                           G.desc, np, p0, 1);
+                           G.desc, np, live, p0, 1);
       else
         hipLaunchKernelGGL((conv_out_kernel<T, n, M, true>), grid, dim3(OutBatch<T, M, true>::NT), 0, s, Zb, cs, pl, g,
-                           G.desc, np, p0, zpb);
+                           G.desc, np, live, p0, zpb);
     }
   }
 }

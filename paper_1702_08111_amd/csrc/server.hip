@@ -44,13 +44,14 @@ double ms_between(Clock::time_point a, Clock::time_point b) {
 
 // A plan serves exactly one problem description.
 using PlanKey = std::tuple<int, double, int, double, double, int, int, int, int, int, int, int, double, double,
-                           double, int>;
+                           double, int, int>;
 PlanKey plan_key(const mlc_problem& p) {
   // levels and the coarser radii as given: 0 and 2 both mean two levels, and
   // a 0 radius equals the finer level's, so equal problems may still get two
   // plans (never one plan for two different problems)
   return PlanKey{p.n_cells, p.h, p.patch, p.alpha, p.beta, p.P, p.Q, p.interp_b, p.conv_precision, p.fft_size,
-                 p.dgf_half_width, p.levels, p.level_alpha[0], p.level_alpha[1], p.level_alpha[2], p.rhs_order};
+                 p.dgf_half_width, p.levels, p.level_alpha[0], p.level_alpha[1], p.level_alpha[2], p.rhs_order,
+                 p.skip_empty};
 }
 
 // Requests whose patch-level work is identical may share a launch.

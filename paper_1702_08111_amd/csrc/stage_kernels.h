@@ -238,6 +238,34 @@ __global__ void sixth_rhs_kernel(const double* __restrict__ f, int N, double* __
   ft[idx] = (67.0 / 120.0) * at(g0, g1, g2) + (1.0 / 18.0) * ax1 - (1.0 / 240.0) * ax2 + (1.0 / 90.0) * dg;
 }
 
+// live[p] = 1 when patch p's node charge (the (n+1)^3 nodes of its closed
+// box) has a nonzero value or its problem does not skip empty patches; an
+// empty patch has a zero local field and zero moments.  Block per patch.
+__global__ void __launch_bounds__(256) patch_live_kernel(const ProbDesc* __restrict__ pd, int nprob, int n,
+                                                         int* __restrict__ live, int p0) {
+  __shared__ int any;
+  const int p = p0 + blockIdx.x;
+  const ProbDesc& D = pd[find_problem(pd, nprob, p)];
+  if (!D.skip) {
+    if (threadIdx.x == 0) live[p] = 1;
+    return;
+  }
+  if (threadIdx.x == 0) any = 0;
+  __syncthreads();
+  const int pl = p - D.patch0, ppa = D.ppa, S = n + 1;
+  const int i0 = pl / (ppa * ppa), i1 = (pl / ppa) % ppa, i2 = pl % ppa;
+  const int64_t Np = D.N + 1;
+  const double* f = D.f + (int64_t(n) * i0 * Np + int64_t(n) * i1) * Np + int64_t(n) * i2;
+  int mine = 0;
+  for (int t = threadIdx.x; t < S * S * S; t += blockDim.x) {
+    const int a = t / (S * S), b = (t / S) % S, c = t % S;
+    mine |= f[(a * Np + b) * Np + c] != 0.0;
+  }
+  if (mine) any = 1;   // benign race: every writer stores 1
+  __syncthreads();
+  if (threadIdx.x == 0) live[p] = any;
+}
+
 template <typename T>
 __global__ void fill_zero_t_kernel(T* __restrict__ p, int64_t count) {
   const int64_t idx = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;

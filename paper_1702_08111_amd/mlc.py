@@ -53,6 +53,7 @@ class mlc_problem(ctypes.Structure):
         ("levels", ctypes.c_int32),
         ("level_alpha", ctypes.c_double * 3),
         ("rhs_order", ctypes.c_int32),
+        ("skip_empty", ctypes.c_int32),
     ]
 
 
@@ -75,7 +76,7 @@ class mlc_plan_info(ctypes.Structure):
                               ("levels", ctypes.c_int32), ("level_margin", ctypes.c_int32),
                               ("level_N", ctypes.c_int32), ("alpha", ctypes.c_double),
                               ("beta", ctypes.c_double), ("level_alpha", ctypes.c_double * 3),
-                              ("rhs_order", ctypes.c_int32)]
+                              ("rhs_order", ctypes.c_int32), ("skip_empty", ctypes.c_int32)]
 
     def as_dict(self):
         d = {k: getattr(self, k) for k, _ in self._fields_}
@@ -191,11 +192,11 @@ def _stream(s):
 
 
 def problem(N, n, alpha=3.0, beta=6.0, P=4, Q=4, b=0, h=None, conv="fp32", fft_size=0, Z=0, levels=0,
-            level_alpha=(), rhs_order=0):
+            level_alpha=(), rhs_order=0, skip_empty=0):
     la = list(level_alpha) + [0.0] * (3 - len(level_alpha))
     return mlc_problem(N, (1.0 / N) if h is None else h, n, alpha, beta, P, Q, b,
                        MLC_CONV_FP32 if conv == "fp32" else MLC_CONV_FP64, fft_size, Z, levels,
-                       (ctypes.c_double * 3)(*la[:3]), rhs_order)
+                       (ctypes.c_double * 3)(*la[:3]), rhs_order, skip_empty)
 
 
 def problem_workspace_bytes(prob):
