@@ -53,6 +53,7 @@ def test_derived_sizes(name, N, n, Q, fft, expect):
     (dict(N=32, n=8, fft_size=40), mlc.MLC_ERR_INVALID_ARG),           # below 2(n+e)+1
     (dict(N=32, n=8, Z=100), mlc.MLC_ERR_UNSUPPORTED),
     (dict(N=32, n=8, rhs_order=5), mlc.MLC_ERR_INVALID_ARG),
+    (dict(N=32, n=8, skip_empty=2), mlc.MLC_ERR_INVALID_ARG),
     (dict(N=32, n=8, Q=4, rhs_order=6), mlc.MLC_ERR_UNSUPPORTED),      # the 27-point operator's
     (dict(N=64, n=8, levels=3, level_alpha=(3.5,)), mlc.MLC_ERR_UNSUPPORTED),  # level-1 margin 10
     (dict(N=64, n=8, levels=3, level_alpha=(0.5,)), mlc.MLC_ERR_INVALID_ARG),    # below 1
