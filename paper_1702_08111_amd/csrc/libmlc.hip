@@ -1244,6 +1244,10 @@ static const double* charge_of(const Group& G, int k) {
 static double final_c2h2(const mlc_plan& P) {
   return (P.correct && P.info.rhs_order != 6) ? P.info.h * P.info.h / 12.0 : 0.0;
 }
+// per-patch live flags of the group (nullptr when no member skips empty patches)
+static const int* live_of(const Group& G) {
+  return G.L.any_skip ? reinterpret_cast<const int*>(G.ws + G.L.o_live) : nullptr;
+}
 static void launch_sixth_rhs(const Group& G, hipStream_t s) {
   for (size_t k = 0; k < G.plans.size(); ++k) {
     const mlc_plan_info& I = G.plans[k]->info;
@@ -1403,7 +1407,7 @@ static mlc_status launch_rest(const Group& G, hipStream_t s, Stage stage) {
       const size_t lds = 3 * sizeof(T) * size_t(I0.Wc) * I0.Wc;   // <= 26 KB (Wc <= 33)
       for (int p0 = 0; p0 < L.total; p0 += kMaxGridY)
         hipLaunchKernelGGL(coarse_lap_kernel<T>, dim3(Li, std::min(kMaxGridY, L.total - p0)), dim3(256), lds, s, cs, lap,
-                           I0.Wc, I0.b, st, p0);
+                           I0.Wc, I0.b, st, live_of(G), p0);
     }
     TimedScope ts(P0, s, "coarse_rhs");
     hipLaunchKernelGGL(coarse_rhs_kernel<T>, dim3(blocks_for(total)), dim3(256), 0, s, pr, np, total, I0.b);
@@ -1575,7 +1579,7 @@ static mlc_status launch_rest(const Group& G, hipStream_t s, Stage stage) {
     const size_t lds = sizeof(double) * (size_t(I0.Wc) * I0.Wc + size_t(I0.Wc) * I0.Wa);   // <= 35 KB (Wc <= 33, Wa <= 97)
     for (int p0 = 0; p0 < L.total; p0 += kMaxGridY)
       hipLaunchKernelGGL(plane_delta_kernel<T>, dim3(3 * I0.nplanes_a, std::min(kMaxGridY, L.total - p0)), dim3(256),
-                         lds, s, pl, cs, pg, P0->lagw, p0);
+                         lds, s, pl, cs, pg, P0->lagw, live_of(G), p0);
   }
   // skeleton boundary values (+ phi there), every problem in one launch each
   // part: the plane-correction sums right after plane_delta (they need no

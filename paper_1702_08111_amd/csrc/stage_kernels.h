@@ -110,11 +110,17 @@ template <typename T> struct CoarseRhsProb {
 // thread per output point.
 template <typename T>
 __global__ void __launch_bounds__(256) coarse_lap_kernel(const T* __restrict__ cs, double* __restrict__ lap, int Wc,
-                                                         int b, Stencil st, int p0) {
+                                                         int b, Stencil st, const int* __restrict__ live, int p0) {
   extern __shared__ unsigned char lap_lds[];
   T* sm = reinterpret_cast<T*>(lap_lds);
   const int Li = Wc - 2 * b, i0 = blockIdx.x, W2 = Wc * Wc;
   const int64_t p = p0 + int64_t(blockIdx.y);
+  if (live && !live[p]) {
+    // an empty patch: the Laplacian of its zero samples
+    double* dst = lap + (p * Li + i0) * Li * Li;
+    for (int t = threadIdx.x; t < Li * Li; t += blockDim.x) dst[t] = 0.0;
+    return;
+  }
   const T* src = cs + (p * Wc + (b + i0 - 1)) * W2;   // planes r0 - 1 .. r0 + 1 are consecutive
   for (int t = threadIdx.x; t < 3 * W2; t += blockDim.x) sm[t] = src[t];
   __syncthreads();
@@ -322,15 +328,17 @@ struct PlaneGeom { int n, e, da, Wa, Wc, P0, npl, b; };
 // slower one.
 template <typename T>
 __global__ void __launch_bounds__(256) plane_delta_kernel(T* __restrict__ planes, const T* __restrict__ cs,
-                                                          PlaneGeom g, LagW lw, int p0) {
+                                                          PlaneGeom g, LagW lw, const int* __restrict__ live,
+                                                          int p0) {
   // dynamic LDS of (Wc^2 + Wc Wa) doubles: the coarse samples C, then the
   // rows interpolated along the faster axis R
   extern __shared__ double plane_lds[];
   double* C = plane_lds;
   double* R = plane_lds + g.Wc * g.Wc;
   __shared__ double W[4][10];
-  if (threadIdx.x < 40) W[threadIdx.x / 10][threadIdx.x % 10] = lw.w[threadIdx.x / 10][threadIdx.x % 10];
   const int pl = blockIdx.x, p = p0 + blockIdx.y;
+  if (live && !live[p]) return;   // an empty patch: its planes hold zeros, and so do their corrections
+  if (threadIdx.x < 40) W[threadIdx.x / 10][threadIdx.x % 10] = lw.w[threadIdx.x / 10][threadIdx.x % 10];
   const int d = pl / g.npl, j = pl % g.npl;
   const int n = g.n, Wc = g.Wc, Wa = g.Wa, b = g.b, o = g.e / NREF;
   const int cd = (g.P0 + j * n + g.e) / NREF;
