@@ -11,7 +11,9 @@
  * Conventions shared by every call
  *  - Every call returns mlc_status; MLC_OK == 0, errors are negative.  No C++
  *    exception or abort crosses this boundary.
- *  - Grids are cubic: N cells per axis, (N+1)^3 nodes g h, g in [0, N]^3.
+ *  - Grids are cubes of N cells per axis, (N+1)^3 nodes g h, g in [0, N]^3, or
+ *    boxes of B0 x B1 x B2 cells (mlc_problem.box_cells), solved inside their
+ *    enclosing cube.
  *    Node arrays are float64, C order [g0][g1][g2] (g2 fastest), length
  *    (N+1)^3.  f must vanish on the outer boundary nodes (the charge is
  *    supported inside the domain, sec. 4).
@@ -111,6 +113,17 @@ typedef struct {
                              zero, so the result is the same as with 0 (the method only
                              needs patches over the support of f, sec. 1).  0: every
                              patch is convolved                                      */
+  int32_t box_cells[3];   /* a box domain [0, B0] x [0, B1] x [0, B2] (cells per axis, each
+                             a multiple of n; n_cells must then be 0): f and phi are
+                             (B0+1)(B1+1)(B2+1) node arrays, C order, axis 2 fastest.  The
+                             box is solved inside the smallest cube of N >= max B_d cells
+                             that the plan can run (N a multiple of n, of 4n with three
+                             levels, 16n with four), f padded with zeros: the free-space
+                             solution on the box does not depend on the padding (with
+                             skip_empty the empty padding patches cost no convolutions).
+                             All zero: the cube of n_cells.  mlc_solve_analytic refuses
+                             box problems                                            */
+  double origin[3];       /* physical coordinates of node (0,0,0); recorded, not used    */
 } mlc_problem;
 
 /* Sizes derived from an mlc_problem (all counts per axis unless noted). */
@@ -136,6 +149,9 @@ typedef struct {
   double level_alpha[3];             /* alpha at 1, 2, 3 levels above (resolved: no 0)  */
   int32_t rhs_order;                 /* 4 or 6 (mlc_problem.rhs_order, 0 -> 4)           */
   int32_t skip_empty;                /* mlc_problem.skip_empty                           */
+  int32_t box[3];                    /* cells per axis of the problem's domain (N, N, N for
+                                        a cube); N above is the cube it is solved in      */
+  double origin[3];                  /* mlc_problem.origin                               */
 } mlc_plan_info;
 
 typedef struct mlc_context mlc_context;

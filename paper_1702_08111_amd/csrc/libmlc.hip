@@ -286,7 +286,7 @@ static mlc_problem child_problem(const mlc_plan_info& I) {
   c.level_alpha[1] = I.level_alpha[2];
   c.level_alpha[2] = 0.0;
   c.rhs_order = 0;   // the coarser levels solve their node charge as it is
-  c.skip_empty = I.skip_empty;
+  c.skip_empty = I.skip_empty;   // box_cells stay zero: the level box is a cube
   const int e = margin_of(c.alpha, I.n) + NREF * I.b;
   c.fft_size = (I.M >= 2 * (I.n + e) + 1 && conv_size_ok(I.conv_precision, I.n, I.M)) ? I.M : 0;
   return c;
@@ -313,6 +313,22 @@ static mlc_status derive(const mlc_problem* p, mlc_plan_info* o, std::string* wh
   I.Z = p->dgf_half_width ? p->dgf_half_width : 128;
   I.levels = p->levels ? p->levels : 2;
   if (I.levels < 2 || I.levels > 4) { *why = "levels must be 2, 3 or 4"; return MLC_ERR_UNSUPPORTED; }
+  if (p->box_cells[0] || p->box_cells[1] || p->box_cells[2]) {
+    // a box domain, solved in the smallest cube the plan can run
+    if (p->n_cells != 0) { *why = "give n_cells or box_cells, not both"; return MLC_ERR_INVALID_ARG; }
+    if (I.n <= 0) { *why = "N, n and h must be positive"; return MLC_ERR_INVALID_ARG; }
+    int bmax = 0;
+    for (int d = 0; d < 3; ++d) {
+      if (p->box_cells[d] <= 0 || p->box_cells[d] % I.n) { *why = "box_cells must be positive multiples of the patch size"; return MLC_ERR_INVALID_ARG; }
+      I.box[d] = p->box_cells[d];
+      bmax = std::max(bmax, p->box_cells[d]);
+    }
+    const int unit = I.levels > 2 ? NREF * I.n : I.n;
+    I.N = (bmax + unit - 1) / unit * unit;
+  } else {
+    I.box[0] = I.box[1] = I.box[2] = I.N;
+  }
+  for (int d = 0; d < 3; ++d) I.origin[d] = p->origin[d];
   if (I.N <= 0 || I.n <= 0 || !(p->h > 0) || !std::isfinite(p->h)) { *why = "N, n and h must be positive"; return MLC_ERR_INVALID_ARG; }
   if (I.N % I.n) { *why = "N must be a multiple of the patch size"; return MLC_ERR_INVALID_ARG; }
   if (I.n % NREF || I.n < 8) { *why = "patch size must be a multiple of 4 and >= 8"; return MLC_ERR_INVALID_ARG; }
@@ -765,6 +781,7 @@ struct Layout {
   std::vector<size_t> o_F, o_tor, o_phiH, o_phiB, o_cpad;
   std::vector<size_t> o_lf, o_lphi, o_lws;   // multilevel problems: the next level's charge, solution, workspace
   std::vector<size_t> o_ft;                  // sixth-order problems: the modified right-hand side
+  std::vector<size_t> o_fbox, o_pbox;        // box problems: f and phi in the enclosing cube
   size_t o_live = 0;                         // per patch: 1 unless skipped as empty (int)
   bool any_skip = false;                     // some problem skips empty patches
   std::vector<int> patch0;
@@ -783,6 +800,8 @@ static int conv_chunk_override() {
   }();
   return v;
 }
+
+static bool is_boxed(const mlc_plan_info& I) { return I.box[0] != I.N || I.box[1] != I.N || I.box[2] != I.N; }
 
 static Layout layout_of(const std::vector<const mlc_plan_info*>& g) {
   Layout L;
@@ -855,6 +874,13 @@ static Layout layout_of(const std::vector<const mlc_plan_info*>& g) {
   L.o_ft.assign(np, 0);
   for (int k = 0; k < np; ++k)
     if (g[k]->rhs_order == 6) L.o_ft[k] = take(sizeof(double) * cube(g[k]->N + 1));
+  L.o_fbox.assign(np, 0);
+  L.o_pbox.assign(np, 0);
+  for (int k = 0; k < np; ++k)
+    if (is_boxed(*g[k])) {
+      L.o_fbox[k] = take(sizeof(double) * cube(g[k]->N + 1));
+      L.o_pbox[k] = take(sizeof(double) * cube(g[k]->N + 1));
+    }
   L.o_lf.assign(np, 0); L.o_lphi.assign(np, 0); L.o_lws.assign(np, 0);
   for (int k = 0; k < np; ++k) {
     if (g[k]->levels <= 2) continue;
@@ -1235,9 +1261,42 @@ static void upload_flat(D* dst, const std::vector<D>& v, hipStream_t s) {
 
 // The charge the method solves for member k: f, or for a sixth-order problem
 // the modified right-hand side in the workspace (written by launch_sixth_rhs).
+static const double* input_of(const Group& G, int k) {
+  if (is_boxed(G.plans[k]->info)) return reinterpret_cast<const double*>(G.ws + G.L.o_fbox[k]);
+  return G.f[k];
+}
 static const double* charge_of(const Group& G, int k) {
   if (G.plans[k]->info.rhs_order == 6) return reinterpret_cast<const double*>(G.ws + G.L.o_ft[k]);
-  return G.f[k];
+  return input_of(G, k);
+}
+// where the solve writes phi: the caller's array, or for a box problem the
+// enclosing cube's (copied out by launch_box_out)
+static double* phi_of(const Group& G, int k) {
+  if (is_boxed(G.plans[k]->info)) return reinterpret_cast<double*>(G.ws + G.L.o_pbox[k]);
+  return G.phi[k];
+}
+// box problems: f into the zeroed enclosing cube, and phi back out of it
+static void launch_box_in(const Group& G, hipStream_t s) {
+  for (size_t k = 0; k < G.plans.size(); ++k) {
+    const mlc_plan_info& I = G.plans[k]->info;
+    if (!is_boxed(I)) continue;
+    double* fc = const_cast<double*>(input_of(G, int(k)));
+    const int64_t nc = cube(I.N + 1);
+    hipLaunchKernelGGL(fill_zero_kernel, dim3(blocks_for(nc)), dim3(256), 0, s, fc, nc);
+    const int64_t nb = int64_t(I.box[0] + 1) * (I.box[1] + 1) * (I.box[2] + 1);
+    hipLaunchKernelGGL(box3_copy_kernel, dim3(blocks_for(nb)), dim3(256), 0, s, G.f[k], I.box[0] + 1, I.box[1] + 1,
+                       I.box[2] + 1, fc, I.N + 1, I.N + 1, I.N + 1, I.box[0] + 1, I.box[1] + 1, I.box[2] + 1);
+  }
+}
+static void launch_box_out(const Group& G, hipStream_t s) {
+  for (size_t k = 0; k < G.plans.size(); ++k) {
+    const mlc_plan_info& I = G.plans[k]->info;
+    if (!is_boxed(I)) continue;
+    const int64_t nb = int64_t(I.box[0] + 1) * (I.box[1] + 1) * (I.box[2] + 1);
+    hipLaunchKernelGGL(box3_copy_kernel, dim3(blocks_for(nb)), dim3(256), 0, s, phi_of(G, int(k)), I.N + 1, I.N + 1,
+                       I.N + 1, G.phi[k], I.box[0] + 1, I.box[1] + 1, I.box[2] + 1, I.box[0] + 1, I.box[1] + 1,
+                       I.box[2] + 1);
+  }
 }
 // C2 h^2 of the final correction (sec. 4.1): none at the coarser levels of a
 // multilevel solve, none for the sixth-order right-hand side
@@ -1252,7 +1311,7 @@ static void launch_sixth_rhs(const Group& G, hipStream_t s) {
   for (size_t k = 0; k < G.plans.size(); ++k) {
     const mlc_plan_info& I = G.plans[k]->info;
     if (I.rhs_order != 6) continue;
-    hipLaunchKernelGGL(sixth_rhs_kernel, dim3(blocks_for(cube(I.N + 1))), dim3(256), 0, s, G.f[k], I.N,
+    hipLaunchKernelGGL(sixth_rhs_kernel, dim3(blocks_for(cube(I.N + 1))), dim3(256), 0, s, input_of(G, int(k)), I.N,
                        const_cast<double*>(charge_of(G, int(k))));
   }
 }
@@ -1267,7 +1326,7 @@ static void upload_descs(const Group& G, hipStream_t s) {
       const mlc_plan_info& I = G.plans[k]->info;
       ProbDesc& d = pk.d[j];
       d.f = charge_of(G, k);
-      d.phi = G.phi[k];
+      d.phi = phi_of(G, k);
       d.phiB = reinterpret_cast<double*>(G.ws + G.L.o_phiB[k]);
       d.N = I.N;
       d.ppa = I.patches_per_axis;
@@ -1594,7 +1653,7 @@ static mlc_status launch_rest(const Group& G, hipStream_t s, Stage stage) {
       const mlc_plan_info& I = P->info;
       SkelGeom sg{I.N, I.n, I.patches_per_axis, P->Kann, I.d_alpha, I.d_beta, I.b, I.Wa, P->P0, I.nplanes_a, P->Wb,
                   P->P0b, P->nplb, I.O_lo, I.No, final_c2h2(*P)};
-      v[k] = SkelProb<T>{phiH_of(k), pl + L.patch0[k] * plsz, charge_of(G, k), phiB_of(k), G.phi[k], sg, total};
+      v[k] = SkelProb<T>{phiH_of(k), pl + L.patch0[k] * plsz, charge_of(G, k), phiB_of(k), phi_of(G, k), sg, total};
       total += int64_t(3) * (I.N / I.n + 1) * (I.N + 1) * (I.N + 1);
     }
     if (stage == PLANES) {
@@ -1709,6 +1768,7 @@ static mlc_status enqueue_group(const Group& G, hipStream_t s, const AnalyticInp
   if (G.one_stream) {
     const bool f32 = I0.conv_precision == MLC_CONV_FP32;
     upload_descs(G, s);
+    launch_box_in(G, s);
     if (an) launch_analytic_fill(G, s, *an);
     launch_sixth_rhs(G, s);
     if (!(f32 ? dispatch_conv<float>(G, s, 0) : dispatch_conv<double>(G, s, 0)))
@@ -1721,6 +1781,7 @@ static mlc_status enqueue_group(const Group& G, hipStream_t s, const AnalyticInp
       const mlc_status r = f32 ? launch_rest<float>(G, s, st) : launch_rest<double>(G, s, st);
       if (r != MLC_OK) return r;
     }
+    launch_box_out(G, s);
     const hipError_t e = hipGetLastError();
     if (e != hipSuccess) return fail(P0->ctx, MLC_ERR_DEVICE, std::string("launch: ") + hipGetErrorString(e));
     return MLC_OK;
@@ -1729,6 +1790,7 @@ static mlc_status enqueue_group(const Group& G, hipStream_t s, const AnalyticInp
   if (!sd) return fail(P0->ctx, MLC_ERR_DEVICE, "could not create the side stream");
   const bool fp32 = I0.conv_precision == MLC_CONV_FP32;
   upload_descs(G, s);
+  launch_box_in(G, s);
   if (an) launch_analytic_fill(G, s, *an);
   launch_sixth_rhs(G, s);
   // the x-DFT pass of the local convolutions also leaves the per-plane
@@ -1763,6 +1825,7 @@ static mlc_status enqueue_group(const Group& G, hipStream_t s, const AnalyticInp
   if (e != hipSuccess) return fail(P0->ctx, MLC_ERR_DEVICE, std::string("join: ") + hipGetErrorString(e));
   if (fp32) launch_rest<float>(G, s, FINISH);
   else launch_rest<double>(G, s, FINISH);
+  launch_box_out(G, s);
   e = hipGetLastError();
   if (e != hipSuccess) return fail(P0->ctx, MLC_ERR_DEVICE, std::string("launch: ") + hipGetErrorString(e));
   return MLC_OK;
@@ -1780,7 +1843,7 @@ static bool check_enabled() {
 // The flag lives with the caller stream's side-stream state, so callers on
 // different streams (a server thread and the caller's own thread) never
 // share one.
-static mlc_status check_boundary(mlc_context* ctx, const double* f, int N, int layers, hipStream_t s) {
+static mlc_status check_boundary(mlc_context* ctx, const double* f, const int* B, int layers, hipStream_t s) {
   mlc_context::Side* sd = side_of(ctx, s);
   if (!sd) return fail(ctx, MLC_ERR_DEVICE, "could not create the side stream");
   int* flag = nullptr;
@@ -1790,9 +1853,11 @@ static mlc_status check_boundary(mlc_context* ctx, const double* f, int N, int l
     flag = sd->check_flag;
   }
   if (!flag) return fail(ctx, MLC_ERR_OUT_OF_MEMORY, "check flag allocation failed");
-  const int64_t faces = int64_t(6) * layers * (N + 1) * (N + 1);
+  const int Bm = std::max(B[0], std::max(B[1], B[2]));
+  const int64_t faces = int64_t(6) * layers * (Bm + 1) * (Bm + 1);
   hipLaunchKernelGGL(set_flag_kernel, dim3(1), dim3(1), 0, s, flag, 0);
-  hipLaunchKernelGGL(boundary_check_kernel, dim3(blocks_for(faces)), dim3(256), 0, s, f, N, layers, flag);
+  hipLaunchKernelGGL(boundary_check_kernel, dim3(blocks_for(faces)), dim3(256), 0, s, f, B[0], B[1], B[2], layers,
+                     flag);
   int h = 0;
   hipError_t e = hipMemcpyAsync(&h, flag, sizeof(int), hipMemcpyDeviceToHost, s);
   if (e == hipSuccess) e = hipStreamSynchronize(s);
@@ -1810,9 +1875,9 @@ bool mlc_check_enabled() { return check_enabled(); }
 // layers of the outer faces a charge must vanish on: one, three for the
 // sixth-order right-hand side
 int mlc_check_layers(const mlc_plan_info& I) { return I.rhs_order == 6 ? 3 : 1; }
-mlc_status mlc_check_charge(mlc_context* ctx, const double* f, int N, int layers, void* stream) {
+mlc_status mlc_check_charge(mlc_context* ctx, const double* f, const mlc_plan_info& I, void* stream) {
   HIP_TRY(ctx, hipSetDevice(ctx->device));
-  return check_boundary(ctx, f, N, layers, static_cast<hipStream_t>(stream));
+  return check_boundary(ctx, f, I.box, mlc_check_layers(I), static_cast<hipStream_t>(stream));
 }
 
 // ----------------------------------------------------------------- trace
@@ -1923,7 +1988,7 @@ extern "C" mlc_status mlc_solve(mlc_plan* plan, const double* f, double* phi, vo
   if (ws_bytes < G.L.bytes) return fail(plan->ctx, MLC_ERR_INVALID_ARG, "workspace too small");
   if (check_enabled()) {
     const mlc_status cs =
-        check_boundary(plan->ctx, f, plan->info.N, mlc_check_layers(plan->info), static_cast<hipStream_t>(stream));
+        check_boundary(plan->ctx, f, plan->info.box, mlc_check_layers(plan->info), static_cast<hipStream_t>(stream));
     if (cs != MLC_OK) return cs;
   }
   G.ws = static_cast<char*>(workspace);
@@ -1967,6 +2032,7 @@ extern "C" mlc_status mlc_solve_analytic(mlc_plan* plan, int32_t nterms, const m
   if (gauss_points < 1 || gauss_points > 4) return fail(ctx, MLC_ERR_INVALID_ARG, "gauss_points must be in [1, 4]");
   if (plan->info.rhs_order == 6)
     return fail(ctx, MLC_ERR_UNSUPPORTED, "the Gauss moments are those of f, not of the sixth-order right-hand side");
+  if (is_boxed(plan->info)) return fail(ctx, MLC_ERR_UNSUPPORTED, "analytic charges are sampled on cubes only");
   if (ws_bytes < plan->ws_total) return fail(ctx, MLC_ERR_INVALID_ARG, "workspace too small");
   if (reinterpret_cast<uintptr_t>(workspace) % 256)
     return fail(ctx, MLC_ERR_INVALID_ARG, "workspace must be 256-byte aligned");
@@ -2074,7 +2140,7 @@ extern "C" mlc_status mlc_solve_batched(int32_t count, mlc_plan* const* plans, c
   HIP_TRY(ctx, hipSetDevice(ctx->device));
   if (check_enabled()) {
     for (int k = 0; k < count; ++k) {
-      st = check_boundary(ctx, f[k], plans[k]->info.N, mlc_check_layers(plans[k]->info), static_cast<hipStream_t>(stream));
+      st = check_boundary(ctx, f[k], plans[k]->info.box, mlc_check_layers(plans[k]->info), static_cast<hipStream_t>(stream));
       if (st != MLC_OK) return st;
     }
   }

@@ -31,8 +31,7 @@ int mlc_context_device(const mlc_context* ctx);
 bool mlc_budget_take(mlc_context* ctx, size_t bytes);
 void mlc_budget_give(mlc_context* ctx, size_t bytes);
 bool mlc_check_enabled();
-mlc_status mlc_check_charge(mlc_context* ctx, const double* f, int N, int layers, void* stream);
-int mlc_check_layers(const mlc_plan_info& I);
+mlc_status mlc_check_charge(mlc_context* ctx, const double* f, const mlc_plan_info& I, void* stream);
 
 namespace {
 
@@ -44,14 +43,14 @@ double ms_between(Clock::time_point a, Clock::time_point b) {
 
 // A plan serves exactly one problem description.
 using PlanKey = std::tuple<int, double, int, double, double, int, int, int, int, int, int, int, double, double,
-                           double, int, int>;
+                           double, int, int, int, int, int>;
 PlanKey plan_key(const mlc_problem& p) {
   // levels and the coarser radii as given: 0 and 2 both mean two levels, and
   // a 0 radius equals the finer level's, so equal problems may still get two
   // plans (never one plan for two different problems)
   return PlanKey{p.n_cells, p.h, p.patch, p.alpha, p.beta, p.P, p.Q, p.interp_b, p.conv_precision, p.fft_size,
                  p.dgf_half_width, p.levels, p.level_alpha[0], p.level_alpha[1], p.level_alpha[2], p.rhs_order,
-                 p.skip_empty};
+                 p.skip_empty, p.box_cells[0], p.box_cells[1], p.box_cells[2]};
 }
 
 // Requests whose patch-level work is identical may share a launch.
@@ -252,7 +251,7 @@ bool admit(mlc_server* S) {
       st = MLC_ERR_OUT_OF_MEMORY;
       P = nullptr;
     }
-    if (P && check) st = mlc_check_charge(S->ctx, r->f, r->info.N, mlc_check_layers(r->info), S->streams[stream]);
+    if (P && check) st = mlc_check_charge(S->ctx, r->f, r->info, S->streams[stream]);
     if (!P || st != MLC_OK) {
       std::lock_guard<std::mutex> lk(S->mu);
       remove_from_queue_locked(S, r);

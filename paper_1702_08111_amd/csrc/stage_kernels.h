@@ -197,21 +197,40 @@ __global__ void __launch_bounds__(256) coarse_rhs_kernel(const CoarseRhsProb<T>*
 }
 
 // The optional input check: flag = 1 if f is nonzero at any node within
-// `layers` node layers of the six outer faces of the (N+1)^3 node box.
+// `layers` node layers of the six outer faces of its (B0+1)(B1+1)(B2+1) node
+// box.  Threads cover (face, layer, a, b) with a, b up to the largest edge;
+// those past a face's own extent do nothing.
 __global__ void set_flag_kernel(int* __restrict__ flag, int v) { *flag = v; }
-__global__ void boundary_check_kernel(const double* __restrict__ f, int N, int layers, int* __restrict__ flag) {
-  const int64_t Np = N + 1;
+__global__ void boundary_check_kernel(const double* __restrict__ f, int B0, int B1, int B2, int layers,
+                                      int* __restrict__ flag) {
+  const int64_t Bm = max(B0, max(B1, B2)) + 1;
   const int64_t idx = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-  if (idx >= 6 * layers * Np * Np) return;
-  const int face = int(idx / (layers * Np * Np));
-  const int layer = int((idx / (Np * Np)) % layers);
-  const int64_t a = (idx / Np) % Np, b = idx % Np;
-  const int64_t e = (face & 1) ? N - layer : layer;
-  int64_t g0, g1, g2;
-  if (face < 2) { g0 = e; g1 = a; g2 = b; }
-  else if (face < 4) { g0 = a; g1 = e; g2 = b; }
-  else { g0 = a; g1 = b; g2 = e; }
-  if (f[(g0 * Np + g1) * Np + g2] != 0.0) *flag = 1;
+  if (idx >= 6 * layers * Bm * Bm) return;
+  const int face = int(idx / (layers * Bm * Bm));
+  const int layer = int((idx / (Bm * Bm)) % layers);
+  const int64_t a = (idx / Bm) % Bm, b = idx % Bm;
+  const int B[3] = {B0, B1, B2};
+  const int d = face / 2;                            // the face's normal axis
+  const int u = d == 0 ? 1 : 0, v = d == 2 ? 1 : 2;   // its in-plane axes
+  if (a > B[u] || b > B[v] || layer > B[d]) return;
+  int64_t g[3];
+  g[d] = (face & 1) ? B[d] - layer : layer;
+  g[u] = a;
+  g[v] = b;
+  if (f[(g[0] * (B1 + 1) + g[1]) * (B2 + 1) + g[2]] != 0.0) *flag = 1;
+}
+
+// dst[i] = src[i] for i in [0, w0) x [0, w1) x [0, w2) of node arrays of
+// extents (s0, s1, s2) and (d0, d1, d2): a box domain into its enclosing cube
+// and the cube's phi back onto the box.
+__global__ void box3_copy_kernel(const double* __restrict__ src, int s0, int s1, int s2, double* __restrict__ dst,
+                                 int d0, int d1, int d2, int w0, int w1, int w2) {
+  const int64_t idx = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (idx >= int64_t(w0) * w1 * w2) return;
+  const int i2 = int(idx % w2), i1 = int((idx / w2) % w1), i0 = int(idx / (int64_t(w1) * w2));
+  (void)s0;
+  (void)d0;
+  dst[(int64_t(i0) * d1 + i1) * d2 + i2] = src[(int64_t(i0) * s1 + i1) * s2 + i2];
 }
 
 // The modified right-hand side of the sixth-order variant for the 27-point

@@ -54,6 +54,8 @@ class mlc_problem(ctypes.Structure):
         ("level_alpha", ctypes.c_double * 3),
         ("rhs_order", ctypes.c_int32),
         ("skip_empty", ctypes.c_int32),
+        ("box_cells", ctypes.c_int32 * 3),
+        ("origin", ctypes.c_double * 3),
     ]
 
 
@@ -76,11 +78,13 @@ class mlc_plan_info(ctypes.Structure):
                               ("levels", ctypes.c_int32), ("level_margin", ctypes.c_int32),
                               ("level_N", ctypes.c_int32), ("alpha", ctypes.c_double),
                               ("beta", ctypes.c_double), ("level_alpha", ctypes.c_double * 3),
-                              ("rhs_order", ctypes.c_int32), ("skip_empty", ctypes.c_int32)]
+                              ("rhs_order", ctypes.c_int32), ("skip_empty", ctypes.c_int32),
+                              ("box", ctypes.c_int32 * 3), ("origin", ctypes.c_double * 3)]
 
     def as_dict(self):
         d = {k: getattr(self, k) for k, _ in self._fields_}
-        d["level_alpha"] = list(d["level_alpha"])
+        for k in ("level_alpha", "box", "origin"):
+            d[k] = list(d[k])
         return d
 
 
@@ -192,11 +196,20 @@ def _stream(s):
 
 
 def problem(N, n, alpha=3.0, beta=6.0, P=4, Q=4, b=0, h=None, conv="fp32", fft_size=0, Z=0, levels=0,
-            level_alpha=(), rhs_order=0, skip_empty=0):
+            level_alpha=(), rhs_order=0, skip_empty=0, origin=(0.0, 0.0, 0.0)):
+    """N: cells per axis of a cube, or a triple (B0, B1, B2) for a box domain
+    (h then defaults to 1 / max B_d)."""
     la = list(level_alpha) + [0.0] * (3 - len(level_alpha))
-    return mlc_problem(N, (1.0 / N) if h is None else h, n, alpha, beta, P, Q, b,
+    if isinstance(N, (tuple, list)):
+        box, ncells = [int(x) for x in N], 0
+        hh = (1.0 / max(box)) if h is None else h
+    else:
+        box, ncells = [0, 0, 0], int(N)
+        hh = (1.0 / N) if h is None else h
+    return mlc_problem(ncells, hh, n, alpha, beta, P, Q, b,
                        MLC_CONV_FP32 if conv == "fp32" else MLC_CONV_FP64, fft_size, Z, levels,
-                       (ctypes.c_double * 3)(*la[:3]), rhs_order, skip_empty)
+                       (ctypes.c_double * 3)(*la[:3]), rhs_order, skip_empty, (ctypes.c_int32 * 3)(*box),
+                       (ctypes.c_double * 3)(*[float(x) for x in origin]))
 
 
 def problem_workspace_bytes(prob):

@@ -54,6 +54,8 @@ def test_derived_sizes(name, N, n, Q, fft, expect):
     (dict(N=32, n=8, Z=100), mlc.MLC_ERR_UNSUPPORTED),
     (dict(N=32, n=8, rhs_order=5), mlc.MLC_ERR_INVALID_ARG),
     (dict(N=32, n=8, skip_empty=2), mlc.MLC_ERR_INVALID_ARG),
+    (dict(N=(64, 40, 32), n=16), mlc.MLC_ERR_INVALID_ARG),      # a box edge not a multiple of n
+    (dict(N=(64, 0, 32), n=16), mlc.MLC_ERR_INVALID_ARG),
     (dict(N=32, n=8, Q=4, rhs_order=6), mlc.MLC_ERR_UNSUPPORTED),      # the 27-point operator's
     (dict(N=64, n=8, levels=3, level_alpha=(3.5,)), mlc.MLC_ERR_UNSUPPORTED),  # level-1 margin 10
     (dict(N=64, n=8, levels=3, level_alpha=(0.5,)), mlc.MLC_ERR_INVALID_ARG),    # below 1
@@ -154,3 +156,21 @@ def test_sixth_order_sizes():
     assert mlc.problem_info(base)["rhs_order"] == 4 and mlc.problem_info(six)["rhs_order"] == 6
     extra = mlc.problem_workspace_bytes(six) - mlc.problem_workspace_bytes(base)
     assert 33 ** 3 * 8 <= extra < 33 ** 3 * 8 + 512
+
+
+def test_box_domain_sizes():
+    """A box is solved in the smallest cube the plan can run: N a multiple of
+    n (two levels) or of 4n (three levels); the info reports both, and the
+    origin as given; n_cells and box_cells together are refused."""
+    i = mlc.problem_info(mlc.problem((64, 48, 32), 16, 3.0, 6.0, 4, 4, origin=(1.0, -2.0, 0.5)))
+    assert i["N"] == 64 and i["box"] == [64, 48, 32] and i["origin"] == [1.0, -2.0, 0.5]
+    assert mlc.problem_info(mlc.problem((80, 16, 16), 16, levels=3))["N"] == 128
+    assert mlc.problem_info(mlc.problem(64, 16))["box"] == [64, 64, 64]
+    p = mlc.problem((64, 48, 32), 16)
+    p.n_cells = 64
+    with pytest.raises(mlc.MLCError) as ei:
+        mlc.problem_info(p)
+    assert ei.value.status == mlc.MLC_ERR_INVALID_ARG
+    # the workspace holds f and phi in the enclosing cube besides the cube's own
+    extra = mlc.problem_workspace_bytes(mlc.problem((64, 48, 32), 16)) - mlc.problem_workspace_bytes(mlc.problem(64, 16))
+    assert 2 * 65 ** 3 * 8 <= extra < 2 * 65 ** 3 * 8 + 1024
