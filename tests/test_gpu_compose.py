@@ -1,5 +1,6 @@
 """The features together through the C ABI (MI355X only): multilevel plans
-(with per-level radii), sixth-order plans and plain two-level plans in one
+(with per-level radii), sixth-order plans, a box domain with empty patches
+skipped and plain two-level plans in one
 batched call, in a library-captured batch graph, through the serving loop
 and on the static scratch; every result equals the same plan solving alone,
 bit for bit (a problem's arithmetic does not depend on what shares its
@@ -24,7 +25,17 @@ PROBLEMS = [
     (dict(N=32, n=8, alpha=3.0, beta=6.0, P=4, Q=6, Z=64, rhs_order=6), lambda: mi.poly_charge(32)),
     (dict(N=32, n=8, alpha=3.0, beta=6.0, P=4, Q=4, Z=64), lambda: mi.bump_charge(32, mi.bumps(2, 5))),
     (dict(N=128, n=16, alpha=3.0, beta=6.0, P=4, Q=4, Z=128, levels=3), lambda: mi.smooth_charge(128)),
+    # a box domain with empty patches skipped
+    (dict(N=(64, 48, 32), n=16, alpha=3.0, beta=6.0, P=4, Q=4, Z=128, skip_empty=1), lambda: _box_charge((64, 48, 32))),
 ]
+
+
+def _box_charge(B):
+    h = 1.0 / max(B)
+    g = [np.arange(b + 1) * h for b in B]
+    r = np.sqrt((g[0][:, None, None] - 0.45) ** 2 + (g[1][None, :, None] - 0.35) ** 2
+                + (g[2][None, None, :] - 0.25) ** 2) / 0.2
+    return np.where(r < 1.0, (1.0 - r * r) ** 4, 0.0)
 
 
 def _setup(conv):
