@@ -124,6 +124,16 @@ typedef struct {
                              All zero: the cube of n_cells.  mlc_solve_analytic refuses
                              box problems                                            */
   double origin[3];       /* physical coordinates of node (0,0,0); recorded, not used    */
+  int32_t max_live;       /* > 0: keep per-patch convolution buffers for at most this many
+                             patches with charge (implies skip_empty): each solve finds
+                             them on the device, waits for its stream once to list them,
+                             and returns MLC_ERR_OUT_OF_MEMORY if there are more; the
+                             patch Dirichlet solves run in chunks.  For large grids whose
+                             charge covers few patches (e.g. 2048^3).  mlc_solve and
+                             mlc_solve_analytic only: batches, graphs, the static
+                             scratch and the server refuse it (MLC_ERR_UNSUPPORTED).
+                             The coarser levels of a multilevel plan keep every patch.
+                             0: buffers for every patch                              */
 } mlc_problem;
 
 /* Sizes derived from an mlc_problem (all counts per axis unless noted). */
@@ -152,6 +162,8 @@ typedef struct {
   int32_t box[3];                    /* cells per axis of the problem's domain (N, N, N for
                                         a cube); N above is the cube it is solved in      */
   double origin[3];                  /* mlc_problem.origin                               */
+  int32_t slots;                     /* patches the per-patch buffers hold (npatch, or
+                                        min(max_live, npatch))                           */
 } mlc_plan_info;
 
 typedef struct mlc_context mlc_context;
@@ -298,6 +310,8 @@ mlc_status mlc_graph_destroy(mlc_graph* graph);
  *                         phi_i on its skeleton planes inside Omega_alpha,
  *                         plane normal d, planes at -d_alpha rounded up to a
  *                         multiple of n, in-plane axes ascending from -d_alpha
+ *   (with max_live the two local views hold [slots] rows: the patches that
+ *   carry charge, in increasing patch order; the other patches' fields are 0)
  *   multilevel plans only (levels > 2), the next coarser level:
  *   MLC_VIEW_LEVEL_CHARGE float64 [(level_N+1)^3]: its node charge (F^H placed
  *                         in its box; node 0 at coarse coordinate -level_margin)

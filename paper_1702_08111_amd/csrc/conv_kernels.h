@@ -26,7 +26,8 @@ namespace mlc {
 template <typename T, int M>
 __global__ void __launch_bounds__(256) conv_xdft_kernel(const ProbDesc* __restrict__ pd, int nprob, int n, int P,
                                                         cplx<T>* __restrict__ X, double* __restrict__ mpart,
-                                                        const int* __restrict__ live, int p0) {
+                                                        const int* __restrict__ live,
+                                                        const int* __restrict__ patch_of, int p0) {
   constexpr int Mh = M / 2 + 1;
   __shared__ T q[SMAX * SMAX];
   __shared__ cplx<T> tw[M];
@@ -34,10 +35,13 @@ __global__ void __launch_bounds__(256) conv_xdft_kernel(const ProbDesc* __restri
   __shared__ double Bw[PMAX][SMAX];    // Boole weight x qhat_a at each node, a < P
   __shared__ double gx[PMAX][SMAX];    // x-contracted moment sums per row
   const int S = n + 1;
-  const int p = p0 + blockIdx.y, sz = blockIdx.x;
+  // slot: this patch's place in the per-patch buffers (its own index unless
+  // the plan keeps only its live patches, listed in patch_of)
+  const int slot = p0 + blockIdx.y, sz = blockIdx.x;
+  const int p = patch_of ? patch_of[slot] : slot;
   if (live && !live[p]) {
     // an empty patch: zero moment sums; its x-DFT is never read
-    if (int(threadIdx.x) < P * P) mpart[(int64_t(p) * (n + 1) + sz) * (P * P) + threadIdx.x] = 0.0;
+    if (int(threadIdx.x) < P * P) mpart[(int64_t(slot) * (n + 1) + sz) * (P * P) + threadIdx.x] = 0.0;
     return;
   }
   const ProbDesc& D = pd[find_problem(pd, nprob, p)];
@@ -74,7 +78,7 @@ __global__ void __launch_bounds__(256) conv_xdft_kernel(const ProbDesc* __restri
   constexpr int TK = 3, TY = 4;
   constexpr int NK = (Mh + TK - 1) / TK;
   const int NY = (S + TY - 1) / TY;
-  cplx<T>* out = X + (int64_t(p) * Mh * S + sz) * S;
+  cplx<T>* out = X + (int64_t(slot) * Mh * S + sz) * S;
   for (int o = threadIdx.x; o < NK * NY; o += blockDim.x) {
     const int kg = o / NY, sg = o % NY;
     int kx[TK], idx[TK], sy[TY];
@@ -121,7 +125,7 @@ __global__ void __launch_bounds__(256) conv_xdft_kernel(const ProbDesc* __restri
     const int a1 = threadIdx.x / P, a2 = threadIdx.x % P;
     double acc = 0.0;
     for (int sy = 0; sy < S; ++sy) acc += Bw[a1][sy] * gx[a2][sy];
-    mpart[(int64_t(p) * S + sz) * (P * P) + threadIdx.x] = acc;
+    mpart[(int64_t(slot) * S + sz) * (P * P) + threadIdx.x] = acc;
   }
 }
 
@@ -362,7 +366,8 @@ __global__ void __launch_bounds__((OutBatch<T, M, MULTI>::NT)) conv_out_kernel(c
                                                                       T* __restrict__ coarse,
                                                                       T* __restrict__ planes, OutGeom g,
                                                                       const ProbDesc* __restrict__ pd, int nprob,
-                                                                      const int* __restrict__ live, int p0,
+                                                                      const int* __restrict__ live,
+                                                                      const int* __restrict__ patch_of, int p0,
                                                                       int zpb_arg) {
   constexpr int Mh = M / 2 + 1;
   constexpr int R1 = Split<M>::R1, R2 = Split<M>::R2;
@@ -413,7 +418,7 @@ __global__ void __launch_bounds__((OutBatch<T, M, MULTI>::NT)) conv_out_kernel(c
   const int tid = threadIdx.x;
   // h^2 in the kernel's precision (for the fp32 kernel: one rounding of h^2,
   // none when h is a power of two)
-  const T hsq = T(pd[find_problem(pd, nprob, p)].h2);
+  const T hsq = T(pd[find_problem(pd, nprob, patch_of ? patch_of[p] : p)].h2);
   const cplx<T>* zin = Zb + (int64_t(pc) * Wp + zi0) * Mh * M;   // the current plane
   constexpr int LW = OutBatch<T, M, MULTI>::LW, NW = OutBatch<T, M, MULTI>::NT / 64;
   const int wave = tid >> 6, lane = tid & 63;

@@ -286,7 +286,7 @@ static mlc_problem child_problem(const mlc_plan_info& I) {
   c.level_alpha[1] = I.level_alpha[2];
   c.level_alpha[2] = 0.0;
   c.rhs_order = 0;   // the coarser levels solve their node charge as it is
-  c.skip_empty = I.skip_empty;   // box_cells stay zero: the level box is a cube
+  c.skip_empty = I.skip_empty;   // box_cells stay zero: the level box is a cube; max_live 0 (dense)
   const int e = margin_of(c.alpha, I.n) + NREF * I.b;
   c.fft_size = (I.M >= 2 * (I.n + e) + 1 && conv_size_ok(I.conv_precision, I.n, I.M)) ? I.M : 0;
   return c;
@@ -360,6 +360,9 @@ static mlc_status derive(const mlc_problem* p, mlc_plan_info* o, std::string* wh
   I.e = I.d_alpha + NREF * I.b;
   I.patches_per_axis = I.N / I.n;
   I.npatch = I.patches_per_axis * I.patches_per_axis * I.patches_per_axis;
+  if (p->max_live < 0) { *why = "max_live must be >= 0"; return MLC_ERR_INVALID_ARG; }
+  I.slots = p->max_live > 0 ? std::min(p->max_live, I.npatch) : I.npatch;
+  if (p->max_live > 0) I.skip_empty = 1;   // the live patches are the ones with charge
   int Mmin = 2 * (I.n + I.e) + 1;
   if (p->fft_size < -1) { *why = "fft_size must be > 0, 0 (smallest) or -1 (autotune)"; return MLC_ERR_INVALID_ARG; }
   if (p->fft_size > 0) {
@@ -782,6 +785,10 @@ struct Layout {
   std::vector<size_t> o_lf, o_lphi, o_lws;   // multilevel problems: the next level's charge, solution, workspace
   std::vector<size_t> o_ft;                  // sixth-order problems: the modified right-hand side
   std::vector<size_t> o_fbox, o_pbox;        // box problems: f and phi in the enclosing cube
+  int slots = 0;                             // per-patch buffer rows (= total unless a plan keeps live patches only)
+  bool compact = false;                      // the group's one plan keeps its live patches only
+  size_t o_patch_of = 0, o_slot_of = 0;      // compact: slot -> patch, patch -> slot (-1: empty)
+  int dir_chunk = 0;                         // patches per Dirichlet launch
   size_t o_live = 0;                         // per patch: 1 unless skipped as empty (int)
   bool any_skip = false;                     // some problem skips empty patches
   std::vector<int> patch0;
@@ -814,6 +821,9 @@ static Layout layout_of(const std::vector<const mlc_plan_info*>& g) {
     L.total += g[k]->npatch;
   }
   const size_t T = size_t(L.total);
+  for (int k = 0; k < np; ++k) L.slots += g[k]->slots;
+  L.compact = L.slots < L.total;
+  const size_t Ts = size_t(L.slots);
   size_t o = 0;
   auto take = [&](size_t bytes) { size_t at = o; o = align_up(o + bytes); return at; };
   L.o_desc = take(sizeof(ProbDesc) * np);
@@ -823,25 +833,34 @@ static Layout layout_of(const std::vector<const mlc_plan_info*>& g) {
   L.o_live = take(sizeof(int) * T);
   for (int k = 0; k < np; ++k) L.any_skip = L.any_skip || g[k]->skip_empty;
   L.o_mom = take(sizeof(double) * T * I.K);
-  L.o_mpart = take(sizeof(double) * T * S * I.P * I.P);
+  L.o_mpart = take(sizeof(double) * Ts * S * I.P * I.P);
+  if (L.compact) {
+    L.o_patch_of = take(sizeof(int) * Ts);
+    L.o_slot_of = take(sizeof(int) * T);
+  }
   L.o_mraw = take(I.P >= 5 ? sizeof(double) * T * I.K : 0);
   // the x-DFT spectra; once the last y/z pass has read them, the same bytes
   // hold the coarse Laplacians of the patches' coarse samples (at most as
   // many bytes, since alpha <= 3)
-  L.o_X = take(std::max(csz * T * Mh * S * S, sizeof(double) * T * size_t(cube(I.Wc - 2 * I.b))));
+  L.o_X = take(std::max(csz * Ts * Mh * S * S, sizeof(double) * Ts * size_t(cube(I.Wc - 2 * I.b))));
   // patch chunks of equal size whose z-transformed spectra stay within
   // 6 GB (MLC_CONV_CHUNK overrides the largest chunk): at 256^3 with 32^3
   // patches one chunk holds every patch, measured faster than two or three
   const size_t per_patch = csz * size_t(Wp) * Mh * I.M;
   int chunk = int(std::max<size_t>(1, (size_t(6) << 30) / per_patch));
   if (const int c = conv_chunk_override()) chunk = c;
-  chunk = std::min(std::min(chunk, L.total), kMaxGridY);
-  const int nchunks = (L.total + chunk - 1) / chunk;
-  L.chunk = (L.total + nchunks - 1) / nchunks;
+  chunk = std::min(std::min(chunk, std::max(L.slots, 1)), kMaxGridY);
+  const int nchunks = (std::max(L.slots, 1) + chunk - 1) / chunk;
+  L.chunk = (std::max(L.slots, 1) + nchunks - 1) / nchunks;
   L.o_Z = take(per_patch * L.chunk);
-  L.o_cs = take(tsz * T * cube(I.Wc));
-  L.o_pl = take(tsz * T * 3 * I.nplanes_a * I.Wa * I.Wa);
-  L.o_dir = take(sizeof(double) * T * cube(I.n - 1));
+  L.o_cs = take(tsz * Ts * cube(I.Wc));
+  L.o_pl = take(tsz * Ts * 3 * I.nplanes_a * I.Wa * I.Wa);
+  // the Dirichlet work array: every patch at once up to 4 GB, else chunks
+  {
+    const size_t per = sizeof(double) * size_t(cube(I.n - 1));
+    L.dir_chunk = int(std::min<size_t>(T, std::max<size_t>(1, (size_t(4) << 30) / per)));
+    L.o_dir = take(per * size_t(L.dir_chunk));
+  }
   {
     size_t nsk = 0;
     for (int k = 0; k < np; ++k) nsk += size_t(3) * (g[k]->N / g[k]->n + 1) * size_t(g[k]->N + 1) * (g[k]->N + 1);
@@ -1183,8 +1202,8 @@ extern "C" mlc_status mlc_workspace_view(const mlc_plan* plan, void* ws, int32_t
     case MLC_VIEW_COARSE_RHS: at = plan->o_F; len = sizeof(double) * cube(I.Ns); break;
     case MLC_VIEW_COARSE_PHI: at = plan->o_phiH; len = sizeof(double) * cube(I.No); break;
     case MLC_VIEW_BOUNDARY: at = plan->o_phiB; len = sizeof(double) * cube(I.N + 1); break;
-    case MLC_VIEW_LOCAL_COARSE: at = plan->o_cs; len = tsz * I.npatch * cube(I.Wc); break;
-    case MLC_VIEW_LOCAL_PLANES: at = plan->o_pl; len = tsz * I.npatch * 3 * I.nplanes_a * I.Wa * I.Wa; break;
+    case MLC_VIEW_LOCAL_COARSE: at = plan->o_cs; len = tsz * I.slots * cube(I.Wc); break;
+    case MLC_VIEW_LOCAL_PLANES: at = plan->o_pl; len = tsz * I.slots * 3 * I.nplanes_a * I.Wa * I.Wa; break;
     case MLC_VIEW_LEVEL_CHARGE:
     case MLC_VIEW_LEVEL_PHI:
     case MLC_VIEW_LEVEL_WORKSPACE:
@@ -1216,6 +1235,7 @@ struct Group {
   char* ws = nullptr;
   ProbDesc* desc = nullptr;
   bool one_stream = false;   // every stage on the caller's stream (no side stream)
+  mutable int nslots = -1;   // slots in use this solve (the live patches when compact)
 };
 
 // Coarse Hockney convolution of a batch of nb tori with the real-even
@@ -1304,8 +1324,19 @@ static double final_c2h2(const mlc_plan& P) {
   return (P.correct && P.info.rhs_order != 6) ? P.info.h * P.info.h / 12.0 : 0.0;
 }
 // per-patch live flags of the group (nullptr when no member skips empty patches)
+// Per-patch flags of which patches carry charge, for kernels indexed by
+// patch; none when no problem skips, or when the buffers hold the live
+// patches only (every slot then is live).
 static const int* live_of(const Group& G) {
-  return G.L.any_skip ? reinterpret_cast<const int*>(G.ws + G.L.o_live) : nullptr;
+  return G.L.any_skip && !G.L.compact ? reinterpret_cast<const int*>(G.ws + G.L.o_live) : nullptr;
+}
+// Rows of the per-patch buffers in use: every patch, or the live ones
+static int slots_in_use(const Group& G) { return G.L.compact ? G.nslots : G.L.total; }
+static const int* patch_of_slot(const Group& G) {
+  return G.L.compact ? reinterpret_cast<const int*>(G.ws + G.L.o_patch_of) : nullptr;
+}
+static const int* slot_of_patch(const Group& G) {
+  return G.L.compact ? reinterpret_cast<const int*>(G.ws + G.L.o_slot_of) : nullptr;
 }
 static void launch_sixth_rhs(const Group& G, hipStream_t s) {
   for (size_t k = 0; k < G.plans.size(); ++k) {
@@ -1353,24 +1384,28 @@ static void launch_conv(const Group& G, hipStream_t s, int phase, const std::fun
   cplx<T>* Zb = reinterpret_cast<cplx<T>*>(G.ws + L.o_Z);
   T* cs = reinterpret_cast<T*>(G.ws + L.o_cs);
   T* pl = reinterpret_cast<T*>(G.ws + L.o_pl);
-  // which patches carry charge (only when some problem skips empty ones)
-  int* live = L.any_skip ? reinterpret_cast<int*>(G.ws + L.o_live) : nullptr;
+  // which patches carry charge (only when some problem skips empty ones and
+  // the buffers hold every patch; compact buffers were filled by compact_live)
+  int* live = const_cast<int*>(live_of(G));
+  const int* pof = patch_of_slot(G);
+  const int ns = slots_in_use(G);
   if (phase == 0) {
     if (live) {
       TimedScope ts(P, s, "patch_live");
       hipLaunchKernelGGL(patch_live_kernel, dim3(L.total), dim3(256), 0, s, G.desc, np, I.n, live, 0);
     }
     TimedScope ts(P, s, "conv_xdft");
-    for (int p0 = 0; p0 < L.total; p0 += kMaxGridY)
-      hipLaunchKernelGGL((conv_xdft_kernel<T, M>), dim3(P->S, std::min(kMaxGridY, L.total - p0)), dim3(256), 0, s,
-                         G.desc, np, I.n, I.P, X, reinterpret_cast<double*>(G.ws + L.o_mpart), live, p0);
+    for (int p0 = 0; p0 < ns; p0 += kMaxGridY)
+      hipLaunchKernelGGL((conv_xdft_kernel<T, M>), dim3(P->S, std::min(kMaxGridY, ns - p0)), dim3(256), 0, s,
+                         G.desc, np, I.n, I.P, X, reinterpret_cast<double*>(G.ws + L.o_mpart), live, pof, p0);
   }
   if (phase == 0) return;
   OutGeom g{I.n, I.e, I.d_alpha, I.b, I.Wa, P->Wp, I.Wc, P->P0, I.nplanes_a};
   // patches in chunks: the chunk's z-transformed spectra (Zb) stay small
   // enough to be re-read from the last-level cache
-  for (int p0 = 0; p0 < L.total; p0 += L.chunk) {
-    const int cnt = std::min(L.chunk, L.total - p0);
+  if (ns == 0 && after_yz) (*after_yz)();   // no live patch: nothing to convolve
+  for (int p0 = 0; p0 < ns; p0 += L.chunk) {
+    const int cnt = std::min(L.chunk, ns - p0);
     {
       TimedScope ts(P, s, "conv_yz");
       hipLaunchKernelGGL((conv_yz_kernel<T, n, M>), dim3(P->Mh, cnt), dim3(256), 0, s, X,
@@ -1391,10 +1426,10 @@ static void launch_conv(const Group& G, hipStream_t s, int phase, const std::fun
       const dim3 grid((P->Wp + zpb - 1) / zpb * kspl, cnt);
       if (zpb == 1)
         hipLaunchKernelGGL((conv_out_kernel<T, n, M, false>), grid, dim3(OutBatch<T, M, false>::NT), 0, s, Zb, cs, pl, g,
-                           G.desc, np, live, p0, 1);
+                           G.desc, np, live, pof, p0, 1);
       else
         hipLaunchKernelGGL((conv_out_kernel<T, n, M, true>), grid, dim3(OutBatch<T, M, true>::NT), 0, s, Zb, cs, pl, g,
-                           G.desc, np, live, p0, zpb);
+                           G.desc, np, live, pof, p0, zpb);
     }
   }
 }
@@ -1457,15 +1492,16 @@ static mlc_status launch_rest(const Group& G, hipStream_t s, Stage stage) {
       const mlc_plan_info& I = P->info;
       CoarseGeom cg{I.n, I.patches_per_axis, P->Kann, I.d_alpha, I.d_beta, I.e, I.Wc, I.S_lo, I.Ns, P->Wbc,
                     1.0 / (I.H * I.H)};
-      v[k] = CoarseRhsProb<T>{lap + L.patch0[k] * lsz, F_of(k), cg, total};
+      v[k] = CoarseRhsProb<T>{lap + L.patch0[k] * lsz, F_of(k), cg, total, slot_of_patch(G)};
       total += cube(I.Ns);
     }
     upload_flat(pr, v, s);
     {
       TimedScope ts(P0, s, "coarse_lap");
       const size_t lds = 3 * sizeof(T) * size_t(I0.Wc) * I0.Wc;   // <= 26 KB (Wc <= 33)
-      for (int p0 = 0; p0 < L.total; p0 += kMaxGridY)
-        hipLaunchKernelGGL(coarse_lap_kernel<T>, dim3(Li, std::min(kMaxGridY, L.total - p0)), dim3(256), lds, s, cs, lap,
+      const int ns = slots_in_use(G);
+      for (int p0 = 0; p0 < ns; p0 += kMaxGridY)
+        hipLaunchKernelGGL(coarse_lap_kernel<T>, dim3(Li, std::min(kMaxGridY, ns - p0)), dim3(256), lds, s, cs, lap,
                            I0.Wc, I0.b, st, live_of(G), p0);
     }
     TimedScope ts(P0, s, "coarse_rhs");
@@ -1636,8 +1672,9 @@ static mlc_status launch_rest(const Group& G, hipStream_t s, Stage stage) {
     TimedScope ts(P0, s, "plane_delta");
     PlaneGeom pg{I0.n, I0.e, I0.d_alpha, I0.Wa, I0.Wc, P0->P0, I0.nplanes_a, I0.b};
     const size_t lds = sizeof(double) * (size_t(I0.Wc) * I0.Wc + size_t(I0.Wc) * I0.Wa);   // <= 35 KB (Wc <= 33, Wa <= 97)
-    for (int p0 = 0; p0 < L.total; p0 += kMaxGridY)
-      hipLaunchKernelGGL(plane_delta_kernel<T>, dim3(3 * I0.nplanes_a, std::min(kMaxGridY, L.total - p0)), dim3(256),
+    const int ns = slots_in_use(G);
+    for (int p0 = 0; p0 < ns; p0 += kMaxGridY)
+      hipLaunchKernelGGL(plane_delta_kernel<T>, dim3(3 * I0.nplanes_a, std::min(kMaxGridY, ns - p0)), dim3(256),
                          lds, s, pl, cs, pg, P0->lagw, live_of(G), p0);
   }
   // skeleton boundary values (+ phi there), every problem in one launch each
@@ -1653,7 +1690,8 @@ static mlc_status launch_rest(const Group& G, hipStream_t s, Stage stage) {
       const mlc_plan_info& I = P->info;
       SkelGeom sg{I.N, I.n, I.patches_per_axis, P->Kann, I.d_alpha, I.d_beta, I.b, I.Wa, P->P0, I.nplanes_a, P->Wb,
                   P->P0b, P->nplb, I.O_lo, I.No, final_c2h2(*P)};
-      v[k] = SkelProb<T>{phiH_of(k), pl + L.patch0[k] * plsz, charge_of(G, k), phiB_of(k), phi_of(G, k), sg, total};
+      v[k] = SkelProb<T>{phiH_of(k), pl + L.patch0[k] * plsz, charge_of(G, k), phiB_of(k), phi_of(G, k), sg, total,
+                         slot_of_patch(G)};
       total += int64_t(3) * (I.N / I.n + 1) * (I.N + 1) * (I.N + 1);
     }
     if (stage == PLANES) {
@@ -1671,11 +1709,15 @@ static mlc_status launch_rest(const Group& G, hipStream_t s, Stage stage) {
   if (stage == FINISH) {
     const int m = I0.n - 1;
     TimedScope ts(P0, s, "dirichlet");
-    DirGeom dg{I0.n, L.total, 2.0 / I0.n, st};
-    dim3 gd(unsigned((int64_t(L.total) * m + DIR_WAVES - 1) / DIR_WAVES));
-    hipLaunchKernelGGL(dirichlet_mfma_kernel<0>, gd, dim3(64 * DIR_WAVES), 0, s, G.desc, np, dir, dg);
-    hipLaunchKernelGGL(dirichlet_mfma_kernel<1>, gd, dim3(64 * DIR_WAVES), 0, s, G.desc, np, dir, dg);
-    hipLaunchKernelGGL(dirichlet_mfma_kernel<2>, gd, dim3(64 * DIR_WAVES), 0, s, G.desc, np, dir, dg);
+    // in chunks of patches when the work array cannot hold them all
+    for (int p0 = 0; p0 < L.total; p0 += L.dir_chunk) {
+      const int cnt = std::min(L.dir_chunk, L.total - p0);
+      DirGeom dg{I0.n, cnt, 2.0 / I0.n, st, p0};
+      dim3 gd(unsigned((int64_t(cnt) * m + DIR_WAVES - 1) / DIR_WAVES));
+      hipLaunchKernelGGL(dirichlet_mfma_kernel<0>, gd, dim3(64 * DIR_WAVES), 0, s, G.desc, np, dir, dg);
+      hipLaunchKernelGGL(dirichlet_mfma_kernel<1>, gd, dim3(64 * DIR_WAVES), 0, s, G.desc, np, dir, dg);
+      hipLaunchKernelGGL(dirichlet_mfma_kernel<2>, gd, dim3(64 * DIR_WAVES), 0, s, G.desc, np, dir, dg);
+    }
   }
   return MLC_OK;
 }
@@ -1713,15 +1755,20 @@ static void launch_moments(const Group& G, hipStream_t s) {
   const mlc_plan_info& I0 = P0->info;
   const int np = int(G.plans.size());
   TimedScope ts(P0, s, "moments");
-  const int64_t work = int64_t(G.L.total) * I0.K;
+  const int ns = slots_in_use(G);
+  const int64_t work = int64_t(ns) * I0.K, all = int64_t(G.L.total) * I0.K;
   const bool diag = I0.P <= 4;
   double* mom = reinterpret_cast<double*>(G.ws + G.L.o_mom);
   double* raw = reinterpret_cast<double*>(G.ws + G.L.o_mraw);
-  hipLaunchKernelGGL(moments_finish_kernel, dim3(unsigned((work + 255) / 256)), dim3(256), 0, s, G.desc, np, I0.n,
-                     I0.P, P0->modes, reinterpret_cast<const double*>(G.ws + G.L.o_mpart), diag ? mom : raw,
-                     G.L.total, diag ? 1 : 0);
+  // compact buffers: the empty patches' moments are zero, the others are set below
+  if (G.L.compact)
+    hipLaunchKernelGGL(fill_zero_kernel, dim3(blocks_for(all)), dim3(256), 0, s, diag ? mom : raw, all);
+  if (work > 0)
+    hipLaunchKernelGGL(moments_finish_kernel, dim3(unsigned((work + 255) / 256)), dim3(256), 0, s, G.desc, np, I0.n,
+                       I0.P, P0->modes, reinterpret_cast<const double*>(G.ws + G.L.o_mpart), diag ? mom : raw, ns,
+                       diag ? 1 : 0, patch_of_slot(G));
   if (!diag)
-    hipLaunchKernelGGL(moments_gram_kernel, dim3(unsigned((work + 255) / 256)), dim3(256), 0, s, raw, P0->gram_inv,
+    hipLaunchKernelGGL(moments_gram_kernel, dim3(unsigned((all + 255) / 256)), dim3(256), 0, s, raw, P0->gram_inv,
                        I0.K, mom, G.L.total);
 }
 
@@ -1759,6 +1806,43 @@ static void launch_gauss_moments(const Group& G, hipStream_t s, const AnalyticIn
   }
 }
 
+// A plan that keeps its live patches only (max_live): flag the patches that
+// carry charge, wait for the flags, and number the live patches in order as
+// the slots of the per-patch buffers.  The one host synchronisation of such
+// a solve; the lists go back to the device before any kernel reads them.
+static mlc_status compact_live(const Group& G, hipStream_t s) {
+  const mlc_plan* P0 = G.plans[0];
+  const Layout& L = G.L;
+  const int np = int(G.plans.size());
+  int* live = reinterpret_cast<int*>(G.ws + L.o_live);
+  {
+    TimedScope ts(P0, s, "patch_live");
+    hipLaunchKernelGGL(patch_live_kernel, dim3(L.total), dim3(256), 0, s, G.desc, np, P0->info.n, live, 0);
+  }
+  std::vector<int> flag(L.total), patch_of, slot_of(L.total, -1);
+  hipError_t e = hipMemcpyAsync(flag.data(), live, sizeof(int) * L.total, hipMemcpyDeviceToHost, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  if (e != hipSuccess) return fail(P0->ctx, MLC_ERR_DEVICE, std::string("live patches: ") + hipGetErrorString(e));
+  for (int p = 0; p < L.total; ++p)
+    if (flag[p]) {
+      slot_of[p] = int(patch_of.size());
+      patch_of.push_back(p);
+    }
+  if (int(patch_of.size()) > L.slots)
+    return fail(P0->ctx, MLC_ERR_OUT_OF_MEMORY,
+                std::to_string(patch_of.size()) + " patches carry charge, more than max_live = " +
+                    std::to_string(L.slots));
+  if (!patch_of.empty())
+    e = hipMemcpyAsync(G.ws + L.o_patch_of, patch_of.data(), sizeof(int) * patch_of.size(), hipMemcpyHostToDevice, s);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(G.ws + L.o_slot_of, slot_of.data(), sizeof(int) * L.total, hipMemcpyHostToDevice, s);
+  // the host lists go out of scope on return
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  if (e != hipSuccess) return fail(P0->ctx, MLC_ERR_DEVICE, std::string("live patches: ") + hipGetErrorString(e));
+  G.nslots = int(patch_of.size());
+  return MLC_OK;
+}
+
 // With G.one_stream set, every stage runs on s in the same order (no side
 // stream, no events): the same kernels on the same data, so the same result.
 static mlc_status enqueue_group(const Group& G, hipStream_t s, const AnalyticInput* an) {
@@ -1771,6 +1855,10 @@ static mlc_status enqueue_group(const Group& G, hipStream_t s, const AnalyticInp
     launch_box_in(G, s);
     if (an) launch_analytic_fill(G, s, *an);
     launch_sixth_rhs(G, s);
+    if (G.L.compact) {
+      const mlc_status r = compact_live(G, s);
+      if (r != MLC_OK) return r;
+    }
     if (!(f32 ? dispatch_conv<float>(G, s, 0) : dispatch_conv<double>(G, s, 0)))
       return fail(P0->ctx, MLC_ERR_UNSUPPORTED, "local FFT size not built");
     if (an) launch_gauss_moments(G, s, *an);
@@ -1793,6 +1881,10 @@ static mlc_status enqueue_group(const Group& G, hipStream_t s, const AnalyticInp
   launch_box_in(G, s);
   if (an) launch_analytic_fill(G, s, *an);
   launch_sixth_rhs(G, s);
+  if (G.L.compact) {
+    const mlc_status r = compact_live(G, s);
+    if (r != MLC_OK) return r;
+  }
   // the x-DFT pass of the local convolutions also leaves the per-plane
   // moment sums, finished here before the far-field sums read the moments
   const bool ok = fp32 ? dispatch_conv<float>(G, s, 0) : dispatch_conv<double>(G, s, 0);
@@ -2074,6 +2166,8 @@ extern "C" mlc_status mlc_solve_analytic(mlc_plan* plan, int32_t nterms, const m
 // is created.  Calls that overlap on one device share the scratch and race.
 extern "C" mlc_status mlc_solve_static(mlc_plan* plan, const double* f, double* phi, void* stream) {
   if (!plan || !f || !phi) return fail(plan ? plan->ctx : nullptr, MLC_ERR_INVALID_ARG, "null argument");
+  if (plan->info.slots < plan->info.npatch)
+    return fail(plan->ctx, MLC_ERR_UNSUPPORTED, "a plan with max_live waits for its live-patch count: use mlc_solve");
   if (plan->ws_total > kStaticScratchBytes)
     return fail(plan->ctx, MLC_ERR_UNSUPPORTED,
                 "the plan's workspace (" + std::to_string(plan->ws_total) + " bytes) exceeds the static scratch (" +
@@ -2098,6 +2192,10 @@ static mlc_status make_groups(int32_t count, mlc_plan* const* plans, std::vector
   if (count <= 0 || !plans || !bytes) return fail(nullptr, MLC_ERR_INVALID_ARG, "bad batch arguments");
   for (int k = 0; k < count; ++k)
     if (!plans[k]) return fail(nullptr, MLC_ERR_INVALID_ARG, "null plan in batch");
+  for (int k = 0; k < count; ++k)
+    if (plans[k]->info.slots < plans[k]->info.npatch)
+      return fail(plans[k]->ctx, MLC_ERR_UNSUPPORTED,
+                  "a plan with max_live solves alone (mlc_solve, mlc_solve_analytic), not in batches or graphs");
   mlc_context* ctx = plans[0]->ctx;
   for (int k = 1; k < count; ++k)
     if (plans[k]->ctx != ctx) return fail(ctx, MLC_ERR_INVALID_ARG, "plans of one batch must share a context");

@@ -396,6 +396,10 @@ extern "C" mlc_status mlc_server_create(mlc_context* ctx, const mlc_server_confi
 
 extern "C" mlc_status mlc_server_prepare(mlc_server* srv, const mlc_problem* prob) {
   if (!srv || !prob) return MLC_ERR_INVALID_ARG;
+  if (prob->max_live > 0) {
+    mlc_set_error(srv->ctx, "the server batches its requests: max_live plans solve alone (mlc_solve)");
+    return MLC_ERR_UNSUPPORTED;
+  }
   mlc_status st = MLC_OK;
   return plan_for(srv, *prob, &st) ? MLC_OK : st;
 }
@@ -403,6 +407,10 @@ extern "C" mlc_status mlc_server_prepare(mlc_server* srv, const mlc_problem* pro
 extern "C" mlc_status mlc_server_submit(mlc_server* srv, const mlc_problem* prob, const double* f, double* phi,
                                         uint64_t* ticket) {
   if (!srv || !prob || !f || !phi || !ticket) return MLC_ERR_INVALID_ARG;
+  if (prob->max_live > 0) {
+    mlc_set_error(srv->ctx, "the server batches its requests: max_live plans solve alone (mlc_solve)");
+    return MLC_ERR_UNSUPPORTED;
+  }
   mlc_plan_info info{};
   mlc_status st = mlc_problem_info(prob, &info);
   if (st != MLC_OK) return st;

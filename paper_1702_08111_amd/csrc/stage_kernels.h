@@ -22,14 +22,17 @@ namespace mlc {
 // thread per (patch, mode).
 __global__ void __launch_bounds__(256) moments_finish_kernel(const ProbDesc* __restrict__ pd, int nprob, int n,
                                                              int P, ModeList modes, const double* __restrict__ part,
-                                                             double* __restrict__ out, int total, int diag) {
+                                                             double* __restrict__ out, int total, int diag,
+                                                             const int* __restrict__ patch_of) {
   const int64_t idx = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
   if (idx >= int64_t(total) * modes.K) return;
-  const int p = int(idx / modes.K), k = int(idx % modes.K);
+  // one thread per (slot, mode); the slot's patch owns the output row
+  const int slot = int(idx / modes.K), k = int(idx % modes.K);
+  const int p = patch_of ? patch_of[slot] : slot;
   const ProbDesc& D = pd[find_problem(pd, nprob, p)];
   const int a0 = modes.p[k][0], a1 = modes.p[k][1], a2 = modes.p[k][2];
   const int S = n + 1, PP = P * P;
-  const double* pp = part + int64_t(p) * S * PP + P * a1 + a2;
+  const double* pp = part + int64_t(slot) * S * PP + P * a1 + a2;
   double s = 0.0, mu0 = 0.0, mu1 = 0.0, mu2 = 0.0;
   for (int j = 0; j < S; ++j) {
     const double t = (j - 0.5 * n) / (0.5 * n), w = boole_w(j, n);
@@ -39,7 +42,7 @@ __global__ void __launch_bounds__(256) moments_finish_kernel(const ProbDesc* __r
     mu1 += w * q1 * q1;
     mu2 += w * q2 * q2;
   }
-  out[idx] = diag ? D.R15 * s / (mu0 * mu1 * mu2) : D.R15 * s;
+  out[int64_t(p) * modes.K + k] = diag ? D.R15 * s / (mu0 * mu1 * mu2) : D.R15 * s;
 }
 
 // c = Gram^{-1} m per patch (P >= 5, where the Boole Gram matrix of the modes
@@ -100,6 +103,7 @@ template <typename T> struct CoarseRhsProb {
   double* F;           // its F^H
   CoarseGeom g;
   int64_t start;
+  const int* slot_of;  // patch -> its slot in lap (-1: an empty patch, no slot), or null (slot = patch)
 };
 
 // Delta^H of each patch's coarse samples at the points r in [b, Wc - b)^3 of
@@ -183,8 +187,9 @@ __global__ void __launch_bounds__(256) coarse_rhs_kernel(const CoarseRhsProb<T>*
         v[j1][j2] = 0.0;
         if (a1 <= hi[1] && a2 <= hi[2]) {
           const int i0 = c[0] - q * a0 + o, i1 = c[1] - q * a1 + o, i2 = c[2] - q * a2 + o;
-          const int pidx = (a0 * g.ppa + a1) * g.ppa + a2;
-          v[j1][j2] = lap[(int64_t(pidx) * Li + i0) * Li * Li + int64_t(i1) * Li + i2];
+          int pidx = (a0 * g.ppa + a1) * g.ppa + a2;
+          if (pb.slot_of) pidx = pb.slot_of[pidx];
+          if (pidx >= 0) v[j1][j2] = lap[(int64_t(pidx) * Li + i0) * Li * Li + int64_t(i1) * Li + i2];
         }
       }
 #pragma unroll
@@ -444,6 +449,7 @@ template <typename T> struct SkelProb {
   double* phi;
   SkelGeom g;
   int64_t start;
+  const int* slot_of;  // patch -> its slot in delta (-1: an empty patch), or null (slot = patch)
 };
 
 // ---------------------------------------------- annulus sums on MFMA ----
@@ -894,9 +900,10 @@ __global__ void __launch_bounds__(256) skeleton_kernel(const SkelProb<T>* __rest
             const bool valid = i2b + t2 <= hi[2];
             const int i2 = valid ? i2b + t2 : hi[2];
             const int r[3] = {gg[0] - n * i0, gg[1] - n * i1, gg[2] - n * i2};
-            const int pidx = (i0 * g.ppa + i1) * g.ppa + i2;
+            int pidx = (i0 * g.ppa + i1) * g.ppa + i2;
+            if (pb.slot_of) pidx = pb.slot_of[pidx];
             const int jj = (r[d] - g.P0) / n;
-            const double x =
+            const double x = pidx < 0 ? 0.0 :
                 double(delta[((((int64_t(pidx) * 3 + d) * g.npl + jj) * Wa + (r[a0] + g.da)) * Wa) + (r[a1] + g.da)]);
             sd += valid ? x : 0.0;
           }
@@ -954,9 +961,10 @@ __global__ void __launch_bounds__(256) skeleton_kernel(const SkelProb<T>* __rest
 //   2: slabs of fixed index 0: S X S (times (2/n)^2), then
 //      phi = u + C2 h^2 f on the patch interior
 struct DirGeom {
-  int n, npatch;
-  double scale;   // 2/n
+  int n, npatch;   // patches of this launch: p0 .. p0 + npatch - 1
+  double scale;    // 2/n
   Stencil st;
+  int p0;
 };
 
 // Orders one wave's LDS writes before its later LDS reads by other lanes
@@ -1017,8 +1025,9 @@ __global__ void __launch_bounds__(64 * DIR_WAVES) dirichlet_mfma_kernel(const Pr
     Sm[k * 33 + j] = (k < m && j < m) ? sn[((k + 1) * (j + 1)) % (2 * g.n)] : 0.0;
   }
   const int slab = blockIdx.x * DIR_WAVES + wave;     // over patches x m
-  const int p = slab / m, u = slab % m;
-  const bool live = p < g.npatch;
+  const int pw = slab / m, u = slab % m;               // pw: the patch's slot in the work array
+  const int p = g.p0 + pw;
+  const bool live = pw < g.npatch;
   const ProbDesc& D = pd[find_problem(pd, nprob, live ? p : 0)];
   const auto* f = gbl(D.f);
   const auto* phiB = gbl(D.phiB);
@@ -1032,7 +1041,7 @@ __global__ void __launch_bounds__(64 * DIR_WAVES) dirichlet_mfma_kernel(const Pr
     if (PASS == 1) return int64_t(i) * m * m + int64_t(u) * m + j;
     return int64_t(u) * m * m + int64_t(i) * m + j;
   };
-  double* wp = work + int64_t(p) * M3;
+  double* wp = work + int64_t(pw) * M3;
   const int i0 = pl / (ppa * ppa), i1 = (pl / ppa) % ppa, i2 = pl % ppa;
   const int64_t Np = D.N + 1;
   const int64_t pbase = (int64_t(g.n) * i0) * Np * Np + int64_t(g.n) * i1 * Np + int64_t(g.n) * i2;

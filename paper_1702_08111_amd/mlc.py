@@ -56,6 +56,7 @@ class mlc_problem(ctypes.Structure):
         ("skip_empty", ctypes.c_int32),
         ("box_cells", ctypes.c_int32 * 3),
         ("origin", ctypes.c_double * 3),
+        ("max_live", ctypes.c_int32),
     ]
 
 
@@ -79,7 +80,8 @@ class mlc_plan_info(ctypes.Structure):
                               ("level_N", ctypes.c_int32), ("alpha", ctypes.c_double),
                               ("beta", ctypes.c_double), ("level_alpha", ctypes.c_double * 3),
                               ("rhs_order", ctypes.c_int32), ("skip_empty", ctypes.c_int32),
-                              ("box", ctypes.c_int32 * 3), ("origin", ctypes.c_double * 3)]
+                              ("box", ctypes.c_int32 * 3), ("origin", ctypes.c_double * 3),
+                              ("slots", ctypes.c_int32)]
 
     def as_dict(self):
         d = {k: getattr(self, k) for k, _ in self._fields_}
@@ -196,7 +198,7 @@ def _stream(s):
 
 
 def problem(N, n, alpha=3.0, beta=6.0, P=4, Q=4, b=0, h=None, conv="fp32", fft_size=0, Z=0, levels=0,
-            level_alpha=(), rhs_order=0, skip_empty=0, origin=(0.0, 0.0, 0.0)):
+            level_alpha=(), rhs_order=0, skip_empty=0, origin=(0.0, 0.0, 0.0), max_live=0):
     """N: cells per axis of a cube, or a triple (B0, B1, B2) for a box domain
     (h then defaults to 1 / max B_d)."""
     la = list(level_alpha) + [0.0] * (3 - len(level_alpha))
@@ -209,7 +211,7 @@ def problem(N, n, alpha=3.0, beta=6.0, P=4, Q=4, b=0, h=None, conv="fp32", fft_s
     return mlc_problem(ncells, hh, n, alpha, beta, P, Q, b,
                        MLC_CONV_FP32 if conv == "fp32" else MLC_CONV_FP64, fft_size, Z, levels,
                        (ctypes.c_double * 3)(*la[:3]), rhs_order, skip_empty, (ctypes.c_int32 * 3)(*box),
-                       (ctypes.c_double * 3)(*[float(x) for x in origin]))
+                       (ctypes.c_double * 3)(*[float(x) for x in origin]), max_live)
 
 
 def problem_workspace_bytes(prob):

@@ -174,3 +174,24 @@ def test_box_domain_sizes():
     # the workspace holds f and phi in the enclosing cube besides the cube's own
     extra = mlc.problem_workspace_bytes(mlc.problem((64, 48, 32), 16)) - mlc.problem_workspace_bytes(mlc.problem(64, 16))
     assert 2 * 65 ** 3 * 8 <= extra < 2 * 65 ** 3 * 8 + 1024
+
+
+def test_max_live_sizes():
+    """max_live keeps per-patch convolution buffers for that many patches only
+    (at most npatch) and turns on skip_empty; the Dirichlet work array is
+    chunked at 4 GB, so at 2048^3 with four levels the workspace fits one GPU
+    beside f and phi."""
+    base = mlc.problem(128, 16, 3.0, 6.0, 4, 4)
+    cap = mlc.problem(128, 16, 3.0, 6.0, 4, 4, max_live=40)
+    ib, ic = mlc.problem_info(base), mlc.problem_info(cap)
+    assert ib["slots"] == ib["npatch"] == 512 and ib["skip_empty"] == 0
+    assert ic["slots"] == 40 and ic["skip_empty"] == 1
+    assert mlc.problem_workspace_bytes(cap) < mlc.problem_workspace_bytes(base) / 2
+    assert mlc.problem_info(mlc.problem(128, 16, max_live=10 ** 6))["slots"] == 512
+    with pytest.raises(mlc.MLCError) as ei:
+        mlc.problem_info(mlc.problem(128, 16, max_live=-1))
+    assert ei.value.status == mlc.MLC_ERR_INVALID_ARG
+    big = mlc.problem(2048, 32, 1.75, 3.25, 4, 6, conv="fp32", levels=4, level_alpha=(2.0, 2.25), max_live=4096)
+    ws = mlc.problem_workspace_bytes(big)
+    nodes = 8 * 2049 ** 3
+    assert ws + 2 * nodes < 270 * 2 ** 30, ws / 2 ** 30
