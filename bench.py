@@ -44,6 +44,9 @@ def parse():
                     help="timed solves per multilevel workload (512^3 three levels, 1024^3 four levels); 0 skips")
     ap.add_argument("--osc-steps", type=int, default=5,
                     help="timed steps of the oscillatory 384^3 workload per path (0: skip)")
+    ap.add_argument("--paper-2048", action="store_true",
+                    help="instead of the headline line: the oscillatory charges of sec. 7.2 at 2048^3 with four "
+                         "levels, Tables 12 and 14's settings (P = 1 and 4), errors over every node")
     return ap.parse_args()
 
 
@@ -376,6 +379,87 @@ def multilevel_bench(ctx, steps, dev):
     return out
 
 
+def _osc_live_patches(N, n):
+    """Patches of an N^3 grid of n^3-cell patches holding a node strictly inside
+    one of the oscillatory charges' balls (other than its centre): the
+    patches with charge."""
+    ppa = N // n
+    live = np.zeros((ppa,) * 3, dtype=bool)
+    for c in mi.OSC_CENTRES:
+        lo = [max(int(np.floor((c[d] - mi.OSC_RO) * N)), 0) for d in range(3)]
+        hi = [min(int(np.ceil((c[d] + mi.OSC_RO) * N)), N) for d in range(3)]
+        ax = [np.arange(lo[d], hi[d] + 1) for d in range(3)]
+        r = np.sqrt(((ax[0] / N - c[0]) ** 2)[:, None, None] + ((ax[1] / N - c[1]) ** 2)[None, :, None]
+                    + ((ax[2] / N - c[2]) ** 2)[None, None, :]) / mi.OSC_RO
+        idx = np.argwhere((r < 1.0) & (r > 0.0)) + np.asarray(lo)
+        # a node on a patch face belongs to the patches on both sides
+        for s0 in (0, 1):
+            for s1 in (0, 1):
+                for s2 in (0, 1):
+                    q = (idx - np.asarray([s0, s1, s2])) // n
+                    ok = np.all((q >= 0) & (q < ppa) & ((idx % n == 0) | (np.asarray([s0, s1, s2]) == 0)), axis=1)
+                    live[tuple(q[ok].T)] = True
+    return int(live.sum())
+
+
+def oscillatory_2048_study(ctx, dev, steps=2):
+    """The oscillatory charges of sec. 7.2 at 2048^3 (32^3-cell patches, L27,
+    beta 3.25, four levels), the settings of Tables 12 (alpha 1.75 at every
+    level) and 14 (1.75, 2, 2.25 from the finest level up), P = 1 and 4, float64
+    local convolutions.  The plans keep per-patch buffers for the live patches
+    only (max_live); the error is the scaled maximum over every node of the
+    finest level against the closed form, evaluated on the device in slabs."""
+    import torch
+    from paper_1702_08111_amd import mlc as gm
+    N, n = 2048, 32
+    live = _osc_live_patches(N, n)
+    cap = 1024
+    progress(f"2048^3: {live} of {(N // n) ** 3} patches carry charge; buffers for {cap}")
+    settings = [("table_14", (2.0, 2.25)), ("table_12", (1.75, 1.75))]
+    probs = {(t, P): gm.problem(N, n, 1.75, 3.25, P, 6, conv="fp64", levels=4, level_alpha=la, max_live=cap)
+             for t, la in settings for P in (1, 4)}
+    ws_bytes = max(gm.problem_workspace_bytes(p) for p in probs.values())
+    ws = torch.empty(ws_bytes, dtype=torch.uint8, device=dev)
+    f = torch.empty((N + 1,) * 3, dtype=torch.float64, device=dev)
+    phi = torch.empty_like(f)
+    ax = torch.arange(N + 1, dtype=torch.float64, device=dev) / N
+    out = {"config": "oscillatory charges (sec. 7.2), 2048^3, 32^3-cell patches, L27, beta 3.25, 4 levels, float64 "
+                     "local convolutions, charge sampled on the device from its radial terms, Boole moments; "
+                     "error = max over all nodes |phi - closed form| / max |closed form|",
+           "live_patches": live, "max_live": cap, "workspace_GiB": ws_bytes / 2 ** 30}
+    for (table, P), prob in probs.items():
+        plan = ctx.plan(prob)
+        # the library samples the radial terms into f; then plain solves of that f
+        plan.solve_analytic(mi.oscillatory_terms(), 2, f, phi, ws)
+        plan.solve(f, phi, ws)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            plan.solve(f, phi, ws)
+        torch.cuda.synchronize()
+        ms = (time.perf_counter() - t0) * 1e3 / steps
+        err = scale = 0.0
+        for k0 in range(0, N + 1, 8):
+            k1 = min(k0 + 8, N + 1)
+            exact = torch.zeros((k1 - k0, N + 1, N + 1), dtype=torch.float64, device=dev)
+            for c in mi.OSC_CENTRES:
+                r = torch.sqrt(((ax[k0:k1] - c[0]) ** 2)[:, None, None] + ((ax - c[1]) ** 2)[None, :, None]
+                               + ((ax - c[2]) ** 2)[None, None, :]) / mi.OSC_RO
+                exact += mi._osc_psi(r, xp=torch) / mi.OSC_RO
+                del r
+            err = max(err, float((phi[k0:k1] - exact).abs().max()))
+            scale = max(scale, float(exact.abs().max()))
+            del exact
+        row = {"ms_per_step": ms, "value": N ** 3 / (ms * 1e-3), "unit": "grid points/s",
+               "level_alpha": list(plan.info["level_alpha"][:2]), "error": err / scale}
+        out.setdefault(table, {})[f"P{P}"] = row
+        progress(f"2048^3 {table} P={P}: {ms:.1f} ms/solve, error {err / scale:.5e}")
+        plan.close()
+    del ws, f, phi
+    torch.cuda.empty_cache()
+    return out
+
+
 SWEEP = [
     # (alpha, beta, P, Q, b): MLC-0 (beta = alpha) and MLC, the 19- and 27-point operators
     (1.5, 1.5, 4, 4, 2), (3.0, 3.0, 4, 4, 2), (1.5, 3.0, 4, 4, 2), (1.5, 6.0, 4, 4, 2), (3.0, 6.0, 4, 4, 2),
@@ -541,6 +625,10 @@ def main():
     import torch
     from paper_1702_08111_amd import mlc as gm
 
+    if args.paper_2048:
+        study = oscillatory_2048_study(gm.Context(0), torch.device("cuda:0"))
+        print(json.dumps({"study": "oscillatory_2048_four_levels", **study}), flush=True)
+        return
     N, n, Q, bumps = mi.workload(args.workload)
     f_np = mi.bump_charge(N, bumps)
     exact = mi.bump_potential(N, bumps)

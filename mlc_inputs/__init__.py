@@ -153,12 +153,13 @@ def _osc_profile(r, g=OSC_GAMMA):
     return np.where(r < 1.0, (r - r * r) ** 2 * np.sin(0.5 * g * r) ** 2, 0.0)
 
 
-def _osc_psi(r, g=OSC_GAMMA):
+def _osc_psi(r, g=OSC_GAMMA, xp=np):
     """The dimensionless potential of one oscillatory charge (sec. 7.2): the
-    potential is psi(|x - x_o| / Ro) / Ro."""
-    r = np.asarray(r, dtype=np.float64)
-    rs = np.where(r > 0, r, 1.0)
-    c, sn = np.cos(g * rs), np.sin(g * rs)
+    potential is psi(|x - x_o| / Ro) / Ro.  xp: the array module (numpy, or
+    torch for device arrays)."""
+    r = xp.asarray(r, dtype=xp.float64)
+    rs = xp.where(r > 0, r, 1.0)
+    c, sn = xp.cos(g * rs), xp.sin(g * rs)
     inside = (rs ** 6 / 84 - rs ** 5 / 30 + rs ** 4 / 40 + 60 / g ** 6 - 9 / g ** 4 - 1 / 120 + 120 / (g ** 6 * rs)
               + (-120 / (g ** 6 * rs) - 9 / g ** 4 + 300 / g ** 6 + 36 * rs / g ** 4 + rs ** 2 / (2 * g ** 2)
                  - 30 * rs ** 2 / g ** 4 - rs ** 3 / g ** 2 + rs ** 4 / (2 * g ** 2)) * c
@@ -166,7 +167,7 @@ def _osc_psi(r, g=OSC_GAMMA):
                  + 8 * rs ** 2 / g ** 3 - 5 * rs ** 3 / g ** 3) * sn)
     outside = (-1.0 / 210 - 12 / g ** 4 + 360 / g ** 6) / rs
     at0 = -1.0 / 120 - 6 / g ** 4
-    return np.where(r == 0, at0, np.where(r < 1.0, inside, outside))
+    return xp.where(r == 0, at0, xp.where(r < 1.0, inside, outside))
 
 
 def oscillatory_charge(N):

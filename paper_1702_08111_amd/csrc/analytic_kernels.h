@@ -42,13 +42,15 @@ __device__ __forceinline__ double term_value(const RadialTerm& t, double x0, dou
 
 // f at the (N+1)^3 nodes g h (C order, axis 2 fastest)
 __global__ void analytic_fill_kernel(RadialCharge q, int N, double h, double* __restrict__ f) {
-  const int64_t idx = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
   const int64_t Np = N + 1;
-  if (idx >= Np * Np * Np) return;
-  const int g2 = int(idx % Np), g1 = int((idx / Np) % Np), g0 = int(idx / (Np * Np));
-  double v = 0.0;
-  for (int k = 0; k < q.count; ++k) v += term_value(q.t[k], g0 * h, g1 * h, g2 * h);
-  f[idx] = v;
+  // grid-stride: (N+1)^3 can exceed the threads of one launch
+  for (int64_t idx = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; idx < Np * Np * Np;
+       idx += int64_t(gridDim.x) * blockDim.x) {
+    const int g2 = int(idx % Np), g1 = int((idx / Np) % Np), g0 = int(idx / (Np * Np));
+    double v = 0.0;
+    for (int k = 0; k < q.count; ++k) v += term_value(q.t[k], g0 * h, g1 * h, g2 * h);
+    f[idx] = v;
+  }
 }
 
 // Composite Gauss-Legendre rule: gp points per cell, nodes xi and weights

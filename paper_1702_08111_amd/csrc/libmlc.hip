@@ -357,6 +357,11 @@ static mlc_status derive(const mlc_problem* p, mlc_plan_info* o, std::string* wh
   I.d_beta = margin_of(p->beta, I.n);
   if (I.d_alpha % NREF || I.d_beta % NREF) { *why = "localisation margins must be multiples of 4"; return MLC_ERR_UNSUPPORTED; }
   if (I.d_alpha > I.n) { *why = "alpha > 3 is not built"; return MLC_ERR_UNSUPPORTED; }
+  // the skeleton kernels take one thread per skeleton node in one launch
+  if (int64_t(3) * (I.N / I.n + 1) * (I.N + 1) * (I.N + 1) >= (int64_t(1) << 31)) {
+    *why = "grid too large: the skeleton exceeds one launch";
+    return MLC_ERR_UNSUPPORTED;
+  }
   I.e = I.d_alpha + NREF * I.b;
   I.patches_per_axis = I.N / I.n;
   I.npatch = I.patches_per_axis * I.patches_per_axis * I.patches_per_axis;
@@ -466,6 +471,11 @@ extern "C" mlc_status mlc_context_destroy(mlc_context* ctx) {
 }
 
 static inline unsigned blocks_for(int64_t n, int t = 256) { return unsigned((n + t - 1) / t); }
+// Blocks of 256 for the grid-stride kernels over node arrays: at most 2^20
+// (one launch holds fewer than 2^32 threads; (N+1)^3 reaches 8.6e9 at 2048^3)
+static inline unsigned flat_blocks(int64_t n) {
+  return unsigned(std::max<int64_t>(1, std::min<int64_t>((n + 255) / 256, int64_t(1) << 20)));
+}
 
 // ----------------------------------------------------- generic 3-D FFT
 template <int M>
@@ -1302,9 +1312,9 @@ static void launch_box_in(const Group& G, hipStream_t s) {
     if (!is_boxed(I)) continue;
     double* fc = const_cast<double*>(input_of(G, int(k)));
     const int64_t nc = cube(I.N + 1);
-    hipLaunchKernelGGL(fill_zero_kernel, dim3(blocks_for(nc)), dim3(256), 0, s, fc, nc);
+    hipLaunchKernelGGL(fill_zero_kernel, dim3(flat_blocks(nc)), dim3(256), 0, s, fc, nc);
     const int64_t nb = int64_t(I.box[0] + 1) * (I.box[1] + 1) * (I.box[2] + 1);
-    hipLaunchKernelGGL(box3_copy_kernel, dim3(blocks_for(nb)), dim3(256), 0, s, G.f[k], I.box[0] + 1, I.box[1] + 1,
+    hipLaunchKernelGGL(box3_copy_kernel, dim3(flat_blocks(nb)), dim3(256), 0, s, G.f[k], I.box[0] + 1, I.box[1] + 1,
                        I.box[2] + 1, fc, I.N + 1, I.N + 1, I.N + 1, I.box[0] + 1, I.box[1] + 1, I.box[2] + 1);
   }
 }
@@ -1313,7 +1323,7 @@ static void launch_box_out(const Group& G, hipStream_t s) {
     const mlc_plan_info& I = G.plans[k]->info;
     if (!is_boxed(I)) continue;
     const int64_t nb = int64_t(I.box[0] + 1) * (I.box[1] + 1) * (I.box[2] + 1);
-    hipLaunchKernelGGL(box3_copy_kernel, dim3(blocks_for(nb)), dim3(256), 0, s, phi_of(G, int(k)), I.N + 1, I.N + 1,
+    hipLaunchKernelGGL(box3_copy_kernel, dim3(flat_blocks(nb)), dim3(256), 0, s, phi_of(G, int(k)), I.N + 1, I.N + 1,
                        I.N + 1, G.phi[k], I.box[0] + 1, I.box[1] + 1, I.box[2] + 1, I.box[0] + 1, I.box[1] + 1,
                        I.box[2] + 1);
   }
@@ -1342,7 +1352,7 @@ static void launch_sixth_rhs(const Group& G, hipStream_t s) {
   for (size_t k = 0; k < G.plans.size(); ++k) {
     const mlc_plan_info& I = G.plans[k]->info;
     if (I.rhs_order != 6) continue;
-    hipLaunchKernelGGL(sixth_rhs_kernel, dim3(blocks_for(cube(I.N + 1))), dim3(256), 0, s, input_of(G, int(k)), I.N,
+    hipLaunchKernelGGL(sixth_rhs_kernel, dim3(flat_blocks(cube(I.N + 1))), dim3(256), 0, s, input_of(G, int(k)), I.N,
                        const_cast<double*>(charge_of(G, int(k))));
   }
 }
@@ -1419,8 +1429,8 @@ static void launch_conv(const Group& G, hipStream_t s, int phase, const std::fun
       if (kspl > 1) {
         // the blocks of a plane add their partial outputs: start from zero
         const int64_t nc = cube(I.Wc), npl = int64_t(3) * I.nplanes_a * I.Wa * I.Wa;
-        hipLaunchKernelGGL(fill_zero_t_kernel<T>, dim3(blocks_for(nc * cnt)), dim3(256), 0, s, cs + p0 * nc, nc * cnt);
-        hipLaunchKernelGGL(fill_zero_t_kernel<T>, dim3(blocks_for(npl * cnt)), dim3(256), 0, s, pl + p0 * npl,
+        hipLaunchKernelGGL(fill_zero_t_kernel<T>, dim3(flat_blocks(nc * cnt)), dim3(256), 0, s, cs + p0 * nc, nc * cnt);
+        hipLaunchKernelGGL(fill_zero_t_kernel<T>, dim3(flat_blocks(npl * cnt)), dim3(256), 0, s, pl + p0 * npl,
                            npl * cnt);
       }
       const dim3 grid((P->Wp + zpb - 1) / zpb * kspl, cnt);
@@ -1474,7 +1484,7 @@ static mlc_status launch_rest(const Group& G, hipStream_t s, Stage stage) {
   if (stage == FAR) {
     // F^H starts at zero: the coarse far-field sums and the inner part add
     for (int k = 0; k < np; ++k)
-      hipLaunchKernelGGL(fill_zero_kernel, dim3(blocks_for(cube(G.plans[k]->info.Ns))), dim3(256), 0, s, F_of(k),
+      hipLaunchKernelGGL(fill_zero_kernel, dim3(flat_blocks(cube(G.plans[k]->info.Ns))), dim3(256), 0, s, F_of(k),
                          cube(G.plans[k]->info.Ns));
   }
   // coarse right-hand side, every problem in one launch
@@ -1647,7 +1657,7 @@ static mlc_status launch_rest(const Group& G, hipStream_t s, Stage stage) {
       const int m = I.level_margin, E = I.level_N + 1;
       double* f1 = reinterpret_cast<double*>(G.ws + L.o_lf[k]);
       double* phi1 = reinterpret_cast<double*>(G.ws + L.o_lphi[k]);
-      hipLaunchKernelGGL(fill_zero_kernel, dim3(blocks_for(cube(E))), dim3(256), 0, s, f1, cube(E));
+      hipLaunchKernelGGL(fill_zero_kernel, dim3(flat_blocks(cube(E))), dim3(256), 0, s, f1, cube(E));
       hipLaunchKernelGGL(box_copy_kernel, dim3(blocks_for(cube(I.Ns))), dim3(256), 0, s, F_of(k), I.Ns, 0, f1, E,
                          I.S_lo + m, I.Ns);
       Group G1;
@@ -1762,7 +1772,7 @@ static void launch_moments(const Group& G, hipStream_t s) {
   double* raw = reinterpret_cast<double*>(G.ws + G.L.o_mraw);
   // compact buffers: the empty patches' moments are zero, the others are set below
   if (G.L.compact)
-    hipLaunchKernelGGL(fill_zero_kernel, dim3(blocks_for(all)), dim3(256), 0, s, diag ? mom : raw, all);
+    hipLaunchKernelGGL(fill_zero_kernel, dim3(flat_blocks(all)), dim3(256), 0, s, diag ? mom : raw, all);
   if (work > 0)
     hipLaunchKernelGGL(moments_finish_kernel, dim3(unsigned((work + 255) / 256)), dim3(256), 0, s, G.desc, np, I0.n,
                        I0.P, P0->modes, reinterpret_cast<const double*>(G.ws + G.L.o_mpart), diag ? mom : raw, ns,
@@ -1783,7 +1793,7 @@ struct AnalyticInput {
 static void launch_analytic_fill(const Group& G, hipStream_t s, const AnalyticInput& an) {
   const mlc_plan_info& I = G.plans[0]->info;
   const int64_t nodes = cube(I.N + 1);
-  hipLaunchKernelGGL(analytic_fill_kernel, dim3(unsigned((nodes + 255) / 256)), dim3(256), 0, s, an.q, I.N, I.h, an.f);
+  hipLaunchKernelGGL(analytic_fill_kernel, dim3(flat_blocks(nodes)), dim3(256), 0, s, an.q, I.N, I.h, an.f);
 }
 
 static void launch_gauss_moments(const Group& G, hipStream_t s, const AnalyticInput& an) {
@@ -1855,6 +1865,8 @@ static mlc_status enqueue_group(const Group& G, hipStream_t s, const AnalyticInp
     launch_box_in(G, s);
     if (an) launch_analytic_fill(G, s, *an);
     launch_sixth_rhs(G, s);
+    if (const hipError_t e0 = hipGetLastError(); e0 != hipSuccess)
+      return fail(P0->ctx, MLC_ERR_DEVICE, std::string("launch: ") + hipGetErrorString(e0));
     if (G.L.compact) {
       const mlc_status r = compact_live(G, s);
       if (r != MLC_OK) return r;
@@ -1881,6 +1893,9 @@ static mlc_status enqueue_group(const Group& G, hipStream_t s, const AnalyticInp
   launch_box_in(G, s);
   if (an) launch_analytic_fill(G, s, *an);
   launch_sixth_rhs(G, s);
+  // the launches so far, checked before the API calls that follow
+  if (const hipError_t e0 = hipGetLastError(); e0 != hipSuccess)
+    return fail(P0->ctx, MLC_ERR_DEVICE, std::string("launch: ") + hipGetErrorString(e0));
   if (G.L.compact) {
     const mlc_status r = compact_live(G, s);
     if (r != MLC_OK) return r;

@@ -230,12 +230,14 @@ __global__ void boundary_check_kernel(const double* __restrict__ f, int B0, int 
 // and the cube's phi back onto the box.
 __global__ void box3_copy_kernel(const double* __restrict__ src, int s0, int s1, int s2, double* __restrict__ dst,
                                  int d0, int d1, int d2, int w0, int w1, int w2) {
-  const int64_t idx = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-  if (idx >= int64_t(w0) * w1 * w2) return;
-  const int i2 = int(idx % w2), i1 = int((idx / w2) % w1), i0 = int(idx / (int64_t(w1) * w2));
   (void)s0;
   (void)d0;
-  dst[(int64_t(i0) * d1 + i1) * d2 + i2] = src[(int64_t(i0) * s1 + i1) * s2 + i2];
+  // grid-stride: node arrays can exceed 2^32 entries, more than one launch's threads
+  for (int64_t idx = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; idx < int64_t(w0) * w1 * w2;
+       idx += int64_t(gridDim.x) * blockDim.x) {
+    const int i2 = int(idx % w2), i1 = int((idx / w2) % w1), i0 = int(idx / (int64_t(w1) * w2));
+    dst[(int64_t(i0) * d1 + i1) * d2 + i2] = src[(int64_t(i0) * s1 + i1) * s2 + i2];
+  }
 }
 
 // The modified right-hand side of the sixth-order variant for the 27-point
@@ -250,22 +252,24 @@ __global__ void box3_copy_kernel(const double* __restrict__ src, int s0, int s1,
 // f is taken as zero past the node box.  One thread per node.
 __global__ void sixth_rhs_kernel(const double* __restrict__ f, int N, double* __restrict__ ft) {
   const int64_t Np = N + 1;
-  const int64_t idx = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-  if (idx >= Np * Np * Np) return;
-  const int g2 = int(idx % Np), g1 = int((idx / Np) % Np), g0 = int(idx / (Np * Np));
-  auto at = [&](int a, int b, int c) -> double {
-    if (a < 0 || a > N || b < 0 || b > N || c < 0 || c > N) return 0.0;
-    return f[(int64_t(a) * Np + b) * Np + c];
-  };
-  const double ax1 = at(g0 - 1, g1, g2) + at(g0 + 1, g1, g2) + at(g0, g1 - 1, g2) + at(g0, g1 + 1, g2) +
-                     at(g0, g1, g2 - 1) + at(g0, g1, g2 + 1);
-  const double ax2 = at(g0 - 2, g1, g2) + at(g0 + 2, g1, g2) + at(g0, g1 - 2, g2) + at(g0, g1 + 2, g2) +
-                     at(g0, g1, g2 - 2) + at(g0, g1, g2 + 2);
-  double dg = 0.0;
-  for (int s = -1; s <= 1; s += 2)
-    for (int t = -1; t <= 1; t += 2)
-      dg += at(g0 + s, g1 + t, g2) + at(g0 + s, g1, g2 + t) + at(g0, g1 + s, g2 + t);
-  ft[idx] = (67.0 / 120.0) * at(g0, g1, g2) + (1.0 / 18.0) * ax1 - (1.0 / 240.0) * ax2 + (1.0 / 90.0) * dg;
+  // grid-stride over the nodes
+  for (int64_t idx = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; idx < Np * Np * Np;
+       idx += int64_t(gridDim.x) * blockDim.x) {
+    const int g2 = int(idx % Np), g1 = int((idx / Np) % Np), g0 = int(idx / (Np * Np));
+    auto at = [&](int a, int b, int c) -> double {
+      if (a < 0 || a > N || b < 0 || b > N || c < 0 || c > N) return 0.0;
+      return f[(int64_t(a) * Np + b) * Np + c];
+    };
+    const double ax1 = at(g0 - 1, g1, g2) + at(g0 + 1, g1, g2) + at(g0, g1 - 1, g2) + at(g0, g1 + 1, g2) +
+                       at(g0, g1, g2 - 1) + at(g0, g1, g2 + 1);
+    const double ax2 = at(g0 - 2, g1, g2) + at(g0 + 2, g1, g2) + at(g0, g1 - 2, g2) + at(g0, g1 + 2, g2) +
+                       at(g0, g1, g2 - 2) + at(g0, g1, g2 + 2);
+    double dg = 0.0;
+    for (int s = -1; s <= 1; s += 2)
+      for (int t = -1; t <= 1; t += 2)
+        dg += at(g0 + s, g1 + t, g2) + at(g0 + s, g1, g2 + t) + at(g0, g1 + s, g2 + t);
+    ft[idx] = (67.0 / 120.0) * at(g0, g1, g2) + (1.0 / 18.0) * ax1 - (1.0 / 240.0) * ax2 + (1.0 / 90.0) * dg;
+  }
 }
 
 // live[p] = 1 when patch p's node charge (the (n+1)^3 nodes of its closed
@@ -298,13 +302,13 @@ __global__ void __launch_bounds__(256) patch_live_kernel(const ProbDesc* __restr
 
 template <typename T>
 __global__ void fill_zero_t_kernel(T* __restrict__ p, int64_t count) {
-  const int64_t idx = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-  if (idx < count) p[idx] = T(0);
+  for (int64_t idx = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; idx < count; idx += int64_t(gridDim.x) * blockDim.x)
+    p[idx] = T(0);
 }
 
 __global__ void fill_zero_kernel(double* __restrict__ p, int64_t count) {
-  const int64_t idx = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-  if (idx < count) p[idx] = 0.0;
+  for (int64_t idx = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; idx < count; idx += int64_t(gridDim.x) * blockDim.x)
+    p[idx] = 0.0;
 }
 
 // Coarse Hockney solve: F^H on slots [0, Ns)^3 of a zeroed Mc^3 torus.

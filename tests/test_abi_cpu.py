@@ -195,3 +195,12 @@ def test_max_live_sizes():
     ws = mlc.problem_workspace_bytes(big)
     nodes = 8 * 2049 ** 3
     assert ws + 2 * nodes < 270 * 2 ** 30, ws / 2 ** 30
+
+
+def test_grid_launch_limit():
+    """The skeleton kernels take one thread per skeleton node in one launch:
+    grids whose skeleton reaches 2^31 nodes are refused as unsupported."""
+    assert mlc.problem_info(mlc.problem(2048, 32, 1.75, 3.25, 4, 6, levels=4, max_live=1024))["N"] == 2048
+    with pytest.raises(mlc.MLCError) as ei:
+        mlc.problem_info(mlc.problem(4096, 32, 1.75, 3.25, 4, 6, levels=4, max_live=1024))
+    assert ei.value.status == mlc.MLC_ERR_UNSUPPORTED
