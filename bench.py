@@ -40,6 +40,9 @@ def parse():
                     help="measured requests of the serving loop after 50 warm-ups (0: skip)")
     ap.add_argument("--serve-load", type=float, default=0.7, help="arrival rate / saturation rate")
     ap.add_argument("--no-sweep", action="store_true", help="skip the (alpha, beta, P, Q) sweep")
+    ap.add_argument("--no-sparse", action="store_true",
+                    help="skip the headline workload's solves with empty patches skipped (profiles of the dense "
+                         "kernels then see dense launches only)")
     ap.add_argument("--ml-steps", type=int, default=3,
                     help="timed solves per multilevel workload (512^3 three levels, 1024^3 four levels); 0 skips")
     ap.add_argument("--osc-steps", type=int, default=5,
@@ -424,20 +427,11 @@ def oscillatory_2048_study(ctx, dev, steps=2):
     phi = torch.empty_like(f)
     ax = torch.arange(N + 1, dtype=torch.float64, device=dev) / N
     out = {"config": "oscillatory charges (sec. 7.2), 2048^3, 32^3-cell patches, L27, beta 3.25, 4 levels, float64 "
-                     "local convolutions, charge sampled on the device from its radial terms, Boole moments; "
-                     "error = max over all nodes |phi - closed form| / max |closed form|",
+                     "local convolutions, charge sampled on the device from its radial terms, Boole moments "
+                     "(error_gauss_moments: the moments integrated from the radial terms, 2 Gauss points per "
+                     "cell); error = max over all nodes |phi - closed form| / max |closed form|",
            "live_patches": live, "max_live": cap, "workspace_GiB": ws_bytes / 2 ** 30}
-    for (table, P), prob in probs.items():
-        plan = ctx.plan(prob)
-        # the library samples the radial terms into f; then plain solves of that f
-        plan.solve_analytic(mi.oscillatory_terms(), 2, f, phi, ws)
-        plan.solve(f, phi, ws)
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        for _ in range(steps):
-            plan.solve(f, phi, ws)
-        torch.cuda.synchronize()
-        ms = (time.perf_counter() - t0) * 1e3 / steps
+    def scaled_error():
         err = scale = 0.0
         for k0 in range(0, N + 1, 8):
             k1 = min(k0 + 8, N + 1)
@@ -450,10 +444,29 @@ def oscillatory_2048_study(ctx, dev, steps=2):
             err = max(err, float((phi[k0:k1] - exact).abs().max()))
             scale = max(scale, float(exact.abs().max()))
             del exact
+        return err / scale
+
+    for (table, P), prob in probs.items():
+        plan = ctx.plan(prob)
+        # the library samples the radial terms into f and integrates the
+        # moments by Gauss quadrature (two points per cell); then plain solves
+        # of that f (Boole moments of the node data)
+        plan.solve_analytic(mi.oscillatory_terms(), 2, f, phi, ws)
+        torch.cuda.synchronize()
+        err_gauss = scaled_error()
+        plan.solve(f, phi, ws)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            plan.solve(f, phi, ws)
+        torch.cuda.synchronize()
+        ms = (time.perf_counter() - t0) * 1e3 / steps
+        err = scaled_error()
         row = {"ms_per_step": ms, "value": N ** 3 / (ms * 1e-3), "unit": "grid points/s",
-               "level_alpha": list(plan.info["level_alpha"][:2]), "error": err / scale}
+               "level_alpha": list(plan.info["level_alpha"][:2]), "error": err,
+               "error_gauss_moments": err_gauss}
         out.setdefault(table, {})[f"P{P}"] = row
-        progress(f"2048^3 {table} P={P}: {ms:.1f} ms/solve, error {err / scale:.5e}")
+        progress(f"2048^3 {table} P={P}: {ms:.1f} ms/solve, error {err:.5e} (Gauss moments {err_gauss:.5e})")
         plan.close()
     del ws, f, phi
     torch.cuda.empty_cache()
@@ -671,7 +684,7 @@ def main():
     # the same workload with empty patches skipped (exact: an empty patch's
     # local field and moments are zero); reported beside the dense figure
     sparse = {}
-    for conv, ref, steps in (("fp32", phi32, args.steps), ("fp64", phi64, args.fp64_steps)):
+    for conv, ref, steps in () if args.no_sparse else (("fp32", phi32, args.steps), ("fp64", phi64, args.fp64_steps)):
         ps = ctx.plan(gm.problem(N, n, 3.0, 6.0, 4, Q, conv=conv, skip_empty=1))
         wss = torch.empty(ps.workspace_bytes, dtype=torch.uint8, device=dev)
         phis = torch.empty_like(f)
@@ -687,11 +700,14 @@ def main():
                         "equal_to_dense": bool(torch.equal(phis, ref))}
         del wss, phis
         ps.close()
-    sparse["note"] = ("mlc_problem.skip_empty = 1: patches whose node charge is all zero skip their local "
-                      "convolutions (found on the device every solve); phi equal to the dense solve element for "
-                      "element")
-    progress(f"empty patches skipped: float32 {sparse['fp32']['ms_per_step']:.3f} ms, "
-             f"float64 {sparse['fp64']['ms_per_step']:.3f} ms")
+    if sparse:
+        sparse["note"] = ("mlc_problem.skip_empty = 1: patches whose node charge is all zero skip their local "
+                          "convolutions (found on the device every solve); phi equal to the dense solve element for "
+                          "element")
+        progress(f"empty patches skipped: float32 {sparse['fp32']['ms_per_step']:.3f} ms, "
+                 f"float64 {sparse['fp64']['ms_per_step']:.3f} ms")
+    else:
+        sparse = None
     a32, a64 = phi32.cpu().numpy(), phi64.cpu().numpy()
     scale = np.abs(a64).max()
     err_32_64 = float(np.abs(a32 - a64).max() / scale)
