@@ -24,6 +24,11 @@ CASES = {
     "oscillatory_128": (dict(N=128, n=32, alpha=1.75, beta=3.25, P=4, Q=6, b=3), lambda: mi.oscillatory_charge(128)),
     "sixth_64": (dict(N=64, n=8, alpha=3.0, beta=6.0, P=4, Q=6, Z=64, rhs_order=6),
                  lambda: mi.poly_charge(64, 6, (0.45, 0.55, 0.5), 0.2)),
+    "bumps_128_l3": (dict(N=128, n=16, alpha=3.0, beta=6.0, P=4, Q=4, levels=3),
+                     lambda: mi.bump_charge(128, mi.bumps(2, 81, radius=(0.1, 0.15)))),
+    # the 2048^3 runs' settings (sec. 7.2, Table 14) on a smaller grid
+    "oscillatory_512_l4": (dict(N=512, n=32, alpha=1.75, beta=3.25, P=4, Q=6, b=3, levels=4, level_alpha=(2.0, 2.25)),
+                           lambda: mi.oscillatory_charge(512)),
 }
 
 
@@ -85,7 +90,7 @@ def _live_count(f, n):
 
 
 @pytest.mark.parametrize("conv", ["fp32", "fp64"])
-@pytest.mark.parametrize("name", ["oscillatory_128", "smooth_128_l3", "sixth_64"])
+@pytest.mark.parametrize("name", ["oscillatory_128", "smooth_128_l3", "sixth_64", "bumps_128_l3", "oscillatory_512_l4"])
 def test_max_live_equals_skip_empty(name, conv):
     """A plan holding buffers for the live patches only (max_live = their
     count) gives the dense plan's phi element for element; one slot fewer is
