@@ -1693,7 +1693,7 @@ static mlc_status launch_rest(const Group& G, hipStream_t s, Stage stage) {
   if (stage == PLANES || stage == FINISH) {
     auto* pr = reinterpret_cast<SkelProb<T>*>(G.ws + L.o_flat + sizeof(CoarseRhsProb<double>) * np);
     double* dsum = reinterpret_cast<double*>(G.ws + L.o_dsum);
-    int64_t total = 0;
+    int64_t total = 0, blocks = 0;
     std::vector<SkelProb<T>> v(np);
     for (int k = 0; k < np; ++k) {
       const mlc_plan* P = G.plans[k];
@@ -1701,17 +1701,18 @@ static mlc_status launch_rest(const Group& G, hipStream_t s, Stage stage) {
       SkelGeom sg{I.N, I.n, I.patches_per_axis, P->Kann, I.d_alpha, I.d_beta, I.b, I.Wa, P->P0, I.nplanes_a, P->Wb,
                   P->P0b, P->nplb, I.O_lo, I.No, final_c2h2(*P)};
       v[k] = SkelProb<T>{phiH_of(k), pl + L.patch0[k] * plsz, charge_of(G, k), phiB_of(k), phi_of(G, k), sg, total,
-                         slot_of_patch(G)};
+                         slot_of_patch(G), blocks};
       total += int64_t(3) * (I.N / I.n + 1) * (I.N + 1) * (I.N + 1);
+      // finishing tiles: planes x (N/4 + 1 coarse row intervals) x column chunks
+      blocks += int64_t(3) * (I.N / I.n + 1) * (I.N / NREF + 1) * ((I.N + SKF_COLS) / SKF_COLS);
     }
     if (stage == PLANES) {
       upload_flat(pr, v, s);   // read by both parts
       TimedScope ts(P0, s, "skeleton_deltas");
-      hipLaunchKernelGGL((skeleton_kernel<T, 0>), dim3(blocks_for(total)), dim3(256), 0, s, pr, np, total, P0->lagw,
-                         P0->Kann > 0 ? 1 : 0, dsum);
+      hipLaunchKernelGGL(skeleton_deltas_kernel<T>, dim3(blocks_for(total)), dim3(256), 0, s, pr, np, total, dsum);
     } else {
       TimedScope ts(P0, s, "skeleton");
-      hipLaunchKernelGGL((skeleton_kernel<T, 1>), dim3(blocks_for(total)), dim3(256), 0, s, pr, np, total, P0->lagw,
+      hipLaunchKernelGGL(skeleton_finish_kernel<T>, dim3(unsigned(blocks)), dim3(256), 0, s, pr, np, P0->lagw,
                          P0->Kann > 0 ? 1 : 0, dsum);
     }
   }

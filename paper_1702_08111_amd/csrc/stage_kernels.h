@@ -454,6 +454,7 @@ template <typename T> struct SkelProb {
   SkelGeom g;
   int64_t start;
   const int* slot_of;  // patch -> its slot in delta (-1: an empty patch), or null (slot = patch)
+  int64_t bstart;      // the problem's first block in skeleton_finish_kernel
 };
 
 // ---------------------------------------------- annulus sums on MFMA ----
@@ -855,28 +856,26 @@ __global__ void __launch_bounds__(256) coarse_reduce_kernel(const AnnProb* __res
 // far field already in phiB when `annulus`) for every skeleton node g (taken
 // once, on its lowest face-normal axis); also writes
 // phi[g] = phi^B[g] + C2 h^2 f[g] (sec. 4.1 eqs. mlcfulldiscr,
-// mcapplicationfulldiscr).  In two launches over the same thread range:
-// PART 0 (needs only the plane corrections) writes the sum of the delta_i
-// to dsum[thread]; PART 1 (needs phi^H) adds the interpolation and the far
-// field, so the first can run while the coarse solve is still going.
-template <typename T, int PART>
-__global__ void __launch_bounds__(256) skeleton_kernel(const SkelProb<T>* __restrict__ pr, int np, int64_t total,
-                                                       LagW lw, int annulus, double* __restrict__ dsum) {
+// mcapplicationfulldiscr).  In two launches: skeleton_deltas_kernel (needs
+// only the plane corrections, one thread per skeleton node slot) writes the
+// sum of the delta_i to dsum[slot]; skeleton_finish_kernel (needs phi^H)
+// adds the interpolation and the far field, so the first can run while the
+// coarse solve is still going.  A slot is ((d planes + j) (N+1) + u) (N+1) + v:
+// plane x_d = j n, in-plane coordinates u (axis a0) and v (axis a1).
+template <typename T>
+__global__ void __launch_bounds__(256) skeleton_deltas_kernel(const SkelProb<T>* __restrict__ pr, int np,
+                                                              int64_t total, double* __restrict__ dsum) {
   const int64_t gidx = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
   if (gidx >= total) return;
   const SkelProb<T>& pb = flat_problem(pr, np, gidx);
   const SkelGeom g = pb.g;
-  const double* __restrict__ phiH = pb.phiH;
   const T* __restrict__ delta = pb.delta;
-  const double* __restrict__ f = pb.f;
-  double* __restrict__ phiB = pb.phiB;
-  double* __restrict__ phi = pb.phi;
   const int N = g.N, n = g.n, Np = N + 1;
   const int planes = N / n + 1;
   const int64_t idx = gidx - pb.start;
-  int v = int(idx % Np), u = int((idx / Np) % Np), j = int((idx / (int64_t(Np) * Np)) % planes);
-  int d = int(idx / (int64_t(Np) * Np * planes));
-  int a0 = d == 0 ? 1 : 0, a1 = d == 2 ? 1 : 2;
+  const int v = int(idx % Np), u = int((idx / Np) % Np), j = int((idx / (int64_t(Np) * Np)) % planes);
+  const int d = int(idx / (int64_t(Np) * Np * planes));
+  const int a0 = d == 0 ? 1 : 0, a1 = d == 2 ? 1 : 2;
   // canonical plane: no lower axis divisible by n
   if (a0 < d && u % n == 0) return;
   if (a1 < d && v % n == 0) return;
@@ -884,72 +883,121 @@ __global__ void __launch_bounds__(256) skeleton_kernel(const SkelProb<T>* __rest
   gg[d] = j * n;
   gg[a0] = u;
   gg[a1] = v;
-  if constexpr (PART == 0) {
-    // patches with g in Omega_alpha(i): n i - da <= g <= n i + n + da
-    int lo[3], hi[3];
-    for (int a = 0; a < 3; ++a) {
-      int x = gg[a] - n - g.da;
-      lo[a] = max(x >= 0 ? (x + n - 1) / n : -((-x) / n), 0);
-      hi[a] = min((gg[a] + g.da) / n, g.ppa - 1);
-    }
-    const int Wa = g.Wa;
-    double sd = 0.0;
-    for (int i0 = lo[0]; i0 <= hi[0]; ++i0)
-      for (int i1 = lo[1]; i1 <= hi[1]; ++i1)
-        // four patches of the last axis at a time (loads issued together); a
-        // slot past hi[2] repeats that patch and adds an exact zero
-        for (int i2b = lo[2]; i2b <= hi[2]; i2b += 4) {
-#pragma unroll
-          for (int t2 = 0; t2 < 4; ++t2) {
-            const bool valid = i2b + t2 <= hi[2];
-            const int i2 = valid ? i2b + t2 : hi[2];
-            const int r[3] = {gg[0] - n * i0, gg[1] - n * i1, gg[2] - n * i2};
-            int pidx = (i0 * g.ppa + i1) * g.ppa + i2;
-            if (pb.slot_of) pidx = pb.slot_of[pidx];
-            const int jj = (r[d] - g.P0) / n;
-            const double x = pidx < 0 ? 0.0 :
-                double(delta[((((int64_t(pidx) * 3 + d) * g.npl + jj) * Wa + (r[a0] + g.da)) * Wa) + (r[a1] + g.da)]);
-            sd += valid ? x : 0.0;
-          }
-        }
-    dsum[gidx] = sd;
-    return;
+  // patches with g in Omega_alpha(i): n i - da <= g <= n i + n + da
+  int lo[3], hi[3];
+  for (int a = 0; a < 3; ++a) {
+    int x = gg[a] - n - g.da;
+    lo[a] = max(x >= 0 ? (x + n - 1) / n : -((-x) / n), 0);
+    hi[a] = min((gg[a] + g.da) / n, g.ppa - 1);
   }
-  // coarse interpolation of phi^H in the plane x_d = g_d
-  double val;
-  {
-    int U0 = u / NREF, V0 = v / NREF, tu = u - NREF * U0, tv = v - NREF * V0;
-    const double* wu = lw.w[tu];
-    const double* wv = lw.w[tv];
-    int ku0 = tu ? -g.b : 0, ku1 = tu ? g.b + 1 : 0, kv0 = tv ? -g.b : 0, kv1 = tv ? g.b + 1 : 0;
-    int cd = gg[d] / NREF - g.O_lo;
-    double s = 0.0;
-    for (int ku = ku0; ku <= ku1; ++ku) {
-      double rs = 0.0;
-      // four taps at a time (loads issued together); a slot past kv1
-      // repeats that tap with weight zero
-      for (int kvb = kv0; kvb <= kv1; kvb += 4) {
+  const int Wa = g.Wa;
+  double sd = 0.0;
+  for (int i0 = lo[0]; i0 <= hi[0]; ++i0)
+    for (int i1 = lo[1]; i1 <= hi[1]; ++i1)
+      // four patches of the last axis at a time (loads issued together); a
+      // slot past hi[2] repeats that patch and adds an exact zero
+      for (int i2b = lo[2]; i2b <= hi[2]; i2b += 4) {
 #pragma unroll
-        for (int t = 0; t < 4; ++t) {
-          const bool valid = kvb + t <= kv1;
-          const int kv = valid ? kvb + t : kv1;
-          int c[3];
-          c[d] = cd;
-          c[a0] = U0 + ku - g.O_lo;
-          c[a1] = V0 + kv - g.O_lo;
-          const double x = phiH[(int64_t(c[0]) * g.No + c[1]) * g.No + c[2]];
-          rs = fma(valid ? wv[kv + g.b] : 0.0, valid ? x : 0.0, rs);
+        for (int t2 = 0; t2 < 4; ++t2) {
+          const bool valid = i2b + t2 <= hi[2];
+          const int i2 = valid ? i2b + t2 : hi[2];
+          const int r[3] = {gg[0] - n * i0, gg[1] - n * i1, gg[2] - n * i2};
+          int pidx = (i0 * g.ppa + i1) * g.ppa + i2;
+          if (pb.slot_of) pidx = pb.slot_of[pidx];
+          const int jj = (r[d] - g.P0) / n;
+          const double x = pidx < 0 ? 0.0 :
+              double(delta[((((int64_t(pidx) * 3 + d) * g.npl + jj) * Wa + (r[a0] + g.da)) * Wa) + (r[a1] + g.da)]);
+          sd += valid ? x : 0.0;
         }
       }
-      s += wu[ku + g.b] * rs;
-    }
-    val = s;
+  dsum[gidx] = sd;
+}
+
+// The interpolation part, one block per tile of 4 rows u (one coarse row
+// interval, u = 4 U0 .. 4 U0 + 3) by 64 columns v of one skeleton plane.  The
+// tile's coarse samples (at most 2b + 2 rows by 16 + 2b + 2 columns) are
+// loaded once into LDS, interpolated along v for each coarse row, then along
+// u: the sum of each node is the same as tap by tap (along v first, then u).
+constexpr int SKF_COLS = 64;
+template <typename T>
+__global__ void __launch_bounds__(256) skeleton_finish_kernel(const SkelProb<T>* __restrict__ pr, int np, LagW lw,
+                                                              int annulus, const double* __restrict__ dsum) {
+  __shared__ double C[10][SKF_COLS / NREF + 12];   // 2b + 2 <= 10 rows, 16 + 2b + 2 <= 26 columns
+  __shared__ double R[10][SKF_COLS];
+  const int64_t bid = blockIdx.x;
+  int k = 0;
+  while (k + 1 < np && pr[k + 1].bstart <= bid) ++k;
+  const SkelProb<T>& pb = pr[k];
+  const SkelGeom g = pb.g;
+  const int N = g.N, n = g.n, Np = N + 1, b = g.b;
+  const int planes = N / n + 1, UT = N / NREF + 1, VT = (Np + SKF_COLS - 1) / SKF_COLS;
+  int64_t t = bid - pb.bstart;
+  const int vt = int(t % VT);
+  t /= VT;
+  const int U0 = int(t % UT);
+  t /= UT;
+  const int j = int(t % planes), d = int(t / planes);
+  const int a0 = d == 0 ? 1 : 0, a1 = d == 2 ? 1 : 2;
+  const int v0 = SKF_COLS * vt, vm = min(v0 + SKF_COLS - 1, N);
+  // coarse rows: U0 - b .. U0 + b + 1 when a row u = 4 U0 + tu, tu > 0 is in
+  // the grid, else U0 alone (u = N)
+  const bool rows_i = NREF * U0 + 1 <= N;
+  const int r_lo = rows_i ? U0 - b : U0, nr = rows_i ? 2 * b + 2 : 1;
+  // coarse columns: the union over v0 .. vm of V0 (tv = 0) or V0 - b .. V0 + b + 1
+  const int c_lo = (vm > v0 || v0 % NREF) ? v0 / NREF - b : v0 / NREF;
+  const int c_hi = (vm % NREF) ? vm / NREF + b + 1 : (vm > v0 ? vm / NREF + b : vm / NREF);
+  const int nc = c_hi - c_lo + 1;
+  const int cd = j * n / NREF - g.O_lo;
+  const double* __restrict__ phiH = pb.phiH;
+  for (int q = threadIdx.x; q < nr * nc; q += blockDim.x) {
+    const int rr = q / nc, cc = q % nc;
+    int c[3];
+    c[d] = cd;
+    c[a0] = r_lo + rr - g.O_lo;
+    c[a1] = c_lo + cc - g.O_lo;
+    C[rr][cc] = phiH[(int64_t(c[0]) * g.No + c[1]) * g.No + c[2]];
   }
-  val += dsum[gidx];
-  int64_t node = (int64_t(gg[0]) * Np + gg[1]) * Np + gg[2];
+  __syncthreads();
+  for (int q = threadIdx.x; q < nr * SKF_COLS; q += blockDim.x) {
+    const int rr = q / SKF_COLS, x = q % SKF_COLS, v = v0 + x;
+    double s = 0.0;
+    if (v <= vm) {
+      const int V0 = v / NREF, tv = v - NREF * V0;
+      if (tv == 0) {
+        s = C[rr][V0 - c_lo];
+      } else {
+        const double* wv = lw.w[tv];
+        for (int kv = -b; kv <= b + 1; ++kv) s = fma(wv[kv + b], C[rr][V0 + kv - c_lo], s);
+      }
+    }
+    R[rr][x] = s;
+  }
+  __syncthreads();
+  const int x = threadIdx.x % SKF_COLS, u = NREF * U0 + int(threadIdx.x) / SKF_COLS, v = v0 + x;
+  if (u > N || v > vm) return;
+  // canonical plane: no lower axis divisible by n
+  if (a0 < d && u % n == 0) return;
+  if (a1 < d && v % n == 0) return;
+  const int tu = u - NREF * U0;
+  double val;
+  if (tu == 0) {
+    val = R[U0 - r_lo][x];
+  } else {
+    const double* wu = lw.w[tu];
+    val = 0.0;
+    for (int ku = -b; ku <= b + 1; ++ku) val = fma(wu[ku + b], R[U0 + ku - r_lo][x], val);
+  }
+  const int64_t slot = pb.start + ((int64_t(d) * planes + j) * Np + u) * Np + v;
+  val += dsum[slot];
+  int gg[3];
+  gg[d] = j * n;
+  gg[a0] = u;
+  gg[a1] = v;
+  const int64_t node = (int64_t(gg[0]) * Np + gg[1]) * Np + gg[2];
+  double* __restrict__ phiB = pb.phiB;
   if (annulus) val += phiB[node];
   phiB[node] = val;
-  phi[node] = val + g.c2h2 * f[node];
+  pb.phi[node] = val + g.c2h2 * pb.f[node];
 }
 
 // --------------------------------------------- Dirichlet solves on MFMA ----
