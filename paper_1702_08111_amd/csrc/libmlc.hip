@@ -894,9 +894,10 @@ static Layout layout_of(const std::vector<const mlc_plan_info*>& g) {
     if (g[k]->d_beta > g[k]->d_alpha) {
       MfmaGeom gs, gc;
       annulus_geoms(*g[k], &gs, &gc);
-      // slot-major and mode-major moment copies, then the partial sums of
-      // split far-field sums
-      bytes = 2 * sizeof(double) * cube(gs.L) * gs.KP + sizeof(double) * ann_split(*g[k]).part;
+      // slot-major and mode-major moment copies, the partial sums of split
+      // far-field sums, then the nonzero-moment flags of the lattice slots
+      bytes = 2 * sizeof(double) * cube(gs.L) * gs.KP + sizeof(double) * ann_split(*g[k]).part +
+              sizeof(int) * cube(gs.L);
     }
     L.o_cpad[k] = take(bytes);
   }
@@ -1539,12 +1540,14 @@ static mlc_status launch_rest(const Group& G, hipStream_t s, Stage stage) {
       const MfmaGeom& gc = P->mg_coarse;
       const AnnSplit sp = ann_split(I);
       double* part = cpad_s(k) + 2 * cube(gs.L) * gs.KP;
+      // plans that skip empty patches also skip zero source patches here
+      const int* nzf = I.skip_empty ? reinterpret_cast<const int*>(part + sp.part) : nullptr;
       vs[k] = AnnProb{P->Am, cpad_s(k), phiB_of(k), gs.ppa, gs.nk0, gs.nk1, gs.nk2, gs.k0lo, gs.k1lo, gs.k2lo, gs.L,
-                      gs.padlo, I.N, I.S_lo, I.Ns, bs, sp.ncb_s, sp.es_s, part, rs};
+                      gs.padlo, I.N, I.S_lo, I.Ns, bs, sp.ncb_s, sp.es_s, part, rs, nzf};
       bs += sp.ncb_s * sp.es_s;
       if (sp.es_s > 1) rs += int64_t(3) * gs.nr * gs.nk0 * gs.nk1 * gs.nk2;
       vc[k] = AnnProb{P->Tm, cpad_p(k), F_of(k), gc.ppa, gc.nk0, gc.nk1, gc.nk2, gc.k0lo, gc.k1lo, gc.k2lo, gc.L,
-                      gc.padlo, I.N, I.S_lo, I.Ns, bc, sp.ncb_c, sp.es_c, part, rc};
+                      gc.padlo, I.N, I.S_lo, I.Ns, bc, sp.ncb_c, sp.es_c, part, rc, nzf};
       bc += sp.ncb_c * sp.es_c;
       if (sp.es_c > 1) rc += int64_t(gc.nr) * gc.nk0 * gc.nk1 * gc.nk2;
     }
@@ -1566,6 +1569,11 @@ static mlc_status launch_rest(const Group& G, hipStream_t s, Stage stage) {
         const MfmaGeom& g = G.plans[k]->mg_coarse;
         hipLaunchKernelGGL(pad_moments_kernel, dim3(blocks_for(cube(g.L) * g.KP)), dim3(256), 0, s,
                            mom + int64_t(L.patch0[k]) * I.K, cpad_s(k), cpad_p(k), g.ppa, g.K, g.KP, g.L, g.padlo);
+        if (I.skip_empty)
+          hipLaunchKernelGGL(pad_flags_kernel, dim3(blocks_for(cube(g.L))), dim3(256), 0, s,
+                             mom + int64_t(L.patch0[k]) * I.K,
+                             reinterpret_cast<int*>(cpad_s(k) + 2 * cube(g.L) * g.KP + ann_split(I).part), g.ppa,
+                             g.K, g.L, g.padlo);
       }
       const MfmaGeom& g = P0->mg_coarse;
       if (coarse_big(I0.n / NREF))

@@ -499,6 +499,23 @@ __global__ void pad_moments_kernel(const double* __restrict__ mom, double* __res
   Cs[slot * KP + p] = v;
 }
 
+// nz[slot] = 1 when the patch at that slot of the padded lattice has a
+// nonzero moment (0 for the padding): the far-field sums of a plan that
+// skips empty patches pass over offsets whose source patches are all zero
+// (an exact skip: those products add zero).
+__global__ void pad_flags_kernel(const double* __restrict__ mom, int* __restrict__ nz, int ppa, int K, int L,
+                                 int padlo) {
+  const int64_t slot = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (slot >= cube(L)) return;
+  const int a2 = int(slot % L) - padlo, a1 = int((slot / L) % L) - padlo, a0 = int(slot / (int64_t(L) * L)) - padlo;
+  int any = 0;
+  if (a0 >= 0 && a0 < ppa && a1 >= 0 && a1 < ppa && a2 >= 0 && a2 < ppa) {
+    const double* m = mom + (int64_t(a0 * ppa + a1) * ppa + a2) * K;
+    for (int p = 0; p < K; ++p) any |= m[p] != 0.0;
+  }
+  nz[slot] = any;
+}
+
 // A rows for the skeleton: r = ra * n + rb over the face plane of normal d;
 // table Am[d][E][pc][r][4] (E = (E0, E1, E2) over the offset box, r < nrp),
 // value D[d][E0 plane][ra + n E1][rb + n E2][p] when inside the table, else 0.
@@ -587,8 +604,9 @@ template <class TL> __device__ __forceinline__ int ann_kbase(int cb, int wave) {
 // wave's box of columns are skipped (a uniform test).
 template <int ANN_TILES, bool PMAJOR, int RT>
 __device__ __forceinline__ void annulus_mfma_tiles(const double* __restrict__ Am, const double* __restrict__ Cpad,
-                                                   const MfmaGeom& mg, int d, int rowbase, int kbase, int e0b,
-                                                   int e0e, f64x4 (&acc)[RT][ANN_TILES]) {
+                                                   const int* __restrict__ nzf, const MfmaGeom& mg, int d,
+                                                   int rowbase, int kbase, int e0b, int e0e,
+                                                   f64x4 (&acc)[RT][ANN_TILES]) {
   const int lane = threadIdx.x & 63;
   const int rl = lane & 15, pj = lane >> 4;
   const int npc = mg.KP / 4;
@@ -599,12 +617,13 @@ __device__ __forceinline__ void annulus_mfma_tiles(const double* __restrict__ Am
   if (d <= 0) { st0 = L * L; st1 = L; st2 = 1; }
   else if (d == 1) { st0 = L; st1 = L * L; st2 = 1; }
   else { st0 = 1; st1 = L * L; st2 = L; }
-  int64_t boff[ANN_TILES];
+  int64_t boff[ANN_TILES], sl[ANN_TILES];
 #pragma unroll
   for (int t = 0; t < ANN_TILES; ++t) {
     const int k = min(kbase + 16 * t + rl, nk - 1);
     const int a = mg.k0lo + k / n12, b = mg.k1lo + (k / mg.nk2) % mg.nk1, c = mg.k2lo + k % mg.nk2;
     const int64_t slot = (a + pad) * st0 + (b + pad) * st1 + (c + pad) * st2;
+    sl[t] = slot;
     boff[t] = PMAJOR ? slot + int64_t(pj) * L * L * L : slot * mg.KP + pj;
 #pragma unroll
     for (int rt = 0; rt < RT; ++rt) acc[rt][t] = f64x4{0.0, 0.0, 0.0, 0.0};
@@ -633,7 +652,15 @@ __device__ __forceinline__ void annulus_mfma_tiles(const double* __restrict__ Am
       for (int e2 = 0; e2 < mg.ne; ++e2) {
         const int E2 = mg.elo + e2;
         if (c_hi - E2 < 0 || c_lo - E2 > ppa - 1) continue;
-        const int64_t off = int64_t(E0 * st0 + E1 * st1 + E2 * st2) * (PMAJOR ? 1 : mg.KP);
+        const int eoff = E0 * st0 + E1 * st1 + E2 * st2;
+        if (nzf) {
+          // skip the offset when every source patch of the wave's columns is zero
+          int any = 0;
+#pragma unroll
+          for (int t = 0; t < ANN_TILES; ++t) any |= nzf[sl[t] - eoff];
+          if (!__any(any)) continue;
+        }
+        const int64_t off = int64_t(eoff) * (PMAJOR ? 1 : mg.KP);
         const double* Ae = Ad + ((int64_t(e0) * mg.ne + e1) * mg.ne + e2) * npc * mg.nrp * 4;
         for (int pc = 0; pc < npc; ++pc) {
           // the RT row tiles' table fragments (16 rows apart) and the
@@ -671,6 +698,7 @@ struct AnnProb {
   int esplit;     // offset chunks: blocks blk0 + c ncb + j take chunk c
   double* part;   // esplit > 1: partial sums [chunk][(d)][row][column]
   int64_t start;  // first thread of the problem in the reduction launch
+  const int* nzf; // per lattice slot: nonzero moments (skips zero sources), or null (no skipping)
 };
 constexpr int ANN_PACK = 8;
 struct AnnPack { AnnProb d[ANN_PACK]; int count; };
@@ -716,7 +744,7 @@ __global__ void __launch_bounds__(64 * TL::WAVES) skeleton_annulus_mfma_kernel(c
   int e0b, e0e;
   ann_chunk(chunk, A.esplit, mg.ne0, &e0b, &e0e);
   f64x4 acc[RT][ANN_TILES];
-  annulus_mfma_tiles<ANN_TILES, false, RT>(A.tab, A.cpad, mg, d, rowbase, kbase, e0b, e0e, acc);
+  annulus_mfma_tiles<ANN_TILES, false, RT>(A.tab, A.cpad, A.nzf, mg, d, rowbase, kbase, e0b, e0e, acc);
   const int a0 = d == 0 ? 1 : 0, a1 = d == 2 ? 1 : 2, Np = N + 1;
   const int nk = mg.nk0 * mg.nk1 * mg.nk2;
   if (A.esplit > 1) {
@@ -774,7 +802,7 @@ __global__ void __launch_bounds__(64 * TL::WAVES) coarse_annulus_mfma_kernel(con
   int e0b, e0e;
   ann_chunk(chunk, A.esplit, mg.ne0, &e0b, &e0e);
   f64x4 acc[RT][ANN_TILES];
-  annulus_mfma_tiles<ANN_TILES, true, RT>(A.tab, A.cpad, mg, -1, rowbase, kbase, e0b, e0e, acc);
+  annulus_mfma_tiles<ANN_TILES, true, RT>(A.tab, A.cpad, A.nzf, mg, -1, rowbase, kbase, e0b, e0e, acc);
   const int nk = mg.nk0 * mg.nk1 * mg.nk2;
   if (A.esplit > 1) {
     // partial sums of this offset chunk; coarse_reduce_kernel adds them
