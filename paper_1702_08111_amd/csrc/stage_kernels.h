@@ -953,9 +953,13 @@ __global__ void __launch_bounds__(256) skeleton_finish_kernel(const SkelProb<T>*
   __shared__ double C[10][SKF_COLS / NREF + 12];   // 2b + 2 <= 10 rows, 16 + 2b + 2 <= 26 columns
   __shared__ double R[10][SKF_COLS];
   const int64_t bid = blockIdx.x;
-  int k = 0;
-  while (k + 1 < np && pr[k + 1].bstart <= bid) ++k;
-  const SkelProb<T>& pb = pr[k];
+  // the problem owning this block: problem k owns blocks [bstart_k, bstart_{k+1})
+  int lo = 0, hi = np - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (pr[mid].bstart <= bid) lo = mid; else hi = mid - 1;
+  }
+  const SkelProb<T>& pb = pr[lo];
   const SkelGeom g = pb.g;
   const int N = g.N, n = g.n, Np = N + 1, b = g.b;
   const int planes = N / n + 1, UT = N / NREF + 1, VT = (Np + SKF_COLS - 1) / SKF_COLS;
