@@ -111,8 +111,9 @@ typedef struct {
                              patch) is zero skip their local convolutions, found on the
                              device at every solve; their local fields and moments are
                              zero, so the result is the same as with 0 (the method only
-                             needs patches over the support of f, sec. 1).  0: every
-                             patch is convolved                                      */
+                             needs patches over the support of f, sec. 1); the far-field
+                             sums also pass over source patches with zero moments.  0:
+                             every patch is convolved                                */
   int32_t box_cells[3];   /* a box domain [0, B0] x [0, B1] x [0, B2] (cells per axis, each
                              a multiple of n; n_cells must then be 0): f and phi are
                              (B0+1)(B1+1)(B2+1) node arrays, C order, axis 2 fastest.  The
