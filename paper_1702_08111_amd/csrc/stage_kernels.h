@@ -1036,16 +1036,11 @@ __global__ void __launch_bounds__(256) skeleton_finish_kernel(const SkelProb<T>*
 // The patch solve (sec. 4.1 eq. last_step_fulldiscr) diagonalises in the
 // DST-I basis of length m = n - 1: u = S^-1 (S rhs / lambda) with
 // S[k][j] = sin(pi (k+1)(j+1) / n) along each axis, S symmetric and
-// S^-1 = (2/n) S.  A slab (one wave, m x m padded to 32 x 32) is transformed
-// along both of its axes as S X S, along one as S X, each product on
-// v_mfma_f64_16x16x4f64.  Three passes over the patches' (n-1)^3 work arrays:
-//   0: slabs of fixed index 0: right-hand side h^2 f - (boundary terms), S X S
-//   1: slabs of fixed index 1: S X along index 0, divide by the symbol,
-//      S X again (times 2/n)
-//   2: slabs of fixed index 0: S X S (times (2/n)^2), then
-//      phi = u + C2 h^2 f on the patch interior
+// S^-1 = (2/n) S.  A slab (m x m padded to 32 x 32) is transformed along
+// both of its axes as S X S, or columns of a staged matrix along one axis as
+// S X, each product on v_mfma_f64_16x16x4f64 (dirichlet_fused_kernel).
 struct DirGeom {
-  int n, npatch;   // patches of this launch: p0 .. p0 + npatch - 1
+  int n, npatch;   // patches of this launch: p0 .. p0 + npatch - 1 (one block each)
   double scale;    // 2/n
   Stencil st;
   int p0;
@@ -1088,76 +1083,63 @@ __device__ __forceinline__ void mm32(const double* A, const double* B, double* D
       for (int r = 0; r < 4; ++r) D[(16 * it + 4 * r + (lane >> 4)) * 33 + 16 * kt + (lane & 15)] = acc[it][kt][r];
 }
 
-// Slabs (waves) per block of the Dirichlet passes.
-constexpr int DIR_WAVES = 8;
-
-template <int PASS>
-__global__ void __launch_bounds__(64 * DIR_WAVES) dirichlet_mfma_kernel(const ProbDesc* __restrict__ pd, int nprob,
-                                                                        double* __restrict__ work, DirGeom g) {
+// One block of 16 waves per patch: the patch's (n-1)^3 values stay on the
+// chip (wave w holds the slabs of index 0 equal to w and w + 16 in
+// registers), so no work array goes through HBM.
+//   A: per slab u: right-hand side h^2 f - (boundary terms), S X S
+//   B: along index 0, in four chunks of 8 rows of index 1: the slabs' rows
+//      are staged in LDS as a 32 x 256 matrix (index 0 by (index 1, index 2)),
+//      each wave takes 16 columns: S X, divide by the symbol, S X (times 2/n)
+//   C: per slab u: S X S (times (2/n)^2), phi = u + C2 h^2 f
+constexpr int DIRF_WAVES = 16;
+constexpr int DIRF_TS = 260;   // row stride of the staging matrix (256 columns + 4)
+static_assert(32 * DIRF_TS <= DIRF_WAVES * 32 * 33, "staging matrix must fit in the slab buffers");
+__global__ void __launch_bounds__(64 * DIRF_WAVES) dirichlet_fused_kernel(const ProbDesc* __restrict__ pd, int nprob,
+                                                                         DirGeom g) {
   __shared__ double Sm[32 * 33];
-  __shared__ double Ls[DIR_WAVES][32 * 33];
+  __shared__ double Ls[DIRF_WAVES][32 * 33];
   __shared__ double sn[2 * 32], cs[32];
+  __shared__ const double* sl_phiB[DIRF_WAVES];
+  __shared__ int64_t sl_base[DIRF_WAVES], sl_Np[DIRF_WAVES];
+  __shared__ int sl_u[DIRF_WAVES], sl_cnt[DIRF_WAVES];
   const int m = g.n - 1;
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  // sin(pi a / n) for a < 2n and cos(pi (k+1) / n): every entry of the
-  // transform matrix and of the symbol is one of these
   if (threadIdx.x < 2 * g.n) sn[threadIdx.x] = sinpi(double(threadIdx.x) / double(g.n));
   if (threadIdx.x < m) cs[threadIdx.x] = cospi(double(threadIdx.x + 1) / double(g.n));
   __syncthreads();
   for (int t = threadIdx.x; t < 32 * 32; t += blockDim.x) {
-    int k = t / 32, j = t % 32;
+    const int k = t / 32, j = t % 32;
     Sm[k * 33 + j] = (k < m && j < m) ? sn[((k + 1) * (j + 1)) % (2 * g.n)] : 0.0;
   }
-  const int slab = blockIdx.x * DIR_WAVES + wave;     // over patches x m
-  const int pw = slab / m, u = slab % m;               // pw: the patch's slot in the work array
-  const int p = g.p0 + pw;
-  const bool live = pw < g.npatch;
-  const ProbDesc& D = pd[find_problem(pd, nprob, live ? p : 0)];
+  const int p = g.p0 + int(blockIdx.x);
+  const ProbDesc& D = pd[find_problem(pd, nprob, p)];
   const auto* f = gbl(D.f);
-  const auto* phiB = gbl(D.phiB);
   auto* phi = gbl(D.phi);
   const int ppa = D.ppa, pl = p - D.patch0;
   const double h2 = D.h2;
-  // slab element (row i, column j):
-  //   passes 0, 2: node index (u, i, j); pass 1: node index (i, u, j)
-  const int64_t M3 = int64_t(m) * m * m;
-  auto off = [&](int i, int j) -> int64_t {
-    if (PASS == 1) return int64_t(i) * m * m + int64_t(u) * m + j;
-    return int64_t(u) * m * m + int64_t(i) * m + j;
-  };
-  double* wp = work + int64_t(pw) * M3;
   const int i0 = pl / (ppa * ppa), i1 = (pl / ppa) % ppa, i2 = pl % ppa;
   const int64_t Np = D.N + 1;
   const int64_t pbase = (int64_t(g.n) * i0) * Np * Np + int64_t(g.n) * i1 * Np + int64_t(g.n) * i2;
   double* L = Ls[wave];
-  // lanes 0..31 walk a row's columns, the two half-waves take alternate
-  // rows; all 16 rows of a lane are loaded before the first LDS write, so
-  // the loads overlap
+  // lanes 0..31 walk a row's columns, the two half-waves take alternate rows
   const int jc = lane & 31, ih = lane >> 5;
-  double rows[16];
+  double xs[2][16];
+  // ---- A: right-hand side and the transforms along indices 1 and 2
 #pragma unroll
-  for (int r = 0; r < 16; ++r) {
-    const int i = ih + 2 * r;
-    double v = 0.0;
-    if (live && i < m && jc < m) {
-      if constexpr (PASS == 0) {
-        v = h2 * f[pbase + (int64_t(u + 1) * Np + (i + 1)) * Np + (jc + 1)];
-      } else {
-        v = wp[off(i, jc)];
-      }
+  for (int sl = 0; sl < 2; ++sl) {
+    const int u = wave + DIRF_WAVES * sl;
+    const bool live = u < m;
+#pragma unroll
+    for (int r = 0; r < 16; ++r) {
+      const int i = ih + 2 * r;
+      double v = 0.0;
+      if (live && i < m && jc < m) v = h2 * f[pbase + (int64_t(u + 1) * Np + (i + 1)) * Np + (jc + 1)];
+      xs[sl][r] = v;
     }
-    rows[r] = v;
-  }
 #pragma unroll
-  for (int r = 0; r < 16; ++r) L[(ih + 2 * r) * 33 + jc] = rows[r];
-  if constexpr (PASS == 0) {
-    // boundary terms, only at nodes next to the patch boundary: the whole
-    // slab if it is the first or last of its patch, else its ring of
-    // 4(m-1) nodes.  The block's threads share the node lists of all its
-    // slabs (a first or last slab has eight times the nodes of the others).
-    __shared__ const double* sl_phiB[DIR_WAVES];
-    __shared__ int64_t sl_base[DIR_WAVES], sl_Np[DIR_WAVES];
-    __shared__ int sl_u[DIR_WAVES], sl_cnt[DIR_WAVES];
+    for (int r = 0; r < 16; ++r) L[(ih + 2 * r) * 33 + jc] = xs[sl][r];
+    // boundary terms at the nodes next to the patch boundary (the whole slab
+    // for the first and last slab, else its ring), shared by the block's threads
     if (lane == 0) {
       const bool end_slab = u == 0 || u == m - 1;
       sl_phiB[wave] = D.phiB;
@@ -1166,10 +1148,10 @@ __global__ void __launch_bounds__(64 * DIR_WAVES) dirichlet_mfma_kernel(const Pr
       sl_u[wave] = u;
       sl_cnt[wave] = live ? (end_slab ? m * m : 4 * (m - 1)) : 0;
     }
-    __syncthreads();   // every slab's L and the node lists
+    __syncthreads();   // every slab's L and the node lists (and Sm)
     int total = 0;
 #pragma unroll
-    for (int w = 0; w < DIR_WAVES; ++w) total += sl_cnt[w];
+    for (int w = 0; w < DIRF_WAVES; ++w) total += sl_cnt[w];
     for (int q0 = threadIdx.x; q0 < total; q0 += blockDim.x) {
       int w = 0, q = q0;
       while (q >= sl_cnt[w]) q -= sl_cnt[w++];
@@ -1189,11 +1171,11 @@ __global__ void __launch_bounds__(64 * DIR_WAVES) dirichlet_mfma_kernel(const Pr
       const auto* phiBw = gbl(sl_phiB[w]);
       const int64_t base = sl_base[w], Npw = sl_Np[w];
       const int l0 = uw + 1, l1 = i + 1, l2 = j + 1;
-      // every neighbour is a node of the patch box, so all 27 loads are
-      // issued together; those off the boundary (whose phi^B is not
-      // defined) are selected away, the boundary ones summed in order
+      // all 27 neighbours are nodes of the patch box: the loads of one
+      // plane of neighbours are issued together, those off the boundary
+      // selected away, the boundary ones summed in order
       double corr = 0.0;
-#pragma unroll
+#pragma unroll 1
       for (int s0 = -1; s0 <= 1; ++s0)
 #pragma unroll
         for (int s1 = -1; s1 <= 1; ++s1)
@@ -1207,40 +1189,103 @@ __global__ void __launch_bounds__(64 * DIR_WAVES) dirichlet_mfma_kernel(const Pr
           }
       Ls[w][i * 33 + j] -= corr;
     }
-  }
-  __syncthreads();   // Sm; from here on each wave touches only its own slab
-  if constexpr (PASS == 1) {
-    mm32(Sm, L, L, lane);                 // forward along index 0
-    wave_sync_lds();
-    for (int i = ih; i < 32; i += 2) {    // divide by the symbol at (k0, k1, k2) = (i, u, jc)
-      double v = 0.0;
-      if (i < m && jc < m) {
-        const double c0 = cs[i], c1 = cs[u], c2 = cs[jc];
-        const double lam = g.st.b[0] + 2.0 * g.st.b[1] * (c0 + c1 + c2) +
-                           4.0 * g.st.b[2] * (c0 * c1 + c0 * c2 + c1 * c2) + 8.0 * g.st.b[3] * c0 * c1 * c2;
-        v = L[i * 33 + jc] / lam;
-      }
-      L[i * 33 + jc] = v;
-    }
-    wave_sync_lds();
-    mm32(Sm, L, L, lane);                 // inverse along index 0
-  } else {
+    __syncthreads();   // from here on each wave touches only its own slab
     mm32(Sm, L, L, lane);                 // along index 1 (rows)
     wave_sync_lds();
     mm32(L, Sm, L, lane);                 // along index 2 (columns)
+    wave_sync_lds();
+#pragma unroll
+    for (int r = 0; r < 16; ++r) xs[sl][r] = L[(ih + 2 * r) * 33 + jc];
   }
-  wave_sync_lds();
-  if (!live) return;
-  const double sc = PASS == 0 ? 1.0 : (PASS == 1 ? g.scale : g.scale * g.scale);
-  for (int i = ih; i < m; i += 2) {
-    if (jc >= m) continue;
-    const double v = sc * L[i * 33 + jc];
-    if constexpr (PASS == 2) {
-      const int64_t node = pbase + (int64_t(u + 1) * Np + (i + 1)) * Np + (jc + 1);
-      phi[node] = v + D.c2h2 * f[node];
-    } else {
-      wp[off(i, jc)] = v;
+  // ---- B: along index 0, 8 rows of index 1 at a time
+  double* T = &Ls[0][0];
+#pragma unroll 1
+  for (int c = 0; c < 4; ++c) {
+    __syncthreads();   // the slab buffers are free (A done, or the previous chunk read back)
+#pragma unroll
+    for (int sl = 0; sl < 2; ++sl) {
+      const int u = wave + DIRF_WAVES * sl;   // 0 .. 31: every row of T
+#pragma unroll
+      for (int r = 0; r < 16; ++r) {
+        const int i = ih + 2 * r;
+        if ((i >> 3) == c) T[u * DIRF_TS + (i & 7) * 32 + jc] = xs[sl][r];
+      }
     }
+    __syncthreads();
+    // this wave's 16 columns: (index 1, index 2) = (8 c + col / 32, col % 32)
+    const int col = 16 * wave + (lane & 15);
+    const int ii = 8 * c + col / 32, j2 = col % 32;
+    f64x4 acc[2];
+#pragma unroll
+    for (int pass = 0; pass < 2; ++pass) {
+#pragma unroll
+      for (int it = 0; it < 2; ++it) acc[it] = f64x4{0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+      for (int jj = 0; jj < 8; ++jj) {
+        const int krow = 4 * jj + (lane >> 4);
+        const double b = T[krow * DIRF_TS + col];
+#pragma unroll
+        for (int it = 0; it < 2; ++it) {
+          const double a = Sm[(16 * it + (lane & 15)) * 33 + krow];
+          acc[it] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc[it], 0, 0, 0);
+        }
+      }
+      wave_sync_lds();   // every lane's reads of its columns before they are overwritten
+#pragma unroll
+      for (int it = 0; it < 2; ++it)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int k = 16 * it + 4 * r + (lane >> 4);
+          double v;
+          if (pass == 0) {
+            // divide by the symbol at (k0, k1, k2) = (k, ii, j2)
+            v = 0.0;
+            if (k < m && ii < m && j2 < m) {
+              const double c0 = cs[k], c1 = cs[ii], c2 = cs[j2];
+              const double lam = g.st.b[0] + 2.0 * g.st.b[1] * (c0 + c1 + c2) +
+                                 4.0 * g.st.b[2] * (c0 * c1 + c0 * c2 + c1 * c2) + 8.0 * g.st.b[3] * c0 * c1 * c2;
+              v = acc[it][r] / lam;
+            }
+          } else {
+            v = g.scale * acc[it][r];
+          }
+          T[k * DIRF_TS + col] = v;
+        }
+      wave_sync_lds();
+    }
+    __syncthreads();
+#pragma unroll
+    for (int sl = 0; sl < 2; ++sl) {
+      const int u = wave + DIRF_WAVES * sl;
+#pragma unroll
+      for (int r = 0; r < 16; ++r) {
+        const int i = ih + 2 * r;
+        if ((i >> 3) == c) xs[sl][r] = T[u * DIRF_TS + (i & 7) * 32 + jc];
+      }
+    }
+  }
+  __syncthreads();   // the staging matrix is read back before the slab buffers are reused
+  // ---- C: the inverse transforms along indices 1 and 2, and phi
+  const double sc = g.scale * g.scale;
+#pragma unroll
+  for (int sl = 0; sl < 2; ++sl) {
+    const int u = wave + DIRF_WAVES * sl;
+#pragma unroll
+    for (int r = 0; r < 16; ++r) L[(ih + 2 * r) * 33 + jc] = xs[sl][r];
+    wave_sync_lds();
+    mm32(Sm, L, L, lane);
+    wave_sync_lds();
+    mm32(L, Sm, L, lane);
+    wave_sync_lds();
+    if (u < m) {
+      for (int i = ih; i < m; i += 2) {
+        if (jc >= m) continue;
+        const double v = sc * L[i * 33 + jc];
+        const int64_t node = pbase + (int64_t(u + 1) * Np + (i + 1)) * Np + (jc + 1);
+        phi[node] = v + D.c2h2 * f[node];
+      }
+    }
+    wave_sync_lds();   // the slab's reads before the next slab overwrites L
   }
 }
 
