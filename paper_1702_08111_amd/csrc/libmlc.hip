@@ -788,7 +788,8 @@ static bool same_class(const mlc_plan* a, const mlc_plan* b) {
 //   per problem: F^H, coarse torus (consecutive within equal M_coarse),
 //   phi^H, phi^B.
 struct Layout {
-  size_t o_desc = 0, o_ann = 0, o_flat = 0, o_mom = 0, o_mpart = 0, o_mraw = 0, o_X = 0, o_Z = 0, o_cs = 0, o_pl = 0;
+  size_t o_desc = 0, o_ann = 0, o_flat = 0, o_mom = 0, o_mpart = 0, o_mraw = 0, o_X = 0, o_Z = 0, o_cs = 0, o_pl = 0,
+         o_dir = 0;
   size_t o_dsum = 0;   // per skeleton thread: the sum of the plane corrections
   std::vector<size_t> o_F, o_tor, o_phiH, o_phiB, o_cpad;
   std::vector<size_t> o_lf, o_lphi, o_lws;   // multilevel problems: the next level's charge, solution, workspace
@@ -797,6 +798,7 @@ struct Layout {
   int slots = 0;                             // per-patch buffer rows (= total unless a plan keeps live patches only)
   bool compact = false;                      // the group's one plan keeps its live patches only
   size_t o_patch_of = 0, o_slot_of = 0;      // compact: slot -> patch, patch -> slot (-1: empty)
+  int dir_chunk = 0;                         // n < 32: patches per three-pass Dirichlet launch
   size_t o_live = 0;                         // per patch: 1 unless skipped as empty (int)
   bool any_skip = false;                     // some problem skips empty patches
   std::vector<int> patch0;
@@ -863,6 +865,13 @@ static Layout layout_of(const std::vector<const mlc_plan_info*>& g) {
   L.o_Z = take(per_patch * L.chunk);
   L.o_cs = take(tsz * Ts * cube(I.Wc));
   L.o_pl = take(tsz * Ts * 3 * I.nplanes_a * I.Wa * I.Wa);
+  // smaller patches: the three-pass Dirichlet work array, every patch at
+  // once up to 4 GB, else chunks (32^3-cell patches need none)
+  if (I.n < 32) {
+    const size_t per = sizeof(double) * size_t(cube(I.n - 1));
+    L.dir_chunk = int(std::min<size_t>(T, std::max<size_t>(1, (size_t(4) << 30) / per)));
+    L.o_dir = take(per * size_t(L.dir_chunk));
+  }
   {
     size_t nsk = 0;
     for (int k = 0; k < np; ++k) nsk += size_t(3) * (g[k]->N / g[k]->n + 1) * size_t(g[k]->N + 1) * (g[k]->N + 1);
@@ -1718,10 +1727,25 @@ static mlc_status launch_rest(const Group& G, hipStream_t s, Stage stage) {
   // Dirichlet solves + Mehrstellen correction on the patch interiors, all patches
   if (stage == FINISH) {
     TimedScope ts(P0, s, "dirichlet");
-    // one block per patch, every patch in one launch (no work array: each
-    // patch's values stay on the chip)
-    DirGeom dg{I0.n, L.total, 2.0 / I0.n, st, 0};
-    hipLaunchKernelGGL(dirichlet_fused_kernel, dim3(unsigned(L.total)), dim3(64 * DIRF_WAVES), 0, s, G.desc, np, dg);
+    if (I0.n == 32) {
+      // one block per patch, every patch in one launch (no work array: each
+      // patch's values stay on the chip)
+      DirGeom dg{I0.n, L.total, 2.0 / I0.n, st, 0};
+      hipLaunchKernelGGL(dirichlet_fused_kernel, dim3(unsigned(L.total)), dim3(64 * DIRF_WAVES), 0, s, G.desc, np,
+                         dg);
+    } else {
+      // three passes over the work array, in chunks of patches when it cannot hold them all
+      double* dir = reinterpret_cast<double*>(G.ws + L.o_dir);
+      const int m = I0.n - 1;
+      for (int p0 = 0; p0 < L.total; p0 += L.dir_chunk) {
+        const int cnt = std::min(L.dir_chunk, L.total - p0);
+        DirGeom dg{I0.n, cnt, 2.0 / I0.n, st, p0};
+        dim3 gd(unsigned((int64_t(cnt) * m + DIR_WAVES - 1) / DIR_WAVES));
+        hipLaunchKernelGGL(dirichlet_mfma_kernel<0>, gd, dim3(64 * DIR_WAVES), 0, s, G.desc, np, dir, dg);
+        hipLaunchKernelGGL(dirichlet_mfma_kernel<1>, gd, dim3(64 * DIR_WAVES), 0, s, G.desc, np, dir, dg);
+        hipLaunchKernelGGL(dirichlet_mfma_kernel<2>, gd, dim3(64 * DIR_WAVES), 0, s, G.desc, np, dir, dg);
+      }
+    }
   }
   return MLC_OK;
 }

@@ -1037,8 +1037,9 @@ __global__ void __launch_bounds__(256) skeleton_finish_kernel(const SkelProb<T>*
 // DST-I basis of length m = n - 1: u = S^-1 (S rhs / lambda) with
 // S[k][j] = sin(pi (k+1)(j+1) / n) along each axis, S symmetric and
 // S^-1 = (2/n) S.  A slab (m x m padded to 32 x 32) is transformed along
-// both of its axes as S X S, or columns of a staged matrix along one axis as
-// S X, each product on v_mfma_f64_16x16x4f64 (dirichlet_fused_kernel).
+// both of its axes as S X S, along one as S X, each product on
+// v_mfma_f64_16x16x4f64 (dirichlet_fused_kernel for 32^3-cell patches,
+// dirichlet_mfma_kernel for smaller ones).
 struct DirGeom {
   int n, npatch;   // patches of this launch: p0 .. p0 + npatch - 1 (one block each)
   double scale;    // 2/n
@@ -1082,6 +1083,170 @@ __device__ __forceinline__ void mm32(const double* A, const double* B, double* D
 #pragma unroll
       for (int r = 0; r < 4; ++r) D[(16 * it + 4 * r + (lane >> 4)) * 33 + 16 * kt + (lane & 15)] = acc[it][kt][r];
 }
+
+// Smaller patches (n < 32: at most 15 slabs, half the fused kernel's waves
+// idle) take three passes over an (n-1)^3 work array per patch instead:
+//   0: slabs of fixed index 0: right-hand side h^2 f - (boundary terms), S X S
+//   1: slabs of fixed index 1: S X along index 0, divide by the symbol,
+//      S X again (times 2/n)
+//   2: slabs of fixed index 0: S X S (times (2/n)^2), then
+//      phi = u + C2 h^2 f on the patch interior
+// Slabs (waves) per block of the Dirichlet passes.
+constexpr int DIR_WAVES = 8;
+
+template <int PASS>
+__global__ void __launch_bounds__(64 * DIR_WAVES) dirichlet_mfma_kernel(const ProbDesc* __restrict__ pd, int nprob,
+                                                                        double* __restrict__ work, DirGeom g) {
+  __shared__ double Sm[32 * 33];
+  __shared__ double Ls[DIR_WAVES][32 * 33];
+  __shared__ double sn[2 * 32], cs[32];
+  const int m = g.n - 1;
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  // sin(pi a / n) for a < 2n and cos(pi (k+1) / n): every entry of the
+  // transform matrix and of the symbol is one of these
+  if (threadIdx.x < 2 * g.n) sn[threadIdx.x] = sinpi(double(threadIdx.x) / double(g.n));
+  if (threadIdx.x < m) cs[threadIdx.x] = cospi(double(threadIdx.x + 1) / double(g.n));
+  __syncthreads();
+  for (int t = threadIdx.x; t < 32 * 32; t += blockDim.x) {
+    int k = t / 32, j = t % 32;
+    Sm[k * 33 + j] = (k < m && j < m) ? sn[((k + 1) * (j + 1)) % (2 * g.n)] : 0.0;
+  }
+  const int slab = blockIdx.x * DIR_WAVES + wave;     // over patches x m
+  const int pw = slab / m, u = slab % m;               // pw: the patch's slot in the work array
+  const int p = g.p0 + pw;
+  const bool live = pw < g.npatch;
+  const ProbDesc& D = pd[find_problem(pd, nprob, live ? p : 0)];
+  const auto* f = gbl(D.f);
+  const auto* phiB = gbl(D.phiB);
+  auto* phi = gbl(D.phi);
+  const int ppa = D.ppa, pl = p - D.patch0;
+  const double h2 = D.h2;
+  // slab element (row i, column j):
+  //   passes 0, 2: node index (u, i, j); pass 1: node index (i, u, j)
+  const int64_t M3 = int64_t(m) * m * m;
+  auto off = [&](int i, int j) -> int64_t {
+    if (PASS == 1) return int64_t(i) * m * m + int64_t(u) * m + j;
+    return int64_t(u) * m * m + int64_t(i) * m + j;
+  };
+  double* wp = work + int64_t(pw) * M3;
+  const int i0 = pl / (ppa * ppa), i1 = (pl / ppa) % ppa, i2 = pl % ppa;
+  const int64_t Np = D.N + 1;
+  const int64_t pbase = (int64_t(g.n) * i0) * Np * Np + int64_t(g.n) * i1 * Np + int64_t(g.n) * i2;
+  double* L = Ls[wave];
+  // lanes 0..31 walk a row's columns, the two half-waves take alternate
+  // rows; all 16 rows of a lane are loaded before the first LDS write, so
+  // the loads overlap
+  const int jc = lane & 31, ih = lane >> 5;
+  double rows[16];
+#pragma unroll
+  for (int r = 0; r < 16; ++r) {
+    const int i = ih + 2 * r;
+    double v = 0.0;
+    if (live && i < m && jc < m) {
+      if constexpr (PASS == 0) {
+        v = h2 * f[pbase + (int64_t(u + 1) * Np + (i + 1)) * Np + (jc + 1)];
+      } else {
+        v = wp[off(i, jc)];
+      }
+    }
+    rows[r] = v;
+  }
+#pragma unroll
+  for (int r = 0; r < 16; ++r) L[(ih + 2 * r) * 33 + jc] = rows[r];
+  if constexpr (PASS == 0) {
+    // boundary terms, only at nodes next to the patch boundary: the whole
+    // slab if it is the first or last of its patch, else its ring of
+    // 4(m-1) nodes.  The block's threads share the node lists of all its
+    // slabs (a first or last slab has eight times the nodes of the others).
+    __shared__ const double* sl_phiB[DIR_WAVES];
+    __shared__ int64_t sl_base[DIR_WAVES], sl_Np[DIR_WAVES];
+    __shared__ int sl_u[DIR_WAVES], sl_cnt[DIR_WAVES];
+    if (lane == 0) {
+      const bool end_slab = u == 0 || u == m - 1;
+      sl_phiB[wave] = D.phiB;
+      sl_base[wave] = pbase;
+      sl_Np[wave] = Np;
+      sl_u[wave] = u;
+      sl_cnt[wave] = live ? (end_slab ? m * m : 4 * (m - 1)) : 0;
+    }
+    __syncthreads();   // every slab's L and the node lists
+    int total = 0;
+#pragma unroll
+    for (int w = 0; w < DIR_WAVES; ++w) total += sl_cnt[w];
+    for (int q0 = threadIdx.x; q0 < total; q0 += blockDim.x) {
+      int w = 0, q = q0;
+      while (q >= sl_cnt[w]) q -= sl_cnt[w++];
+      const int uw = sl_u[w];
+      int i, j;
+      if (uw == 0 || uw == m - 1) {
+        i = q / m;
+        j = q % m;
+      } else if (q < 2 * m) {
+        i = q < m ? 0 : m - 1;
+        j = q % m;
+      } else {
+        const int r = q - 2 * m;
+        i = 1 + r / 2;
+        j = (r & 1) ? m - 1 : 0;
+      }
+      const auto* phiBw = gbl(sl_phiB[w]);
+      const int64_t base = sl_base[w], Npw = sl_Np[w];
+      const int l0 = uw + 1, l1 = i + 1, l2 = j + 1;
+      // every neighbour is a node of the patch box, so all 27 loads are
+      // issued together; those off the boundary (whose phi^B is not
+      // defined) are selected away, the boundary ones summed in order
+      double corr = 0.0;
+#pragma unroll
+      for (int s0 = -1; s0 <= 1; ++s0)
+#pragma unroll
+        for (int s1 = -1; s1 <= 1; ++s1)
+#pragma unroll
+          for (int s2 = -1; s2 <= 1; ++s2) {
+            const int k0 = l0 + s0, k1 = l1 + s1, k2 = l2 + s2;
+            const bool bnd = k0 == 0 || k0 == g.n || k1 == 0 || k1 == g.n || k2 == 0 || k2 == g.n;
+            const int nz = (s0 != 0) + (s1 != 0) + (s2 != 0);
+            const double x = phiBw[base + (int64_t(k0) * Npw + k1) * Npw + k2];
+            corr = fma(bnd ? g.st.b[nz] : 0.0, bnd ? x : 0.0, corr);
+          }
+      Ls[w][i * 33 + j] -= corr;
+    }
+  }
+  __syncthreads();   // Sm; from here on each wave touches only its own slab
+  if constexpr (PASS == 1) {
+    mm32(Sm, L, L, lane);                 // forward along index 0
+    wave_sync_lds();
+    for (int i = ih; i < 32; i += 2) {    // divide by the symbol at (k0, k1, k2) = (i, u, jc)
+      double v = 0.0;
+      if (i < m && jc < m) {
+        const double c0 = cs[i], c1 = cs[u], c2 = cs[jc];
+        const double lam = g.st.b[0] + 2.0 * g.st.b[1] * (c0 + c1 + c2) +
+                           4.0 * g.st.b[2] * (c0 * c1 + c0 * c2 + c1 * c2) + 8.0 * g.st.b[3] * c0 * c1 * c2;
+        v = L[i * 33 + jc] / lam;
+      }
+      L[i * 33 + jc] = v;
+    }
+    wave_sync_lds();
+    mm32(Sm, L, L, lane);                 // inverse along index 0
+  } else {
+    mm32(Sm, L, L, lane);                 // along index 1 (rows)
+    wave_sync_lds();
+    mm32(L, Sm, L, lane);                 // along index 2 (columns)
+  }
+  wave_sync_lds();
+  if (!live) return;
+  const double sc = PASS == 0 ? 1.0 : (PASS == 1 ? g.scale : g.scale * g.scale);
+  for (int i = ih; i < m; i += 2) {
+    if (jc >= m) continue;
+    const double v = sc * L[i * 33 + jc];
+    if constexpr (PASS == 2) {
+      const int64_t node = pbase + (int64_t(u + 1) * Np + (i + 1)) * Np + (jc + 1);
+      phi[node] = v + D.c2h2 * f[node];
+    } else {
+      wp[off(i, jc)] = v;
+    }
+  }
+}
+
 
 // One block of 16 waves per patch: the patch's (n-1)^3 values stay on the
 // chip (wave w holds the slabs of index 0 equal to w and w + 16 in
