@@ -128,9 +128,9 @@ typedef struct {
   int32_t max_live;       /* > 0: keep per-patch convolution buffers for at most this many
                              patches with charge (implies skip_empty): each solve finds
                              them on the device, waits for its stream once to list them,
-                             and returns MLC_ERR_OUT_OF_MEMORY if there are more; the
-                             patch Dirichlet solves run in chunks.  For large grids whose
-                             charge covers few patches (e.g. 2048^3).  mlc_solve and
+                             and returns MLC_ERR_OUT_OF_MEMORY if there are more.  For
+                             large grids whose charge covers few patches (e.g. 2048^3).
+                             mlc_solve and
                              mlc_solve_analytic only: batches, graphs, the static
                              scratch and the server refuse it (MLC_ERR_UNSUPPORTED).
                              The coarser levels of a multilevel plan keep every patch.
