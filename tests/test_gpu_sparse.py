@@ -173,3 +173,25 @@ def test_max_live_analytic_and_refusals():
     assert ei.value.status == gm.MLC_ERR_UNSUPPORTED
     dense.close()
     cap.close()
+
+
+def test_max_live_box_domain():
+    """A box domain with max_live: the live patches are found in the box's
+    enclosing cube (f padded by zeros), and phi on the box equals the dense
+    box solve's element for element."""
+    import torch
+    N, n = 96, 16
+    fc = mi.bump_charge(N, mi.bumps(1, 91, radius=(0.08, 0.1), centre=(0.22, 0.28)))
+    fb = np.ascontiguousarray(fc[:, :65, :49])
+    assert np.array_equal(fc[:, 65:, :], np.zeros_like(fc[:, 65:, :])) and not fc[:, :, 49:].any()
+    live = _live_count(fc, n)
+    assert 0 < live < (N // n) ** 3
+    kw = dict(N=(96, 64, 48), n=n, alpha=3.0, beta=6.0, P=4, Q=4, conv="fp64")
+    f = torch.from_numpy(fb).cuda()
+    dense = context().plan(gm.problem(skip_empty=1, **kw))
+    cap = context().plan(gm.problem(max_live=live, **kw))
+    a, _ = _solve(dense, f)
+    b, _ = _solve(cap, f)
+    assert torch.equal(a, b)
+    dense.close()
+    cap.close()
