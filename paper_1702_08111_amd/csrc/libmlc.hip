@@ -1731,8 +1731,10 @@ static mlc_status launch_rest(const Group& G, hipStream_t s, Stage stage) {
       // one block per patch, every patch in one launch (no work array: each
       // patch's values stay on the chip)
       DirGeom dg{I0.n, L.total, 2.0 / I0.n, st, 0};
+      // the per-patch flags of which patches carry charge, when the solve has them
+      const int* plive = L.any_skip ? reinterpret_cast<const int*>(G.ws + L.o_live) : nullptr;
       hipLaunchKernelGGL(dirichlet_fused_kernel, dim3(unsigned(L.total)), dim3(64 * DIRF_WAVES), 0, s, G.desc, np,
-                         dg);
+                         dg, plive);
     } else {
       // three passes over the work array, in chunks of patches when it cannot hold them all
       double* dir = reinterpret_cast<double*>(G.ws + L.o_dir);

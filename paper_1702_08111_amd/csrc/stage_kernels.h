@@ -1260,7 +1260,8 @@ constexpr int DIRF_WAVES = 16;
 constexpr int DIRF_TS = 260;   // row stride of the staging matrix (256 columns + 4)
 static_assert(32 * DIRF_TS <= DIRF_WAVES * 32 * 33, "staging matrix must fit in the slab buffers");
 __global__ void __launch_bounds__(64 * DIRF_WAVES) dirichlet_fused_kernel(const ProbDesc* __restrict__ pd, int nprob,
-                                                                         DirGeom g) {
+                                                                         DirGeom g,
+                                                                         const int* __restrict__ patch_live) {
   __shared__ double Sm[32 * 33];
   __shared__ double Ls[DIRF_WAVES][32 * 33];
   __shared__ double sn[2 * 32], cs[32];
@@ -1282,6 +1283,8 @@ __global__ void __launch_bounds__(64 * DIRF_WAVES) dirichlet_fused_kernel(const 
   auto* phi = gbl(D.phi);
   const int ppa = D.ppa, pl = p - D.patch0;
   const double h2 = D.h2;
+  // a patch known to be empty (every node of its closed box zero) reads no f
+  const bool has_f = !patch_live || patch_live[p];
   const int i0 = pl / (ppa * ppa), i1 = (pl / ppa) % ppa, i2 = pl % ppa;
   const int64_t Np = D.N + 1;
   const int64_t pbase = (int64_t(g.n) * i0) * Np * Np + int64_t(g.n) * i1 * Np + int64_t(g.n) * i2;
@@ -1298,7 +1301,7 @@ __global__ void __launch_bounds__(64 * DIRF_WAVES) dirichlet_fused_kernel(const 
     for (int r = 0; r < 16; ++r) {
       const int i = ih + 2 * r;
       double v = 0.0;
-      if (live && i < m && jc < m) v = h2 * f[pbase + (int64_t(u + 1) * Np + (i + 1)) * Np + (jc + 1)];
+      if (has_f && live && i < m && jc < m) v = h2 * f[pbase + (int64_t(u + 1) * Np + (i + 1)) * Np + (jc + 1)];
       xs[sl][r] = v;
     }
 #pragma unroll
@@ -1447,7 +1450,7 @@ __global__ void __launch_bounds__(64 * DIRF_WAVES) dirichlet_fused_kernel(const 
         if (jc >= m) continue;
         const double v = sc * L[i * 33 + jc];
         const int64_t node = pbase + (int64_t(u + 1) * Np + (i + 1)) * Np + (jc + 1);
-        phi[node] = v + D.c2h2 * f[node];
+        phi[node] = v + D.c2h2 * (has_f ? f[node] : 0.0);
       }
     }
     wave_sync_lds();   // the slab's reads before the next slab overwrites L
