@@ -1708,8 +1708,9 @@ static mlc_status launch_rest(const Group& G, hipStream_t s, Stage stage) {
       const mlc_plan_info& I = P->info;
       SkelGeom sg{I.N, I.n, I.patches_per_axis, P->Kann, I.d_alpha, I.d_beta, I.b, I.Wa, P->P0, I.nplanes_a, P->Wb,
                   P->P0b, P->nplb, I.O_lo, I.No, final_c2h2(*P)};
+      const int* plive = L.any_skip ? reinterpret_cast<const int*>(G.ws + L.o_live) + L.patch0[k] : nullptr;
       v[k] = SkelProb<T>{phiH_of(k), pl + L.patch0[k] * plsz, charge_of(G, k), phiB_of(k), phi_of(G, k), sg, total,
-                         slot_of_patch(G), blocks};
+                         slot_of_patch(G), blocks, plive};
       total += int64_t(3) * (I.N / I.n + 1) * (I.N + 1) * (I.N + 1);
       // finishing tiles: planes x (N/4 + 1 coarse row intervals) x column chunks
       blocks += int64_t(3) * (I.N / I.n + 1) * (I.N / NREF + 1) * ((I.N + SKF_COLS) / SKF_COLS);

@@ -455,6 +455,7 @@ template <typename T> struct SkelProb {
   int64_t start;
   const int* slot_of;  // patch -> its slot in delta (-1: an empty patch), or null (slot = patch)
   int64_t bstart;      // the problem's first block in skeleton_finish_kernel
+  const int* live;     // per patch of the problem: 1 unless known empty, or null (read f everywhere)
 };
 
 // ---------------------------------------------- annulus sums on MFMA ----
@@ -1029,7 +1030,20 @@ __global__ void __launch_bounds__(256) skeleton_finish_kernel(const SkelProb<T>*
   double* __restrict__ phiB = pb.phiB;
   if (annulus) val += phiB[node];
   phiB[node] = val;
-  pb.phi[node] = val + g.c2h2 * pb.f[node];
+  // f at the node is zero when every patch whose closed box holds it is empty
+  bool has_f = true;
+  if (pb.live) {
+    int lo[3], hi[3];
+    for (int a = 0; a < 3; ++a) {
+      hi[a] = min(gg[a] / n, g.ppa - 1);
+      lo[a] = (gg[a] % n == 0 && gg[a] > 0) ? gg[a] / n - 1 : hi[a];
+    }
+    has_f = false;
+    for (int i0 = lo[0]; i0 <= hi[0]; ++i0)
+      for (int i1 = lo[1]; i1 <= hi[1]; ++i1)
+        for (int i2 = lo[2]; i2 <= hi[2]; ++i2) has_f = has_f || pb.live[(i0 * g.ppa + i1) * g.ppa + i2] != 0;
+  }
+  pb.phi[node] = val + g.c2h2 * (has_f ? pb.f[node] : 0.0);
 }
 
 // --------------------------------------------- Dirichlet solves on MFMA ----
