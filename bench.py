@@ -632,8 +632,8 @@ def serving_bench(ctx, count, load, dev, warm=50, sat_requests=120, pool=4, ring
 def main():
     args = parse()
     if args.gpus != 1:
-        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the path is single-GPU "
-              "and multi-GPU sharding is described in DESIGN.md, not built.", file=sys.stderr)
+        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}): the solver runs on a single "
+              "GPU; sharding across GPUs is not built.", file=sys.stderr)
         sys.exit(2)
     import torch
     from paper_1702_08111_amd import mlc as gm
