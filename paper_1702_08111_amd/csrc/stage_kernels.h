@@ -1098,6 +1098,66 @@ __device__ __forceinline__ void mm32(const double* A, const double* B, double* D
       for (int r = 0; r < 4; ++r) D[(16 * it + 4 * r + (lane >> 4)) * 33 + 16 * kt + (lane & 15)] = acc[it][kt][r];
 }
 
+// For 32^3-cell patches (m = 31) the transform matrix pairs its rows k and
+// 30 - k: S[30 - k][j] = (-1)^j S[k][j] (and S is symmetric).  A product
+// S X then takes the even and the odd j apart over the 16 rows k < 16,
+// E = sum over even j of S[k][j] X[j], O = the same over odd j (half the
+// MFMAs of mm32), and gives row k = E + O and row 30 - k = E - O (row 15
+// pairs with itself, its O being zero; row 31, padding, is zero).  X S
+// likewise along the columns.  D may be the matrix that is not S.
+__device__ __forceinline__ void mm32_sl(const double* S, const double* B, double* D, int lane) {
+  f64x4 e[2], o[2];
+#pragma unroll
+  for (int kt = 0; kt < 2; ++kt) e[kt] = o[kt] = f64x4{0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+  for (int kk = 0; kk < 4; ++kk) {
+    const int jj = 4 * kk + (lane >> 4);
+    const double ae = S[(lane & 15) * 33 + 2 * jj], ao = S[(lane & 15) * 33 + 2 * jj + 1];
+#pragma unroll
+    for (int kt = 0; kt < 2; ++kt) {
+      const double be = B[(2 * jj) * 33 + 16 * kt + (lane & 15)];
+      const double bo = B[(2 * jj + 1) * 33 + 16 * kt + (lane & 15)];
+      e[kt] = __builtin_amdgcn_mfma_f64_16x16x4f64(ae, be, e[kt], 0, 0, 0);
+      o[kt] = __builtin_amdgcn_mfma_f64_16x16x4f64(ao, bo, o[kt], 0, 0, 0);
+    }
+  }
+#pragma unroll
+  for (int kt = 0; kt < 2; ++kt)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int k = 4 * r + (lane >> 4), col = 16 * kt + (lane & 15);
+      const double ev = e[kt][r], ov = o[kt][r];
+      D[k * 33 + col] = ev + ov;
+      D[(k < 15 ? 30 - k : 31) * 33 + col] = k < 15 ? ev - ov : 0.0;
+    }
+}
+__device__ __forceinline__ void mm32_sr(const double* B, const double* S, double* D, int lane) {
+  f64x4 e[2], o[2];
+#pragma unroll
+  for (int it = 0; it < 2; ++it) e[it] = o[it] = f64x4{0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+  for (int kk = 0; kk < 4; ++kk) {
+    const int jj = 4 * kk + (lane >> 4);
+    const double se = S[(2 * jj) * 33 + (lane & 15)], so = S[(2 * jj + 1) * 33 + (lane & 15)];
+#pragma unroll
+    for (int it = 0; it < 2; ++it) {
+      const double ae = B[(16 * it + (lane & 15)) * 33 + 2 * jj];
+      const double ao = B[(16 * it + (lane & 15)) * 33 + 2 * jj + 1];
+      e[it] = __builtin_amdgcn_mfma_f64_16x16x4f64(ae, se, e[it], 0, 0, 0);
+      o[it] = __builtin_amdgcn_mfma_f64_16x16x4f64(ao, so, o[it], 0, 0, 0);
+    }
+  }
+#pragma unroll
+  for (int it = 0; it < 2; ++it)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int i = 16 * it + 4 * r + (lane >> 4), c = lane & 15;
+      const double ev = e[it][r], ov = o[it][r];
+      D[i * 33 + c] = ev + ov;
+      D[i * 33 + (c < 15 ? 30 - c : 31)] = c < 15 ? ev - ov : 0.0;
+    }
+}
+
 // Smaller patches (n < 32: at most 15 slabs, half the fused kernel's waves
 // idle) take three passes over an (n-1)^3 work array per patch instead:
 //   0: slabs of fixed index 0: right-hand side h^2 f - (boundary terms), S X S
@@ -1372,9 +1432,9 @@ __global__ void __launch_bounds__(64 * DIRF_WAVES) dirichlet_fused_kernel(const 
       Ls[w][i * 33 + j] -= corr;
     }
     __syncthreads();   // from here on each wave touches only its own slab
-    mm32(Sm, L, L, lane);                 // along index 1 (rows)
+    mm32_sl(Sm, L, L, lane);              // along index 1 (rows)
     wave_sync_lds();
-    mm32(L, Sm, L, lane);                 // along index 2 (columns)
+    mm32_sr(L, Sm, L, lane);              // along index 2 (columns)
     wave_sync_lds();
 #pragma unroll
     for (int r = 0; r < 16; ++r) xs[sl][r] = L[(ih + 2 * r) * 33 + jc];
@@ -1397,42 +1457,42 @@ __global__ void __launch_bounds__(64 * DIRF_WAVES) dirichlet_fused_kernel(const 
     // this wave's 16 columns: (index 1, index 2) = (8 c + col / 32, col % 32)
     const int col = 16 * wave + (lane & 15);
     const int ii = 8 * c + col / 32, j2 = col % 32;
-    f64x4 acc[2];
 #pragma unroll
     for (int pass = 0; pass < 2; ++pass) {
+      // S times the wave's columns, rows k < 16 from the even and odd u apart
+      f64x4 e = f64x4{0.0, 0.0, 0.0, 0.0}, o = e;
 #pragma unroll
-      for (int it = 0; it < 2; ++it) acc[it] = f64x4{0.0, 0.0, 0.0, 0.0};
-#pragma unroll
-      for (int jj = 0; jj < 8; ++jj) {
-        const int krow = 4 * jj + (lane >> 4);
-        const double b = T[krow * DIRF_TS + col];
-#pragma unroll
-        for (int it = 0; it < 2; ++it) {
-          const double a = Sm[(16 * it + (lane & 15)) * 33 + krow];
-          acc[it] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc[it], 0, 0, 0);
-        }
+      for (int kk = 0; kk < 4; ++kk) {
+        const int jj = 4 * kk + (lane >> 4);
+        const double ae = Sm[(lane & 15) * 33 + 2 * jj], ao = Sm[(lane & 15) * 33 + 2 * jj + 1];
+        const double be = T[(2 * jj) * DIRF_TS + col], bo = T[(2 * jj + 1) * DIRF_TS + col];
+        e = __builtin_amdgcn_mfma_f64_16x16x4f64(ae, be, e, 0, 0, 0);
+        o = __builtin_amdgcn_mfma_f64_16x16x4f64(ao, bo, o, 0, 0, 0);
       }
       wave_sync_lds();   // every lane's reads of its columns before they are overwritten
 #pragma unroll
-      for (int it = 0; it < 2; ++it)
+      for (int r = 0; r < 4; ++r) {
+        const int k0 = 4 * r + (lane >> 4);
+        const double y[2] = {e[r] + o[r], e[r] - o[r]};
 #pragma unroll
-        for (int r = 0; r < 4; ++r) {
-          const int k = 16 * it + 4 * r + (lane >> 4);
-          double v;
+        for (int h = 0; h < 2; ++h) {
+          // row k0 (E + O) and its pair 30 - k0 (E - O); row 15's pair is row 31, zero
+          const int k = h == 0 ? k0 : (k0 < 15 ? 30 - k0 : 31);
+          double v = 0.0;
           if (pass == 0) {
             // divide by the symbol at (k0, k1, k2) = (k, ii, j2)
-            v = 0.0;
             if (k < m && ii < m && j2 < m) {
               const double c0 = cs[k], c1 = cs[ii], c2 = cs[j2];
               const double lam = g.st.b[0] + 2.0 * g.st.b[1] * (c0 + c1 + c2) +
                                  4.0 * g.st.b[2] * (c0 * c1 + c0 * c2 + c1 * c2) + 8.0 * g.st.b[3] * c0 * c1 * c2;
-              v = acc[it][r] / lam;
+              v = y[h] / lam;
             }
-          } else {
-            v = g.scale * acc[it][r];
+          } else if (k < m) {
+            v = g.scale * y[h];
           }
           T[k * DIRF_TS + col] = v;
         }
+      }
       wave_sync_lds();
     }
     __syncthreads();
@@ -1455,9 +1515,9 @@ __global__ void __launch_bounds__(64 * DIRF_WAVES) dirichlet_fused_kernel(const 
 #pragma unroll
     for (int r = 0; r < 16; ++r) L[(ih + 2 * r) * 33 + jc] = xs[sl][r];
     wave_sync_lds();
-    mm32(Sm, L, L, lane);
+    mm32_sl(Sm, L, L, lane);
     wave_sync_lds();
-    mm32(L, Sm, L, lane);
+    mm32_sr(L, Sm, L, lane);
     wave_sync_lds();
     if (u < m) {
       for (int i = ih; i < m; i += 2) {
