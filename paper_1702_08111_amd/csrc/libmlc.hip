@@ -1744,9 +1744,15 @@ static mlc_status launch_rest(const Group& G, hipStream_t s, Stage stage) {
         const int cnt = std::min(L.dir_chunk, L.total - p0);
         DirGeom dg{I0.n, cnt, 2.0 / I0.n, st, p0};
         dim3 gd(unsigned((int64_t(cnt) * m + DIR_WAVES - 1) / DIR_WAVES));
-        hipLaunchKernelGGL(dirichlet_mfma_kernel<0>, gd, dim3(64 * DIR_WAVES), 0, s, G.desc, np, dir, dg);
-        hipLaunchKernelGGL(dirichlet_mfma_kernel<1>, gd, dim3(64 * DIR_WAVES), 0, s, G.desc, np, dir, dg);
-        hipLaunchKernelGGL(dirichlet_mfma_kernel<2>, gd, dim3(64 * DIR_WAVES), 0, s, G.desc, np, dir, dg);
+        if (I0.n <= 16) {   // 16 x 16 slab tiles
+          hipLaunchKernelGGL((dirichlet_mfma_kernel<0, 16>), gd, dim3(64 * DIR_WAVES), 0, s, G.desc, np, dir, dg);
+          hipLaunchKernelGGL((dirichlet_mfma_kernel<1, 16>), gd, dim3(64 * DIR_WAVES), 0, s, G.desc, np, dir, dg);
+          hipLaunchKernelGGL((dirichlet_mfma_kernel<2, 16>), gd, dim3(64 * DIR_WAVES), 0, s, G.desc, np, dir, dg);
+        } else {
+          hipLaunchKernelGGL((dirichlet_mfma_kernel<0, 32>), gd, dim3(64 * DIR_WAVES), 0, s, G.desc, np, dir, dg);
+          hipLaunchKernelGGL((dirichlet_mfma_kernel<1, 32>), gd, dim3(64 * DIR_WAVES), 0, s, G.desc, np, dir, dg);
+          hipLaunchKernelGGL((dirichlet_mfma_kernel<2, 32>), gd, dim3(64 * DIR_WAVES), 0, s, G.desc, np, dir, dg);
+        }
       }
     }
   }

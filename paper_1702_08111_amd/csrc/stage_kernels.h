@@ -1158,6 +1158,23 @@ __device__ __forceinline__ void mm32_sr(const double* B, const double* S, double
     }
 }
 
+// D = A B for TW x TW row-major LDS matrices of stride TW + 1 (one wave):
+// mm32, or for TW = 16 a single 16 x 16 MFMA tile over four k-steps.
+__device__ __forceinline__ void mm16(const double* A, const double* B, double* D, int lane) {
+  f64x4 acc = f64x4{0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+  for (int kk = 0; kk < 4; ++kk) {
+    const int krow = 4 * kk + (lane >> 4);
+    acc = __builtin_amdgcn_mfma_f64_16x16x4f64(A[(lane & 15) * 17 + krow], B[krow * 17 + (lane & 15)], acc, 0, 0, 0);
+  }
+#pragma unroll
+  for (int r = 0; r < 4; ++r) D[(4 * r + (lane >> 4)) * 17 + (lane & 15)] = acc[r];
+}
+template <int TW> __device__ __forceinline__ void mm_tile(const double* A, const double* B, double* D, int lane) {
+  if constexpr (TW == 32) mm32(A, B, D, lane);
+  else mm16(A, B, D, lane);
+}
+
 // Smaller patches (n < 32: at most 15 slabs, half the fused kernel's waves
 // idle) take three passes over an (n-1)^3 work array per patch instead:
 //   0: slabs of fixed index 0: right-hand side h^2 f - (boundary terms), S X S
@@ -1168,11 +1185,14 @@ __device__ __forceinline__ void mm32_sr(const double* B, const double* S, double
 // Slabs (waves) per block of the Dirichlet passes.
 constexpr int DIR_WAVES = 8;
 
-template <int PASS>
+// TW: the slab tile, 32 (n - 1 <= 31) or 16 (n - 1 <= 15: a quarter of the
+// LDS and an eighth of the MFMAs of a padded 32 x 32 slab)
+template <int PASS, int TW>
 __global__ void __launch_bounds__(64 * DIR_WAVES) dirichlet_mfma_kernel(const ProbDesc* __restrict__ pd, int nprob,
                                                                         double* __restrict__ work, DirGeom g) {
-  __shared__ double Sm[32 * 33];
-  __shared__ double Ls[DIR_WAVES][32 * 33];
+  constexpr int LD = TW + 1, RG = 64 / TW, NR = TW * TW / 64;   // row stride, row groups, rows per lane
+  __shared__ double Sm[TW * LD];
+  __shared__ double Ls[DIR_WAVES][TW * LD];
   __shared__ double sn[2 * 32], cs[32];
   const int m = g.n - 1;
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
@@ -1181,9 +1201,9 @@ __global__ void __launch_bounds__(64 * DIR_WAVES) dirichlet_mfma_kernel(const Pr
   if (threadIdx.x < 2 * g.n) sn[threadIdx.x] = sinpi(double(threadIdx.x) / double(g.n));
   if (threadIdx.x < m) cs[threadIdx.x] = cospi(double(threadIdx.x + 1) / double(g.n));
   __syncthreads();
-  for (int t = threadIdx.x; t < 32 * 32; t += blockDim.x) {
-    int k = t / 32, j = t % 32;
-    Sm[k * 33 + j] = (k < m && j < m) ? sn[((k + 1) * (j + 1)) % (2 * g.n)] : 0.0;
+  for (int t = threadIdx.x; t < TW * TW; t += blockDim.x) {
+    int k = t / TW, j = t % TW;
+    Sm[k * LD + j] = (k < m && j < m) ? sn[((k + 1) * (j + 1)) % (2 * g.n)] : 0.0;
   }
   const int slab = blockIdx.x * DIR_WAVES + wave;     // over patches x m
   const int pw = slab / m, u = slab % m;               // pw: the patch's slot in the work array
@@ -1207,14 +1227,14 @@ __global__ void __launch_bounds__(64 * DIR_WAVES) dirichlet_mfma_kernel(const Pr
   const int64_t Np = D.N + 1;
   const int64_t pbase = (int64_t(g.n) * i0) * Np * Np + int64_t(g.n) * i1 * Np + int64_t(g.n) * i2;
   double* L = Ls[wave];
-  // lanes 0..31 walk a row's columns, the two half-waves take alternate
-  // rows; all 16 rows of a lane are loaded before the first LDS write, so
+  // lanes 0..TW-1 walk a row's columns, the RG lane groups take every RG-th
+  // row; all NR rows of a lane are loaded before the first LDS write, so
   // the loads overlap
-  const int jc = lane & 31, ih = lane >> 5;
-  double rows[16];
+  const int jc = lane % TW, ih = lane / TW;
+  double rows[NR];
 #pragma unroll
-  for (int r = 0; r < 16; ++r) {
-    const int i = ih + 2 * r;
+  for (int r = 0; r < NR; ++r) {
+    const int i = ih + RG * r;
     double v = 0.0;
     if (live && i < m && jc < m) {
       if constexpr (PASS == 0) {
@@ -1226,7 +1246,7 @@ __global__ void __launch_bounds__(64 * DIR_WAVES) dirichlet_mfma_kernel(const Pr
     rows[r] = v;
   }
 #pragma unroll
-  for (int r = 0; r < 16; ++r) L[(ih + 2 * r) * 33 + jc] = rows[r];
+  for (int r = 0; r < NR; ++r) L[(ih + RG * r) * LD + jc] = rows[r];
   if constexpr (PASS == 0) {
     // boundary terms, only at nodes next to the patch boundary: the whole
     // slab if it is the first or last of its patch, else its ring of
@@ -1282,36 +1302,36 @@ __global__ void __launch_bounds__(64 * DIR_WAVES) dirichlet_mfma_kernel(const Pr
             const double x = phiBw[base + (int64_t(k0) * Npw + k1) * Npw + k2];
             corr = fma(bnd ? g.st.b[nz] : 0.0, bnd ? x : 0.0, corr);
           }
-      Ls[w][i * 33 + j] -= corr;
+      Ls[w][i * LD + j] -= corr;
     }
   }
   __syncthreads();   // Sm; from here on each wave touches only its own slab
   if constexpr (PASS == 1) {
-    mm32(Sm, L, L, lane);                 // forward along index 0
+    mm_tile<TW>(Sm, L, L, lane);          // forward along index 0
     wave_sync_lds();
-    for (int i = ih; i < 32; i += 2) {    // divide by the symbol at (k0, k1, k2) = (i, u, jc)
+    for (int i = ih; i < TW; i += RG) {   // divide by the symbol at (k0, k1, k2) = (i, u, jc)
       double v = 0.0;
       if (i < m && jc < m) {
         const double c0 = cs[i], c1 = cs[u], c2 = cs[jc];
         const double lam = g.st.b[0] + 2.0 * g.st.b[1] * (c0 + c1 + c2) +
                            4.0 * g.st.b[2] * (c0 * c1 + c0 * c2 + c1 * c2) + 8.0 * g.st.b[3] * c0 * c1 * c2;
-        v = L[i * 33 + jc] / lam;
+        v = L[i * LD + jc] / lam;
       }
-      L[i * 33 + jc] = v;
+      L[i * LD + jc] = v;
     }
     wave_sync_lds();
-    mm32(Sm, L, L, lane);                 // inverse along index 0
+    mm_tile<TW>(Sm, L, L, lane);          // inverse along index 0
   } else {
-    mm32(Sm, L, L, lane);                 // along index 1 (rows)
+    mm_tile<TW>(Sm, L, L, lane);          // along index 1 (rows)
     wave_sync_lds();
-    mm32(L, Sm, L, lane);                 // along index 2 (columns)
+    mm_tile<TW>(L, Sm, L, lane);          // along index 2 (columns)
   }
   wave_sync_lds();
   if (!live) return;
   const double sc = PASS == 0 ? 1.0 : (PASS == 1 ? g.scale : g.scale * g.scale);
-  for (int i = ih; i < m; i += 2) {
+  for (int i = ih; i < m; i += RG) {
     if (jc >= m) continue;
-    const double v = sc * L[i * 33 + jc];
+    const double v = sc * L[i * LD + jc];
     if constexpr (PASS == 2) {
       const int64_t node = pbase + (int64_t(u + 1) * Np + (i + 1)) * Np + (jc + 1);
       phi[node] = v + D.c2h2 * f[node];
